@@ -1,0 +1,408 @@
+"""CPU pins of the oracle's setup phase (Algorithm 1 and its steps).
+
+Each check compares the oracle with something other than itself: values the
+paper prints (the worked Galerkin example of Section 3.1), closed forms,
+brute-force enumeration on tiny graphs, dense linear algebra, and the
+jamming limit of random sequential adsorption for MIS(2) on a path.
+"""
+import itertools
+import math
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.sparse as sp
+
+from oracle import amg_oracle as O
+from synthetic import problems as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- hash
+
+def _inv_xorshift(y, s):
+    x = y
+    for _ in range(32 // s + 1):
+        x = y ^ (x >> s)
+    return x & 0xFFFFFFFF
+
+
+def _fmix32_inverse(h):
+    h = _inv_xorshift(h, 16)
+    h = (h * pow(0xC2B2AE35, -1, 2 ** 32)) & 0xFFFFFFFF
+    h = _inv_xorshift(h, 13)
+    h = (h * pow(0x85EBCA6B, -1, 2 ** 32)) & 0xFFFFFFFF
+    return _inv_xorshift(h, 16)
+
+
+def test_fmix32_reference_values():
+    # MurmurHash3's published finaliser maps 0 to 0 and 1 to 0x514e28b7
+    assert int(O.fmix32(0)) == 0
+    assert int(O.fmix32(1)) == 0x514E28B7
+
+
+def test_fmix32_is_a_bijection():
+    rng = np.random.default_rng(7)
+    xs = rng.integers(0, 2 ** 32, size=2000, dtype=np.uint64)
+    hs = O.fmix32(xs)
+    for x, h in zip(xs.tolist(), hs.tolist()):
+        assert _fmix32_inverse(h) == x
+    # injective on a block of consecutive node indices for several seeds
+    for seed in (0, 1, 12345):
+        h = O.node_hash(np.arange(1 << 18), seed)
+        assert np.unique(h).shape[0] == 1 << 18
+
+
+def test_unit_uniform_range_and_exactness():
+    u = O.unit_uniform(np.arange(100000), 3)
+    assert u.min() >= -1.0 and u.max() < 1.0
+    # exact multiples of 2^-31
+    assert np.all((u + 1.0) * 2.0 ** 31 == np.round((u + 1.0) * 2.0 ** 31))
+    assert abs(u.mean()) < 0.01
+
+
+# --------------------------------------------------------------------------- strength
+
+def _one_row(diag, offs, alpha):
+    """A (len(offs)+1)-square matrix whose row 0 is [diag, offs...]."""
+    k = len(offs) + 1
+    M = np.eye(k) * abs(diag) + 0.0
+    M[0, 0] = diag
+    M[0, 1:] = offs
+    A = sp.csr_matrix(M)
+    A.sort_indices()
+    C = O.strength(A, alpha)
+    return C[A.indptr[0]:A.indptr[1]]
+
+
+def test_strength_hand_rows():
+    # -s a: 1, 0.2, -0.5, 0.3 -> max over positives 1; threshold 0.25
+    assert _one_row(4.0, [-1.0, -0.2, 0.5, -0.3], 0.25).tolist() == [False, True, False, False, True]
+    # negative diagonal flips the sign convention
+    assert _one_row(-4.0, [1.0, 0.2, -0.5, 0.3], 0.25).tolist() == [False, True, False, False, True]
+    # strict '>' : an entry equal to alpha * max is weak
+    assert _one_row(4.0, [-1.0, -0.25], 0.25).tolist() == [False, True, False]
+    # only positive couplings: no strong entry at all
+    assert _one_row(4.0, [1.0, 2.0], 0.25).tolist() == [False, False, False]
+
+
+def test_strength_poisson_and_anisotropy():
+    A = P.poisson2d(12).to_scipy()
+    C = O.strength(A, 0.25)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    assert np.array_equal(C, A.indices != rows)          # every neighbour strong
+    A3 = P.aniso3d(6, 1e-3).to_scipy()
+    C3 = O.strength(A3, 0.5)
+    rows3 = np.repeat(np.arange(A3.shape[0]), np.diff(A3.indptr))
+    dz = np.abs(A3.indices - rows3) == 36
+    dxy = (A3.indices != rows3) & ~dz
+    assert not C3[dz].any() and C3[dxy].all()
+
+
+# --------------------------------------------------------------------------- MIS(2)
+
+def _random_graph(rng, n, p):
+    M = rng.random((n, n)) < p
+    M = np.triu(M, 1)
+    M = M | M.T
+    G = sp.csr_matrix(M.astype(np.int8))
+    G.sort_indices()
+    return G
+
+
+def _dist(G, src):
+    n = G.shape[0]
+    d = np.full(n, 10 ** 9)
+    d[src] = 0
+    q = deque([src])
+    while q:
+        u = q.popleft()
+        for w in G.indices[G.indptr[u]:G.indptr[u + 1]]:
+            if d[w] > d[u] + 1:
+                d[w] = d[u] + 1
+                q.append(w)
+    return d
+
+
+def _check_mis2(G, s):
+    roots = np.flatnonzero(s == 1)
+    n = G.shape[0]
+    near = np.full(n, 10 ** 9)
+    for r in roots:
+        d = _dist(G, r)
+        others = roots[roots != r]
+        assert np.all(d[others] > 2), "two MIS(2) nodes within distance 2"
+        near = np.minimum(near, d)
+    assert np.all(near <= 2), "a node farther than 2 from every MIS(2) node"
+
+
+def test_mis2_literal_equals_greedy_and_is_mis2():
+    rng = np.random.default_rng(11)
+    for trial in range(120):
+        n = int(rng.integers(1, 60))
+        G = _random_graph(rng, n, float(rng.uniform(0.02, 0.3)))
+        cnt = rng.integers(0, 5, size=n)
+        v = O.priorities(cnt, seed=trial)
+        s, _ = O.mis2_parallel(G, v)
+        assert np.array_equal(s, O.mis2_greedy(G, v))
+        _check_mis2(G, s)
+
+
+def test_mis2_brute_force_tiny():
+    """Among all distance-2-independent node sets, the lexicographically largest
+    indicator (nodes taken by decreasing v) is unique; the parallel rounds
+    must find exactly it."""
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        n = int(rng.integers(1, 11))
+        G = _random_graph(rng, n, float(rng.uniform(0.1, 0.5)))
+        v = O.priorities(rng.integers(0, 3, size=n), seed=100 + trial)
+        dist = np.array([_dist(G, i) for i in range(n)])
+        order = np.argsort(-v)
+        best = None
+        for mask in itertools.product([0, 1], repeat=n):
+            S = [i for i in range(n) if mask[i]]
+            if any(dist[a, b] <= 2 for a, b in itertools.combinations(S, 2)):
+                continue
+            key = tuple(mask[i] for i in order)
+            if best is None or key > best[0]:
+                best = (key, mask)
+        s, _ = O.mis2_parallel(G, v)
+        assert np.array_equal((s == 1).astype(int), np.array(best[1]))
+
+
+def test_mis2_isolated_nodes_are_roots():
+    G = sp.csr_matrix((5, 5), dtype=np.int8)
+    s, rounds = O.mis2_parallel(G, O.priorities(np.zeros(5, int), 0))
+    assert np.all(s == 1) and rounds == 1
+
+
+def test_mis2_path_density_matches_trimer_jamming():
+    """MIS(2) with random priorities on a path is random sequential adsorption
+    of trimers.  The k-mer jamming coverage on a lattice line is
+    k * int_0^inf exp(-t - 2 sum_{j<k} (1 - e^{-jt}) / j) dt (it gives Flory's
+    1 - e^-2 for dimers), so the root density tends to theta_3 / 3 (about
+    0.27455; the paper's anisotropic level-1 ratio 1e6/274979 is 0.27498)."""
+    def coverage(k):
+        f = lambda t: math.exp(-t - 2.0 * sum((1 - math.exp(-j * t)) / j for j in range(1, k)))
+        return k * si.quad(f, 0, np.inf)[0]
+    assert abs(coverage(2) - (1 - math.exp(-2))) < 1e-10
+    theta3 = coverage(3)
+    n = 300000
+    A = P.poisson1d(n).to_scipy()
+    C = O.strength(A, 0.25)
+    G = O.strong_graph(A, C)
+    v = O.priorities(O.influence_count(A, C), seed=9)
+    s, _ = O.mis2_parallel(G, v)
+    density = np.mean(s == 1)
+    assert abs(density - theta3 / 3.0) < 0.002
+    assert abs(theta3 / 3.0 - 0.27455) < 1e-4
+
+
+# --------------------------------------------------------------------------- aggregation
+
+def test_aggregate_nearest_root_brute_force():
+    rng = np.random.default_rng(21)
+    for trial in range(60):
+        n = int(rng.integers(2, 50))
+        G = _random_graph(rng, n, float(rng.uniform(0.03, 0.3)))
+        v = O.priorities(rng.integers(0, 4, size=n), seed=trial)
+        s, _ = O.mis2_parallel(G, v)
+        agg, nc = O.aggregate(G, s, v)
+        roots = np.flatnonzero(s == 1)
+        assert nc == roots.size
+        assert np.array_equal(agg[roots], np.arange(nc))     # ids by ascending root index
+        D = np.array([_dist(G, r) for r in roots])           # [root, node]
+        for i in range(n):
+            dmin = D[:, i].min()
+            cands = roots[D[:, i] == dmin]
+            want = np.flatnonzero(roots == cands[np.argmax(v[cands])])[0]
+            assert agg[i] == want
+        # aggregates are connected inside themselves
+        for I in range(nc):
+            members = np.flatnonzero(agg == I)
+            sub = G[members][:, members]
+            assert np.all(_dist(sub.tocsr(), int(np.flatnonzero(members == roots[I])[0])) < 10 ** 9)
+
+
+# --------------------------------------------------------------------------- interpolation
+
+def test_interpolation_orthonormal_and_nullspace():
+    rng = np.random.default_rng(3)
+    n, nc = 200, 37
+    agg = np.concatenate([np.arange(nc), rng.integers(0, nc, n - nc)])
+    B = rng.uniform(0.5, 2.0, n)
+    pval, Bc, Pm = O.interpolation(agg, nc, B)
+    assert np.all(np.diff(Pm.indptr) == 1)                       # one nonzero per row
+    assert np.allclose((Pm.T @ Pm).toarray(), np.eye(nc), atol=1e-15, rtol=0)
+    assert np.allclose(Pm @ Bc, B, atol=1e-15, rtol=1e-15)        # B_k = P_k B_{k+1}
+    _, Bc1, _ = O.interpolation(agg, nc, np.ones(n))
+    assert np.allclose(Bc1, np.sqrt(np.bincount(agg, minlength=nc)), rtol=1e-15)
+
+
+# --------------------------------------------------------------------------- Galerkin
+
+def _read_worked_example():
+    pattern, agg, coarse = [], {}, {}
+    with open(os.path.join(GOLDEN, "galerkin_worked_example.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            tag, rest = line.split(None, 1)
+            if tag == "pattern":
+                pattern = [tuple(int(t) for t in p.split(",")) for p in rest.split()]
+            elif tag == "agg":
+                agg = {int(a): int(b) for a, b in (p.split(":") for p in rest.split())}
+            elif tag == "coarse":
+                lhs, rhs = rest.split(":")
+                I, J = (int(t) for t in lhs.split())
+                coarse[(I, J)] = [tuple(int(t) for t in p.split(",")) for p in rhs.split()]
+    return pattern, agg, coarse
+
+
+def test_galerkin_worked_example_from_paper():
+    pattern, aggmap, coarse = _read_worked_example()
+    assert len(pattern) == 28
+    assert sum(len(v) for v in coarse.values()) == 28
+    n = 8
+    a = {(i, j): 10 * i + j + 1.0 / (i + j) for (i, j) in pattern}
+    rows = [i - 1 for i, _ in pattern]
+    cols = [j - 1 for _, j in pattern]
+    A = sp.csr_matrix(([a[p] for p in pattern], (rows, cols)), shape=(n, n))
+    A.sort_indices()
+    agg = np.array([aggmap[i + 1] - 1 for i in range(n)])
+    # unnormalised piecewise-constant P (all ones): the printed symbolic sums
+    Ac = O.galerkin(A, agg, np.ones(n), 3).toarray()
+    want = np.zeros((3, 3))
+    for (I, J), terms in coarse.items():
+        want[I - 1, J - 1] = sum(a[t] for t in terms)
+    assert np.allclose(Ac, want, rtol=1e-14, atol=0)
+    got_pattern = {(I + 1, J + 1) for I, J in zip(*O.galerkin(A, agg, np.ones(n), 3).nonzero())}
+    assert got_pattern == set(coarse)
+    # the paper's normalised P (B_0 = 1): divide by sqrt(m_I m_J), sizes (3, 2, 3)
+    pval, Bc, _ = O.interpolation(agg, 3, np.ones(n))
+    m = np.array([3, 2, 3], float)
+    assert np.allclose(Bc, np.sqrt(m), rtol=1e-15)
+    Acn = O.galerkin(A, agg, pval, 3).toarray()
+    assert np.allclose(Acn, want / np.sqrt(np.outer(m, m)), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("sizes", [[2] * 10, [3, 1, 4, 1, 5, 9, 2, 6], [1], [7, 7]])
+def test_galerkin_1d_poisson_closed_form(sizes):
+    n = sum(sizes)
+    A = P.poisson1d(n).to_scipy()
+    agg = np.repeat(np.arange(len(sizes)), sizes)
+    pval, _, _ = O.interpolation(agg, len(sizes), np.ones(n))
+    Ac = O.galerkin(A, agg, pval, len(sizes)).toarray()
+    m = np.array(sizes, float)
+    want = np.diag(2.0 / m)
+    for I in range(len(sizes) - 1):
+        want[I, I + 1] = want[I + 1, I] = -1.0 / math.sqrt(m[I] * m[I + 1])
+    assert np.allclose(Ac, want, rtol=1e-14, atol=1e-15)
+    if sizes == [2] * 10:   # pairwise: tridiag(-1,2,-1) with unnormalised P, half of it normalised
+        Au = O.galerkin(A, agg, np.ones(n), len(sizes)).toarray()
+        assert np.array_equal(Au, P.poisson1d(10).to_scipy().toarray())
+
+
+def test_galerkin_matches_dense_triple_product():
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        n = int(rng.integers(2, 40))
+        M = sp.random(n, n, density=0.2, random_state=rng) + sp.identity(n)
+        A = M.tocsr()
+        A.sort_indices()
+        nc = int(rng.integers(1, n + 1))
+        agg = np.concatenate([np.arange(nc), rng.integers(0, nc, n - nc)])
+        rng.shuffle(agg)
+        B = rng.uniform(0.5, 2, n)
+        pval, Bc, Pm = O.interpolation(agg, nc, B)
+        Ac = O.galerkin(A, agg, pval, nc).toarray()
+        Pd = Pm.toarray()
+        assert np.allclose(Ac, Pd.T @ A.toarray() @ Pd, rtol=1e-13, atol=1e-14)
+        # A_c B_{k+1} = P^T (A B_k)
+        assert np.allclose(Ac @ Bc, Pd.T @ (A @ B), rtol=1e-12, atol=1e-13)
+
+
+def test_galerkin_symmetry_and_constant_invariant_on_mis_aggregates():
+    A = P.hetero3d(8, seed=4).to_scipy()
+    lv = O.coarsen_level(A, np.ones(A.shape[0]), O.Options.for_dim(3))
+    Ac = lv.Ac
+    assert abs(Ac - Ac.T).max() <= 1e-12 * abs(Ac).max()
+    # unnormalised aggregate sums: (D_B A_c D_B) 1 = P_hat^T (A 1)
+    Ahat = sp.diags(lv.Bc) @ Ac @ sp.diags(lv.Bc)
+    Phat = sp.csr_matrix((np.ones(A.shape[0]), lv.agg, np.arange(A.shape[0] + 1)), shape=(A.shape[0], lv.nc))
+    lhs = Ahat @ np.ones(lv.nc)
+    rhs = Phat.T @ (A @ np.ones(A.shape[0]))
+    assert np.allclose(lhs, rhs, rtol=1e-11, atol=1e-11 * abs(A).max())
+
+
+def test_mis_aggregation_on_path_gives_closed_form_coarse_operator():
+    n = 500
+    A = P.poisson1d(n).to_scipy()
+    lv = O.coarsen_level(A, np.ones(n), O.Options.for_dim(2))
+    sizes = np.bincount(lv.agg)
+    assert np.all(np.diff(lv.agg) >= 0)               # aggregates are contiguous on a path
+    assert sizes.min() >= 1 and sizes.max() <= 5
+    m = sizes.astype(float)
+    Ac = lv.Ac.toarray()
+    assert np.allclose(np.diag(Ac), 2.0 / m, rtol=1e-14)
+    assert np.allclose(np.diag(Ac, 1), -1.0 / np.sqrt(m[:-1] * m[1:]), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------- Arnoldi / omega
+
+def test_arnoldi_full_dimension_gives_exact_spectral_radius():
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 3, 4, 5):
+        M = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(3, 5, n))
+        A = sp.csr_matrix(M)
+        H = O.arnoldi_hessenberg(A, 5, stream=1)
+        rho_true = np.max(np.abs(np.linalg.eigvals(np.diag(1 / np.diag(M)) @ M)))
+        rho = np.max(np.abs(np.linalg.eigvals(H)))
+        assert abs(rho - rho_true) <= 1e-12 * rho_true
+
+
+def test_jacobi_weight_poisson_bounds():
+    for A, rho_true in ((P.poisson2d(64), 1 + math.cos(math.pi / 65)),
+                        (P.poisson3d(16), 1 + math.cos(math.pi / 17))):
+        omega, rho = O.jacobi_weight(A.to_scipy(), 5, 1)
+        assert 0.9 * rho_true <= rho <= rho_true * (1 + 1e-12)
+        assert abs(omega - 4.0 / 3.0 / rho) < 1e-15
+
+
+# --------------------------------------------------------------------------- Algorithm 1
+
+def test_setup_levels_shrink_and_stop_near_coarse_max():
+    A = P.poisson2d(128)
+    H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(2))
+    ns = [lv.n for lv in H.levels]
+    assert ns[0] == 16384 and ns[-1] <= 600 and ns[-2] > 600
+    assert all(b < 0.9 * a for a, b in zip(ns, ns[1:]))
+    assert 1.0 < O.operator_complexity(H) < 2.0
+
+
+@pytest.mark.slow
+def test_table1_level1_size_anisotropic_1000():
+    """Paper Table 1 (unsmoothed aggregation, 2-D anisotropic Poisson 1000^2):
+    level 1 has 274,979 unknowns.  With strong anisotropy the strength graph is
+    a set of lines, so the statistic is the trimer jamming density."""
+    A = P.aniso2d(1000, 1e-3).to_scipy()
+    lv = O.coarsen_level(A, np.ones(A.shape[0]), O.Options.for_dim(2))
+    assert abs(lv.nc - 274979) < 0.005 * 274979
+
+
+def test_validate_rejects_bad_input():
+    A = P.poisson2d(4)
+    with pytest.raises(O.OracleError):
+        O.validate_csr(A.row_ptr, A.col, np.where(A.col == np.repeat(np.arange(16), np.diff(A.row_ptr)), 0.0, A.val))
+    col = A.col.copy()
+    col[1], col[2] = col[2], col[1]
+    with pytest.raises(O.OracleError):
+        O.validate_csr(A.row_ptr, col, A.val)
+    v = A.val.copy()
+    v[3] = np.nan
+    with pytest.raises(O.OracleError):
+        O.validate_csr(A.row_ptr, A.col, v)
