@@ -1,0 +1,159 @@
+"""Benchmark: aggregation-AMG setup + solve to a relative residual of 1e-8.
+
+One step = amg_setup + amg_solve of the named workload (3-D 7-point Poisson
+128^3 by default: 2,097,152 unknowns, 14,581,760 nonzeros), inputs already
+resident in device memory.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload C2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+WORKLOADS = {
+    "C1": ("2-D 5-point Poisson 128x128, FP64, K-cycle FCG", 2),
+    "C2": ("3-D 7-point Poisson 128^3, FP64, K-cycle FCG", 3),
+    "C3": ("3-D heterogeneous FV diffusion 160^3 (k=exp(2g)), FP64, K-cycle FCG", 3),
+    "C4a": ("3-D anisotropic 7-point 96^3 (eps_z=1e-3), FP64, K-cycle FCG", 3),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnz, val_bytes=8):
+    """Compulsory traffic of y = A x in CSR: values + columns + row pointers + x + y."""
+    return val_bytes * nnz + 4 * nnz + 4 * (n + 1) + 2 * val_bytes * n
+
+
+def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
+    rp, ci, v = dev
+    bt = torch.from_numpy(b).cuda()
+    x = torch.empty_like(bt)
+    opts = amg.Options(dim=dim, **opt)
+    results = []
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        h = amg.setup(rp, ci, v, opts)
+        _, it, rel = amg.solve(h, bt, 1e-8, x=x)
+        if i >= warmup:
+            s_ms, v_ms = h.timings()
+            results.append((it, rel, s_ms, v_ms))
+        del h
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, results, x
+
+
+def cpu_baseline(A, dim, b):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import amg_oracle as O
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(dim))
+        t1 = time.perf_counter()
+        res = O.solve(H, b, 1e-8)
+        t2 = time.perf_counter()
+    return {"value": A.n / (t2 - t0) / 1e6, "unit": "MDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"full workload, one setup+solve ({res.iters} FCG iterations, relres "
+                      f"{res.relres:.2e}); setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1403_1649_amd as amg
+    from synthetic import problems as P
+
+    desc, dim = WORKLOADS[args.workload]
+    log(f"bench: building {args.workload} ({desc})")
+    A, _, _ = P.config(args.workload)
+    xs = P.exact_solution(A.n, 1)
+    b = P.rhs(A, xs)
+    dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+    torch.cuda.synchronize()
+
+    log("bench: fp64 setup+solve")
+    wall, res, x = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup)
+    iters = [r[0] for r in res]
+    rels = [r[1] for r in res]
+    ok = all(r <= 1e-8 for r in rels)
+    value = A.n / wall / 1e6 if ok else 0.0
+
+    forms = {"fp64": {"mdof_s": round(value, 3), "iters": iters[-1], "relres": max(rels),
+                      "setup_ms": round(float(np.median([r[2] for r in res])), 3),
+                      "solve_ms": round(float(np.median([r[3] for r in res])), 3)}}
+    if not args.no_mixed:
+        log("bench: mixed setup+solve")
+        wall_m, res_m, xm = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup, precision="mixed")
+        ok_m = all(r[1] <= 1e-8 for r in res_m)
+        forms["mixed"] = {"mdof_s": round(A.n / wall_m / 1e6 if ok_m else 0.0, 3), "iters": res_m[-1][0],
+                          "relres": max(r[1] for r in res_m),
+                          "setup_ms": round(float(np.median([r[2] for r in res_m])), 3),
+                          "solve_ms": round(float(np.median([r[3] for r in res_m])), 3),
+                          "x_err_vs_fp64": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
+
+    # level-0 SpMV: events around repeated launches on the current stream
+    log("bench: level-0 SpMV")
+    xv = torch.from_numpy(xs).cuda()
+    y = torch.empty_like(xv)
+    reps = 50
+    for _ in range(5):
+        amg.spmv(*dev, xv, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        amg.spmv(*dev, xv, y)
+    e1.record()
+    torch.cuda.synchronize()
+    t_spmv = e0.elapsed_time(e1) / reps * 1e-3
+    nbytes = spmv_bytes(A.n, A.nnz)
+    gbs = nbytes / t_spmv / 1e9
+
+    line = {
+        "metric": "setup+solve MDOF/s to rel-res 1e-8 (FP64; mixed reported beside)",
+        "value": round(value, 3), "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": A.n, "nnz": A.nnz, "rtol": 1e-8},
+        "forms": forms,
+        "spmv": {"gb_s": round(gbs, 1), "us": round(t_spmv * 1e6, 2), "bytes": nbytes},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "level-0 CSR SpMV (amg_spmv)"},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: oracle CPU baseline (single thread)")
+        line["cpu_baseline"] = cpu_baseline(A, dim, b)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,174 @@
+/*
+ * amg.h — C ABI of the MI355X aggregation algebraic multigrid library.
+ *
+ * Method: Gandham, Esler & Zhang, "A GPU Accelerated Aggregation Algebraic
+ * Multigrid Method" (arXiv 1403.1649).  The library solves A x = b
+ * (Section 2, eq. axb) with an outer flexible Krylov method preconditioned by
+ * one K-/V-cycle (Section 2.2, Algorithms 4 and 5) over a hierarchy built by
+ * Algorithm 1 (strength, MIS(2) aggregation, one-nonzero-per-row
+ * interpolation, Galerkin product by aggregate index).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the argument is marked (host).
+ *  - Matrices are square, 0-based CSR: int32 row_ptr[n+1], int32
+ *    col_idx[nnz] strictly increasing within each row, float64 val[nnz]; every
+ *    row stores a nonzero diagonal; the pattern must be structurally
+ *    symmetric (values may be nonsymmetric).
+ *  - Work is ordered on the caller's stream.  Calls that return host results
+ *    (sizes, iteration counts, residuals) synchronise that stream before they
+ *    return; the others only enqueue.
+ *  - The caller owns every buffer it passes; the library owns the hierarchy
+ *    and all device memory inside it.  One hierarchy serves one stream at a
+ *    time; distinct hierarchies are independent.
+ *  - No call throws; each returns an amg_status.  On error, outputs are
+ *    unspecified unless stated otherwise.
+ */
+#ifndef AMG_H
+#define AMG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMG_OK = 0,
+  AMG_EINVAL = 1,       /* bad argument: shape, CSR structure, zero diagonal, nonsymmetric pattern */
+  AMG_ENOMEM = 2,       /* device or pinned-host allocation failed */
+  AMG_EHIP = 3,         /* a HIP runtime call failed */
+  AMG_ENOTCONV = 4,     /* max_iter reached; x holds the last iterate, relres is set */
+  AMG_EBREAKDOWN = 5,   /* Krylov breakdown (p^T A p <= 0) or a non-positive spectral estimate */
+  AMG_ECOARSEN = 6,     /* coarsening stalled above the dense-solve limit, or an unsupported aggregate */
+  AMG_ENANINF = 7,      /* non-finite value in the matrix, the right-hand side or the iteration */
+  AMG_EUNSUPPORTED = 8  /* option combination not provided by this build */
+} amg_status;
+
+typedef enum { AMG_KRYLOV_FCG = 0, AMG_KRYLOV_FGMRES = 1 } amg_krylov;
+typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_MIXED = 1 } amg_precision;
+typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1 } amg_smoother;
+
+/* Options (Sections 2.1.1, 2.2, 2.2.1, 3). */
+typedef struct {
+  double strength_alpha;  /* alpha of the classic strength test; 0.25 (2-D), 0.5 (3-D) */
+  int32_t coarse_max;     /* coarsen while a level has more unknowns than this (600) */
+  int32_t max_levels;     /* hard limit on the number of levels (20) */
+  int32_t kcycle_levels;  /* levels 0..kcycle_levels-1 use K-cycles, the rest V-cycles (2) */
+  double kcycle_t;        /* second inner Krylov step skipped when ||r~|| <= t ||r|| (0.25) */
+  double jacobi_scale;    /* omega = jacobi_scale / rho(D^-1 A) (4/3) */
+  int32_t arnoldi_m;      /* Arnoldi steps for rho(D^-1 A), at most 5 (5) */
+  uint32_t seed;          /* node-hash seed of the MIS(2) priorities; Arnoldi uses seed+1 */
+  int32_t krylov;         /* amg_krylov: outer method and K-cycle variant (FCG) */
+  int32_t gmres_restart;  /* FGMRES restart length (30) */
+  int32_t precision;      /* amg_precision (FP64) */
+  int32_t smoother;       /* amg_smoother (JACOBI) */
+  int32_t max_iter;       /* outer iteration limit (200) */
+  int32_t dense_max;      /* largest coarsest level accepted after a stall (4096) */
+  int32_t check_every;    /* outer iterations enqueued between host convergence checks (1) */
+  uint32_t flags;         /* reserved, 0 */
+} amg_options;
+
+/* A matrix handed to the library: device arrays, see the conventions above. */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* val;
+} amg_csr;
+
+typedef struct amg_hierarchy amg_hierarchy;
+
+/* Fill *opt with the defaults listed above; dim selects alpha (2 -> 0.25,
+ * otherwise 0.5; Section 2.1.1). */
+void amg_default_options(amg_options* opt, int32_t dim);
+
+/* Human-readable name of a status code (static storage). */
+const char* amg_status_string(int32_t status);
+
+/* (host) message of the last failed call on this thread (empty if none).
+ * Valid until the next failing call on the same thread. */
+const char* amg_last_error(void);
+
+/* Algorithm 1: build the hierarchy A_k, P_k (one nonzero per row, eq.
+ * null_space), B_k and A_{k+1} = P_k^T A_k P_k (Section 3.1, eq. galerkin)
+ * until a level has at most coarse_max unknowns; per level the damped Jacobi
+ * weight of eq. damped_jacobi from an Arnoldi estimate of rho(D^-1 A), and a
+ * dense factorisation of the coarsest level (Section 3).
+ * A: device CSR (copied; the caller may free it after the call returns).
+ * opt: (host) options, NULL for amg_default_options(dim=3).
+ * out: (host) receives the new hierarchy; free it with amg_destroy.
+ * Errors: EINVAL (structure, zero diagonal, nonsymmetric pattern), ENANINF,
+ * ECOARSEN, ENOMEM, EHIP; *out is NULL on error.  Synchronises s. */
+int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_hierarchy** out);
+
+/* Outer Krylov solve of A x = b to ||b - A x|| <= rtol ||b|| from x_0 = 0,
+ * preconditioned by one cycle (Algorithms 4 and 5 with the K-cycle on the
+ * top kcycle_levels levels; Section 2.2).
+ * b, x: device float64[n]; x is overwritten.  iters, relres: (host) outputs
+ * (outer iterations; true relative residual recomputed in FP64 at exit).
+ * Errors: ENOTCONV (x = last iterate), EBREAKDOWN, ENANINF, EHIP.
+ * Synchronises s. */
+int32_t amg_solve(amg_hierarchy* h, const double* b, double rtol, double* x,
+                  int32_t* iters, double* relres, hipStream_t s);
+
+/* Release the hierarchy and its device memory (NULL is ignored). */
+void amg_destroy(amg_hierarchy* h);
+
+/* Number of levels L+1 of a hierarchy (the coarsest level is index L). */
+int32_t amg_num_levels(const amg_hierarchy* h);
+
+/* (host) size of level k: n_k, nnz(A_k), omega_k (0 on the coarsest level),
+ * n_{k+1} (0 on the coarsest level) and the number of Algorithm 2 rounds.
+ * Any output pointer may be NULL. */
+int32_t amg_level_info(const amg_hierarchy* h, int32_t k, int32_t* n, int32_t* nnz,
+                       double* omega, int32_t* n_coarse, int32_t* mis_rounds);
+
+/* Copy level k to (host) buffers, for inspection and level-wise testing:
+ * row_ptr[n+1], col_idx[nnz], val[nnz] of A_k; strong[nnz] the strength mask
+ * C of Section 2.1.1 over A_k's pattern (0/1); state[n] the MIS(2) state of
+ * Algorithm 2 (1 root, -1 other); agg[n] the aggregate index; pval[n] the
+ * value of P_k's single nonzero per row (Algorithm 3); B[n] the near null
+ * space vector B_k.  Setup-only arrays are absent on the coarsest level
+ * (EINVAL if requested there).  Any pointer may be NULL.  Synchronises the
+ * hierarchy's setup stream. */
+int32_t amg_export_level(const amg_hierarchy* h, int32_t k, int32_t* row_ptr, int32_t* col_idx,
+                         double* val, uint8_t* strong, int8_t* state, int32_t* agg,
+                         double* pval, double* B);
+
+/* y = A x (the sparse mat-vec of Section 3, "axpy" there), float64, with the
+ * same kernel family the solve uses on level 0.  lanes_per_row in
+ * {0,1,2,4,8,16,32,64}; 0 picks from the average row length.
+ * Enqueue only. */
+int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s);
+
+/* Node hash of the MIS(2) priorities (the random r_i of Algorithm 2 made
+ * deterministic): out[i] = fmix32((i + stream * 0x9E3779B9) mod 2^32), the
+ * MurmurHash3 32-bit finaliser; out: device uint32[n].  Enqueue only. */
+int32_t amg_node_hash(int32_t n, uint32_t stream, uint32_t* out, hipStream_t s);
+
+/* Galerkin product by aggregate index (Section 3.1, eq. galerkin) for a
+ * given aggregation: (A_c)_IJ = sum over stored (i,j) with agg[i]=I,
+ * agg[j]=J of (pval[i] * a_ij) * pval[j].  A, agg[n], pval[n]: device.
+ * nnz_c: (host) receives nnz(A_c).  row_ptr_c[nc+1], col_c[cap], val_c[cap]:
+ * (host) outputs, written only when cap >= nnz(A_c) (otherwise EINVAL with
+ * *nnz_c set).  Synchronises s. */
+int32_t amg_galerkin(const amg_csr* A, const int32_t* agg, const double* pval, int32_t nc,
+                     int32_t* nnz_c, int32_t* row_ptr_c, int32_t* col_c, double* val_c,
+                     int32_t cap, hipStream_t s);
+
+/* (host) largest eigenvalue modulus of a real m-by-m upper Hessenberg matrix
+ * H (row-major, m <= 8): the spectral estimate of Section 2.2.1 taken from
+ * the Arnoldi Hessenberg matrix.  No device work. */
+int32_t amg_hessenberg_radius(const double* H, int32_t m, double* rho);
+
+/* (host) timing of the last setup and solve on this hierarchy, in ms, from
+ * HIP events on the hierarchy's stream. */
+int32_t amg_timings(const amg_hierarchy* h, double* setup_ms, double* solve_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMG_H */

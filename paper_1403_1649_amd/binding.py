@@ -1,0 +1,268 @@
+"""ctypes marshalling for the C ABI in include/amg.h (argument passing only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+AMG_OK, AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTCONV = 0, 1, 2, 3, 4
+AMG_EBREAKDOWN, AMG_ECOARSEN, AMG_ENANINF, AMG_EUNSUPPORTED = 5, 6, 7, 8
+_PREC = {"fp64": 0, "mixed": 1}
+_KRYLOV = {"fcg": 0, "fgmres": 1}
+
+EXPORTED = [
+    "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",
+    "amg_destroy", "amg_num_levels", "amg_level_info", "amg_export_level", "amg_spmv",
+    "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings",
+]
+
+
+class AmgOptionsC(C.Structure):
+    _fields_ = [
+        ("strength_alpha", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+        ("kcycle_levels", C.c_int32), ("kcycle_t", C.c_double), ("jacobi_scale", C.c_double),
+        ("arnoldi_m", C.c_int32), ("seed", C.c_uint32), ("krylov", C.c_int32),
+        ("gmres_restart", C.c_int32), ("precision", C.c_int32), ("smoother", C.c_int32),
+        ("max_iter", C.c_int32), ("dense_max", C.c_int32), ("check_every", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class AmgCsrC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class AmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{status_string(code)} ({msg})")
+        self.code = code
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libamg_hip.so")
+
+
+def lib():
+    """Load libamg_hip.so (after torch, so both share one HIP runtime)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the tensors use)
+    except ImportError:
+        pass
+    L = C.CDLL(path)
+    vp, i32, u32, dbl = C.c_void_p, C.c_int32, C.c_uint32, C.c_double
+    P = C.POINTER
+    L.amg_default_options.argtypes = [P(AmgOptionsC), i32]
+    L.amg_default_options.restype = None
+    L.amg_status_string.argtypes = [i32]
+    L.amg_status_string.restype = C.c_char_p
+    L.amg_last_error.argtypes = []
+    L.amg_last_error.restype = C.c_char_p
+    L.amg_setup.argtypes = [P(AmgCsrC), P(AmgOptionsC), vp, P(vp)]
+    L.amg_setup.restype = i32
+    L.amg_solve.argtypes = [vp, vp, dbl, vp, P(i32), P(dbl), vp]
+    L.amg_solve.restype = i32
+    L.amg_destroy.argtypes = [vp]
+    L.amg_destroy.restype = None
+    L.amg_num_levels.argtypes = [vp]
+    L.amg_num_levels.restype = i32
+    L.amg_level_info.argtypes = [vp, i32, P(i32), P(i32), P(dbl), P(i32), P(i32)]
+    L.amg_level_info.restype = i32
+    L.amg_export_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.amg_export_level.restype = i32
+    L.amg_spmv.argtypes = [P(AmgCsrC), vp, vp, i32, vp]
+    L.amg_spmv.restype = i32
+    L.amg_node_hash.argtypes = [i32, u32, vp, vp]
+    L.amg_node_hash.restype = i32
+    L.amg_galerkin.argtypes = [P(AmgCsrC), vp, vp, i32, P(i32), vp, vp, vp, i32, vp]
+    L.amg_galerkin.restype = i32
+    L.amg_hessenberg_radius.argtypes = [vp, i32, P(dbl)]
+    L.amg_hessenberg_radius.restype = i32
+    L.amg_timings.argtypes = [vp, P(dbl), P(dbl)]
+    L.amg_timings.restype = i32
+    _LIB = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return lib().amg_status_string(int(code)).decode()
+
+
+def _check(code: int, allow=(AMG_OK,)):
+    if code not in allow:
+        raise AmgError(code, lib().amg_last_error().decode())
+    return code
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+def _nptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+class Options:
+    """Setup/solve options (amg_options); keyword names follow the C struct."""
+
+    def __init__(self, dim: int = 3, **kw):
+        self.c = AmgOptionsC()
+        lib().amg_default_options(C.byref(self.c), int(dim))
+        for k, v in kw.items():
+            if k == "precision" and isinstance(v, str):
+                v = _PREC[v]
+            if k == "krylov" and isinstance(v, str):
+                v = _KRYLOV[v]
+            if not hasattr(self.c, k):
+                raise KeyError(k)
+            setattr(self.c, k, v)
+
+    def __getattr__(self, k):
+        return getattr(self.c, k)
+
+
+def default_options(dim: int = 3) -> Options:
+    return Options(dim)
+
+
+def _csr(row_ptr, col, val) -> AmgCsrC:
+    import torch
+    for t, dt in ((row_ptr, torch.int32), (col, torch.int32), (val, torch.float64)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError("CSR arrays must be contiguous CUDA tensors (int32, int32, float64)")
+    return AmgCsrC(int(row_ptr.numel() - 1), int(col.numel()), row_ptr.data_ptr(), col.data_ptr(),
+                   val.data_ptr())
+
+
+class Hierarchy:
+    """An amg_hierarchy handle (destroyed with the object)."""
+
+    def __init__(self, handle: C.c_void_p, n: int, opts: Options):
+        self._h = handle
+        self.n = n
+        self.opts = opts
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.amg_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_levels(self) -> int:
+        return lib().amg_num_levels(self._h)
+
+    def level_info(self, k: int) -> dict:
+        n, nnz, nc, rounds = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        om = C.c_double()
+        _check(lib().amg_level_info(self._h, k, C.byref(n), C.byref(nnz), C.byref(om), C.byref(nc),
+                                    C.byref(rounds)))
+        return {"n": n.value, "nnz": nnz.value, "omega": om.value, "nc": nc.value,
+                "mis_rounds": rounds.value}
+
+    def export_level(self, k: int, what=("A", "strong", "state", "agg", "pval", "B")) -> dict:
+        info = self.level_info(k)
+        n, nnz = info["n"], info["nnz"]
+        out = {}
+        bufs = {
+            "row_ptr": np.empty(n + 1, np.int32) if "A" in what else None,
+            "col": np.empty(nnz, np.int32) if "A" in what else None,
+            "val": np.empty(nnz, np.float64) if "A" in what else None,
+            "strong": np.empty(nnz, np.uint8) if "strong" in what else None,
+            "state": np.empty(n, np.int8) if "state" in what else None,
+            "agg": np.empty(n, np.int32) if "agg" in what else None,
+            "pval": np.empty(n, np.float64) if "pval" in what else None,
+            "B": np.empty(n, np.float64) if "B" in what else None,
+        }
+        args = [(_nptr(b) if b is not None else None) for b in bufs.values()]
+        _check(lib().amg_export_level(self._h, k, *args))
+        for key, b in bufs.items():
+            if b is not None:
+                out[key] = b
+        out.update(info)
+        return out
+
+    def timings(self):
+        s, v = C.c_double(), C.c_double()
+        _check(lib().amg_timings(self._h, C.byref(s), C.byref(v)))
+        return s.value, v.value
+
+
+def setup(row_ptr, col, val, opts: Options | None = None, dim: int = 3) -> Hierarchy:
+    """amg_setup on CUDA tensors; the current torch stream orders the work."""
+    opts = opts or Options(dim)
+    A = _csr(row_ptr, col, val)
+    h = C.c_void_p()
+    _check(lib().amg_setup(C.byref(A), C.byref(opts.c), _stream(), C.byref(h)))
+    return Hierarchy(h, A.n, opts)
+
+
+def solve(h: Hierarchy, b, rtol: float = 1e-8, x=None, allow_notconv: bool = False):
+    """amg_solve: returns (x, iters, relres)."""
+    import torch
+    if not (b.is_cuda and b.dtype == torch.float64 and b.is_contiguous() and b.numel() == h.n):
+        raise TypeError("b must be a contiguous CUDA float64 tensor of length n")
+    if x is None:
+        x = torch.empty_like(b)
+    it = C.c_int32()
+    rel = C.c_double()
+    code = lib().amg_solve(h.handle, _ptr(b), float(rtol), _ptr(x), C.byref(it), C.byref(rel), _stream())
+    _check(code, (AMG_OK, AMG_ENOTCONV) if allow_notconv else (AMG_OK,))
+    return x, it.value, rel.value
+
+
+def spmv(row_ptr, col, val, x, y=None, lanes_per_row: int = 0):
+    import torch
+    A = _csr(row_ptr, col, val)
+    if y is None:
+        y = torch.empty(A.n, dtype=torch.float64, device=x.device)
+    _check(lib().amg_spmv(C.byref(A), _ptr(x), _ptr(y), int(lanes_per_row), _stream()))
+    return y
+
+
+def node_hash(n: int, stream: int, device="cuda"):
+    import torch
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    _check(lib().amg_node_hash(int(n), int(stream) & 0xFFFFFFFF, _ptr(out), _stream()))
+    return out
+
+
+def galerkin(row_ptr, col, val, agg, pval, nc: int):
+    """amg_galerkin: returns (row_ptr_c, col_c, val_c) as NumPy arrays."""
+    A = _csr(row_ptr, col, val)
+    nnz = C.c_int32()
+    code = lib().amg_galerkin(C.byref(A), _ptr(agg), _ptr(pval), int(nc), C.byref(nnz), None, None, None,
+                              0, _stream())
+    if code != AMG_EINVAL or nnz.value <= 0:
+        _check(code)
+    rp = np.empty(nc + 1, np.int32)
+    ci = np.empty(nnz.value, np.int32)
+    v = np.empty(nnz.value, np.float64)
+    _check(lib().amg_galerkin(C.byref(A), _ptr(agg), _ptr(pval), int(nc), C.byref(nnz), _nptr(rp),
+                              _nptr(ci), _nptr(v), int(nnz.value), _stream()))
+    return rp, ci, v
+
+
+def hessenberg_radius(H: np.ndarray) -> float:
+    """Host-only: largest |eigenvalue| of a small upper Hessenberg matrix."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    rho = C.c_double()
+    _check(lib().amg_hessenberg_radius(_nptr(H), int(H.shape[0]), C.byref(rho)))
+    return rho.value

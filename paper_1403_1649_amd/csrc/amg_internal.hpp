@@ -1,0 +1,213 @@
+// Internal host-side declarations of the aggregation-AMG library: status
+// handling, the device arena, the level / hierarchy records and the kernel
+// launchers implemented in the .hip translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/amg.h"
+
+namespace amg {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define AMG_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::amg::Error(AMG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Device error bits raised by kernels (atomic OR into one int per hierarchy).
+enum : int {
+  kErrZeroDiag = 1,
+  kErrNonSymPattern = 2,
+  kErrNonFinite = 4,
+  kErrCountOverflow = 8,
+  kErrUnassigned = 16,
+  kErrSingular = 32,
+  kErrBreakdown = 64,
+  kErrBadColumn = 128,
+};
+
+// ---------------------------------------------------------------- memory
+// Device memory for one hierarchy: large chunks, bump-allocated with 256-byte
+// alignment, returned to a process-wide cache on destruction so that repeated
+// setups do not pay hipMalloc again.
+class Arena {
+ public:
+  Arena() = default;
+  ~Arena();
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  void reserve(size_t bytes);
+  void* alloc(size_t bytes);
+  template <typename T>
+  T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  size_t used() const { return used_; }
+
+ private:
+  struct Chunk { char* base; size_t size; size_t off; };
+  std::vector<Chunk> chunks_;
+  size_t used_ = 0;
+};
+
+// ---------------------------------------------------------------- records
+struct Level {
+  // A_k (float64, device); val32 is the float32 copy used by the mixed cycle
+  int n = 0, nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  double* diag = nullptr;      // a_ii
+  double* B = nullptr;         // near null space vector B_k
+  int lpr = 8;                 // lanes per row of the level's SpMV kernels
+  // setup products (absent on the coarsest level)
+  uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
+  uint64_t* tuple = nullptr;   // final MIS(2) tuples (state in the top two bits)
+  int mis_rounds = 0;
+  int nc = 0;                  // n_{k+1}
+  int* agg = nullptr;          // aggregate index per fine node
+  int* agg_ptr = nullptr;      // aggregate segments: rows of aggregate I are
+  int* agg_rows = nullptr;     //   agg_rows[agg_ptr[I] .. agg_ptr[I+1]) ascending
+  double* pval = nullptr;      // the single nonzero of row i of P_k
+  float* pval32 = nullptr;
+  double omega = 0.0, rho = 0.0;
+  double* wdinv = nullptr;     // omega / a_ii
+  float* wdinv32 = nullptr;
+  // solve scratch (typed by the cycle precision; size n or n_{k+1})
+  void* r = nullptr;           // fine residual
+  void* xt = nullptr;          // fine iterate inside the cycle
+  void* rc = nullptr;          // restricted residual
+  void* c = nullptr;           // first inner correction (or the V-cycle correction)
+  void* v = nullptr;           // A_{k+1} c
+  void* rt = nullptr;          // r~
+  void* d = nullptr;           // second inner correction
+  void* w = nullptr;           // A_{k+1} d
+};
+
+struct Hierarchy {
+  amg_options opt{};
+  std::vector<Level> levels;
+  Arena arena;
+  hipStream_t stream = nullptr;
+  int dim_hint = 3;
+  // coarsest level: explicit inverse (row-major n_L x n_L)
+  double* cinv = nullptr;
+  float* cinv32 = nullptr;
+  // device control block
+  int* d_err = nullptr;        // error bits
+  int* d_ctl = nullptr;        // integer control words (flags, counters)
+  double* d_sc = nullptr;      // scalar slots (dots, coefficients)
+  double* d_part = nullptr;    // per-block partial sums of reductions
+  unsigned* d_ticket = nullptr;// last-block tickets
+  int* d_scan = nullptr;       // block sums of device scans
+  // pinned host mirror for read-backs
+  void* h_pinned = nullptr;
+  // outer solve vectors (float64, size n_0)
+  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  void* z = nullptr;           // preconditioned residual (cycle precision)
+  void* bz = nullptr;          // cycle right-hand side in cycle precision (mixed mode)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  float setup_ms = 0.f, solve_ms = 0.f;
+  bool mixed() const { return opt.precision == AMG_PREC_MIXED; }
+  int L() const { return (int)levels.size() - 1; }
+  ~Hierarchy();
+};
+
+// Slots of the device control block.
+enum CtlWord : int {
+  kCtlRunning = 0,     // outer iteration active
+  kCtlIters = 1,       // outer iterations performed
+  kCtlMisPing = 2,     // undecided counters of MIS(2) rounds (two words)
+  kCtlMisRounds = 4,   // rounds that found undecided nodes
+  kCtlOne = 5,         // constant 1 (an always-active flag)
+  kCtlAggFill = 6,     // scratch counter
+  kCtlKFlags = 16,     // per level k: [16 + 4k] step-2 flag, [17 + 4k] use-d flag
+  kCtlWords = 128,
+};
+enum ScSlot : int {
+  kScBB = 0, kScRtol2 = 1, kScAlpha = 2, kScBeta = 3, kScPQ = 4, kScRR = 5,
+  kScTrue = 6, kScArn = 8,     // Arnoldi: [8 .. 8+64)
+  kScK = 80,                   // per level k: 16 slots from 80 + 16k
+  kScWords = 80 + 16 * 24,
+};
+enum KSlot : int {
+  kKRho1 = 0, kKAlpha1 = 1, kKRcRc = 2, kKRtRt = 3, kKGamma = 4, kKBeta = 5,
+  kKAlpha2 = 6, kKCoefC = 7, kKCoefD = 8,
+};
+constexpr int kMaxPartialBlocks = 2048;
+
+// ---------------------------------------------------------------- launchers
+// scan.hip
+void scan_to_ptr(const int* counts, int* ptr, int n, int* block_sums, hipStream_t s);
+int scan_blocks_needed(int n);
+
+// setup_kernels.hip
+void launch_check_rowptr(int n, const int* rp, int* err, hipStream_t s);
+void launch_check_index(int n, const int* idx, int limit, int* err, hipStream_t s);
+void launch_check_matrix(int n, const int* rp, const int* ci, const double* val, int* err, hipStream_t s);
+void launch_strength(int n, const int* rp, const int* ci, const double* val, double alpha,
+                     uint8_t* strong, double* diag, int* err, hipStream_t s);
+void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* strong,
+                        uint8_t* gmask, int* gdeg, int* cnt, int* err, hipStream_t s);
+void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask,
+                       const int* gptr, int* gcol, hipStream_t s);
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s);
+void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1,
+                      int* ctl, int round, hipStream_t s);
+void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
+void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T,
+                      const int* root_id, int* choice, int* agg, int* err, hipStream_t s);
+void launch_agg_count(int n, const int* agg, int* counts, hipStream_t s);
+void launch_agg_scatter(int n, const int* agg, const int* agg_ptr, int* fill, int* agg_rows, hipStream_t s);
+void launch_agg_sort(int nc, const int* agg_ptr, int* agg_rows, hipStream_t s);
+void launch_interp(int n, int nc, const int* agg, const int* agg_ptr, const int* agg_rows,
+                   const double* B, double* Bc, double* pval, hipStream_t s);
+void launch_node_hash(int n, uint32_t stream, uint32_t* out, hipStream_t s);
+void launch_jacobi_weights(int n, double omega, const double* diag, double* wdinv, float* wdinv32, hipStream_t s);
+void launch_to_float(size_t n, const double* in, float* out, hipStream_t s);
+void launch_state_from_tuple(int n, const uint64_t* T, int8_t* state, hipStream_t s);
+void launch_fill_int(size_t n, int* p, int v, hipStream_t s);
+void launch_fill_double(size_t n, double* p, double v, hipStream_t s);
+
+// galerkin.hip
+void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
+                           const int* agg_rows, int* row_count, int* ovf_list, int* ctl_ovf, hipStream_t s);
+void launch_galerkin_fill(int nc, const int* rp, const int* ci, const double* val, const int* agg,
+                          const double* pval, const int* agg_ptr, const int* agg_rows,
+                          const int* rp_c, int* ci_c, double* val_c, const int* ovf_list,
+                          const int* ctl_ovf, hipStream_t s);
+
+// dense.hip
+void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val, double* work,
+                          double* inv, float* inv32, int* sync, int* err, hipStream_t s);
+
+// arnoldi / reductions (solve_kernels.hip)
+void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double* w, double* H_out,
+             double* wnorm_out);
+
+// cycle and outer solvers (solver.hip)
+int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
+void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
+              int lpr, hipStream_t s);
+int pick_lanes_per_row(int n, int nnz);
+
+// host runtime (hierarchy.cpp)
+double hessenberg_spectral_radius(const double* H, int m);
+void init_control(Hierarchy& h);
+void build_hierarchy(Hierarchy& h, const amg_csr& A);
+void galerkin_standalone(Hierarchy& h, const amg_csr& A, const int* agg, const double* pval, int nc,
+                         int* nnz_c, int** rp_c, int** ci_c, double** val_c);
+
+}  // namespace amg

@@ -1,0 +1,256 @@
+// extern "C" entry points declared in include/amg.h.  Argument checks on the
+// host, then the internal runtime; no exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+
+#include "amg_internal.hpp"
+
+struct amg_hierarchy {
+  amg::Hierarchy h;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_last_error = msg;
+  if (std::getenv("AMG_VERBOSE")) std::fprintf(stderr, "amg: %s\n", msg.c_str());
+  return code;
+}
+
+int32_t run_guarded(const char* where, void (*fn)(void*), void* ctx) {
+  try {
+    fn(ctx);
+    return AMG_OK;
+  } catch (const amg::Error& e) {
+    return fail(e.code, std::string(where) + ": " + e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(AMG_ENOMEM, std::string(where) + ": host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(AMG_EHIP, std::string(where) + ": " + e.what());
+  }
+}
+
+template <class F>
+int32_t guarded(const char* where, F&& f) {
+  return run_guarded(where, [](void* c) { (*static_cast<F*>(c))(); }, &f);
+}
+
+bool csr_args_ok(const amg_csr* A) {
+  return A && A->n > 0 && A->nnz >= A->n && A->row_ptr && A->col_idx && A->val;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amg_default_options(amg_options* opt, int32_t dim) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->strength_alpha = dim == 2 ? 0.25 : 0.5;
+  opt->coarse_max = 600;
+  opt->max_levels = 20;
+  opt->kcycle_levels = 2;
+  opt->kcycle_t = 0.25;
+  opt->jacobi_scale = 4.0 / 3.0;
+  opt->arnoldi_m = 5;
+  opt->seed = 0;
+  opt->krylov = AMG_KRYLOV_FCG;
+  opt->gmres_restart = 30;
+  opt->precision = AMG_PREC_FP64;
+  opt->smoother = AMG_SMOOTHER_JACOBI;
+  opt->max_iter = 200;
+  opt->dense_max = 4096;
+  opt->check_every = 1;
+  opt->flags = 0;
+}
+
+const char* amg_status_string(int32_t status) {
+  switch (status) {
+    case AMG_OK: return "AMG_OK";
+    case AMG_EINVAL: return "AMG_EINVAL: invalid argument or matrix";
+    case AMG_ENOMEM: return "AMG_ENOMEM: allocation failed";
+    case AMG_EHIP: return "AMG_EHIP: HIP runtime error";
+    case AMG_ENOTCONV: return "AMG_ENOTCONV: iteration limit reached";
+    case AMG_EBREAKDOWN: return "AMG_EBREAKDOWN: breakdown";
+    case AMG_ECOARSEN: return "AMG_ECOARSEN: coarsening failed";
+    case AMG_ENANINF: return "AMG_ENANINF: non-finite value";
+    case AMG_EUNSUPPORTED: return "AMG_EUNSUPPORTED: unsupported option";
+    default: return "AMG: unknown status";
+  }
+}
+
+const char* amg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_hierarchy** out) {
+  if (!out) return fail(AMG_EINVAL, "amg_setup: out is NULL");
+  *out = nullptr;
+  if (!csr_args_ok(A)) return fail(AMG_EINVAL, "amg_setup: bad matrix descriptor");
+  amg_options o;
+  if (opt) o = *opt; else amg_default_options(&o, 3);
+  if (!(o.strength_alpha >= 0.0) || o.coarse_max < 1 || o.max_levels < 1 || o.kcycle_levels < 0 ||
+      !(o.kcycle_t >= 0.0) || !(o.jacobi_scale > 0.0) || o.arnoldi_m < 1 || o.arnoldi_m > 5 ||
+      o.max_iter < 0 || o.dense_max < 1 || o.dense_max > 8192)
+    return fail(AMG_EINVAL, "amg_setup: option out of range");
+  if (o.krylov != AMG_KRYLOV_FCG) return fail(AMG_EUNSUPPORTED, "amg_setup: only flexible CG is built");
+  if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
+    return fail(AMG_EINVAL, "amg_setup: unknown precision");
+  if (o.smoother != AMG_SMOOTHER_JACOBI) return fail(AMG_EUNSUPPORTED, "amg_setup: smoother");
+  auto* H = new (std::nothrow) amg_hierarchy();
+  if (!H) return fail(AMG_ENOMEM, "amg_setup: host allocation");
+  int32_t st = guarded("amg_setup", [&] {
+    amg::Hierarchy& h = H->h;
+    h.opt = o;
+    h.stream = s;
+    for (auto& e : h.ev) AMG_HIP(hipEventCreate(&e));
+    AMG_HIP(hipEventRecord(h.ev[0], s));
+    amg::init_control(h);
+    amg::build_hierarchy(h, *A);
+    AMG_HIP(hipEventRecord(h.ev[1], s));
+    AMG_HIP(hipEventSynchronize(h.ev[1]));
+    AMG_HIP(hipEventElapsedTime(&h.setup_ms, h.ev[0], h.ev[1]));
+  });
+  if (st != AMG_OK) {
+    delete H;
+    return st;
+  }
+  *out = H;
+  return AMG_OK;
+}
+
+int32_t amg_solve(amg_hierarchy* H, const double* b, double rtol, double* x, int32_t* iters, double* relres,
+                  hipStream_t s) {
+  if (!H || !b || !x || !iters || !relres) return fail(AMG_EINVAL, "amg_solve: NULL argument");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(AMG_EINVAL, "amg_solve: rtol must be positive");
+  int32_t status = AMG_OK;
+  int32_t st = guarded("amg_solve", [&] {
+    amg::Hierarchy& h = H->h;
+    h.stream = s;
+    AMG_HIP(hipEventRecord(h.ev[2], s));
+    int it = 0;
+    double rel = 0.0;
+    status = amg::solve_fcg_impl(h, b, rtol, x, &it, &rel);
+    AMG_HIP(hipEventRecord(h.ev[3], s));
+    AMG_HIP(hipEventSynchronize(h.ev[3]));
+    AMG_HIP(hipEventElapsedTime(&h.solve_ms, h.ev[2], h.ev[3]));
+    *iters = it;
+    *relres = rel;
+  });
+  if (st != AMG_OK) return st;
+  if (status != AMG_OK) return fail(status, "amg_solve: iteration limit reached");
+  return AMG_OK;
+}
+
+void amg_destroy(amg_hierarchy* H) { delete H; }
+
+int32_t amg_num_levels(const amg_hierarchy* H) { return H ? (int32_t)H->h.levels.size() : 0; }
+
+int32_t amg_level_info(const amg_hierarchy* H, int32_t k, int32_t* n, int32_t* nnz, double* omega,
+                       int32_t* n_coarse, int32_t* mis_rounds) {
+  if (!H || k < 0 || k >= (int32_t)H->h.levels.size()) return fail(AMG_EINVAL, "amg_level_info: level");
+  const amg::Level& lv = H->h.levels[k];
+  const bool coarsest = k == (int32_t)H->h.levels.size() - 1;
+  if (n) *n = lv.n;
+  if (nnz) *nnz = lv.nnz;
+  if (omega) *omega = coarsest ? 0.0 : lv.omega;
+  if (n_coarse) *n_coarse = coarsest ? 0 : lv.nc;
+  if (mis_rounds) *mis_rounds = coarsest ? 0 : lv.mis_rounds;
+  return AMG_OK;
+}
+
+int32_t amg_export_level(const amg_hierarchy* H, int32_t k, int32_t* row_ptr, int32_t* col_idx, double* val,
+                         uint8_t* strong, int8_t* state, int32_t* agg, double* pval, double* B) {
+  if (!H || k < 0 || k >= (int32_t)H->h.levels.size()) return fail(AMG_EINVAL, "amg_export_level: level");
+  const amg::Hierarchy& h = H->h;
+  const amg::Level& lv = h.levels[k];
+  const bool coarsest = k == (int32_t)h.levels.size() - 1;
+  if (coarsest && (strong || state || agg || pval))
+    return fail(AMG_EINVAL, "amg_export_level: the coarsest level has no aggregation");
+  return guarded("amg_export_level", [&] {
+    hipStream_t s = h.stream;
+    if (row_ptr) AMG_HIP(hipMemcpyAsync(row_ptr, lv.rp, (lv.n + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (col_idx) AMG_HIP(hipMemcpyAsync(col_idx, lv.ci, (size_t)lv.nnz * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (val) AMG_HIP(hipMemcpyAsync(val, lv.val, (size_t)lv.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (strong) AMG_HIP(hipMemcpyAsync(strong, lv.strong, (size_t)lv.nnz, hipMemcpyDeviceToHost, s));
+    if (agg) AMG_HIP(hipMemcpyAsync(agg, lv.agg, (size_t)lv.n * sizeof(int), hipMemcpyDeviceToHost, s));
+    if (pval) AMG_HIP(hipMemcpyAsync(pval, lv.pval, (size_t)lv.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (B) AMG_HIP(hipMemcpyAsync(B, lv.B, (size_t)lv.n * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (state) {
+      int8_t* dst = nullptr;
+      AMG_HIP(hipMallocAsync((void**)&dst, lv.n, s));
+      amg::launch_state_from_tuple(lv.n, lv.tuple, dst, s);
+      AMG_HIP(hipMemcpyAsync(state, dst, lv.n, hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipFreeAsync(dst, s));
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s) {
+  if (!csr_args_ok(A) || !x || !y) return fail(AMG_EINVAL, "amg_spmv: bad argument");
+  if (lanes_per_row < 0 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1)))
+    return fail(AMG_EINVAL, "amg_spmv: lanes_per_row must be 0 or a power of two <= 64");
+  return guarded("amg_spmv", [&] {
+    amg::spmv_f64(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, x, y, lanes_per_row, s);
+    AMG_HIP(hipGetLastError());
+  });
+}
+
+int32_t amg_node_hash(int32_t n, uint32_t stream, uint32_t* out, hipStream_t s) {
+  if (n < 0 || (n > 0 && !out)) return fail(AMG_EINVAL, "amg_node_hash: bad argument");
+  return guarded("amg_node_hash", [&] {
+    amg::launch_node_hash(n, stream, out, s);
+    AMG_HIP(hipGetLastError());
+  });
+}
+
+int32_t amg_galerkin(const amg_csr* A, const int32_t* agg, const double* pval, int32_t nc, int32_t* nnz_c,
+                     int32_t* row_ptr_c, int32_t* col_c, double* val_c, int32_t cap, hipStream_t s) {
+  if (!csr_args_ok(A) || !agg || !pval || nc < 1 || nc > A->n || !nnz_c)
+    return fail(AMG_EINVAL, "amg_galerkin: bad argument");
+  int32_t too_small = 0;
+  int32_t st = guarded("amg_galerkin", [&] {
+    amg::Hierarchy h;
+    h.stream = s;
+    h.opt.dense_max = 1;
+    amg::init_control(h);
+    h.d_scan = h.arena.alloc_n<int>(amg::scan_blocks_needed(A->nnz > A->n ? A->nnz : A->n) + 2);
+    int *rp = nullptr, *ci = nullptr;
+    double* v = nullptr;
+    int nz = 0;
+    amg::galerkin_standalone(h, *A, agg, pval, nc, &nz, &rp, &ci, &v);
+    *nnz_c = nz;
+    if (cap < nz || !row_ptr_c || !col_c || !val_c) {
+      too_small = 1;
+      return;
+    }
+    AMG_HIP(hipMemcpyAsync(row_ptr_c, rp, (nc + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(col_c, ci, (size_t)nz * sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(val_c, v, (size_t)nz * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  });
+  if (st != AMG_OK) return st;
+  if (too_small) return fail(AMG_EINVAL, "amg_galerkin: output capacity too small");
+  return AMG_OK;
+}
+
+int32_t amg_hessenberg_radius(const double* H, int32_t m, double* rho) {
+  if (!H || !rho || m < 1 || m > 8) return fail(AMG_EINVAL, "amg_hessenberg_radius: bad argument");
+  *rho = amg::hessenberg_spectral_radius(H, m);
+  return AMG_OK;
+}
+
+int32_t amg_timings(const amg_hierarchy* H, double* setup_ms, double* solve_ms) {
+  if (!H) return fail(AMG_EINVAL, "amg_timings: NULL hierarchy");
+  if (setup_ms) *setup_ms = H->h.setup_ms;
+  if (solve_ms) *solve_ms = H->h.solve_ms;
+  return AMG_OK;
+}
+
+}  // extern "C"

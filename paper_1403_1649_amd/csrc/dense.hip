@@ -1,0 +1,182 @@
+// Coarsest-level exact solve (Algorithms 4/5, "exact solution of coarse
+// grid"; Section 3 keeps that level near 600 unknowns).  The dense A_L is
+// inverted once in setup by Gauss-Jordan elimination with partial pivoting,
+// so each coarse solve in the cycle is one dense mat-vec (a GEMV over at most
+// dense_max^2 entries) instead of two sequential triangular solves.
+//
+// The elimination runs as one cooperative kernel: each block owns a band of
+// columns of the row-major work matrix; per pivot step the owner of column k
+// picks the pivot and publishes column k, one grid barrier, then every block
+// updates its band.  A single block needs no grid barrier at all.
+#include <hip/hip_cooperative_groups.h>
+
+#include <cmath>
+
+#include "amg_internal.hpp"
+#include "device_utils.hpp"
+
+namespace amg {
+
+namespace {
+constexpr int kGJThreads = 1024;
+
+__global__ void k_dense_zero(size_t nn, double* W) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t st = (size_t)gridDim.x * blockDim.x;
+  for (; i < nn; i += st) W[i] = 0.0;
+}
+
+__global__ void k_dense_scatter(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ val, double* __restrict__ W) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) W[(size_t)i * n + ci[k]] = val[k];
+}
+
+__device__ __forceinline__ void grid_barrier(int* sync, int nblocks) {
+  if (nblocks == 1) {
+    __syncthreads();
+    return;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int gen = __hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const int arrived = __hip_atomic_fetch_add(&sync[0], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&sync[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&sync[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen)
+        __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// In-place Gauss-Jordan inversion of the n x n row-major W.  piv[k] records
+// the row exchanged with row k at step k; colbuf holds 2 x n doubles.
+__global__ void __launch_bounds__(kGJThreads) k_gauss_jordan(int n, int band, double* __restrict__ W,
+                                                             int* __restrict__ piv,
+                                                             double* __restrict__ colbuf, int* sync,
+                                                             int* err) {
+  __shared__ double s_rowk[1024];
+  __shared__ double s_val[kGJThreads / kWave];
+  __shared__ int s_idx[kGJThreads / kWave];
+  const int nb = gridDim.x;
+  const int c0 = blockIdx.x * band;
+  const int c1 = min(n, c0 + band);
+  const int w = c1 - c0;
+  for (int k = 0; k < n; ++k) {
+    double* cb = colbuf + (size_t)(k & 1) * n;
+    const int owner = k / band;
+    if ((int)blockIdx.x == owner) {
+      // pivot: the largest |W[i][k]| over rows i >= k (smallest index on ties)
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double a = fabs(W[(size_t)i * n + k]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if ((threadIdx.x & (kWave - 1)) == 0) {
+        s_val[threadIdx.x / kWave] = best;
+        s_idx[threadIdx.x / kWave] = bi;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x / kWave); ++q)
+          if (s_val[q] > best || (s_val[q] == best && s_idx[q] < bi)) { best = s_val[q]; bi = s_idx[q]; }
+        piv[k] = bi;
+        if (!(best > 0.0)) atomic_or_flag(err, kErrSingular);
+      }
+      for (int i = threadIdx.x; i < n; i += blockDim.x) cb[i] = W[(size_t)i * n + k];
+    }
+    grid_barrier(sync, nb);
+    const int p = __hip_atomic_load(&piv[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // column k after the exchange of rows k and p
+    const double ck = cb[p];
+    // exchange rows k and p inside this band, keep the (exchanged) row k
+    for (int j = threadIdx.x; j < w; j += blockDim.x) {
+      const int col = c0 + j;
+      double a = W[(size_t)k * n + col];
+      if (p != k) {
+        const double b = W[(size_t)p * n + col];
+        W[(size_t)p * n + col] = a;
+        a = b;
+      }
+      s_rowk[j] = a;
+    }
+    __syncthreads();
+    const double inv = 1.0 / ck;
+    for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
+      const int i = e / w;
+      const int j = e - i * w;
+      const int col = c0 + j;
+      const double ci = (i == k) ? ck : (i == p ? cb[k] : cb[i]);
+      double* dst = W + (size_t)i * n + col;
+      if (col == k) {
+        *dst = (i == k) ? inv : -ci * inv;
+      } else if (i == k) {
+        *dst = s_rowk[j] * inv;
+      } else {
+        *dst -= ci * (s_rowk[j] * inv);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Undo the row exchanges as column exchanges (last step first) and emit the
+// float64 and float32 inverses.
+__global__ void k_gj_unpermute(int n, const double* __restrict__ W, const int* __restrict__ piv,
+                               double* __restrict__ inv, float* __restrict__ inv32, int* perm_tmp) {
+  extern __shared__ int s_perm[];
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < n; ++j) s_perm[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = piv[k];
+      const int t = s_perm[k];
+      s_perm[k] = s_perm[p];
+      s_perm[p] = t;
+    }
+  }
+  __syncthreads();
+  (void)perm_tmp;
+  const size_t nn = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n);
+    const int j = (int)(e - (size_t)i * n);
+    const double v = W[(size_t)i * n + s_perm[j]];
+    inv[e] = v;
+    if (inv32) inv32[e] = (float)v;
+  }
+}
+}  // namespace
+
+void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val, double* work, double* inv,
+                          float* inv32, int* sync, int* err, hipStream_t s) {
+  const size_t nn = (size_t)n * n;
+  k_dense_zero<<<(int)std::min<size_t>((nn + 255) / 256, 4096), 256, 0, s>>>(nn, work);
+  k_dense_scatter<<<(n + 255) / 256, 256, 0, s>>>(n, rp, ci, val, work);
+  // band of columns per block: at most 1024 (the LDS copy of pivot row k)
+  int nb = (int)std::min<long>(64, std::max<long>(1, (long)nn / 16384));
+  int band = (n + nb - 1) / nb;
+  if (band > 1024) band = 1024;
+  nb = (n + band - 1) / band;
+  int* piv = sync + 4;
+  double* colbuf = work + nn;
+  launch_fill_int(4, sync, 0, s);
+  void* args[] = {(void*)&n, (void*)&band, (void*)&work, (void*)&piv, (void*)&colbuf, (void*)&sync,
+                  (void*)&err};
+  AMG_HIP(hipLaunchCooperativeKernel((const void*)k_gauss_jordan, dim3(nb), dim3(kGJThreads), args, 0, s));
+  const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
+  k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
+}
+
+}  // namespace amg

@@ -1,0 +1,117 @@
+// Device-side primitives shared by the HIP kernels (wave64 CDNA4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amg {
+
+constexpr int kWave = 64;
+
+// MurmurHash3 32-bit finaliser: a bijection of uint32 (every step invertible).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Seeded counter hash of a node index: fmix32(i + stream * 0x9E3779B9 mod 2^32).
+__device__ __forceinline__ uint32_t node_hash(uint32_t i, uint32_t stream) {
+  return fmix32(i + stream * 0x9E3779B9u);
+}
+
+// Exact float64 in [-1, 1): hash * 2^-31 - 1.
+__device__ __forceinline__ double unit_uniform(uint32_t i, uint32_t stream) {
+  return (double)node_hash(i, stream) * 4.656612873077392578125e-10 - 1.0;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over a sub-group of G consecutive lanes (G a power of two <= 64);
+// the result is valid in every lane of the group.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// Block-wide sum of NV values (fixed combination order: lanes, then waves).
+// `red` must hold NV * (blockDim.x / 64) doubles of LDS.  Result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[k * nw + w];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Exclusive scan of one int per thread over the block; returns the exclusive
+// prefix, *total receives the block sum (valid in all threads).
+// `tmp` must hold blockDim.x/64 + 1 ints of LDS.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (lane == kWave - 1) tmp[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < nw; ++w) {
+      int t = tmp[w];
+      tmp[w] = run;
+      run += t;
+    }
+    tmp[nw] = run;
+  }
+  __syncthreads();
+  int res = incl - v + tmp[wid];
+  *total = tmp[nw];
+  __syncthreads();
+  return res;
+}
+
+// Device-scope atomic helpers.
+__device__ __forceinline__ void atomic_or_flag(int* p, int bits) {
+  __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int load_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace amg

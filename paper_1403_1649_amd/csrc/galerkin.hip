@@ -1,0 +1,211 @@
+// Galerkin product by aggregate index (Section 3.1, eq. galerkin):
+//   (A_{k+1})_IJ = sum_{i in G_I} sum_{j in G_J} P_iI A_ij P_jJ.
+// Instead of a global sort of all (I, J) tuples, each coarse row I is built
+// from its own aggregate segment G_I: the terms (J, (P_iI a_ij) P_jJ) of the
+// segment's fine rows are staged in LDS, unique J are found with an LDS hash
+// (first occurrence wins, so the result does not depend on timing), and each
+// coarse entry is the sum of its terms in segment order.  A count pass sizes
+// the rows, a scan makes the row pointers, a fill pass writes sorted columns.
+// Rows whose segment holds more than kCap terms go to a block-per-row path
+// that extracts the distinct J in ascending order without staging.
+#include <climits>
+
+#include "amg_internal.hpp"
+#include "device_utils.hpp"
+
+namespace amg {
+
+namespace {
+constexpr int kCap = 256;       // staged terms per coarse row (fast path)
+constexpr int kHashBits = 9;
+constexpr int kHash = 1 << kHashBits;
+constexpr int kBig = 256;       // threads per block on the large-row path
+
+__device__ __forceinline__ int hslot(int J) {
+  return (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - kHashBits));
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(kWave) k_galerkin_wave(
+    int nc, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+    const int* __restrict__ agg, const double* __restrict__ pval, const int* __restrict__ agg_ptr,
+    const int* __restrict__ agg_rows, int* __restrict__ row_count, int* __restrict__ ovf_list,
+    int* __restrict__ ovf_count, const int* __restrict__ rp_c, int* __restrict__ ci_c,
+    double* __restrict__ val_c) {
+  __shared__ int keys[kCap];
+  __shared__ double vals[FILL ? kCap : 1];
+  __shared__ int hkey[kHash];
+  __shared__ int hfirst[kHash];
+  __shared__ int ukeys[kCap];
+  __shared__ int s_cnt;
+  const int I = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int sb = agg_ptr[I], se = agg_ptr[I + 1];
+
+  int T = 0;
+  for (int base = sb; base < se; base += kWave) {
+    int k = base + lane;
+    int len = 0;
+    if (k < se) { int i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
+    T += wave_sum_int(len);
+  }
+  if (T > kCap) {
+    if (!FILL && lane == 0) {
+      int p = atomicAdd(ovf_count, 1);
+      ovf_list[p] = I;
+    }
+    return;
+  }
+  for (int s = lane; s < kHash; s += kWave) { hkey[s] = -1; hfirst[s] = INT_MAX; }
+  if (lane == 0) s_cnt = 0;
+
+  // stage the terms in segment order (row by row, entries in column order)
+  int off = 0;
+  for (int base = sb; base < se; base += kWave) {
+    int k = base + lane;
+    int i = -1, len = 0;
+    if (k < se) { i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      int t = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += t;
+    }
+    int pos = off + incl - len;
+    if (i >= 0) {
+      const double pi = FILL ? pval[i] : 0.0;
+      for (int e = rp[i]; e < rp[i + 1]; ++e, ++pos) {
+        int j = ci[e];
+        keys[pos] = agg[j];
+        if (FILL) vals[pos] = __dmul_rn(__dmul_rn(pi, val[e]), pval[j]);
+      }
+    }
+    off += __shfl(incl, kWave - 1, kWave);
+  }
+  __syncthreads();
+
+  for (int t = lane; t < T; t += kWave) {
+    int J = keys[t];
+    int s = hslot(J);
+    while (true) {
+      int prev = atomicCAS(&hkey[s], -1, J);
+      if (prev == -1 || prev == J) { atomicMin(&hfirst[s], t); break; }
+      s = (s + 1) & (kHash - 1);
+    }
+  }
+  __syncthreads();
+  for (int t = lane; t < T; t += kWave) {
+    int J = keys[t];
+    int s = hslot(J);
+    while (hkey[s] != J) s = (s + 1) & (kHash - 1);
+    if (hfirst[s] == t) ukeys[atomicAdd(&s_cnt, 1)] = J;
+  }
+  __syncthreads();
+  const int U = s_cnt;
+  if (!FILL) {
+    if (lane == 0) row_count[I] = U;
+    return;
+  }
+  const int out0 = rp_c[I];
+  for (int u = lane; u < U; u += kWave) {
+    const int J = ukeys[u];
+    int rank = 0;
+    for (int v = 0; v < U; ++v) rank += ukeys[v] < J;
+    double s = 0.0;
+    for (int t = 0; t < T; ++t)
+      if (keys[t] == J) s = __dadd_rn(s, vals[t]);
+    ci_c[out0 + rank] = J;
+    val_c[out0 + rank] = s;
+  }
+}
+
+__device__ __forceinline__ int block_min_int(int v, int* red) {
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    int o = __shfl_xor(v, off, kWave);
+    v = o < v ? o : v;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int w = 1; w < kBig / kWave; ++w) r = red[w] < r ? red[w] : r;
+  __syncthreads();
+  return r;
+}
+
+// Large coarse rows: repeatedly take the smallest J above the last one over
+// all terms of the segment, then sum its terms (fixed thread assignment and
+// reduction order).  Grid-strides over the overflow list.
+template <bool FILL>
+__global__ void __launch_bounds__(kBig) k_galerkin_big(
+    const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
+    const int* __restrict__ agg, const double* __restrict__ pval, const int* __restrict__ agg_ptr,
+    const int* __restrict__ agg_rows, int* __restrict__ row_count, const int* __restrict__ ovf_list,
+    const int* __restrict__ ovf_count, const int* __restrict__ rp_c, int* __restrict__ ci_c,
+    double* __restrict__ val_c) {
+  __shared__ int ired[kBig / kWave];
+  __shared__ double dred[kBig / kWave];
+  const int count = *ovf_count;
+  for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int I = ovf_list[idx];
+    const int sb = agg_ptr[I], se = agg_ptr[I + 1];
+    const int out0 = FILL ? rp_c[I] : 0;
+    int last = -1, U = 0;
+    while (true) {
+      int mn = INT_MAX;
+      for (int k = sb + threadIdx.x; k < se; k += kBig) {
+        int i = agg_rows[k];
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+          int J = agg[ci[e]];
+          if (J > last && J < mn) mn = J;
+        }
+      }
+      mn = block_min_int(mn, ired);
+      if (mn == INT_MAX) break;
+      if (FILL) {
+        double s = 0.0;
+        for (int k = sb + threadIdx.x; k < se; k += kBig) {
+          int i = agg_rows[k];
+          double pi = pval[i];
+          for (int e = rp[i]; e < rp[i + 1]; ++e) {
+            int j = ci[e];
+            if (agg[j] == mn) s = __dadd_rn(s, __dmul_rn(__dmul_rn(pi, val[e]), pval[j]));
+          }
+        }
+        double v[1] = {s};
+        block_sum<1>(v, dred);
+        if (threadIdx.x == 0) {
+          ci_c[out0 + U] = mn;
+          val_c[out0 + U] = v[0];
+        }
+      }
+      ++U;
+      last = mn;
+    }
+    if (!FILL && threadIdx.x == 0) row_count[I] = U;
+    __syncthreads();
+  }
+}
+}  // namespace
+
+void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
+                           const int* agg_rows, int* row_count, int* ovf_list, int* ctl_ovf, hipStream_t s) {
+  if (nc <= 0) return;
+  launch_fill_int(1, ctl_ovf, 0, s);
+  k_galerkin_wave<false><<<nc, kWave, 0, s>>>(nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows,
+                                              row_count, ovf_list, ctl_ovf, nullptr, nullptr, nullptr);
+  k_galerkin_big<false><<<256, kBig, 0, s>>>(rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows,
+                                             row_count, ovf_list, ctl_ovf, nullptr, nullptr, nullptr);
+}
+
+void launch_galerkin_fill(int nc, const int* rp, const int* ci, const double* val, const int* agg,
+                          const double* pval, const int* agg_ptr, const int* agg_rows, const int* rp_c,
+                          int* ci_c, double* val_c, const int* ovf_list, const int* ctl_ovf, hipStream_t s) {
+  if (nc <= 0) return;
+  k_galerkin_wave<true><<<nc, kWave, 0, s>>>(nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr,
+                                             nullptr, nullptr, rp_c, ci_c, val_c);
+  k_galerkin_big<true><<<256, kBig, 0, s>>>(rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr,
+                                            ovf_list, ctl_ovf, rp_c, ci_c, val_c);
+}
+
+}  // namespace amg

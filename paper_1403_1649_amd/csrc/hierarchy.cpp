@@ -1,0 +1,458 @@
+// Host runtime of setup (Algorithm 1): device arena, the level loop that
+// drives the setup kernels, the Arnoldi spectral estimate with a small
+// complex-shift QR eigenvalue solve on the host, and the dense coarsest-level
+// inverse.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+
+// ---------------------------------------------------------------- arena
+namespace {
+std::mutex g_cache_mu;
+std::multimap<size_t, void*>& chunk_cache() {
+  static std::multimap<size_t, void*> c;
+  return c;
+}
+constexpr size_t kMinChunk = size_t(64) << 20;
+constexpr size_t kAlign = 256;
+
+void* take_chunk(size_t want, size_t* got) {
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto& c = chunk_cache();
+    auto it = c.lower_bound(want);
+    if (it != c.end() && it->first <= 4 * want + kMinChunk) {
+      *got = it->first;
+      void* p = it->second;
+      c.erase(it);
+      return p;
+    }
+  }
+  size_t sz = std::max(want, kMinChunk);
+  void* p = nullptr;
+  if (hipMalloc(&p, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached chunks and retry once
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (auto& kv : chunk_cache()) (void)hipFree(kv.second);
+    chunk_cache().clear();
+    if (hipMalloc(&p, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(AMG_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
+    }
+  }
+  *got = sz;
+  return p;
+}
+
+void give_chunk(void* p, size_t sz) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  chunk_cache().emplace(sz, p);
+}
+}  // namespace
+
+Arena::~Arena() {
+  for (auto& c : chunks_) give_chunk(c.base, c.size);
+}
+
+void Arena::reserve(size_t bytes) {
+  size_t got = 0;
+  char* p = static_cast<char*>(take_chunk(bytes, &got));
+  chunks_.push_back(Chunk{p, got, 0});
+}
+
+void* Arena::alloc(size_t bytes) {
+  bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+  if (bytes == 0) bytes = kAlign;
+  for (auto& c : chunks_) {
+    if (c.off + bytes <= c.size) {
+      void* p = c.base + c.off;
+      c.off += bytes;
+      used_ += bytes;
+      return p;
+    }
+  }
+  reserve(bytes);
+  Chunk& c = chunks_.back();
+  void* p = c.base + c.off;
+  c.off += bytes;
+  used_ += bytes;
+  return p;
+}
+
+Hierarchy::~Hierarchy() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (h_pinned) (void)hipHostFree(h_pinned);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+// ---------------------------------------------------------------- eigenvalues
+// Largest eigenvalue modulus of a real upper Hessenberg matrix (m <= 8) by the
+// shifted QR algorithm in complex arithmetic: Givens rotations reduce
+// H - mu I to triangular form, the product RQ + mu I is the next iterate,
+// Wilkinson shifts from the trailing 2x2 block, deflation on a negligible
+// subdiagonal entry.
+double hessenberg_spectral_radius(const double* Hin, int m) {
+  using cd = std::complex<double>;
+  if (m <= 0) return 0.0;
+  cd H[8][8];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) H[i][j] = cd(Hin[i * m + j], 0.0);
+  double rho = 0.0;
+  int hi = m - 1;
+  int iter = 0;
+  while (hi >= 0) {
+    if (hi == 0) {
+      rho = std::max(rho, std::abs(H[0][0]));
+      break;
+    }
+    int l = hi;
+    while (l > 0) {
+      const double scale = std::abs(H[l][l]) + std::abs(H[l - 1][l - 1]);
+      if (std::abs(H[l][l - 1]) <= 1e-15 * (scale > 0.0 ? scale : 1.0)) break;
+      --l;
+    }
+    if (l == hi) {
+      rho = std::max(rho, std::abs(H[hi][hi]));
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 200) {
+      for (int i = l; i <= hi; ++i) rho = std::max(rho, std::abs(H[i][i]));
+      break;
+    }
+    // Wilkinson shift: eigenvalue of the trailing 2x2 closer to H[hi][hi]
+    const cd a = H[hi - 1][hi - 1], b = H[hi - 1][hi], c = H[hi][hi - 1], d = H[hi][hi];
+    const cd tr = a + d, det = a * d - b * c;
+    const cd disc = std::sqrt(tr * tr * 0.25 - det);
+    const cd mu1 = tr * 0.5 + disc, mu2 = tr * 0.5 - disc;
+    cd mu = std::abs(mu1 - d) < std::abs(mu2 - d) ? mu1 : mu2;
+    if (iter % 11 == 10) mu = d + cd(std::abs(c), 0.0);   // exceptional shift
+    for (int i = l; i <= hi; ++i) H[i][i] -= mu;
+    cd cs[8], sn[8];
+    for (int k = l; k < hi; ++k) {
+      const cd x = H[k][k], y = H[k + 1][k];
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      if (r == 0.0) { cs[k] = 1.0; sn[k] = 0.0; continue; }
+      cs[k] = x / r;
+      sn[k] = y / r;
+      for (int j = k; j <= hi; ++j) {
+        const cd u = H[k][j], v = H[k + 1][j];
+        H[k][j] = std::conj(cs[k]) * u + std::conj(sn[k]) * v;
+        H[k + 1][j] = -sn[k] * u + cs[k] * v;
+      }
+    }
+    for (int k = l; k < hi; ++k) {
+      const int top = std::min(k + 2, hi);
+      for (int i = l; i <= top; ++i) {
+        const cd u = H[i][k], v = H[i][k + 1];
+        H[i][k] = u * cs[k] + v * sn[k];
+        H[i][k + 1] = -u * std::conj(sn[k]) + v * std::conj(cs[k]);
+      }
+    }
+    for (int i = l; i <= hi; ++i) H[i][i] += mu;
+  }
+  return rho;
+}
+
+// ---------------------------------------------------------------- setup
+namespace {
+
+struct Sync {
+  Hierarchy& h;
+  int* hp() { return static_cast<int*>(h.h_pinned); }
+  // copy `count` ints from device to the pinned mirror (slot offset), no sync
+  void fetch(const int* dptr, int slot, int count = 1) {
+    AMG_HIP(hipMemcpyAsync(hp() + slot, dptr, count * sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  }
+  void wait_and_check() {
+    AMG_HIP(hipGetLastError());   // a failed launch surfaces here
+    AMG_HIP(hipMemcpyAsync(hp() + 63, h.d_err, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    AMG_HIP(hipStreamSynchronize(h.stream));
+    AMG_HIP(hipGetLastError());
+    const int e = hp()[63];
+    if (!e) return;
+    if (e & kErrNonFinite) throw Error(AMG_ENANINF, "non-finite matrix entry");
+    if (e & kErrZeroDiag) throw Error(AMG_EINVAL, "zero or missing diagonal entry");
+    if (e & kErrBadColumn) throw Error(AMG_EINVAL, "column index out of range or not strictly increasing");
+    if (e & kErrNonSymPattern) throw Error(AMG_EINVAL, "sparsity pattern is not structurally symmetric");
+    if (e & kErrCountOverflow) throw Error(AMG_EINVAL, "strong influence count exceeds 2^21");
+    if (e & kErrUnassigned) throw Error(AMG_ECOARSEN, "node farther than 2 from every MIS(2) node");
+    if (e & kErrSingular) throw Error(AMG_EBREAKDOWN, "coarsest matrix is singular");
+    throw Error(AMG_EHIP, "device error bits " + std::to_string(e));
+  }
+};
+
+void alloc_solve_vectors(Hierarchy& h) {
+  const size_t es = h.mixed() ? sizeof(float) : sizeof(double);
+  const int L = h.L();
+  for (int k = 0; k < L; ++k) {
+    Level& lv = h.levels[k];
+    const size_t n = lv.n, nc = lv.nc;
+    lv.r = h.arena.alloc(n * es);
+    lv.xt = h.arena.alloc(n * es);
+    lv.rc = h.arena.alloc(nc * es);
+    lv.c = h.arena.alloc(nc * es);
+    if (k < h.opt.kcycle_levels) {
+      lv.v = h.arena.alloc(nc * es);
+      lv.rt = h.arena.alloc(nc * es);
+      lv.d = h.arena.alloc(nc * es);
+      lv.w = h.arena.alloc(nc * es);
+    }
+  }
+  const size_t n0 = h.levels[0].n;
+  h.r = h.arena.alloc_n<double>(n0);
+  h.p = h.arena.alloc_n<double>(n0);
+  h.q = h.arena.alloc_n<double>(n0);
+  h.z = h.arena.alloc(n0 * es);
+  if (h.mixed()) h.bz = h.arena.alloc(n0 * es);
+}
+
+void make_float_copies(Hierarchy& h) {
+  for (int k = 0; k < (int)h.levels.size(); ++k) {
+    Level& lv = h.levels[k];
+    lv.val32 = h.arena.alloc_n<float>(lv.nnz);
+    launch_to_float(lv.nnz, lv.val, lv.val32, h.stream);
+    if (k < h.L()) {
+      lv.pval32 = h.arena.alloc_n<float>(lv.n);
+      launch_to_float(lv.n, lv.pval, lv.pval32, h.stream);
+    }
+  }
+}
+}  // namespace
+
+// Aggregate segments: members of aggregate I at agg_rows[agg_ptr[I]..agg_ptr[I+1]),
+// ascending.  Scratch from `tmp`.
+static void build_segments(Hierarchy& h, Arena& tmp, int n, int nc, const int* agg, int* agg_ptr,
+                           int* agg_rows) {
+  hipStream_t s = h.stream;
+  int* counts = tmp.alloc_n<int>(nc);
+  launch_fill_int(nc, counts, 0, s);
+  launch_agg_count(n, agg, counts, s);
+  scan_to_ptr(counts, agg_ptr, nc, h.d_scan, s);
+  launch_fill_int(nc, counts, 0, s);
+  launch_agg_scatter(n, agg, agg_ptr, counts, agg_rows, s);
+  launch_agg_sort(nc, agg_ptr, agg_rows, s);
+}
+
+// Galerkin product A_c = P^T A P for given segments (count, scan, fill).
+static void galerkin_product(Hierarchy& h, Arena& tmp, Arena& out, const Level& lv, int nc,
+                             const int* agg, const double* pval, const int* agg_ptr, const int* agg_rows,
+                             int** rp_c, int** ci_c, double** val_c, int* nnz_c) {
+  hipStream_t s = h.stream;
+  Sync sy{h};
+  int* row_count = tmp.alloc_n<int>(nc);
+  int* ovf = tmp.alloc_n<int>(nc);
+  int* ctl_ovf = h.d_ctl + kCtlAggFill;
+  launch_galerkin_count(nc, lv.rp, lv.ci, agg, agg_ptr, agg_rows, row_count, ovf, ctl_ovf, s);
+  *rp_c = out.alloc_n<int>(nc + 1);
+  scan_to_ptr(row_count, *rp_c, nc, h.d_scan, s);
+  sy.fetch(*rp_c + nc, 0);
+  sy.wait_and_check();
+  *nnz_c = sy.hp()[0];
+  *ci_c = out.alloc_n<int>(*nnz_c);
+  *val_c = out.alloc_n<double>(*nnz_c);
+  launch_galerkin_fill(nc, lv.rp, lv.ci, lv.val, agg, pval, agg_ptr, agg_rows, *rp_c, *ci_c, *val_c, ovf,
+                       ctl_ovf, s);
+}
+
+void galerkin_standalone(Hierarchy& h, const amg_csr& A, const int* agg, const double* pval, int nc,
+                         int* nnz_c, int** rp_c, int** ci_c, double** val_c) {
+  Arena& tmp = h.arena;
+  Level lv;
+  lv.n = A.n;
+  lv.nnz = A.nnz;
+  lv.rp = const_cast<int*>(A.row_ptr);
+  lv.ci = const_cast<int*>(A.col_idx);
+  lv.val = const_cast<double*>(A.val);
+  Sync sy0{h};
+  AMG_HIP(hipMemcpyAsync(sy0.hp(), A.row_ptr, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  AMG_HIP(hipMemcpyAsync(sy0.hp() + 1, A.row_ptr + A.n, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  sy0.wait_and_check();
+  if (sy0.hp()[0] != 0 || sy0.hp()[1] != A.nnz) throw Error(AMG_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  launch_check_rowptr(A.n, A.row_ptr, h.d_err, h.stream);
+  sy0.wait_and_check();
+  launch_check_matrix(A.n, A.row_ptr, A.col_idx, A.val, h.d_err, h.stream);
+  launch_check_index(A.n, agg, nc, h.d_err, h.stream);
+  sy0.wait_and_check();
+  int* agg_ptr = tmp.alloc_n<int>(nc + 1);
+  int* agg_rows = tmp.alloc_n<int>(A.n);
+  build_segments(h, tmp, A.n, nc, agg, agg_ptr, agg_rows);
+  galerkin_product(h, tmp, tmp, lv, nc, agg, pval, agg_ptr, agg_rows, rp_c, ci_c, val_c, nnz_c);
+  Sync sy{h};
+  sy.wait_and_check();
+}
+
+void init_control(Hierarchy& h) {
+  h.d_err = h.arena.alloc_n<int>(64);
+  h.d_ctl = h.arena.alloc_n<int>(kCtlWords);
+  h.d_sc = h.arena.alloc_n<double>(kScWords);
+  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4);
+  h.d_ticket = h.arena.alloc_n<unsigned>(64);
+  launch_fill_int(64, h.d_err, 0, h.stream);
+  launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);
+  launch_fill_int(64, reinterpret_cast<int*>(h.d_ticket), 0, h.stream);
+  launch_fill_int(1, h.d_ctl + kCtlOne, 1, h.stream);
+  if (!h.h_pinned) AMG_HIP(hipHostMalloc(&h.h_pinned, 4096, hipHostMallocDefault));
+}
+
+void build_hierarchy(Hierarchy& h, const amg_csr& A) {
+  hipStream_t s = h.stream;
+  const amg_options& o = h.opt;
+  Sync sy{h};
+  Arena tmp;
+  // on any exit, drain the stream before the scratch chunks go back to the cache
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+  // scan scratch sized for the largest level
+  h.d_scan = h.arena.alloc_n<int>(scan_blocks_needed(std::max(A.n, A.nnz)) + 2);
+
+  Level l0;
+  l0.n = A.n;
+  l0.nnz = A.nnz;
+  l0.rp = h.arena.alloc_n<int>(A.n + 1);
+  l0.ci = h.arena.alloc_n<int>(A.nnz);
+  l0.val = h.arena.alloc_n<double>(A.nnz);
+  AMG_HIP(hipMemcpyAsync(l0.rp, A.row_ptr, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+  AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+  AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // the row pointers must be consistent before any kernel walks the rows
+  sy.fetch(l0.rp, 0, 1);
+  sy.fetch(l0.rp + A.n, 1, 1);
+  sy.wait_and_check();
+  if (sy.hp()[0] != 0 || sy.hp()[1] != A.nnz) throw Error(AMG_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  launch_check_rowptr(l0.n, l0.rp, h.d_err, s);   // monotone: every row lies inside [0, nnz)
+  sy.wait_and_check();
+  launch_check_matrix(l0.n, l0.rp, l0.ci, l0.val, h.d_err, s);
+  l0.B = h.arena.alloc_n<double>(A.n);
+  launch_fill_double(A.n, l0.B, 1.0, s);   // B_0 = 1, the constant near null space vector
+  h.levels.push_back(l0);
+  sy.wait_and_check();
+
+  const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  while (true) {
+    const int k = (int)h.levels.size() - 1;
+    Level& lv = h.levels[k];
+    lv.diag = h.arena.alloc_n<double>(lv.n);
+    lv.lpr = pick_lanes_per_row(lv.n, lv.nnz);
+    if (lv.n <= o.coarse_max || k + 1 >= o.max_levels) break;
+    const int n = lv.n, nnz = lv.nnz;
+
+    // strength (Section 2.1.1) and the strong graph G = C u C^T
+    lv.strong = h.arena.alloc_n<uint8_t>(nnz);
+    launch_strength(n, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, h.d_err, s);
+    uint8_t* gmask = tmp.alloc_n<uint8_t>(nnz);
+    int* gdeg = tmp.alloc_n<int>(n);
+    int* cnt = tmp.alloc_n<int>(n);
+    launch_graph_count(n, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
+    int* gptr = tmp.alloc_n<int>(n + 1);
+    scan_to_ptr(gdeg, gptr, n, h.d_scan, s);
+    sy.fetch(gptr + n, 0);
+    sy.wait_and_check();
+    const int nnzg = sy.hp()[0];
+    int* gcol = tmp.alloc_n<int>(nnzg > 0 ? nnzg : 1);
+    launch_graph_fill(n, lv.rp, lv.ci, gmask, gptr, gcol, s);
+
+    // MIS(2) rounds (Algorithm 2)
+    lv.tuple = h.arena.alloc_n<uint64_t>(n);
+    uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, h.d_ctl, h.d_err, s);
+    int round = 0;
+    const int batch = 4;
+    while (true) {
+      for (int b = 0; b < batch; ++b, ++round) launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, s);
+      sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
+      sy.fetch(h.d_ctl + kCtlMisRounds, 1);
+      sy.wait_and_check();
+      if (sy.hp()[0] == 0) break;
+      if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
+    }
+    lv.mis_rounds = sy.hp()[1];
+    if (debug) std::fprintf(stderr, "amg: level %d n=%d nnz=%d nnz(G)=%d mis_rounds=%d\n", k, n, nnz, nnzg,
+                            lv.mis_rounds);
+
+    // aggregates: coarse ids of the roots, nearest-root assignment
+    int* flags = tmp.alloc_n<int>(n);
+    int* root_id = tmp.alloc_n<int>(n + 1);
+    launch_root_flags(n, lv.tuple, flags, s);
+    scan_to_ptr(flags, root_id, n, h.d_scan, s);
+    sy.fetch(root_id + n, 0);
+    sy.wait_and_check();
+    const int nc = sy.hp()[0];
+    if (nc <= 0 || nc > 0.9 * n) {
+      lv.strong = nullptr;   // stalled: this level is the coarsest
+      lv.tuple = nullptr;
+      break;
+    }
+    int* choice = tmp.alloc_n<int>(n);
+    lv.agg = h.arena.alloc_n<int>(n);
+    launch_aggregate(n, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    lv.nc = nc;
+    lv.agg_ptr = h.arena.alloc_n<int>(nc + 1);
+    lv.agg_rows = h.arena.alloc_n<int>(n);
+    build_segments(h, tmp, n, nc, lv.agg, lv.agg_ptr, lv.agg_rows);
+
+    // interpolation (Algorithm 3)
+    Level lc;
+    lc.n = nc;
+    lc.B = h.arena.alloc_n<double>(nc);
+    lv.pval = h.arena.alloc_n<double>(n);
+    launch_interp(n, nc, lv.agg, lv.agg_ptr, lv.agg_rows, lv.B, lc.B, lv.pval, s);
+
+    // Galerkin product (Section 3.1)
+    galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
+                     &lc.val, &lc.nnz);
+
+    // damped Jacobi weight (Section 2.2.1)
+    const int m = std::min(o.arnoldi_m, n);
+    double* Q = tmp.alloc_n<double>((size_t)(m + 1) * n);
+    double* w = tmp.alloc_n<double>(n);
+    double Hh[48], wn[8];
+    arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
+    int size = m;
+    for (int j = 0; j < m; ++j) {
+      if (Hh[(j + 1) * 8 + j] <= 1e-14 * wn[j]) { size = j + 1; break; }
+    }
+    double Hs[64];
+    for (int i = 0; i < size; ++i)
+      for (int j = 0; j < size; ++j) Hs[i * size + j] = Hh[i * 8 + j];
+    lv.rho = hessenberg_spectral_radius(Hs, size);
+    if (!(lv.rho > 0.0) || !std::isfinite(lv.rho))
+      throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive");
+    lv.omega = o.jacobi_scale / lv.rho;
+    if (debug) std::fprintf(stderr, "amg: level %d nc=%d nnz_c=%d rho=%.6f omega=%.6f\n", k, nc, lc.nnz, lv.rho,
+                            lv.omega);
+    lv.wdinv = h.arena.alloc_n<double>(n);
+    if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
+    launch_jacobi_weights(n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, s);
+    h.levels.push_back(lc);
+  }
+
+  // coarsest level: dense inverse
+  Level& cl = h.levels.back();
+  if (cl.n > o.dense_max)
+    throw Error(AMG_ECOARSEN, "coarsest level has " + std::to_string(cl.n) + " unknowns");
+  const size_t nn = (size_t)cl.n * cl.n;
+  double* work = tmp.alloc_n<double>(nn + 2 * (size_t)cl.n);
+  int* gj_sync = tmp.alloc_n<int>(4 + cl.n);
+  h.cinv = h.arena.alloc_n<double>(nn);
+  if (h.mixed()) h.cinv32 = h.arena.alloc_n<float>(nn);
+  launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
+  if (h.mixed()) make_float_copies(h);
+  alloc_solve_vectors(h);
+  sy.wait_and_check();
+}
+
+}  // namespace amg

@@ -1,0 +1,143 @@
+// Generic launch skeletons of the solve phase: a CSR row kernel (L lanes per
+// row, wave64 sub-groups) and an elementwise kernel, both with an optional
+// fused reduction.  Reductions are deterministic: each block reduces in a
+// fixed order, writes one partial per block, and the last block to finish
+// (ticket counter) sums the partials in block order and hands the totals to
+// the operation's finalizer, which writes device scalars and flags.  Every
+// operation carries an `active` flag read at kernel entry, so branches of
+// the K-cycle and the outer iteration are decided on the device.
+#pragma once
+#include "amg_internal.hpp"
+#include "device_utils.hpp"
+
+namespace amg {
+
+constexpr int kBlock = 256;
+
+struct RedCtx {
+  double* part;       // kMaxPartialBlocks * NV doubles
+  unsigned* ticket;   // one counter, zero between kernels
+};
+
+template <int NV, class Op>
+__device__ __forceinline__ void reduce_and_finalize(double (&acc)[NV], Op& op, RedCtx rc) {
+  __shared__ double red[NV * (kBlock / kWave)];
+  __shared__ int s_last;
+  block_sum<NV>(acc, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) rc.part[k * gridDim.x + blockIdx.x] = acc[k];
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(rc.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+        s += __hip_atomic_load(&rc.part[k * gridDim.x + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v[k] = s;
+    }
+    block_sum<NV>(v, red);
+    if (threadIdx.x == 0) {
+      op.finalize(v);
+      __hip_atomic_store(rc.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// y-side of a sparse row operation: Op provides
+//   static constexpr int NV;           number of fused reductions
+//   bool active() const;               kernel-wide enable
+//   void idle() const;                 run by thread 0 of block 0 when inactive
+//   T x(int j) const;                  the gathered operand
+//   void row(int i, T ax, double* acc) the epilogue of row i
+//   void finalize(const double* v)     totals of the reductions
+template <typename T, int LPR, class Op>
+__global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const T* __restrict__ av, Op op, RedCtx rc) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  constexpr int RPB = kBlock / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  double acc[Op::NV > 0 ? Op::NV : 1];
+#pragma unroll
+  for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
+  for (int row0 = blockIdx.x * RPB; row0 < n; row0 += gridDim.x * RPB) {
+    const int row = row0 + threadIdx.x / LPR;
+    T sum = T(0);
+    if (row < n) {
+      const int s = rp[row], e = rp[row + 1];
+      for (int k = s + lane; k < e; k += LPR) sum += av[k] * op.x(ci[k]);
+    }
+    sum = group_sum<LPR>(sum);
+    if (row < n && lane == 0) op.row(row, sum, acc);
+  }
+  if constexpr (Op::NV > 0) reduce_and_finalize<Op::NV>(acc, op, rc);
+}
+
+// Elementwise operation over [0, n): Op provides NV, active(), idle(),
+// elem(int i, double* acc), finalize(const double*).
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_elem(int n, Op op, RedCtx rc) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  double acc[Op::NV > 0 ? Op::NV : 1];
+#pragma unroll
+  for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) op.elem(i, acc);
+  if constexpr (Op::NV > 0) reduce_and_finalize<Op::NV>(acc, op, rc);
+}
+
+inline int rows_grid(int n, int lpr, bool reduce) {
+  long rpb = kBlock / lpr;
+  long g = (n + rpb - 1) / rpb;
+  long cap = reduce ? kMaxPartialBlocks : 65536;
+  if (g < 1) g = 1;
+  return (int)(g < cap ? g : cap);
+}
+
+inline int elem_grid(int n, bool reduce) {
+  long g = ((long)n + kBlock - 1) / kBlock;
+  long cap = reduce ? kMaxPartialBlocks : 65536;
+  if (g < 1) g = 1;
+  return (int)(g < cap ? g : cap);
+}
+
+template <typename T, class Op>
+void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc,
+                 hipStream_t s) {
+  const int g = rows_grid(n, lpr, Op::NV > 0);
+  switch (lpr) {
+    case 1: k_rows<T, 1, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 2: k_rows<T, 2, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 4: k_rows<T, 4, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 8: k_rows<T, 8, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 16: k_rows<T, 16, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 32: k_rows<T, 32, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+  }
+}
+
+template <class Op>
+void launch_elem(int n, const Op& op, RedCtx rc, hipStream_t s) {
+  k_elem<Op><<<elem_grid(n, Op::NV > 0), kBlock, 0, s>>>(n, op, rc);
+}
+
+inline int pick_lpr(int n, int nnz) {
+  double avg = n > 0 ? (double)nnz / n : 1.0;
+  int l = 1;
+  while (l < avg && l < 64) l <<= 1;
+  return l < 2 ? 2 : l;
+}
+
+}  // namespace amg

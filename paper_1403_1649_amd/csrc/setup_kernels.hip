@@ -1,0 +1,423 @@
+// Setup kernels of Algorithm 1: input checks, classic strength of connection
+// (Section 2.1.1), the undirected strong graph, MIS(2) rounds (Algorithm 2),
+// nearest-root aggregation, aggregate segments and the interpolation of
+// Algorithm 3.  One thread per row / node: these run once per level and their
+// rows are short, so the simple mapping keeps the integer decisions exact.
+#include "amg_internal.hpp"
+#include "device_utils.hpp"
+
+namespace amg {
+
+namespace {
+constexpr int kT = 256;
+inline int grid_for(long n) { return (int)((n + kT - 1) / kT); }
+
+constexpr uint64_t kLow62 = (1ull << 62) - 1;
+// tuple state field (top two bits) = s + 1: 0 non-MIS, 1 undecided, 2 MIS
+__device__ __forceinline__ int tstate(uint64_t t) { return (int)(t >> 62); }
+
+__global__ void k_check_matrix(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ val, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1];
+  int bits = 0;
+  if (e < s) { atomic_or_flag(err, kErrBadColumn); return; }
+  bool have_diag = false;
+  int prev = -1;
+  for (int k = s; k < e; ++k) {
+    int j = ci[k];
+    double a = val[k];
+    if (j < 0 || j >= n || j <= prev) bits |= kErrBadColumn;
+    if (!isfinite(a)) bits |= kErrNonFinite;
+    if (j == i) { have_diag = true; if (a == 0.0) bits |= kErrZeroDiag; }
+    prev = j;
+  }
+  if (!have_diag) bits |= kErrZeroDiag;
+  if (bits) atomic_or_flag(err, bits);
+}
+
+__global__ void k_check_rowptr(int n, const int* __restrict__ rp, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && rp[i] > rp[i + 1]) atomic_or_flag(err, kErrBadColumn);
+}
+
+__global__ void k_check_index(int n, const int* __restrict__ idx, int limit, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (idx[i] < 0 || idx[i] >= limit)) atomic_or_flag(err, kErrBadColumn);
+}
+
+// C_ij = [-s_i a_ij > alpha * max_{-s_i a_ij > 0} (-s_i a_ij)], s_i = sign(a_ii).
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ val, double alpha,
+                           uint8_t* __restrict__ strong, double* __restrict__ diag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1];
+  double d = 0.0;
+  for (int k = s; k < e; ++k)
+    if (ci[k] == i) d = val[k];
+  const double sg = d > 0.0 ? 1.0 : -1.0;
+  double m = 0.0;
+  for (int k = s; k < e; ++k) {
+    double t = -sg * val[k];
+    if (t > m) m = t;            // the running max only ever holds positive values
+  }
+  const double thr = __dmul_rn(alpha, m);
+  for (int k = s; k < e; ++k) strong[k] = (-sg * val[k] > thr) ? 1 : 0;
+  diag[i] = d;
+}
+
+__device__ __forceinline__ int find_in_row(const int* __restrict__ ci, int lo, int hi, int key) {
+  // binary search in ci[lo, hi) (sorted); returns the position or -1
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    int c = ci[mid];
+    if (c == key) return mid;
+    if (c < key) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+// G = C union C^T over A's (structurally symmetric) pattern; influence counts
+// cnt_i = #{j : C_ji = 1}.
+__global__ void k_graph_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const uint8_t* __restrict__ strong, uint8_t* __restrict__ gmask,
+                              int* __restrict__ gdeg, int* __restrict__ cnt, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1];
+  int gd = 0, c = 0;
+  bool nonsym = false;
+  for (int k = s; k < e; ++k) {
+    int j = ci[k];
+    if (j == i) { gmask[k] = 0; continue; }
+    int t = find_in_row(ci, rp[j], rp[j + 1], i);
+    if (t < 0) nonsym = true;
+    bool cji = t >= 0 && strong[t];
+    bool g = strong[k] || cji;
+    gmask[k] = g ? 1 : 0;
+    gd += g;
+    c += cji;
+  }
+  gdeg[i] = gd;
+  cnt[i] = c;
+  if (nonsym) atomic_or_flag(err, kErrNonSymPattern);
+}
+
+__global__ void k_graph_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                             const uint8_t* __restrict__ gmask, const int* __restrict__ gptr,
+                             int* __restrict__ gcol) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = gptr[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (gmask[k]) gcol[o++] = ci[k];
+}
+
+// Tuple T_i = (s_i, v_i, i) packed so that integer order is lexicographic
+// order: bits 63..62 = s_i + 1, bits 61..32 = influence count, bits 31..0 =
+// node hash (a bijection of i, so the hash both breaks ties and names i).
+__global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
+                           uint64_t* __restrict__ T, int* ctl, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl[kCtlMisPing] = n;
+    ctl[kCtlMisPing + 1] = 0;
+    ctl[kCtlMisRounds] = 0;
+  }
+  if (i >= n) return;
+  int c = cnt[i];
+  if (c >= (1 << 21)) atomic_or_flag(err, kErrCountOverflow);
+  T[i] = (1ull << 62) | ((uint64_t)(c & ((1 << 30) - 1)) << 32) | (uint64_t)node_hash((uint32_t)i, seed);
+}
+
+// First max sweep of a round: M1_i = max(T_i, max_{j in N_i} T_j).
+// Thread 0 clears the counter the round's second sweep fills, also when the
+// round has nothing left to do, so a finished MIS keeps reading zero.
+__global__ void k_mis_sweep1(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
+                             const uint64_t* __restrict__ T, uint64_t* __restrict__ M1, int* ctl,
+                             int round) {
+  const int undecided = load_acquire(&ctl[kCtlMisPing + (round & 1)]);
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctl[kCtlMisPing + ((round + 1) & 1)] = 0;
+    if (undecided) ctl[kCtlMisRounds] += 1;
+  }
+  if (undecided == 0 || i >= n) return;
+  uint64_t t = T[i];
+  for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
+    uint64_t u = T[gcol[k]];
+    t = u > t ? u : t;
+  }
+  M1[i] = t;
+}
+
+// Second sweep plus the state update: an undecided node whose distance-2 max
+// is its own tuple joins the MIS; one that sees an MIS tuple leaves.
+__global__ void k_mis_sweep2(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
+                             uint64_t* __restrict__ T, const uint64_t* __restrict__ M1, int* ctl,
+                             int round) {
+  if (load_acquire(&ctl[kCtlMisPing + (round & 1)]) == 0) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int undecided = 0;
+  if (i < n) {
+    uint64_t t = M1[i];
+    for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
+      uint64_t u = M1[gcol[k]];
+      t = u > t ? u : t;
+    }
+    uint64_t own = T[i];
+    if (tstate(own) == 1) {
+      if (t == own) {
+        T[i] = (own & kLow62) | (2ull << 62);
+      } else if (tstate(t) == 2) {
+        T[i] = own & kLow62;
+      } else {
+        undecided = 1;
+      }
+    }
+  }
+  int c = wave_sum_int(undecided);
+  if ((threadIdx.x & (kWave - 1)) == 0 && c)
+    atomicAdd(&ctl[kCtlMisPing + ((round + 1) & 1)], c);
+}
+
+__global__ void k_root_flags(int n, const uint64_t* __restrict__ T, int* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = tstate(T[i]) == 2 ? 1 : 0;
+}
+
+// Round 1: roots take themselves; nodes next to roots take the adjacent root
+// with the largest tuple.
+__global__ void k_agg_round1(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
+                             const uint64_t* __restrict__ T, int* __restrict__ choice) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t own = T[i];
+  if (tstate(own) == 2) { choice[i] = i; return; }
+  uint64_t best = 0;
+  int bj = -1;
+  for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
+    int j = gcol[k];
+    uint64_t u = T[j];
+    if (tstate(u) == 2 && u > best) { best = u; bj = j; }
+  }
+  choice[i] = bj;
+}
+
+// Round 2: the remaining nodes (distance 2 from every root) take, among the
+// roots chosen by their round-1 neighbours, the one with the largest tuple.
+__global__ void k_agg_round2(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
+                             const uint64_t* __restrict__ T, const int* __restrict__ choice,
+                             const int* __restrict__ root_id, int* __restrict__ agg, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = choice[i];
+  if (c < 0) {
+    uint64_t best = 0;
+    for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
+      int cj = choice[gcol[k]];
+      if (cj >= 0) {
+        uint64_t u = T[cj];
+        if (u > best) { best = u; c = cj; }
+      }
+    }
+  }
+  if (c < 0) {
+    atomic_or_flag(err, kErrUnassigned);
+    agg[i] = 0;
+    return;
+  }
+  agg[i] = root_id[c];
+}
+
+__global__ void k_agg_count(int n, const int* __restrict__ agg, int* counts) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&counts[agg[i]], 1);
+}
+
+__global__ void k_agg_scatter(int n, const int* __restrict__ agg, const int* __restrict__ agg_ptr,
+                              int* fill, int* __restrict__ agg_rows) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int I = agg[i];
+  int pos = atomicAdd(&fill[I], 1);
+  agg_rows[agg_ptr[I] + pos] = i;
+}
+
+__device__ void sift_down(int* a, int start, int end) {
+  int root = start;
+  while (2 * root + 1 <= end) {
+    int child = 2 * root + 1;
+    if (child + 1 <= end && a[child] < a[child + 1]) ++child;
+    if (a[root] < a[child]) {
+      int t = a[root]; a[root] = a[child]; a[child] = t;
+      root = child;
+    } else {
+      return;
+    }
+  }
+}
+
+// Each aggregate's member list sorted ascending (atomics left it in arrival
+// order); insertion sort for short segments, heap sort for long ones.
+__global__ void k_agg_sort(int nc, const int* __restrict__ agg_ptr, int* __restrict__ agg_rows) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int* a = agg_rows + agg_ptr[I];
+  int m = agg_ptr[I + 1] - agg_ptr[I];
+  if (m <= 32) {
+    for (int k = 1; k < m; ++k) {
+      int x = a[k];
+      int j = k - 1;
+      while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
+      a[j + 1] = x;
+    }
+    return;
+  }
+  for (int start = (m - 2) / 2; start >= 0; --start) sift_down(a, start, m - 1);
+  for (int end = m - 1; end > 0; --end) {
+    int t = a[0]; a[0] = a[end]; a[end] = t;
+    sift_down(a, 0, end - 1);
+  }
+}
+
+// Algorithm 3: B_{k+1}(I) = ||R_k(I,:)||_2 with R_k(I,i) = B_k(i), summed in
+// ascending i; then P_k(i, I) = B_k(i) / B_{k+1}(I).
+__global__ void k_interp_coarse(int nc, const int* __restrict__ agg_ptr, const int* __restrict__ agg_rows,
+                                const double* __restrict__ B, double* __restrict__ Bc) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  double s = 0.0;
+  for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
+    double b = B[agg_rows[k]];
+    s = __dadd_rn(s, __dmul_rn(b, b));
+  }
+  Bc[I] = sqrt(s);
+}
+
+__global__ void k_interp_fine(int n, const int* __restrict__ agg, const double* __restrict__ B,
+                              const double* __restrict__ Bc, double* __restrict__ pval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) pval[i] = B[i] / Bc[agg[i]];
+}
+
+__global__ void k_node_hash(int n, uint32_t stream, uint32_t* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = node_hash((uint32_t)i, stream);
+}
+
+__global__ void k_jacobi_weights(int n, double omega, const double* __restrict__ diag,
+                                 double* __restrict__ wdinv, float* __restrict__ wdinv32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double w = omega / diag[i];
+  wdinv[i] = w;
+  if (wdinv32) wdinv32[i] = (float)w;
+}
+
+__global__ void k_to_float(size_t n, const double* __restrict__ in, float* __restrict__ out) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) out[i] = (float)in[i];
+}
+
+__global__ void k_state_from_tuple(int n, const uint64_t* __restrict__ T, int8_t* __restrict__ st) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) st[i] = (int8_t)(tstate(T[i]) - 1);
+}
+
+__global__ void k_fill_double(size_t n, double* p, double v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_int(size_t n, int* p, int v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+}  // namespace
+
+void launch_check_rowptr(int n, const int* rp, int* err, hipStream_t s) {
+  k_check_rowptr<<<grid_for(n), kT, 0, s>>>(n, rp, err);
+}
+void launch_check_index(int n, const int* idx, int limit, int* err, hipStream_t s) {
+  k_check_index<<<grid_for(n), kT, 0, s>>>(n, idx, limit, err);
+}
+void launch_check_matrix(int n, const int* rp, const int* ci, const double* val, int* err, hipStream_t s) {
+  k_check_matrix<<<grid_for(n), kT, 0, s>>>(n, rp, ci, val, err);
+}
+void launch_strength(int n, const int* rp, const int* ci, const double* val, double alpha,
+                     uint8_t* strong, double* diag, int* err, hipStream_t s) {
+  (void)err;
+  k_strength<<<grid_for(n), kT, 0, s>>>(n, rp, ci, val, alpha, strong, diag);
+}
+void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* strong, uint8_t* gmask,
+                        int* gdeg, int* cnt, int* err, hipStream_t s) {
+  k_graph_count<<<grid_for(n), kT, 0, s>>>(n, rp, ci, strong, gmask, gdeg, cnt, err);
+}
+void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask, const int* gptr,
+                       int* gcol, hipStream_t s) {
+  k_graph_fill<<<grid_for(n), kT, 0, s>>>(n, rp, ci, gmask, gptr, gcol);
+}
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s) {
+  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, ctl, err);
+}
+void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl,
+                      int round, hipStream_t s) {
+  k_mis_sweep1<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+  k_mis_sweep2<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+}
+void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s) {
+  k_root_flags<<<grid_for(n), kT, 0, s>>>(n, T, flags);
+}
+void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
+                      int* choice, int* agg, int* err, hipStream_t s) {
+  k_agg_round1<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, choice);
+  k_agg_round2<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, choice, root_id, agg, err);
+}
+void launch_agg_count(int n, const int* agg, int* counts, hipStream_t s) {
+  k_agg_count<<<grid_for(n), kT, 0, s>>>(n, agg, counts);
+}
+void launch_agg_scatter(int n, const int* agg, const int* agg_ptr, int* fill, int* agg_rows, hipStream_t s) {
+  k_agg_scatter<<<grid_for(n), kT, 0, s>>>(n, agg, agg_ptr, fill, agg_rows);
+}
+void launch_agg_sort(int nc, const int* agg_ptr, int* agg_rows, hipStream_t s) {
+  k_agg_sort<<<grid_for(nc), kT, 0, s>>>(nc, agg_ptr, agg_rows);
+}
+void launch_interp(int n, int nc, const int* agg, const int* agg_ptr, const int* agg_rows,
+                   const double* B, double* Bc, double* pval, hipStream_t s) {
+  k_interp_coarse<<<grid_for(nc), kT, 0, s>>>(nc, agg_ptr, agg_rows, B, Bc);
+  k_interp_fine<<<grid_for(n), kT, 0, s>>>(n, agg, B, Bc, pval);
+}
+void launch_node_hash(int n, uint32_t stream, uint32_t* out, hipStream_t s) {
+  if (n > 0) k_node_hash<<<grid_for(n), kT, 0, s>>>(n, stream, out);
+}
+void launch_jacobi_weights(int n, double omega, const double* diag, double* wdinv, float* wdinv32,
+                           hipStream_t s) {
+  k_jacobi_weights<<<grid_for(n), kT, 0, s>>>(n, omega, diag, wdinv, wdinv32);
+}
+void launch_to_float(size_t n, const double* in, float* out, hipStream_t s) {
+  if (n == 0) return;
+  long g = (long)((n + kT - 1) / kT);
+  k_to_float<<<(int)(g < 8192 ? g : 8192), kT, 0, s>>>(n, in, out);
+}
+void launch_state_from_tuple(int n, const uint64_t* T, int8_t* state, hipStream_t s) {
+  k_state_from_tuple<<<grid_for(n), kT, 0, s>>>(n, T, state);
+}
+void launch_fill_int(size_t n, int* p, int v, hipStream_t s) {
+  if (n == 0) return;
+  long g = (long)((n + kT - 1) / kT);
+  k_fill_int<<<(int)(g < 8192 ? g : 8192), kT, 0, s>>>(n, p, v);
+}
+
+void launch_fill_double(size_t n, double* p, double v, hipStream_t s) {
+  if (n == 0) return;
+  long g = (long)((n + kT - 1) / kT);
+  k_fill_double<<<(int)(g < 8192 ? g : 8192), kT, 0, s>>>(n, p, v);
+}
+
+}  // namespace amg

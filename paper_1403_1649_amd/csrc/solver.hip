@@ -1,0 +1,699 @@
+// Solve phase: damped Jacobi (eq. damped_jacobi), the V-cycle (Algorithm 4)
+// and K-cycle (Algorithm 5) preconditioners, flexible CG outside, and the
+// Arnoldi estimate of rho(D^-1 A) used by setup (Section 2.2.1).
+//
+// All scalars of the K-cycle and of the outer iteration live in device
+// memory; the branch "skip the second inner step when ||r~|| <= t ||r||" and
+// the convergence test are device flags read by every kernel of the guarded
+// region, so a whole outer iteration is enqueued without host round-trips.
+#include <cmath>
+
+#include "kernels_common.hpp"
+
+namespace amg {
+
+namespace {
+
+struct Act {
+  const int* p;
+  __device__ __forceinline__ bool on() const { return p == nullptr || *p != 0; }
+};
+
+// ------------------------------------------------------------------ row ops
+template <typename T>
+struct OpSpmv {
+  static constexpr int NV = 0;
+  Act a;
+  const T* xv;
+  T* y;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return xv[j]; }
+  __device__ void row(int i, T ax, double*) const { y[i] = ax; }
+  __device__ void finalize(const double*) const {}
+};
+
+// pre-smoothing from a zero guess and the residual: x = w.*b, r = b - A x
+template <typename T>
+struct OpPresmoothResid {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* wd;
+  T* xt;
+  T* r;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return wd[j] * b[j]; }
+  __device__ void row(int i, T ax, double*) const {
+    const T bi = b[i];
+    xt[i] = wd[i] * bi;
+    r[i] = bi - ax;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// new residual and post-smoothing: r = b - A x, x_out = x + w.*r
+template <typename T>
+struct OpResidSmooth {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* xt;
+  const T* wd;
+  T* xo;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return xt[j]; }
+  __device__ void row(int i, T ax, double*) const { xo[i] = xt[i] + wd[i] * (b[i] - ax); }
+  __device__ void finalize(const double*) const {}
+};
+
+// first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r)
+template <typename T>
+struct OpKDots1 {
+  static constexpr int NV = 2;
+  Act a;
+  const T* c;
+  const T* rcv;
+  T* v;
+  double* K;
+  int gmres;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return c[j]; }
+  __device__ void row(int i, T ax, double* acc) const {
+    v[i] = ax;
+    const double l = gmres ? (double)ax : (double)c[i];
+    acc[0] += l * (double)ax;
+    acc[1] += l * (double)rcv[i];
+  }
+  __device__ void finalize(const double* s) const {
+    K[kKRho1] = s[0];
+    K[kKAlpha1] = s[1];
+  }
+};
+
+// second inner step: w = A d; gamma, beta, alpha2; then the combination
+// coefficients of x_{k+1} = coef_c c + coef_d d
+template <typename T>
+struct OpKDots2 {
+  static constexpr int NV = 3;
+  Act a;
+  const T* d;
+  const T* v;
+  const T* rt;
+  T* w;
+  double* K;
+  int* F;
+  int gmres;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return d[j]; }
+  __device__ void row(int i, T ax, double* acc) const {
+    w[i] = ax;
+    const double l = gmres ? (double)ax : (double)d[i];
+    acc[0] += l * (double)v[i];
+    acc[1] += l * (double)ax;
+    acc[2] += l * (double)rt[i];
+  }
+  __device__ void finalize(const double* s) const {
+    const double gamma = s[0], beta = s[1], alpha2 = s[2];
+    const double rho1 = K[kKRho1], alpha1 = K[kKAlpha1];
+    K[kKGamma] = gamma;
+    K[kKBeta] = beta;
+    K[kKAlpha2] = alpha2;
+    const double rho2 = beta - gamma * gamma / rho1;
+    if (rho2 > 0.0) {
+      K[kKCoefC] = alpha1 / rho1 - gamma * alpha2 / (rho1 * rho2);
+      K[kKCoefD] = alpha2 / rho2;
+      F[1] = 1;
+    }
+  }
+};
+
+// outer FCG: q = A p with p'q and p'r; alpha = p'r / p'q
+struct OpFcgSpmv {
+  static constexpr int NV = 2;
+  Act a;
+  const double* p;
+  const double* r;
+  double* q;
+  double* sc;
+  int* ctl;
+  int* err;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ double x(int j) const { return p[j]; }
+  __device__ void row(int i, double ax, double* acc) const {
+    q[i] = ax;
+    acc[0] += p[i] * ax;
+    acc[1] += p[i] * r[i];
+  }
+  __device__ void finalize(const double* s) const {
+    sc[kScPQ] = s[0];
+    sc[kScAlpha] = s[1] / s[0];
+    ctl[kCtlIters] += 1;
+    if (!(s[0] > 0.0)) {
+      *err |= __builtin_isfinite(s[0]) ? kErrBreakdown : kErrNonFinite;
+      ctl[kCtlRunning] = 0;
+    }
+  }
+};
+
+// b - A x and its squared norm (true residual)
+struct OpTrueResid {
+  static constexpr int NV = 1;
+  Act a;
+  const double* b;
+  const double* xv;
+  double* r;
+  double* sc;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ double x(int j) const { return xv[j]; }
+  __device__ void row(int i, double ax, double* acc) const {
+    const double t = b[i] - ax;
+    r[i] = t;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(const double* s) const { sc[kScTrue] = s[0]; }
+};
+
+// Arnoldi: w = D^-1 A q_j with ||w||^2 and q_0'w
+struct OpArnSpmv {
+  static constexpr int NV = 2;
+  const double* q;
+  const double* q0;
+  const double* diag;
+  double* w;
+  double* sc;
+  int j;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ double x(int c) const { return q[c]; }
+  __device__ void row(int i, double ax, double* acc) const {
+    const double t = (1.0 / diag[i]) * ax;
+    w[i] = t;
+    acc[0] += t * t;
+    acc[1] += q0[i] * t;
+  }
+  __device__ void finalize(const double* s) const {
+    sc[kScArn + 48 + j] = sqrt(s[0]);
+    sc[kScArn + 0 * 8 + j] = s[1];
+  }
+};
+
+// ------------------------------------------------------------ element ops
+struct OpFcgInit {
+  static constexpr int NV = 1;
+  const double* b;
+  double* r;
+  double* xv;
+  double* sc;
+  int* ctl;
+  int* err;
+  double rtol;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const {
+    const double t = b[i];
+    r[i] = t;
+    xv[i] = 0.0;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(const double* s) const {
+    sc[kScBB] = s[0];
+    sc[kScRtol2] = rtol * rtol * s[0];
+    ctl[kCtlIters] = 0;
+    ctl[kCtlRunning] = s[0] > 0.0 ? 1 : 0;
+    if (!__builtin_isfinite(s[0])) {
+      *err |= kErrNonFinite;
+      ctl[kCtlRunning] = 0;
+    }
+  }
+};
+
+struct OpFcgUpdate {
+  static constexpr int NV = 1;
+  Act a;
+  const double* p;
+  const double* q;
+  double* xv;
+  double* r;
+  double* sc;
+  int* ctl;
+  int* err;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const {
+    const double al = sc[kScAlpha];
+    xv[i] += al * p[i];
+    const double t = r[i] - al * q[i];
+    r[i] = t;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(const double* s) const {
+    sc[kScRR] = s[0];
+    if (!__builtin_isfinite(s[0])) {
+      *err |= kErrNonFinite;
+      ctl[kCtlRunning] = 0;
+    } else if (s[0] <= sc[kScRtol2]) {
+      ctl[kCtlRunning] = 0;
+    }
+  }
+};
+
+template <typename T>
+struct OpDotZQ {
+  static constexpr int NV = 1;
+  Act a;
+  const T* z;
+  const double* q;
+  double* sc;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const { acc[0] += (double)z[i] * q[i]; }
+  __device__ void finalize(const double* s) const { sc[kScBeta] = -s[0] / sc[kScPQ]; }
+};
+
+template <typename T>
+struct OpPUpdate {
+  static constexpr int NV = 0;
+  Act a;
+  const T* z;
+  double* p;
+  const double* sc;
+  int first;  // p = z
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    p[i] = first ? (double)z[i] : (double)z[i] + sc[kScBeta] * p[i];
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+struct OpToFloat {
+  static constexpr int NV = 0;
+  Act a;
+  const double* in;
+  float* out;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { out[i] = (float)in[i]; }
+  __device__ void finalize(const double*) const {}
+};
+
+struct OpCopy {
+  static constexpr int NV = 0;
+  const double* in;
+  double* out;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { out[i] = in[i]; }
+  __device__ void finalize(const double*) const {}
+};
+
+// restriction r_c = P^T r by aggregate segments (ascending fine index)
+template <typename T, bool DOT>
+struct OpRestrict {
+  static constexpr int NV = DOT ? 1 : 0;
+  Act a;
+  const int* agg_ptr;
+  const int* agg_rows;
+  const T* pval;
+  const T* r;
+  T* rcv;
+  double* K;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int I, double* acc) const {
+    T s = T(0);
+    for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
+      const int i = agg_rows[k];
+      s += pval[i] * r[i];
+    }
+    rcv[I] = s;
+    if (DOT) acc[0] += (double)s * (double)s;
+  }
+  __device__ void finalize(const double* s) const {
+    if (DOT) K[kKRcRc] = s[0];
+  }
+};
+
+// prolongation x += P c
+template <typename T>
+struct OpProlong {
+  static constexpr int NV = 0;
+  Act a;
+  const int* agg;
+  const T* pval;
+  const T* c;
+  T* xt;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { xt[i] += pval[i] * c[agg[i]]; }
+  __device__ void finalize(const double*) const {}
+};
+
+// prolongation of the K-cycle combination x += P (coef_c c + coef_d d)
+template <typename T>
+struct OpProlongK {
+  static constexpr int NV = 0;
+  Act a;
+  const int* agg;
+  const T* pval;
+  const T* c;
+  const T* d;
+  T* xt;
+  const double* K;
+  const int* F;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    const int I = agg[i];
+    const T cc = (T)K[kKCoefC];
+    T xc = cc * c[I];
+    if (F[1]) xc += (T)K[kKCoefD] * d[I];
+    xt[i] += pval[i] * xc;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// r~ = r - (alpha1/rho1) v with ||r~||^2; decides the second inner step
+template <typename T>
+struct OpRtilde {
+  static constexpr int NV = 1;
+  Act a;
+  const T* rcv;
+  const T* v;
+  T* rt;
+  double* K;
+  int* F;
+  double t;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const { F[0] = 0; }
+  __device__ void elem(int i, double* acc) const {
+    const T ar = (T)(K[kKAlpha1] / K[kKRho1]);
+    const T u = rcv[i] - ar * v[i];
+    rt[i] = u;
+    acc[0] += (double)u * (double)u;
+  }
+  __device__ void finalize(const double* s) const {
+    const double rho1 = K[kKRho1];
+    K[kKRtRt] = s[0];
+    F[1] = 0;
+    if (rho1 > 0.0) {
+      K[kKCoefC] = K[kKAlpha1] / rho1;
+      F[0] = (sqrt(s[0]) <= t * sqrt(K[kKRcRc])) ? 0 : 1;
+    } else {
+      K[kKCoefC] = 0.0;
+      F[0] = 0;
+    }
+  }
+};
+
+struct OpArnStart {
+  static constexpr int NV = 1;
+  double* q;
+  double* sc;
+  uint32_t stream;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const {
+    const double u = unit_uniform((uint32_t)i, stream);
+    q[i] = u;
+    acc[0] += u * u;
+  }
+  __device__ void finalize(const double* s) const { sc[kScArn + 56] = sqrt(s[0]); }
+};
+
+struct OpDivide {
+  static constexpr int NV = 0;
+  const double* in;
+  double* out;
+  const double* den;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { out[i] = in[i] / *den; }
+  __device__ void finalize(const double*) const {}
+};
+
+// modified Gram-Schmidt step: w -= h q_i, then the next dot (q_{i+1}'w, or
+// ||w|| after the last projection)
+struct OpArnAxpyDot {
+  static constexpr int NV = 1;
+  const double* qi;
+  const double* qn;   // nullptr: norm of w
+  double* w;
+  const double* h;
+  double* out;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const {
+    const double t = w[i] - (*h) * qi[i];
+    w[i] = t;
+    acc[0] += (qn ? qn[i] : t) * t;
+  }
+  __device__ void finalize(const double* s) const { *out = qn ? s[0] : sqrt(s[0]); }
+};
+
+struct OpSetCtl {
+  static constexpr int NV = 0;
+  int* ctl;
+  int word, value;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    if (i == 0) ctl[word] = value;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gemv(int n, const T* __restrict__ A, const T* __restrict__ xv,
+                                                 T* __restrict__ y, Act a) {
+  if (!a.on()) return;
+  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (row >= n) return;
+  T s = T(0);
+  const T* Ar = A + (size_t)row * n;
+  for (int j = lane; j < n; j += kWave) s += Ar[j] * xv[j];
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
+// ------------------------------------------------------------ typed views
+template <typename T> const T* vals(const Level& l);
+template <> const double* vals<double>(const Level& l) { return l.val; }
+template <> const float* vals<float>(const Level& l) { return l.val32; }
+template <typename T> const T* wdinv(const Level& l);
+template <> const double* wdinv<double>(const Level& l) { return l.wdinv; }
+template <> const float* wdinv<float>(const Level& l) { return l.wdinv32; }
+template <typename T> const T* pvals(const Level& l);
+template <> const double* pvals<double>(const Level& l) { return l.pval; }
+template <> const float* pvals<float>(const Level& l) { return l.pval32; }
+template <typename T> const T* cinv(const Hierarchy& h);
+template <> const double* cinv<double>(const Hierarchy& h) { return h.cinv; }
+template <> const float* cinv<float>(const Hierarchy& h) { return h.cinv32; }
+
+inline RedCtx red(Hierarchy& h) { return RedCtx{h.d_part, h.d_ticket}; }
+
+template <typename T>
+void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
+  const int n = h.levels.back().n;
+  const int rpb = kBlock / kWave;
+  k_gemv<T><<<(n + rpb - 1) / rpb, kBlock, 0, h.stream>>>(n, cinv<T>(h), b, x, Act{act});
+}
+
+// cycle(k): x_out = M_k b with a zero initial guess (Algorithm 5 on the top
+// kcycle_levels levels, Algorithm 4 below); `act` guards every kernel.
+template <typename T>
+void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
+  if (h.L() == 0) {
+    coarse_solve<T>(h, b, xo, act);
+    return;
+  }
+  Level& lv = h.levels[k];
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  T* xt = static_cast<T*>(lv.xt);
+  T* r = static_cast<T*>(lv.r);
+  T* rcv = static_cast<T*>(lv.rc);
+  T* c = static_cast<T*>(lv.c);
+  const T* wd = wdinv<T>(lv);
+  const T* pv = pvals<T>(lv);
+  const int L = h.L();
+  const Act A{act};
+
+  launch_rows<T>(lv.n, lv.lpr, lv.rp, lv.ci, vals<T>(lv), OpPresmoothResid<T>{A, b, wd, xt, r}, rc, s);
+  const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
+  if (!kcyc) {
+    launch_elem(lv.nc, OpRestrict<T, false>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr}, rc, s);
+    if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
+    else cycle<T>(h, k + 1, rcv, c, act);
+    launch_elem(lv.n, OpProlong<T>{A, lv.agg, pv, c, xt}, rc, s);
+  } else {
+    Level& lc = h.levels[k + 1];
+    double* K = h.d_sc + kScK + 16 * k;
+    int* F = h.d_ctl + kCtlKFlags + 4 * k;
+    T* v = static_cast<T*>(lv.v);
+    T* rt = static_cast<T*>(lv.rt);
+    T* d = static_cast<T*>(lv.d);
+    T* w = static_cast<T*>(lv.w);
+    const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
+    launch_elem(lv.nc, OpRestrict<T, true>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K}, rc, s);
+    cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
+    launch_rows<T>(lc.n, lc.lpr, lc.rp, lc.ci, vals<T>(lc), OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
+    launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
+    cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
+    launch_rows<T>(lc.n, lc.lpr, lc.rp, lc.ci, vals<T>(lc), OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm},
+                   rc, s);
+    launch_elem(lv.n, OpProlongK<T>{A, lv.agg, pv, c, d, xt, K, F}, rc, s);
+  }
+  launch_rows<T>(lv.n, lv.lpr, lv.rp, lv.ci, vals<T>(lv), OpResidSmooth<T>{A, b, xt, wd, xo}, rc, s);
+}
+
+void set_ctl(Hierarchy& h, int word, int value) {
+  launch_elem(1, OpSetCtl{h.d_ctl, word, value}, red(h), h.stream);
+}
+
+template <typename T>
+void precondition(Hierarchy& h, const int* act) {
+  hipStream_t s = h.stream;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    launch_elem(h.levels[0].n, OpToFloat{Act{act}, h.r, static_cast<float*>(h.bz)}, red(h), s);
+    cycle<float>(h, 0, static_cast<const float*>(h.bz), static_cast<float*>(h.z), act);
+  } else {
+    cycle<double>(h, 0, h.r, static_cast<double*>(h.z), act);
+  }
+}
+
+template <typename T>
+void fcg_iteration(Hierarchy& h, const int* run) {
+  Level& l0 = h.levels[0];
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  const int n = l0.n;
+  launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val,
+                      OpFcgSpmv{Act{run}, h.p, h.r, h.q, h.d_sc, h.d_ctl, h.d_err}, rc, s);
+  launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.x, h.r, h.d_sc, h.d_ctl, h.d_err}, rc, s);
+  precondition<T>(h, run);
+  launch_elem(n, OpDotZQ<T>{Act{run}, static_cast<const T*>(h.z), h.q, h.d_sc}, rc, s);
+  launch_elem(n, OpPUpdate<T>{Act{run}, static_cast<const T*>(h.z), h.p, h.d_sc, 0}, rc, s);
+}
+
+template <typename T>
+void fcg_restart(Hierarchy& h, const int* run) {
+  const int n = h.levels[0].n;
+  precondition<T>(h, run);
+  launch_elem(n, OpPUpdate<T>{Act{run}, static_cast<const T*>(h.z), h.p, h.d_sc, 1}, red(h), h.stream);
+}
+
+void check_err(Hierarchy& h, int bits) {
+  if (!bits) return;
+  if (bits & kErrNonFinite) throw Error(AMG_ENANINF, "non-finite value in the iteration");
+  if (bits & kErrBreakdown) throw Error(AMG_EBREAKDOWN, "Krylov breakdown: p^T A p <= 0");
+  throw Error(AMG_EHIP, "device error bits " + std::to_string(bits));
+}
+
+template <typename T>
+int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
+  Level& l0 = h.levels[0];
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  const int n = l0.n;
+  h.x = x;
+  const int* run = h.d_ctl + kCtlRunning;
+  int* hp = static_cast<int*>(h.h_pinned);
+  double* hd = reinterpret_cast<double*>(hp + 16);
+
+  launch_elem(n, OpFcgInit{b, h.r, x, h.d_sc, h.d_ctl, h.d_err, rtol}, rc, s);
+  fcg_restart<T>(h, run);
+  const int max_iter = h.opt.max_iter;
+  const int every = h.opt.check_every > 0 ? h.opt.check_every : 1;
+  int enqueued = 0;
+  int status = AMG_OK;
+  while (true) {
+    int batch = every;
+    if (enqueued + batch > max_iter) batch = max_iter - enqueued;
+    for (int it = 0; it < batch; ++it) fcg_iteration<T>(h, run);
+    enqueued += batch;
+    AMG_HIP(hipGetLastError());
+    AMG_HIP(hipMemcpyAsync(hp, h.d_ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hp + 2, h.d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    check_err(h, hp[2]);
+    const int running = hp[kCtlRunning];
+    const int done = hp[kCtlIters];
+    if (running && enqueued < max_iter) continue;
+    // recompute the true residual in FP64
+    launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val, OpTrueResid{Act{nullptr}, b, x, h.q, h.d_sc},
+                        rc, s);
+    AMG_HIP(hipMemcpyAsync(hd, h.d_sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    const double bb = hd[kScBB];
+    const double rel = bb > 0.0 ? std::sqrt(hd[kScTrue] / bb) : 0.0;
+    *iters = done;
+    *relres = rel;
+    if (!std::isfinite(rel)) throw Error(AMG_ENANINF, "non-finite residual");
+    if (rel <= rtol || bb == 0.0) break;
+    if (done >= max_iter || enqueued >= max_iter) {
+      status = AMG_ENOTCONV;
+      break;
+    }
+    // the recurrence residual met the tolerance but the true one did not:
+    // restart from the true residual
+    launch_elem(n, OpCopy{h.q, h.r}, rc, s);
+    set_ctl(h, kCtlRunning, 1);
+    fcg_restart<T>(h, run);
+  }
+  return status;
+}
+}  // namespace
+
+int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
+  if (h.mixed()) return fcg<float>(h, b, rtol, x, iters, relres);
+  return fcg<double>(h, b, rtol, x, iters, relres);
+}
+
+// Arnoldi on D^-1 A_k (modified Gram-Schmidt) from the seeded start vector;
+// the (m+1) x m Hessenberg matrix and the norms ||D^-1 A q_j|| are copied to
+// the host (row stride 8).
+void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double* w, double* H_out,
+             double* wnorm_out) {
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  const int n = lv.n;
+  double* sc = h.d_sc;
+  launch_elem(n, OpArnStart{Q, sc, stream}, rc, s);
+  launch_elem(n, OpDivide{Q, Q, sc + kScArn + 56}, rc, s);
+  for (int j = 0; j < m; ++j) {
+    const double* qj = Q + (size_t)j * n;
+    launch_rows<double>(n, lv.lpr, lv.rp, lv.ci, lv.val, OpArnSpmv{qj, Q, lv.diag, w, sc, j}, rc, s);
+    for (int i = 0; i <= j; ++i) {
+      const double* qi = Q + (size_t)i * n;
+      const double* qn = i < j ? Q + (size_t)(i + 1) * n : nullptr;
+      launch_elem(n, OpArnAxpyDot{qi, qn, w, sc + kScArn + i * 8 + j, sc + kScArn + (i + 1) * 8 + j}, rc, s);
+    }
+    launch_elem(n, OpDivide{w, Q + (size_t)(j + 1) * n, sc + kScArn + (j + 1) * 8 + j}, rc, s);
+  }
+  double* hd = static_cast<double*>(h.h_pinned);
+  AMG_HIP(hipMemcpyAsync(hd, sc + kScArn, 56 * sizeof(double), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 48; ++i) H_out[i] = hd[i];
+  for (int j = 0; j < 8; ++j) wnorm_out[j] = hd[48 + j];
+}
+
+int pick_lanes_per_row(int n, int nnz) { return pick_lpr(n, nnz); }
+
+// y = A x for a caller's matrix (float64)
+void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
+              int lpr, hipStream_t s) {
+  if (lpr <= 0) lpr = pick_lpr(n, nnz);
+  RedCtx rc{nullptr, nullptr};
+  launch_rows<double>(n, lpr, rp, ci, val, OpSpmv<double>{Act{nullptr}, x, y}, rc, s);
+}
+
+}  // namespace amg

@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI library: it loads, exports every symbol the header
+declares, and its host-only entry points behave (no GPU work is issued)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amg.h")
+
+amg = pytest.importorskip("paper_1403_1649_amd")
+
+
+def _lib_or_skip():
+    if not os.path.exists(amg.library_path()):
+        pytest.skip("libamg_hip.so not built")
+    return amg.lib()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(amg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("amg_setup", "amg_solve", "amg_destroy", "amg_export_level", "amg_spmv", "amg_galerkin"):
+        assert name in syms
+    assert set(syms) == set(amg.binding.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_default_options_follow_the_paper():
+    _lib_or_skip()
+    o2, o3 = amg.Options(dim=2), amg.Options(dim=3)
+    assert o2.strength_alpha == 0.25 and o3.strength_alpha == 0.5
+    assert o3.coarse_max == 600 and o3.kcycle_levels == 2 and o3.arnoldi_m == 5
+    assert abs(o3.jacobi_scale - 4.0 / 3.0) < 1e-15 and o3.kcycle_t == 0.25
+
+
+def test_status_strings():
+    _lib_or_skip()
+    for code in range(9):
+        assert amg.status_string(code).startswith("AMG")
+
+
+def test_hessenberg_radius_matches_numpy():
+    _lib_or_skip()
+    rng = np.random.default_rng(0)
+    for m in range(1, 9):
+        for _ in range(25):
+            H = np.triu(rng.standard_normal((m, m)), -1)
+            rho = amg.hessenberg_radius(H)
+            want = np.abs(np.linalg.eigvals(H)).max()
+            assert abs(rho - want) <= 1e-10 * max(1.0, want)
+    # complex pair of modulus 2: rotation-scaled 2x2 block
+    H = np.array([[0.0, -2.0], [2.0, 0.0]])
+    assert abs(amg.hessenberg_radius(H) - 2.0) < 1e-14
+
+
+def test_argument_validation_without_gpu():
+    L = _lib_or_skip()
+    h = C.c_void_p()
+    assert L.amg_setup(None, None, None, C.byref(h)) == 1
+    assert L.amg_solve(None, None, 1e-8, None, None, None, None) == 1
+    A = amg.binding.AmgCsrC(0, 0, None, None, None)
+    assert L.amg_spmv(C.byref(A), None, None, 0, None) == 1
+    assert L.amg_node_hash(-1, 0, None, None) == 1
+    assert L.amg_level_info(None, 0, None, None, None, None, None) == 1
+    assert b"amg_level_info" in L.amg_last_error()

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: integer decisions (strength mask, MIS(2) state, aggregates) bit-exact;
+A_{k+1} to 1e-12 (normwise and per entry against the magnitude of its terms);
+omega to 1e-12 relative; the solution to a true relative residual <= 1e-8 on
+both sides with iteration counts within one.
+"""
+import numpy as np
+import pytest
+
+from oracle import amg_oracle as O
+from synthetic import problems as P
+from tests.gpu_helpers import compare_level, dev_vec, oracle_level, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amg = pytest.importorskip("paper_1403_1649_amd")
+
+
+def _setup(A, dim, **kw):
+    rp, ci, v = to_dev(A)
+    opts = amg.Options(dim=dim, **kw)
+    return amg.setup(rp, ci, v, opts), opts
+
+
+def _oracle_opts(dim, **kw):
+    return O.Options.for_dim(dim, **kw)
+
+
+def test_node_hash_bit_exact():
+    for stream in (0, 1, 12345, 0xFFFFFFFF):
+        n = (1 << 20) + 17
+        got = amg.node_hash(n, stream).cpu().numpy().view(np.uint32)
+        want = O.node_hash(np.arange(n), stream).astype(np.uint32)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("lpr", [0, 1, 2, 4, 8, 16, 32, 64])
+def test_spmv_matches_oracle(lpr):
+    A = P.hetero3d(24, seed=7)
+    rp, ci, v = to_dev(A)
+    x = P.exact_solution(A.n, 3)
+    y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=lpr).cpu().numpy()
+    S = A.to_scipy()
+    want = S @ x
+    bound = 1e-15 * 8 * (abs(S) @ np.abs(x))
+    assert np.all(np.abs(y - want) <= bound + 1e-300)
+
+
+def test_galerkin_worked_example_on_gpu():
+    from tests.test_oracle_setup import _read_worked_example
+    import scipy.sparse as sp
+    pattern, aggmap, coarse = _read_worked_example()
+    n = 8
+    a = {(i, j): 10 * i + j + 1.0 / (i + j) for (i, j) in pattern}
+    S = sp.csr_matrix(([a[p] for p in pattern], ([i - 1 for i, _ in pattern], [j - 1 for _, j in pattern])),
+                      shape=(n, n))
+    S.sort_indices()
+    A = P.CSR(S.indptr, S.indices, S.data)
+    agg = np.array([aggmap[i + 1] - 1 for i in range(n)], np.int32)
+    rp, ci, v = to_dev(A)
+    for pval in (np.ones(n), O.interpolation(agg, 3, np.ones(n))[0]):
+        got_rp, got_ci, got_v = amg.galerkin(rp, ci, v, torch.from_numpy(agg).cuda(), dev_vec(pval), 3)
+        want = O.galerkin(S, agg.astype(np.int64), pval, 3)
+        assert np.array_equal(got_rp, want.indptr) and np.array_equal(got_ci, want.indices)
+        assert np.allclose(got_v, want.data, rtol=1e-14, atol=0)
+
+
+def test_galerkin_large_rows_path():
+    """Aggregates whose segments exceed the LDS staging capacity (dense rows)."""
+    rng = np.random.default_rng(4)
+    n = 600
+    import scipy.sparse as sp
+    M = sp.random(n, n, density=0.08, random_state=rng)
+    M = M + M.T + sp.identity(n) * 50
+    S = M.tocsr()
+    S.sort_indices()
+    A = P.CSR(S.indptr, S.indices, S.data)
+    nc = 7
+    agg = np.concatenate([np.arange(nc), rng.integers(0, nc, n - nc)]).astype(np.int32)
+    pval = rng.uniform(0.5, 1.5, n)
+    rp, ci, v = to_dev(A)
+    got_rp, got_ci, got_v = amg.galerkin(rp, ci, v, torch.from_numpy(agg).cuda(), dev_vec(pval), nc)
+    want = O.galerkin(S, agg.astype(np.int64), pval, nc)
+    assert np.array_equal(got_rp, want.indptr) and np.array_equal(got_ci, want.indices)
+    assert np.allclose(got_v, want.data, rtol=1e-12, atol=1e-12 * np.abs(want.data).max())
+
+
+CASES = [
+    ("poisson2d_128", lambda: P.poisson2d(128), 2),
+    ("poisson2d_37x53", lambda: P.poisson2d(37, 53), 2),
+    ("aniso2d_90", lambda: P.aniso2d(90, 1e-3), 2),
+    ("poisson3d_24", lambda: P.poisson3d(24), 3),
+    ("hetero3d_20", lambda: P.hetero3d(20, seed=11), 3),
+    ("aniso3d_18", lambda: P.aniso3d(18, 1e-3), 3),
+]
+
+
+@pytest.mark.parametrize("name,make,dim", CASES, ids=[c[0] for c in CASES])
+def test_levelwise_setup_parity(name, make, dim):
+    A = make()
+    h, _ = _setup(A, dim)
+    oo = _oracle_opts(dim)
+    L = h.num_levels()
+    assert L >= 2
+    for k in range(L - 1):
+        ex = h.export_level(k)
+        nxt = h.export_level(k + 1, what=("A", "B"))
+        if k == 0:
+            assert np.array_equal(ex["row_ptr"], A.row_ptr) and np.array_equal(ex["val"], A.val)
+        lv = oracle_level(ex, oo)
+        compare_level(ex, lv, nxt)
+        assert np.allclose(nxt["B"], lv.Bc, rtol=1e-14, atol=0)
+        omega, _ = O.jacobi_weight(lv.A, oo.arnoldi_m, oo.seed + 1, oo.jacobi_scale)
+        assert abs(ex["omega"] - omega) <= 1e-12 * omega
+        assert ex["mis_rounds"] == lv.mis_rounds
+    last = h.export_level(L - 1, what=("A",))
+    assert last["n"] <= 600
+
+
+@pytest.mark.parametrize("name,make,dim", CASES[:4] + CASES[4:5], ids=[c[0] for c in CASES[:5]])
+def test_solve_matches_oracle(name, make, dim):
+    A = make()
+    xs = P.exact_solution(A.n, 1)
+    b = P.rhs(A, xs)
+    h, _ = _setup(A, dim)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    H = O.setup(A.row_ptr, A.col, A.val, _oracle_opts(dim))
+    ref = O.solve(H, b, 1e-8)
+    true_rel = np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b)
+    assert rel <= 1e-8 and true_rel <= 1.01e-8
+    assert abs(it - ref.iters) <= 1, (it, ref.iters)
+    assert np.linalg.norm(x - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("name,make,dim", [CASES[0], CASES[4]], ids=[CASES[0][0], CASES[4][0]])
+def test_mixed_precision_solve(name, make, dim):
+    A = make()
+    xs = P.exact_solution(A.n, 1)
+    b = P.rhs(A, xs)
+    h64, _ = _setup(A, dim)
+    _, it64, _ = amg.solve(h64, dev_vec(b), 1e-8)
+    h, _ = _setup(A, dim, precision="mixed")
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8
+    assert np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1.01e-8
+    assert it <= it64 + 3
+
+
+def test_single_level_and_zero_rhs():
+    A = P.poisson2d(20)              # 400 <= coarse_max: the preconditioner is the exact solve
+    h, _ = _setup(A, 2)
+    assert h.num_levels() == 1
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    assert it == 1 and rel <= 1e-12
+    x, it, rel = amg.solve(h, dev_vec(np.zeros(A.n)), 1e-8)
+    assert it == 0 and rel == 0.0 and float(x.abs().max()) == 0.0
+
+
+def test_error_paths():
+    A = P.poisson2d(64)
+    h, _ = _setup(A, 2, max_iter=1)
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    with pytest.raises(amg.AmgError) as e:
+        amg.solve(h, dev_vec(b), 1e-8)
+    assert e.value.code == 4
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8, allow_notconv=True)
+    assert it == 1 and rel > 1e-8
+    bad = b.copy()
+    bad[3] = np.nan
+    h2, _ = _setup(A, 2)
+    with pytest.raises(amg.AmgError) as e:
+        amg.solve(h2, dev_vec(bad), 1e-8)
+    assert e.value.code == 7
+    # zero diagonal
+    v = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    v[np.flatnonzero(A.col == rows)[5]] = 0.0
+    with pytest.raises(amg.AmgError) as e:
+        _setup(P.CSR(A.row_ptr, A.col, v), 2)
+    assert e.value.code == 1
+    # structurally nonsymmetric pattern
+    import scipy.sparse as sp
+    S = A.to_scipy().tolil()
+    S[0, A.n - 1] = -0.5
+    S = S.tocsr()
+    S.sort_indices()
+    with pytest.raises(amg.AmgError) as e:
+        _setup(P.CSR(S.indptr, S.indices, S.data), 2)
+    assert e.value.code == 1
+
+
+def test_repeated_setup_is_deterministic():
+    A = P.hetero3d(16, seed=3)
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    outs = []
+    for _ in range(2):
+        h, _ = _setup(A, 3)
+        x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+        outs.append((x.cpu().numpy(), it, rel, h.export_level(1, what=("A",))["val"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][3], outs[1][3])
