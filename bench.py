@@ -35,12 +35,19 @@ def spmv_bytes(n, nnz, val_bytes=8):
     return val_bytes * nnz + 4 * nnz + 4 * (n + 1) + 2 * val_bytes * n
 
 
+def presmooth_bytes(n, nnz, val_bytes=8):
+    """Compulsory traffic of the level-0 pre-smoothing + residual kernel
+    (x = w.*b, r = b - A x): A in CSR, b and w read once, x and r written."""
+    return (val_bytes + 4) * nnz + 4 * (n + 1) + 4 * val_bytes * n
+
+
 def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
     rp, ci, v = dev
     bt = torch.from_numpy(b).cuda()
     x = torch.empty_like(bt)
     opts = amg.Options(dim=dim, **opt)
     results = []
+    probe = [0.0, 0]
     for i in range(warmup + steps):
         if i == warmup:
             torch.cuda.synchronize()
@@ -50,10 +57,14 @@ def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
         if i >= warmup:
             s_ms, v_ms = h.timings()
             results.append((it, rel, s_ms, v_ms))
+            ms, cnt = h.probe_timing()
+            probe[0] += ms * cnt
+            probe[1] += cnt
         del h
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    return wall, results, x
+    probe_ms = probe[0] / probe[1] if probe[1] else None
+    return wall, results, x, (probe_ms, probe[1])
 
 
 def cpu_baseline(A, dim, b):
@@ -100,7 +111,8 @@ def main():
     torch.cuda.synchronize()
 
     log("bench: fp64 setup+solve")
-    wall, res, x = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup)
+    wall, res, x, (probe_ms, probe_n) = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup,
+                                                 probe="l0_presmooth")
     iters = [r[0] for r in res]
     rels = [r[1] for r in res]
     ok = all(r <= 1e-8 for r in rels)
@@ -111,7 +123,7 @@ def main():
                       "solve_ms": round(float(np.median([r[3] for r in res])), 3)}}
     if not args.no_mixed:
         log("bench: mixed setup+solve")
-        wall_m, res_m, xm = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup, precision="mixed")
+        wall_m, res_m, xm, _ = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup, precision="mixed")
         ok_m = all(r[1] <= 1e-8 for r in res_m)
         forms["mixed"] = {"mdof_s": round(A.n / wall_m / 1e6 if ok_m else 0.0, 3), "iters": res_m[-1][0],
                           "relres": max(r[1] for r in res_m),
@@ -143,11 +155,18 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": A.n, "nnz": A.nnz, "rtol": 1e-8},
         "forms": forms,
-        "spmv": {"gb_s": round(gbs, 1), "us": round(t_spmv * 1e6, 2), "bytes": nbytes},
-        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "level-0 CSR SpMV (amg_spmv)"},
+        "spmv": {"gb_s": round(gbs, 1), "us": round(t_spmv * 1e6, 2), "bytes": nbytes,
+                 "frac": round(gbs / PEAK_HBM_GBS, 4)},
     }
+    pbytes = presmooth_bytes(A.n, A.nnz)
+    if probe_ms:
+        ach = pbytes / (probe_ms * 1e-3) / 1e9
+        line["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                            "kernel": "k_rows<double,8,OpPresmoothResid<double>> (level-0 pre-smoothing + "
+                                      "residual, inside the solve)",
+                            "bytes_per_launch": pbytes, "avg_us": round(probe_ms * 1e3, 2),
+                            "samples": probe_n}
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline (single thread)")
         line["cpu_baseline"] = cpu_baseline(A, dim, b)

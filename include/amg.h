@@ -48,6 +48,11 @@ typedef enum {
 typedef enum { AMG_KRYLOV_FCG = 0, AMG_KRYLOV_FGMRES = 1 } amg_krylov;
 typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_MIXED = 1 } amg_precision;
 typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1 } amg_smoother;
+/* Kernels that amg_probe_timing can report: the level-0 pre-smoothing plus
+ * residual kernel (x = omega D^-1 b, r = b - A x), the level-0 residual plus
+ * post-smoothing kernel, and the outer Krylov mat-vec q = A p. */
+typedef enum { AMG_PROBE_NONE = 0, AMG_PROBE_L0_PRESMOOTH = 1, AMG_PROBE_L0_POSTSMOOTH = 2,
+               AMG_PROBE_OUTER_SPMV = 3 } amg_probe;
 
 /* Options (Sections 2.1.1, 2.2, 2.2.1, 3). */
 typedef struct {
@@ -65,9 +70,15 @@ typedef struct {
   int32_t smoother;       /* amg_smoother (JACOBI) */
   int32_t max_iter;       /* outer iteration limit (200) */
   int32_t dense_max;      /* largest coarsest level accepted after a stall (4096) */
-  int32_t check_every;    /* outer iterations enqueued between host convergence checks (1) */
-  uint32_t flags;         /* reserved, 0 */
+  int32_t probe;          /* amg_probe: level-0 kernel timed with HIP events during solves (0) */
+  int32_t check_every;    /* largest number of outer iterations enqueued between host
+                             convergence checks; the batch adapts to the observed rate (16) */
+  uint32_t flags;         /* AMG_FLAG_* bits (0) */
 } amg_options;
+
+/* amg_options.flags: launch every kernel from the host instead of replaying
+ * the captured HIP graph of an outer iteration (for debugging and timing). */
+#define AMG_FLAG_NO_GRAPH 1u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {
@@ -166,6 +177,13 @@ int32_t amg_hessenberg_radius(const double* H, int32_t m, double* rho);
 /* (host) timing of the last setup and solve on this hierarchy, in ms, from
  * HIP events on the hierarchy's stream. */
 int32_t amg_timings(const amg_hierarchy* h, double* setup_ms, double* solve_ms);
+
+/* (host) average duration in ms of the kernel selected by opt.probe, over the
+ * samples taken since setup: HIP events recorded on the solve stream right
+ * before and after that kernel (inside the replayed outer iteration), read at
+ * host convergence checks whose last iteration ran the kernel.  *samples = 0
+ * when no probe was selected or no sample was taken. */
+int32_t amg_probe_timing(const amg_hierarchy* h, double* avg_ms, int32_t* samples);
 
 #ifdef __cplusplus
 }

@@ -12,12 +12,13 @@ _LIB = None
 AMG_OK, AMG_EINVAL, AMG_ENOMEM, AMG_EHIP, AMG_ENOTCONV = 0, 1, 2, 3, 4
 AMG_EBREAKDOWN, AMG_ECOARSEN, AMG_ENANINF, AMG_EUNSUPPORTED = 5, 6, 7, 8
 _PREC = {"fp64": 0, "mixed": 1}
+_PROBE = {"none": 0, "l0_presmooth": 1, "l0_postsmooth": 2, "outer_spmv": 3}
 _KRYLOV = {"fcg": 0, "fgmres": 1}
 
 EXPORTED = [
     "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",
     "amg_destroy", "amg_num_levels", "amg_level_info", "amg_export_level", "amg_spmv",
-    "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings",
+    "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
 ]
 
 
@@ -27,7 +28,7 @@ class AmgOptionsC(C.Structure):
         ("kcycle_levels", C.c_int32), ("kcycle_t", C.c_double), ("jacobi_scale", C.c_double),
         ("arnoldi_m", C.c_int32), ("seed", C.c_uint32), ("krylov", C.c_int32),
         ("gmres_restart", C.c_int32), ("precision", C.c_int32), ("smoother", C.c_int32),
-        ("max_iter", C.c_int32), ("dense_max", C.c_int32), ("check_every", C.c_int32),
+        ("max_iter", C.c_int32), ("dense_max", C.c_int32), ("probe", C.c_int32), ("check_every", C.c_int32),
         ("flags", C.c_uint32),
     ]
 
@@ -90,6 +91,8 @@ def lib():
     L.amg_hessenberg_radius.restype = i32
     L.amg_timings.argtypes = [vp, P(dbl), P(dbl)]
     L.amg_timings.restype = i32
+    L.amg_probe_timing.argtypes = [vp, P(dbl), P(i32)]
+    L.amg_probe_timing.restype = i32
     _LIB = L
     return L
 
@@ -128,6 +131,8 @@ class Options:
                 v = _PREC[v]
             if k == "krylov" and isinstance(v, str):
                 v = _KRYLOV[v]
+            if k == "probe" and isinstance(v, str):
+                v = _PROBE[v]
             if not hasattr(self.c, k):
                 raise KeyError(k)
             setattr(self.c, k, v)
@@ -203,6 +208,12 @@ class Hierarchy:
         s, v = C.c_double(), C.c_double()
         _check(lib().amg_timings(self._h, C.byref(s), C.byref(v)))
         return s.value, v.value
+
+    def probe_timing(self):
+        """(average ms, samples) of the kernel selected by the probe option."""
+        ms, n = C.c_double(), C.c_int32()
+        _check(lib().amg_probe_timing(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
 
 def setup(row_ptr, col, val, opts: Options | None = None, dim: int = 3) -> Hierarchy:

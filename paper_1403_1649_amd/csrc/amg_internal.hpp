@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <cstddef>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -115,10 +116,23 @@ struct Hierarchy {
   // pinned host mirror for read-backs
   void* h_pinned = nullptr;
   // outer solve vectors (float64, size n_0)
-  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double *r = nullptr, *p = nullptr, *q = nullptr;
   void* z = nullptr;           // preconditioned residual (cycle precision)
   void* bz = nullptr;          // cycle right-hand side in cycle precision (mixed mode)
+  double* xint = nullptr;      // iterate of the outer solve (copied to the caller's x at exit)
+  // captured launch sequences of one outer iteration (one segment, or two
+  // around the probed kernel, which is then launched from the host between
+  // them) and of the (re)start
+  std::vector<hipGraphExec_t> g_iter;
+  hipGraphExec_t g_restart = nullptr;
+  std::function<void(hipStream_t)> probe_fn;
+  hipStream_t cap_stream = nullptr;
+  bool capturing = false;      // inside any stream capture
+  bool split_at_probe = false; // capturing the outer iteration with a probe
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t pev[2] = {nullptr, nullptr};   // around the probed kernel
+  double probe_ms = 0.0;
+  int probe_samples = 0;
   float setup_ms = 0.f, solve_ms = 0.f;
   bool mixed() const { return opt.precision == AMG_PREC_MIXED; }
   int L() const { return (int)levels.size() - 1; }
@@ -129,7 +143,7 @@ struct Hierarchy {
 enum CtlWord : int {
   kCtlRunning = 0,     // outer iteration active
   kCtlIters = 1,       // outer iterations performed
-  kCtlMisPing = 2,     // undecided counters of MIS(2) rounds (two words)
+  kCtlMisPing = 2,     // "some node undecided" flags of MIS(2) rounds (two words)
   kCtlMisRounds = 4,   // rounds that found undecided nodes
   kCtlOne = 5,         // constant 1 (an always-active flag)
   kCtlAggFill = 6,     // scratch counter
@@ -165,7 +179,7 @@ void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask
                        const int* gptr, int* gcol, hipStream_t s);
 void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s);
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1,
-                      int* ctl, int round, hipStream_t s);
+                      int* ctl, int round, int lanes, hipStream_t s);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
 void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T,
                       const int* root_id, int* choice, int* agg, int* err, hipStream_t s);
@@ -199,6 +213,7 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 
 // cycle and outer solvers (solver.hip)
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
+void build_solve_graphs(Hierarchy& h);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
               int lpr, hipStream_t s);
 int pick_lanes_per_row(int n, int nnz);

@@ -67,7 +67,8 @@ void amg_default_options(amg_options* opt, int32_t dim) {
   opt->smoother = AMG_SMOOTHER_JACOBI;
   opt->max_iter = 200;
   opt->dense_max = 4096;
-  opt->check_every = 1;
+  opt->probe = AMG_PROBE_NONE;
+  opt->check_every = 16;
   opt->flags = 0;
 }
 
@@ -102,6 +103,7 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
   if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
     return fail(AMG_EINVAL, "amg_setup: unknown precision");
   if (o.smoother != AMG_SMOOTHER_JACOBI) return fail(AMG_EUNSUPPORTED, "amg_setup: smoother");
+  if (o.probe < AMG_PROBE_NONE || o.probe > AMG_PROBE_OUTER_SPMV) return fail(AMG_EINVAL, "amg_setup: probe");
   auto* H = new (std::nothrow) amg_hierarchy();
   if (!H) return fail(AMG_ENOMEM, "amg_setup: host allocation");
   int32_t st = guarded("amg_setup", [&] {
@@ -250,6 +252,13 @@ int32_t amg_timings(const amg_hierarchy* H, double* setup_ms, double* solve_ms) 
   if (!H) return fail(AMG_EINVAL, "amg_timings: NULL hierarchy");
   if (setup_ms) *setup_ms = H->h.setup_ms;
   if (solve_ms) *solve_ms = H->h.solve_ms;
+  return AMG_OK;
+}
+
+int32_t amg_probe_timing(const amg_hierarchy* H, double* avg_ms, int32_t* samples) {
+  if (!H || !avg_ms || !samples) return fail(AMG_EINVAL, "amg_probe_timing: NULL argument");
+  *samples = H->h.probe_samples;
+  *avg_ms = H->h.probe_samples ? H->h.probe_ms / H->h.probe_samples : 0.0;
   return AMG_OK;
 }
 

@@ -4,12 +4,14 @@
 // so each coarse solve in the cycle is one dense mat-vec (a GEMV over at most
 // dense_max^2 entries) instead of two sequential triangular solves.
 //
-// The elimination runs as one cooperative kernel: each block owns a band of
-// columns of the row-major work matrix; per pivot step the owner of column k
-// picks the pivot and publishes column k, one grid barrier, then every block
-// updates its band.  A single block needs no grid barrier at all.
-#include <hip/hip_cooperative_groups.h>
-
+// The elimination runs as one kernel of at most 128 blocks: each block owns a
+// band of columns (in LDS when the bands fit, else in the row-major work
+// matrix in global memory); per pivot step the owner of
+// column k picks the pivot and publishes column k, one grid barrier, then
+// every block updates its band.  A single block needs no grid barrier.  The
+// barrier needs all blocks resident at once: each block is one 1024-thread
+// workgroup (one CU), and the grid never exceeds 128 of the 256 CUs, so later
+// blocks always find room even while other work occupies the device.
 #include <cmath>
 
 #include "amg_internal.hpp"
@@ -132,6 +134,107 @@ __global__ void __launch_bounds__(kGJThreads) k_gauss_jordan(int n, int band, do
   }
 }
 
+// Same elimination with each block's band of columns resident in LDS
+// (column-major: S[j*n + i] = W[i][c0 + j]); only the pivot column crosses
+// blocks, through global memory and the grid barrier.  Dynamic LDS holds the
+// band, the pivot column and the pivot row.
+__global__ void __launch_bounds__(kGJThreads) k_gauss_jordan_lds(int n, int band, double* __restrict__ W,
+                                                                 int* __restrict__ piv,
+                                                                 double* __restrict__ colbuf, int* sync,
+                                                                 int* err) {
+  extern __shared__ double S[];
+  double* s_col = S + (size_t)band * n;
+  double* s_rowk = s_col + n;
+  __shared__ double s_val[kGJThreads / kWave];
+  __shared__ int s_idx[kGJThreads / kWave];
+  __shared__ int s_p;
+  const int nb = gridDim.x;
+  const int c0 = blockIdx.x * band;
+  const int w = min(n, c0 + band) - c0;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w * n; e += blockDim.x) {
+    const int i = e / w, j = e - i * w;
+    S[j * n + i] = W[(size_t)i * n + c0 + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const int owner = k / band;
+    if ((int)blockIdx.x == owner) {
+      const double* col = S + (size_t)(k - c0) * n;
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < n; i += blockDim.x) {
+        const double a = fabs(col[i]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if ((tid & (kWave - 1)) == 0) {
+        s_val[tid / kWave] = best;
+        s_idx[tid / kWave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int q = 1; q < (int)(blockDim.x / kWave); ++q)
+          if (s_val[q] > best || (s_val[q] == best && s_idx[q] < bi)) { best = s_val[q]; bi = s_idx[q]; }
+        piv[k] = bi;
+        s_p = bi;
+        if (!(best > 0.0)) atomic_or_flag(err, kErrSingular);
+      }
+      if (nb > 1) {
+        double* cb = colbuf + (size_t)(k & 1) * n;
+        for (int i = tid; i < n; i += blockDim.x) cb[i] = col[i];
+      } else {
+        for (int i = tid; i < n; i += blockDim.x) s_col[i] = col[i];
+      }
+    }
+    int p;
+    if (nb > 1) {
+      grid_barrier(sync, nb);
+      p = __hip_atomic_load(&piv[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double* cb = colbuf + (size_t)(k & 1) * n;
+      for (int i = tid; i < n; i += blockDim.x) s_col[i] = cb[i];
+      __syncthreads();
+    } else {
+      __syncthreads();
+      p = s_p;
+    }
+    const double ck = s_col[p];
+    for (int j = tid; j < w; j += blockDim.x) {
+      double a = S[(size_t)j * n + k];
+      if (p != k) {
+        const double b = S[(size_t)j * n + p];
+        S[(size_t)j * n + p] = a;
+        a = b;
+      }
+      s_rowk[j] = a;
+    }
+    __syncthreads();
+    const double inv = 1.0 / ck;
+    for (int e = tid; e < w * n; e += blockDim.x) {
+      const int j = e / n, i = e - j * n;
+      const int colj = c0 + j;
+      const double ci = (i == k) ? ck : (i == p ? s_col[k] : s_col[i]);
+      double* dst = S + (size_t)j * n + i;
+      if (colj == k) {
+        *dst = (i == k) ? inv : -ci * inv;
+      } else if (i == k) {
+        *dst = s_rowk[j] * inv;
+      } else {
+        *dst -= ci * (s_rowk[j] * inv);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < w * n; e += blockDim.x) {
+    const int i = e / w, j = e - i * w;
+    W[(size_t)i * n + c0 + j] = S[j * n + i];
+  }
+}
+
 // Undo the row exchanges as column exchanges (last step first) and emit the
 // float64 and float32 inverses.
 __global__ void k_gj_unpermute(int n, const double* __restrict__ W, const int* __restrict__ piv,
@@ -164,17 +267,35 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
   const size_t nn = (size_t)n * n;
   k_dense_zero<<<(int)std::min<size_t>((nn + 255) / 256, 4096), 256, 0, s>>>(nn, work);
   k_dense_scatter<<<(n + 255) / 256, 256, 0, s>>>(n, rp, ci, val, work);
-  // band of columns per block: at most 1024 (the LDS copy of pivot row k)
-  int nb = (int)std::min<long>(64, std::max<long>(1, (long)nn / 16384));
-  int band = (n + nb - 1) / nb;
-  if (band > 1024) band = 1024;
-  nb = (n + band - 1) / band;
   int* piv = sync + 4;
   double* colbuf = work + nn;
   launch_fill_int(4, sync, 0, s);
-  void* args[] = {(void*)&n, (void*)&band, (void*)&work, (void*)&piv, (void*)&colbuf, (void*)&sync,
-                  (void*)&err};
-  AMG_HIP(hipLaunchCooperativeKernel((const void*)k_gauss_jordan, dim3(nb), dim3(kGJThreads), args, 0, s));
+  // LDS-resident bands when at most 128 blocks hold the matrix, else bands in
+  // global memory (at most 64 blocks, band <= 1024 for the LDS pivot row)
+  int dev = 0, lds_max = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  AMG_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const long budget = (long)lds_max - 4096;   // static LDS of the kernel
+  long band = budget / 8 / (n + 1) - 1;
+  if (band >= 1) {
+    long nb = (n + band - 1) / band;
+    band = (n + nb - 1) / nb;
+    nb = (n + band - 1) / band;
+    if (nb <= 128) {
+      const size_t bytes = ((size_t)band * n + n + band) * sizeof(double);
+      AMG_HIP(hipFuncSetAttribute((const void*)k_gauss_jordan_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes));
+      k_gauss_jordan_lds<<<(int)nb, kGJThreads, bytes, s>>>(n, (int)band, work, piv, colbuf, sync, err);
+      const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
+      k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
+      return;
+    }
+  }
+  int nbg = (int)std::min<long>(64, std::max<long>(1, (long)nn / 16384));
+  int bandg = (n + nbg - 1) / nbg;
+  if (bandg > 1024) bandg = 1024;
+  nbg = (n + bandg - 1) / bandg;
+  k_gauss_jordan<<<nbg, kGJThreads, 0, s>>>(n, bandg, work, piv, colbuf, sync, err);
   const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
   k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
 }

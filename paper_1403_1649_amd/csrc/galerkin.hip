@@ -6,8 +6,9 @@
 // (first occurrence wins, so the result does not depend on timing), and each
 // coarse entry is the sum of its terms in segment order.  A count pass sizes
 // the rows, a scan makes the row pointers, a fill pass writes sorted columns.
-// Rows whose segment holds more than kCap terms go to a block-per-row path
-// that extracts the distinct J in ascending order without staging.
+// Rows whose segment holds more than 256 terms are staged by a whole block
+// (up to 1536 terms); larger ones go to a block-per-row path that extracts
+// the distinct J in ascending order without staging.
 #include <climits>
 
 #include "amg_internal.hpp"
@@ -16,106 +17,99 @@
 namespace amg {
 
 namespace {
-constexpr int kCap = 256;       // staged terms per coarse row (fast path)
-constexpr int kHashBits = 9;
-constexpr int kHash = 1 << kHashBits;
 constexpr int kBig = 256;       // threads per block on the large-row path
 
-__device__ __forceinline__ int hslot(int J) {
-  return (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - kHashBits));
-}
-
-template <bool FILL>
-__global__ void __launch_bounds__(kWave) k_galerkin_wave(
+// One coarse row per group of NT threads (NT = 64: a wave; NT = 256: a block).
+// Terms are staged in LDS up to CAP; rows with more terms go to the next
+// overflow list in the count pass and are skipped in the fill pass.
+template <int NT, int CAP, int HB, bool FILL, bool LISTED>
+__global__ void __launch_bounds__(NT) k_galerkin_stage(
     int nc, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
     const int* __restrict__ agg, const double* __restrict__ pval, const int* __restrict__ agg_ptr,
-    const int* __restrict__ agg_rows, int* __restrict__ row_count, int* __restrict__ ovf_list,
-    int* __restrict__ ovf_count, const int* __restrict__ rp_c, int* __restrict__ ci_c,
-    double* __restrict__ val_c) {
-  __shared__ int keys[kCap];
-  __shared__ double vals[FILL ? kCap : 1];
-  __shared__ int hkey[kHash];
-  __shared__ int hfirst[kHash];
-  __shared__ int ukeys[kCap];
+    const int* __restrict__ agg_rows, int* __restrict__ row_count, const int* __restrict__ in_list,
+    const int* __restrict__ in_count, int* __restrict__ out_list, int* __restrict__ out_count,
+    const int* __restrict__ rp_c, int* __restrict__ ci_c, double* __restrict__ val_c) {
+  constexpr int HS = 1 << HB;
+  __shared__ int keys[CAP];
+  __shared__ double vals[FILL ? CAP : 1];
+  __shared__ int hkey[HS];
+  __shared__ int hfirst[HS];
+  __shared__ int ukeys[CAP];
+  __shared__ int tmp[NT / kWave + 1];
   __shared__ int s_cnt;
-  const int I = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int sb = agg_ptr[I], se = agg_ptr[I + 1];
-
-  int T = 0;
-  for (int base = sb; base < se; base += kWave) {
-    int k = base + lane;
-    int len = 0;
-    if (k < se) { int i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
-    T += wave_sum_int(len);
-  }
-  if (T > kCap) {
-    if (!FILL && lane == 0) {
-      int p = atomicAdd(ovf_count, 1);
-      ovf_list[p] = I;
+  const int tid = threadIdx.x;
+  const int count = LISTED ? *in_count : nc;
+  for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int I = LISTED ? in_list[idx] : idx;
+    const int sb = agg_ptr[I], se = agg_ptr[I + 1];
+    int T = 0;
+    for (int base = sb; base < se; base += NT) {
+      const int k = base + tid;
+      int len = 0;
+      if (k < se) { const int i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
+      int tot;
+      (void)block_exclusive_scan(len, tmp, &tot);
+      T += tot;
     }
-    return;
-  }
-  for (int s = lane; s < kHash; s += kWave) { hkey[s] = -1; hfirst[s] = INT_MAX; }
-  if (lane == 0) s_cnt = 0;
-
-  // stage the terms in segment order (row by row, entries in column order)
-  int off = 0;
-  for (int base = sb; base < se; base += kWave) {
-    int k = base + lane;
-    int i = -1, len = 0;
-    if (k < se) { i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
-    int incl = len;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      int t = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += t;
+    if (T > CAP) {
+      if (!FILL && tid == 0) out_list[atomicAdd(out_count, 1)] = I;
+      continue;
     }
-    int pos = off + incl - len;
-    if (i >= 0) {
-      const double pi = FILL ? pval[i] : 0.0;
-      for (int e = rp[i]; e < rp[i + 1]; ++e, ++pos) {
-        int j = ci[e];
-        keys[pos] = agg[j];
-        if (FILL) vals[pos] = __dmul_rn(__dmul_rn(pi, val[e]), pval[j]);
+    for (int q = tid; q < HS; q += NT) { hkey[q] = -1; hfirst[q] = INT_MAX; }
+    if (tid == 0) s_cnt = 0;
+    // stage the terms in segment order (row by row, entries in column order)
+    int off = 0;
+    for (int base = sb; base < se; base += NT) {
+      const int k = base + tid;
+      int i = -1, len = 0;
+      if (k < se) { i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
+      int tot;
+      int pos = off + block_exclusive_scan(len, tmp, &tot);
+      if (i >= 0) {
+        const double pi = FILL ? pval[i] : 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; ++e, ++pos) {
+          const int j = ci[e];
+          keys[pos] = agg[j];
+          if (FILL) vals[pos] = __dmul_rn(__dmul_rn(pi, val[e]), pval[j]);
+        }
+      }
+      off += tot;
+    }
+    __syncthreads();
+    for (int t = tid; t < T; t += NT) {
+      const int J = keys[t];
+      int q = (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - HB));
+      while (true) {
+        const int prev = atomicCAS(&hkey[q], -1, J);
+        if (prev == -1 || prev == J) { atomicMin(&hfirst[q], t); break; }
+        q = (q + 1) & (HS - 1);
       }
     }
-    off += __shfl(incl, kWave - 1, kWave);
-  }
-  __syncthreads();
-
-  for (int t = lane; t < T; t += kWave) {
-    int J = keys[t];
-    int s = hslot(J);
-    while (true) {
-      int prev = atomicCAS(&hkey[s], -1, J);
-      if (prev == -1 || prev == J) { atomicMin(&hfirst[s], t); break; }
-      s = (s + 1) & (kHash - 1);
+    __syncthreads();
+    for (int t = tid; t < T; t += NT) {
+      const int J = keys[t];
+      int q = (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - HB));
+      while (hkey[q] != J) q = (q + 1) & (HS - 1);
+      if (hfirst[q] == t) ukeys[atomicAdd(&s_cnt, 1)] = J;
     }
-  }
-  __syncthreads();
-  for (int t = lane; t < T; t += kWave) {
-    int J = keys[t];
-    int s = hslot(J);
-    while (hkey[s] != J) s = (s + 1) & (kHash - 1);
-    if (hfirst[s] == t) ukeys[atomicAdd(&s_cnt, 1)] = J;
-  }
-  __syncthreads();
-  const int U = s_cnt;
-  if (!FILL) {
-    if (lane == 0) row_count[I] = U;
-    return;
-  }
-  const int out0 = rp_c[I];
-  for (int u = lane; u < U; u += kWave) {
-    const int J = ukeys[u];
-    int rank = 0;
-    for (int v = 0; v < U; ++v) rank += ukeys[v] < J;
-    double s = 0.0;
-    for (int t = 0; t < T; ++t)
-      if (keys[t] == J) s = __dadd_rn(s, vals[t]);
-    ci_c[out0 + rank] = J;
-    val_c[out0 + rank] = s;
+    __syncthreads();
+    const int U = s_cnt;
+    if (!FILL) {
+      if (tid == 0) row_count[I] = U;
+    } else {
+      const int out0 = rp_c[I];
+      for (int u = tid; u < U; u += NT) {
+        const int J = ukeys[u];
+        int rank = 0;
+        for (int v = 0; v < U; ++v) rank += ukeys[v] < J;
+        double sum = 0.0;
+        for (int t = 0; t < T; ++t)
+          if (keys[t] == J) sum = __dadd_rn(sum, vals[t]);
+        ci_c[out0 + rank] = J;
+        val_c[out0 + rank] = sum;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -188,24 +182,37 @@ __global__ void __launch_bounds__(kBig) k_galerkin_big(
 }
 }  // namespace
 
+// Count pass: waves take rows of up to 256 terms; blocks take the rows
+// listed as larger (up to 1536 terms); the rest go to the extraction path.
 void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
                            const int* agg_rows, int* row_count, int* ovf_list, int* ctl_ovf, hipStream_t s) {
   if (nc <= 0) return;
-  launch_fill_int(1, ctl_ovf, 0, s);
-  k_galerkin_wave<false><<<nc, kWave, 0, s>>>(nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows,
-                                              row_count, ovf_list, ctl_ovf, nullptr, nullptr, nullptr);
-  k_galerkin_big<false><<<256, kBig, 0, s>>>(rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows,
-                                             row_count, ovf_list, ctl_ovf, nullptr, nullptr, nullptr);
+  int* list1 = ovf_list;
+  int* list2 = ovf_list + nc;
+  launch_fill_int(2, ctl_ovf, 0, s);
+  k_galerkin_stage<kWave, 256, 9, false, false><<<nc, kWave, 0, s>>>(
+      nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, nullptr, nullptr, list1, ctl_ovf, nullptr,
+      nullptr, nullptr);
+  k_galerkin_stage<256, 1536, 12, false, true><<<1024, 256, 0, s>>>(
+      nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, list1, ctl_ovf, list2, ctl_ovf + 1,
+      nullptr, nullptr, nullptr);
+  k_galerkin_big<false><<<256, kBig, 0, s>>>(rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, list2,
+                                             ctl_ovf + 1, nullptr, nullptr, nullptr);
 }
 
 void launch_galerkin_fill(int nc, const int* rp, const int* ci, const double* val, const int* agg,
                           const double* pval, const int* agg_ptr, const int* agg_rows, const int* rp_c,
                           int* ci_c, double* val_c, const int* ovf_list, const int* ctl_ovf, hipStream_t s) {
   if (nc <= 0) return;
-  k_galerkin_wave<true><<<nc, kWave, 0, s>>>(nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr,
-                                             nullptr, nullptr, rp_c, ci_c, val_c);
-  k_galerkin_big<true><<<256, kBig, 0, s>>>(rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr,
-                                            ovf_list, ctl_ovf, rp_c, ci_c, val_c);
+  const int* list1 = ovf_list;
+  const int* list2 = ovf_list + nc;
+  k_galerkin_stage<kWave, 256, 9, true, false><<<nc, kWave, 0, s>>>(
+      nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, nullptr, nullptr, nullptr, nullptr, rp_c, ci_c,
+      val_c);
+  k_galerkin_stage<256, 1536, 12, true, true><<<1024, 256, 0, s>>>(
+      nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, list1, ctl_ovf, nullptr, nullptr, rp_c, ci_c, val_c);
+  k_galerkin_big<true><<<256, kBig, 0, s>>>(rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, list2,
+                                            ctl_ovf + 1, rp_c, ci_c, val_c);
 }
 
 }  // namespace amg

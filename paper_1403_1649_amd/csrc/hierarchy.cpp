@@ -93,8 +93,12 @@ void* Arena::alloc(size_t bytes) {
 
 Hierarchy::~Hierarchy() {
   if (stream) (void)hipStreamSynchronize(stream);
+  for (auto& g : g_iter) (void)hipGraphExecDestroy(g);
+  if (g_restart) (void)hipGraphExecDestroy(g_restart);
   if (h_pinned) (void)hipHostFree(h_pinned);
   for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : pev)
     if (e) (void)hipEventDestroy(e);
 }
 
@@ -218,6 +222,7 @@ void alloc_solve_vectors(Hierarchy& h) {
   h.p = h.arena.alloc_n<double>(n0);
   h.q = h.arena.alloc_n<double>(n0);
   h.z = h.arena.alloc(n0 * es);
+  h.xint = h.arena.alloc_n<double>(n0);
   if (h.mixed()) h.bz = h.arena.alloc(n0 * es);
 }
 
@@ -255,7 +260,7 @@ static void galerkin_product(Hierarchy& h, Arena& tmp, Arena& out, const Level& 
   hipStream_t s = h.stream;
   Sync sy{h};
   int* row_count = tmp.alloc_n<int>(nc);
-  int* ovf = tmp.alloc_n<int>(nc);
+  int* ovf = tmp.alloc_n<int>(2 * (size_t)nc);
   int* ctl_ovf = h.d_ctl + kCtlAggFill;
   launch_galerkin_count(nc, lv.rp, lv.ci, agg, agg_ptr, agg_rows, row_count, ovf, ctl_ovf, s);
   *rp_c = out.alloc_n<int>(nc + 1);
@@ -371,8 +376,11 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     launch_mis_init(n, cnt, o.seed, lv.tuple, h.d_ctl, h.d_err, s);
     int round = 0;
     const int batch = 4;
+    int glanes = 1;
+    while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
     while (true) {
-      for (int b = 0; b < batch; ++b, ++round) launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, s);
+      for (int b = 0; b < batch; ++b, ++round)
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, s);
       sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
       sy.fetch(h.d_ctl + kCtlMisRounds, 1);
       sy.wait_and_check();
@@ -453,6 +461,11 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
   sy.wait_and_check();
+  if (o.probe != AMG_PROBE_NONE) {
+    AMG_HIP(hipEventCreate(&h.pev[0]));
+    AMG_HIP(hipEventCreate(&h.pev[1]));
+  }
+  if (!(o.flags & AMG_FLAG_NO_GRAPH)) build_solve_graphs(h);
 }
 
 }  // namespace amg

@@ -1,11 +1,12 @@
 // Generic launch skeletons of the solve phase: a CSR row kernel (L lanes per
 // row, wave64 sub-groups) and an elementwise kernel, both with an optional
-// fused reduction.  Reductions are deterministic: each block reduces in a
-// fixed order, writes one partial per block, and the last block to finish
-// (ticket counter) sums the partials in block order and hands the totals to
-// the operation's finalizer, which writes device scalars and flags.  Every
-// operation carries an `active` flag read at kernel entry, so branches of
-// the K-cycle and the outer iteration are decided on the device.
+// fused reduction.  Reductions are deterministic and free of same-address
+// atomics: each block reduces in a fixed order and writes one partial per
+// block; a one-block finalize kernel then sums the partials in block order
+// and hands the totals to the operation's finalizer, which writes device
+// scalars and flags.  Every operation carries an `active` flag read at
+// kernel entry, so branches of the K-cycle and the outer iteration are
+// decided on the device.
 #pragma once
 #include "amg_internal.hpp"
 #include "device_utils.hpp"
@@ -16,38 +17,33 @@ constexpr int kBlock = 256;
 
 struct RedCtx {
   double* part;       // kMaxPartialBlocks * NV doubles
-  unsigned* ticket;   // one counter, zero between kernels
+  unsigned* ticket;   // unused (kept for the launch signature)
 };
 
-template <int NV, class Op>
-__device__ __forceinline__ void reduce_and_finalize(double (&acc)[NV], Op& op, RedCtx rc) {
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc) {
   __shared__ double red[NV * (kBlock / kWave)];
-  __shared__ int s_last;
   block_sum<NV>(acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) rc.part[k * gridDim.x + blockIdx.x] = acc[k];
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(rc.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
   }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    double v[NV];
+}
+
+template <class Op>
+__global__ void __launch_bounds__(kBlock) k_finalize(Op op, const double* __restrict__ part, int nb) {
+  if (!op.active()) return;
+  constexpr int NV = Op::NV;
+  __shared__ double red[NV * (kBlock / kWave)];
+  double v[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-        s += __hip_atomic_load(&rc.part[k * gridDim.x + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      v[k] = s;
-    }
-    block_sum<NV>(v, red);
-    if (threadIdx.x == 0) {
-      op.finalize(v);
-      __hip_atomic_store(rc.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += part[k * nb + b];
+    v[k] = s;
   }
+  block_sum<NV>(v, red);
+  if (threadIdx.x == 0) op.finalize(v);
 }
 
 // y-side of a sparse row operation: Op provides
@@ -80,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
     sum = group_sum<LPR>(sum);
     if (row < n && lane == 0) op.row(row, sum, acc);
   }
-  if constexpr (Op::NV > 0) reduce_and_finalize<Op::NV>(acc, op, rc);
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
 }
 
 // Elementwise operation over [0, n): Op provides NV, active(), idle(),
@@ -95,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_elem(int n, Op op, RedCtx rc) {
 #pragma unroll
   for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) op.elem(i, acc);
-  if constexpr (Op::NV > 0) reduce_and_finalize<Op::NV>(acc, op, rc);
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
 }
 
 inline int rows_grid(int n, int lpr, bool reduce) {
@@ -126,11 +122,14 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
     case 32: k_rows<T, 32, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
     default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
   }
+  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
 }
 
 template <class Op>
 void launch_elem(int n, const Op& op, RedCtx rc, hipStream_t s) {
-  k_elem<Op><<<elem_grid(n, Op::NV > 0), kBlock, 0, s>>>(n, op, rc);
+  const int g = elem_grid(n, Op::NV > 0);
+  k_elem<Op><<<g, kBlock, 0, s>>>(n, op, rc);
+  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
 }
 
 inline int pick_lpr(int n, int nnz) {

@@ -122,7 +122,7 @@ __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
                            uint64_t* __restrict__ T, int* ctl, int* err) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    ctl[kCtlMisPing] = n;
+    ctl[kCtlMisPing] = n > 0 ? 1 : 0;
     ctl[kCtlMisPing + 1] = 0;
     ctl[kCtlMisRounds] = 0;
   }
@@ -132,55 +132,81 @@ __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
   T[i] = (1ull << 62) | ((uint64_t)(c & ((1 << 30) - 1)) << 32) | (uint64_t)node_hash((uint32_t)i, seed);
 }
 
-// First max sweep of a round: M1_i = max(T_i, max_{j in N_i} T_j).
-// Thread 0 clears the counter the round's second sweep fills, also when the
-// round has nothing left to do, so a finished MIS keeps reading zero.
-__global__ void k_mis_sweep1(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
-                             const uint64_t* __restrict__ T, uint64_t* __restrict__ M1, int* ctl,
-                             int round) {
-  const int undecided = load_acquire(&ctl[kCtlMisPing + (round & 1)]);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
+template <int G>
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    uint64_t o = __shfl_xor(v, off, G);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// First max sweep of a round: M1_i = max(T_i, max_{j in N_i} T_j), G lanes per
+// node.  Thread 0 clears the flag the round's second sweep raises, also when
+// the round has nothing left to do, so a finished MIS keeps reading zero.
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict__ gptr,
+                                                    const int* __restrict__ gcol,
+                                                    const uint64_t* __restrict__ T,
+                                                    uint64_t* __restrict__ M1, int* ctl, int round) {
+  const int undecided = ctl[kCtlMisPing + (round & 1)];   // written by an earlier kernel
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) {
     ctl[kCtlMisPing + ((round + 1) & 1)] = 0;
     if (undecided) ctl[kCtlMisRounds] += 1;
   }
-  if (undecided == 0 || i >= n) return;
-  uint64_t t = T[i];
-  for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
-    uint64_t u = T[gcol[k]];
-    t = u > t ? u : t;
-  }
-  M1[i] = t;
-}
-
-// Second sweep plus the state update: an undecided node whose distance-2 max
-// is its own tuple joins the MIS; one that sees an MIS tuple leaves.
-__global__ void k_mis_sweep2(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
-                             uint64_t* __restrict__ T, const uint64_t* __restrict__ M1, int* ctl,
-                             int round) {
-  if (load_acquire(&ctl[kCtlMisPing + (round & 1)]) == 0) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int undecided = 0;
+  if (undecided == 0) return;
+  const int i = gid / G, lane = gid & (G - 1);
+  uint64_t t = 0;
   if (i < n) {
-    uint64_t t = M1[i];
-    for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
-      uint64_t u = M1[gcol[k]];
+    if (lane == 0) t = T[i];
+    for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
+      uint64_t u = T[gcol[k]];
       t = u > t ? u : t;
     }
-    uint64_t own = T[i];
+  }
+  t = group_max_u64<G>(t);
+  if (i < n && lane == 0) M1[i] = t;
+}
+
+// Second sweep plus the state update (undecided nodes only): a node whose
+// distance-2 max is its own tuple joins the MIS; one that sees an MIS tuple
+// leaves.  Any node left undecided raises the round's flag (set once).
+template <int G>
+__global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict__ gptr,
+                                                    const int* __restrict__ gcol, uint64_t* __restrict__ T,
+                                                    const uint64_t* __restrict__ M1, int* ctl, int round) {
+  if (ctl[kCtlMisPing + (round & 1)] == 0) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / G, lane = gid & (G - 1);
+  uint64_t own = 0, t = 0;
+  if (i < n) {
+    own = T[i];
     if (tstate(own) == 1) {
-      if (t == own) {
-        T[i] = (own & kLow62) | (2ull << 62);
-      } else if (tstate(t) == 2) {
-        T[i] = own & kLow62;
-      } else {
-        undecided = 1;
+      if (lane == 0) t = M1[i];
+      for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
+        uint64_t u = M1[gcol[k]];
+        t = u > t ? u : t;
       }
     }
   }
-  int c = wave_sum_int(undecided);
-  if ((threadIdx.x & (kWave - 1)) == 0 && c)
-    atomicAdd(&ctl[kCtlMisPing + ((round + 1) & 1)], c);
+  t = group_max_u64<G>(t);
+  int undecided = 0;
+  if (i < n && lane == 0 && tstate(own) == 1) {
+    if (t == own) {
+      T[i] = (own & kLow62) | (2ull << 62);
+    } else if (tstate(t) == 2) {
+      T[i] = own & kLow62;
+    } else {
+      undecided = 1;
+    }
+  }
+  if (__ballot(undecided) && (threadIdx.x & (kWave - 1)) == 0) {
+    int* flag = &ctl[kCtlMisPing + ((round + 1) & 1)];
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 __global__ void k_root_flags(int n, const uint64_t* __restrict__ T, int* __restrict__ flags) {
@@ -366,10 +392,24 @@ void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask
 void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s) {
   k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, ctl, err);
 }
+template <int G>
+static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,
+                        hipStream_t s) {
+  const int g = grid_for((long)n * G);
+  k_mis_sweep1<G><<<g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+  k_mis_sweep2<G><<<g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+}
+
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl,
-                      int round, hipStream_t s) {
-  k_mis_sweep1<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
-  k_mis_sweep2<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+                      int round, int lanes, hipStream_t s) {
+  switch (lanes) {
+    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    default: mis_round_g<32>(n, gptr, gcol, T, M1, ctl, round, s); break;
+  }
 }
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s) {
   k_root_flags<<<grid_for(n), kT, 0, s>>>(n, T, flags);

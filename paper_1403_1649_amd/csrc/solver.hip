@@ -500,6 +500,27 @@ template <> const float* cinv<float>(const Hierarchy& h) { return h.cinv32; }
 
 inline RedCtx red(Hierarchy& h) { return RedCtx{h.d_part, h.d_ticket}; }
 
+// The probed kernel: while the outer iteration is being captured, close the
+// current graph segment and keep the launch for the host to issue between
+// segments; otherwise launch it (between HIP events when a probe is set).
+void probe_point(Hierarchy& h, bool selected, std::function<void(hipStream_t)> fn) {
+  if (selected && h.split_at_probe) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    AMG_HIP(hipStreamEndCapture(h.cap_stream, &g));
+    AMG_HIP(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    AMG_HIP(hipGraphDestroy(g));
+    h.g_iter.push_back(e);
+    h.probe_fn = std::move(fn);
+    AMG_HIP(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeRelaxed));
+    return;
+  }
+  const bool timed = selected && h.pev[0] && !h.capturing;
+  if (timed) AMG_HIP(hipEventRecord(h.pev[0], h.stream));
+  fn(h.stream);
+  if (timed) AMG_HIP(hipEventRecord(h.pev[1], h.stream));
+}
+
 template <typename T>
 void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
   const int n = h.levels.back().n;
@@ -527,7 +548,15 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
   const int L = h.L();
   const Act A{act};
 
-  launch_rows<T>(lv.n, lv.lpr, lv.rp, lv.ci, vals<T>(lv), OpPresmoothResid<T>{A, b, wd, xt, r}, rc, s);
+  {
+    const int n = lv.n, lpr = lv.lpr;
+    const int* rp = lv.rp;
+    const int* ci = lv.ci;
+    const T* av = vals<T>(lv);
+    const OpPresmoothResid<T> op{A, b, wd, xt, r};
+    probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_PRESMOOTH,
+                [=](hipStream_t st) { launch_rows<T>(n, lpr, rp, ci, av, op, rc, st); });
+  }
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
   if (!kcyc) {
     launch_elem(lv.nc, OpRestrict<T, false>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr}, rc, s);
@@ -552,7 +581,15 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
                    rc, s);
     launch_elem(lv.n, OpProlongK<T>{A, lv.agg, pv, c, d, xt, K, F}, rc, s);
   }
-  launch_rows<T>(lv.n, lv.lpr, lv.rp, lv.ci, vals<T>(lv), OpResidSmooth<T>{A, b, xt, wd, xo}, rc, s);
+  {
+    const int n = lv.n, lpr = lv.lpr;
+    const int* rp = lv.rp;
+    const int* ci = lv.ci;
+    const T* av = vals<T>(lv);
+    const OpResidSmooth<T> op{A, b, xt, wd, xo};
+    probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH,
+                [=](hipStream_t st) { launch_rows<T>(n, lpr, rp, ci, av, op, rc, st); });
+  }
 }
 
 void set_ctl(Hierarchy& h, int word, int value) {
@@ -576,9 +613,16 @@ void fcg_iteration(Hierarchy& h, const int* run) {
   hipStream_t s = h.stream;
   RedCtx rc = red(h);
   const int n = l0.n;
-  launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val,
-                      OpFcgSpmv{Act{run}, h.p, h.r, h.q, h.d_sc, h.d_ctl, h.d_err}, rc, s);
-  launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.x, h.r, h.d_sc, h.d_ctl, h.d_err}, rc, s);
+  {
+    const int lpr = l0.lpr;
+    const int* rp = l0.rp;
+    const int* ci = l0.ci;
+    const double* av = l0.val;
+    const OpFcgSpmv op{Act{run}, h.p, h.r, h.q, h.d_sc, h.d_ctl, h.d_err};
+    probe_point(h, h.opt.probe == AMG_PROBE_OUTER_SPMV,
+                [=](hipStream_t st) { launch_rows<double>(n, lpr, rp, ci, av, op, rc, st); });
+  }
+  launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.xint, h.r, h.d_sc, h.d_ctl, h.d_err}, rc, s);
   precondition<T>(h, run);
   launch_elem(n, OpDotZQ<T>{Act{run}, static_cast<const T*>(h.z), h.q, h.d_sc}, rc, s);
   launch_elem(n, OpPUpdate<T>{Act{run}, static_cast<const T*>(h.z), h.p, h.d_sc, 0}, rc, s);
@@ -598,38 +642,86 @@ void check_err(Hierarchy& h, int bits) {
   throw Error(AMG_EHIP, "device error bits " + std::to_string(bits));
 }
 
-template <typename T>
+void enqueue_iterations(Hierarchy& h, int count, bool mixed) {
+  const int* run = h.d_ctl + kCtlRunning;
+  for (int i = 0; i < count; ++i) {
+    if (h.g_iter.empty()) {
+      if (mixed) fcg_iteration<float>(h, run);
+      else fcg_iteration<double>(h, run);
+      continue;
+    }
+    AMG_HIP(hipGraphLaunch(h.g_iter[0], h.stream));
+    if (h.g_iter.size() > 1) {
+      AMG_HIP(hipEventRecord(h.pev[0], h.stream));
+      h.probe_fn(h.stream);
+      AMG_HIP(hipEventRecord(h.pev[1], h.stream));
+      AMG_HIP(hipGraphLaunch(h.g_iter[1], h.stream));
+    }
+  }
+}
+
+void enqueue_restart(Hierarchy& h, bool mixed) {
+  const int* run = h.d_ctl + kCtlRunning;
+  if (h.g_restart) AMG_HIP(hipGraphLaunch(h.g_restart, h.stream));
+  else if (mixed) fcg_restart<float>(h, run);
+  else fcg_restart<double>(h, run);
+}
+
+// Outer flexible CG.  Iterations are enqueued in batches between host checks
+// of the device convergence flag; the batch length follows the residual
+// reduction observed so far (iterations after convergence are no-ops).
 int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
   Level& l0 = h.levels[0];
   hipStream_t s = h.stream;
   RedCtx rc = red(h);
   const int n = l0.n;
-  h.x = x;
-  const int* run = h.d_ctl + kCtlRunning;
+  const bool mixed = h.mixed();
   int* hp = static_cast<int*>(h.h_pinned);
   double* hd = reinterpret_cast<double*>(hp + 16);
 
-  launch_elem(n, OpFcgInit{b, h.r, x, h.d_sc, h.d_ctl, h.d_err, rtol}, rc, s);
-  fcg_restart<T>(h, run);
+  launch_elem(n, OpFcgInit{b, h.r, h.xint, h.d_sc, h.d_ctl, h.d_err, rtol}, rc, s);
+  enqueue_restart(h, mixed);
   const int max_iter = h.opt.max_iter;
-  const int every = h.opt.check_every > 0 ? h.opt.check_every : 1;
-  int enqueued = 0;
+  const int cap = h.opt.check_every > 0 ? h.opt.check_every : 1;
+  int enqueued = 0, batch = 1, it_prev = 0;
+  double rel_prev = 1.0;
   int status = AMG_OK;
   while (true) {
-    int batch = every;
     if (enqueued + batch > max_iter) batch = max_iter - enqueued;
-    for (int it = 0; it < batch; ++it) fcg_iteration<T>(h, run);
+    enqueue_iterations(h, batch, mixed);
     enqueued += batch;
     AMG_HIP(hipGetLastError());
     AMG_HIP(hipMemcpyAsync(hp, h.d_ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipMemcpyAsync(hp + 2, h.d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hd, h.d_sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
     check_err(h, hp[2]);
     const int running = hp[kCtlRunning];
     const int done = hp[kCtlIters];
-    if (running && enqueued < max_iter) continue;
+    if (running && h.pev[0]) {
+      // the batch's last iteration ran every kernel: sample the probed one
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h.pev[0], h.pev[1]) == hipSuccess) {
+        h.probe_ms += ms;
+        h.probe_samples += 1;
+      }
+    }
+    if (running && enqueued < max_iter) {
+      const double rel = std::sqrt(hd[kScRR] / hd[kScBB]);
+      batch = 1;
+      if (done > it_prev && rel < rel_prev && rel > 0.0) {
+        const double f = std::pow(rel / rel_prev, 1.0 / (done - it_prev));
+        if (f < 1.0) {
+          const double need = std::ceil(std::log(rtol / rel) / std::log(f));
+          batch = need < 1.0 ? 1 : (need > cap ? cap : (int)need);
+        }
+      }
+      rel_prev = rel;
+      it_prev = done;
+      continue;
+    }
     // recompute the true residual in FP64
-    launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val, OpTrueResid{Act{nullptr}, b, x, h.q, h.d_sc},
+    launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val, OpTrueResid{Act{nullptr}, b, h.xint, h.q, h.d_sc},
                         rc, s);
     AMG_HIP(hipMemcpyAsync(hd, h.d_sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
@@ -647,15 +739,62 @@ int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, doubl
     // restart from the true residual
     launch_elem(n, OpCopy{h.q, h.r}, rc, s);
     set_ctl(h, kCtlRunning, 1);
-    fcg_restart<T>(h, run);
+    enqueue_restart(h, mixed);
+    batch = 1;
   }
+  AMG_HIP(hipMemcpyAsync(x, h.xint, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   return status;
 }
 }  // namespace
 
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
-  if (h.mixed()) return fcg<float>(h, b, rtol, x, iters, relres);
-  return fcg<double>(h, b, rtol, x, iters, relres);
+  return fcg(h, b, rtol, x, iters, relres);
+}
+
+// Capture one outer iteration and the (re)start sequence into HIP graphs on
+// a private stream; the solve replays them on the caller's stream.  Every
+// captured kernel reads its device flag, so one graph serves all branches.
+void build_solve_graphs(Hierarchy& h) {
+  hipStream_t user = h.stream;
+  hipStream_t cs = nullptr;
+  AMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const int* run = h.d_ctl + kCtlRunning;
+  const bool mixed = h.mixed();
+  auto finish = [&](hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    AMG_HIP(hipStreamEndCapture(cs, &g));
+    AMG_HIP(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    AMG_HIP(hipGraphDestroy(g));
+  };
+  try {
+    h.stream = cs;
+    h.cap_stream = cs;
+    h.capturing = true;
+    // outer iteration, split at the probed kernel when a probe is selected
+    h.split_at_probe = h.opt.probe != AMG_PROBE_NONE && h.pev[0];
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (mixed) fcg_iteration<float>(h, run);
+    else fcg_iteration<double>(h, run);
+    hipGraphExec_t last = nullptr;
+    finish(&last);
+    h.g_iter.push_back(last);
+    h.split_at_probe = false;
+    // (re)start sequence
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (mixed) fcg_restart<float>(h, run);
+    else fcg_restart<double>(h, run);
+    finish(&h.g_restart);
+  } catch (...) {
+    h.stream = user;
+    h.capturing = false;
+    h.split_at_probe = false;
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  h.stream = user;
+  h.capturing = false;
+  h.cap_stream = nullptr;
+  AMG_HIP(hipStreamDestroy(cs));
 }
 
 // Arnoldi on D^-1 A_k (modified Gram-Schmidt) from the seeded start vector;

@@ -204,3 +204,55 @@ def test_repeated_setup_is_deterministic():
         outs.append((x.cpu().numpy(), it, rel, h.export_level(1, what=("A",))["val"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][3], outs[1][3])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager_launches(precision):
+    """The captured outer iteration replayed many times (several solves with
+    different right-hand sides, eager work and syncs in between) gives the
+    same bits as launching every kernel from the host."""
+    A = P.hetero3d(18, seed=9)
+    hg, _ = _setup(A, 3, precision=precision)
+    he, _ = _setup(A, 3, precision=precision, flags=1)
+    for seed in (1, 2, 3):
+        b = dev_vec(P.rhs(A, P.exact_solution(A.n, seed)))
+        xg, itg, relg = amg.solve(hg, b, 1e-8)
+        torch.cuda.synchronize()
+        xe, ite, rele = amg.solve(he, b, 1e-8)
+        assert itg == ite and relg == rele
+        assert torch.equal(xg, xe)
+
+
+@pytest.mark.parametrize("n,nonsym", [(1, False), (37, False), (143, False), (250, True), (600, False)])
+def test_coarse_inverse_is_exact_solve(n, nonsym):
+    """Single-level hierarchies: the preconditioner is the dense inverse, so one
+    FCG step solves the system (covers one- and many-block eliminations)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(n)
+    if n == 1:
+        S = sp.csr_matrix(np.array([[3.0]]))
+    else:
+        A0 = P.hetero3d(int(round(n ** (1 / 3))) + 1, seed=n).to_scipy()[:n, :n].tocsr()
+        S = A0 + sp.identity(n) * 1e-3
+        if nonsym:
+            S = S + sp.triu(S, 1) * 0.3
+    S = S.tocsr()
+    S.sort_indices()
+    A = P.CSR(S.indptr, S.indices, S.data)
+    h, _ = _setup(A, 3, coarse_max=600)
+    assert h.num_levels() == 1
+    b = rng.standard_normal(A.n)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    xs = np.linalg.solve(S.toarray(), b)
+    assert it <= 2 and rel <= 1e-10
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("probe", ["l0_presmooth", "l0_postsmooth", "outer_spmv"])
+def test_probe_timing_samples_in_solve(probe):
+    A = P.poisson3d(40)
+    h, _ = _setup(A, 3, probe=probe)
+    b = dev_vec(P.rhs(A, P.exact_solution(A.n, 1)))
+    _, it, rel = amg.solve(h, b, 1e-8)
+    ms, n = h.probe_timing()
+    assert rel <= 1e-8 and n >= 1 and 0.0 < ms < 50.0
