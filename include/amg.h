@@ -79,6 +79,9 @@ typedef struct {
 /* amg_options.flags: launch every kernel from the host instead of replaying
  * the captured HIP graph of an outer iteration (for debugging and timing). */
 #define AMG_FLAG_NO_GRAPH 1u
+/* amg_options.flags: skip the per-level kernel autotuner (CSR kernels with
+ * lanes per row from the average row length). */
+#define AMG_FLAG_NO_TUNE 2u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {
@@ -124,6 +127,16 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
 int32_t amg_solve(amg_hierarchy* h, const double* b, double rtol, double* x,
                   int32_t* iters, double* relres, hipStream_t s);
 
+/* The same solve for nrhs right-hand sides at once, each column as if solved
+ * alone: B, X: device float64 row-major [n][nrhs] (1 <= nrhs <= 64); the
+ * cycle is applied to the whole block (A streamed once for all columns) with
+ * per-column K-cycle scalars and branches and a per-column outer iteration
+ * that stops updating a column once it has converged.
+ * iters, relres: (host) arrays of nrhs.  Errors as amg_solve (ENOTCONV when
+ * any column did not converge).  Synchronises s. */
+int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double rtol, double* X,
+                        int32_t* iters, double* relres, hipStream_t s);
+
 /* Release the hierarchy and its device memory (NULL is ignored). */
 void amg_destroy(amg_hierarchy* h);
 
@@ -149,9 +162,11 @@ int32_t amg_export_level(const amg_hierarchy* h, int32_t k, int32_t* row_ptr, in
                          double* pval, double* B);
 
 /* y = A x (the sparse mat-vec of Section 3, "axpy" there), float64, with the
- * same kernel family the solve uses on level 0.  lanes_per_row in
- * {0,1,2,4,8,16,32,64}; 0 picks from the average row length.
- * Enqueue only. */
+ * kernel families the solve uses: lanes_per_row in {1,2,4,8,16,32,64} selects
+ * the CSR kernel with that many lanes per row, 0 picks the lane count from the
+ * average row length, -1 selects the sliced-ELL kernel (the matrix is
+ * converted into a temporary copy first; synchronises s).  Otherwise enqueue
+ * only. */
 int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s);
 
 /* Node hash of the MIS(2) priorities (the random r_i of Algorithm 2 made

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     node_hash,
     setup,
     solve,
+    solve_multi,
     spmv,
     status_string,
 )

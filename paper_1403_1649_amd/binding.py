@@ -19,6 +19,7 @@ EXPORTED = [
     "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",
     "amg_destroy", "amg_num_levels", "amg_level_info", "amg_export_level", "amg_spmv",
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
+    "amg_solve_multi",
 ]
 
 
@@ -91,6 +92,8 @@ def lib():
     L.amg_hessenberg_radius.restype = i32
     L.amg_timings.argtypes = [vp, P(dbl), P(dbl)]
     L.amg_timings.restype = i32
+    L.amg_solve_multi.argtypes = [vp, i32, vp, dbl, vp, vp, vp, vp]
+    L.amg_solve_multi.restype = i32
     L.amg_probe_timing.argtypes = [vp, P(dbl), P(i32)]
     L.amg_probe_timing.restype = i32
     _LIB = L
@@ -237,6 +240,22 @@ def solve(h: Hierarchy, b, rtol: float = 1e-8, x=None, allow_notconv: bool = Fal
     code = lib().amg_solve(h.handle, _ptr(b), float(rtol), _ptr(x), C.byref(it), C.byref(rel), _stream())
     _check(code, (AMG_OK, AMG_ENOTCONV) if allow_notconv else (AMG_OK,))
     return x, it.value, rel.value
+
+
+def solve_multi(h: Hierarchy, B, rtol: float = 1e-8, X=None, allow_notconv: bool = False):
+    """amg_solve_multi on a row-major [n][nrhs] CUDA float64 block: (X, iters[], relres[])."""
+    import torch
+    if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous() and B.dim() == 2
+            and B.shape[0] == h.n):
+        raise TypeError("B must be a contiguous CUDA float64 tensor of shape [n, nrhs]")
+    R = int(B.shape[1])
+    if X is None:
+        X = torch.empty_like(B)
+    it = np.zeros(R, np.int32)
+    rel = np.zeros(R, np.float64)
+    code = lib().amg_solve_multi(h.handle, R, _ptr(B), float(rtol), _ptr(X), _nptr(it), _nptr(rel), _stream())
+    _check(code, (AMG_OK, AMG_ENOTCONV) if allow_notconv else (AMG_OK,))
+    return X, it, rel
 
 
 def spmv(row_ptr, col, val, x, y=None, lanes_per_row: int = 0):

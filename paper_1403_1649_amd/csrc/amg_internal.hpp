@@ -72,7 +72,16 @@ struct Level {
   float* val32 = nullptr;
   double* diag = nullptr;      // a_ii
   double* B = nullptr;         // near null space vector B_k
-  int lpr = 8;                 // lanes per row of the level's SpMV kernels
+  int lpr = 8;                 // lanes per row picked from the average row length
+  // sliced ELL copy for the solve (slices of 64 rows, column-major per slice)
+  int nslices = 0;
+  int* sl_ptr = nullptr;       // element offset of each slice (nslices + 1)
+  int* sl_col = nullptr;
+  double* sl_val = nullptr;
+  float* sl_val32 = nullptr;
+  // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
+  // per row, fmt 1 = sliced ELL
+  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; } t64, t32;
   // setup products (absent on the coarsest level)
   uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
   uint64_t* tuple = nullptr;   // final MIS(2) tuples (state in the top two bits)
@@ -194,6 +203,9 @@ void launch_to_float(size_t n, const double* in, float* out, hipStream_t s);
 void launch_state_from_tuple(int n, const uint64_t* T, int8_t* state, hipStream_t s);
 void launch_fill_int(size_t n, int* p, int v, hipStream_t s);
 void launch_fill_double(size_t n, double* p, double v, hipStream_t s);
+void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s);
+void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
+                      int* sl_col, double* sl_val, float* sl_val32, hipStream_t s);
 
 // galerkin.hip
 void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
@@ -214,6 +226,10 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 // cycle and outer solvers (solver.hip)
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
 void build_solve_graphs(Hierarchy& h);
+void autotune_levels(Hierarchy& h);
+int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres);
+void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y);
+void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
               int lpr, hipStream_t s);
 int pick_lanes_per_row(int n, int nnz);

@@ -149,6 +149,26 @@ int32_t amg_solve(amg_hierarchy* H, const double* b, double rtol, double* x, int
   return AMG_OK;
 }
 
+int32_t amg_solve_multi(amg_hierarchy* H, int32_t nrhs, const double* B, double rtol, double* X, int32_t* iters,
+                        double* relres, hipStream_t s) {
+  if (!H || !B || !X || !iters || !relres) return fail(AMG_EINVAL, "amg_solve_multi: NULL argument");
+  if (nrhs < 1 || nrhs > 64) return fail(AMG_EINVAL, "amg_solve_multi: nrhs must be in [1, 64]");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(AMG_EINVAL, "amg_solve_multi: rtol must be positive");
+  int32_t status = AMG_OK;
+  int32_t st = guarded("amg_solve_multi", [&] {
+    amg::Hierarchy& h = H->h;
+    h.stream = s;
+    AMG_HIP(hipEventRecord(h.ev[2], s));
+    status = amg::solve_multi_impl(h, nrhs, B, rtol, X, iters, relres);
+    AMG_HIP(hipEventRecord(h.ev[3], s));
+    AMG_HIP(hipEventSynchronize(h.ev[3]));
+    AMG_HIP(hipEventElapsedTime(&h.solve_ms, h.ev[2], h.ev[3]));
+  });
+  if (st != AMG_OK) return st;
+  if (status != AMG_OK) return fail(status, "amg_solve_multi: a column reached the iteration limit");
+  return AMG_OK;
+}
+
 void amg_destroy(amg_hierarchy* H) { delete H; }
 
 int32_t amg_num_levels(const amg_hierarchy* H) { return H ? (int32_t)H->h.levels.size() : 0; }
@@ -196,8 +216,17 @@ int32_t amg_export_level(const amg_hierarchy* H, int32_t k, int32_t* row_ptr, in
 
 int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s) {
   if (!csr_args_ok(A) || !x || !y) return fail(AMG_EINVAL, "amg_spmv: bad argument");
+  if (lanes_per_row == -1) {
+    return guarded("amg_spmv", [&] {
+      amg::Hierarchy h;
+      h.stream = s;
+      amg::init_control(h);
+      h.d_scan = h.arena.alloc_n<int>(amg::scan_blocks_needed(A->n) + 2);
+      amg::spmv_sell_f64(h, *A, x, y);
+    });
+  }
   if (lanes_per_row < 0 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1)))
-    return fail(AMG_EINVAL, "amg_spmv: lanes_per_row must be 0 or a power of two <= 64");
+    return fail(AMG_EINVAL, "amg_spmv: lanes_per_row must be -1, 0 or a power of two <= 64");
   return guarded("amg_spmv", [&] {
     amg::spmv_f64(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, x, y, lanes_per_row, s);
     AMG_HIP(hipGetLastError());

@@ -226,6 +226,43 @@ void alloc_solve_vectors(Hierarchy& h) {
   if (h.mixed()) h.bz = h.arena.alloc(n0 * es);
 }
 
+// Sliced-ELL copy of A_k for the solve kernels.
+void build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
+  Sync sy{h};
+  const int nsl = (lv.n + 63) / 64;
+  int* widths = tmp.alloc_n<int>(nsl);
+  launch_sell_widths(lv.n, lv.rp, widths, h.stream);
+  lv.nslices = nsl;
+  lv.sl_ptr = h.arena.alloc_n<int>(nsl + 1);
+  scan_to_ptr(widths, lv.sl_ptr, nsl, h.d_scan, h.stream);
+  sy.fetch(lv.sl_ptr + nsl, 0);
+  sy.wait_and_check();
+  const size_t total = (size_t)sy.hp()[0];
+  lv.sl_col = h.arena.alloc_n<int>(total);
+  lv.sl_val = h.arena.alloc_n<double>(total);
+  if (h.mixed()) lv.sl_val32 = h.arena.alloc_n<float>(total);
+  launch_sell_fill(lv.n, nsl, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_val, lv.sl_val32, h.stream);
+}
+
+}  // namespace
+
+void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y) {
+  Arena tmp;
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{h.stream};
+  Level lv;
+  lv.n = A.n;
+  lv.nnz = A.nnz;
+  lv.rp = const_cast<int*>(A.row_ptr);
+  lv.ci = const_cast<int*>(A.col_idx);
+  lv.val = const_cast<double*>(A.val);
+  build_sell(h, tmp, lv);
+  spmv_sell_level(h, lv, x, y);
+  Sync sy{h};
+  sy.wait_and_check();
+}
+
+namespace {
+
 void make_float_copies(Hierarchy& h) {
   for (int k = 0; k < (int)h.levels.size(); ++k) {
     Level& lv = h.levels[k];
@@ -352,6 +389,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     Level& lv = h.levels[k];
     lv.diag = h.arena.alloc_n<double>(lv.n);
     lv.lpr = pick_lanes_per_row(lv.n, lv.nnz);
+    lv.t64.lpr = lv.t32.lpr = lv.lpr;
     if (lv.n <= o.coarse_max || k + 1 >= o.max_levels) break;
     const int n = lv.n, nnz = lv.nnz;
 
@@ -460,7 +498,9 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
+  for (int k = 0; k < h.L(); ++k) build_sell(h, tmp, h.levels[k]);
   sy.wait_and_check();
+  if (!(o.flags & AMG_FLAG_NO_TUNE)) autotune_levels(h);
   if (o.probe != AMG_PROBE_NONE) {
     AMG_HIP(hipEventCreate(&h.pev[0]));
     AMG_HIP(hipEventCreate(&h.pev[1]));

@@ -53,6 +53,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Op op, const double* __rest
 //   T x(int j) const;                  the gathered operand
 //   void row(int i, T ax, double* acc) the epilogue of row i
 //   void finalize(const double* v)     totals of the reductions
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// The logical block index gives every XCD a contiguous run of blocks, and
+// each logical block a contiguous chunk of the work, so the neighbouring rows
+// whose x entries overlap share one L2.
+__device__ __forceinline__ int xcd_logical_block() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if (g < 8 || (g & 7)) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
 template <typename T, int LPR, class Op>
 __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ rp,
                                                  const int* __restrict__ ci,
@@ -66,8 +76,12 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
   double acc[Op::NV > 0 ? Op::NV : 1];
 #pragma unroll
   for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
-  for (int row0 = blockIdx.x * RPB; row0 < n; row0 += gridDim.x * RPB) {
-    const int row = row0 + threadIdx.x / LPR;
+  const int groups = (n + RPB - 1) / RPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = xcd_logical_block() * per;
+  const int g1 = min(groups, g0 + per);
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RPB + threadIdx.x / LPR;
     T sum = T(0);
     if (row < n) {
       const int s = rp[row], e = rp[row + 1];
@@ -75,6 +89,43 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
     }
     sum = group_sum<LPR>(sum);
     if (row < n && lane == 0) op.row(row, sum, acc);
+  }
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
+}
+
+// Sliced ELL with slices of 64 rows (one wave): slice s holds its rows
+// column-major, element (row s*64 + l, k) at sl_ptr[s] + 64 k + l, padded
+// with zero values that point at the row itself.  One thread per row, so
+// every value and column load of a wave is one contiguous 512 / 256 bytes.
+template <typename T, class Op>
+__global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* __restrict__ sl_ptr,
+                                                 const int* __restrict__ sl_col, const T* __restrict__ sl_val,
+                                                 Op op, RedCtx rc) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  double acc[Op::NV > 0 ? Op::NV : 1];
+#pragma unroll
+  for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
+  constexpr int SPB = kBlock / kWave;   // slices per block step
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int steps = (nslices + SPB - 1) / SPB;
+  const int per = (steps + gridDim.x - 1) / gridDim.x;
+  const int t0 = xcd_logical_block() * per;
+  const int t1 = min(steps, t0 + per);
+  for (int t = t0; t < t1; ++t) {
+    const int sl = t * SPB + wv;
+    if (sl >= nslices) break;
+    const int row = sl * kWave + lane;
+    const int base = sl_ptr[sl];
+    const int w = (sl_ptr[sl + 1] - base) / kWave;
+    T sum = T(0);
+    const int* cp = sl_col + base + lane;
+    const T* vp = sl_val + base + lane;
+    for (int k = 0; k < w; ++k) sum += vp[k * kWave] * op.x(cp[k * kWave]);
+    if (row < n) op.row(row, sum, acc);
   }
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
 }
@@ -94,12 +145,18 @@ __global__ void __launch_bounds__(kBlock) k_elem(int n, Op op, RedCtx rc) {
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
 }
 
+// Grid of the row kernels: one block per 256-row (or RPB-row) group up to a
+// cap of 2048 resident blocks (8 per CU); a multiple of 8 above 8 blocks so
+// that the XCD-aware mapping is a bijection.
 inline int rows_grid(int n, int lpr, bool reduce) {
+  (void)reduce;
   long rpb = kBlock / lpr;
   long g = (n + rpb - 1) / rpb;
-  long cap = reduce ? kMaxPartialBlocks : 65536;
+  const long cap = kMaxPartialBlocks;
   if (g < 1) g = 1;
-  return (int)(g < cap ? g : cap);
+  if (g > cap) g = cap;
+  if (g > 8) g &= ~7L;
+  return (int)g;
 }
 
 inline int elem_grid(int n, bool reduce) {
@@ -123,6 +180,17 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
     default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
   }
   if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
+}
+
+template <typename T, class Op>
+void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const T* sl_val, const Op& op,
+                 RedCtx rc, hipStream_t s) {
+  long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
+  if (g < 1) g = 1;
+  if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
+  if (g > 8) g &= ~7L;
+  k_sell<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, rc);
+  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, (int)g);
 }
 
 template <class Op>

@@ -354,6 +354,42 @@ __global__ void k_state_from_tuple(int n, const uint64_t* __restrict__ T, int8_t
   if (i < n) st[i] = (int8_t)(tstate(T[i]) - 1);
 }
 
+// Sliced ELL: slice width = longest row of its 64 rows (one wave per slice).
+__global__ void k_sell_widths(int n, const int* __restrict__ rp, int* __restrict__ widths) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  int len = row < n ? rp[row + 1] - rp[row] : 0;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const int o = __shfl_xor(len, off, kWave);
+    len = o > len ? o : len;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) widths[row / kWave] = len * kWave;
+}
+
+// Fill the slices: entry k of row s*64+l at sl_ptr[s] + 64 k + l; padding
+// (short rows and the rows past n in the last slice) has value 0 and a valid
+// column (the row itself, or 0).
+__global__ void k_sell_fill(int n, int nslices, const int* __restrict__ rp, const int* __restrict__ ci,
+                            const double* __restrict__ val, const int* __restrict__ sl_ptr,
+                            int* __restrict__ sl_col, double* __restrict__ sl_val, float* __restrict__ sl_val32) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = row / kWave, l = row & (kWave - 1);
+  if (sl >= nslices) return;
+  const int base = sl_ptr[sl];
+  const int w = (sl_ptr[sl + 1] - base) / kWave;
+  const int s0 = row < n ? rp[row] : 0;
+  const int len = row < n ? rp[row + 1] - s0 : 0;
+  for (int k = 0; k < w; ++k) {
+    const int idx = base + k * kWave + l;
+    int c = row < n ? row : 0;
+    double v = 0.0;
+    if (k < len) { c = ci[s0 + k]; v = val[s0 + k]; }
+    sl_col[idx] = c;
+    sl_val[idx] = v;
+    if (sl_val32) sl_val32[idx] = (float)v;
+  }
+}
+
 __global__ void k_fill_double(size_t n, double* p, double v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -454,6 +490,15 @@ void launch_fill_int(size_t n, int* p, int v, hipStream_t s) {
   k_fill_int<<<(int)(g < 8192 ? g : 8192), kT, 0, s>>>(n, p, v);
 }
 
+void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s) {
+  const int nsl = (n + kWave - 1) / kWave;
+  k_sell_widths<<<(nsl * kWave + kT - 1) / kT, kT, 0, s>>>(n, rp, widths);
+}
+void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
+                      int* sl_col, double* sl_val, float* sl_val32, hipStream_t s) {
+  k_sell_fill<<<(nslices * kWave + kT - 1) / kT, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, sl_col, sl_val,
+                                                             sl_val32);
+}
 void launch_fill_double(size_t n, double* p, double v, hipStream_t s) {
   if (n == 0) return;
   long g = (long)((n + kT - 1) / kT);

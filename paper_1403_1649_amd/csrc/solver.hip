@@ -7,6 +7,11 @@
 // the convergence test are device flags read by every kernel of the guarded
 // region, so a whole outer iteration is enqueued without host round-trips.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "kernels_common.hpp"
 
@@ -500,6 +505,21 @@ template <> const float* cinv<float>(const Hierarchy& h) { return h.cinv32; }
 
 inline RedCtx red(Hierarchy& h) { return RedCtx{h.d_part, h.d_ticket}; }
 
+template <typename T> const Level::Tune& tune_of(const Level& l);
+template <> const Level::Tune& tune_of<double>(const Level& l) { return l.t64; }
+template <> const Level::Tune& tune_of<float>(const Level& l) { return l.t32; }
+template <typename T> const T* sell_vals(const Level& l);
+template <> const double* sell_vals<double>(const Level& l) { return l.sl_val; }
+template <> const float* sell_vals<float>(const Level& l) { return l.sl_val32; }
+
+// A row operation on A_k with the level's tuned kernel (CSR or sliced ELL).
+template <typename T, class Op>
+void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
+  const Level::Tune& t = tune_of<T>(lv);
+  if (t.fmt == 1 && lv.sl_ptr) launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s);
+  else launch_rows<T>(lv.n, t.lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s);
+}
+
 // The probed kernel: while the outer iteration is being captured, close the
 // current graph segment and keep the launch for the host to issue between
 // segments; otherwise launch it (between HIP events when a probe is set).
@@ -549,13 +569,10 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
   const Act A{act};
 
   {
-    const int n = lv.n, lpr = lv.lpr;
-    const int* rp = lv.rp;
-    const int* ci = lv.ci;
-    const T* av = vals<T>(lv);
+    const Level* lp = &lv;
     const OpPresmoothResid<T> op{A, b, wd, xt, r};
     probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_PRESMOOTH,
-                [=](hipStream_t st) { launch_rows<T>(n, lpr, rp, ci, av, op, rc, st); });
+                [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
   }
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
   if (!kcyc) {
@@ -574,21 +591,17 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
     launch_elem(lv.nc, OpRestrict<T, true>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K}, rc, s);
     cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
-    launch_rows<T>(lc.n, lc.lpr, lc.rp, lc.ci, vals<T>(lc), OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
+    launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
     cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
-    launch_rows<T>(lc.n, lc.lpr, lc.rp, lc.ci, vals<T>(lc), OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm},
-                   rc, s);
+    launch_level<T>(lc, OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm}, rc, s);
     launch_elem(lv.n, OpProlongK<T>{A, lv.agg, pv, c, d, xt, K, F}, rc, s);
   }
   {
-    const int n = lv.n, lpr = lv.lpr;
-    const int* rp = lv.rp;
-    const int* ci = lv.ci;
-    const T* av = vals<T>(lv);
+    const Level* lp = &lv;
     const OpResidSmooth<T> op{A, b, xt, wd, xo};
     probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH,
-                [=](hipStream_t st) { launch_rows<T>(n, lpr, rp, ci, av, op, rc, st); });
+                [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
   }
 }
 
@@ -614,13 +627,10 @@ void fcg_iteration(Hierarchy& h, const int* run) {
   RedCtx rc = red(h);
   const int n = l0.n;
   {
-    const int lpr = l0.lpr;
-    const int* rp = l0.rp;
-    const int* ci = l0.ci;
-    const double* av = l0.val;
+    const Level* lp = &l0;
     const OpFcgSpmv op{Act{run}, h.p, h.r, h.q, h.d_sc, h.d_ctl, h.d_err};
     probe_point(h, h.opt.probe == AMG_PROBE_OUTER_SPMV,
-                [=](hipStream_t st) { launch_rows<double>(n, lpr, rp, ci, av, op, rc, st); });
+                [=](hipStream_t st) { launch_level<double>(*lp, op, rc, st); });
   }
   launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.xint, h.r, h.d_sc, h.d_ctl, h.d_err}, rc, s);
   precondition<T>(h, run);
@@ -721,8 +731,7 @@ int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, doubl
       continue;
     }
     // recompute the true residual in FP64
-    launch_rows<double>(n, l0.lpr, l0.rp, l0.ci, l0.val, OpTrueResid{Act{nullptr}, b, h.xint, h.q, h.d_sc},
-                        rc, s);
+    launch_level<double>(l0, OpTrueResid{Act{nullptr}, b, h.xint, h.q, h.d_sc}, rc, s);
     AMG_HIP(hipMemcpyAsync(hd, h.d_sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));
     const double bb = hd[kScBB];
@@ -745,7 +754,115 @@ int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, doubl
   AMG_HIP(hipMemcpyAsync(x, h.xint, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   return status;
 }
+// ------------------------------------------------------------ autotuner
+struct TuneKey {
+  int n, nnz, bytes;
+  bool operator<(const TuneKey& o) const {
+    return n != o.n ? n < o.n : (nnz != o.nnz ? nnz < o.nnz : bytes < o.bytes);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Level::Tune>& tune_cache() {
+  static std::map<TuneKey, Level::Tune> c;
+  static bool loaded = false;
+  if (!loaded) {
+    loaded = true;
+    if (const char* path = std::getenv("AMG_TUNE_CACHE")) {
+      if (FILE* f = std::fopen(path, "r")) {
+        TuneKey k{};
+        Level::Tune t{};
+        while (std::fscanf(f, " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"us\": %f}",
+                           &k.n, &k.nnz, &k.bytes, &t.fmt, &t.lpr, &t.us) == 6)
+          c[k] = t;
+        std::fclose(f);
+      }
+    }
+  }
+  return c;
+}
+
+void save_tune(const TuneKey& k, const Level::Tune& t) {
+  if (const char* path = std::getenv("AMG_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"us\": %.3f}\n", k.n,
+                   k.nnz, k.bytes, t.fmt, t.lpr, t.us);
+      std::fclose(f);
+    }
+  }
+}
+
+template <typename T>
+struct OpFillT {
+  static constexpr int NV = 0;
+  T* p;
+  T v;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { p[i] = v; }
+  __device__ void finalize(const double*) const {}
+};
+
+// Time y = A x for CSR with 2..32 lanes per row and for sliced ELL; keep the
+// fastest.  Results are cached per (n, nnz, value size) for the process and,
+// when AMG_TUNE_CACHE names a file, across processes (one JSON object per line).
+template <typename T>
+Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
+  TuneKey key{lv.n, lv.nnz, (int)sizeof(T)};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto& c = tune_cache();
+    auto it = c.find(key);
+    if (it != c.end()) return it->second;
+  }
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  launch_elem(lv.n, OpFillT<T>{x, T(1)}, rc, s);
+  Level::Tune best;
+  best.us = 1e30f;
+  hipEvent_t e0 = h.ev[2], e1 = h.ev[3];
+  const int reps = 4;
+  auto time_it = [&](auto&& launch) {
+    launch();
+    AMG_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch();
+    AMG_HIP(hipEventRecord(e1, s));
+    AMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms * 1000.f / reps;
+  };
+  const OpSpmv<T> op{Act{nullptr}, x, y};
+  for (int lpr = 2; lpr <= 32; lpr <<= 1) {
+    const float us = time_it([&] { launch_rows<T>(lv.n, lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s); });
+    if (us < best.us) { best.us = us; best.fmt = 0; best.lpr = lpr; }
+  }
+  if (lv.sl_ptr && sell_vals<T>(lv)) {
+    const float us = time_it([&] { launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s); });
+    if (us < best.us) { best.us = us; best.fmt = 1; best.lpr = lv.lpr; }
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_cache()[key] = best;
+  save_tune(key, best);
+  return best;
+}
+
 }  // namespace
+
+void autotune_levels(Hierarchy& h) {
+  const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  for (int k = 0; k < h.L(); ++k) {
+    Level& lv = h.levels[k];
+    if (h.mixed()) {
+      lv.t32 = tune_one<float>(h, lv, static_cast<float*>(lv.xt), static_cast<float*>(lv.r));
+      if (k == 0) lv.t64 = tune_one<double>(h, lv, h.p, h.q);
+    } else {
+      lv.t64 = tune_one<double>(h, lv, static_cast<double*>(lv.xt), static_cast<double*>(lv.r));
+    }
+    if (debug)
+      std::fprintf(stderr, "amg: tune level %d n=%d fp64 fmt=%d lpr=%d %.2f us | fp32 fmt=%d lpr=%d %.2f us\n", k,
+                   lv.n, lv.t64.fmt, lv.t64.lpr, lv.t64.us, lv.t32.fmt, lv.t32.lpr, lv.t32.us);
+  }
+}
 
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
   return fcg(h, b, rtol, x, iters, relres);
@@ -826,6 +943,11 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 }
 
 int pick_lanes_per_row(int n, int nnz) { return pick_lpr(n, nnz); }
+
+void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y) {
+  launch_sell<double>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, OpSpmv<double>{Act{nullptr}, x, y},
+                      red(h), h.stream);
+}
 
 // y = A x for a caller's matrix (float64)
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,

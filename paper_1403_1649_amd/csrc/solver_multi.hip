@@ -1,0 +1,864 @@
+// Several right-hand sides with one hierarchy: the cycle of Algorithms 4/5 and
+// the outer flexible CG applied to a row-major block X[n][R] (R <= 64).
+// Each matrix row is handled by W = pow2(R) lanes, lane c owning column c:
+// the row's values and columns are loaded once (a broadcast within the lane
+// group) and the gathered X rows are contiguous, so A is streamed once for
+// all R columns.  Every scalar of the K-cycle and of the outer iteration is
+// per column, and so is the K-cycle branch: the second inner step runs when
+// any column needs it, and only the columns that need it use its result, so
+// each column follows exactly the arithmetic of a single-column solve.
+// Converged columns stop updating; kernels stop when no column is running.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "kernels_common.hpp"
+
+namespace amg {
+
+namespace {
+
+constexpr int kMaxRhs = 64;
+constexpr int kMultiBlocks = 512;
+
+// per-column scalar slots: slot s of column c at sc[s * R + c]
+enum : int {
+  mBB = 0, mRtol2, mAlpha, mBeta, mPQ, mRR, mTrue, mK0,   // K-level k: mK0 + 16 k + KSlot
+  mSlots = mK0 + 16 * 24,
+};
+// per-column int flags: word w of column c at fl[w * R + c]
+enum : int {
+  fRun = 0, fIters, fK0,   // K-level k: fK0 + 2 k (+0 step-2, +1 use-d)
+  fWords = fK0 + 2 * 24,
+};
+// single words (any column): any running, any step 2 on level k
+enum : int { aRun = 0, aK0 = 1, aWords = 1 + 24 };
+
+struct MCtx {
+  int R;
+  double* sc;
+  int* fl;
+  int* any;
+  double* part;
+  int* err;
+};
+
+struct ActAny {
+  const int* p;
+  __device__ __forceinline__ bool on() const { return p == nullptr || *p != 0; }
+};
+
+template <int NV, int W>
+__device__ __forceinline__ void write_partials_m(double (&acc)[NV], int R, double* part) {
+  __shared__ double red[NV][kBlock / kWave][W];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = W; off < kWave; off <<= 1) acc[k] += __shfl_xor(acc[k], off, kWave);
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  if (lane < W) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid][lane] = acc[k];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < W && c < R) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < kBlock / kWave; ++w) s += red[k][w][c];
+      part[((size_t)k * R + c) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// per-column totals (fixed block order), then the op's per-column and
+// all-column finalizers
+template <class Op>
+__global__ void __launch_bounds__(kWave) k_finalize_m(Op op, const double* __restrict__ part, int nb, int R) {
+  if (!op.active()) return;
+  constexpr int NV = Op::NV;
+  const int c = threadIdx.x;
+  if (c < R) {
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      const double* p = part + ((size_t)k * R + c) * nb;
+      for (int b = 0; b < nb; ++b) s += p[b];
+      v[k] = s;
+    }
+    op.finalize(c, v);
+  }
+  __syncthreads();
+  if (c == 0) op.finalize_all();
+}
+
+__device__ __forceinline__ int xcd_block() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if (g < 8 || (g & 7)) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// rows of A times the block, W lanes per row
+template <typename T, int W, class Op>
+__global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ av,
+                                                   Op op, double* part) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  constexpr int NV = Op::NV > 0 ? Op::NV : 1;
+  constexpr int RPB = kBlock / W;
+  const int c = threadIdx.x & (W - 1);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const int groups = (n + RPB - 1) / RPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = xcd_block() * per, g1 = min(groups, g0 + per);
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RPB + threadIdx.x / W;
+    if (row < n && c < R) {
+      T sum = T(0);
+      for (int k = rp[row]; k < rp[row + 1]; ++k) sum += av[k] * op.x(ci[k], c);
+      op.row(row, c, sum, acc);
+    }
+  }
+  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, part);
+}
+
+template <int W, class Op>
+__global__ void __launch_bounds__(kBlock) k_elem_m(int n, int R, Op op, double* part) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  constexpr int NV = Op::NV > 0 ? Op::NV : 1;
+  constexpr int RPB = kBlock / W;
+  const int c = threadIdx.x & (W - 1);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  const int groups = (n + RPB - 1) / RPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = xcd_block() * per, g1 = min(groups, g0 + per);
+  for (int g = g0; g < g1; ++g) {
+    const int i = g * RPB + threadIdx.x / W;
+    if (i < n && c < R) op.elem(i, c, acc);
+  }
+  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, part);
+}
+
+inline int grid_m(int n, int W, bool reduce) {
+  long rpb = kBlock / W;
+  long g = (n + rpb - 1) / rpb;
+  const long cap = reduce ? kMultiBlocks : kMaxPartialBlocks;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  if (g > 8) g &= ~7L;
+  return (int)g;
+}
+
+template <typename T, int W, class Op>
+void rows_m_w(int n, const MCtx& m, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
+  const int g = grid_m(n, W, Op::NV > 0);
+  k_rows_m<T, W, Op><<<g, kBlock, 0, s>>>(n, m.R, rp, ci, av, op, m.part);
+  if constexpr (Op::NV > 0) k_finalize_m<Op><<<1, kWave, 0, s>>>(op, m.part, g, m.R);
+}
+
+template <int W, class Op>
+void elem_m_w(int n, const MCtx& m, const Op& op, hipStream_t s) {
+  const int g = grid_m(n, W, Op::NV > 0);
+  k_elem_m<W, Op><<<g, kBlock, 0, s>>>(n, m.R, op, m.part);
+  if constexpr (Op::NV > 0) k_finalize_m<Op><<<1, kWave, 0, s>>>(op, m.part, g, m.R);
+}
+
+inline int width_of(int R) {
+  int w = 1;
+  while (w < R) w <<= 1;
+  return w;
+}
+
+template <typename T, class Op>
+void rows_m(int n, const MCtx& m, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
+  switch (width_of(m.R)) {
+    case 1: rows_m_w<T, 1>(n, m, rp, ci, av, op, s); break;
+    case 2: rows_m_w<T, 2>(n, m, rp, ci, av, op, s); break;
+    case 4: rows_m_w<T, 4>(n, m, rp, ci, av, op, s); break;
+    case 8: rows_m_w<T, 8>(n, m, rp, ci, av, op, s); break;
+    case 16: rows_m_w<T, 16>(n, m, rp, ci, av, op, s); break;
+    case 32: rows_m_w<T, 32>(n, m, rp, ci, av, op, s); break;
+    default: rows_m_w<T, 64>(n, m, rp, ci, av, op, s); break;
+  }
+}
+
+template <class Op>
+void elem_m(int n, const MCtx& m, const Op& op, hipStream_t s) {
+  switch (width_of(m.R)) {
+    case 1: elem_m_w<1>(n, m, op, s); break;
+    case 2: elem_m_w<2>(n, m, op, s); break;
+    case 4: elem_m_w<4>(n, m, op, s); break;
+    case 8: elem_m_w<8>(n, m, op, s); break;
+    case 16: elem_m_w<16>(n, m, op, s); break;
+    case 32: elem_m_w<32>(n, m, op, s); break;
+    default: elem_m_w<64>(n, m, op, s); break;
+  }
+}
+
+// ------------------------------------------------------------------ ops
+#define M_COMMON                                                  \
+  __device__ bool active() const { return a.on(); }              \
+  __device__ void idle() const {}                                \
+  __device__ void finalize_all() const {}
+
+template <typename T>
+struct MPresmoothResid {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const T* b;
+  const T* wd;
+  T* xt;
+  T* r;
+  M_COMMON
+  __device__ T x(int j, int c) const { return wd[j] * b[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, T ax, double*) const {
+    const size_t q = (size_t)i * R + c;
+    const T bi = b[q];
+    xt[q] = wd[i] * bi;
+    r[q] = bi - ax;
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+template <typename T>
+struct MResidSmooth {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const T* b;
+  const T* xt;
+  const T* wd;
+  T* xo;
+  M_COMMON
+  __device__ T x(int j, int c) const { return xt[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, T ax, double*) const {
+    const size_t q = (size_t)i * R + c;
+    xo[q] = xt[q] + wd[i] * (b[q] - ax);
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+template <typename T, bool DOT>
+struct MRestrict {
+  static constexpr int NV = DOT ? 1 : 0;
+  ActAny a;
+  int R;
+  const int* agg_ptr;
+  const int* agg_rows;
+  const T* pval;
+  const T* r;
+  T* rcv;
+  double* K;   // per-column K slots of this level (slot * R + c)
+  M_COMMON
+  __device__ void elem(int I, int c, double* acc) const {
+    T s = T(0);
+    for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
+      const int i = agg_rows[k];
+      s += pval[i] * r[(size_t)i * R + c];
+    }
+    rcv[(size_t)I * R + c] = s;
+    if (DOT) acc[0] += (double)s * (double)s;
+  }
+  __device__ void finalize(int c, const double* v) const {
+    if (DOT) K[kKRcRc * R + c] = v[0];
+  }
+};
+
+template <typename T>
+struct MProlong {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const int* agg;
+  const T* pval;
+  const T* cc;
+  T* xt;
+  M_COMMON
+  __device__ void elem(int i, int c, double*) const {
+    xt[(size_t)i * R + c] += pval[i] * cc[(size_t)agg[i] * R + c];
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+template <typename T>
+struct MKDots1 {
+  static constexpr int NV = 2;
+  ActAny a;
+  int R;
+  const T* cc;
+  const T* rcv;
+  T* v;
+  double* K;
+  int gmres;
+  M_COMMON
+  __device__ T x(int j, int c) const { return cc[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, T ax, double* acc) const {
+    const size_t q = (size_t)i * R + c;
+    v[q] = ax;
+    const double l = gmres ? (double)ax : (double)cc[q];
+    acc[0] += l * (double)ax;
+    acc[1] += l * (double)rcv[q];
+  }
+  __device__ void finalize(int c, const double* s) const {
+    K[kKRho1 * R + c] = s[0];
+    K[kKAlpha1 * R + c] = s[1];
+  }
+};
+
+template <typename T>
+struct MRtilde {
+  static constexpr int NV = 1;
+  ActAny a;
+  int R;
+  const T* rcv;
+  const T* v;
+  T* rt;
+  double* K;
+  int* F;       // per-column: F[c] step 2, F[R + c] use d
+  int* any2;    // any column needs step 2
+  double t;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const { *any2 = 0; }
+  __device__ void elem(int i, int c, double* acc) const {
+    const size_t q = (size_t)i * R + c;
+    const T ar = (T)(K[kKAlpha1 * R + c] / K[kKRho1 * R + c]);
+    const T u = rcv[q] - ar * v[q];
+    rt[q] = u;
+    acc[0] += (double)u * (double)u;
+  }
+  __device__ void finalize(int c, const double* s) const {
+    const double rho1 = K[kKRho1 * R + c];
+    K[kKRtRt * R + c] = s[0];
+    F[R + c] = 0;
+    if (rho1 > 0.0) {
+      K[kKCoefC * R + c] = K[kKAlpha1 * R + c] / rho1;
+      F[c] = (sqrt(s[0]) <= t * sqrt(K[kKRcRc * R + c])) ? 0 : 1;
+    } else {
+      K[kKCoefC * R + c] = 0.0;
+      F[c] = 0;
+    }
+  }
+  __device__ void finalize_all() const {
+    int any = 0;
+    for (int c = 0; c < R; ++c) any |= F[c];
+    *any2 = any;
+  }
+};
+
+template <typename T>
+struct MKDots2 {
+  static constexpr int NV = 3;
+  ActAny a;
+  int R;
+  const T* d;
+  const T* v;
+  const T* rt;
+  T* w;
+  double* K;
+  int* F;
+  int gmres;
+  M_COMMON
+  __device__ T x(int j, int c) const { return d[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, T ax, double* acc) const {
+    const size_t q = (size_t)i * R + c;
+    w[q] = ax;
+    const double l = gmres ? (double)ax : (double)d[q];
+    acc[0] += l * (double)v[q];
+    acc[1] += l * (double)ax;
+    acc[2] += l * (double)rt[q];
+  }
+  __device__ void finalize(int c, const double* s) const {
+    if (!F[c]) return;
+    const double gamma = s[0], beta = s[1], alpha2 = s[2];
+    const double rho1 = K[kKRho1 * R + c], alpha1 = K[kKAlpha1 * R + c];
+    const double rho2 = beta - gamma * gamma / rho1;
+    if (rho2 > 0.0) {
+      K[kKCoefC * R + c] = alpha1 / rho1 - gamma * alpha2 / (rho1 * rho2);
+      K[kKCoefD * R + c] = alpha2 / rho2;
+      F[R + c] = 1;
+    }
+  }
+};
+
+template <typename T>
+struct MProlongK {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const int* agg;
+  const T* pval;
+  const T* cc;
+  const T* d;
+  T* xt;
+  const double* K;
+  const int* F;
+  M_COMMON
+  __device__ void elem(int i, int c, double*) const {
+    const size_t I = (size_t)agg[i] * R + c;
+    T xc = (T)K[kKCoefC * R + c] * cc[I];
+    if (F[R + c]) xc += (T)K[kKCoefD * R + c] * d[I];
+    xt[(size_t)i * R + c] += pval[i] * xc;
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+// coarsest level: X_L = A_L^-1 B_L, one wave per row, lanes over columns
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gemm_coarse(int n, int R, const T* __restrict__ Ainv,
+                                                        const T* __restrict__ B, T* __restrict__ X, ActAny a) {
+  if (!a.on()) return;
+  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int c = threadIdx.x & (kWave - 1);
+  if (row >= n || c >= R) return;
+  const T* Ar = Ainv + (size_t)row * n;
+  T s = T(0);
+  for (int j = 0; j < n; ++j) s += Ar[j] * B[(size_t)j * R + c];
+  X[(size_t)row * R + c] = s;
+}
+
+// outer flexible CG, per column
+struct MFcgInit {
+  static constexpr int NV = 1;
+  ActAny a;
+  int R;
+  const double* b;
+  double* r;
+  double* xv;
+  double* sc;
+  int* fl;
+  int* any;
+  int* err;
+  double rtol;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, int c, double* acc) const {
+    const size_t q = (size_t)i * R + c;
+    const double t = b[q];
+    r[q] = t;
+    xv[q] = 0.0;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(int c, const double* s) const {
+    sc[mBB * R + c] = s[0];
+    sc[mRtol2 * R + c] = rtol * rtol * s[0];
+    fl[fIters * R + c] = 0;
+    fl[fRun * R + c] = s[0] > 0.0 ? 1 : 0;
+    if (!__builtin_isfinite(s[0])) {
+      *err |= kErrNonFinite;
+      fl[fRun * R + c] = 0;
+    }
+  }
+  __device__ void finalize_all() const {
+    int x = 0;
+    for (int c = 0; c < R; ++c) x |= fl[fRun * R + c];
+    any[aRun] = x;
+  }
+};
+
+struct MFcgSpmv {
+  static constexpr int NV = 2;
+  ActAny a;
+  int R;
+  const double* p;
+  const double* r;
+  double* q;
+  double* sc;
+  int* fl;
+  int* any;
+  int* err;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ double x(int j, int c) const { return p[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, double ax, double* acc) const {
+    const size_t k = (size_t)i * R + c;
+    q[k] = ax;
+    acc[0] += p[k] * ax;
+    acc[1] += p[k] * r[k];
+  }
+  __device__ void finalize(int c, const double* s) const {
+    if (!fl[fRun * R + c]) return;
+    sc[mPQ * R + c] = s[0];
+    sc[mAlpha * R + c] = s[1] / s[0];
+    fl[fIters * R + c] += 1;
+    if (!(s[0] > 0.0)) {
+      *err |= __builtin_isfinite(s[0]) ? kErrBreakdown : kErrNonFinite;
+      fl[fRun * R + c] = 0;
+    }
+  }
+  __device__ void finalize_all() const {
+    int x = 0;
+    for (int c = 0; c < R; ++c) x |= fl[fRun * R + c];
+    any[aRun] = x;
+  }
+};
+
+struct MFcgUpdate {
+  static constexpr int NV = 1;
+  ActAny a;
+  int R;
+  const double* p;
+  const double* q;
+  double* xv;
+  double* r;
+  double* sc;
+  int* fl;
+  int* any;
+  int* err;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, int c, double* acc) const {
+    if (!fl[fRun * R + c]) return;
+    const size_t k = (size_t)i * R + c;
+    const double al = sc[mAlpha * R + c];
+    xv[k] += al * p[k];
+    const double t = r[k] - al * q[k];
+    r[k] = t;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(int c, const double* s) const {
+    if (!fl[fRun * R + c]) return;
+    sc[mRR * R + c] = s[0];
+    if (!__builtin_isfinite(s[0])) {
+      *err |= kErrNonFinite;
+      fl[fRun * R + c] = 0;
+    } else if (s[0] <= sc[mRtol2 * R + c]) {
+      fl[fRun * R + c] = 0;
+    }
+  }
+  __device__ void finalize_all() const {
+    int x = 0;
+    for (int c = 0; c < R; ++c) x |= fl[fRun * R + c];
+    any[aRun] = x;
+  }
+};
+
+template <typename T>
+struct MDotZQ {
+  static constexpr int NV = 1;
+  ActAny a;
+  int R;
+  const T* z;
+  const double* q;
+  double* sc;
+  M_COMMON
+  __device__ void elem(int i, int c, double* acc) const {
+    const size_t k = (size_t)i * R + c;
+    acc[0] += (double)z[k] * q[k];
+  }
+  __device__ void finalize(int c, const double* s) const { sc[mBeta * R + c] = -s[0] / sc[mPQ * R + c]; }
+};
+
+template <typename T>
+struct MPUpdate {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const T* z;
+  double* p;
+  const double* sc;
+  const int* fl;
+  int first;
+  M_COMMON
+  __device__ void elem(int i, int c, double*) const {
+    if (!fl[fRun * R + c]) return;
+    const size_t k = (size_t)i * R + c;
+    p[k] = first ? (double)z[k] : (double)z[k] + sc[mBeta * R + c] * p[k];
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+struct MToFloat {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const double* in;
+  float* out;
+  M_COMMON
+  __device__ void elem(int i, int c, double*) const {
+    const size_t k = (size_t)i * R + c;
+    out[k] = (float)in[k];
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+struct MTrueResid {
+  static constexpr int NV = 1;
+  ActAny a;
+  int R;
+  const double* b;
+  const double* xv;
+  double* r;
+  double* sc;
+  M_COMMON
+  __device__ double x(int j, int c) const { return xv[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, double ax, double* acc) const {
+    const size_t k = (size_t)i * R + c;
+    const double t = b[k] - ax;
+    r[k] = t;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(int c, const double* s) const { sc[mTrue * R + c] = s[0]; }
+};
+
+// restart the columns whose recurrence converged but whose true residual did
+// not: r = b - A x for them, running again
+struct MRestartMask {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const double* rtrue;
+  double* r;
+  const int* again;   // host-chosen columns
+  int* fl;
+  int* any;
+  M_COMMON
+  __device__ void elem(int i, int c, double*) const {
+    if (!again[c]) return;
+    const size_t k = (size_t)i * R + c;
+    r[k] = rtrue[k];
+    if (i == 0) {
+      fl[fRun * R + c] = 1;
+      any[aRun] = 1;
+    }
+  }
+  __device__ void finalize(int, const double*) const {}
+};
+
+#undef M_COMMON
+
+// ------------------------------------------------------------ typed views
+template <typename T> const T* vals_t(const Level& l);
+template <> const double* vals_t<double>(const Level& l) { return l.val; }
+template <> const float* vals_t<float>(const Level& l) { return l.val32; }
+template <typename T> const T* wdinv_t(const Level& l);
+template <> const double* wdinv_t<double>(const Level& l) { return l.wdinv; }
+template <> const float* wdinv_t<float>(const Level& l) { return l.wdinv32; }
+template <typename T> const T* pvals_t(const Level& l);
+template <> const double* pvals_t<double>(const Level& l) { return l.pval; }
+template <> const float* pvals_t<float>(const Level& l) { return l.pval32; }
+template <typename T> const T* cinv_t(const Hierarchy& h);
+template <> const double* cinv_t<double>(const Hierarchy& h) { return h.cinv; }
+template <> const float* cinv_t<float>(const Hierarchy& h) { return h.cinv32; }
+
+// per-level work blocks [n][R] (or [n_{k+1}][R])
+struct MLevel {
+  void *r, *xt, *rc, *c, *v, *rt, *d, *w;
+};
+
+struct MWork {
+  int R = 0;
+  Arena arena;
+  std::vector<MLevel> lv;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *xv = nullptr, *rtrue = nullptr;
+  void* z = nullptr;
+  void* bz = nullptr;
+  MCtx m{};
+  int* again = nullptr;
+};
+
+template <typename T>
+void coarse_m(Hierarchy& h, const MCtx& m, const T* b, T* x, const int* act) {
+  const int n = h.levels.back().n;
+  const int rpb = kBlock / kWave;
+  k_gemm_coarse<T><<<(n + rpb - 1) / rpb, kBlock, 0, h.stream>>>(n, m.R, cinv_t<T>(h), b, x, ActAny{act});
+}
+
+template <typename T>
+void cycle_m(Hierarchy& h, MWork& W, int k, const T* b, T* xo, const int* act) {
+  const MCtx& m = W.m;
+  hipStream_t s = h.stream;
+  if (h.L() == 0) {
+    coarse_m<T>(h, m, b, xo, act);
+    return;
+  }
+  Level& lv = h.levels[k];
+  MLevel& ml = W.lv[k];
+  const int R = m.R, L = h.L();
+  T* xt = static_cast<T*>(ml.xt);
+  T* r = static_cast<T*>(ml.r);
+  T* rcv = static_cast<T*>(ml.rc);
+  T* c = static_cast<T*>(ml.c);
+  const T* wd = wdinv_t<T>(lv);
+  const T* pv = pvals_t<T>(lv);
+  const ActAny A{act};
+  rows_m<T>(lv.n, m, lv.rp, lv.ci, vals_t<T>(lv), MPresmoothResid<T>{A, R, b, wd, xt, r}, s);
+  const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
+  if (!kcyc) {
+    elem_m(lv.nc, m, MRestrict<T, false>{A, R, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr}, s);
+    if (k + 1 == L) coarse_m<T>(h, m, rcv, c, act);
+    else cycle_m<T>(h, W, k + 1, rcv, c, act);
+    elem_m(lv.n, m, MProlong<T>{A, R, lv.agg, pv, c, xt}, s);
+  } else {
+    Level& lc = h.levels[k + 1];
+    double* K = m.sc + (size_t)(mK0 + 16 * k) * R;
+    int* F = m.fl + (size_t)(fK0 + 2 * k) * R;
+    int* any2 = m.any + aK0 + k;
+    T* v = static_cast<T*>(ml.v);
+    T* rt = static_cast<T*>(ml.rt);
+    T* d = static_cast<T*>(ml.d);
+    T* w = static_cast<T*>(ml.w);
+    const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
+    elem_m(lv.nc, m, MRestrict<T, true>{A, R, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K}, s);
+    cycle_m<T>(h, W, k + 1, rcv, c, act);
+    rows_m<T>(lc.n, m, lc.rp, lc.ci, vals_t<T>(lc), MKDots1<T>{A, R, c, rcv, v, K, gm}, s);
+    elem_m(lc.n, m, MRtilde<T>{A, R, rcv, v, rt, K, F, any2, h.opt.kcycle_t}, s);
+    cycle_m<T>(h, W, k + 1, rt, d, any2);
+    rows_m<T>(lc.n, m, lc.rp, lc.ci, vals_t<T>(lc), MKDots2<T>{ActAny{any2}, R, d, v, rt, w, K, F, gm}, s);
+    elem_m(lv.n, m, MProlongK<T>{A, R, lv.agg, pv, c, d, xt, K, F}, s);
+  }
+  rows_m<T>(lv.n, m, lv.rp, lv.ci, vals_t<T>(lv), MResidSmooth<T>{A, R, b, xt, wd, xo}, s);
+}
+
+template <typename T>
+void precondition_m(Hierarchy& h, MWork& W, const int* act) {
+  const int n = h.levels[0].n;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    elem_m(n, W.m, MToFloat{ActAny{act}, W.m.R, W.r, static_cast<float*>(W.bz)}, h.stream);
+    cycle_m<float>(h, W, 0, static_cast<const float*>(W.bz), static_cast<float*>(W.z), act);
+  } else {
+    cycle_m<double>(h, W, 0, W.r, static_cast<double*>(W.z), act);
+  }
+}
+
+template <typename T>
+void iteration_m(Hierarchy& h, MWork& W) {
+  const MCtx& m = W.m;
+  const Level& l0 = h.levels[0];
+  const int n = l0.n, R = m.R;
+  const int* run = m.any + aRun;
+  const ActAny A{run};
+  hipStream_t s = h.stream;
+  rows_m<double>(n, m, l0.rp, l0.ci, l0.val, MFcgSpmv{A, R, W.p, W.r, W.q, m.sc, m.fl, m.any, m.err}, s);
+  elem_m(n, m, MFcgUpdate{A, R, W.p, W.q, W.xv, W.r, m.sc, m.fl, m.any, m.err}, s);
+  precondition_m<T>(h, W, run);
+  elem_m(n, m, MDotZQ<T>{A, R, static_cast<const T*>(W.z), W.q, m.sc}, s);
+  elem_m(n, m, MPUpdate<T>{A, R, static_cast<const T*>(W.z), W.p, m.sc, m.fl, 0}, s);
+}
+
+template <typename T>
+void restart_m(Hierarchy& h, MWork& W) {
+  const int* run = W.m.any + aRun;
+  precondition_m<T>(h, W, run);
+  elem_m(h.levels[0].n, W.m, MPUpdate<T>{ActAny{run}, W.m.R, static_cast<const T*>(W.z), W.p, W.m.sc, W.m.fl, 1},
+         h.stream);
+}
+
+void alloc_work(Hierarchy& h, MWork& W, int R) {
+  const size_t es = h.mixed() ? sizeof(float) : sizeof(double);
+  W.R = R;
+  const int L = h.L();
+  W.lv.assign(std::max(L, 1), MLevel{});
+  for (int k = 0; k < L; ++k) {
+    const Level& lv = h.levels[k];
+    MLevel& ml = W.lv[k];
+    const size_t n = (size_t)lv.n * R, nc = (size_t)lv.nc * R;
+    ml.r = W.arena.alloc(n * es);
+    ml.xt = W.arena.alloc(n * es);
+    ml.rc = W.arena.alloc(nc * es);
+    ml.c = W.arena.alloc(nc * es);
+    if (k < h.opt.kcycle_levels) {
+      ml.v = W.arena.alloc(nc * es);
+      ml.rt = W.arena.alloc(nc * es);
+      ml.d = W.arena.alloc(nc * es);
+      ml.w = W.arena.alloc(nc * es);
+    }
+  }
+  const size_t n0 = (size_t)h.levels[0].n * R;
+  W.r = W.arena.alloc_n<double>(n0);
+  W.p = W.arena.alloc_n<double>(n0);
+  W.q = W.arena.alloc_n<double>(n0);
+  W.xv = W.arena.alloc_n<double>(n0);
+  W.z = W.arena.alloc(n0 * es);
+  if (h.mixed()) W.bz = W.arena.alloc(n0 * es);
+  W.m.R = R;
+  W.m.sc = W.arena.alloc_n<double>((size_t)mSlots * R);
+  W.m.fl = W.arena.alloc_n<int>((size_t)fWords * R);
+  W.m.any = W.arena.alloc_n<int>(aWords);
+  W.m.part = W.arena.alloc_n<double>((size_t)3 * R * kMultiBlocks);
+  W.m.err = h.d_err;
+  W.again = W.arena.alloc_n<int>(kMaxRhs);
+  launch_fill_int((size_t)fWords * R, W.m.fl, 0, h.stream);
+  launch_fill_int(aWords, W.m.any, 0, h.stream);
+}
+
+}  // namespace
+
+// Solve A X = B for R columns from X_0 = 0.  iters / relres: host arrays[R].
+int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres) {
+  if (R < 1 || R > kMaxRhs) throw Error(AMG_EINVAL, "nrhs must be in [1, 64]");
+  MWork W;
+  hipStream_t s = h.stream;
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+  alloc_work(h, W, R);
+  const Level& l0 = h.levels[0];
+  const int n = l0.n;
+  const bool mixed = h.mixed();
+  std::vector<int> hfl((size_t)fWords * R);
+  std::vector<double> hsc((size_t)mK0 * R);
+  std::vector<int> again(R);
+  elem_m(n, W.m, MFcgInit{ActAny{nullptr}, R, B, W.r, W.xv, W.m.sc, W.m.fl, W.m.any, W.m.err, rtol}, s);
+  if (mixed) restart_m<float>(h, W);
+  else restart_m<double>(h, W);
+  const int max_iter = h.opt.max_iter;
+  int enqueued = 0;
+  int status = AMG_OK;
+  int* hp = static_cast<int*>(h.h_pinned);
+  while (true) {
+    const int batch = std::min(4, max_iter - enqueued);
+    for (int i = 0; i < batch; ++i) {
+      if (mixed) iteration_m<float>(h, W);
+      else iteration_m<double>(h, W);
+    }
+    enqueued += batch;
+    AMG_HIP(hipGetLastError());
+    AMG_HIP(hipMemcpyAsync(hp, W.m.any + aRun, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hp + 1, h.d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    if (hp[1]) {
+      if (hp[1] & kErrNonFinite) throw Error(AMG_ENANINF, "non-finite value in the iteration");
+      if (hp[1] & kErrBreakdown) throw Error(AMG_EBREAKDOWN, "Krylov breakdown");
+      throw Error(AMG_EHIP, "device error bits " + std::to_string(hp[1]));
+    }
+    if (hp[0] && enqueued < max_iter) continue;
+    rows_m<double>(n, W.m, l0.rp, l0.ci, l0.val, MTrueResid{ActAny{nullptr}, R, B, W.xv, W.q, W.m.sc}, s);
+    AMG_HIP(hipMemcpyAsync(hfl.data(), W.m.fl, hfl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hsc.data(), W.m.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    bool any_again = false;
+    for (int c = 0; c < R; ++c) {
+      const double bb = hsc[mBB * R + c];
+      const double rel = bb > 0.0 ? std::sqrt(hsc[mTrue * R + c] / bb) : 0.0;
+      if (!std::isfinite(rel)) throw Error(AMG_ENANINF, "non-finite residual");
+      iters[c] = hfl[fIters * R + c];
+      relres[c] = rel;
+      again[c] = (rel > rtol && bb > 0.0 && iters[c] < max_iter && enqueued < max_iter) ? 1 : 0;
+      any_again |= again[c] != 0;
+      if (rel > rtol && bb > 0.0 && !again[c]) status = AMG_ENOTCONV;
+    }
+    if (!any_again) break;
+    AMG_HIP(hipMemcpyAsync(W.again, again.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
+    elem_m(n, W.m, MRestartMask{ActAny{nullptr}, R, W.q, W.r, W.again, W.m.fl, W.m.any}, s);
+    if (mixed) restart_m<float>(h, W);
+    else restart_m<double>(h, W);
+  }
+  AMG_HIP(hipMemcpyAsync(X, W.xv, (size_t)n * R * sizeof(double), hipMemcpyDeviceToDevice, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return status;
+}
+
+}  // namespace amg

@@ -1,0 +1,73 @@
+"""GPU: several right-hand sides in one solve (row-major block [n][nrhs]).
+
+Each column must behave as if solved alone: the same convergence (true
+relative residual <= 1e-8, iterations within one of the single-column solve)
+and the same solution to the accuracy the tolerance implies; the oracle's
+multi-RHS semantics (solve_multi: each column alone) pins the reference.
+"""
+import numpy as np
+import pytest
+
+from oracle import amg_oracle as O
+from synthetic import problems as P
+from tests.gpu_helpers import dev_vec, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amg = pytest.importorskip("paper_1403_1649_amd")
+
+
+def _block(A, R, seed=1):
+    X = P.multi_exact_solution(A.n, R, seed)
+    return P.rhs(A, X)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("R", [1, 5, 32])
+def test_columns_match_single_solves(precision, R):
+    A = P.hetero3d(18, seed=6)
+    rp, ci, v = to_dev(A)
+    h = amg.setup(rp, ci, v, amg.Options(dim=3, precision=precision))
+    B = _block(A, R)
+    X, its, rels = amg.solve_multi(h, torch.from_numpy(np.ascontiguousarray(B)).cuda(), 1e-8)
+    X = X.cpu().numpy()
+    S = A.to_scipy()
+    for c in range(R):
+        xs, it, rel = amg.solve(h, dev_vec(B[:, c]), 1e-8)
+        xs = xs.cpu().numpy()
+        assert rels[c] <= 1e-8 and abs(its[c] - it) <= 1, (c, its[c], it)
+        true_rel = np.linalg.norm(B[:, c] - S @ X[:, c]) / np.linalg.norm(B[:, c])
+        assert true_rel <= 1.01e-8
+        assert np.linalg.norm(X[:, c] - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_multi_rhs_against_oracle_and_zero_column():
+    A = P.aniso3d(16, 1e-3)
+    rp, ci, v = to_dev(A)
+    h = amg.setup(rp, ci, v, amg.Options(dim=3))
+    B = _block(A, 4, seed=2)
+    B[:, 2] = 0.0
+    X, its, rels = amg.solve_multi(h, torch.from_numpy(np.ascontiguousarray(B)).cuda(), 1e-8)
+    X = X.cpu().numpy()
+    H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(3))
+    ref = O.solve_multi(H, B, 1e-8)
+    for c in range(4):
+        if c == 2:
+            assert its[c] == 0 and rels[c] == 0.0 and np.all(X[:, c] == 0)
+            continue
+        assert abs(its[c] - ref[c].iters) <= 1 and rels[c] <= 1e-8
+        assert np.linalg.norm(X[:, c] - ref[c].x) <= 1e-6 * np.linalg.norm(ref[c].x)
+
+
+def test_multi_rhs_bad_arguments():
+    A = P.poisson2d(30)
+    rp, ci, v = to_dev(A)
+    h = amg.setup(rp, ci, v, amg.Options(dim=2))
+    with pytest.raises(amg.AmgError):
+        amg.solve_multi(h, torch.zeros((A.n, 65), dtype=torch.float64, device="cuda"))
+    B = _block(A, 3)
+    B[7, 1] = np.inf
+    with pytest.raises(amg.AmgError) as e:
+        amg.solve_multi(h, torch.from_numpy(np.ascontiguousarray(B)).cuda())
+    assert e.value.code == 7

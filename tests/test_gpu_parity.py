@@ -36,7 +36,7 @@ def test_node_hash_bit_exact():
         assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("lpr", [0, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lpr", [-1, 0, 1, 2, 4, 8, 16, 32, 64])
 def test_spmv_matches_oracle(lpr):
     A = P.hetero3d(24, seed=7)
     rp, ci, v = to_dev(A)
@@ -256,3 +256,25 @@ def test_probe_timing_samples_in_solve(probe):
     _, it, rel = amg.solve(h, b, 1e-8)
     ms, n = h.probe_timing()
     assert rel <= 1e-8 and n >= 1 and 0.0 < ms < 50.0
+
+
+@pytest.mark.parametrize("make", [lambda: P.poisson2d(37, 53), lambda: P.hetero3d(17, seed=2)])
+def test_sell_spmv_ragged_rows(make):
+    """Sliced ELL on ragged inputs: n not a multiple of 64, short boundary rows."""
+    A = make()
+    rp, ci, v = to_dev(A)
+    x = P.exact_solution(A.n, 5)
+    y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=-1).cpu().numpy()
+    S = A.to_scipy()
+    assert np.all(np.abs(y - S @ x) <= 1e-15 * 8 * (abs(S) @ np.abs(x)) + 1e-300)
+
+
+def test_tuned_and_untuned_kernels_agree():
+    A = P.hetero3d(30, seed=8)
+    b = dev_vec(P.rhs(A, P.exact_solution(A.n, 1)))
+    ht, _ = _setup(A, 3)
+    hu, _ = _setup(A, 3, flags=2)
+    xt, it_t, rel_t = amg.solve(ht, b, 1e-8)
+    xu, it_u, rel_u = amg.solve(hu, b, 1e-8)
+    assert rel_t <= 1e-8 and rel_u <= 1e-8 and abs(it_t - it_u) <= 1
+    assert float(torch.linalg.norm(xt - xu) / torch.linalg.norm(xu)) < 1e-7
