@@ -74,6 +74,8 @@ typedef struct {
   int32_t check_every;    /* largest number of outer iterations enqueued between host
                              convergence checks; the batch adapts to the observed rate (16) */
   uint32_t flags;         /* AMG_FLAG_* bits (0) */
+  const float* mlp_weights; /* (host) AMG_SMOOTHER_LEARNED: the 1409 FP32 weights of
+                               amg_mlp_num_params(), copied during setup (NULL) */
 } amg_options;
 
 /* amg_options.flags: launch every kernel from the host instead of replaying
@@ -136,6 +138,51 @@ int32_t amg_solve(amg_hierarchy* h, const double* b, double rtol, double* x,
  * any column did not converge).  Synchronises s. */
 int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double rtol, double* X,
                         int32_t* iters, double* relres, hipStream_t s);
+
+/* ---- Learned per-row Jacobi weights (an extension beyond the paper, which
+ * fixes one omega per level by eq. damped_jacobi).  omega_i = sigmoid(y_i) *
+ * 2|a_ii| / (|a_ii| + sum_{j!=i} |a_ij|), y = MLP 9->32->32->1 (ReLU) of the row
+ * features [log|a_ii| - level mean, six largest |a_ij|/|a_ii| descending,
+ * row sum / a_ii, level]; bfloat16 weights and inputs, FP32 accumulation.
+ * The bound keeps the smoother convergent for SPD A.  With
+ * opt.smoother = AMG_SMOOTHER_LEARNED, setup uses the learned weights on a
+ * level only when they lower the smoothing loss below the plain omega_k on
+ * four validation samples, and falls back to plain damped Jacobi otherwise. */
+
+/* Number of MLP parameters (1409): W1[32][9], b1[32], W2[32][32], b2[32], W3[32], b3. */
+int32_t amg_mlp_num_params(void);
+
+/* feats: device float [n_k][9], the bfloat16-rounded features of level k. */
+int32_t amg_mlp_features(const amg_hierarchy* h, int32_t k, float* feats, hipStream_t s);
+
+/* omega: device float64 [n_k], the learned weights of level k for the device
+ * parameter vector w (FP32 masters, rounded to bfloat16 inside). */
+int32_t amg_mlp_omega(const amg_hierarchy* h, int32_t k, const float* w, double* omega, hipStream_t s);
+
+/* Smoothing loss of level k, L = (1/S) sum_s ||(I - W A) e_s||_A^2 / ||e_s||_A^2,
+ * W = diag(omega_i / a_ii), over S = nsamples + n_extra error samples with the
+ * coarse-space component removed (e = v - P P^T v): v = unit_uniform(i,
+ * seed + s) for the first nsamples and the caller's device [n_k][n_extra]
+ * row-major block `extra` for the rest.  loss: (host).  grad (device float
+ * [1409], may be NULL): dL/dw, added to grad when accumulate != 0.
+ * 1 <= S <= 64.  Synchronises s. */
+int32_t amg_mlp_loss_grad(const amg_hierarchy* h, int32_t k, const float* w, int32_t nsamples, uint32_t seed,
+                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t accumulate,
+                          hipStream_t s);
+
+/* Adam step on device arrays of n floats: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, w -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+int32_t amg_mlp_adam(float* w, float* m, float* v, const float* g, int32_t n, int32_t step, float lr, float b1,
+                     float b2, float eps, hipStream_t s);
+
+/* (host) smoother used on level k: *learned = 1 when the learned weights
+ * passed validation there, with the validation losses of plain omega_k and of
+ * the learned weights (0 when not evaluated). */
+int32_t amg_level_smoother(const amg_hierarchy* h, int32_t k, int32_t* learned, double* loss_plain,
+                           double* loss_learned);
+
+/* (host) copy of omega_i / a_ii, the Jacobi scaling the cycle applies on level k. */
+int32_t amg_export_jacobi(const amg_hierarchy* h, int32_t k, double* wdinv);
 
 /* Release the hierarchy and its device memory (NULL is ignored). */
 void amg_destroy(amg_hierarchy* h);

@@ -14,6 +14,11 @@ from .binding import (  # noqa: F401
     galerkin,
     hessenberg_radius,
     lib,
+    mlp_adam,
+    mlp_features,
+    mlp_loss_grad,
+    mlp_num_params,
+    mlp_omega,
     library_path,
     node_hash,
     setup,

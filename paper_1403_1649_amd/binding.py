@@ -19,7 +19,8 @@ EXPORTED = [
     "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",
     "amg_destroy", "amg_num_levels", "amg_level_info", "amg_export_level", "amg_spmv",
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
-    "amg_solve_multi",
+    "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
+    "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi",
 ]
 
 
@@ -30,7 +31,7 @@ class AmgOptionsC(C.Structure):
         ("arnoldi_m", C.c_int32), ("seed", C.c_uint32), ("krylov", C.c_int32),
         ("gmres_restart", C.c_int32), ("precision", C.c_int32), ("smoother", C.c_int32),
         ("max_iter", C.c_int32), ("dense_max", C.c_int32), ("probe", C.c_int32), ("check_every", C.c_int32),
-        ("flags", C.c_uint32),
+        ("flags", C.c_uint32), ("mlp_weights", C.c_void_p),
     ]
 
 
@@ -94,6 +95,20 @@ def lib():
     L.amg_timings.restype = i32
     L.amg_solve_multi.argtypes = [vp, i32, vp, dbl, vp, vp, vp, vp]
     L.amg_solve_multi.restype = i32
+    L.amg_mlp_num_params.argtypes = []
+    L.amg_mlp_num_params.restype = i32
+    L.amg_mlp_features.argtypes = [vp, i32, vp, vp]
+    L.amg_mlp_features.restype = i32
+    L.amg_mlp_omega.argtypes = [vp, i32, vp, vp, vp]
+    L.amg_mlp_omega.restype = i32
+    L.amg_mlp_loss_grad.argtypes = [vp, i32, vp, i32, u32, vp, i32, P(dbl), vp, i32, vp]
+    L.amg_mlp_loss_grad.restype = i32
+    L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.amg_mlp_adam.restype = i32
+    L.amg_level_smoother.argtypes = [vp, i32, P(i32), P(dbl), P(dbl)]
+    L.amg_level_smoother.restype = i32
+    L.amg_export_jacobi.argtypes = [vp, i32, vp]
+    L.amg_export_jacobi.restype = i32
     L.amg_probe_timing.argtypes = [vp, P(dbl), P(i32)]
     L.amg_probe_timing.restype = i32
     _LIB = L
@@ -124,11 +139,23 @@ def _nptr(a: np.ndarray) -> C.c_void_p:
 
 
 class Options:
-    """Setup/solve options (amg_options); keyword names follow the C struct."""
+    """Setup/solve options (amg_options); keyword names follow the C struct.
+
+    ``mlp_weights`` takes a NumPy float32 array of amg_mlp_num_params()
+    values and selects the learned smoother."""
 
     def __init__(self, dim: int = 3, **kw):
         self.c = AmgOptionsC()
+        self._keep = None
         lib().amg_default_options(C.byref(self.c), int(dim))
+        if kw.get("mlp_weights") is not None:
+            w = np.ascontiguousarray(kw.pop("mlp_weights"), dtype=np.float32)
+            if w.size != lib().amg_mlp_num_params():
+                raise ValueError("mlp_weights has the wrong length")
+            self._keep = w
+            self.c.mlp_weights = w.ctypes.data
+            self.c.smoother = 1
+        kw.pop("mlp_weights", None)
         for k, v in kw.items():
             if k == "precision" and isinstance(v, str):
                 v = _PREC[v]
@@ -211,6 +238,18 @@ class Hierarchy:
         s, v = C.c_double(), C.c_double()
         _check(lib().amg_timings(self._h, C.byref(s), C.byref(v)))
         return s.value, v.value
+
+    def smoother_info(self, k: int):
+        """(learned?, validation loss with plain omega, with learned weights)."""
+        l, a, b = C.c_int32(), C.c_double(), C.c_double()
+        _check(lib().amg_level_smoother(self._h, k, C.byref(l), C.byref(a), C.byref(b)))
+        return bool(l.value), a.value, b.value
+
+    def jacobi_weights(self, k: int) -> np.ndarray:
+        """omega_i / a_ii of level k (host copy)."""
+        out = np.empty(self.level_info(k)["n"], np.float64)
+        _check(lib().amg_export_jacobi(self._h, k, _nptr(out)))
+        return out
 
     def probe_timing(self):
         """(average ms, samples) of the kernel selected by the probe option."""
@@ -296,3 +335,39 @@ def hessenberg_radius(H: np.ndarray) -> float:
     rho = C.c_double()
     _check(lib().amg_hessenberg_radius(_nptr(H), int(H.shape[0]), C.byref(rho)))
     return rho.value
+
+
+# ---------------------------------------------------------------- learned weights
+def mlp_num_params() -> int:
+    return lib().amg_mlp_num_params()
+
+
+def mlp_features(h: Hierarchy, k: int):
+    import torch
+    n = h.level_info(k)["n"]
+    F = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    _check(lib().amg_mlp_features(h.handle, k, _ptr(F), _stream()))
+    return F
+
+
+def mlp_omega(h: Hierarchy, k: int, w):
+    import torch
+    n = h.level_info(k)["n"]
+    om = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(lib().amg_mlp_omega(h.handle, k, _ptr(w), _ptr(om), _stream()))
+    return om
+
+
+def mlp_loss_grad(h: Hierarchy, k: int, w, nsamples: int, seed: int, extra=None, grad=None,
+                  accumulate: bool = False) -> float:
+    loss = C.c_double()
+    n_extra = 0 if extra is None else int(extra.shape[1])
+    _check(lib().amg_mlp_loss_grad(h.handle, k, _ptr(w), int(nsamples), int(seed) & 0xFFFFFFFF,
+                                   None if extra is None else _ptr(extra), n_extra, C.byref(loss),
+                                   None if grad is None else _ptr(grad), int(bool(accumulate)), _stream()))
+    return loss.value
+
+
+def mlp_adam(w, m, v, g, step: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    _check(lib().amg_mlp_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(g), int(w.numel()), int(step), float(lr),
+                              float(b1), float(b2), float(eps), _stream()))

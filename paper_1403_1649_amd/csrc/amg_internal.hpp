@@ -93,7 +93,9 @@ struct Level {
   double* pval = nullptr;      // the single nonzero of row i of P_k
   float* pval32 = nullptr;
   double omega = 0.0, rho = 0.0;
-  double* wdinv = nullptr;     // omega / a_ii
+  double* wdinv = nullptr;     // omega / a_ii (or omega_i / a_ii with learned weights)
+  int learned = 0;             // learned weights in use on this level
+  double loss_plain = 0.0, loss_learned = 0.0;
   float* wdinv32 = nullptr;
   // solve scratch (typed by the cycle precision; size n or n_{k+1})
   void* r = nullptr;           // fine residual
@@ -128,7 +130,8 @@ struct Hierarchy {
   double *r = nullptr, *p = nullptr, *q = nullptr;
   void* z = nullptr;           // preconditioned residual (cycle precision)
   void* bz = nullptr;          // cycle right-hand side in cycle precision (mixed mode)
-  double* xint = nullptr;      // iterate of the outer solve (copied to the caller's x at exit)
+  double* xint = nullptr;
+  float* mlp_w = nullptr;      // device copy of the learned-weight parameters      // iterate of the outer solve (copied to the caller's x at exit)
   // captured launch sequences of one outer iteration (one segment, or two
   // around the probed kernel, which is then launched from the host between
   // them) and of the (re)start
@@ -227,6 +230,15 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
 void build_solve_graphs(Hierarchy& h);
 void autotune_levels(Hierarchy& h);
+int mlp_num_params();
+void mlp_features(Hierarchy& h, const Level& lv, int level, float* F, double* beta);
+void mlp_omega(Hierarchy& h, const Level& lv, const float* F, const double* beta, const float* wdev, double* omega,
+               double* wdinv, float* wdinv32, double* sig);
+double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const float* wdev, int S_rand,
+                     uint32_t seed, const double* extra, int S_extra, const double* omega_fixed, float* grad,
+                     int accumulate);
+void mlp_adam(float* w, float* m, float* v, const float* g, int n, int step, float lr, float b1, float b2, float eps,
+              hipStream_t s);
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres);
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y);
 void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y);

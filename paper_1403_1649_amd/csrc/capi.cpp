@@ -70,6 +70,7 @@ void amg_default_options(amg_options* opt, int32_t dim) {
   opt->probe = AMG_PROBE_NONE;
   opt->check_every = 16;
   opt->flags = 0;
+  opt->mlp_weights = nullptr;
 }
 
 const char* amg_status_string(int32_t status) {
@@ -102,7 +103,10 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
   if (o.krylov != AMG_KRYLOV_FCG) return fail(AMG_EUNSUPPORTED, "amg_setup: only flexible CG is built");
   if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
     return fail(AMG_EINVAL, "amg_setup: unknown precision");
-  if (o.smoother != AMG_SMOOTHER_JACOBI) return fail(AMG_EUNSUPPORTED, "amg_setup: smoother");
+  if (o.smoother != AMG_SMOOTHER_JACOBI && o.smoother != AMG_SMOOTHER_LEARNED)
+    return fail(AMG_EINVAL, "amg_setup: smoother");
+  if (o.smoother == AMG_SMOOTHER_LEARNED && !o.mlp_weights)
+    return fail(AMG_EINVAL, "amg_setup: the learned smoother needs mlp_weights");
   if (o.probe < AMG_PROBE_NONE || o.probe > AMG_PROBE_OUTER_SPMV) return fail(AMG_EINVAL, "amg_setup: probe");
   auto* H = new (std::nothrow) amg_hierarchy();
   if (!H) return fail(AMG_ENOMEM, "amg_setup: host allocation");
@@ -282,6 +286,87 @@ int32_t amg_timings(const amg_hierarchy* H, double* setup_ms, double* solve_ms) 
   if (setup_ms) *setup_ms = H->h.setup_ms;
   if (solve_ms) *solve_ms = H->h.solve_ms;
   return AMG_OK;
+}
+
+int32_t amg_mlp_num_params(void) { return amg::mlp_num_params(); }
+
+static bool level_ok(const amg_hierarchy* H, int32_t k) {
+  return H && k >= 0 && k + 1 < (int32_t)H->h.levels.size();
+}
+
+int32_t amg_mlp_features(const amg_hierarchy* H, int32_t k, float* feats, hipStream_t s) {
+  if (!level_ok(H, k) || !feats) return fail(AMG_EINVAL, "amg_mlp_features: bad argument");
+  return guarded("amg_mlp_features", [&] {
+    amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
+    hipStream_t keep = h.stream;
+    h.stream = s;
+    amg::mlp_features(h, h.levels[k], k, feats, nullptr);
+    h.stream = keep;
+    AMG_HIP(hipGetLastError());
+  });
+}
+
+int32_t amg_mlp_omega(const amg_hierarchy* H, int32_t k, const float* w, double* omega, hipStream_t s) {
+  if (!level_ok(H, k) || !w || !omega) return fail(AMG_EINVAL, "amg_mlp_omega: bad argument");
+  return guarded("amg_mlp_omega", [&] {
+    amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
+    hipStream_t keep = h.stream;
+    h.stream = s;
+    amg::Arena tmp;
+    struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+    const amg::Level& lv = h.levels[k];
+    float* F = tmp.alloc_n<float>((size_t)lv.n * 9);
+    double* beta = tmp.alloc_n<double>(lv.n);
+    amg::mlp_features(h, lv, k, F, beta);
+    amg::mlp_omega(h, lv, F, beta, w, omega, nullptr, nullptr, nullptr);
+    h.stream = keep;
+    AMG_HIP(hipGetLastError());
+  });
+}
+
+int32_t amg_mlp_loss_grad(const amg_hierarchy* H, int32_t k, const float* w, int32_t nsamples, uint32_t seed,
+                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t accumulate,
+                          hipStream_t s) {
+  if (!level_ok(H, k) || !w || !loss || nsamples < 0 || n_extra < 0 || (n_extra > 0 && !extra) ||
+      nsamples + n_extra < 1 || nsamples + n_extra > 64)
+    return fail(AMG_EINVAL, "amg_mlp_loss_grad: bad argument");
+  return guarded("amg_mlp_loss_grad", [&] {
+    amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
+    hipStream_t keep = h.stream;
+    h.stream = s;
+    amg::Arena tmp;
+    struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+    *loss = amg::mlp_loss_grad(h, tmp, h.levels[k], k, w, nsamples, seed, extra, n_extra, nullptr, grad, accumulate);
+    h.stream = keep;
+  });
+}
+
+int32_t amg_mlp_adam(float* w, float* m, float* v, const float* g, int32_t n, int32_t step, float lr, float b1,
+                     float b2, float eps, hipStream_t s) {
+  if (!w || !m || !v || !g || n < 1 || step < 1) return fail(AMG_EINVAL, "amg_mlp_adam: bad argument");
+  return guarded("amg_mlp_adam", [&] {
+    amg::mlp_adam(w, m, v, g, n, step, lr, b1, b2, eps, s);
+    AMG_HIP(hipGetLastError());
+  });
+}
+
+int32_t amg_level_smoother(const amg_hierarchy* H, int32_t k, int32_t* learned, double* loss_plain,
+                           double* loss_learned) {
+  if (!H || k < 0 || k >= (int32_t)H->h.levels.size()) return fail(AMG_EINVAL, "amg_level_smoother: level");
+  const amg::Level& lv = H->h.levels[k];
+  if (learned) *learned = lv.learned;
+  if (loss_plain) *loss_plain = lv.loss_plain;
+  if (loss_learned) *loss_learned = lv.loss_learned;
+  return AMG_OK;
+}
+
+int32_t amg_export_jacobi(const amg_hierarchy* H, int32_t k, double* wdinv) {
+  if (!level_ok(H, k) || !wdinv) return fail(AMG_EINVAL, "amg_export_jacobi: bad argument");
+  return guarded("amg_export_jacobi", [&] {
+    const amg::Level& lv = H->h.levels[k];
+    AMG_HIP(hipMemcpyAsync(wdinv, lv.wdinv, (size_t)lv.n * sizeof(double), hipMemcpyDeviceToHost, H->h.stream));
+    AMG_HIP(hipStreamSynchronize(H->h.stream));
+  });
 }
 
 int32_t amg_probe_timing(const amg_hierarchy* H, double* avg_ms, int32_t* samples) {

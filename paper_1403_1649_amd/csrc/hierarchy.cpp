@@ -384,6 +384,16 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   sy.wait_and_check();
 
   const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  if (o.smoother == AMG_SMOOTHER_LEARNED) {
+    if (!o.mlp_weights) throw Error(AMG_EINVAL, "learned smoother without weights");
+    const int np = mlp_num_params();
+    for (int q = 0; q < np; ++q)
+      if (!std::isfinite(o.mlp_weights[q])) throw Error(AMG_EINVAL, "non-finite MLP weight");
+    h.mlp_w = h.arena.alloc_n<float>(np);
+    AMG_HIP(hipMemcpyAsync(h.mlp_w, o.mlp_weights, np * sizeof(float), hipMemcpyHostToDevice, s));
+    sy.wait_and_check();
+    h.opt.mlp_weights = nullptr;   // the host pointer is not kept
+  }
   while (true) {
     const int k = (int)h.levels.size() - 1;
     Level& lv = h.levels[k];
@@ -483,6 +493,24 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     lv.wdinv = h.arena.alloc_n<double>(n);
     if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
     launch_jacobi_weights(n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, s);
+    if (o.smoother == AMG_SMOOTHER_LEARNED) {
+      // learned per-row weights, kept only when they smooth better than omega_k
+      const double* plain_om = nullptr;
+      double* omv = tmp.alloc_n<double>(n);
+      launch_fill_double(n, omv, lv.omega, s);
+      plain_om = omv;
+      Arena vt;
+      lv.loss_plain = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, plain_om, nullptr, 0);
+      lv.loss_learned = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, nullptr, nullptr, 0);
+      if (std::isfinite(lv.loss_learned) && lv.loss_learned < lv.loss_plain) {
+        float* F = vt.alloc_n<float>((size_t)n * 9);
+        double* beta = vt.alloc_n<double>(n);
+        mlp_features(h, lv, k, F, beta);
+        mlp_omega(h, lv, F, beta, h.mlp_w, nullptr, lv.wdinv, lv.wdinv32, nullptr);
+        lv.learned = 1;
+      }
+      sy.wait_and_check();
+    }
     h.levels.push_back(lc);
   }
 

@@ -1,0 +1,123 @@
+"""GPU parity of the learned Jacobi weights against the FP64 oracle (same
+bfloat16 rounding): features, omega, loss and gradient; then training and
+what the trained weights gain over plain damped Jacobi."""
+import numpy as np
+import pytest
+
+from oracle import amg_oracle as O
+from oracle import mlp_oracle as M
+from synthetic import problems as P
+from tests.gpu_helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amg = pytest.importorskip("paper_1403_1649_amd")
+
+
+def _setup(A, **kw):
+    rp, ci, v = to_dev(A)
+    return amg.setup(rp, ci, v, amg.Options(dim=3, **kw))
+
+
+def _weights(seed=3):
+    w = M.init_weights(seed).astype(np.float32)
+    w[-1] = 0.4
+    return w
+
+
+def test_features_match_oracle():
+    A = P.hetero3d(14, seed=5)
+    h = _setup(A)
+    for k in range(h.num_levels() - 1):
+        ex = h.export_level(k, what=("A",))
+        S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+        want = M.bf16(M.features(S, k))
+        got = amg.mlp_features(h, k).cpu().numpy().astype(np.float64)
+        # identical but for rare last-place differences of log() before rounding
+        ulp = np.maximum(np.abs(want), 1e-30) * 2.0 ** -7
+        assert np.all(np.abs(got - want) <= ulp)
+        assert np.mean(got == want) > 0.999
+
+
+def test_omega_loss_and_gradient_match_oracle():
+    A = P.hetero3d(12, seed=8)
+    h = _setup(A)
+    w = _weights()
+    wd = torch.from_numpy(w).cuda()
+    for k in range(h.num_levels() - 1):
+        ex = h.export_level(k)
+        S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+        F = amg.mlp_features(h, k).cpu().numpy().astype(np.float64)
+        om = amg.mlp_omega(h, k, wd).cpu().numpy()
+        want = M.omega(w.astype(np.float64), S, F)
+        assert np.allclose(om, want, rtol=1e-5, atol=0)
+        E = M.projected_errors(S, ex["agg"], ex["pval"], ex["nc"], 6, 77)
+        lo, go = M.loss_and_grad(w.astype(np.float64), S, F, E)
+        g = torch.zeros_like(wd)
+        loss = amg.mlp_loss_grad(h, k, wd, 6, 77, None, g)
+        assert abs(loss - lo) <= 1e-5 * lo
+        g = g.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+
+
+def test_extra_samples_and_accumulation():
+    A = P.hetero3d(12, seed=9)
+    h = _setup(A)
+    wd = torch.from_numpy(_weights(4)).cuda()
+    n = A.n
+    extra = torch.from_numpy(np.random.default_rng(0).standard_normal((n, 2))).cuda()
+    g1 = torch.zeros_like(wd)
+    g2 = torch.zeros_like(wd)
+    amg.mlp_loss_grad(h, 0, wd, 3, 5, extra, g1)
+    amg.mlp_loss_grad(h, 0, wd, 3, 5, extra, g2)
+    amg.mlp_loss_grad(h, 0, wd, 3, 5, extra, g2, accumulate=True)
+    assert torch.allclose(2 * g1, g2, rtol=1e-6, atol=0)
+
+
+def test_adam_step_matches_formula():
+    rng = np.random.default_rng(1)
+    w, m, v, g = (rng.standard_normal(1409).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    tw, tm, tv, tg = (torch.from_numpy(a.copy()).cuda() for a in (w, m, v, g))
+    amg.mlp_adam(tw, tm, tv, tg, 3, 1e-2)
+    m2 = 0.9 * m + 0.1 * g
+    v2 = 0.999 * v + 0.001 * g * g
+    w2 = w - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
+    assert np.allclose(tw.cpu().numpy(), w2, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss_and_learned_setup_is_safe():
+    from paper_1403_1649_amd import learned as Ld
+    train = [P.hetero3d(16, seed=100 + i) for i in range(3)]
+    systems = []
+    for A in train:
+        h = _setup(A)
+        systems.append((h, Ld.solver_errors(h, A, P.exact_solution(A.n, 1))))
+    wd = torch.from_numpy(Ld.init_weights(0)).cuda()
+    before = sum(amg.mlp_loss_grad(h, 0, wd, 8, 999) for h, _ in systems)
+    w = Ld.train(systems, steps=60, lr=3e-3, samples=8)
+    after = sum(amg.mlp_loss_grad(h, 0, torch.from_numpy(w).cuda(), 8, 999) for h, _ in systems)
+    assert after < before
+    A = P.hetero3d(20, seed=2)
+    hl = _setup(A, mlp_weights=w)
+    b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+    x, it, rel = amg.solve(hl, b, 1e-8)
+    assert rel <= 1e-8
+    for k in range(hl.num_levels() - 1):
+        learned, lp, ll = hl.smoother_info(k)
+        assert lp > 0 and ll > 0 and learned == (ll < lp)
+        if learned:
+            ex = hl.export_level(k, what=("A",))
+            S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+            F = amg.mlp_features(hl, k).cpu().numpy().astype(np.float64)
+            want = M.omega(w.astype(np.float64), S, F) / S.diagonal()
+            assert np.allclose(hl.jacobi_weights(k), want, rtol=1e-5)
+
+
+def test_learned_setup_rejects_bad_weights():
+    A = P.hetero3d(10, seed=1)
+    w = _weights()
+    w[5] = np.nan
+    with pytest.raises(amg.AmgError):
+        _setup(A, mlp_weights=w)
