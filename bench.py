@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -67,6 +69,42 @@ def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
     return wall, results, x, (probe_ms, probe[1])
 
 
+def multi_rhs_form(amg, torch, P, reps=2):
+    """C4a: 3-D anisotropic 96^3 (eps_z = 1e-3), 32 right-hand sides.  One
+    mixed-precision setup + one block solve against one plain FP64 setup + 32
+    single solves; MDOF/s counts n * 32."""
+    A = P.aniso3d(96, 1e-3)
+    R = 32
+    Xs = P.multi_exact_solution(A.n, R, 1)
+    Bm = torch.from_numpy(np.ascontiguousarray(P.rhs(A, Xs))).cuda()
+    dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+    best_b, best_s = None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = amg.setup(*dev, amg.Options(dim=3, precision="mixed"))
+        X, its, rels = amg.solve_multi(h, Bm, 1e-8)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        del h
+        t0 = time.perf_counter()
+        h = amg.setup(*dev, amg.Options(dim=3))
+        its_s = []
+        for c in range(R):
+            _, it, rel = amg.solve(h, Bm[:, c].contiguous(), 1e-8)
+            its_s.append(it)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        del h
+        best_b = tb if best_b is None else min(best_b, tb)
+        best_s = ts if best_s is None else min(best_s, ts)
+    ok = bool(np.all(rels <= 1e-8))
+    return {"workload": "C4a 96^3 anisotropic, 32 RHS", "mdof_s": round(A.n * R / best_b / 1e6, 3) if ok else 0.0,
+            "ms": round(best_b * 1e3, 2), "sequential_fp64_ms": round(best_s * 1e3, 2),
+            "speedup_vs_sequential": round(best_s / best_b, 3), "iters_max": int(its.max()),
+            "iters_sequential_max": int(max(its_s)), "relres_max": float(rels.max())}
+
+
 def cpu_baseline(A, dim, b):
     from threadpoolctl import threadpool_limits
 
@@ -90,17 +128,29 @@ def main():
     ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 512 MiB (3 times), the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1403_1649_amd as amg
     from synthetic import problems as P
+
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)   # one elementwise kernel: reads 512 MiB, writes 512 MiB
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
+        return 0
 
     desc, dim = WORKLOADS[args.workload]
     log(f"bench: building {args.workload} ({desc})")
@@ -130,6 +180,10 @@ def main():
                           "setup_ms": round(float(np.median([r[2] for r in res_m])), 3),
                           "solve_ms": round(float(np.median([r[3] for r in res_m])), 3),
                           "x_err_vs_fp64": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
+
+    if not args.no_multi:
+        log("bench: multi-RHS form (C4a)")
+        forms["multi_rhs"] = multi_rhs_form(amg, torch, P)
 
     # level-0 SpMV: events around repeated launches on the current stream
     log("bench: level-0 SpMV")

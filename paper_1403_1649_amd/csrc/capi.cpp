@@ -100,7 +100,8 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
       !(o.kcycle_t >= 0.0) || !(o.jacobi_scale > 0.0) || o.arnoldi_m < 1 || o.arnoldi_m > 5 ||
       o.max_iter < 0 || o.dense_max < 1 || o.dense_max > 8192)
     return fail(AMG_EINVAL, "amg_setup: option out of range");
-  if (o.krylov != AMG_KRYLOV_FCG) return fail(AMG_EUNSUPPORTED, "amg_setup: only flexible CG is built");
+  if (o.krylov != AMG_KRYLOV_FCG && o.krylov != AMG_KRYLOV_FGMRES) return fail(AMG_EINVAL, "amg_setup: krylov");
+  if (o.gmres_restart < 1 || o.gmres_restart > 64) return fail(AMG_EINVAL, "amg_setup: gmres_restart in [1, 64]");
   if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
     return fail(AMG_EINVAL, "amg_setup: unknown precision");
   if (o.smoother != AMG_SMOOTHER_JACOBI && o.smoother != AMG_SMOOTHER_LEARNED)

@@ -134,10 +134,45 @@ __global__ void __launch_bounds__(kGJThreads) k_gauss_jordan(int n, int band, do
   }
 }
 
-// Same elimination with each block's band of columns resident in LDS
-// (column-major: S[j*n + i] = W[i][c0 + j]); only the pivot column crosses
-// blocks, through global memory and the grid barrier.  Dynamic LDS holds the
-// band, the pivot column and the pivot row.
+// One Gauss-Jordan step k applied to a block's LDS band (column-major,
+// S[j*n + i] = W[i][c0 + j]): rows k and p exchanged, then the update with
+// the pre-exchange pivot column `col` (LDS) and the staged pivot row.
+__device__ __forceinline__ void gj_apply(double* S, int n, int c0, int w, int k, int p, const double* col,
+                                         double* s_rowk) {
+  const int tid = threadIdx.x;
+  const double ck = col[p];
+  for (int j = tid; j < w; j += blockDim.x) {
+    double a = S[(size_t)j * n + k];
+    if (p != k) {
+      const double b = S[(size_t)j * n + p];
+      S[(size_t)j * n + p] = a;
+      a = b;
+    }
+    s_rowk[j] = a;
+  }
+  __syncthreads();
+  const double inv = 1.0 / ck;
+  for (int e = tid; e < w * n; e += blockDim.x) {
+    const int j = e / n, i = e - j * n;
+    const int colj = c0 + j;
+    const double ci = (i == k) ? ck : (i == p ? col[k] : col[i]);
+    double* dst = S + (size_t)j * n + i;
+    if (colj == k) {
+      *dst = (i == k) ? inv : -ci * inv;
+    } else if (i == k) {
+      *dst = s_rowk[j] * inv;
+    } else {
+      *dst -= ci * (s_rowk[j] * inv);
+    }
+  }
+  __syncthreads();
+}
+
+// Gauss-Jordan with each block's band of columns resident in LDS.  The owner
+// of a band runs that band's pivot steps on its own (no grid barrier: its
+// columns already hold every earlier step), publishes the pivot rows and the
+// pre-exchange pivot columns, and after one grid barrier the other blocks
+// replay those steps on their bands.  Grid barriers: one per band.
 __global__ void __launch_bounds__(kGJThreads) k_gauss_jordan_lds(int n, int band, double* __restrict__ W,
                                                                  int* __restrict__ piv,
                                                                  double* __restrict__ colbuf, int* sync,
@@ -157,77 +192,53 @@ __global__ void __launch_bounds__(kGJThreads) k_gauss_jordan_lds(int n, int band
     S[j * n + i] = W[(size_t)i * n + c0 + j];
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const int owner = k / band;
-    if ((int)blockIdx.x == owner) {
-      const double* col = S + (size_t)(k - c0) * n;
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + tid; i < n; i += blockDim.x) {
-        const double a = fabs(col[i]);
-        if (a > best) { best = a; bi = i; }
-      }
-      for (int off = kWave / 2; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, kWave);
-        const int oi = __shfl_xor(bi, off, kWave);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if ((tid & (kWave - 1)) == 0) {
-        s_val[tid / kWave] = best;
-        s_idx[tid / kWave] = bi;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        for (int q = 1; q < (int)(blockDim.x / kWave); ++q)
-          if (s_val[q] > best || (s_val[q] == best && s_idx[q] < bi)) { best = s_val[q]; bi = s_idx[q]; }
-        piv[k] = bi;
-        s_p = bi;
-        if (!(best > 0.0)) atomic_or_flag(err, kErrSingular);
-      }
-      if (nb > 1) {
-        double* cb = colbuf + (size_t)(k & 1) * n;
-        for (int i = tid; i < n; i += blockDim.x) cb[i] = col[i];
-      } else {
-        for (int i = tid; i < n; i += blockDim.x) s_col[i] = col[i];
+  for (int pb = 0; pb < nb; ++pb) {
+    const int pc0 = pb * band, pc1 = min(n, pc0 + band);
+    if ((int)blockIdx.x == pb) {
+      for (int k = pc0; k < pc1; ++k) {
+        const double* col = S + (size_t)(k - c0) * n;
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += blockDim.x) {
+          const double a = fabs(col[i]);
+          if (a > best) { best = a; bi = i; }
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, kWave);
+          const int oi = __shfl_xor(bi, off, kWave);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if ((tid & (kWave - 1)) == 0) {
+          s_val[tid / kWave] = best;
+          s_idx[tid / kWave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          for (int q = 1; q < (int)(blockDim.x / kWave); ++q)
+            if (s_val[q] > best || (s_val[q] == best && s_idx[q] < bi)) { best = s_val[q]; bi = s_idx[q]; }
+          piv[k] = bi;
+          s_p = bi;
+          if (!(best > 0.0)) atomic_or_flag(err, kErrSingular);
+        }
+        for (int i = tid; i < n; i += blockDim.x) {
+          s_col[i] = col[i];
+          if (nb > 1) colbuf[(size_t)k * n + i] = col[i];
+        }
+        __syncthreads();
+        gj_apply(S, n, c0, w, k, s_p, s_col, s_rowk);
       }
     }
-    int p;
     if (nb > 1) {
       grid_barrier(sync, nb);
-      p = __hip_atomic_load(&piv[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double* cb = colbuf + (size_t)(k & 1) * n;
-      for (int i = tid; i < n; i += blockDim.x) s_col[i] = cb[i];
-      __syncthreads();
-    } else {
-      __syncthreads();
-      p = s_p;
-    }
-    const double ck = s_col[p];
-    for (int j = tid; j < w; j += blockDim.x) {
-      double a = S[(size_t)j * n + k];
-      if (p != k) {
-        const double b = S[(size_t)j * n + p];
-        S[(size_t)j * n + p] = a;
-        a = b;
-      }
-      s_rowk[j] = a;
-    }
-    __syncthreads();
-    const double inv = 1.0 / ck;
-    for (int e = tid; e < w * n; e += blockDim.x) {
-      const int j = e / n, i = e - j * n;
-      const int colj = c0 + j;
-      const double ci = (i == k) ? ck : (i == p ? s_col[k] : s_col[i]);
-      double* dst = S + (size_t)j * n + i;
-      if (colj == k) {
-        *dst = (i == k) ? inv : -ci * inv;
-      } else if (i == k) {
-        *dst = s_rowk[j] * inv;
-      } else {
-        *dst -= ci * (s_rowk[j] * inv);
+      if ((int)blockIdx.x != pb) {
+        for (int k = pc0; k < pc1; ++k) {
+          const int p = __hip_atomic_load(&piv[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int i = tid; i < n; i += blockDim.x) s_col[i] = colbuf[(size_t)k * n + i];
+          __syncthreads();
+          gj_apply(S, n, c0, w, k, p, s_col, s_rowk);
+        }
       }
     }
-    __syncthreads();
   }
   for (int e = tid; e < w * n; e += blockDim.x) {
     const int i = e / w, j = e - i * w;
@@ -268,7 +279,7 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
   k_dense_zero<<<(int)std::min<size_t>((nn + 255) / 256, 4096), 256, 0, s>>>(nn, work);
   k_dense_scatter<<<(n + 255) / 256, 256, 0, s>>>(n, rp, ci, val, work);
   int* piv = sync + 4;
-  double* colbuf = work + nn;
+  double* colbuf = work + nn;   // 2n doubles (global path) or n*n (LDS path)
   launch_fill_int(4, sync, 0, s);
   // LDS-resident bands when at most 128 blocks hold the matrix, else bands in
   // global memory (at most 64 blocks, band <= 1024 for the LDS pivot row)

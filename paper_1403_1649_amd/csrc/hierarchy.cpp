@@ -519,7 +519,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   if (cl.n > o.dense_max)
     throw Error(AMG_ECOARSEN, "coarsest level has " + std::to_string(cl.n) + " unknowns");
   const size_t nn = (size_t)cl.n * cl.n;
-  double* work = tmp.alloc_n<double>(nn + 2 * (size_t)cl.n);
+  double* work = tmp.alloc_n<double>(2 * nn + 2 * (size_t)cl.n);
   int* gj_sync = tmp.alloc_n<int>(4 + cl.n);
   h.cinv = h.arena.alloc_n<double>(nn);
   if (h.mixed()) h.cinv32 = h.arena.alloc_n<float>(nn);
@@ -533,7 +533,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     AMG_HIP(hipEventCreate(&h.pev[0]));
     AMG_HIP(hipEventCreate(&h.pev[1]));
   }
-  if (!(o.flags & AMG_FLAG_NO_GRAPH)) build_solve_graphs(h);
+  if (!(o.flags & AMG_FLAG_NO_GRAPH) && o.krylov == AMG_KRYLOV_FCG) build_solve_graphs(h);
 }
 
 }  // namespace amg

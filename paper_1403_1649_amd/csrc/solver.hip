@@ -6,6 +6,7 @@
 // memory; the branch "skip the second inner step when ||r~|| <= t ||r||" and
 // the convergence test are device flags read by every kernel of the guarded
 // region, so a whole outer iteration is enqueued without host round-trips.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -72,6 +73,28 @@ struct OpResidSmooth {
   __device__ T x(int j) const { return xt[j]; }
   __device__ void row(int i, T ax, double*) const { xo[i] = xt[i] + wd[i] * (b[i] - ax); }
   __device__ void finalize(const double*) const {}
+};
+
+// the same at level 0 of the outer iteration, with z'q for the FCG beta
+template <typename T>
+struct OpResidSmoothDot {
+  static constexpr int NV = 1;
+  Act a;
+  const T* b;
+  const T* xt;
+  const T* wd;
+  T* xo;
+  const double* q;
+  double* sc;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return xt[j]; }
+  __device__ void row(int i, T ax, double* acc) const {
+    const T z = xt[i] + wd[i] * (b[i] - ax);
+    xo[i] = z;
+    acc[0] += (double)z * q[i];
+  }
+  __device__ void finalize(const double* s) const { sc[kScBeta] = -s[0] / sc[kScPQ]; }
 };
 
 // first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r)
@@ -249,6 +272,7 @@ struct OpFcgUpdate {
   double* sc;
   int* ctl;
   int* err;
+  float* r32;   // mixed precision: the cycle's FP32 right-hand side
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
   __device__ void elem(int i, double* acc) const {
@@ -256,6 +280,7 @@ struct OpFcgUpdate {
     xv[i] += al * p[i];
     const double t = r[i] - al * q[i];
     r[i] = t;
+    if (r32) r32[i] = (float)t;
     acc[0] += t * t;
   }
   __device__ void finalize(const double* s) const {
@@ -551,7 +576,7 @@ void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
 // cycle(k): x_out = M_k b with a zero initial guess (Algorithm 5 on the top
 // kcycle_levels levels, Algorithm 4 below); `act` guards every kernel.
 template <typename T>
-void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
+void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double* fuse_q = nullptr) {
   if (h.L() == 0) {
     coarse_solve<T>(h, b, xo, act);
     return;
@@ -599,9 +624,14 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
   }
   {
     const Level* lp = &lv;
-    const OpResidSmooth<T> op{A, b, xt, wd, xo};
-    probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH,
-                [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+    const bool sel = k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH;
+    if (fuse_q) {
+      const OpResidSmoothDot<T> op{A, b, xt, wd, xo, fuse_q, h.d_sc};
+      probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+    } else {
+      const OpResidSmooth<T> op{A, b, xt, wd, xo};
+      probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+    }
   }
 }
 
@@ -609,15 +639,19 @@ void set_ctl(Hierarchy& h, int word, int value) {
   launch_elem(1, OpSetCtl{h.d_ctl, word, value}, red(h), h.stream);
 }
 
+// z = M r.  fuse_q: compute z'q (the FCG beta) inside the cycle's last
+// kernel; r32_ready: the FP32 copy of r is already written (mixed mode).
+// Returns whether z'q was computed.
 template <typename T>
-void precondition(Hierarchy& h, const int* act) {
+bool precondition(Hierarchy& h, const int* act, const double* fuse_q = nullptr, bool r32_ready = false) {
   hipStream_t s = h.stream;
   if constexpr (sizeof(T) == sizeof(float)) {
-    launch_elem(h.levels[0].n, OpToFloat{Act{act}, h.r, static_cast<float*>(h.bz)}, red(h), s);
-    cycle<float>(h, 0, static_cast<const float*>(h.bz), static_cast<float*>(h.z), act);
+    if (!r32_ready) launch_elem(h.levels[0].n, OpToFloat{Act{act}, h.r, static_cast<float*>(h.bz)}, red(h), s);
+    cycle<float>(h, 0, static_cast<const float*>(h.bz), static_cast<float*>(h.z), act, fuse_q);
   } else {
-    cycle<double>(h, 0, h.r, static_cast<double*>(h.z), act);
+    cycle<double>(h, 0, h.r, static_cast<double*>(h.z), act, fuse_q);
   }
+  return fuse_q != nullptr && h.L() > 0;
 }
 
 template <typename T>
@@ -632,9 +666,10 @@ void fcg_iteration(Hierarchy& h, const int* run) {
     probe_point(h, h.opt.probe == AMG_PROBE_OUTER_SPMV,
                 [=](hipStream_t st) { launch_level<double>(*lp, op, rc, st); });
   }
-  launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.xint, h.r, h.d_sc, h.d_ctl, h.d_err}, rc, s);
-  precondition<T>(h, run);
-  launch_elem(n, OpDotZQ<T>{Act{run}, static_cast<const T*>(h.z), h.q, h.d_sc}, rc, s);
+  float* r32 = sizeof(T) == sizeof(float) ? static_cast<float*>(h.bz) : nullptr;
+  launch_elem(n, OpFcgUpdate{Act{run}, h.p, h.q, h.xint, h.r, h.d_sc, h.d_ctl, h.d_err, r32}, rc, s);
+  if (!precondition<T>(h, run, h.q, r32 != nullptr))
+    launch_elem(n, OpDotZQ<T>{Act{run}, static_cast<const T*>(h.z), h.q, h.d_sc}, rc, s);
   launch_elem(n, OpPUpdate<T>{Act{run}, static_cast<const T*>(h.z), h.p, h.d_sc, 0}, rc, s);
 }
 
@@ -754,6 +789,256 @@ int fcg(Hierarchy& h, const double* b, double rtol, double* x, int* iters, doubl
   AMG_HIP(hipMemcpyAsync(x, h.xint, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   return status;
 }
+// ------------------------------------------------------------ flexible GMRES
+// Right-preconditioned FGMRES(m) (flexible: the preconditioned vectors z_j
+// are kept and x = x_0 + Z y).  Hessenberg entries come from device dots,
+// the Givens rotations, the residual estimate |g_{j+1}| and the triangular
+// solve run in one-thread kernels, so a restart cycle is enqueued without
+// host round-trips.  Device block `gm`: H[(m+1) x m] (row stride m), cs[m],
+// sn[m], g[m+1], y[m], then [bnorm, jdone].
+struct GmView {
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* y;
+  double* misc;   // misc[0] = ||b||, misc[1] = inner steps of this cycle
+  int m;
+};
+
+inline GmView gm_view(double* base, int m) {
+  GmView v;
+  v.m = m;
+  v.H = base;
+  v.cs = v.H + (size_t)(m + 1) * m;
+  v.sn = v.cs + m;
+  v.g = v.sn + m;
+  v.y = v.g + m + 1;
+  v.misc = v.y + m;
+  return v;
+}
+
+// r = b - A x with ||r||^2: starts a cycle (g = [beta, 0, ...]); on the first
+// cycle also records ||b|| (x = 0 there)
+struct OpGmInit {
+  static constexpr int NV = 1;
+  Act a;
+  const double* b;
+  const double* xv;
+  double* r;
+  GmView gv;
+  int first;
+  double rtol;
+  int* ctl;
+  int* err;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ double x(int j) const { return xv[j]; }
+  __device__ void row(int i, double ax, double* acc) const {
+    const double t = b[i] - ax;
+    r[i] = t;
+    acc[0] += t * t;
+  }
+  __device__ void finalize(const double* s) const {
+    const double beta = sqrt(s[0]);
+    if (first) gv.misc[0] = beta;
+    gv.misc[1] = 0.0;
+    gv.g[0] = beta;
+    for (int j = 1; j <= gv.m; ++j) gv.g[j] = 0.0;
+    if (!__builtin_isfinite(beta)) {
+      *err |= kErrNonFinite;
+      ctl[kCtlRunning] = 0;
+    } else {
+      ctl[kCtlRunning] = beta > rtol * gv.misc[0] ? 1 : 0;
+    }
+  }
+};
+
+// w = A z_j (z in the cycle precision) with v_0' w -> H[0][j]
+template <typename T>
+struct OpGmSpmv {
+  static constexpr int NV = 1;
+  Act a;
+  const T* z;
+  const double* v0;
+  double* w;
+  double* hout;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ double x(int j) const { return (double)z[j]; }
+  __device__ void row(int i, double ax, double* acc) const {
+    w[i] = ax;
+    acc[0] += v0[i] * ax;
+  }
+  __device__ void finalize(const double* s) const { *hout = s[0]; }
+};
+
+struct OpGmAxpyDot {
+  static constexpr int NV = 1;
+  Act a;
+  const double* vi;
+  const double* vn;   // nullptr: the norm of w
+  double* w;
+  const double* hcoef;
+  double* out;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double* acc) const {
+    const double t = w[i] - (*hcoef) * vi[i];
+    w[i] = t;
+    acc[0] += (vn ? vn[i] : t) * t;
+  }
+  __device__ void finalize(const double* s) const { *out = vn ? s[0] : sqrt(s[0]); }
+};
+
+struct OpGmScale {
+  static constexpr int NV = 0;
+  Act a;
+  const double* in;
+  double* out;
+  const double* den;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { out[i] = in[i] / *den; }
+  __device__ void finalize(const double*) const {}
+};
+
+// Givens update of column j and the convergence test
+__global__ void k_gm_givens(GmView gv, int j, double rtol, int* ctl, int* err) {
+  if (!ctl[kCtlRunning]) return;
+  const int m = gv.m;
+  double* Hc = gv.H;   // H[i][j] at Hc[i * m + j]
+  for (int i = 0; i < j; ++i) {
+    const double t = gv.cs[i] * Hc[i * m + j] + gv.sn[i] * Hc[(i + 1) * m + j];
+    Hc[(i + 1) * m + j] = -gv.sn[i] * Hc[i * m + j] + gv.cs[i] * Hc[(i + 1) * m + j];
+    Hc[i * m + j] = t;
+  }
+  const double hjj = Hc[j * m + j], hj1 = Hc[(j + 1) * m + j];
+  const double den = hypot(hjj, hj1);
+  ctl[kCtlIters] += 1;
+  gv.misc[1] = j + 1;
+  if (!(den > 0.0) || !__builtin_isfinite(den)) {
+    if (!__builtin_isfinite(den)) *err |= kErrNonFinite;
+    ctl[kCtlRunning] = 0;
+    gv.misc[1] = j;   // nothing usable from this column
+    return;
+  }
+  gv.cs[j] = hjj / den;
+  gv.sn[j] = hj1 / den;
+  Hc[j * m + j] = den;
+  Hc[(j + 1) * m + j] = 0.0;
+  gv.g[j + 1] = -gv.sn[j] * gv.g[j];
+  gv.g[j] = gv.cs[j] * gv.g[j];
+  if (fabs(gv.g[j + 1]) <= rtol * gv.misc[0] || hj1 == 0.0) ctl[kCtlRunning] = 0;
+}
+
+// y = R^-1 g over the inner steps of the cycle (back substitution)
+__global__ void k_gm_trisolve(GmView gv) {
+  const int k = (int)gv.misc[1];
+  const int m = gv.m;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = gv.g[i];
+    for (int q = i + 1; q < k; ++q) t -= gv.H[i * m + q] * gv.y[q];
+    gv.y[i] = t / gv.H[i * m + i];
+  }
+}
+
+// x += Z y
+template <typename T>
+struct OpGmUpdate {
+  static constexpr int NV = 0;
+  const T* Z;
+  size_t ld;
+  GmView gv;
+  double* xv;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    const int k = (int)gv.misc[1];
+    double t = xv[i];
+    for (int j = 0; j < k; ++j) t += gv.y[j] * (double)Z[(size_t)j * ld + i];
+    xv[i] = t;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+template <typename T>
+int fgmres(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
+  Level& l0 = h.levels[0];
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  const int n = l0.n;
+  const int m = std::max(1, std::min(h.opt.gmres_restart, 64));
+  Arena ws;
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+  double* V = ws.alloc_n<double>((size_t)(m + 1) * n);
+  T* Z = ws.alloc_n<T>((size_t)m * n);
+  float* v32 = sizeof(T) == sizeof(float) ? ws.alloc_n<float>(n) : nullptr;
+  double* w = ws.alloc_n<double>(n);
+  double* gmem = ws.alloc_n<double>((size_t)(m + 1) * m + 4 * m + 4);
+  GmView gv = gm_view(gmem, m);
+  const int* run = h.d_ctl + kCtlRunning;
+  const Act A{run};
+  double* xv = h.xint;
+  int* hp = static_cast<int*>(h.h_pinned);
+  double* hd = reinterpret_cast<double*>(hp + 16);
+  launch_fill_double(n, xv, 0.0, s);
+  set_ctl(h, kCtlIters, 0);
+  int status = AMG_OK;
+  bool first = true;
+  int done_before = 0;
+  while (true) {
+    const int steps = std::min(m, h.opt.max_iter - done_before);
+    launch_level<double>(l0, OpGmInit{Act{nullptr}, b, xv, w, gv, first ? 1 : 0, rtol, h.d_ctl, h.d_err}, rc, s);
+    first = false;
+    launch_elem(n, OpGmScale{A, w, V, gv.g}, rc, s);
+    for (int j = 0; j < steps; ++j) {
+      double* vj = V + (size_t)j * n;
+      T* zj = Z + (size_t)j * n;
+      if constexpr (sizeof(T) == sizeof(float)) {
+        launch_elem(n, OpToFloat{A, vj, v32}, rc, s);
+        cycle<float>(h, 0, v32, reinterpret_cast<float*>(zj), run);
+      } else {
+        cycle<double>(h, 0, vj, reinterpret_cast<double*>(zj), run);
+      }
+      launch_level<double>(l0, OpGmSpmv<T>{A, zj, V, w, gv.H + j}, rc, s);
+      for (int i = 0; i <= j; ++i) {
+        const double* vi = V + (size_t)i * n;
+        const double* vn = i < j ? V + (size_t)(i + 1) * n : nullptr;
+        launch_elem(n, OpGmAxpyDot{A, vi, vn, w, gv.H + (size_t)i * m + j, gv.H + (size_t)(i + 1) * m + j}, rc, s);
+      }
+      launch_elem(n, OpGmScale{A, w, V + (size_t)(j + 1) * n, gv.H + (size_t)(j + 1) * m + j}, rc, s);
+      k_gm_givens<<<1, 1, 0, s>>>(gv, j, rtol, h.d_ctl, h.d_err);
+    }
+    k_gm_trisolve<<<1, 1, 0, s>>>(gv);
+    launch_elem(n, OpGmUpdate<T>{Z, (size_t)n, gv, xv}, rc, s);
+    AMG_HIP(hipGetLastError());
+    AMG_HIP(hipMemcpyAsync(hp, h.d_ctl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hp + 2, h.d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipMemcpyAsync(hd, gv.misc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    check_err(h, hp[2]);
+    const int done = hp[kCtlIters];
+    done_before = done;
+    const double bnorm = hd[0];
+    // true residual
+    launch_level<double>(l0, OpTrueResid{Act{nullptr}, b, xv, h.q, h.d_sc}, rc, s);
+    AMG_HIP(hipMemcpyAsync(hd, h.d_sc + kScTrue, sizeof(double), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    const double rel = bnorm > 0.0 ? std::sqrt(hd[0]) / bnorm : 0.0;
+    if (!std::isfinite(rel)) throw Error(AMG_ENANINF, "non-finite residual");
+    *iters = done;
+    *relres = rel;
+    if (rel <= rtol || bnorm == 0.0) break;
+    if (done >= h.opt.max_iter) {
+      status = AMG_ENOTCONV;
+      break;
+    }
+  }
+  AMG_HIP(hipMemcpyAsync(x, xv, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return status;
+}
+
 // ------------------------------------------------------------ autotuner
 struct TuneKey {
   int n, nnz, bytes;
@@ -865,6 +1150,10 @@ void autotune_levels(Hierarchy& h) {
 }
 
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
+  if (h.opt.krylov == AMG_KRYLOV_FGMRES) {
+    if (h.mixed()) return fgmres<float>(h, b, rtol, x, iters, relres);
+    return fgmres<double>(h, b, rtol, x, iters, relres);
+  }
   return fcg(h, b, rtol, x, iters, relres);
 }
 

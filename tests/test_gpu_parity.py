@@ -278,3 +278,35 @@ def test_tuned_and_untuned_kernels_agree():
     xu, it_u, rel_u = amg.solve(hu, b, 1e-8)
     assert rel_t <= 1e-8 and rel_u <= 1e-8 and abs(it_t - it_u) <= 1
     assert float(torch.linalg.norm(xt - xu) / torch.linalg.norm(xu)) < 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fgmres_matches_oracle(precision):
+    A = P.hetero3d(16, seed=12)
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    h, _ = _setup(A, 3, krylov="fgmres", precision=precision)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    H = O.setup(A.row_ptr, A.col, A.val, _oracle_opts(3, krylov="fgmres"))
+    ref = O.solve(H, b, 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1.01e-8
+    assert abs(it - ref.iters) <= (1 if precision == "fp64" else 3), (it, ref.iters)
+
+
+def test_fgmres_nonsymmetric_and_restart():
+    n = 48
+    S = P.poisson2d(n).to_scipy().tolil()
+    for i in range(n * n):
+        if i % n:
+            S[i, i - 1] -= 0.8
+            S[i, i] += 0.8
+    S = S.tocsr()
+    S.sort_indices()
+    A = P.CSR(S.indptr, S.indices, S.data)
+    b = S @ P.exact_solution(A.n, 1)
+    for restart in (30, 4):
+        h, _ = _setup(A, 2, krylov="fgmres", coarse_max=100, gmres_restart=restart)
+        x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+        H = O.setup(A.row_ptr, A.col, A.val, _oracle_opts(2, krylov="fgmres", coarse_max=100, gmres_restart=restart))
+        ref = O.solve(H, b, 1e-8)
+        assert rel <= 1e-8 and abs(it - ref.iters) <= 1, (restart, it, ref.iters)
