@@ -139,6 +139,44 @@ int32_t amg_solve(amg_hierarchy* h, const double* b, double rtol, double* x,
 int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double rtol, double* X,
                         int32_t* iters, double* relres, hipStream_t s);
 
+/* Independent systems in one hierarchy, each set up and solved as if alone
+ * (Algorithm 1 and the solve of Algorithms 4/5 applied per system).  A is
+ * their block-diagonal matrix: system q owns rows and columns
+ * [sys_off[q], sys_off[q+1]) and no entry may couple two systems.  Each
+ * setup kernel runs once over all systems: the node hash of the MIS(2)
+ * priorities takes the row index local to its system; a system stops
+ * coarsening by the rule of Algorithm 1 applied to its own size and
+ * coarsening ratio and is solved there by its own dense inverse; its damped
+ * Jacobi weight (eq. damped_jacobi) comes from its own Arnoldi estimate.
+ * nsys: 1 <= nsys <= n.  sys_off: (host) int32[nsys+1] with sys_off[0] = 0,
+ * sys_off[nsys] = n and every system nonempty.  A: device CSR (copied).
+ * opt: (host) options, NULL for amg_default_options(dim=2); the batch uses
+ * flexible CG and the Jacobi smoother without probe (EUNSUPPORTED otherwise);
+ * flags are ignored.
+ * amg_solve on such a hierarchy runs one outer flexible CG per system with
+ * per-system scalars and stopping test (||b_q - A_q x_q|| <= rtol ||b_q||); it
+ * returns the largest iteration count and relative residual over the systems
+ * and ENOTCONV when any system did not converge; amg_batch_results gives the
+ * per-system values.  amg_solve_multi and the amg_mlp_* calls return
+ * EUNSUPPORTED on a batched hierarchy.
+ * Errors: as amg_setup, and EINVAL when an entry couples two systems.
+ * Synchronises s. */
+int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off, const amg_options* opt,
+                          hipStream_t s, amg_hierarchy** out);
+
+/* Per-system outer iterations and true relative residuals of the last
+ * amg_solve on a batched hierarchy.  iters: (host) int32[nsys] or NULL;
+ * relres: (host) float64[nsys] or NULL.  EINVAL if the hierarchy is not
+ * batched or has not been solved with. */
+int32_t amg_batch_results(const amg_hierarchy* h, int32_t* iters, double* relres);
+
+/* Level k of a batched hierarchy: sys_off (host int32[nsys+1] or NULL)
+ * receives the row range of every system on that level (an empty range once
+ * a finer level was the system's coarsest); omega (host float64[nsys] or NULL)
+ * the system's damped Jacobi weight on that level (0 where the system does
+ * not coarsen from level k).  EINVAL if not batched or k is out of range. */
+int32_t amg_batch_level(const amg_hierarchy* h, int32_t k, int32_t* sys_off, double* omega);
+
 /* ---- Learned per-row Jacobi weights (an extension beyond the paper, which
  * fixes one omega per level by eq. damped_jacobi).  omega_i = sigmoid(y_i) *
  * 2|a_ii| / (|a_ii| + sum_{j!=i} |a_ij|), y = MLP 9->32->32->1 (ReLU) of the row

@@ -22,6 +22,7 @@ from .binding import (  # noqa: F401
     library_path,
     node_hash,
     setup,
+    setup_batched,
     solve,
     solve_multi,
     spmv,

@@ -20,7 +20,8 @@ EXPORTED = [
     "amg_destroy", "amg_num_levels", "amg_level_info", "amg_export_level", "amg_spmv",
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
-    "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi",
+    "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
+    "amg_batch_level",
 ]
 
 
@@ -111,6 +112,12 @@ def lib():
     L.amg_export_jacobi.restype = i32
     L.amg_probe_timing.argtypes = [vp, P(dbl), P(i32)]
     L.amg_probe_timing.restype = i32
+    L.amg_setup_batched.argtypes = [P(AmgCsrC), i32, vp, P(AmgOptionsC), vp, P(vp)]
+    L.amg_setup_batched.restype = i32
+    L.amg_batch_results.argtypes = [vp, vp, vp]
+    L.amg_batch_results.restype = i32
+    L.amg_batch_level.argtypes = [vp, i32, vp, vp]
+    L.amg_batch_level.restype = i32
     _LIB = L
     return L
 
@@ -187,10 +194,11 @@ def _csr(row_ptr, col, val) -> AmgCsrC:
 class Hierarchy:
     """An amg_hierarchy handle (destroyed with the object)."""
 
-    def __init__(self, handle: C.c_void_p, n: int, opts: Options):
+    def __init__(self, handle: C.c_void_p, n: int, opts: Options, nsys: int = 0):
         self._h = handle
         self.n = n
         self.opts = opts
+        self.nsys = nsys
 
     def __del__(self):
         if getattr(self, "_h", None) and _LIB is not None:
@@ -251,6 +259,20 @@ class Hierarchy:
         _check(lib().amg_export_jacobi(self._h, k, _nptr(out)))
         return out
 
+    def batch_results(self):
+        """Per-system (iters[], relres[]) of the last solve of a batched hierarchy."""
+        it = np.zeros(self.nsys, np.int32)
+        rel = np.zeros(self.nsys, np.float64)
+        _check(lib().amg_batch_results(self._h, _nptr(it), _nptr(rel)))
+        return it, rel
+
+    def batch_level(self, k: int):
+        """(sys_off[nsys+1], omega[nsys]) of level k of a batched hierarchy."""
+        off = np.zeros(self.nsys + 1, np.int32)
+        om = np.zeros(self.nsys, np.float64)
+        _check(lib().amg_batch_level(self._h, int(k), _nptr(off), _nptr(om)))
+        return off, om
+
     def probe_timing(self):
         """(average ms, samples) of the kernel selected by the probe option."""
         ms, n = C.c_double(), C.c_int32()
@@ -265,6 +287,18 @@ def setup(row_ptr, col, val, opts: Options | None = None, dim: int = 3) -> Hiera
     h = C.c_void_p()
     _check(lib().amg_setup(C.byref(A), C.byref(opts.c), _stream(), C.byref(h)))
     return Hierarchy(h, A.n, opts)
+
+
+def setup_batched(row_ptr, col, val, sys_off, opts: Options | None = None, dim: int = 2) -> Hierarchy:
+    """amg_setup_batched: independent systems on the block diagonal, system q
+    owning rows [sys_off[q], sys_off[q+1]) (a host int sequence)."""
+    opts = opts or Options(dim)
+    A = _csr(row_ptr, col, val)
+    off = np.ascontiguousarray(sys_off, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().amg_setup_batched(C.byref(A), int(off.size - 1), _nptr(off), C.byref(opts.c), _stream(),
+                                   C.byref(h)))
+    return Hierarchy(h, A.n, opts, nsys=int(off.size - 1))
 
 
 def solve(h: Hierarchy, b, rtol: float = 1e-8, x=None, allow_notconv: bool = False):

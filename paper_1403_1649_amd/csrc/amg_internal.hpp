@@ -38,6 +38,7 @@ enum : int {
   kErrSingular = 32,
   kErrBreakdown = 64,
   kErrBadColumn = 128,
+  kErrCrossSystem = 256,
 };
 
 // ---------------------------------------------------------------- memory
@@ -63,6 +64,8 @@ class Arena {
 };
 
 // ---------------------------------------------------------------- records
+struct TermInfo;
+
 struct Level {
   // A_k (float64, device); val32 is the float32 copy used by the mixed cycle
   int n = 0, nnz = 0;
@@ -106,6 +109,30 @@ struct Level {
   void* rt = nullptr;          // r~
   void* d = nullptr;           // second inner correction
   void* w = nullptr;           // A_{k+1} d
+  // batched systems (block-diagonal A_0): system s owns rows
+  // [sys_off[s], sys_off[s+1]) of this level, an empty range once a finer
+  // level was its coarsest
+  std::vector<int> sys_off;    // host copy
+  int* d_sys_off = nullptr;
+  int* blk = nullptr;          // block table: (system, row0, row1) per block; system -1 pads
+  int nblk = 0;                // table entries (a multiple of 8 above 8)
+  int* blk_sys = nullptr;      // blocks of system s: [blk_sys[s], blk_sys[s+1])
+  int* kv = nullptr;           // per system: the K-cycle applies on this level
+  int kcyc = 0;                // some system takes the K-cycle on this level
+  std::vector<int> term;       // systems whose coarsest level this is
+  TermInfo* d_term = nullptr;
+  int* tblk = nullptr;         // coarse GEMV blocks: (terminal index, first local row)
+  int ntblk = 0;
+  double* tinv = nullptr;      // row-major dense inverses of the terminal systems
+  float* tinv32 = nullptr;
+  std::vector<double> sys_omega, sys_rho;
+};
+
+// A system whose coarsest level is a given level: its rows there and the
+// offset of its dense inverse (n x n, row-major) in the level's inverse block.
+struct TermInfo {
+  int sys, row0, n, pad;
+  long long off;
 };
 
 struct Hierarchy {
@@ -130,8 +157,8 @@ struct Hierarchy {
   double *r = nullptr, *p = nullptr, *q = nullptr;
   void* z = nullptr;           // preconditioned residual (cycle precision)
   void* bz = nullptr;          // cycle right-hand side in cycle precision (mixed mode)
-  double* xint = nullptr;
-  float* mlp_w = nullptr;      // device copy of the learned-weight parameters      // iterate of the outer solve (copied to the caller's x at exit)
+  double* xint = nullptr;      // iterate of the outer solve (copied to the caller's x at exit)
+  float* mlp_w = nullptr;      // device copy of the learned-weight parameters
   // captured launch sequences of one outer iteration (one segment, or two
   // around the probed kernel, which is then launched from the host between
   // them) and of the (re)start
@@ -146,6 +173,16 @@ struct Hierarchy {
   double probe_ms = 0.0;
   int probe_samples = 0;
   float setup_ms = 0.f, solve_ms = 0.f;
+  // batched systems: count (0 = one system), per-system control of the solve
+  // and the results of the last solve
+  int nsys = 0;
+  double* b_sc = nullptr;      // per-system scalar slots [slot][nsys]
+  int* b_fl = nullptr;         // per-system flags [word][nsys]
+  int* b_any = nullptr;        // flags over all systems
+  double* b_part = nullptr;    // block partials (3 per block of the largest table)
+  int* b_again = nullptr;      // systems restarted from their true residual
+  std::vector<int> b_iters;
+  std::vector<double> b_relres;
   bool mixed() const { return opt.precision == AMG_PREC_MIXED; }
   int L() const { return (int)levels.size() - 1; }
   ~Hierarchy();
@@ -173,6 +210,7 @@ enum KSlot : int {
   kKAlpha2 = 6, kKCoefC = 7, kKCoefD = 8,
 };
 constexpr int kMaxPartialBlocks = 2048;
+constexpr int kBlockRowsGemv = 4;   // rows per 256-thread block of a dense GEMV (one wave per row)
 
 // ---------------------------------------------------------------- launchers
 // scan.hip
@@ -189,7 +227,8 @@ void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* stro
                         uint8_t* gmask, int* gdeg, int* cnt, int* err, hipStream_t s);
 void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask,
                        const int* gptr, int* gcol, hipStream_t s);
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s);
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s,
+                     const int* lbase = nullptr);
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1,
                       int* ctl, int round, int lanes, hipStream_t s);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
@@ -240,6 +279,22 @@ double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const
 void mlp_adam(float* w, float* m, float* v, const float* g, int n, int step, float lr, float b1, float b2, float eps,
               hipStream_t s);
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres);
+// batch.hip: independent systems on the block diagonal
+void batch_blocks(Hierarchy& h, Level& lv);
+void batch_local_base(const Level& lv, int* lbase, hipStream_t s);
+void batch_check_blocks(const Level& lv, int* err, hipStream_t s);
+void batch_gather(int m, const int* src, const int* idx, int* dst, hipStream_t s);
+void batch_remap_agg(const Level& lv, const int* cont, const int* shift, int* agg, hipStream_t s);
+void batch_arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, const int* mask, double* Q, double* w,
+                   double* H_out /* host [nsys][64] */);
+void batch_jacobi_weights(const Level& lv, const double* omega_sys, double* wdinv, float* wdinv32,
+                          hipStream_t s);
+void batch_control(Hierarchy& h);
+int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
+// dense.hip: inverses of the terminal systems of a level, one workgroup each
+void launch_dense_inverse_batched(const Level& lv, int nterm, const TermInfo* d_term, const TermInfo* h_term,
+                                  double* work, int* piv, double* inv, float* inv32, int* err, hipStream_t s);
+void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off);
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y);
 void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,

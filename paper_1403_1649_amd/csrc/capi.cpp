@@ -2,6 +2,7 @@
 // host, then the internal runtime; no exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -131,6 +132,72 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
   return AMG_OK;
 }
 
+int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off, const amg_options* opt,
+                          hipStream_t s, amg_hierarchy** out) {
+  if (!out) return fail(AMG_EINVAL, "amg_setup_batched: out is NULL");
+  *out = nullptr;
+  if (!csr_args_ok(A)) return fail(AMG_EINVAL, "amg_setup_batched: bad matrix descriptor");
+  if (nsys < 1 || nsys > A->n || !sys_off) return fail(AMG_EINVAL, "amg_setup_batched: nsys or sys_off");
+  if (sys_off[0] != 0 || sys_off[nsys] != A->n)
+    return fail(AMG_EINVAL, "amg_setup_batched: sys_off must run from 0 to n");
+  for (int32_t q = 0; q < nsys; ++q)
+    if (sys_off[q + 1] <= sys_off[q]) return fail(AMG_EINVAL, "amg_setup_batched: empty or decreasing system");
+  amg_options o;
+  if (opt) o = *opt; else amg_default_options(&o, 2);
+  if (!(o.strength_alpha >= 0.0) || o.coarse_max < 1 || o.max_levels < 1 || o.kcycle_levels < 0 ||
+      o.kcycle_levels > 24 || !(o.kcycle_t >= 0.0) || !(o.jacobi_scale > 0.0) || o.arnoldi_m < 1 ||
+      o.arnoldi_m > 5 || o.max_iter < 0 || o.dense_max < 1 || o.dense_max > 8192)
+    return fail(AMG_EINVAL, "amg_setup_batched: option out of range");
+  if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
+    return fail(AMG_EINVAL, "amg_setup_batched: unknown precision");
+  if (o.krylov != AMG_KRYLOV_FCG) return fail(AMG_EUNSUPPORTED, "amg_setup_batched: batches use flexible CG");
+  if (o.smoother != AMG_SMOOTHER_JACOBI)
+    return fail(AMG_EUNSUPPORTED, "amg_setup_batched: batches use the damped Jacobi smoother");
+  if (o.probe != AMG_PROBE_NONE) return fail(AMG_EUNSUPPORTED, "amg_setup_batched: no kernel probe in batches");
+  auto* H = new (std::nothrow) amg_hierarchy();
+  if (!H) return fail(AMG_ENOMEM, "amg_setup_batched: host allocation");
+  int32_t st = guarded("amg_setup_batched", [&] {
+    amg::Hierarchy& h = H->h;
+    h.opt = o;
+    h.stream = s;
+    h.nsys = nsys;
+    for (auto& e : h.ev) AMG_HIP(hipEventCreate(&e));
+    AMG_HIP(hipEventRecord(h.ev[0], s));
+    amg::init_control(h);
+    amg::build_batch_hierarchy(h, *A, sys_off);
+    AMG_HIP(hipEventRecord(h.ev[1], s));
+    AMG_HIP(hipEventSynchronize(h.ev[1]));
+    AMG_HIP(hipEventElapsedTime(&h.setup_ms, h.ev[0], h.ev[1]));
+  });
+  if (st != AMG_OK) {
+    delete H;
+    return st;
+  }
+  *out = H;
+  return AMG_OK;
+}
+
+int32_t amg_batch_results(const amg_hierarchy* H, int32_t* iters, double* relres) {
+  if (!H || H->h.nsys == 0) return fail(AMG_EINVAL, "amg_batch_results: not a batched hierarchy");
+  if (H->h.b_iters.empty()) return fail(AMG_EINVAL, "amg_batch_results: no solve yet");
+  for (int q = 0; q < H->h.nsys; ++q) {
+    if (iters) iters[q] = H->h.b_iters[q];
+    if (relres) relres[q] = H->h.b_relres[q];
+  }
+  return AMG_OK;
+}
+
+int32_t amg_batch_level(const amg_hierarchy* H, int32_t k, int32_t* sys_off, double* omega) {
+  if (!H || H->h.nsys == 0) return fail(AMG_EINVAL, "amg_batch_level: not a batched hierarchy");
+  if (k < 0 || k >= (int32_t)H->h.levels.size()) return fail(AMG_EINVAL, "amg_batch_level: level");
+  const amg::Level& lv = H->h.levels[k];
+  for (int q = 0; q <= H->h.nsys; ++q)
+    if (sys_off) sys_off[q] = lv.sys_off[q];
+  for (int q = 0; q < H->h.nsys; ++q)
+    if (omega) omega[q] = lv.sys_omega.empty() ? 0.0 : lv.sys_omega[q];
+  return AMG_OK;
+}
+
 int32_t amg_solve(amg_hierarchy* H, const double* b, double rtol, double* x, int32_t* iters, double* relres,
                   hipStream_t s) {
   if (!H || !b || !x || !iters || !relres) return fail(AMG_EINVAL, "amg_solve: NULL argument");
@@ -142,7 +209,17 @@ int32_t amg_solve(amg_hierarchy* H, const double* b, double rtol, double* x, int
     AMG_HIP(hipEventRecord(h.ev[2], s));
     int it = 0;
     double rel = 0.0;
-    status = amg::solve_fcg_impl(h, b, rtol, x, &it, &rel);
+    if (h.nsys > 0) {
+      h.b_iters.assign(h.nsys, 0);
+      h.b_relres.assign(h.nsys, 0.0);
+      status = amg::solve_batch_impl(h, b, rtol, x, h.b_iters.data(), h.b_relres.data());
+      for (int q = 0; q < h.nsys; ++q) {
+        it = std::max(it, h.b_iters[q]);
+        rel = std::max(rel, h.b_relres[q]);
+      }
+    } else {
+      status = amg::solve_fcg_impl(h, b, rtol, x, &it, &rel);
+    }
     AMG_HIP(hipEventRecord(h.ev[3], s));
     AMG_HIP(hipEventSynchronize(h.ev[3]));
     AMG_HIP(hipEventElapsedTime(&h.solve_ms, h.ev[2], h.ev[3]));
@@ -159,6 +236,7 @@ int32_t amg_solve_multi(amg_hierarchy* H, int32_t nrhs, const double* B, double 
   if (!H || !B || !X || !iters || !relres) return fail(AMG_EINVAL, "amg_solve_multi: NULL argument");
   if (nrhs < 1 || nrhs > 64) return fail(AMG_EINVAL, "amg_solve_multi: nrhs must be in [1, 64]");
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(AMG_EINVAL, "amg_solve_multi: rtol must be positive");
+  if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_solve_multi: batched hierarchy");
   int32_t status = AMG_OK;
   int32_t st = guarded("amg_solve_multi", [&] {
     amg::Hierarchy& h = H->h;
@@ -297,6 +375,7 @@ static bool level_ok(const amg_hierarchy* H, int32_t k) {
 
 int32_t amg_mlp_features(const amg_hierarchy* H, int32_t k, float* feats, hipStream_t s) {
   if (!level_ok(H, k) || !feats) return fail(AMG_EINVAL, "amg_mlp_features: bad argument");
+  if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_mlp_features: batched hierarchy");
   return guarded("amg_mlp_features", [&] {
     amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
     hipStream_t keep = h.stream;
@@ -309,6 +388,7 @@ int32_t amg_mlp_features(const amg_hierarchy* H, int32_t k, float* feats, hipStr
 
 int32_t amg_mlp_omega(const amg_hierarchy* H, int32_t k, const float* w, double* omega, hipStream_t s) {
   if (!level_ok(H, k) || !w || !omega) return fail(AMG_EINVAL, "amg_mlp_omega: bad argument");
+  if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_mlp_omega: batched hierarchy");
   return guarded("amg_mlp_omega", [&] {
     amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
     hipStream_t keep = h.stream;
@@ -331,6 +411,7 @@ int32_t amg_mlp_loss_grad(const amg_hierarchy* H, int32_t k, const float* w, int
   if (!level_ok(H, k) || !w || !loss || nsamples < 0 || n_extra < 0 || (n_extra > 0 && !extra) ||
       nsamples + n_extra < 1 || nsamples + n_extra > 64)
     return fail(AMG_EINVAL, "amg_mlp_loss_grad: bad argument");
+  if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_mlp_loss_grad: batched hierarchy");
   return guarded("amg_mlp_loss_grad", [&] {
     amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
     hipStream_t keep = h.stream;

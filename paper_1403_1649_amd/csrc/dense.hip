@@ -12,6 +12,7 @@
 // barrier needs all blocks resident at once: each block is one 1024-thread
 // workgroup (one CU), and the grid never exceeds 128 of the 256 CUs, so later
 // blocks always find room even while other work occupies the device.
+#include <algorithm>
 #include <cmath>
 
 #include "amg_internal.hpp"
@@ -271,6 +272,139 @@ __global__ void k_gj_unpermute(int n, const double* __restrict__ W, const int* _
     if (inv32) inv32[e] = (float)v;
   }
 }
+// Batched systems: one workgroup inverts one terminal system.  Its bands of
+// columns pass through LDS one after another (left-looking): a band first
+// replays the pivot steps already taken (pivot rows in piv, pre-exchange pivot
+// columns in cb), then takes its own steps and publishes them; a second pass
+// replays the later steps on the earlier bands.  Each element sees the same
+// sequence of updates as in k_gauss_jordan_lds, so the inverse is the same.
+__global__ void __launch_bounds__(kGJThreads) k_gj_batched(const TermInfo* __restrict__ ti, double* __restrict__ work,
+                                                           double* __restrict__ cbuf, int* __restrict__ pivbuf,
+                                                           int lds_doubles, int* err) {
+  extern __shared__ double S[];
+  __shared__ double s_val[kGJThreads / kWave];
+  __shared__ int s_idx[kGJThreads / kWave];
+  __shared__ int s_p;
+  const TermInfo t = ti[blockIdx.x];
+  const int n = t.n;
+  double* W = work + t.off;
+  double* cb = cbuf + t.off;
+  int* piv = pivbuf + t.row0;
+  const int band = min(n, (lds_doubles - n) / (n + 1));
+  double* s_col = S + (size_t)band * n;
+  double* s_rowk = s_col + n;
+  const int nb = (n + band - 1) / band;
+  const int tid = threadIdx.x;
+  auto load = [&](int c0, int w) {
+    for (int e = tid; e < w * n; e += blockDim.x) {
+      const int i = e / w, j = e - i * w;
+      S[j * n + i] = W[(size_t)i * n + c0 + j];
+    }
+    __syncthreads();
+  };
+  auto store = [&](int c0, int w) {
+    for (int e = tid; e < w * n; e += blockDim.x) {
+      const int i = e / w, j = e - i * w;
+      W[(size_t)i * n + c0 + j] = S[j * n + i];
+    }
+    __threadfence_block();
+    __syncthreads();
+  };
+  auto replay = [&](int c0, int w, int k) {
+    const int p = piv[k];
+    for (int i = tid; i < n; i += blockDim.x) s_col[i] = cb[(size_t)k * n + i];
+    __syncthreads();
+    gj_apply(S, n, c0, w, k, p, s_col, s_rowk);
+  };
+  for (int pb = 0; pb < nb; ++pb) {
+    const int c0 = pb * band, w = min(n, c0 + band) - c0;
+    load(c0, w);
+    for (int k = 0; k < c0; ++k) replay(c0, w, k);
+    for (int k = c0; k < c0 + w; ++k) {
+      const double* col = S + (size_t)(k - c0) * n;
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < n; i += blockDim.x) {
+        const double a = fabs(col[i]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if ((tid & (kWave - 1)) == 0) {
+        s_val[tid / kWave] = best;
+        s_idx[tid / kWave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int q = 1; q < (int)(blockDim.x / kWave); ++q)
+          if (s_val[q] > best || (s_val[q] == best && s_idx[q] < bi)) { best = s_val[q]; bi = s_idx[q]; }
+        piv[k] = bi;
+        s_p = bi;
+        if (!(best > 0.0)) atomic_or_flag(err, kErrSingular);
+      }
+      for (int i = tid; i < n; i += blockDim.x) {
+        s_col[i] = col[i];
+        cb[(size_t)k * n + i] = col[i];
+      }
+      __threadfence_block();
+      __syncthreads();
+      gj_apply(S, n, c0, w, k, s_p, s_col, s_rowk);
+    }
+    store(c0, w);
+  }
+  for (int pb = 0; pb + 1 < nb; ++pb) {
+    const int c0 = pb * band, w = min(n, c0 + band) - c0;
+    load(c0, w);
+    for (int k = c0 + w; k < n; ++k) replay(c0, w, k);
+    store(c0, w);
+  }
+}
+
+// Undo the row exchanges of each system as column exchanges (last step
+// first); one workgroup per system.
+__global__ void k_gj_unpermute_batched(const TermInfo* __restrict__ ti, const double* __restrict__ work,
+                                       const int* __restrict__ pivbuf, double* __restrict__ inv,
+                                       float* __restrict__ inv32) {
+  extern __shared__ int s_perm[];
+  const TermInfo t = ti[blockIdx.x];
+  const int n = t.n;
+  const int* piv = pivbuf + t.row0;
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < n; ++j) s_perm[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = piv[k];
+      const int q = s_perm[k];
+      s_perm[k] = s_perm[p];
+      s_perm[p] = q;
+    }
+  }
+  __syncthreads();
+  const double* W = work + t.off;
+  const size_t nn = (size_t)n * n;
+  for (size_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = (int)(e / n);
+    const int j = (int)(e - (size_t)i * n);
+    const double v = W[(size_t)i * n + s_perm[j]];
+    inv[t.off + e] = v;
+    if (inv32) inv32[t.off + e] = (float)v;
+  }
+}
+
+// dense copy of each terminal system's diagonal block (columns shifted to the
+// system's first row)
+__global__ void k_dense_scatter_batched(const TermInfo* __restrict__ ti, const int* __restrict__ rp,
+                                        const int* __restrict__ ci, const double* __restrict__ val,
+                                        double* __restrict__ work) {
+  const TermInfo t = ti[blockIdx.x];
+  double* W = work + t.off;
+  for (int r = threadIdx.x; r < t.n; r += blockDim.x) {
+    const int row = t.row0 + r;
+    for (int k = rp[row]; k < rp[row + 1]; ++k) W[(size_t)r * t.n + (ci[k] - t.row0)] = val[k];
+  }
+}
 }  // namespace
 
 void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val, double* work, double* inv,
@@ -309,6 +443,35 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
   k_gauss_jordan<<<nbg, kGJThreads, 0, s>>>(n, bandg, work, piv, colbuf, sync, err);
   const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
   k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
+}
+
+}  // namespace amg
+
+namespace amg {
+
+void launch_dense_inverse_batched(const Level& lv, int nterm, const TermInfo* d_term, const TermInfo* h_term,
+                                  double* work, int* piv, double* inv, float* inv32, int* err, hipStream_t s) {
+  if (nterm == 0) return;
+  size_t total = 0;
+  int nmax = 0;
+  for (int t = 0; t < nterm; ++t) {
+    total += (size_t)h_term[t].n * h_term[t].n;
+    nmax = std::max(nmax, h_term[t].n);
+  }
+  double* cbuf = work + total;   // pre-exchange pivot columns, n x n per system
+  launch_fill_double(total, work, 0.0, s);
+  k_dense_scatter_batched<<<nterm, 256, 0, s>>>(d_term, lv.rp, lv.ci, lv.val, work);
+  int dev = 0, lds_max = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  AMG_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const long budget = (long)lds_max - 4096;   // static LDS of the kernel
+  const long need = (long)nmax * nmax + 2L * nmax;
+  const long lds_d = std::min(need, budget / 8);
+  if ((lds_d - nmax) / (nmax + 1) < 1) throw Error(AMG_ECOARSEN, "coarsest system too large for the LDS band");
+  const size_t bytes = (size_t)lds_d * sizeof(double);
+  AMG_HIP(hipFuncSetAttribute((const void*)k_gj_batched, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  k_gj_batched<<<nterm, kGJThreads, bytes, s>>>(d_term, work, cbuf, piv, (int)lds_d, err);
+  k_gj_unpermute_batched<<<nterm, 256, nmax * sizeof(int), s>>>(d_term, work, piv, inv, inv32);
 }
 
 }  // namespace amg

@@ -196,6 +196,7 @@ struct Sync {
     if (e & kErrCountOverflow) throw Error(AMG_EINVAL, "strong influence count exceeds 2^21");
     if (e & kErrUnassigned) throw Error(AMG_ECOARSEN, "node farther than 2 from every MIS(2) node");
     if (e & kErrSingular) throw Error(AMG_EBREAKDOWN, "coarsest matrix is singular");
+    if (e & kErrCrossSystem) throw Error(AMG_EINVAL, "a matrix entry couples two systems of the batch");
     throw Error(AMG_EHIP, "device error bits " + std::to_string(e));
   }
 };
@@ -534,6 +535,258 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     AMG_HIP(hipEventCreate(&h.pev[1]));
   }
   if (!(o.flags & AMG_FLAG_NO_GRAPH) && o.krylov == AMG_KRYLOV_FCG) build_solve_graphs(h);
+}
+
+
+// ---------------------------------------------------------------- batches
+// Algorithm 1 for independent systems on the block diagonal, each coarsened
+// as if alone: the node hash takes the row index local to the system, each
+// system stops by the rule of Algorithm 1 applied to its own size and
+// coarsening ratio, and its Jacobi weight comes from its own Arnoldi
+// estimate.  A system that stops on level k keeps its rows there (with a zero
+// smoother weight and no aggregate) and is solved by its dense inverse.
+void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
+  hipStream_t s = h.stream;
+  const amg_options& o = h.opt;
+  const int nsys = h.nsys;
+  Sync sy{h};
+  Arena tmp;
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+  h.d_scan = h.arena.alloc_n<int>(scan_blocks_needed(std::max(A.n, A.nnz)) + 2);
+  batch_control(h);   // per-system scalars and block partials, used from the first Arnoldi on
+
+  Level l0;
+  l0.n = A.n;
+  l0.nnz = A.nnz;
+  l0.rp = h.arena.alloc_n<int>(A.n + 1);
+  l0.ci = h.arena.alloc_n<int>(A.nnz);
+  l0.val = h.arena.alloc_n<double>(A.nnz);
+  AMG_HIP(hipMemcpyAsync(l0.rp, A.row_ptr, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+  AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+  AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  sy.fetch(l0.rp, 0, 1);
+  sy.fetch(l0.rp + A.n, 1, 1);
+  sy.wait_and_check();
+  if (sy.hp()[0] != 0 || sy.hp()[1] != A.nnz) throw Error(AMG_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  launch_check_rowptr(l0.n, l0.rp, h.d_err, s);
+  sy.wait_and_check();
+  launch_check_matrix(l0.n, l0.rp, l0.ci, l0.val, h.d_err, s);
+  l0.sys_off.assign(sys_off, sys_off + nsys + 1);
+  batch_blocks(h, l0);
+  batch_check_blocks(l0, h.d_err, s);
+  l0.B = h.arena.alloc_n<double>(A.n);
+  launch_fill_double(A.n, l0.B, 1.0, s);
+  h.levels.push_back(l0);
+  sy.wait_and_check();
+
+  const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  std::vector<int> term_level(nsys, -1);
+  std::vector<int> hroot(nsys + 1), cont(nsys), shift(nsys);
+  std::vector<double> Hs((size_t)64 * nsys), omega(nsys);
+  int* d_sysint = tmp.alloc_n<int>(2 * (size_t)nsys + 1);
+  double* d_omega = tmp.alloc_n<double>(nsys);
+  while (true) {
+    const int k = (int)h.levels.size() - 1;
+    Level& lv = h.levels[k];
+    const int n = lv.n, nnz = lv.nnz;
+    lv.diag = h.arena.alloc_n<double>(n);
+    lv.lpr = pick_lanes_per_row(n, nnz);
+    std::vector<int> present(nsys), size_term(nsys);
+    bool any_cont = false;
+    for (int q = 0; q < nsys; ++q) {
+      const int ns = lv.sys_off[q + 1] - lv.sys_off[q];
+      present[q] = ns > 0;
+      size_term[q] = present[q] && (ns <= o.coarse_max || k + 1 >= o.max_levels);
+      any_cont |= present[q] && !size_term[q];
+    }
+    if (!any_cont) break;
+
+    // strength, strong graph, MIS(2) with per-system priorities
+    lv.strong = h.arena.alloc_n<uint8_t>(nnz);
+    launch_strength(n, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, h.d_err, s);
+    uint8_t* gmask = tmp.alloc_n<uint8_t>(nnz);
+    int* gdeg = tmp.alloc_n<int>(n);
+    int* cnt = tmp.alloc_n<int>(n);
+    launch_graph_count(n, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
+    int* gptr = tmp.alloc_n<int>(n + 1);
+    scan_to_ptr(gdeg, gptr, n, h.d_scan, s);
+    sy.fetch(gptr + n, 0);
+    sy.wait_and_check();
+    const int nnzg = sy.hp()[0];
+    int* gcol = tmp.alloc_n<int>(nnzg > 0 ? nnzg : 1);
+    launch_graph_fill(n, lv.rp, lv.ci, gmask, gptr, gcol, s);
+    int* lbase = tmp.alloc_n<int>(n);
+    batch_local_base(lv, lbase, s);
+    lv.tuple = h.arena.alloc_n<uint64_t>(n);
+    uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, h.d_ctl, h.d_err, s, lbase);
+    int round = 0;
+    int glanes = 1;
+    while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
+    while (true) {
+      for (int b = 0; b < 4; ++b, ++round) launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, s);
+      sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
+      sy.fetch(h.d_ctl + kCtlMisRounds, 1);
+      sy.wait_and_check();
+      if (sy.hp()[0] == 0) break;
+      if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
+    }
+    lv.mis_rounds = sy.hp()[1];
+
+    // roots per system; a system whose coarsening stalls stops here
+    int* flags = tmp.alloc_n<int>(n);
+    int* root_id = tmp.alloc_n<int>(n + 1);
+    launch_root_flags(n, lv.tuple, flags, s);
+    scan_to_ptr(flags, root_id, n, h.d_scan, s);
+    batch_gather(nsys + 1, root_id, lv.d_sys_off, d_sysint, s);
+    AMG_HIP(hipMemcpyAsync(hroot.data(), d_sysint, (nsys + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+    sy.wait_and_check();
+    std::vector<int> next_off(nsys + 1, 0);
+    int nc = 0;
+    bool any_c = false;
+    for (int q = 0; q < nsys; ++q) {
+      const int ns = lv.sys_off[q + 1] - lv.sys_off[q];
+      const int ncs = hroot[q + 1] - hroot[q];
+      const bool stop = present[q] && (size_term[q] || ncs <= 0 || ncs > 0.9 * ns);
+      cont[q] = present[q] && !stop ? 1 : 0;
+      if (stop) {
+        lv.term.push_back(q);
+        term_level[q] = k;
+      }
+      next_off[q] = nc;
+      shift[q] = hroot[q] - nc;
+      if (cont[q]) nc += ncs;
+      any_c |= cont[q] != 0;
+    }
+    next_off[nsys] = nc;
+    if (!any_c) {   // every remaining system stops here: this is the coarsest level
+      lv.term.clear();
+      for (int q = 0; q < nsys; ++q)
+        if (term_level[q] == k) term_level[q] = -1;
+      lv.strong = nullptr;
+      lv.tuple = nullptr;
+      break;
+    }
+    AMG_HIP(hipMemcpyAsync(d_sysint, cont.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(d_sysint + nsys, shift.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
+    int* choice = tmp.alloc_n<int>(n);
+    lv.agg = h.arena.alloc_n<int>(n);
+    launch_aggregate(n, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    batch_remap_agg(lv, d_sysint, d_sysint + nsys, lv.agg, s);
+    lv.nc = nc;
+    lv.agg_ptr = h.arena.alloc_n<int>(nc + 1);
+    lv.agg_rows = h.arena.alloc_n<int>(n);
+    build_segments(h, tmp, n, nc, lv.agg, lv.agg_ptr, lv.agg_rows);
+
+    Level lc;
+    lc.n = nc;
+    lc.B = h.arena.alloc_n<double>(nc);
+    lv.pval = h.arena.alloc_n<double>(n);
+    launch_interp(n, nc, lv.agg, lv.agg_ptr, lv.agg_rows, lv.B, lc.B, lv.pval, s);
+    galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
+                     &lc.val, &lc.nnz);
+
+    // per-system damped Jacobi weight
+    int m = 0;
+    for (int q = 0; q < nsys; ++q)
+      if (cont[q]) m = std::max(m, std::min(o.arnoldi_m, lv.sys_off[q + 1] - lv.sys_off[q]));
+    double* Q = tmp.alloc_n<double>((size_t)(m + 1) * n);
+    double* w = tmp.alloc_n<double>(n);
+    AMG_HIP(hipMemcpyAsync(d_sysint, cont.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
+    batch_arnoldi(h, lv, m, o.seed + 1, d_sysint, Q, w, Hs.data());
+    lv.sys_omega.assign(nsys, 0.0);
+    lv.sys_rho.assign(nsys, 0.0);
+    for (int q = 0; q < nsys; ++q) {
+      omega[q] = 0.0;
+      if (!cont[q]) continue;
+      const double* Hq = Hs.data() + (size_t)q * 64;
+      const int mq = std::min(o.arnoldi_m, lv.sys_off[q + 1] - lv.sys_off[q]);
+      int size = mq;
+      for (int j = 0; j < mq; ++j) {
+        if (Hq[(j + 1) * 8 + j] <= 1e-14 * Hq[48 + j]) { size = j + 1; break; }
+      }
+      double Hsq[64];
+      for (int i = 0; i < size; ++i)
+        for (int j = 0; j < size; ++j) Hsq[i * size + j] = Hq[i * 8 + j];
+      const double rho = hessenberg_spectral_radius(Hsq, size);
+      if (!(rho > 0.0) || !std::isfinite(rho))
+        throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive (system " + std::to_string(q) + ")");
+      lv.sys_rho[q] = rho;
+      omega[q] = lv.sys_omega[q] = o.jacobi_scale / rho;
+    }
+    AMG_HIP(hipMemcpyAsync(d_omega, omega.data(), nsys * sizeof(double), hipMemcpyHostToDevice, s));
+    lv.wdinv = h.arena.alloc_n<double>(n);
+    if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
+    batch_jacobi_weights(lv, d_omega, lv.wdinv, lv.wdinv32, s);
+    sy.wait_and_check();   // pageable host sources above stay valid until here
+    if (debug)
+      std::fprintf(stderr, "amg batch: level %d n=%d nnz=%d mis_rounds=%d nc=%d stop=%zu\n", k, n, nnz,
+                   lv.mis_rounds, nc, lv.term.size());
+    lc.sys_off = next_off;
+    h.levels.push_back(lc);
+    batch_blocks(h, h.levels.back());
+  }
+
+  // the coarsest level: every system present there stops
+  const int L = (int)h.levels.size() - 1;
+  {
+    Level& cl = h.levels[L];
+    for (int q = 0; q < nsys; ++q)
+      if (cl.sys_off[q + 1] > cl.sys_off[q]) {
+        cl.term.push_back(q);
+        term_level[q] = L;
+      }
+  }
+  // dense inverses of the systems stopping on each level
+  for (int k = 0; k <= L; ++k) {
+    Level& lv = h.levels[k];
+    if (lv.term.empty()) continue;
+    std::vector<TermInfo> ti;
+    std::vector<int> tb;
+    long long off = 0;
+    for (size_t t = 0; t < lv.term.size(); ++t) {
+      const int q = lv.term[t];
+      const int ns = lv.sys_off[q + 1] - lv.sys_off[q];
+      if (ns > o.dense_max)
+        throw Error(AMG_ECOARSEN, "system " + std::to_string(q) + " stops with " + std::to_string(ns) + " unknowns");
+      ti.push_back(TermInfo{q, lv.sys_off[q], ns, 0, off});
+      off += (long long)ns * ns;
+      for (int r = 0; r < ns; r += kBlockRowsGemv) {
+        tb.push_back((int)t);
+        tb.push_back(r);
+      }
+    }
+    const int nt = (int)ti.size();
+    lv.d_term = h.arena.alloc_n<TermInfo>(nt);
+    lv.tblk = h.arena.alloc_n<int>(tb.size());
+    lv.ntblk = (int)(tb.size() / 2);
+    lv.tinv = h.arena.alloc_n<double>((size_t)off);
+    if (h.mixed()) lv.tinv32 = h.arena.alloc_n<float>((size_t)off);
+    AMG_HIP(hipMemcpyAsync(lv.d_term, ti.data(), nt * sizeof(TermInfo), hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(lv.tblk, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    Arena work;
+    double* wk = work.alloc_n<double>(2 * (size_t)off);
+    int* piv = work.alloc_n<int>(lv.n);
+    launch_dense_inverse_batched(lv, nt, lv.d_term, ti.data(), wk, piv, lv.tinv, lv.tinv32, h.d_err, s);
+    sy.wait_and_check();
+  }
+  // K-cycle levels: a system takes the K-cycle on level k when its next level
+  // is not its coarsest (as the single-system cycle does)
+  for (int k = 0; k < L && k < o.kcycle_levels; ++k) {
+    Level& lv = h.levels[k];
+    const Level& lc = h.levels[k + 1];
+    std::vector<int> kv(nsys, 0);
+    for (int q = 0; q < nsys; ++q) {
+      kv[q] = (lc.sys_off[q + 1] > lc.sys_off[q] && term_level[q] > k + 1) ? 1 : 0;
+      lv.kcyc |= kv[q];
+    }
+    lv.kv = h.arena.alloc_n<int>(nsys);
+    AMG_HIP(hipMemcpyAsync(lv.kv, kv.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
+    sy.wait_and_check();
+  }
+  if (h.mixed()) make_float_copies(h);
+  alloc_solve_vectors(h);
+  sy.wait_and_check();
 }
 
 }  // namespace amg

@@ -118,8 +118,10 @@ __global__ void k_graph_fill(int n, const int* __restrict__ rp, const int* __res
 // Tuple T_i = (s_i, v_i, i) packed so that integer order is lexicographic
 // order: bits 63..62 = s_i + 1, bits 61..32 = influence count, bits 31..0 =
 // node hash (a bijection of i, so the hash both breaks ties and names i).
+// With lbase (batched systems) the hash takes the index local to the row's
+// system, i - lbase[i], so each system draws the priorities it would alone.
 __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
-                           uint64_t* __restrict__ T, int* ctl, int* err) {
+                           uint64_t* __restrict__ T, int* ctl, int* err, const int* __restrict__ lbase) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     ctl[kCtlMisPing] = n > 0 ? 1 : 0;
@@ -129,7 +131,8 @@ __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
   if (i >= n) return;
   int c = cnt[i];
   if (c >= (1 << 21)) atomic_or_flag(err, kErrCountOverflow);
-  T[i] = (1ull << 62) | ((uint64_t)(c & ((1 << 30) - 1)) << 32) | (uint64_t)node_hash((uint32_t)i, seed);
+  const uint32_t li = (uint32_t)(lbase ? i - lbase[i] : i);
+  T[i] = (1ull << 62) | ((uint64_t)(c & ((1 << 30) - 1)) << 32) | (uint64_t)node_hash(li, seed);
 }
 
 template <int G>
@@ -260,7 +263,7 @@ __global__ void k_agg_round2(int n, const int* __restrict__ gptr, const int* __r
 
 __global__ void k_agg_count(int n, const int* __restrict__ agg, int* counts) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&counts[agg[i]], 1);
+  if (i < n && agg[i] >= 0) atomicAdd(&counts[agg[i]], 1);   // -1: row of a system not coarsened
 }
 
 __global__ void k_agg_scatter(int n, const int* __restrict__ agg, const int* __restrict__ agg_ptr,
@@ -268,6 +271,7 @@ __global__ void k_agg_scatter(int n, const int* __restrict__ agg, const int* __r
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int I = agg[i];
+  if (I < 0) return;
   int pos = atomicAdd(&fill[I], 1);
   agg_rows[agg_ptr[I] + pos] = i;
 }
@@ -326,7 +330,7 @@ __global__ void k_interp_coarse(int nc, const int* __restrict__ agg_ptr, const i
 __global__ void k_interp_fine(int n, const int* __restrict__ agg, const double* __restrict__ B,
                               const double* __restrict__ Bc, double* __restrict__ pval) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) pval[i] = B[i] / Bc[agg[i]];
+  if (i < n) pval[i] = agg[i] >= 0 ? B[i] / Bc[agg[i]] : 0.0;
 }
 
 __global__ void k_node_hash(int n, uint32_t stream, uint32_t* out) {
@@ -425,8 +429,9 @@ void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask
                        int* gcol, hipStream_t s) {
   k_graph_fill<<<grid_for(n), kT, 0, s>>>(n, rp, ci, gmask, gptr, gcol);
 }
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s) {
-  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, ctl, err);
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s,
+                     const int* lbase) {
+  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, ctl, err, lbase);
 }
 template <int G>
 static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,

@@ -76,3 +76,25 @@ def test_argument_validation_without_gpu():
     assert L.amg_node_hash(-1, 0, None, None) == 1
     assert L.amg_level_info(None, 0, None, None, None, None, None) == 1
     assert b"amg_level_info" in L.amg_last_error()
+
+
+def test_batched_setup_validation_without_gpu():
+    L = _lib_or_skip()
+    h = C.c_void_p()
+    dummy = np.zeros(8, np.int64)
+    p = dummy.ctypes.data
+    A = amg.binding.AmgCsrC(10, 28, p, p, p)   # never dereferenced: the checks fail first
+    opts = amg.Options(dim=2)
+    bad_offsets = ([1, 10], [0, 9], [0, 5, 5, 10], [0, 6, 4, 10])
+    for off in bad_offsets:
+        o = np.array(off, np.int32)
+        assert L.amg_setup_batched(C.byref(A), len(off) - 1, o.ctypes.data, C.byref(opts.c), None,
+                                   C.byref(h)) == 1, off
+    o = np.array([0, 4, 10], np.int32)
+    assert L.amg_setup_batched(C.byref(A), 0, o.ctypes.data, C.byref(opts.c), None, C.byref(h)) == 1
+    assert L.amg_setup_batched(C.byref(A), 2, None, C.byref(opts.c), None, C.byref(h)) == 1
+    fg = amg.Options(dim=2, krylov="fgmres")
+    assert L.amg_setup_batched(C.byref(A), 2, o.ctypes.data, C.byref(fg.c), None, C.byref(h)) == 8
+    assert b"flexible CG" in L.amg_last_error()
+    assert L.amg_batch_results(None, None, None) == 1
+    assert L.amg_batch_level(None, 0, None, None) == 1
