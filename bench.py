@@ -43,6 +43,37 @@ def presmooth_bytes(n, nnz, val_bytes=8):
     return (val_bytes + 4) * nnz + 4 * (n + 1) + 4 * val_bytes * n
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "l0_presmooth_c2_traffic.md")
+KERNEL_SOURCES = ["solver.hip", "kernels_common.hpp", "device_utils.hpp", "amg_internal.hpp"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1403_1649_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
+    summary is missing, is for another workload, or the kernel sources have
+    changed since the counters were taken."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("workload") != workload or kv.get("sources_sha256") != kernel_sources_sha256():
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
     rp, ci, v = dev
     bt = torch.from_numpy(b).cuda()
@@ -105,6 +136,55 @@ def multi_rhs_form(amg, torch, P, reps=2):
             "iters_sequential_max": int(max(its_s)), "relres_max": float(rels.max())}
 
 
+def batch_form(amg, torch, P, reps=2):
+    """C4b: 64 2-D 5-point Poisson systems with sides uniform in [64, 512]
+    (seed 3) in one batched hierarchy: mixed-precision batched setup + solve,
+    plain FP64 batched, and 64 sequential single-system FP64 setups + solves.
+    MDOF/s counts the unknowns of all systems."""
+    sides = P.batch_sides()
+    mats = [P.poisson2d(int(s)) for s in sides]
+    Abd, off = P.block_diag(mats)
+    b = P.rhs(Abd, P.exact_solution(Abd.n, 1))
+    bt = torch.from_numpy(b).cuda()
+    x = torch.empty_like(bt)
+    dev = tuple(torch.from_numpy(a).cuda() for a in (Abd.row_ptr, Abd.col, Abd.val))
+    singles = [tuple(torch.from_numpy(a).cuda() for a in (m.row_ptr, m.col, m.val)) for m in mats]
+    out = {"workload": f"C4b {len(mats)} 2-D Poisson systems, sides U[64,512], n={Abd.n}", "n": int(Abd.n)}
+    for name, prec in (("mixed", "mixed"), ("fp64", "fp64")):
+        best, info = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = amg.setup_batched(*dev, off, amg.Options(dim=2, precision=prec))
+            _, it, rel = amg.solve(h, bt, 1e-8, x=x)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            s_ms, v_ms = h.timings()
+            its, rels = h.batch_results()
+            del h
+            if best is None or t < best:
+                best, info = t, (int(its.max()), float(rels.max()), s_ms, v_ms)
+        ok = info[1] <= 1e-8
+        out[name] = {"mdof_s": round(Abd.n / best / 1e6, 3) if ok else 0.0, "ms": round(best * 1e3, 2),
+                     "iters_max": info[0], "relres_max": info[1], "setup_ms": round(info[2], 2),
+                     "solve_ms": round(info[3], 2)}
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q, d in enumerate(singles):
+            h = amg.setup(*d, amg.Options(dim=2))
+            bs = bt[int(off[q]):int(off[q + 1])]
+            amg.solve(h, bs, 1e-8)
+            del h
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        best = t if best is None else min(best, t)
+    out["sequential_fp64"] = {"mdof_s": round(Abd.n / best / 1e6, 3), "ms": round(best * 1e3, 2)}
+    out["speedup_mixed_vs_sequential"] = round(best / (out["mixed"]["ms"] * 1e-3), 3)
+    return out
+
+
 def cpu_baseline(A, dim, b):
     from threadpoolctl import threadpool_limits
 
@@ -129,10 +209,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the roofline kernel's sources and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 512 MiB (3 times), the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_sources_sha256())
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -185,6 +271,10 @@ def main():
         log("bench: multi-RHS form (C4a)")
         forms["multi_rhs"] = multi_rhs_form(amg, torch, P)
 
+    if not args.no_batch:
+        log("bench: batched form (C4b)")
+        forms["batch"] = batch_form(amg, torch, P)
+
     # level-0 SpMV: events around repeated launches on the current stream
     log("bench: level-0 SpMV")
     xv = torch.from_numpy(xs).cuda()
@@ -216,7 +306,7 @@ def main():
     if probe_ms:
         ach = pbytes / (probe_ms * 1e-3) / 1e9
         line["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
                             "kernel": "k_rows<double,8,OpPresmoothResid<double>> (level-0 pre-smoothing + "
                                       "residual, inside the solve)",
                             "bytes_per_launch": pbytes, "avg_us": round(probe_ms * 1e3, 2),

@@ -347,6 +347,7 @@ void init_control(Hierarchy& h) {
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
   launch_fill_int(64, h.d_err, 0, h.stream);
   launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);
+  launch_fill_double(kScWords, h.d_sc, 0.0, h.stream);   // arena memory is recycled, not cleared
   launch_fill_int(64, reinterpret_cast<int*>(h.d_ticket), 0, h.stream);
   launch_fill_int(1, h.d_ctl + kCtlOne, 1, h.stream);
   if (!h.h_pinned) AMG_HIP(hipHostMalloc(&h.h_pinned, 4096, hipHostMallocDefault));
@@ -482,9 +483,10 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     for (int j = 0; j < m; ++j) {
       if (Hh[(j + 1) * 8 + j] <= 1e-14 * wn[j]) { size = j + 1; break; }
     }
+    // upper Hessenberg: the slots below the subdiagonal are never written
     double Hs[64];
     for (int i = 0; i < size; ++i)
-      for (int j = 0; j < size; ++j) Hs[i * size + j] = Hh[i * 8 + j];
+      for (int j = 0; j < size; ++j) Hs[i * size + j] = i <= j + 1 ? Hh[i * 8 + j] : 0.0;
     lv.rho = hessenberg_spectral_radius(Hs, size);
     if (!(lv.rho > 0.0) || !std::isfinite(lv.rho))
       throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive");
@@ -707,7 +709,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
       }
       double Hsq[64];
       for (int i = 0; i < size; ++i)
-        for (int j = 0; j < size; ++j) Hsq[i * size + j] = Hq[i * 8 + j];
+        for (int j = 0; j < size; ++j) Hsq[i * size + j] = i <= j + 1 ? Hq[i * 8 + j] : 0.0;
       const double rho = hessenberg_spectral_radius(Hsq, size);
       if (!(rho > 0.0) || !std::isfinite(rho))
         throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive (system " + std::to_string(q) + ")");

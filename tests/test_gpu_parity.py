@@ -310,3 +310,23 @@ def test_fgmres_nonsymmetric_and_restart():
         H = O.setup(A.row_ptr, A.col, A.val, _oracle_opts(2, krylov="fgmres", coarse_max=100, gmres_restart=restart))
         ref = O.solve(H, b, 1e-8)
         assert rel <= 1e-8 and abs(it - ref.iters) <= 1, (restart, it, ref.iters)
+
+
+def test_omega_independent_of_recycled_device_memory():
+    """Device memory of destroyed hierarchies is recycled without clearing;
+    the Arnoldi estimate must only read what it wrote (regression: the
+    Hessenberg entries below the subdiagonal were read from that memory)."""
+    A0 = P.hetero3d(18, seed=6)
+    rp, ci, v = to_dev(A0)
+    h0 = amg.setup(rp, ci, v, amg.Options(dim=3, precision="mixed"))
+    B = np.ascontiguousarray(P.rhs(A0, P.multi_exact_solution(A0.n, 8, 3)))
+    amg.solve_multi(h0, torch.from_numpy(B).cuda(), 1e-8)
+    del h0
+    A = P.poisson2d(37, 53)
+    h, _ = _setup(A, 2)
+    oo = _oracle_opts(2)
+    for k in range(h.num_levels() - 1):
+        ex = h.export_level(k, what=("A",))
+        S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+        omega, _ = O.jacobi_weight(S, oo.arnoldi_m, oo.seed + 1, oo.jacobi_scale)
+        assert abs(ex["omega"] - omega) <= 1e-12 * omega, (k, ex["omega"], omega)
