@@ -11,8 +11,12 @@ features of row i on level k (9 values, then rounded to bfloat16):
   f7 = (sum_j a_ij) / a_ii
   f8 = k
 MLP 9 -> 32 -> 32 -> 1 with ReLU: bfloat16 weights and inputs (round to
-nearest even), wide accumulation, FP32 biases; hidden activations are rounded
-to bfloat16 before the next layer (straight-through in the backward pass).
+nearest even), FP32 biases; hidden activations are rounded to bfloat16 before
+the next layer (straight-through in the backward pass).  Each pre-activation
+is accumulated in FP32, bias first, then the products in ascending input
+index (a product of two bfloat16 values is exact in FP32, so each step is one
+FP32 rounding): the bfloat16 rounding of a hidden unit is a quantisation, and
+both sides take it from the same FP32 value.
 omega_i = sigmoid(y_i) * 2|a_ii| / (|a_ii| + sum_{j != i} |a_ij|): then
 2 D Omega^-1 - A is strictly diagonally dominant with a positive diagonal, so
 the smoother x += Omega D^-1 (b - A x) converges for SPD A.
@@ -80,17 +84,35 @@ def omega_bound(A: sp.csr_matrix) -> np.ndarray:
     return 2.0 * d / (d + (rowabs - d))
 
 
+def _acc32(bias, X, W):
+    """FP32 accumulation in index order: s = bias, then s += W[:, q] * X[:, q]
+    for q ascending (operands are bfloat16 values, products exact in FP32)."""
+    s = np.broadcast_to(np.asarray(bias, np.float32), (X.shape[0], W.shape[0])).copy()
+    X32, W32 = X.astype(np.float32), W.astype(np.float32)
+    for q in range(X.shape[1]):
+        s = s + X32[:, q:q + 1] * W32[:, q][None, :]
+    return s.astype(np.float64)
+
+
 def forward(w, F, round_bf16=True):
     """Returns y and the intermediates needed by backward."""
     p = unpack(w)
-    r = bf16 if round_bf16 else (lambda x: np.asarray(x, np.float64))
-    X = r(F)
-    W1, W2, W3 = r(p["W1"]), r(p["W2"]), r(p["W3"])
-    z1 = X @ W1.T + p["b1"]
-    h1 = r(np.maximum(z1, 0.0))
-    z2 = h1 @ W2.T + p["b2"]
-    h2 = r(np.maximum(z2, 0.0))
-    y = h2 @ W3 + p["b3"][0]
+    if round_bf16:
+        X = bf16(F)
+        W1, W2, W3 = bf16(p["W1"]), bf16(p["W2"]), bf16(p["W3"])
+        z1 = _acc32(p["b1"], X, W1)
+        h1 = bf16(np.maximum(z1, 0.0))
+        z2 = _acc32(p["b2"], h1, W2)
+        h2 = bf16(np.maximum(z2, 0.0))
+        y = _acc32(p["b3"], h2, W3[None, :])[:, 0]
+    else:
+        X = np.asarray(F, np.float64)
+        W1, W2, W3 = p["W1"], p["W2"], p["W3"]
+        z1 = X @ W1.T + p["b1"]
+        h1 = np.maximum(z1, 0.0)
+        z2 = h1 @ W2.T + p["b2"]
+        h2 = np.maximum(z2, 0.0)
+        y = h2 @ W3 + p["b3"][0]
     return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2, W2=W2, W3=W3)
 
 

@@ -72,3 +72,22 @@ def test_gradient_matches_central_differences():
         fd = (M.loss_and_grad(wp, A, F, E, False)[0] - M.loss_and_grad(wm, A, F, E, False)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g).max()), (k, fd, g[k])
     assert 0.0 < loss < 1.0
+
+
+def test_fp32_accumulation_of_the_forward_pass():
+    """The pre-activations accumulate in FP32 (bias first, ascending index):
+    exact when every partial sum is representable, otherwise within one FP32
+    rounding per step of the FP64 sum."""
+    rng = np.random.default_rng(5)
+    # small integers: products and partial sums exact in FP32 and FP64 alike
+    X = rng.integers(-8, 9, size=(50, M.N_IN)).astype(np.float64)
+    W = rng.integers(-8, 9, size=(M.N_H, M.N_IN)).astype(np.float64)
+    b = rng.integers(-8, 9, size=M.N_H).astype(np.float64)
+    assert np.array_equal(M._acc32(b, X, W), X @ W.T + b)
+    # general bfloat16 operands: bounded by the FP32 rounding of each step
+    X = M.bf16(rng.standard_normal((200, M.N_IN)))
+    W = M.bf16(rng.standard_normal((M.N_H, M.N_IN)))
+    b = rng.standard_normal(M.N_H).astype(np.float32).astype(np.float64)
+    got, want = M._acc32(b, X, W), X @ W.T + b
+    bound = (M.N_IN + 1) * 2.0 ** -24 * (np.abs(X) @ np.abs(W).T + np.abs(b))
+    assert np.all(np.abs(got - want) <= bound)
