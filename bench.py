@@ -74,6 +74,10 @@ def measured_traffic(workload: str):
         return None
 
 
+def kernel_name(fmt: int, lpr: int, op: str) -> str:
+    return f"k_sell<double,{op}>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"
+
+
 def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
     rp, ci, v = dev
     bt = torch.from_numpy(b).cuda()
@@ -93,11 +97,14 @@ def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
             ms, cnt = h.probe_timing()
             probe[0] += ms * cnt
             probe[1] += cnt
+            if opt.get("probe"):
+                probe.append(h.level_format(0, "fp64"))
         del h
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     probe_ms = probe[0] / probe[1] if probe[1] else None
-    return wall, results, x, (probe_ms, probe[1])
+    fmt = probe[2] if len(probe) > 2 else None
+    return wall, results, x, (probe_ms, probe[1], fmt)
 
 
 def multi_rhs_form(amg, torch, P, reps=2):
@@ -247,7 +254,7 @@ def main():
     torch.cuda.synchronize()
 
     log("bench: fp64 setup+solve")
-    wall, res, x, (probe_ms, probe_n) = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup,
+    wall, res, x, (probe_ms, probe_n, probe_fmt) = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup,
                                                  probe="l0_presmooth")
     iters = [r[0] for r in res]
     rels = [r[1] for r in res]
@@ -307,8 +314,9 @@ def main():
         ach = pbytes / (probe_ms * 1e-3) / 1e9
         line["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
-                            "kernel": "k_rows<double,8,OpPresmoothResid<double>> (level-0 pre-smoothing + "
-                                      "residual, inside the solve)",
+                            "kernel": (kernel_name(probe_fmt[0], probe_fmt[1], "OpPresmoothResid<double>")
+                                       if probe_fmt else "level-0 OpPresmoothResid<double>")
+                                      + " (level-0 pre-smoothing + residual, inside the solve)",
                             "bytes_per_launch": pbytes, "avg_us": round(probe_ms * 1e3, 2),
                             "samples": probe_n}
     if not args.no_cpu_baseline:

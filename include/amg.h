@@ -164,6 +164,14 @@ int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double 
 int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off, const amg_options* opt,
                           hipStream_t s, amg_hierarchy** out);
 
+/* SpMV format the autotuner chose for level k in the given arithmetic
+ * (amg_precision: FP64 for the float64 kernels, MIXED for the float32 cycle):
+ * format (host) 0 = CSR with *lanes_per_row lanes per row, 1 = sliced ELL
+ * with 64-row slices; us (host, may be NULL) = its timed duration (0 if the
+ * level was not timed).  EINVAL if k is not a level that runs a cycle. */
+int32_t amg_level_format(const amg_hierarchy* h, int32_t k, int32_t precision, int32_t* format,
+                         int32_t* lanes_per_row, float* us);
+
 /* Per-system outer iterations and true relative residuals of the last
  * amg_solve on a batched hierarchy.  iters: (host) int32[nsys] or NULL;
  * relres: (host) float64[nsys] or NULL.  EINVAL if the hierarchy is not

@@ -21,7 +21,7 @@ EXPORTED = [
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
-    "amg_batch_level",
+    "amg_batch_level", "amg_level_format",
 ]
 
 
@@ -118,6 +118,8 @@ def lib():
     L.amg_batch_results.restype = i32
     L.amg_batch_level.argtypes = [vp, i32, vp, vp]
     L.amg_batch_level.restype = i32
+    L.amg_level_format.argtypes = [vp, i32, i32, P(i32), P(i32), P(C.c_float)]
+    L.amg_level_format.restype = i32
     _LIB = L
     return L
 
@@ -258,6 +260,13 @@ class Hierarchy:
         out = np.empty(self.level_info(k)["n"], np.float64)
         _check(lib().amg_export_jacobi(self._h, k, _nptr(out)))
         return out
+
+    def level_format(self, k: int, precision: str = "fp64"):
+        """(format, lanes_per_row, timed us) the autotuner chose for level k;
+        format 0 = CSR, 1 = sliced ELL."""
+        f, l, us = C.c_int32(), C.c_int32(), C.c_float()
+        _check(lib().amg_level_format(self._h, int(k), _PREC[precision], C.byref(f), C.byref(l), C.byref(us)))
+        return f.value, l.value, us.value
 
     def batch_results(self):
         """Per-system (iters[], relres[]) of the last solve of a batched hierarchy."""

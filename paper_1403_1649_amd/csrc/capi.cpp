@@ -177,6 +177,19 @@ int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off
   return AMG_OK;
 }
 
+int32_t amg_level_format(const amg_hierarchy* H, int32_t k, int32_t precision, int32_t* format,
+                         int32_t* lanes_per_row, float* us) {
+  if (!H || k < 0 || k + 1 >= (int32_t)H->h.levels.size() || !format || !lanes_per_row)
+    return fail(AMG_EINVAL, "amg_level_format: bad argument");
+  if (precision != AMG_PREC_FP64 && precision != AMG_PREC_MIXED) return fail(AMG_EINVAL, "amg_level_format: precision");
+  const amg::Level& lv = H->h.levels[k];
+  const amg::Level::Tune& t = precision == AMG_PREC_FP64 ? lv.t64 : lv.t32;
+  *format = t.fmt;
+  *lanes_per_row = t.lpr;
+  if (us) *us = t.us;
+  return AMG_OK;
+}
+
 int32_t amg_batch_results(const amg_hierarchy* H, int32_t* iters, double* relres) {
   if (!H || H->h.nsys == 0) return fail(AMG_EINVAL, "amg_batch_results: not a batched hierarchy");
   if (H->h.b_iters.empty()) return fail(AMG_EINVAL, "amg_batch_results: no solve yet");
