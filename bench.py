@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched C4b form and print its JSON (for profiling)")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the roofline kernel's sources and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -243,6 +245,10 @@ def main():
             torch.add(src, 0.0, out=dst)   # one elementwise kernel: reads 512 MiB, writes 512 MiB
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 8, "bytes_written": dst.numel() * 8}))
+        return 0
+
+    if args.batch_only:
+        print(json.dumps({"batch": batch_form(amg, torch, P, reps=max(1, args.steps))}), flush=True)
         return 0
 
     desc, dim = WORKLOADS[args.workload]

@@ -39,6 +39,7 @@ enum : int {
   kErrBreakdown = 64,
   kErrBadColumn = 128,
   kErrCrossSystem = 256,
+  kErrNotSPD = 512,
 };
 
 // ---------------------------------------------------------------- memory
@@ -294,6 +295,9 @@ int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int*
 // dense.hip: inverses of the terminal systems of a level, one workgroup each
 void launch_dense_inverse_batched(const Level& lv, int nterm, const TermInfo* d_term, const TermInfo* h_term,
                                   double* work, int* piv, double* inv, float* inv32, int* err, hipStream_t s);
+void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo* h_term, int nrows, const int* rp,
+                              const int* ci, const double* val, double* inv, float* inv32, Arena& tmp, int* err,
+                              hipStream_t s);
 void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off);
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y);
 void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y);

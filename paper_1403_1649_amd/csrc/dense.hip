@@ -14,6 +14,7 @@
 // blocks always find room even while other work occupies the device.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "amg_internal.hpp"
 #include "device_utils.hpp"
@@ -405,6 +406,136 @@ __global__ void k_dense_scatter_batched(const TermInfo* __restrict__ ti, const i
     for (int k = rp[row]; k < rp[row + 1]; ++k) W[(size_t)r * t.n + (ci[k] - t.row0)] = val[k];
   }
 }
+// ---------------------------------------------------------------- SPD, blocked
+// A symmetric positive definite matrix needs no pivoting in Gauss-Jordan
+// elimination: every pivot is a diagonal entry of a Schur complement, hence
+// positive.  Panels of b columns: the panel's b steps run in one workgroup
+// with the panel resident in LDS (no pivot search, so one step is two
+// barriers); every other column then receives the panel's combined
+// elementary transformation M = I + (Y - E) E^T at once, where Y is the panel
+// after its steps and E the unit columns of the panel's pivot rows:
+// A_J <- A_J + (Y - E) T with T = the panel's pivot rows of A_J before the
+// update.  That rank-b update is a tiled product over all columns of all
+// systems; no grid barrier is needed because panel and update are separate
+// launches.  A non-positive or non-finite pivot raises kErrNotSPD and the
+// caller falls back to the pivoting kernels.
+constexpr int kPanelThreads = 1024;
+constexpr int kUpdTile = 64;
+
+__global__ void __launch_bounds__(kPanelThreads) k_gjb_panel(const TermInfo* __restrict__ ti, double* __restrict__ work,
+                                                             double* __restrict__ ybuf, double* __restrict__ tbuf,
+                                                             int K, int b, int* err) {
+  extern __shared__ double P[];   // panel column-major: P[j * n + i]; then colj[n], rowk[b]
+  const TermInfo t = ti[blockIdx.x];
+  const int n = t.n, c0 = K * b;
+  if (c0 >= n) return;
+  const int w = min(b, n - c0);
+  double* W = work + t.off;
+  double* Y = ybuf + (size_t)t.row0 * b;   // n x b, row-major
+  double* T = tbuf + (size_t)t.row0 * b;   // b x n, row-major
+  double* colj = P + (size_t)n * w;
+  double* rowk = colj + n;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * w; e += blockDim.x) {
+    const int i = e / w, j = e - i * w;
+    P[(size_t)j * n + i] = W[(size_t)i * n + c0 + j];
+  }
+  for (int e = tid; e < w * n; e += blockDim.x) {
+    const int j = e / n, J = e - j * n;
+    T[(size_t)j * n + J] = W[(size_t)(c0 + j) * n + J];
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const int k = c0 + j;
+    const double p = P[(size_t)j * n + k];
+    if (tid == 0 && !(p > 0.0 && p < INFINITY)) atomic_or_flag(err, kErrNotSPD);
+    for (int i = tid; i < n; i += blockDim.x) colj[i] = P[(size_t)j * n + i];
+    for (int q = tid; q < w; q += blockDim.x) rowk[q] = P[(size_t)q * n + k];
+    __syncthreads();
+    const double inv = 1.0 / p;
+    for (int e = tid; e < n * w; e += blockDim.x) {
+      const int q = e / n, i = e - q * n;
+      double* dst = P + (size_t)q * n + i;
+      if (q == j) {
+        *dst = (i == k) ? inv : -colj[i] * inv;
+      } else {
+        const double rk = rowk[q] * inv;
+        *dst = (i == k) ? rk : *dst - colj[i] * rk;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * w; e += blockDim.x) {
+    const int i = e / w, j = e - i * w;
+    const double v = P[(size_t)j * n + i];
+    W[(size_t)i * n + c0 + j] = v;
+    Y[(size_t)i * b + j] = v;
+  }
+}
+
+// A_J += (Y - E) T for every column J outside the panel: 64 x 64 output tiles,
+// each thread 4 x 4 outputs; the panel's pivot rows get Y T directly.
+__global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__ ti, const int* __restrict__ tiles,
+                                                    double* __restrict__ work, const double* __restrict__ ybuf,
+                                                    const double* __restrict__ tbuf, int K, int b) {
+  __shared__ double sY[kUpdTile][33];
+  __shared__ double sT[32][kUpdTile + 1];
+  const TermInfo t = ti[tiles[2 * blockIdx.x]];
+  const int n = t.n, c0 = K * b;
+  if (c0 >= n) return;
+  const int w = min(b, n - c0);
+  const int nt = (n + kUpdTile - 1) / kUpdTile;
+  const int tile = tiles[2 * blockIdx.x + 1];
+  const int r0 = (tile / nt) * kUpdTile, q0 = (tile % nt) * kUpdTile;
+  if (q0 >= c0 && q0 + kUpdTile <= c0 + w) return;   // tile entirely inside the panel
+  double* W = work + t.off;
+  const double* Y = ybuf + (size_t)t.row0 * b;
+  const double* T = tbuf + (size_t)t.row0 * b;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kUpdTile * w; e += 256) {
+    const int i = e / w, j = e - i * w;
+    sY[i][j] = (r0 + i < n) ? Y[(size_t)(r0 + i) * b + j] : 0.0;
+  }
+  for (int e = tid; e < w * kUpdTile; e += 256) {
+    const int j = e / kUpdTile, c = e - j * kUpdTile;
+    sT[j][c] = (q0 + c < n) ? T[(size_t)j * n + q0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int ty = tid / 16, tx = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = r0 + ty * 4 + a, J = q0 + tx * 4 + c;
+      const bool pivot_row = i >= c0 && i < c0 + w;
+      acc[a][c] = (i < n && J < n && !pivot_row) ? W[(size_t)i * n + J] : 0.0;
+    }
+  for (int j = 0; j < w; ++j) {
+    double y[4], tv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) y[a] = sY[ty * 4 + a][j];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tv[c] = sT[j][tx * 4 + c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = fma(y[a], tv[c], acc[a][c]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = r0 + ty * 4 + a, J = q0 + tx * 4 + c;
+      if (i < n && J < n && (J < c0 || J >= c0 + w)) W[(size_t)i * n + J] = acc[a][c];
+    }
+}
+
+__global__ void k_dense_to_float(size_t nn, const double* __restrict__ in, float* __restrict__ out) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x)
+    out[e] = (float)in[e];
+}
+
 }  // namespace
 
 void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val, double* work, double* inv,
@@ -472,6 +603,56 @@ void launch_dense_inverse_batched(const Level& lv, int nterm, const TermInfo* d_
   AMG_HIP(hipFuncSetAttribute((const void*)k_gj_batched, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   k_gj_batched<<<nterm, kGJThreads, bytes, s>>>(d_term, work, cbuf, piv, (int)lds_d, err);
   k_gj_unpermute_batched<<<nterm, 256, nmax * sizeof(int), s>>>(d_term, work, piv, inv, inv32);
+}
+
+}  // namespace amg
+
+namespace amg {
+
+// Inverses of symmetric positive definite diagonal blocks (one per TermInfo)
+// in place in inv (row-major n x n at each TermInfo's offset), blocked
+// Gauss-Jordan without pivoting; inv32 (optional) receives the float copy.
+// Raises kErrNotSPD on a non-positive pivot; the caller then redoes the
+// inversion with pivoting.  Scratch from tmp.
+void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo* h_term, int nrows, const int* rp,
+                              const int* ci, const double* val, double* inv, float* inv32, Arena& tmp, int* err,
+                              hipStream_t s) {
+  if (nterm == 0) return;
+  size_t total = 0;
+  int nmax = 0;
+  std::vector<int> tiles;
+  for (int t = 0; t < nterm; ++t) {
+    const int n = h_term[t].n;
+    total += (size_t)n * n;
+    nmax = std::max(nmax, n);
+    const int nt = (n + kUpdTile - 1) / kUpdTile;
+    for (int q = 0; q < nt * nt; ++q) {
+      tiles.push_back(t);
+      tiles.push_back(q);
+    }
+  }
+  int dev = 0, lds_max = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  AMG_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const long lds_d = (long)lds_max / 8 - 16;
+  int b = (int)std::min<long>(32, (lds_d - nmax - 32) / (nmax + 1));
+  if (b < 1) throw Error(AMG_ECOARSEN, "coarsest system too large for the LDS panel");
+  launch_fill_double(total, inv, 0.0, s);
+  k_dense_scatter_batched<<<nterm, 256, 0, s>>>(d_term, rp, ci, val, inv);
+  double* ybuf = tmp.alloc_n<double>((size_t)nrows * b);
+  double* tbuf = tmp.alloc_n<double>((size_t)nrows * b);
+  int* d_tiles = tmp.alloc_n<int>(tiles.size());
+  AMG_HIP(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  const size_t bytes = ((size_t)nmax * b + nmax + b) * sizeof(double);
+  AMG_HIP(hipFuncSetAttribute((const void*)k_gjb_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  const int npanels = (nmax + b - 1) / b;
+  const int ntiles = (int)(tiles.size() / 2);
+  for (int K = 0; K < npanels; ++K) {
+    k_gjb_panel<<<nterm, kPanelThreads, bytes, s>>>(d_term, inv, ybuf, tbuf, K, b, err);
+    k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, tbuf, K, b);
+  }
+  if (inv32) k_dense_to_float<<<(int)std::min<size_t>((total + 255) / 256, 4096), 256, 0, s>>>(total, inv, inv32);
+  AMG_HIP(hipStreamSynchronize(s));   // the host tile table is read before it goes away
 }
 
 }  // namespace amg

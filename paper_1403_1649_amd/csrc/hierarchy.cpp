@@ -199,6 +199,15 @@ struct Sync {
     if (e & kErrCrossSystem) throw Error(AMG_EINVAL, "a matrix entry couples two systems of the batch");
     throw Error(AMG_EHIP, "device error bits " + std::to_string(e));
   }
+  // true (and the bit cleared) when the SPD elimination met a non-positive pivot
+  bool take_not_spd() {
+    AMG_HIP(hipMemcpyAsync(hp() + 62, h.d_err, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    AMG_HIP(hipStreamSynchronize(h.stream));
+    const int e = hp()[62];
+    if (!(e & kErrNotSPD)) return false;
+    launch_fill_int(1, h.d_err, e & ~kErrNotSPD, h.stream);
+    return true;
+  }
 };
 
 void alloc_solve_vectors(Hierarchy& h) {
@@ -526,7 +535,17 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   int* gj_sync = tmp.alloc_n<int>(4 + cl.n);
   h.cinv = h.arena.alloc_n<double>(nn);
   if (h.mixed()) h.cinv32 = h.arena.alloc_n<float>(nn);
-  launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
+  // flexible CG assumes a symmetric positive definite operator: blocked
+  // elimination without pivoting, unless a pivot says otherwise
+  bool inverted = false;
+  if (o.krylov == AMG_KRYLOV_FCG) {
+    const TermInfo t{0, 0, cl.n, 0, 0};
+    TermInfo* dt = tmp.alloc_n<TermInfo>(1);
+    AMG_HIP(hipMemcpyAsync(dt, &t, sizeof(TermInfo), hipMemcpyHostToDevice, s));
+    launch_dense_inverse_spd(1, dt, &t, cl.n, cl.rp, cl.ci, cl.val, h.cinv, h.cinv32, tmp, h.d_err, s);
+    inverted = !sy.take_not_spd();
+  }
+  if (!inverted) launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
   for (int k = 0; k < h.L(); ++k) build_sell(h, tmp, h.levels[k]);
@@ -767,9 +786,13 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     AMG_HIP(hipMemcpyAsync(lv.d_term, ti.data(), nt * sizeof(TermInfo), hipMemcpyHostToDevice, s));
     AMG_HIP(hipMemcpyAsync(lv.tblk, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice, s));
     Arena work;
-    double* wk = work.alloc_n<double>(2 * (size_t)off);
-    int* piv = work.alloc_n<int>(lv.n);
-    launch_dense_inverse_batched(lv, nt, lv.d_term, ti.data(), wk, piv, lv.tinv, lv.tinv32, h.d_err, s);
+    launch_dense_inverse_spd(nt, lv.d_term, ti.data(), lv.n, lv.rp, lv.ci, lv.val, lv.tinv, lv.tinv32, work,
+                             h.d_err, s);
+    if (sy.take_not_spd()) {   // some system is not SPD: eliminate all of them with pivoting
+      double* wk = work.alloc_n<double>(2 * (size_t)off);
+      int* piv = work.alloc_n<int>(lv.n);
+      launch_dense_inverse_batched(lv, nt, lv.d_term, ti.data(), wk, piv, lv.tinv, lv.tinv32, h.d_err, s);
+    }
     sy.wait_and_check();
   }
   // K-cycle levels: a system takes the K-cycle on level k when its next level
