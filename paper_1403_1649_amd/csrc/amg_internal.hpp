@@ -96,6 +96,12 @@ struct Level {
   int* agg_rows = nullptr;     //   agg_rows[agg_ptr[I] .. agg_ptr[I+1]) ascending
   double* pval = nullptr;      // the single nonzero of row i of P_k
   float* pval32 = nullptr;
+  // R_k = P_k^T in CSR: row I = aggregate I, columns agg_rows[agg_ptr[I] ..],
+  // values rval[k] = pval[agg_rows[k]] (nr = rows that belong to an aggregate)
+  double* rval = nullptr;
+  float* rval32 = nullptr;
+  int nr = 0;
+  int rlpr = 8;                // lanes per aggregate of the restriction kernel
   double omega = 0.0, rho = 0.0;
   double* wdinv = nullptr;     // omega / a_ii (or omega_i / a_ii with learned weights)
   int learned = 0;             // learned weights in use on this level
@@ -246,6 +252,7 @@ void launch_to_float(size_t n, const double* in, float* out, hipStream_t s);
 void launch_state_from_tuple(int n, const uint64_t* T, int8_t* state, hipStream_t s);
 void launch_fill_int(size_t n, int* p, int v, hipStream_t s);
 void launch_fill_double(size_t n, double* p, double v, hipStream_t s);
+void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s);
 void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s);
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
                       int* sl_col, double* sl_val, float* sl_val32, hipStream_t s);

@@ -22,6 +22,8 @@ namespace amg {
 
 namespace {
 
+constexpr int kBatchBlocks = 8192;   // target number of blocks per level
+
 // per-system scalar slots: slot q of system s at sc[q * nsys + s]
 enum : int {
   bBB = 0, bRtol2, bAlpha, bBeta, bPQ, bRR, bTrue, bArnNorm, bArn,   // Arnoldi H: bArn + 8 i + j, norms bArn + 48 + j
@@ -104,25 +106,30 @@ __global__ void __launch_bounds__(kBlock) k_belem(const int* __restrict__ blk, i
   if constexpr (Op::NV > 0) write_part<Op::NV>(acc, part, nb, lb);
 }
 
-// per-system totals in block order; masked-off systems get skip()
+// per-system totals: one wave per system (lanes stride over its blocks, then
+// a fixed shuffle tree), so the sum order is fixed; masked-off systems get
+// skip()
+constexpr int kFinThreads = 1024;
+
 template <class Op>
-__global__ void __launch_bounds__(kBlock) k_bfinal(Op op, const double* __restrict__ part, int nb,
-                                                   const int* __restrict__ blk_sys, int nsys) {
+__global__ void __launch_bounds__(kFinThreads) k_bfinal(Op op, const double* __restrict__ part, int nb,
+                                                        const int* __restrict__ blk_sys, int nsys) {
   if (!op.m.active()) return;
   constexpr int NV = Op::NV;
-  for (int s = threadIdx.x; s < nsys; s += kBlock) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int s = wv; s < nsys; s += kFinThreads / kWave) {
     if (!op.m.on(s)) {
-      op.skip(s);
+      if (lane == 0) op.skip(s);
       continue;
     }
     double v[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double t = 0.0;
-      for (int b = blk_sys[s]; b < blk_sys[s + 1]; ++b) t += part[(size_t)k * nb + b];
-      v[k] = t;
+      for (int b = blk_sys[s] + lane; b < blk_sys[s + 1]; b += kWave) t += part[(size_t)k * nb + b];
+      v[k] = wave_sum(t);
     }
-    op.finalize(s, v);
+    if (lane == 0) op.finalize(s, v);
   }
   __syncthreads();
   if (threadIdx.x == 0) op.finalize_all();
@@ -133,19 +140,27 @@ struct BCtx {
   double* part;
 };
 
+// rows of a CSR matrix (rp, ci, av) whose rows are those of the level `tab`
+// (A_k itself, or R_k = P_k^T over the rows of level k+1)
+template <typename T, class Op>
+void brows_on(const Level& tab, int lpr, const int* rp, const int* ci, const T* av, const BCtx& c, const Op& op,
+              hipStream_t s) {
+  if (tab.nblk == 0) return;
+  const int g = tab.nblk;
+  switch (lpr) {
+    case 2: k_brows<T, 2, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+    case 4: k_brows<T, 4, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+    case 8: k_brows<T, 8, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+    case 16: k_brows<T, 16, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+    case 32: k_brows<T, 32, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+    default: k_brows<T, 64, Op><<<g, kBlock, 0, s>>>(tab.blk, g, rp, ci, av, op, c.part); break;
+  }
+  if constexpr (Op::NV > 0) k_bfinal<Op><<<1, kFinThreads, 0, s>>>(op, c.part, g, tab.blk_sys, c.nsys);
+}
+
 template <typename T, class Op>
 void brows(const Level& lv, int lpr, const BCtx& c, const T* av, const Op& op, hipStream_t s) {
-  if (lv.nblk == 0) return;
-  const int g = lv.nblk;
-  switch (lpr) {
-    case 2: k_brows<T, 2, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-    case 4: k_brows<T, 4, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-    case 8: k_brows<T, 8, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-    case 16: k_brows<T, 16, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-    case 32: k_brows<T, 32, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-    default: k_brows<T, 64, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.rp, lv.ci, av, op, c.part); break;
-  }
-  if constexpr (Op::NV > 0) k_bfinal<Op><<<1, kBlock, 0, s>>>(op, c.part, g, lv.blk_sys, c.nsys);
+  brows_on<T>(lv, lpr, lv.rp, lv.ci, av, c, op, s);
 }
 
 template <class Op>
@@ -153,7 +168,7 @@ void belem(const Level& lv, const BCtx& c, const Op& op, hipStream_t s) {
   if (lv.nblk == 0) return;
   const int g = lv.nblk;
   k_belem<Op><<<g, kBlock, 0, s>>>(lv.blk, g, op, c.part);
-  if constexpr (Op::NV > 0) k_bfinal<Op><<<1, kBlock, 0, s>>>(op, c.part, g, lv.blk_sys, c.nsys);
+  if constexpr (Op::NV > 0) k_bfinal<Op><<<1, kFinThreads, 0, s>>>(op, c.part, g, lv.blk_sys, c.nsys);
 }
 
 #define B_NOFIN                                                   \
@@ -322,22 +337,15 @@ struct BResidSmooth {
 };
 
 template <typename T, bool DOT>
-struct BRestrict {
+struct BRestrict {   // rows of R = P^T (aggregates, the rows of the next level)
   static constexpr int NV = DOT ? 1 : 0;
   Mask m;
-  const int* agg_ptr;
-  const int* agg_rows;
-  const T* pval;
   const T* r;
   T* rcv;
   double* K;   // K slots of this level: slot q of system s at K[q * nsys + s]
   int nsys;
-  __device__ void elem(int I, int, double* acc) const {
-    T s = T(0);
-    for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
-      const int i = agg_rows[k];
-      s += pval[i] * r[i];
-    }
+  __device__ T x(int j) const { return r[j]; }
+  __device__ void row(int I, int, T s, double* acc) const {
     rcv[I] = s;
     if (DOT) acc[0] += (double)s * (double)s;
   }
@@ -697,6 +705,9 @@ template <> const float* bwd<float>(const Level& l) { return l.wdinv32; }
 template <typename T> const T* bpv(const Level& l);
 template <> const double* bpv<double>(const Level& l) { return l.pval; }
 template <> const float* bpv<float>(const Level& l) { return l.pval32; }
+template <typename T> const T* brv(const Level& l);
+template <> const double* brv<double>(const Level& l) { return l.rval; }
+template <> const float* brv<float>(const Level& l) { return l.rval32; }
 template <typename T> const T* btinv(const Level& l);
 template <> const double* btinv<double>(const Level& l) { return l.tinv; }
 template <> const float* btinv<float>(const Level& l) { return l.tinv32; }
@@ -730,8 +741,9 @@ void cycle_b(Hierarchy& h, int k, const T* b, T* xo, Mask m) {
   const T* av = bvals<T>(lv);
   Level& lc = h.levels[k + 1];
   brows<T>(lv, lv.lpr, c, av, BPresmoothResid<T>{m, b, wd, xt, r}, s);
+  const T* rv = brv<T>(lv);
   if (!lv.kcyc) {
-    belem(lc, c, BRestrict<T, false>{m, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr, nsys}, s);
+    brows_on<T>(lc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rv, c, BRestrict<T, false>{m, r, rcv, nullptr, nsys}, s);
     cycle_b<T>(h, k + 1, rcv, cc, m);
     belem(lv, c, BProlong<T>{m, lv.agg, pv, cc, xt}, s);
   } else {
@@ -743,7 +755,7 @@ void cycle_b(Hierarchy& h, int k, const T* b, T* xo, Mask m) {
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
     const T* avc = bvals<T>(lc);
-    belem(lc, c, BRestrict<T, true>{m, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K, nsys}, s);
+    brows_on<T>(lc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rv, c, BRestrict<T, true>{m, r, rcv, K, nsys}, s);
     cycle_b<T>(h, k + 1, rcv, cc, m);
     brows<T>(lc, lc.lpr, c, avc, BKDots1<T>{m, cc, rcv, v, K, nsys}, s);
     belem(lc, c, BRtilde<T>{m, rcv, v, rt, K, F, any2, lv.kv, h.opt.kcycle_t, nsys}, s);
@@ -796,12 +808,13 @@ void restart_b(Hierarchy& h) {
 // ---------------------------------------------------------------- setup API
 int batch_max_blocks(int nsys);
 // Block table of a level from its host system offsets: blocks of at most rb
-// rows inside one system, rb a multiple of 256 chosen so that about 2048
-// blocks cover the level.
+// rows inside one system, rb a multiple of 256 chosen so that about 8192
+// blocks cover the level (enough waves in flight to hide the row kernels'
+// dependent loads).
 void batch_blocks(Hierarchy& h, Level& lv) {
   const int nsys = h.nsys;
   const long n = lv.n;
-  int rb = (int)(((n + 2047) / 2048 + 255) / 256 * 256);
+  int rb = (int)(((n + kBatchBlocks - 1) / kBatchBlocks + 255) / 256 * 256);
   if (rb < 256) rb = 256;
   std::vector<int> tab;
   std::vector<int> bs(nsys + 1);
@@ -896,7 +909,7 @@ void batch_arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, const int* m
 
 // Per-system control block and block partials (setup and solve).  A level
 // of n rows has at most n / rb + nsys <= 2048 + nsys blocks before padding.
-int batch_max_blocks(int nsys) { return 2048 + nsys + 8; }
+int batch_max_blocks(int nsys) { return kBatchBlocks + nsys + 8; }
 
 void batch_control(Hierarchy& h) {
   const int nsys = h.nsys;

@@ -453,14 +453,16 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel(const TermInfo* __r
     for (int q = tid; q < w; q += blockDim.x) rowk[q] = P[(size_t)q * n + k];
     __syncthreads();
     const double inv = 1.0 / p;
-    for (int e = tid; e < n * w; e += blockDim.x) {
-      const int q = e / n, i = e - q * n;
-      double* dst = P + (size_t)q * n + i;
-      if (q == j) {
-        *dst = (i == k) ? inv : -colj[i] * inv;
-      } else {
-        const double rk = rowk[q] * inv;
-        *dst = (i == k) ? rk : *dst - colj[i] * rk;
+    for (int i = tid; i < n; i += blockDim.x) {
+      const double c = colj[i];
+      for (int q = 0; q < w; ++q) {
+        double* dst = P + (size_t)q * n + i;
+        if (q == j) {
+          *dst = (i == k) ? inv : -c * inv;
+        } else {
+          const double rk = rowk[q] * inv;
+          *dst = (i == k) ? rk : *dst - c * rk;
+        }
       }
     }
     __syncthreads();

@@ -281,6 +281,8 @@ void make_float_copies(Hierarchy& h) {
     if (k < h.L()) {
       lv.pval32 = h.arena.alloc_n<float>(lv.n);
       launch_to_float(lv.n, lv.pval, lv.pval32, h.stream);
+      lv.rval32 = h.arena.alloc_n<float>(std::max(lv.nr, 1));
+      launch_to_float(lv.nr, lv.rval, lv.rval32, h.stream);
     }
   }
 }
@@ -477,6 +479,10 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     lc.B = h.arena.alloc_n<double>(nc);
     lv.pval = h.arena.alloc_n<double>(n);
     launch_interp(n, nc, lv.agg, lv.agg_ptr, lv.agg_rows, lv.B, lc.B, lv.pval, s);
+    lv.nr = n;
+    lv.rval = h.arena.alloc_n<double>(n);
+    launch_gather_double(n, lv.agg_rows, lv.pval, lv.rval, s);
+    lv.rlpr = pick_lanes_per_row(nc, n);
 
     // Galerkin product (Section 3.1)
     galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
@@ -704,6 +710,12 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     lc.B = h.arena.alloc_n<double>(nc);
     lv.pval = h.arena.alloc_n<double>(n);
     launch_interp(n, nc, lv.agg, lv.agg_ptr, lv.agg_rows, lv.B, lc.B, lv.pval, s);
+    lv.nr = 0;
+    for (int q = 0; q < nsys; ++q)
+      if (cont[q]) lv.nr += lv.sys_off[q + 1] - lv.sys_off[q];
+    lv.rval = h.arena.alloc_n<double>(std::max(lv.nr, 1));
+    launch_gather_double(lv.nr, lv.agg_rows, lv.pval, lv.rval, s);
+    lv.rlpr = pick_lanes_per_row(nc, lv.nr);
     galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
                      &lc.val, &lc.nnz);
 

@@ -394,6 +394,12 @@ __global__ void k_sell_fill(int n, int nslices, const int* __restrict__ rp, cons
   }
 }
 
+__global__ void k_gather_double(int m, const int* __restrict__ idx, const double* __restrict__ src,
+                                double* __restrict__ dst) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) dst[k] = src[idx[k]];
+}
+
 __global__ void k_fill_double(size_t n, double* p, double v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -503,6 +509,9 @@ void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const do
                       int* sl_col, double* sl_val, float* sl_val32, hipStream_t s) {
   k_sell_fill<<<(nslices * kWave + kT - 1) / kT, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, sl_col, sl_val,
                                                              sl_val32);
+}
+void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s) {
+  if (m > 0) k_gather_double<<<grid_for(m), kT, 0, s>>>(m, idx, src, dst);
 }
 void launch_fill_double(size_t n, double* p, double v, hipStream_t s) {
   if (n == 0) return;

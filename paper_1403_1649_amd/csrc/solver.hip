@@ -346,23 +346,16 @@ struct OpCopy {
 
 // restriction r_c = P^T r by aggregate segments (ascending fine index)
 template <typename T, bool DOT>
-struct OpRestrict {
+struct OpRestrict {   // rows of R = P^T (aggregates): r_c = R r, with ||r_c||^2
   static constexpr int NV = DOT ? 1 : 0;
   Act a;
-  const int* agg_ptr;
-  const int* agg_rows;
-  const T* pval;
   const T* r;
   T* rcv;
   double* K;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
-  __device__ void elem(int I, double* acc) const {
-    T s = T(0);
-    for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
-      const int i = agg_rows[k];
-      s += pval[i] * r[i];
-    }
+  __device__ T x(int j) const { return r[j]; }
+  __device__ void row(int I, T s, double* acc) const {
     rcv[I] = s;
     if (DOT) acc[0] += (double)s * (double)s;
   }
@@ -521,6 +514,9 @@ template <> const float* vals<float>(const Level& l) { return l.val32; }
 template <typename T> const T* wdinv(const Level& l);
 template <> const double* wdinv<double>(const Level& l) { return l.wdinv; }
 template <> const float* wdinv<float>(const Level& l) { return l.wdinv32; }
+template <typename T> const T* rvals(const Level& l);
+template <> const double* rvals<double>(const Level& l) { return l.rval; }
+template <> const float* rvals<float>(const Level& l) { return l.rval32; }
 template <typename T> const T* pvals(const Level& l);
 template <> const double* pvals<double>(const Level& l) { return l.pval; }
 template <> const float* pvals<float>(const Level& l) { return l.pval32; }
@@ -601,7 +597,8 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
   }
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
   if (!kcyc) {
-    launch_elem(lv.nc, OpRestrict<T, false>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr}, rc, s);
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T, false>{A, r, rcv, nullptr},
+                   rc, s);
     if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
     else cycle<T>(h, k + 1, rcv, c, act);
     launch_elem(lv.n, OpProlong<T>{A, lv.agg, pv, c, xt}, rc, s);
@@ -614,7 +611,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    launch_elem(lv.nc, OpRestrict<T, true>{A, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K}, rc, s);
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T, true>{A, r, rcv, K}, rc, s);
     cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
     launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);

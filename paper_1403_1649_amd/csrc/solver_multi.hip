@@ -254,23 +254,16 @@ struct MResidSmooth {
 };
 
 template <typename T, bool DOT>
-struct MRestrict {
+struct MRestrict {   // rows of R = P^T (aggregates) times the block
   static constexpr int NV = DOT ? 1 : 0;
   ActAny a;
   int R;
-  const int* agg_ptr;
-  const int* agg_rows;
-  const T* pval;
   const T* r;
   T* rcv;
   double* K;   // per-column K slots of this level (slot * R + c)
   M_COMMON
-  __device__ void elem(int I, int c, double* acc) const {
-    T s = T(0);
-    for (int k = agg_ptr[I]; k < agg_ptr[I + 1]; ++k) {
-      const int i = agg_rows[k];
-      s += pval[i] * r[(size_t)i * R + c];
-    }
+  __device__ T x(int j, int c) const { return r[(size_t)j * R + c]; }
+  __device__ void row(int I, int c, T s, double* acc) const {
     rcv[(size_t)I * R + c] = s;
     if (DOT) acc[0] += (double)s * (double)s;
   }
@@ -651,6 +644,9 @@ template <> const float* wdinv_t<float>(const Level& l) { return l.wdinv32; }
 template <typename T> const T* pvals_t(const Level& l);
 template <> const double* pvals_t<double>(const Level& l) { return l.pval; }
 template <> const float* pvals_t<float>(const Level& l) { return l.pval32; }
+template <typename T> const T* rvals_t(const Level& l);
+template <> const double* rvals_t<double>(const Level& l) { return l.rval; }
+template <> const float* rvals_t<float>(const Level& l) { return l.rval32; }
 template <typename T> const T* cinv_t(const Hierarchy& h);
 template <> const double* cinv_t<double>(const Hierarchy& h) { return h.cinv; }
 template <> const float* cinv_t<float>(const Hierarchy& h) { return h.cinv32; }
@@ -699,7 +695,7 @@ void cycle_m(Hierarchy& h, MWork& W, int k, const T* b, T* xo, const int* act) {
   rows_m<T>(lv.n, m, lv.rp, lv.ci, vals_t<T>(lv), MPresmoothResid<T>{A, R, b, wd, xt, r}, s);
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
   if (!kcyc) {
-    elem_m(lv.nc, m, MRestrict<T, false>{A, R, lv.agg_ptr, lv.agg_rows, pv, r, rcv, nullptr}, s);
+    rows_m<T>(lv.nc, m, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, false>{A, R, r, rcv, nullptr}, s);
     if (k + 1 == L) coarse_m<T>(h, m, rcv, c, act);
     else cycle_m<T>(h, W, k + 1, rcv, c, act);
     elem_m(lv.n, m, MProlong<T>{A, R, lv.agg, pv, c, xt}, s);
@@ -713,7 +709,7 @@ void cycle_m(Hierarchy& h, MWork& W, int k, const T* b, T* xo, const int* act) {
     T* d = static_cast<T*>(ml.d);
     T* w = static_cast<T*>(ml.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    elem_m(lv.nc, m, MRestrict<T, true>{A, R, lv.agg_ptr, lv.agg_rows, pv, r, rcv, K}, s);
+    rows_m<T>(lv.nc, m, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, true>{A, R, r, rcv, K}, s);
     cycle_m<T>(h, W, k + 1, rcv, c, act);
     rows_m<T>(lc.n, m, lc.rp, lc.ci, vals_t<T>(lc), MKDots1<T>{A, R, c, rcv, v, K, gm}, s);
     elem_m(lc.n, m, MRtilde<T>{A, R, rcv, v, rt, K, F, any2, h.opt.kcycle_t}, s);
