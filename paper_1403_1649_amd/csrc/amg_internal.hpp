@@ -234,10 +234,11 @@ void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* stro
                         uint8_t* gmask, int* gdeg, int* cnt, int* err, hipStream_t s);
 void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask,
                        const int* gptr, int* gcol, hipStream_t s);
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s,
-                     const int* lbase = nullptr);
-void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1,
-                      int* ctl, int round, int lanes, hipStream_t s);
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* ctl, int* err,
+                     hipStream_t s, const int* lbase = nullptr);
+// one MIS(2) round (two sweeps and the undecided flag); block_flag: 2048 ints
+void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,
+                      int lanes, int* block_flag, hipStream_t s);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
 void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T,
                       const int* root_id, int* choice, int* agg, int* err, hipStream_t s);

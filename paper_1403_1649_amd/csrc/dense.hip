@@ -453,15 +453,34 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel(const TermInfo* __r
     for (int q = tid; q < w; q += blockDim.x) rowk[q] = P[(size_t)q * n + k];
     __syncthreads();
     const double inv = 1.0 / p;
-    for (int i = tid; i < n; i += blockDim.x) {
+    // G groups of threads share the rows, group g taking columns g, g+G, ...
+    // (independent LDS updates, unrolled so that they overlap)
+    const int G = max(1, min(w, (int)blockDim.x / n));
+    const int g = tid / n, i = tid - g * n;
+    if (g < G) {
       const double c = colj[i];
-      for (int q = 0; q < w; ++q) {
+#pragma unroll 4
+      for (int q = g; q < w; q += G) {
         double* dst = P + (size_t)q * n + i;
         if (q == j) {
           *dst = (i == k) ? inv : -c * inv;
         } else {
           const double rk = rowk[q] * inv;
           *dst = (i == k) ? rk : *dst - c * rk;
+        }
+      }
+    }
+    if (n > (int)blockDim.x) {   // rows beyond one thread each (n > 1024)
+      for (int r = tid + blockDim.x; r < n; r += blockDim.x) {
+        const double c = colj[r];
+        for (int q = 0; q < w; ++q) {
+          double* dst = P + (size_t)q * n + r;
+          if (q == j) {
+            *dst = (r == k) ? inv : -c * inv;
+          } else {
+            const double rk = rowk[q] * inv;
+            *dst = (r == k) ? rk : *dst - c * rk;
+          }
         }
       }
     }

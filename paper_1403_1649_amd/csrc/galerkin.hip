@@ -37,6 +37,8 @@ __global__ void __launch_bounds__(NT) k_galerkin_stage(
   __shared__ int ukeys[CAP];
   __shared__ int tmp[NT / kWave + 1];
   __shared__ int s_cnt;
+  __shared__ int m_start[NT], m_off[NT + 1];   // staging: member rows of one step
+  __shared__ double m_pi[FILL ? NT : 1];
   const int tid = threadIdx.x;
   const int count = LISTED ? *in_count : nc;
   for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
@@ -57,25 +59,34 @@ __global__ void __launch_bounds__(NT) k_galerkin_stage(
     }
     for (int q = tid; q < HS; q += NT) { hkey[q] = -1; hfirst[q] = INT_MAX; }
     if (tid == 0) s_cnt = 0;
-    // stage the terms in segment order (row by row, entries in column order)
+    // stage the terms in segment order (row by row, entries in column order);
+    // lanes take terms, not rows, so the gathers of a step are independent
     int off = 0;
     for (int base = sb; base < se; base += NT) {
       const int k = base + tid;
-      int i = -1, len = 0;
-      if (k < se) { i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
+      int i = -1, len = 0, start = 0;
+      if (k < se) { i = agg_rows[k]; start = rp[i]; len = rp[i + 1] - start; }
       int tot;
-      int pos = off + block_exclusive_scan(len, tmp, &tot);
-      if (i >= 0) {
-        const double pi = FILL ? pval[i] : 0.0;
-        for (int e = rp[i]; e < rp[i + 1]; ++e, ++pos) {
-          const int j = ci[e];
-          keys[pos] = agg[j];
-          if (FILL) vals[pos] = __dmul_rn(__dmul_rn(pi, val[e]), pval[j]);
+      const int pos = block_exclusive_scan(len, tmp, &tot);
+      m_start[tid] = start;
+      m_off[tid] = pos;
+      if (FILL) m_pi[tid] = i >= 0 ? pval[i] : 0.0;
+      if (tid == 0) m_off[NT] = tot;
+      __syncthreads();
+      for (int t = tid; t < tot; t += NT) {
+        int lo = 0, hi = NT;   // member m with m_off[m] <= t < m_off[m + 1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (m_off[mid] <= t) lo = mid; else hi = mid;
         }
+        const int e = m_start[lo] + (t - m_off[lo]);
+        const int j = ci[e];
+        keys[off + t] = agg[j];
+        if (FILL) vals[off + t] = __dmul_rn(__dmul_rn(m_pi[lo], val[e]), pval[j]);
       }
       off += tot;
+      __syncthreads();
     }
-    __syncthreads();
     for (int t = tid; t < T; t += NT) {
       const int J = keys[t];
       int q = (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - HB));

@@ -434,14 +434,15 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     // MIS(2) rounds (Algorithm 2)
     lv.tuple = h.arena.alloc_n<uint64_t>(n);
     uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
-    launch_mis_init(n, cnt, o.seed, lv.tuple, h.d_ctl, h.d_err, s);
+    int* mis_flags = tmp.alloc_n<int>(2048);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_ctl, h.d_err, s);
     int round = 0;
     const int batch = 4;
     int glanes = 1;
     while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
     while (true) {
       for (int b = 0; b < batch; ++b, ++round)
-        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, s);
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, mis_flags, s);
       sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
       sy.fetch(h.d_ctl + kCtlMisRounds, 1);
       sy.wait_and_check();
@@ -646,12 +647,14 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     batch_local_base(lv, lbase, s);
     lv.tuple = h.arena.alloc_n<uint64_t>(n);
     uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
-    launch_mis_init(n, cnt, o.seed, lv.tuple, h.d_ctl, h.d_err, s, lbase);
+    int* mis_flags = tmp.alloc_n<int>(2048);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_ctl, h.d_err, s, lbase);
     int round = 0;
     int glanes = 1;
     while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
     while (true) {
-      for (int b = 0; b < 4; ++b, ++round) launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, s);
+      for (int b = 0; b < 4; ++b, ++round)
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, mis_flags, s);
       sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
       sy.fetch(h.d_ctl + kCtlMisRounds, 1);
       sy.wait_and_check();

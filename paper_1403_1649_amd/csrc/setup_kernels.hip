@@ -121,7 +121,8 @@ __global__ void k_graph_fill(int n, const int* __restrict__ rp, const int* __res
 // With lbase (batched systems) the hash takes the index local to the row's
 // system, i - lbase[i], so each system draws the priorities it would alone.
 __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
-                           uint64_t* __restrict__ T, int* ctl, int* err, const int* __restrict__ lbase) {
+                           uint64_t* __restrict__ T, uint64_t* __restrict__ M1, int* ctl, int* err,
+                           const int* __restrict__ lbase) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     ctl[kCtlMisPing] = n > 0 ? 1 : 0;
@@ -133,6 +134,7 @@ __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
   if (c >= (1 << 21)) atomic_or_flag(err, kErrCountOverflow);
   const uint32_t li = (uint32_t)(lbase ? i - lbase[i] : i);
   T[i] = (1ull << 62) | ((uint64_t)(c & ((1 << 30) - 1)) << 32) | (uint64_t)node_hash(li, seed);
+  M1[i] = 0;
 }
 
 template <int G>
@@ -145,70 +147,103 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
   return v;
 }
 
+// Node groups of one MIS(2) sweep: grid of at most kMisBlocks blocks (a
+// multiple of 8), each taking a contiguous run of node groups, so per-block
+// flags stay few and no flag is written by more than one block.
+constexpr int kMisBlocks = 2048;
+
 // First max sweep of a round: M1_i = max(T_i, max_{j in N_i} T_j), G lanes per
-// node.  Thread 0 clears the flag the round's second sweep raises, also when
-// the round has nothing left to do, so a finished MIS keeps reading zero.
+// node.  A node whose M1 already holds an MIS tuple keeps it: two MIS(2) nodes
+// never share a closed neighbourhood, so that maximum cannot change again.
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol,
                                                     const uint64_t* __restrict__ T,
-                                                    uint64_t* __restrict__ M1, int* ctl, int round) {
-  const int undecided = ctl[kCtlMisPing + (round & 1)];   // written by an earlier kernel
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0) {
-    ctl[kCtlMisPing + ((round + 1) & 1)] = 0;
-    if (undecided) ctl[kCtlMisRounds] += 1;
-  }
-  if (undecided == 0) return;
-  const int i = gid / G, lane = gid & (G - 1);
-  uint64_t t = 0;
-  if (i < n) {
-    if (lane == 0) t = T[i];
-    for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
-      uint64_t u = T[gcol[k]];
-      t = u > t ? u : t;
+                                                    uint64_t* __restrict__ M1, const int* ctl, int round) {
+  if (ctl[kCtlMisPing + (round & 1)] == 0) return;   // nothing undecided
+  constexpr int NPB = 256 / G;                       // nodes per block step
+  const int lane = threadIdx.x & (G - 1);
+  const int groups = (n + NPB - 1) / NPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = blockIdx.x * per, g1 = min(groups, g0 + per);
+  for (int g = g0; g < g1; ++g) {
+    const int i = g * NPB + threadIdx.x / G;
+    uint64_t t = 0;
+    bool work = false;
+    if (i < n) {
+      const uint64_t prev = M1[i];
+      work = tstate(prev) != 2;
+      if (work) {
+        if (lane == 0) t = T[i];
+        for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
+          uint64_t u = T[gcol[k]];
+          t = u > t ? u : t;
+        }
+      }
     }
+    t = group_max_u64<G>(t);
+    if (work && lane == 0) M1[i] = t;
   }
-  t = group_max_u64<G>(t);
-  if (i < n && lane == 0) M1[i] = t;
 }
 
 // Second sweep plus the state update (undecided nodes only): a node whose
 // distance-2 max is its own tuple joins the MIS; one that sees an MIS tuple
-// leaves.  Any node left undecided raises the round's flag (set once).
+// leaves.  Each block records whether it left a node undecided.
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol, uint64_t* __restrict__ T,
-                                                    const uint64_t* __restrict__ M1, int* ctl, int round) {
+                                                    const uint64_t* __restrict__ M1, const int* ctl, int round,
+                                                    int* __restrict__ block_flag) {
   if (ctl[kCtlMisPing + (round & 1)] == 0) return;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / G, lane = gid & (G - 1);
-  uint64_t own = 0, t = 0;
-  if (i < n) {
-    own = T[i];
-    if (tstate(own) == 1) {
-      if (lane == 0) t = M1[i];
-      for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
-        uint64_t u = M1[gcol[k]];
-        t = u > t ? u : t;
+  constexpr int NPB = 256 / G;
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & (G - 1);
+  const int groups = (n + NPB - 1) / NPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = blockIdx.x * per, g1 = min(groups, g0 + per);
+  int undecided = 0;
+  for (int g = g0; g < g1; ++g) {
+    const int i = g * NPB + threadIdx.x / G;
+    uint64_t own = 0, t = 0;
+    if (i < n) {
+      own = T[i];
+      if (tstate(own) == 1) {
+        if (lane == 0) t = M1[i];
+        for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
+          uint64_t u = M1[gcol[k]];
+          t = u > t ? u : t;
+        }
+      }
+    }
+    t = group_max_u64<G>(t);
+    if (i < n && lane == 0 && tstate(own) == 1) {
+      if (t == own) {
+        T[i] = (own & kLow62) | (2ull << 62);
+      } else if (tstate(t) == 2) {
+        T[i] = own & kLow62;
+      } else {
+        undecided = 1;
       }
     }
   }
-  t = group_max_u64<G>(t);
-  int undecided = 0;
-  if (i < n && lane == 0 && tstate(own) == 1) {
-    if (t == own) {
-      T[i] = (own & kLow62) | (2ull << 62);
-    } else if (tstate(t) == 2) {
-      T[i] = own & kLow62;
-    } else {
-      undecided = 1;
-    }
-  }
-  if (__ballot(undecided) && (threadIdx.x & (kWave - 1)) == 0) {
-    int* flag = &ctl[kCtlMisPing + ((round + 1) & 1)];
-    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-      __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (undecided) s_any = 1;   // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0) block_flag[blockIdx.x] = s_any;
+}
+
+// End of a round: OR of the block flags into the next round's "undecided"
+// word, and the count of rounds that found undecided nodes.
+__global__ void __launch_bounds__(256) k_mis_ping(int nb, const int* __restrict__ block_flag, int* ctl, int round) {
+  const int cur = ctl[kCtlMisPing + (round & 1)];
+  int any = 0;
+  if (cur)
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) any |= block_flag[b];
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) {
+    ctl[kCtlMisPing + ((round + 1) & 1)] = any;
+    if (cur) ctl[kCtlMisRounds] += 1;
   }
 }
 
@@ -435,27 +470,31 @@ void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask
                        int* gcol, hipStream_t s) {
   k_graph_fill<<<grid_for(n), kT, 0, s>>>(n, rp, ci, gmask, gptr, gcol);
 }
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, int* ctl, int* err, hipStream_t s,
-                     const int* lbase) {
-  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, ctl, err, lbase);
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* ctl, int* err,
+                     hipStream_t s, const int* lbase) {
+  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, M1, ctl, err, lbase);
 }
 template <int G>
 static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,
-                        hipStream_t s) {
-  const int g = grid_for((long)n * G);
-  k_mis_sweep1<G><<<g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
-  k_mis_sweep2<G><<<g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+                        int* block_flag, hipStream_t s) {
+  long g = ((long)n * G + kT - 1) / kT;
+  if (g < 1) g = 1;
+  if (g > kMisBlocks) g = kMisBlocks;
+  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
+  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round, block_flag);
+  k_mis_ping<<<1, kT, 0, s>>>((int)g, block_flag, ctl, round);
 }
 
+// block_flag: kMisBlocks ints of scratch
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl,
-                      int round, int lanes, hipStream_t s) {
+                      int round, int lanes, int* block_flag, hipStream_t s) {
   switch (lanes) {
-    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, ctl, round, s); break;
-    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, ctl, round, s); break;
-    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, ctl, round, s); break;
-    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, ctl, round, s); break;
-    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, ctl, round, s); break;
-    default: mis_round_g<32>(n, gptr, gcol, T, M1, ctl, round, s); break;
+    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    default: mis_round_g<32>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
   }
 }
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s) {
