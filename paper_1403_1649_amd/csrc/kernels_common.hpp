@@ -1,10 +1,10 @@
 // Generic launch skeletons of the solve phase: a CSR row kernel (L lanes per
 // row, wave64 sub-groups) and an elementwise kernel, both with an optional
-// fused reduction.  Reductions are deterministic and free of same-address
-// atomics: each block reduces in a fixed order and writes one partial per
-// block; a one-block finalize kernel then sums the partials in block order
-// and hands the totals to the operation's finalizer, which writes device
-// scalars and flags.  Every operation carries an `active` flag read at
+// fused reduction.  Reductions are deterministic: each block reduces in a
+// fixed order and writes one partial per block; the partials are then summed
+// in block order (by a one-block finalize kernel, or for grids of at most
+// kTailBlocks blocks by the last block of the kernel itself) and handed to
+// the operation's finalizer, which writes device scalars and flags.  Every operation carries an `active` flag read at
 // kernel entry, so branches of the K-cycle and the outer iteration are
 // decided on the device.
 #pragma once
@@ -15,18 +15,46 @@ namespace amg {
 
 constexpr int kBlock = 256;
 
+// Grids of at most kTailBlocks blocks finish their reduction in the kernel:
+// the last block to arrive (a ticket counter, so at most that many atomics on
+// one address) sums the partials in block order, exactly as k_finalize does,
+// and runs the finalizer; larger grids use the separate finalize kernel.
+constexpr int kTailBlocks = 64;
+
 struct RedCtx {
   double* part;       // kMaxPartialBlocks * NV doubles
-  unsigned* ticket;   // unused (kept for the launch signature)
+  unsigned* ticket;   // arrival counter of the in-kernel finalize (zero between kernels)
 };
 
-template <int NV>
-__device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc) {
+template <int NV, class Op>
+__device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc, const Op& op, bool tail) {
   __shared__ double red[NV * (kBlock / kWave)];
+  __shared__ int s_last;
   block_sum<NV>(acc, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) rc.part[k * gridDim.x + blockIdx.x] = acc[k];
+  }
+  if (!tail) return;
+  if (threadIdx.x == 0) {
+    __threadfence();   // the partial is visible before the ticket is taken
+    s_last = atomicAdd(rc.ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int nb = gridDim.x;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) t += rc.part[k * nb + b];
+    v[k] = t;
+  }
+  block_sum<NV>(v, red);
+  if (threadIdx.x == 0) {
+    op.finalize(v);
+    *rc.ticket = 0u;
   }
 }
 
@@ -90,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
     sum = group_sum<LPR>(sum);
     if (row < n && lane == 0) op.row(row, sum, acc);
   }
-  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
 
 // Sliced ELL with slices of 64 rows (one wave): slice s holds its rows
@@ -127,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
     for (int k = 0; k < w; ++k) sum += vp[k * kWave] * op.x(cp[k * kWave]);
     if (row < n) op.row(row, sum, acc);
   }
-  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
 
 // Elementwise operation over [0, n): Op provides NV, active(), idle(),
@@ -142,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_elem(int n, Op op, RedCtx rc) {
 #pragma unroll
   for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) op.elem(i, acc);
-  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc);
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
 
 // Grid of the row kernels: one block per 256-row (or RPB-row) group up to a
@@ -170,16 +198,19 @@ template <typename T, class Op>
 void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc,
                  hipStream_t s) {
   const int g = rows_grid(n, lpr, Op::NV > 0);
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
+  const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
   switch (lpr) {
-    case 1: k_rows<T, 1, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    case 2: k_rows<T, 2, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    case 4: k_rows<T, 4, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    case 8: k_rows<T, 8, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    case 16: k_rows<T, 16, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    case 32: k_rows<T, 32, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
-    default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, rc); break;
+    case 1: k_rows<T, 1, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    case 2: k_rows<T, 2, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    case 4: k_rows<T, 4, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    case 8: k_rows<T, 8, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    case 16: k_rows<T, 16, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    case 32: k_rows<T, 32, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
+    default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
   }
-  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
+  if constexpr (Op::NV > 0)
+    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
 }
 
 template <typename T, class Op>
@@ -189,15 +220,20 @@ void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > 8) g &= ~7L;
-  k_sell<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, rc);
-  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, (int)g);
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
+  k_sell<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op,
+                                          RedCtx{rc.part, tail ? rc.ticket : nullptr});
+  if constexpr (Op::NV > 0)
+    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, (int)g);
 }
 
 template <class Op>
 void launch_elem(int n, const Op& op, RedCtx rc, hipStream_t s) {
   const int g = elem_grid(n, Op::NV > 0);
-  k_elem<Op><<<g, kBlock, 0, s>>>(n, op, rc);
-  if constexpr (Op::NV > 0) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
+  k_elem<Op><<<g, kBlock, 0, s>>>(n, op, RedCtx{rc.part, tail ? rc.ticket : nullptr});
+  if constexpr (Op::NV > 0)
+    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
 }
 
 inline int pick_lpr(int n, int nnz) {

@@ -59,8 +59,37 @@ struct OpPresmoothResid {
   __device__ void finalize(const double*) const {}
 };
 
-// new residual and post-smoothing: r = b - A x, x_out = x + w.*r
+// The coarse-grid correction is applied where the post-smoothing reads the
+// iterate, x_j + P_j (correction of aggregate agg_j), so it needs no pass of
+// its own.  V-cycle: the correction is c; K-cycle: coef_c c (+ coef_d d when
+// the second inner step was kept).
 template <typename T>
+struct CorrV {
+  const int* agg;
+  const T* pval;
+  const T* c;
+  __device__ T at(const T* xt, int j) const { return xt[j] + pval[j] * c[agg[j]]; }
+};
+
+template <typename T>
+struct CorrK {
+  const int* agg;
+  const T* pval;
+  const T* c;
+  const T* d;
+  const double* K;
+  const int* F;
+  __device__ T at(const T* xt, int j) const {
+    const int I = agg[j];
+    T xc = (T)K[kKCoefC] * c[I];
+    if (F[1]) xc += (T)K[kKCoefD] * d[I];
+    return xt[j] + pval[j] * xc;
+  }
+};
+
+// new residual and post-smoothing on the corrected iterate x = xt + P e:
+// r = b - A x, x_out = x + w.*r
+template <typename T, class Corr>
 struct OpResidSmooth {
   static constexpr int NV = 0;
   Act a;
@@ -68,15 +97,16 @@ struct OpResidSmooth {
   const T* xt;
   const T* wd;
   T* xo;
+  Corr corr;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
-  __device__ T x(int j) const { return xt[j]; }
-  __device__ void row(int i, T ax, double*) const { xo[i] = xt[i] + wd[i] * (b[i] - ax); }
+  __device__ T x(int j) const { return corr.at(xt, j); }
+  __device__ void row(int i, T ax, double*) const { xo[i] = corr.at(xt, i) + wd[i] * (b[i] - ax); }
   __device__ void finalize(const double*) const {}
 };
 
 // the same at level 0 of the outer iteration, with z'q for the FCG beta
-template <typename T>
+template <typename T, class Corr>
 struct OpResidSmoothDot {
   static constexpr int NV = 1;
   Act a;
@@ -84,13 +114,14 @@ struct OpResidSmoothDot {
   const T* xt;
   const T* wd;
   T* xo;
+  Corr corr;
   const double* q;
   double* sc;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
-  __device__ T x(int j) const { return xt[j]; }
+  __device__ T x(int j) const { return corr.at(xt, j); }
   __device__ void row(int i, T ax, double* acc) const {
-    const T z = xt[i] + wd[i] * (b[i] - ax);
+    const T z = corr.at(xt, i) + wd[i] * (b[i] - ax);
     xo[i] = z;
     acc[0] += (double)z * q[i];
   }
@@ -364,45 +395,6 @@ struct OpRestrict {   // rows of R = P^T (aggregates): r_c = R r, with ||r_c||^2
   }
 };
 
-// prolongation x += P c
-template <typename T>
-struct OpProlong {
-  static constexpr int NV = 0;
-  Act a;
-  const int* agg;
-  const T* pval;
-  const T* c;
-  T* xt;
-  __device__ bool active() const { return a.on(); }
-  __device__ void idle() const {}
-  __device__ void elem(int i, double*) const { xt[i] += pval[i] * c[agg[i]]; }
-  __device__ void finalize(const double*) const {}
-};
-
-// prolongation of the K-cycle combination x += P (coef_c c + coef_d d)
-template <typename T>
-struct OpProlongK {
-  static constexpr int NV = 0;
-  Act a;
-  const int* agg;
-  const T* pval;
-  const T* c;
-  const T* d;
-  T* xt;
-  const double* K;
-  const int* F;
-  __device__ bool active() const { return a.on(); }
-  __device__ void idle() const {}
-  __device__ void elem(int i, double*) const {
-    const int I = agg[i];
-    const T cc = (T)K[kKCoefC];
-    T xc = cc * c[I];
-    if (F[1]) xc += (T)K[kKCoefD] * d[I];
-    xt[i] += pval[i] * xc;
-  }
-  __device__ void finalize(const double*) const {}
-};
-
 // r~ = r - (alpha1/rho1) v with ||r~||^2; decides the second inner step
 template <typename T>
 struct OpRtilde {
@@ -571,6 +563,22 @@ void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
 
 // cycle(k): x_out = M_k b with a zero initial guess (Algorithm 5 on the top
 // kcycle_levels levels, Algorithm 4 below); `act` guards every kernel.
+// Residual + post-smoothing of level k on the corrected iterate (and z'q at
+// the top of the outer iteration when fuse_q is given).
+template <typename T, class Corr>
+void post_smooth(Hierarchy& h, const Level& lv, int k, Act A, const T* b, const T* xt, const T* wd, T* xo, Corr corr,
+                 const double* fuse_q, RedCtx rc) {
+  const Level* lp = &lv;
+  const bool sel = k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH;
+  if (fuse_q) {
+    const OpResidSmoothDot<T, Corr> op{A, b, xt, wd, xo, corr, fuse_q, h.d_sc};
+    probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+  } else {
+    const OpResidSmooth<T, Corr> op{A, b, xt, wd, xo, corr};
+    probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+  }
+}
+
 template <typename T>
 void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double* fuse_q = nullptr) {
   if (h.L() == 0) {
@@ -601,7 +609,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
                    rc, s);
     if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
     else cycle<T>(h, k + 1, rcv, c, act);
-    launch_elem(lv.n, OpProlong<T>{A, lv.agg, pv, c, xt}, rc, s);
+    post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrV<T>{lv.agg, pv, c}, fuse_q, rc);
   } else {
     Level& lc = h.levels[k + 1];
     double* K = h.d_sc + kScK + 16 * k;
@@ -617,18 +625,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
     cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
     launch_level<T>(lc, OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm}, rc, s);
-    launch_elem(lv.n, OpProlongK<T>{A, lv.agg, pv, c, d, xt, K, F}, rc, s);
-  }
-  {
-    const Level* lp = &lv;
-    const bool sel = k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH;
-    if (fuse_q) {
-      const OpResidSmoothDot<T> op{A, b, xt, wd, xo, fuse_q, h.d_sc};
-      probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
-    } else {
-      const OpResidSmooth<T> op{A, b, xt, wd, xo};
-      probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
-    }
+    post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrK<T>{lv.agg, pv, c, d, K, F}, fuse_q, rc);
   }
 }
 
