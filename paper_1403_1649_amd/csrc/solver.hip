@@ -59,16 +59,25 @@ struct OpPresmoothResid {
   __device__ void finalize(const double*) const {}
 };
 
-// The coarse-grid correction is applied where the post-smoothing reads the
-// iterate, x_j + P_j (correction of aggregate agg_j), so it needs no pass of
-// its own.  V-cycle: the correction is c; K-cycle: coef_c c (+ coef_d d when
+// On small levels (at most kFuseCorrectionRows rows, where a launch costs more
+// than the work) the coarse-grid correction is applied where the
+// post-smoothing reads the iterate, x_j + P_j (correction of aggregate agg_j),
+// so it needs no pass of its own; larger levels run the prolongation as its
+// own pass, which is cheaper than three extra gathers per nonzero.  V-cycle: the correction is c; K-cycle: coef_c c (+ coef_d d when
 // the second inner step was kept).
+constexpr int kFuseCorrectionRows = 65536;
+
 template <typename T>
 struct CorrV {
   const int* agg;
   const T* pval;
   const T* c;
   __device__ T at(const T* xt, int j) const { return xt[j] + pval[j] * c[agg[j]]; }
+};
+
+template <typename T>
+struct CorrNone {   // correction already applied by a prolongation pass
+  __device__ T at(const T* xt, int j) const { return xt[j]; }
 };
 
 template <typename T>
@@ -395,6 +404,45 @@ struct OpRestrict {   // rows of R = P^T (aggregates): r_c = R r, with ||r_c||^2
   }
 };
 
+// prolongation x += P c
+template <typename T>
+struct OpProlong {
+  static constexpr int NV = 0;
+  Act a;
+  const int* agg;
+  const T* pval;
+  const T* c;
+  T* xt;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { xt[i] += pval[i] * c[agg[i]]; }
+  __device__ void finalize(const double*) const {}
+};
+
+// prolongation of the K-cycle combination x += P (coef_c c + coef_d d)
+template <typename T>
+struct OpProlongK {
+  static constexpr int NV = 0;
+  Act a;
+  const int* agg;
+  const T* pval;
+  const T* c;
+  const T* d;
+  T* xt;
+  const double* K;
+  const int* F;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    const int I = agg[i];
+    const T cc = (T)K[kKCoefC];
+    T xc = cc * c[I];
+    if (F[1]) xc += (T)K[kKCoefD] * d[I];
+    xt[i] += pval[i] * xc;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
 // r~ = r - (alpha1/rho1) v with ||r~||^2; decides the second inner step
 template <typename T>
 struct OpRtilde {
@@ -609,7 +657,12 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
                    rc, s);
     if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
     else cycle<T>(h, k + 1, rcv, c, act);
-    post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrV<T>{lv.agg, pv, c}, fuse_q, rc);
+    if (lv.n <= kFuseCorrectionRows) {
+      post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrV<T>{lv.agg, pv, c}, fuse_q, rc);
+    } else {
+      launch_elem(lv.n, OpProlong<T>{A, lv.agg, pv, c, xt}, rc, s);
+      post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrNone<T>{}, fuse_q, rc);
+    }
   } else {
     Level& lc = h.levels[k + 1];
     double* K = h.d_sc + kScK + 16 * k;
@@ -625,7 +678,12 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
     cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
     launch_level<T>(lc, OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm}, rc, s);
-    post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrK<T>{lv.agg, pv, c, d, K, F}, fuse_q, rc);
+    if (lv.n <= kFuseCorrectionRows) {
+      post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrK<T>{lv.agg, pv, c, d, K, F}, fuse_q, rc);
+    } else {
+      launch_elem(lv.n, OpProlongK<T>{A, lv.agg, pv, c, d, xt, K, F}, rc, s);
+      post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrNone<T>{}, fuse_q, rc);
+    }
   }
 }
 
