@@ -354,7 +354,7 @@ void init_control(Hierarchy& h) {
   h.d_err = h.arena.alloc_n<int>(64);
   h.d_ctl = h.arena.alloc_n<int>(kCtlWords);
   h.d_sc = h.arena.alloc_n<double>(kScWords);
-  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4);
+  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4 + 256);   // block partials, then group partials
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
   launch_fill_int(64, h.d_err, 0, h.stream);
   launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);
@@ -489,7 +489,9 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
                      &lc.val, &lc.nnz);
 
-    // damped Jacobi weight (Section 2.2.1)
+    // damped Jacobi weight (Section 2.2.1); the sliced-ELL copy serves the
+    // Arnoldi mat-vecs on stencil-like levels
+    build_sell(h, tmp, lv);
     const int m = std::min(o.arnoldi_m, n);
     double* Q = tmp.alloc_n<double>((size_t)(m + 1) * n);
     double* w = tmp.alloc_n<double>(n);
@@ -555,7 +557,8 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   if (!inverted) launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
-  for (int k = 0; k < h.L(); ++k) build_sell(h, tmp, h.levels[k]);
+  for (int k = 0; k < h.L(); ++k)
+    if (h.levels[k].nslices == 0) build_sell(h, tmp, h.levels[k]);
   sy.wait_and_check();
   if (!(o.flags & AMG_FLAG_NO_TUNE)) autotune_levels(h);
   if (o.probe != AMG_PROBE_NONE) {

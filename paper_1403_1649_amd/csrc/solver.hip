@@ -1268,7 +1268,11 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
   launch_elem(n, OpDivide{Q, Q, sc + kScArn + 56}, rc, s);
   for (int j = 0; j < m; ++j) {
     const double* qj = Q + (size_t)j * n;
-    launch_rows<double>(n, lv.lpr, lv.rp, lv.ci, lv.val, OpArnSpmv{qj, Q, lv.diag, w, sc, j}, rc, s);
+    const OpArnSpmv op{qj, Q, lv.diag, w, sc, j};
+    if (lv.nslices > 0 && lv.nnz <= 12L * n)   // short, even rows: sliced ELL
+      launch_sell<double>(n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, op, rc, s);
+    else
+      launch_rows<double>(n, lv.lpr, lv.rp, lv.ci, lv.val, op, rc, s);
     for (int i = 0; i <= j; ++i) {
       const double* qi = Q + (size_t)i * n;
       const double* qn = i < j ? Q + (size_t)(i + 1) * n : nullptr;
