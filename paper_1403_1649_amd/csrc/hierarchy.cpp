@@ -354,7 +354,7 @@ void init_control(Hierarchy& h) {
   h.d_err = h.arena.alloc_n<int>(64);
   h.d_ctl = h.arena.alloc_n<int>(kCtlWords);
   h.d_sc = h.arena.alloc_n<double>(kScWords);
-  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4 + 256);   // block partials, then group partials
+  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4);
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
   launch_fill_int(64, h.d_err, 0, h.stream);
   launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);

@@ -2,11 +2,11 @@
 // row, wave64 sub-groups) and an elementwise kernel, both with an optional
 // fused reduction.  Reductions are deterministic: each block reduces in a
 // fixed order and writes one partial per block; the partials are then summed
-// in a fixed order (by the last blocks of the kernel itself, or by a one-block
-// finalize kernel when no ticket counters are given) and handed to the
-// operation's finalizer, which writes device scalars and flags.  Every
-// operation carries an `active` flag read at kernel entry, so branches of the
-// K-cycle and the outer iteration are decided on the device.
+// in block order (by a one-block finalize kernel, or for grids of at most
+// kTailBlocks blocks by the last block of the kernel itself) and handed to
+// the operation's finalizer, which writes device scalars and flags.  Every operation carries an `active` flag read at
+// kernel entry, so branches of the K-cycle and the outer iteration are
+// decided on the device.
 #pragma once
 #include "amg_internal.hpp"
 #include "device_utils.hpp"
@@ -15,78 +15,48 @@ namespace amg {
 
 constexpr int kBlock = 256;
 
-// Reductions finish inside the kernel: blocks form groups of kTailGroup; the
-// last block to arrive in a group (a ticket counter per group, so at most
-// kTailGroup atomics on one address) sums the group's partials in block order
-// into a group partial, and the last group to finish (a second counter) sums
-// the group partials in group order and runs the finalizer.  The order of
-// every sum is fixed, so results do not depend on timing.  Counters return to
-// zero at the end of each kernel.
-constexpr int kTailGroup = 64;
-constexpr int kTailGroupsMax = kMaxPartialBlocks / kTailGroup;   // 32
+// Grids of at most kTailBlocks blocks finish their reduction in the kernel:
+// the last block to arrive (a ticket counter) sums the partials in block
+// order, exactly as k_finalize does, and runs the finalizer; larger grids use
+// the separate finalize kernel.  The limit is set by the release fence each
+// block needs before taking its ticket: at device scope it writes back the
+// XCD's L2, which grows expensive when many blocks of a large kernel do it.
+constexpr int kTailBlocks = 64;
 
 struct RedCtx {
-  double* part;       // kMaxPartialBlocks * 4 block partials, then kTailGroupsMax * 4 group partials
-  unsigned* ticket;   // [0] group arrivals, [1 + g] block arrivals of group g (zero between kernels)
+  double* part;       // kMaxPartialBlocks * NV doubles
+  unsigned* ticket;   // arrival counter of the in-kernel finalize (zero between kernels)
 };
-
-template <int NV>
-__device__ __forceinline__ void sum_range(const double* __restrict__ src, int stride, int b0, int b1, double (&v)[NV],
-                                          double* red) {
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double t = 0.0;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) t += src[k * stride + b];
-    v[k] = t;
-  }
-  block_sum<NV>(v, red);
-}
 
 template <int NV, class Op>
 __device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc, const Op& op, bool tail) {
   __shared__ double red[NV * (kBlock / kWave)];
   __shared__ int s_last;
   block_sum<NV>(acc, red);
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) rc.part[k * nb + blockIdx.x] = acc[k];
+    for (int k = 0; k < NV; ++k) rc.part[k * gridDim.x + blockIdx.x] = acc[k];
   }
   if (!tail) return;
-  const int g = blockIdx.x / kTailGroup;
-  const int ng = (nb + kTailGroup - 1) / kTailGroup;
-  const int gsize = min(kTailGroup, nb - g * kTailGroup);
   if (threadIdx.x == 0) {
     __threadfence();   // the partial is visible before the ticket is taken
-    s_last = atomicAdd(rc.ticket + 1 + g, 1u) == (unsigned)(gsize - 1);
+    s_last = atomicAdd(rc.ticket, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (!s_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int nb = gridDim.x;
   double v[NV];
-  sum_range<NV>(rc.part, nb, g * kTailGroup, g * kTailGroup + gsize, v, red);
-  if (ng == 1) {
-    if (threadIdx.x == 0) {
-      op.finalize(v);
-      rc.ticket[1] = 0u;
-    }
-    return;
-  }
-  double* gpart = rc.part + (size_t)kMaxPartialBlocks * 4;
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) gpart[k * kTailGroupsMax + g] = v[k];
-    rc.ticket[1 + g] = 0u;
-    __threadfence();
-    s_last = atomicAdd(rc.ticket, 1u) == (unsigned)(ng - 1);
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) t += rc.part[k * nb + b];
+    v[k] = t;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  sum_range<NV>(gpart, kTailGroupsMax, 0, ng, v, red);
+  block_sum<NV>(v, red);
   if (threadIdx.x == 0) {
     op.finalize(v);
-    rc.ticket[0] = 0u;
+    *rc.ticket = 0u;
   }
 }
 
@@ -230,7 +200,7 @@ template <typename T, class Op>
 void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc,
                  hipStream_t s) {
   const int g = rows_grid(n, lpr, Op::NV > 0);
-  const bool tail = Op::NV > 0 && rc.ticket != nullptr;
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
   switch (lpr) {
     case 1: k_rows<T, 1, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
@@ -252,7 +222,7 @@ void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > 8) g &= ~7L;
-  const bool tail = Op::NV > 0 && rc.ticket != nullptr;
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   k_sell<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op,
                                           RedCtx{rc.part, tail ? rc.ticket : nullptr});
   if constexpr (Op::NV > 0)
@@ -262,7 +232,7 @@ void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const
 template <class Op>
 void launch_elem(int n, const Op& op, RedCtx rc, hipStream_t s) {
   const int g = elem_grid(n, Op::NV > 0);
-  const bool tail = Op::NV > 0 && rc.ticket != nullptr;
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   k_elem<Op><<<g, kBlock, 0, s>>>(n, op, RedCtx{rc.part, tail ? rc.ticket : nullptr});
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
