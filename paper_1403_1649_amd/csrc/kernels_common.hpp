@@ -154,7 +154,24 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
     T sum = T(0);
     const int* cp = sl_col + base + lane;
     const T* vp = sl_val + base + lane;
-    for (int k = 0; k < w; ++k) sum += vp[k * kWave] * op.x(cp[k * kWave]);
+    // chunks of 8 entries: all column and value loads of a chunk, then all
+    // gathers, then the FMAs in entry order, so a chunk costs one round trip
+    for (int k0 = 0; k0 < w; k0 += 8) {
+      int c[8];
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool in = k0 + q < w;
+        c[q] = in ? cp[(k0 + q) * kWave] : 0;
+        v[q] = in ? vp[(k0 + q) * kWave] : T(0);
+      }
+      T xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[q] = k0 + q < w ? op.x(c[q]) : T(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < w) sum += v[q] * xv[q];
+    }
     if (row < n) op.row(row, sum, acc);
   }
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
