@@ -124,6 +124,8 @@ struct Level {
   int* blk = nullptr;          // block table: (system, row0, row1) per block; system -1 pads
   int nblk = 0;                // table entries (a multiple of 8 above 8)
   int* blk_sys = nullptr;      // blocks of system s: [blk_sys[s], blk_sys[s+1])
+  int* sl_base = nullptr;      // sliced ELL of a batch: first slice of each system
+  int bsell = 0;               // batch level uses its sliced-ELL copy
   int* kv = nullptr;           // per system: the K-cycle applies on this level
   int kcyc = 0;                // some system takes the K-cycle on this level
   std::vector<int> term;       // systems whose coarsest level this is
@@ -292,6 +294,7 @@ int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* 
 void batch_blocks(Hierarchy& h, Level& lv);
 void batch_local_base(const Level& lv, int* lbase, hipStream_t s);
 void batch_check_blocks(const Level& lv, int* err, hipStream_t s);
+void batch_build_sell(Hierarchy& h, Arena& tmp, Level& lv);
 void batch_gather(int m, const int* src, const int* idx, int* dst, hipStream_t s);
 void batch_remap_agg(const Level& lv, const int* cont, const int* shift, int* agg, hipStream_t s);
 void batch_arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, const int* mask, double* Q, double* w,

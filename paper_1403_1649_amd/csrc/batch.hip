@@ -163,6 +163,77 @@ void brows(const Level& lv, int lpr, const BCtx& c, const T* av, const Op& op, h
   brows_on<T>(lv, lpr, lv.rp, lv.ci, av, c, op, s);
 }
 
+// Sliced ELL of a batch level: slices of 64 rows aligned to each system's
+// first row (the last slice of a system may be short), column-major inside a
+// slice.  Blocks of the row table start at system offsets in multiples of
+// 256 rows, so each block covers whole slices; wave q of a block takes the
+// block's slices q, q + 4, ...
+template <typename T, class Op>
+__global__ void __launch_bounds__(kBlock) k_bsell(const int* __restrict__ blk, int nb, const int* __restrict__ sys_off,
+                                                  const int* __restrict__ sl_base, const int* __restrict__ sl_ptr,
+                                                  const int* __restrict__ sl_col, const T* __restrict__ sl_val, Op op,
+                                                  double* part) {
+  if (!op.m.active()) return;
+  constexpr int NV = Op::NV > 0 ? Op::NV : 1;
+  const int lb = logical_block();
+  const int sys = blk[3 * lb], r0 = blk[3 * lb + 1], r1 = blk[3 * lb + 2];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  if (sys >= 0 && op.m.on(sys)) {
+    const int so = sys_off[sys], sb = sl_base[sys];
+    for (int r = r0 + wv * kWave; r < r1; r += kBlock) {
+      const int sl = sb + (r - so) / kWave;
+      const int row = r + lane;
+      const int base = sl_ptr[sl];
+      const int w = (sl_ptr[sl + 1] - base) / kWave;
+      const int* cp = sl_col + base + lane;
+      const T* vp = sl_val + base + lane;
+      T sum = T(0);
+      for (int k0 = 0; k0 < w; k0 += 8) {
+        int cc[8];
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool in = k0 + q < w;
+          cc[q] = in ? cp[(k0 + q) * kWave] : 0;
+          v[q] = in ? vp[(k0 + q) * kWave] : T(0);
+        }
+        T xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[q] = k0 + q < w ? op.x(cc[q]) : T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < w) sum += v[q] * xv[q];
+      }
+      if (row < r1) op.row(row, sys, sum, acc);
+    }
+  }
+  if constexpr (Op::NV > 0) write_part<Op::NV>(acc, part, nb, lb);
+}
+
+template <typename T> const T* bsv(const Level& l);
+template <> const double* bsv<double>(const Level& l) { return l.sl_val; }
+template <> const float* bsv<float>(const Level& l) { return l.sl_val32; }
+template <typename T> const T* bav(const Level& l);
+template <> const double* bav<double>(const Level& l) { return l.val; }
+template <> const float* bav<float>(const Level& l) { return l.val32; }
+
+// A_k applied by a row operation, in the level's format
+template <typename T, class Op>
+void blevel(const Level& lv, const BCtx& c, const Op& op, hipStream_t s) {
+  if (!lv.bsell) {
+    brows_on<T>(lv, lv.lpr, lv.rp, lv.ci, bav<T>(lv), c, op, s);
+    return;
+  }
+  if (lv.nblk == 0) return;
+  const int g = lv.nblk;
+  k_bsell<T, Op><<<g, kBlock, 0, s>>>(lv.blk, g, lv.d_sys_off, lv.sl_base, lv.sl_ptr, lv.sl_col, bsv<T>(lv), op,
+                                      c.part);
+  if constexpr (Op::NV > 0) k_bfinal<Op><<<1, kFinThreads, 0, s>>>(op, c.part, g, lv.blk_sys, c.nsys);
+}
+
 template <class Op>
 void belem(const Level& lv, const BCtx& c, const Op& op, hipStream_t s) {
   if (lv.nblk == 0) return;
@@ -738,9 +809,8 @@ void cycle_b(Hierarchy& h, int k, const T* b, T* xo, Mask m) {
   T* cc = static_cast<T*>(lv.c);
   const T* wd = bwd<T>(lv);
   const T* pv = bpv<T>(lv);
-  const T* av = bvals<T>(lv);
   Level& lc = h.levels[k + 1];
-  brows<T>(lv, lv.lpr, c, av, BPresmoothResid<T>{m, b, wd, xt, r}, s);
+  blevel<T>(lv, c, BPresmoothResid<T>{m, b, wd, xt, r}, s);
   const T* rv = brv<T>(lv);
   if (!lv.kcyc) {
     brows_on<T>(lc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rv, c, BRestrict<T, false>{m, r, rcv, nullptr, nsys}, s);
@@ -754,17 +824,16 @@ void cycle_b(Hierarchy& h, int k, const T* b, T* xo, Mask m) {
     T* rt = static_cast<T*>(lv.rt);
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
-    const T* avc = bvals<T>(lc);
     brows_on<T>(lc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rv, c, BRestrict<T, true>{m, r, rcv, K, nsys}, s);
     cycle_b<T>(h, k + 1, rcv, cc, m);
-    brows<T>(lc, lc.lpr, c, avc, BKDots1<T>{m, cc, rcv, v, K, nsys}, s);
+    blevel<T>(lc, c, BKDots1<T>{m, cc, rcv, v, K, nsys}, s);
     belem(lc, c, BRtilde<T>{m, rcv, v, rt, K, F, any2, lv.kv, h.opt.kcycle_t, nsys}, s);
     const Mask m2{any2, F};
     cycle_b<T>(h, k + 1, rt, d, m2);
-    brows<T>(lc, lc.lpr, c, avc, BKDots2<T>{m2, d, v, rt, w, K, F, nsys}, s);
+    blevel<T>(lc, c, BKDots2<T>{m2, d, v, rt, w, K, F, nsys}, s);
     belem(lv, c, BProlongK<T>{m, lv.agg, pv, cc, d, xt, K, F, nsys}, s);
   }
-  brows<T>(lv, lv.lpr, c, av, BResidSmooth<T>{m, b, xt, wd, xo}, s);
+  blevel<T>(lv, c, BResidSmooth<T>{m, b, xt, wd, xo}, s);
   term_solve<T>(h, lv, b, xo, m);   // systems whose coarsest level is this one
 }
 
@@ -788,7 +857,7 @@ void iteration_b(Hierarchy& h) {
   const Mask m{h.b_any + aRun, h.b_fl + fRun * nsys};
   hipStream_t s = h.stream;
   float* r32 = sizeof(T) == sizeof(float) ? static_cast<float*>(h.bz) : nullptr;
-  brows<double>(l0, l0.lpr, c, l0.val, BFcgSpmv{m, h.p, h.r, h.q, h.b_sc, h.b_fl, h.d_err, nsys}, s);
+  blevel<double>(l0, c, BFcgSpmv{m, h.p, h.r, h.q, h.b_sc, h.b_fl, h.d_err, nsys}, s);
   belem(l0, c, BFcgUpdate{m, h.p, h.q, h.xint, h.r, r32, h.b_sc, h.b_fl, h.b_any, h.d_err, nsys}, s);
   precondition_b<T>(h, m, r32 != nullptr);
   belem(l0, c, BDotZQ<T>{m, static_cast<const T*>(h.z), h.q, h.b_sc, nsys}, s);
@@ -854,6 +923,92 @@ void batch_local_base(const Level& lv, int* lbase, hipStream_t s) {
   belem(lv, c, BLocalBase{Mask{nullptr, nullptr}, lv.d_sys_off, lbase}, s);
 }
 
+namespace {
+__global__ void k_bsell_widths(int nsl, const int* __restrict__ srow, const int* __restrict__ rp,
+                               int* __restrict__ widths) {
+  const int sl = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  int len = 0;
+  if (sl < nsl) {
+    const int row = srow[2 * sl] + lane;
+    if (row < srow[2 * sl + 1]) len = rp[row + 1] - rp[row];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const int o = __shfl_xor(len, off, kWave);
+    len = o > len ? o : len;
+  }
+  if (sl < nsl && lane == 0) widths[sl] = len * kWave;
+}
+
+// entry k of slice row l at sl_ptr[sl] + 64 k + l; padding has value 0 and a
+// column inside the slice's system (the row itself, or the slice's first row)
+__global__ void k_bsell_fill(int nsl, const int* __restrict__ srow, const int* __restrict__ rp,
+                             const int* __restrict__ ci, const double* __restrict__ val,
+                             const int* __restrict__ sl_ptr, int* __restrict__ sl_col, double* __restrict__ sl_val,
+                             float* __restrict__ sl_val32) {
+  const int sl = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (sl >= nsl) return;
+  const int row = srow[2 * sl] + lane;
+  const bool valid = row < srow[2 * sl + 1];
+  const int s0 = valid ? rp[row] : 0;
+  const int len = valid ? rp[row + 1] - s0 : 0;
+  const int base = sl_ptr[sl];
+  const int w = (sl_ptr[sl + 1] - base) / kWave;
+  for (int k = 0; k < w; ++k) {
+    const int idx = base + k * kWave + lane;
+    int c = valid ? row : srow[2 * sl];
+    double v = 0.0;
+    if (k < len) {
+      c = ci[s0 + k];
+      v = val[s0 + k];
+    }
+    sl_col[idx] = c;
+    sl_val[idx] = v;
+    if (sl_val32) sl_val32[idx] = (float)v;
+  }
+}
+}  // namespace
+
+// Sliced-ELL copy of a batch level (used when its rows are short: at most 12
+// entries on average).
+void batch_build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
+  const int nsys = h.nsys;
+  lv.bsell = lv.nnz <= 12L * lv.n ? 1 : 0;
+  if (!lv.bsell) return;
+  std::vector<int> srow, base(nsys + 1);
+  int nsl = 0;
+  for (int q = 0; q < nsys; ++q) {
+    base[q] = nsl;
+    for (int r = lv.sys_off[q]; r < lv.sys_off[q + 1]; r += kWave) {
+      srow.push_back(r);
+      srow.push_back(std::min(r + kWave, lv.sys_off[q + 1]));
+      ++nsl;
+    }
+  }
+  base[nsys] = nsl;
+  hipStream_t s = h.stream;
+  int* d_srow = tmp.alloc_n<int>(std::max<size_t>(srow.size(), 2));
+  int* widths = tmp.alloc_n<int>(std::max(nsl, 1));
+  lv.sl_base = h.arena.alloc_n<int>(nsys + 1);
+  lv.sl_ptr = h.arena.alloc_n<int>(nsl + 1);
+  lv.nslices = nsl;
+  AMG_HIP(hipMemcpyAsync(d_srow, srow.data(), srow.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(lv.sl_base, base.data(), base.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  const int g = (nsl + kBlock / kWave - 1) / (kBlock / kWave);
+  k_bsell_widths<<<g, kBlock, 0, s>>>(nsl, d_srow, lv.rp, widths);
+  scan_to_ptr(widths, lv.sl_ptr, nsl, h.d_scan, s);
+  int total = 0;
+  AMG_HIP(hipMemcpyAsync(&total, lv.sl_ptr + nsl, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  lv.sl_col = h.arena.alloc_n<int>(std::max(total, 1));
+  lv.sl_val = h.arena.alloc_n<double>(std::max(total, 1));
+  if (h.mixed()) lv.sl_val32 = h.arena.alloc_n<float>(std::max(total, 1));
+  k_bsell_fill<<<g, kBlock, 0, s>>>(nsl, d_srow, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_val, lv.sl_val32);
+  AMG_HIP(hipStreamSynchronize(s));   // the host slice table is read before it goes away
+}
+
 void batch_check_blocks(const Level& lv, int* err, hipStream_t s) {
   BCtx c{0, nullptr};
   belem(lv, c, BCheckBlocks{Mask{nullptr, nullptr}, lv.d_sys_off, lv.rp, lv.ci, err}, s);
@@ -888,7 +1043,7 @@ void batch_arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, const int* m
   belem(lv, c, BDivide{mk, Q, Q, sc + (size_t)bArnNorm * nsys}, s);
   for (int j = 0; j < m; ++j) {
     const double* qj = Q + (size_t)j * n;
-    brows<double>(lv, lv.lpr, c, lv.val, BArnSpmv{mk, qj, Q, lv.diag, w, sc, nsys, j}, s);
+    blevel<double>(lv, c, BArnSpmv{mk, qj, Q, lv.diag, w, sc, nsys, j}, s);
     for (int i = 0; i <= j; ++i) {
       const double* qi = Q + (size_t)i * n;
       const double* qn = i < j ? Q + (size_t)(i + 1) * n : nullptr;
@@ -961,7 +1116,7 @@ int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int*
       throw Error(AMG_EHIP, "device error bits " + std::to_string(hp[1]));
     }
     if (hp[0] && enqueued < max_iter) continue;
-    brows<double>(l0, l0.lpr, c, l0.val, BTrueResid{all, b, h.xint, h.q, h.b_sc, nsys}, s);
+    blevel<double>(l0, c, BTrueResid{all, b, h.xint, h.q, h.b_sc, nsys}, s);
     AMG_HIP(hipMemcpyAsync(hfl.data(), h.b_fl, hfl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipMemcpyAsync(hsc.data(), h.b_sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));

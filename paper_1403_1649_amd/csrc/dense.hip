@@ -410,8 +410,8 @@ __global__ void k_dense_scatter_batched(const TermInfo* __restrict__ ti, const i
 // A symmetric positive definite matrix needs no pivoting in Gauss-Jordan
 // elimination: every pivot is a diagonal entry of a Schur complement, hence
 // positive.  Panels of b columns: the panel's b steps run in one workgroup
-// with the panel resident in LDS (no pivot search, so one step is two
-// barriers); every other column then receives the panel's combined
+// with the panel held in registers (no pivot search, so one step is two
+// barriers and one broadcast of the pivot row); every other column then receives the panel's combined
 // elementary transformation M = I + (Y - E) E^T at once, where Y is the panel
 // after its steps and E the unit columns of the panel's pivot rows:
 // A_J <- A_J + (Y - E) T with T = the panel's pivot rows of A_J before the
@@ -422,75 +422,80 @@ __global__ void k_dense_scatter_batched(const TermInfo* __restrict__ ti, const i
 constexpr int kPanelThreads = 1024;
 constexpr int kUpdTile = 64;
 
-__global__ void __launch_bounds__(kPanelThreads) k_gjb_panel(const TermInfo* __restrict__ ti, double* __restrict__ work,
-                                                             double* __restrict__ ybuf, double* __restrict__ tbuf,
-                                                             int K, int b, int* err) {
-  extern __shared__ double P[];   // panel column-major: P[j * n + i]; then colj[n], rowk[b]
+// The panel: thread t owns rows t, t + 1024, ... (R of them) and keeps their
+// B panel entries in registers (B * R = 32); per step only the pivot row goes
+// through LDS.  In-place Gauss-Jordan step k restricted to the panel:
+// pivot row scaled by 1/p, other rows minus their column-k entry times the
+// scaled pivot row, column k replaced by -a_ik/p (and 1/p at the pivot).
+template <int B, int R>
+__global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo* __restrict__ ti,
+                                                                 double* __restrict__ work,
+                                                                 double* __restrict__ ybuf,
+                                                                 double* __restrict__ tbuf, int K, int* err) {
+  __shared__ double s_row[B];
   const TermInfo t = ti[blockIdx.x];
-  const int n = t.n, c0 = K * b;
+  const int n = t.n, c0 = K * B;
   if (c0 >= n) return;
-  const int w = min(b, n - c0);
+  const int w = min(B, n - c0);
   double* W = work + t.off;
-  double* Y = ybuf + (size_t)t.row0 * b;   // n x b, row-major
-  double* T = tbuf + (size_t)t.row0 * b;   // b x n, row-major
-  double* colj = P + (size_t)n * w;
-  double* rowk = colj + n;
+  double* Y = ybuf + (size_t)t.row0 * B;
+  double* T = tbuf + (size_t)t.row0 * B;
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * w; e += blockDim.x) {
-    const int i = e / w, j = e - i * w;
-    P[(size_t)j * n + i] = W[(size_t)i * n + c0 + j];
-  }
-  for (int e = tid; e < w * n; e += blockDim.x) {
+  for (int e = tid; e < w * n; e += kPanelThreads) {
     const int j = e / n, J = e - j * n;
     T[(size_t)j * n + J] = W[(size_t)(c0 + j) * n + J];
   }
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
+  double P[R][B];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kPanelThreads;
+#pragma unroll
+    for (int q = 0; q < B; ++q) P[r][q] = (i < n && q < w) ? W[(size_t)i * n + c0 + q] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    if (j >= w) break;
     const int k = c0 + j;
-    const double p = P[(size_t)j * n + k];
-    if (tid == 0 && !(p > 0.0 && p < INFINITY)) atomic_or_flag(err, kErrNotSPD);
-    for (int i = tid; i < n; i += blockDim.x) colj[i] = P[(size_t)j * n + i];
-    for (int q = tid; q < w; q += blockDim.x) rowk[q] = P[(size_t)q * n + k];
-    __syncthreads();
-    const double inv = 1.0 / p;
-    // G groups of threads share the rows, group g taking columns g, g+G, ...
-    // (independent LDS updates, unrolled so that they overlap)
-    const int G = max(1, min(w, (int)blockDim.x / n));
-    const int g = tid / n, i = tid - g * n;
-    if (g < G) {
-      const double c = colj[i];
-#pragma unroll 4
-      for (int q = g; q < w; q += G) {
-        double* dst = P + (size_t)q * n + i;
-        if (q == j) {
-          *dst = (i == k) ? inv : -c * inv;
-        } else {
-          const double rk = rowk[q] * inv;
-          *dst = (i == k) ? rk : *dst - c * rk;
+    if (tid == k % kPanelThreads) {
+      const int rk = k / kPanelThreads;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r == rk) {
+#pragma unroll
+          for (int q = 0; q < B; ++q) s_row[q] = P[r][q];
         }
-      }
     }
-    if (n > (int)blockDim.x) {   // rows beyond one thread each (n > 1024)
-      for (int r = tid + blockDim.x; r < n; r += blockDim.x) {
-        const double c = colj[r];
-        for (int q = 0; q < w; ++q) {
-          double* dst = P + (size_t)q * n + r;
-          if (q == j) {
-            *dst = (r == k) ? inv : -c * inv;
-          } else {
-            const double rk = rowk[q] * inv;
-            *dst = (r == k) ? rk : *dst - c * rk;
-          }
+    __syncthreads();
+    const double p = s_row[j];
+    if (tid == 0 && !(p > 0.0 && p < INFINITY)) atomic_or_flag(err, kErrNotSPD);
+    const double inv = 1.0 / p;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * kPanelThreads;
+      const double c = P[r][j];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        if (q == j) {
+          P[r][q] = (i == k) ? inv : -c * inv;
+        } else {
+          const double rk = s_row[q] * inv;
+          P[r][q] = (i == k) ? rk : P[r][q] - c * rk;
         }
       }
     }
     __syncthreads();
   }
-  for (int e = tid; e < n * w; e += blockDim.x) {
-    const int i = e / w, j = e - i * w;
-    const double v = P[(size_t)j * n + i];
-    W[(size_t)i * n + c0 + j] = v;
-    Y[(size_t)i * b + j] = v;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * kPanelThreads;
+    if (i >= n) continue;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (q < w) {
+        W[(size_t)i * n + c0 + q] = P[r][q];
+        Y[(size_t)i * B + q] = P[r][q];
+      }
+    }
   }
 }
 
@@ -652,24 +657,28 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
       tiles.push_back(q);
     }
   }
-  int dev = 0, lds_max = 0;
-  AMG_HIP(hipGetDevice(&dev));
-  AMG_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const long lds_d = (long)lds_max / 8 - 16;
-  int b = (int)std::min<long>(32, (lds_d - nmax - 32) / (nmax + 1));
-  if (b < 1) throw Error(AMG_ECOARSEN, "coarsest system too large for the LDS panel");
+  // panel width b and rows per thread R with b * R = 32 register doubles
+  int b = 32, R = 1;
+  while (R * kPanelThreads < nmax) {
+    b /= 2;
+    R *= 2;
+  }
+  if (b < 4) throw Error(AMG_ECOARSEN, "coarsest system too large for the register panel");
   launch_fill_double(total, inv, 0.0, s);
   k_dense_scatter_batched<<<nterm, 256, 0, s>>>(d_term, rp, ci, val, inv);
   double* ybuf = tmp.alloc_n<double>((size_t)nrows * b);
   double* tbuf = tmp.alloc_n<double>((size_t)nrows * b);
   int* d_tiles = tmp.alloc_n<int>(tiles.size());
   AMG_HIP(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  const size_t bytes = ((size_t)nmax * b + nmax + b) * sizeof(double);
-  AMG_HIP(hipFuncSetAttribute((const void*)k_gjb_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   const int npanels = (nmax + b - 1) / b;
   const int ntiles = (int)(tiles.size() / 2);
   for (int K = 0; K < npanels; ++K) {
-    k_gjb_panel<<<nterm, kPanelThreads, bytes, s>>>(d_term, inv, ybuf, tbuf, K, b, err);
+    switch (b) {
+      case 32: k_gjb_panel_reg<32, 1><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 16: k_gjb_panel_reg<16, 2><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 8: k_gjb_panel_reg<8, 4><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      default: k_gjb_panel_reg<4, 8><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+    }
     k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, tbuf, K, b);
   }
   if (inv32) k_dense_to_float<<<(int)std::min<size_t>((total + 255) / 256, 4096), 256, 0, s>>>(total, inv, inv32);

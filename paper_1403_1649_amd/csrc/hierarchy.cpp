@@ -622,6 +622,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     const int n = lv.n, nnz = lv.nnz;
     lv.diag = h.arena.alloc_n<double>(n);
     lv.lpr = pick_lanes_per_row(n, nnz);
+    batch_build_sell(h, tmp, lv);
     std::vector<int> present(nsys), size_term(nsys);
     bool any_cont = false;
     for (int q = 0; q < nsys; ++q) {
