@@ -454,7 +454,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
   }
 #pragma unroll
   for (int j = 0; j < B; ++j) {
-    if (j >= w) break;
+    if (j >= w) continue;   // uniform; a fixed trip count keeps P in registers
     const int k = c0 + j;
     if (tid == k % kPanelThreads) {
       const int rk = k / kPanelThreads;
