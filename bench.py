@@ -288,6 +288,20 @@ def main():
         log("bench: batched form (C4b)")
         forms["batch"] = batch_form(amg, torch, P)
 
+    # device copy bandwidth (reference for the attainable HBM rate): 1 GiB read + 1 GiB written
+    src_c = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst_c = torch.empty_like(src_c)
+    for _ in range(3):
+        dst_c.copy_(src_c)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        dst_c.copy_(src_c)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src_c.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del src_c, dst_c
+
     # level-0 SpMV: events around repeated launches on the current stream
     log("bench: level-0 SpMV")
     xv = torch.from_numpy(xs).cuda()
@@ -314,6 +328,7 @@ def main():
         "forms": forms,
         "spmv": {"gb_s": round(gbs, 1), "us": round(t_spmv * 1e6, 2), "bytes": nbytes,
                  "frac": round(gbs / PEAK_HBM_GBS, 4)},
+        "device_copy_gb_s": round(copy_gbs, 1),
     }
     pbytes = presmooth_bytes(A.n, A.nnz)
     if probe_ms:

@@ -441,23 +441,25 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
   double* Y = ybuf + (size_t)t.row0 * B;
   double* T = tbuf + (size_t)t.row0 * B;
   const int tid = threadIdx.x;
-  for (int e = tid; e < w * n; e += kPanelThreads) {
+  const int nt = blockDim.x;
+  for (int e = tid; e < w * n; e += nt) {
     const int j = e / n, J = e - j * n;
     T[(size_t)j * n + J] = W[(size_t)(c0 + j) * n + J];
   }
   double P[R][B];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = tid + r * kPanelThreads;
+    const int i = tid + r * nt;
 #pragma unroll
     for (int q = 0; q < B; ++q) P[r][q] = (i < n && q < w) ? W[(size_t)i * n + c0 + q] : 0.0;
   }
-#pragma unroll
-  for (int j = 0; j < B; ++j) {
-    if (j >= w) continue;   // uniform; a fixed trip count keeps P in registers
+  // the step loop stays rolled (one copy of the unrolled column loop), so the
+  // pivot column entry is selected with compares instead of a runtime index
+#pragma unroll 1
+  for (int j = 0; j < w; ++j) {
     const int k = c0 + j;
-    if (tid == k % kPanelThreads) {
-      const int rk = k / kPanelThreads;
+    if (tid == k % nt) {
+      const int rk = k / nt;
 #pragma unroll
       for (int r = 0; r < R; ++r)
         if (r == rk) {
@@ -471,8 +473,10 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
     const double inv = 1.0 / p;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = tid + r * kPanelThreads;
-      const double c = P[r][j];
+      const int i = tid + r * nt;
+      double c = 0.0;
+#pragma unroll
+      for (int q = 0; q < B; ++q) c = (q == j) ? P[r][q] : c;
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         if (q == j) {
@@ -487,7 +491,7 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = tid + r * kPanelThreads;
+    const int i = tid + r * nt;
     if (i >= n) continue;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -657,12 +661,14 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
       tiles.push_back(q);
     }
   }
-  // panel width b and rows per thread R with b * R = 32 register doubles
+  // panel width b and rows per thread R with b * R = 32 register doubles; a
+  // workgroup of just enough waves for the largest system
   int b = 32, R = 1;
   while (R * kPanelThreads < nmax) {
     b /= 2;
     R *= 2;
   }
+  const int pth = R > 1 ? kPanelThreads : std::max(kWave, (nmax + kWave - 1) / kWave * kWave);
   if (b < 4) throw Error(AMG_ECOARSEN, "coarsest system too large for the register panel");
   launch_fill_double(total, inv, 0.0, s);
   k_dense_scatter_batched<<<nterm, 256, 0, s>>>(d_term, rp, ci, val, inv);
@@ -674,10 +680,10 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
   const int ntiles = (int)(tiles.size() / 2);
   for (int K = 0; K < npanels; ++K) {
     switch (b) {
-      case 32: k_gjb_panel_reg<32, 1><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
-      case 16: k_gjb_panel_reg<16, 2><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
-      case 8: k_gjb_panel_reg<8, 4><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
-      default: k_gjb_panel_reg<4, 8><<<nterm, kPanelThreads, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 32: k_gjb_panel_reg<32, 1><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 16: k_gjb_panel_reg<16, 2><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 8: k_gjb_panel_reg<8, 4><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      default: k_gjb_panel_reg<4, 8><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
     }
     k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, tbuf, K, b);
   }
