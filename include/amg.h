@@ -84,9 +84,6 @@ typedef struct {
 /* amg_options.flags: skip the per-level kernel autotuner (CSR kernels with
  * lanes per row from the average row length). */
 #define AMG_FLAG_NO_TUNE 2u
-/* amg_options.flags: run every level of the cycle with its own kernels, also
- * the small coarse levels that otherwise share one single-workgroup launch. */
-#define AMG_FLAG_NO_TAIL 4u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {

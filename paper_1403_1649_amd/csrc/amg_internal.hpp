@@ -182,7 +182,6 @@ struct Hierarchy {
   double probe_ms = 0.0;
   int probe_samples = 0;
   float setup_ms = 0.f, solve_ms = 0.f;
-  int tail_k = -1;             // levels tail_k.. run as one single-workgroup V-cycle (-1: none)
   // batched systems: count (0 = one system), per-system control of the solve
   // and the results of the last solve
   int nsys = 0;
@@ -279,7 +278,6 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 
 // cycle and outer solvers (solver.hip)
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
-int tail_start(const Hierarchy& h);
 void build_solve_graphs(Hierarchy& h);
 void autotune_levels(Hierarchy& h);
 int mlp_num_params();

@@ -557,7 +557,6 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   if (!inverted) launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
-  if (!(o.flags & AMG_FLAG_NO_TAIL)) h.tail_k = tail_start(h);
   for (int k = 0; k < h.L(); ++k)
     if (h.levels[k].nslices == 0) build_sell(h, tmp, h.levels[k]);
   sy.wait_and_check();

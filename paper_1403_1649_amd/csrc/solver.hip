@@ -625,161 +625,10 @@ void post_smooth(Hierarchy& h, const Level& lv, int k, Act A, const T* b, const 
   }
 }
 
-// ---------------------------------------------------------------- small tail
-// The V-cycle below a level whose remaining levels are all small runs as one
-// workgroup: pre-smoothing + residual and restriction down to the coarsest
-// level, the dense coarse solve, then prolongation folded into the
-// post-smoothing back up, with barriers between the stages.  One launch
-// replaces about five per level, and every stage's data stays in L2.
-constexpr int kTailRows = 4096, kTailNnz = 65536, kTailLevels = 4, kTailCoarse = 1024;
-constexpr int kTailThreads = 1024;
-
-struct TailLevel {
-  int n, nc;
-  const int* rp;
-  const int* ci;
-  const void* val;
-  const void* wd;
-  const void* pval;
-  const void* rval;
-  const int* agg;
-  const int* agg_ptr;
-  const int* agg_rows;
-  void* xt;
-  void* r;
-  void* rc;
-  void* c;
-};
-
-struct TailArgs {
-  int nlev, nL;
-  TailLevel lv[kTailLevels];
-  const void* cinv;
-  const int* act;
-  const void* b;
-  void* xo;
-};
-
-template <typename T>
-__global__ void __launch_bounds__(kTailThreads) k_vtail(TailArgs a) {
-  if (a.act && *a.act == 0) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const T* b = static_cast<const T*>(a.b);
-  for (int q = 0; q < a.nlev; ++q) {   // down: x = w.*b, r = b - A x, r_c = P^T r
-    const TailLevel& L = a.lv[q];
-    const T* val = static_cast<const T*>(L.val);
-    const T* wd = static_cast<const T*>(L.wd);
-    T* xt = static_cast<T*>(L.xt);
-    T* r = static_cast<T*>(L.r);
-    for (int i = tid; i < L.n; i += nt) {
-      T ax = T(0);
-      for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) {
-        const int j = L.ci[k];
-        ax += val[k] * (wd[j] * b[j]);
-      }
-      const T bi = b[i];
-      xt[i] = wd[i] * bi;
-      r[i] = bi - ax;
-    }
-    __syncthreads();
-    const T* rval = static_cast<const T*>(L.rval);
-    T* rc = static_cast<T*>(L.rc);
-    for (int I = tid; I < L.nc; I += nt) {
-      T sum = T(0);
-      for (int k = L.agg_ptr[I]; k < L.agg_ptr[I + 1]; ++k) sum += rval[k] * r[L.agg_rows[k]];
-      rc[I] = sum;
-    }
-    __syncthreads();
-    b = rc;
-  }
-  {   // coarsest level: x_L = A_L^-1 b_L
-    const T* inv = static_cast<const T*>(a.cinv);
-    T* cl = static_cast<T*>(a.lv[a.nlev - 1].c);
-    for (int i = tid; i < a.nL; i += nt) {
-      const T* row = inv + (size_t)i * a.nL;
-      T sum = T(0);
-      for (int j = 0; j < a.nL; ++j) sum += row[j] * b[j];
-      cl[i] = sum;
-    }
-    __syncthreads();
-  }
-  for (int q = a.nlev - 1; q >= 0; --q) {   // up: x = xt + P c, x_out = x + w.*(b - A x)
-    const TailLevel& L = a.lv[q];
-    const T* bq = q == 0 ? static_cast<const T*>(a.b) : static_cast<const T*>(a.lv[q - 1].rc);
-    T* xo = q == 0 ? static_cast<T*>(a.xo) : static_cast<T*>(a.lv[q - 1].c);
-    const T* val = static_cast<const T*>(L.val);
-    const T* wd = static_cast<const T*>(L.wd);
-    const T* pval = static_cast<const T*>(L.pval);
-    const T* xt = static_cast<const T*>(L.xt);
-    const T* c = static_cast<const T*>(L.c);
-    for (int i = tid; i < L.n; i += nt) {
-      T ax = T(0);
-      for (int k = L.rp[i]; k < L.rp[i + 1]; ++k) {
-        const int j = L.ci[k];
-        ax += val[k] * (xt[j] + pval[j] * c[L.agg[j]]);
-      }
-      const T xi = xt[i] + pval[i] * c[L.agg[i]];
-      xo[i] = xi + wd[i] * (bq[i] - ax);
-    }
-    __syncthreads();
-  }
-}
-
-template <typename T> const void* tail_vals(const Level& l) {
-  return sizeof(T) == sizeof(double) ? (const void*)l.val : (const void*)l.val32;
-}
-
-// first level from which the rest of the hierarchy runs in one workgroup, or -1
-int find_tail_start(const Hierarchy& h) {
-  const int L = h.L();
-  if (L < 1 || h.levels[L].n > kTailCoarse) return -1;
-  int k = L;
-  while (k - 1 >= std::max(1, h.opt.kcycle_levels) && L - (k - 1) <= kTailLevels &&
-         h.levels[k - 1].n <= kTailRows && h.levels[k - 1].nnz <= kTailNnz)
-    --k;
-  return k < L ? k : -1;
-}
-
-template <typename T>
-void tail_cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act) {
-  TailArgs a{};
-  const int L = h.L();
-  a.nlev = L - k;
-  a.nL = h.levels[L].n;
-  for (int q = 0; q < a.nlev; ++q) {
-    const Level& lv = h.levels[k + q];
-    TailLevel& t = a.lv[q];
-    t.n = lv.n;
-    t.nc = lv.nc;
-    t.rp = lv.rp;
-    t.ci = lv.ci;
-    t.val = tail_vals<T>(lv);
-    t.wd = wdinv<T>(lv);
-    t.pval = pvals<T>(lv);
-    t.rval = rvals<T>(lv);
-    t.agg = lv.agg;
-    t.agg_ptr = lv.agg_ptr;
-    t.agg_rows = lv.agg_rows;
-    t.xt = lv.xt;
-    t.r = lv.r;
-    t.rc = lv.rc;
-    t.c = lv.c;
-  }
-  a.cinv = cinv<T>(h);
-  a.act = act;
-  a.b = b;
-  a.xo = xo;
-  k_vtail<T><<<1, kTailThreads, 0, h.stream>>>(a);
-}
-
 // cycle(k): x_out = M_k b with a zero initial guess (Algorithm 5 on the top
 // kcycle_levels levels, Algorithm 4 below); `act` guards every kernel.
 template <typename T>
 void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double* fuse_q = nullptr) {
-  if (h.tail_k >= 0 && k == h.tail_k && !fuse_q) {
-    tail_cycle<T>(h, k, b, xo, act);
-    return;
-  }
   if (h.L() == 0) {
     coarse_solve<T>(h, b, xo, act);
     return;
@@ -1439,8 +1288,6 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 }
 
 int pick_lanes_per_row(int n, int nnz) { return pick_lpr(n, nnz); }
-
-int tail_start(const Hierarchy& h) { return find_tail_start(h); }
 
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y) {
   launch_sell<double>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, OpSpmv<double>{Act{nullptr}, x, y},

@@ -330,19 +330,3 @@ def test_omega_independent_of_recycled_device_memory():
         S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
         omega, _ = O.jacobi_weight(S, oo.arnoldi_m, oo.seed + 1, oo.jacobi_scale)
         assert abs(ex["omega"] - omega) <= 1e-12 * omega, (k, ex["omega"], omega)
-
-
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_small_level_tail_matches_separate_kernels(precision):
-    """2-D Poisson 400^2 coarsens 160,000 -> ~23,000 -> ~3,300 -> ~470: the
-    V-cycle below level 2 runs as one single-workgroup launch; with
-    AMG_FLAG_NO_TAIL (4) every level runs its own kernels.  Both solve alike."""
-    A = P.poisson2d(400)
-    b = dev_vec(P.rhs(A, P.exact_solution(A.n, 1)))
-    ht, _ = _setup(A, 2, precision=precision)
-    hs, _ = _setup(A, 2, precision=precision, flags=4)
-    assert ht.num_levels() >= 4
-    xt, it_t, rel_t = amg.solve(ht, b, 1e-8)
-    xs, it_s, rel_s = amg.solve(hs, b, 1e-8)
-    assert rel_t <= 1e-8 and rel_s <= 1e-8 and abs(it_t - it_s) <= 1
-    assert float(torch.linalg.norm(xt - xs) / torch.linalg.norm(xs)) < 1e-7
