@@ -192,6 +192,51 @@ def batch_form(amg, torch, P, reps=2):
     return out
 
 
+def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
+    """C5 -> C3: the per-row Jacobi weight network trained with the library's
+    own kernels on heterogeneous-diffusion 64^3 fields (seeds 100..), errors
+    generated by the solver itself, then evaluated on the 160^3 field (seed 2)
+    against the plain method, FP64 and mixed."""
+    from paper_1403_1649_amd import learned as Ld
+    t0 = time.perf_counter()
+    systems = []
+    for q in range(train_fields):
+        At = P.hetero3d(64, seed=100 + q)
+        dt = tuple(torch.from_numpy(a).cuda() for a in (At.row_ptr, At.col, At.val))
+        ht = amg.setup(*dt, amg.Options(dim=3))
+        systems.append((ht, Ld.solver_errors(ht, At, P.exact_solution(At.n, 1))))
+    w = Ld.train(systems, steps=steps, lr=3e-3, samples=8)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del systems
+    A = P.hetero3d(160, seed=2)
+    b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+    dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+    x = torch.empty_like(b)
+    out = {"workload": f"C3 heterogeneous FV 160^3 (n={A.n}); network trained on {train_fields} C5 fields 64^3",
+           "train_steps": steps, "train_s": round(train_s, 2)}
+    for name, kw in (("plain_fp64", {}), ("plain_mixed", {"precision": "mixed"}),
+                     ("learned_fp64", {"mlp_weights": w}), ("learned_mixed", {"precision": "mixed", "mlp_weights": w})):
+        best, info = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            h = amg.setup(*dev, amg.Options(dim=3, **kw))
+            _, it, rel = amg.solve(h, b, 1e-8, x=x)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t1
+            s_ms, v_ms = h.timings()
+            kept = [int(h.smoother_info(k)[0]) for k in range(h.num_levels() - 1)] if "mlp_weights" in kw else None
+            del h
+            if best is None or t < best:
+                best, info = t, (it, rel, s_ms, v_ms, kept)
+        out[name] = {"mdof_s": round(A.n / best / 1e6, 3) if info[1] <= 1e-8 else 0.0, "iters": info[0],
+                     "relres": info[1], "setup_ms": round(info[2], 2), "solve_ms": round(info[3], 2)}
+        if info[4] is not None:
+            out[name]["learned_levels"] = info[4]
+    return out
+
+
 def cpu_baseline(A, dim, b):
     from threadpoolctl import threadpool_limits
 
@@ -217,6 +262,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched C4b form and print its JSON (for profiling)")
     ap.add_argument("--print-source-hash", action="store_true",
@@ -287,6 +333,9 @@ def main():
     if not args.no_batch:
         log("bench: batched form (C4b)")
         forms["batch"] = batch_form(amg, torch, P)
+    if not args.no_learned:
+        log("bench: learned smoother form (C5 -> C3)")
+        forms["learned"] = learned_form(amg, torch, P)
 
     # device copy bandwidth (reference for the attainable HBM rate): 1 GiB read + 1 GiB written
     src_c = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
