@@ -152,7 +152,7 @@ int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double 
  * sys_off[nsys] = n and every system nonempty.  A: device CSR (copied).
  * opt: (host) options, NULL for amg_default_options(dim=2); the batch uses
  * flexible CG and the Jacobi smoother without probe (EUNSUPPORTED otherwise);
- * flags are ignored.
+ * of the flags only AMG_FLAG_NO_GRAPH applies.
  * amg_solve on such a hierarchy runs one outer flexible CG per system with
  * per-system scalars and stopping test (||b_q - A_q x_q|| <= rtol ||b_q||); it
  * returns the largest iteration count and relative residual over the systems

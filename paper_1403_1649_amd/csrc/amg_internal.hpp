@@ -302,6 +302,7 @@ void batch_arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, const int* m
 void batch_jacobi_weights(const Level& lv, const double* omega_sys, double* wdinv, float* wdinv32,
                           hipStream_t s);
 void batch_control(Hierarchy& h);
+void build_batch_graphs(Hierarchy& h);
 int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
 // dense.hip: inverses of the terminal systems of a level, one workgroup each
 void launch_dense_inverse_batched(const Level& lv, int nterm, const TermInfo* d_term, const TermInfo* h_term,

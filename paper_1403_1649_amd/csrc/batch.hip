@@ -1079,6 +1079,54 @@ void batch_control(Hierarchy& h) {
   launch_fill_double((size_t)bSlots * nsys, h.b_sc, 0.0, h.stream);
 }
 
+// One outer iteration and the (re)start sequence captured as HIP graphs on a
+// capture stream (the kernels read every branch decision from device flags,
+// so one recording serves every replay).
+void build_batch_graphs(Hierarchy& h) {
+  hipStream_t user = h.stream;
+  hipStream_t cs = nullptr;
+  AMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const bool mixed = h.mixed();
+  auto finish = [&](hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    AMG_HIP(hipStreamEndCapture(cs, &g));
+    AMG_HIP(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    AMG_HIP(hipGraphDestroy(g));
+  };
+  try {
+    h.stream = cs;
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (mixed) iteration_b<float>(h);
+    else iteration_b<double>(h);
+    hipGraphExec_t it = nullptr;
+    finish(&it);
+    h.g_iter.push_back(it);
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (mixed) restart_b<float>(h);
+    else restart_b<double>(h);
+    finish(&h.g_restart);
+  } catch (...) {
+    h.stream = user;
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  h.stream = user;
+  AMG_HIP(hipStreamDestroy(cs));
+}
+
+namespace {
+void launch_iteration_b(Hierarchy& h) {
+  if (!h.g_iter.empty()) AMG_HIP(hipGraphLaunch(h.g_iter[0], h.stream));
+  else if (h.mixed()) iteration_b<float>(h);
+  else iteration_b<double>(h);
+}
+void launch_restart_b(Hierarchy& h) {
+  if (h.g_restart) AMG_HIP(hipGraphLaunch(h.g_restart, h.stream));
+  else if (h.mixed()) restart_b<float>(h);
+  else restart_b<double>(h);
+}
+}  // namespace
+
 // ---------------------------------------------------------------- solve
 // Outer flexible CG per system from x_0 = 0; iters / relres: host [nsys].
 int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres) {
@@ -1093,18 +1141,14 @@ int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int*
   std::vector<double> hsc((size_t)bArn * nsys);
   std::vector<int> again(nsys);
   belem(l0, c, BFcgInit{all, b, h.r, h.xint, h.b_sc, h.b_fl, h.b_any, h.d_err, rtol, nsys}, s);
-  if (mixed) restart_b<float>(h);
-  else restart_b<double>(h);
+  launch_restart_b(h);
   const int max_iter = h.opt.max_iter;
   int enqueued = 0;
   int status = AMG_OK;
   int* hp = static_cast<int*>(h.h_pinned);
   while (true) {
     const int batch = std::min(4, max_iter - enqueued);
-    for (int i = 0; i < batch; ++i) {
-      if (mixed) iteration_b<float>(h);
-      else iteration_b<double>(h);
-    }
+    for (int i = 0; i < batch; ++i) launch_iteration_b(h);
     enqueued += batch;
     AMG_HIP(hipGetLastError());
     AMG_HIP(hipMemcpyAsync(hp, h.b_any + aRun, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1139,8 +1183,7 @@ int solve_batch_impl(Hierarchy& h, const double* b, double rtol, double* x, int*
     launch_fill_int(1, h.b_any + aRun, 1, s);
     belem(l0, c, BCopy{Mask{nullptr, h.b_again}, h.q, h.r}, s);
     AMG_HIP(hipStreamSynchronize(s));   // the pageable `again` is read before it changes
-    if (mixed) restart_b<float>(h);
-    else restart_b<double>(h);
+    launch_restart_b(h);
   }
   AMG_HIP(hipMemcpyAsync(x, h.xint, (size_t)l0.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));

@@ -831,6 +831,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
   sy.wait_and_check();
+  if (!(o.flags & AMG_FLAG_NO_GRAPH)) build_batch_graphs(h);
 }
 
 }  // namespace amg

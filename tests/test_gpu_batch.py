@@ -179,3 +179,17 @@ def test_c4b_full_size_sampled():
         H = O.setup(m.row_ptr, m.col, m.val, O.Options.for_dim(2))
         ref = O.solve(H, b[lo:hi])
         assert abs(int(its[q]) - ref.iters) <= 2, (q, its[q], ref.iters)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager_launches(precision):
+    mats = [P.poisson2d(41), P.poisson2d(29), P.aniso2d(33, 1e-3)]
+    Abd, off, hg = _batched(mats, precision=precision)
+    _, _, he = _batched(mats, precision=precision, flags=1)
+    b = dev_vec(P.rhs(Abd, P.exact_solution(Abd.n, 6)))
+    xg, _, _ = amg.solve(hg, b, 1e-8)
+    itg, relg = hg.batch_results()
+    xe, _, _ = amg.solve(he, b, 1e-8)
+    ite, rele = he.batch_results()
+    assert np.array_equal(itg, ite) and np.array_equal(relg, rele)
+    assert torch.equal(xg, xe)
