@@ -84,6 +84,10 @@ typedef struct {
 /* amg_options.flags: skip the per-level kernel autotuner (CSR kernels with
  * lanes per row from the average row length). */
 #define AMG_FLAG_NO_TUNE 2u
+/* amg_options.flags: with AMG_SMOOTHER_LEARNED, keep the learned weights on
+ * every level without the setup-time comparison against plain omega_k (for
+ * weights already validated by the caller on actual solves). */
+#define AMG_FLAG_LEARNED_ALWAYS 8u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {
@@ -210,10 +214,15 @@ int32_t amg_mlp_omega(const amg_hierarchy* h, int32_t k, const float* w, double*
  * coarse-space component removed (e = v - P P^T v): v = unit_uniform(i,
  * seed + s) for the first nsamples and the caller's device [n_k][n_extra]
  * row-major block `extra` for the rest.  loss: (host).  grad (device float
- * [1409], may be NULL): dL/dw, added to grad when accumulate != 0.
- * 1 <= S <= 64.  Synchronises s. */
+ * [1409], may be NULL): dL/dw.  flags: bit 0 (AMG_MLP_ACCUMULATE) adds to
+ * grad instead of overwriting it; bit 1 (AMG_MLP_RAW_EXTRA) uses the extra
+ * samples as given, without removing their coarse-space component (for
+ * errors that the solver itself left, which the coarse correction has
+ * already acted on).  1 <= S <= 64.  Synchronises s. */
+#define AMG_MLP_ACCUMULATE 1
+#define AMG_MLP_RAW_EXTRA 2
 int32_t amg_mlp_loss_grad(const amg_hierarchy* h, int32_t k, const float* w, int32_t nsamples, uint32_t seed,
-                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t accumulate,
+                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t flags,
                           hipStream_t s);
 
 /* Adam step on device arrays of n floats: m = b1 m + (1-b1) g,

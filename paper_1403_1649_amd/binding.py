@@ -402,12 +402,15 @@ def mlp_omega(h: Hierarchy, k: int, w):
 
 
 def mlp_loss_grad(h: Hierarchy, k: int, w, nsamples: int, seed: int, extra=None, grad=None,
-                  accumulate: bool = False) -> float:
+                  accumulate: bool = False, raw_extra: bool = False) -> float:
+    """Smoothing loss (and gradient into grad); raw_extra: use the extra
+    samples without removing their coarse-space component."""
     loss = C.c_double()
     n_extra = 0 if extra is None else int(extra.shape[1])
+    flags = (1 if accumulate else 0) | (2 if raw_extra else 0)
     _check(lib().amg_mlp_loss_grad(h.handle, k, _ptr(w), int(nsamples), int(seed) & 0xFFFFFFFF,
                                    None if extra is None else _ptr(extra), n_extra, C.byref(loss),
-                                   None if grad is None else _ptr(grad), int(bool(accumulate)), _stream()))
+                                   None if grad is None else _ptr(grad), flags, _stream()))
     return loss.value
 
 

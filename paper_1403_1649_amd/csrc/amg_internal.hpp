@@ -286,7 +286,7 @@ void mlp_omega(Hierarchy& h, const Level& lv, const float* F, const double* beta
                double* wdinv, float* wdinv32, double* sig);
 double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const float* wdev, int S_rand,
                      uint32_t seed, const double* extra, int S_extra, const double* omega_fixed, float* grad,
-                     int accumulate);
+                     int accumulate, bool raw_extra = false);
 void mlp_adam(float* w, float* m, float* v, const float* g, int n, int step, float lr, float b1, float b2, float eps,
               hipStream_t s);
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres);

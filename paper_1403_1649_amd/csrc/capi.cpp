@@ -419,7 +419,7 @@ int32_t amg_mlp_omega(const amg_hierarchy* H, int32_t k, const float* w, double*
 }
 
 int32_t amg_mlp_loss_grad(const amg_hierarchy* H, int32_t k, const float* w, int32_t nsamples, uint32_t seed,
-                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t accumulate,
+                          const double* extra, int32_t n_extra, double* loss, float* grad, int32_t flags,
                           hipStream_t s) {
   if (!level_ok(H, k) || !w || !loss || nsamples < 0 || n_extra < 0 || (n_extra > 0 && !extra) ||
       nsamples + n_extra < 1 || nsamples + n_extra > 64)
@@ -431,7 +431,8 @@ int32_t amg_mlp_loss_grad(const amg_hierarchy* H, int32_t k, const float* w, int
     h.stream = s;
     amg::Arena tmp;
     struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
-    *loss = amg::mlp_loss_grad(h, tmp, h.levels[k], k, w, nsamples, seed, extra, n_extra, nullptr, grad, accumulate);
+    *loss = amg::mlp_loss_grad(h, tmp, h.levels[k], k, w, nsamples, seed, extra, n_extra, nullptr, grad,
+                               flags & AMG_MLP_ACCUMULATE, (flags & AMG_MLP_RAW_EXTRA) != 0);
     h.stream = keep;
   });
 }

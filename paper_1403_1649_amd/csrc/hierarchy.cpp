@@ -515,15 +515,19 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
     launch_jacobi_weights(n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, s);
     if (o.smoother == AMG_SMOOTHER_LEARNED) {
-      // learned per-row weights, kept only when they smooth better than omega_k
-      const double* plain_om = nullptr;
-      double* omv = tmp.alloc_n<double>(n);
-      launch_fill_double(n, omv, lv.omega, s);
-      plain_om = omv;
+      // learned per-row weights, kept only when they smooth better than
+      // omega_k on validation samples (or always, when the caller says so)
+      const bool always = (o.flags & AMG_FLAG_LEARNED_ALWAYS) != 0;
       Arena vt;
-      lv.loss_plain = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, plain_om, nullptr, 0);
-      lv.loss_learned = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, nullptr, nullptr, 0);
-      if (std::isfinite(lv.loss_learned) && lv.loss_learned < lv.loss_plain) {
+      bool keep = always;
+      if (!always) {
+        double* omv = vt.alloc_n<double>(n);
+        launch_fill_double(n, omv, lv.omega, s);
+        lv.loss_plain = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, omv, nullptr, 0);
+        lv.loss_learned = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, nullptr, nullptr, 0);
+        keep = std::isfinite(lv.loss_learned) && lv.loss_learned < lv.loss_plain;
+      }
+      if (keep) {
         float* F = vt.alloc_n<float>((size_t)n * 9);
         double* beta = vt.alloc_n<double>(n);
         mlp_features(h, lv, k, F, beta);

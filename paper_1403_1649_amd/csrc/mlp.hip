@@ -152,12 +152,13 @@ __global__ void k_err_restrict(int nc, int S, const int* __restrict__ agg_ptr, c
   C[t] = acc;
 }
 
-__global__ void k_err_project(int n, int S, const int* __restrict__ agg, const double* __restrict__ pval,
+// e_s -= P (P^T e_s) for the first S_proj samples (the others stay as given)
+__global__ void k_err_project(int n, int S, int S_proj, const int* __restrict__ agg, const double* __restrict__ pval,
                               const double* __restrict__ C, double* __restrict__ E) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)n * S) return;
   const int i = (int)(t / S), s = (int)(t - (long)i * S);
-  E[t] -= pval[i] * C[(size_t)agg[i] * S + s];
+  if (s < S_proj) E[t] -= pval[i] * C[(size_t)agg[i] * S + s];
 }
 
 // Y = A X for a [n][S] block (thread per entry)
@@ -352,7 +353,7 @@ void mlp_omega(Hierarchy& h, const Level& lv, const float* F, const double* beta
 // `tmp`.  Returns the loss (synchronises); grad (device, kNP) when non-null.
 double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const float* wdev, int S_rand,
                      uint32_t seed, const double* extra, int S_extra, const double* omega_fixed, float* grad,
-                     int accumulate) {
+                     int accumulate, bool raw_extra) {
   hipStream_t s = h.stream;
   const int n = lv.n, S = S_rand + S_extra;
   if (S < 1 || S > 64) throw Error(AMG_EINVAL, "1 to 64 error samples");
@@ -368,7 +369,7 @@ double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const
   double* dpart = tmp.alloc_n<double>((size_t)64 * nbd);
   k_err_raw<<<nblk((long)nS), 256, 0, s>>>(n, S, S_rand, seed, extra, E);
   k_err_restrict<<<nblk((long)lv.nc * S), 256, 0, s>>>(lv.nc, S, lv.agg_ptr, lv.agg_rows, lv.pval, E, C);
-  k_err_project<<<nblk((long)nS), 256, 0, s>>>(n, S, lv.agg, lv.pval, C, E);
+  k_err_project<<<nblk((long)nS), 256, 0, s>>>(n, S, raw_extra ? S_rand : S, lv.agg, lv.pval, C, E);
   k_spmm_simple<<<nblk((long)nS), 256, 0, s>>>(n, S, lv.rp, lv.ci, lv.val, E, AE);
   k_coldot_part<<<nbd, 256, 0, s>>>(n, S, E, AE, dpart);
   k_coldot_final<<<1, 64, 0, s>>>(S, nbd, dpart, ee);

@@ -121,3 +121,28 @@ def test_learned_setup_rejects_bad_weights():
     w[5] = np.nan
     with pytest.raises(amg.AmgError):
         _setup(A, mlp_weights=w)
+
+
+def test_raw_extra_samples_and_learned_always():
+    """AMG_MLP_RAW_EXTRA: the caller's samples enter the loss unprojected (the
+    oracle's loss on [projected random | raw extra]); AMG_FLAG_LEARNED_ALWAYS
+    keeps the learned weights on every level without validation."""
+    A = P.hetero3d(12, seed=13)
+    h = _setup(A)
+    w = _weights(5)
+    wd = torch.from_numpy(w).cuda()
+    ex = h.export_level(0)
+    S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+    F = amg.mlp_features(h, 0).cpu().numpy().astype(np.float64)
+    extra = np.random.default_rng(3).standard_normal((A.n, 2))
+    E = np.concatenate([M.projected_errors(S, ex["agg"], ex["pval"], ex["nc"], 4, 21), extra], axis=1)
+    lo, go = M.loss_and_grad(w.astype(np.float64), S, F, E)
+    g = torch.zeros_like(wd)
+    loss = amg.mlp_loss_grad(h, 0, wd, 4, 21, torch.from_numpy(extra).cuda(), g, raw_extra=True)
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert np.linalg.norm(g.cpu().numpy() - go) <= 1e-4 * np.linalg.norm(go)
+    hl = _setup(A, mlp_weights=w, flags=8)
+    assert all(hl.smoother_info(k)[0] for k in range(hl.num_levels() - 1))
+    b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+    _, it, rel = amg.solve(hl, b, 1e-8)
+    assert rel <= 1e-8
