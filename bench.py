@@ -369,7 +369,7 @@ def main():
     gbs = nbytes / t_spmv / 1e9
 
     line = {
-        "metric": "setup+solve MDOF/s to rel-res 1e-8 (FP64; mixed reported beside)",
+        "metric": "setup+solve MDOF/s to rel-res 1e-8, FP64 vs mixed/batched/learned; SpMV GB/s",
         "value": round(value, 3), "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",

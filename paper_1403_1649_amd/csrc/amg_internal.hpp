@@ -64,6 +64,15 @@ class Arena {
   size_t used_ = 0;
 };
 
+// Scratch of the single-pass device scan: one status word per tile, then the
+// 64-bit ticket counter (zero between calls); the call epoch.
+struct ScanCtx {
+  uint64_t* status = nullptr;
+  unsigned long long* ticket = nullptr;
+  int max_blocks = 0;
+  uint32_t epoch = 1;
+};
+
 // ---------------------------------------------------------------- records
 struct TermInfo;
 
@@ -159,7 +168,8 @@ struct Hierarchy {
   double* d_sc = nullptr;      // scalar slots (dots, coefficients)
   double* d_part = nullptr;    // per-block partial sums of reductions
   unsigned* d_ticket = nullptr;// last-block tickets
-  int* d_scan = nullptr;       // block sums of device scans
+  ScanCtx scan;                // look-back words of device scans
+  int* d_mis = nullptr;        // MIS(2) round counters (kMisWords ints)
   // pinned host mirror for read-backs
   void* h_pinned = nullptr;
   // outer solve vectors (float64, size n_0)
@@ -201,10 +211,8 @@ struct Hierarchy {
 enum CtlWord : int {
   kCtlRunning = 0,     // outer iteration active
   kCtlIters = 1,       // outer iterations performed
-  kCtlMisPing = 2,     // "some node undecided" flags of MIS(2) rounds (two words)
-  kCtlMisRounds = 4,   // rounds that found undecided nodes
   kCtlOne = 5,         // constant 1 (an always-active flag)
-  kCtlAggFill = 6,     // scratch counter
+  kCtlAggFill = 6,     // scratch counters of the Galerkin tiers (two words)
   kCtlKFlags = 16,     // per level k: [16 + 4k] step-2 flag, [17 + 4k] use-d flag
   kCtlWords = 128,
 };
@@ -219,31 +227,57 @@ enum KSlot : int {
   kKAlpha2 = 6, kKCoefC = 7, kKCoefD = 8,
 };
 constexpr int kMaxPartialBlocks = 2048;
+// pinned host mirror: ints 0..63 for control read-backs, then (in doubles
+// from kPinnedArn) 64 per level for Arnoldi results
+constexpr int kPinnedArn = 64;
+constexpr size_t kPinnedBytes = (kPinnedArn + 64 * 24) * sizeof(double);
 constexpr int kBlockRowsGemv = 4;   // rows per 256-thread block of a dense GEMV (one wave per row)
 
 // ---------------------------------------------------------------- launchers
 // scan.hip
-void scan_to_ptr(const int* counts, int* ptr, int n, int* block_sums, hipStream_t s);
+void init_scan(ScanCtx& sc, Arena& arena, int nmax, hipStream_t s);
+void scan_to_ptr(const int* counts, int* ptr, int n, ScanCtx& sc, hipStream_t s);
 int scan_blocks_needed(int n);
 
 // setup_kernels.hip
 void launch_check_rowptr(int n, const int* rp, int* err, hipStream_t s);
 void launch_check_index(int n, const int* idx, int limit, int* err, hipStream_t s);
 void launch_check_matrix(int n, const int* rp, const int* ci, const double* val, int* err, hipStream_t s);
-void launch_strength(int n, const int* rp, const int* ci, const double* val, double alpha,
-                     uint8_t* strong, double* diag, int* err, hipStream_t s);
-void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* strong,
+// Up to 8 device ints copied to host pinned slots (0..62) by one launch,
+// together with the error word (slot 63).
+struct Mailbox {
+  const int* src[8];
+  int slot[8];
+  int count[8];    // the slot receives the sum of count ints at this stride
+  int stride[8];
+  int n;
+};
+void launch_mailbox(const Mailbox& m, const int* err, int* host, hipStream_t s);
+// Lanes per row of the row-group setup kernels: about four entries per lane,
+// more on small levels so that a launch still covers the chip.
+int group_lanes(int n, long entries);
+void launch_strength(int n, int nnz, const int* rp, const int* ci, const double* val, double alpha,
+                     uint8_t* strong, double* diag, hipStream_t s);
+void launch_graph_count(int n, int nnz, const int* rp, const int* ci, const uint8_t* strong,
                         uint8_t* gmask, int* gdeg, int* cnt, int* err, hipStream_t s);
-void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask,
+void launch_graph_fill(int n, int nnz, const int* rp, const int* ci, const uint8_t* gmask,
                        const int* gptr, int* gcol, hipStream_t s);
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* ctl, int* err,
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* mc, int* err,
                      hipStream_t s, const int* lbase = nullptr);
-// one MIS(2) round (two sweeps and the undecided flag); block_flag: 2048 ints
-void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,
-                      int lanes, int* block_flag, hipStream_t s);
+// MIS(2) round counters (int array of kMisWords, touched only by atomics):
+// per round parity, 64 counters of blocks that left a node undecided, each
+// in a 128-byte line of its own; then the number of rounds that found one.
+constexpr int kMisSlots = 64;
+__host__ __device__ constexpr int mis_word(int parity, int slot) { return (parity * kMisSlots + slot) * 32; }
+constexpr int kMisRoundsWord = 2 * kMisSlots * 32;
+constexpr int kMisWords = kMisRoundsWord + 32;
+// one MIS(2) round (two sweeps; the second counts the blocks that left a node
+// undecided, for the next round's early exit)
+void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc, int round,
+                      int lanes, hipStream_t s);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
-void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T,
-                      const int* root_id, int* choice, int* agg, int* err, hipStream_t s);
+void launch_aggregate(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
+                      int* choice, int* agg, int* err, hipStream_t s);
 void launch_agg_count(int n, const int* agg, int* counts, hipStream_t s);
 void launch_agg_scatter(int n, const int* agg, const int* agg_ptr, int* fill, int* agg_rows, hipStream_t s);
 void launch_agg_sort(int nc, const int* agg_ptr, int* agg_rows, hipStream_t s);
@@ -260,19 +294,38 @@ void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s);
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
                       int* sl_col, double* sl_val, float* sl_val32, hipStream_t s);
 
-// galerkin.hip
-void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
-                           const int* agg_rows, int* row_count, int* ovf_list, int* ctl_ovf, hipStream_t s);
-void launch_galerkin_fill(int nc, const int* rp, const int* ci, const double* val, const int* agg,
-                          const double* pval, const int* agg_ptr, const int* agg_rows,
-                          const int* rp_c, int* ci_c, double* val_c, const int* ovf_list,
-                          const int* ctl_ovf, hipStream_t s);
+// galerkin.hip: scratch of one Galerkin product (n fine rows, nnz entries,
+// nc coarse rows): lens[n], inv[n], toff[n+1], tkey[nnz], tval[nnz],
+// ucount[nc], list[2 nc], ctl: two counters.
+struct GalerkinScratch {
+  int* lens;
+  int* inv;
+  int* toff;
+  int* tkey;
+  double* tval;
+  int* ucount;
+  int* list;
+  int* ctl;
+};
+void launch_galerkin_stage(const GalerkinScratch& g, int n, int nc, int nnz, const int* rp, const int* ci,
+                           const double* val, const int* agg, const double* pval, const int* agg_ptr,
+                           const int* agg_rows, ScanCtx& sc, hipStream_t s);
+void launch_galerkin_finish(const GalerkinScratch& g, int nc, const int* agg_ptr, const int* rp_c, int* ci_c,
+                            double* val_c, hipStream_t s);
 
 // dense.hip
 void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val, double* work,
                           double* inv, float* inv32, int* sync, int* err, hipStream_t s);
 
 // arnoldi / reductions (solve_kernels.hip)
+// Reduction context of the solve-phase kernels: per-block partials and the
+// arrival counter of the in-kernel finalize (zero between kernels).
+struct RedCtx {
+  double* part;       // kMaxPartialBlocks * 4 doubles
+  unsigned* ticket;
+};
+void arnoldi_enqueue(Hierarchy& h, const Level& lv, int m, uint32_t stream, double* Q, double* w, double* sc,
+                     RedCtx rc, double* host_out, hipStream_t s);
 void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double* w, double* H_out,
              double* wnorm_out);
 

@@ -998,7 +998,7 @@ void batch_build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
   AMG_HIP(hipMemcpyAsync(lv.sl_base, base.data(), base.size() * sizeof(int), hipMemcpyHostToDevice, s));
   const int g = (nsl + kBlock / kWave - 1) / (kBlock / kWave);
   k_bsell_widths<<<g, kBlock, 0, s>>>(nsl, d_srow, lv.rp, widths);
-  scan_to_ptr(widths, lv.sl_ptr, nsl, h.d_scan, s);
+  scan_to_ptr(widths, lv.sl_ptr, nsl, h.scan, s);
   int total = 0;
   AMG_HIP(hipMemcpyAsync(&total, lv.sl_ptr + nsl, sizeof(int), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));

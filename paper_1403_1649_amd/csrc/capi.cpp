@@ -317,7 +317,7 @@ int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per
       amg::Hierarchy h;
       h.stream = s;
       amg::init_control(h);
-      h.d_scan = h.arena.alloc_n<int>(amg::scan_blocks_needed(A->n) + 2);
+      amg::init_scan(h.scan, h.arena, A->n, s);
       amg::spmv_sell_f64(h, *A, x, y);
     });
   }
@@ -347,7 +347,7 @@ int32_t amg_galerkin(const amg_csr* A, const int32_t* agg, const double* pval, i
     h.stream = s;
     h.opt.dense_max = 1;
     amg::init_control(h);
-    h.d_scan = h.arena.alloc_n<int>(amg::scan_blocks_needed(A->nnz > A->n ? A->nnz : A->n) + 2);
+    amg::init_scan(h.scan, h.arena, A->nnz > A->n ? A->nnz : A->n, s);
     int *rp = nullptr, *ci = nullptr;
     double* v = nullptr;
     int nz = 0;

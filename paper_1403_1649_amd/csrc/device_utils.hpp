@@ -1,6 +1,9 @@
 // Device-side primitives shared by the HIP kernels (wave64 CDNA4).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
 #include <stdint.h>
 
 namespace amg {
@@ -103,6 +106,68 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
   *total = tmp[nw];
   __syncthreads();
   return res;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// This bijection of [0, gridDim.x) gives every XCD a contiguous run of
+// logical blocks, so rows that gather from overlapping neighbourhoods share
+// an L2 (XCD x holds the blocks b = 8 s + x).
+__device__ __forceinline__ int xcd_block_index() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if (g < 8) return b;
+  const int x = b & 7, f = g >> 3, r = g & 7;
+  return x * f + (x < r ? x : r) + (b >> 3);
+}
+
+// Rows by groups of G lanes (G divides the wave): group id and lane of this
+// thread, and the group-wide reductions the row kernels use.
+template <int G>
+struct RowGroup {
+  long gid, ngroups;
+  int lane;
+  __device__ RowGroup()
+      : gid(((long)xcd_block_index() * blockDim.x + threadIdx.x) / G),
+        ngroups((long)gridDim.x * blockDim.x / G),
+        lane(threadIdx.x & (G - 1)) {}
+  __device__ static int sum(int v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+  }
+  __device__ static double max(double v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off, G);
+      v = o > v ? o : v;
+    }
+    return v;
+  }
+  // bits of this group's lanes in a wave ballot
+  __device__ static uint64_t group_bits(uint64_t ballot) {
+    if (G == 64) return ballot;
+    const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+    return (ballot >> shift) & ((1ull << G) - 1);
+  }
+};
+
+
+// Grid for n rows at G lanes each (256-thread blocks, grid-stride beyond).
+inline int group_grid(int n, int G) {
+  long b = ((long)n * G + 255) / 256;
+  if (b < 1) b = 1;
+  return (int)(b < 65536 ? b : 65536);
+}
+// Calls f(std::integral_constant<int, G>) for G = the lanes per row.
+template <typename F>
+void with_lanes(int G, F&& f) {
+  switch (G) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 16: f(std::integral_constant<int, 16>()); break;
+    default: f(std::integral_constant<int, 32>()); break;
+  }
 }
 
 // Device-scope atomic helpers.

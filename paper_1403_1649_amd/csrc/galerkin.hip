@@ -1,14 +1,23 @@
 // Galerkin product by aggregate index (Section 3.1, eq. galerkin):
 //   (A_{k+1})_IJ = sum_{i in G_I} sum_{j in G_J} P_iI A_ij P_jJ.
 // Instead of a global sort of all (I, J) tuples, each coarse row I is built
-// from its own aggregate segment G_I: the terms (J, (P_iI a_ij) P_jJ) of the
-// segment's fine rows are staged in LDS, unique J are found with an LDS hash
-// (first occurrence wins, so the result does not depend on timing), and each
-// coarse entry is the sum of its terms in segment order.  A count pass sizes
-// the rows, a scan makes the row pointers, a fill pass writes sorted columns.
-// Rows whose segment holds more than 256 terms are staged by a whole block
-// (up to 1536 terms); larger ones go to a block-per-row path that extracts
-// the distinct J in ascending order without staging.
+// from its own aggregate segment G_I, in four steps:
+//   1. term offsets: the entries of the fine rows, taken in segment order
+//      (aggregate by aggregate, members ascending, entries in column order),
+//      are numbered by a scan of the row lengths;
+//   2. expand (one streaming pass over A in row order): every entry (i, j)
+//      becomes the term (J = agg(j), (P_iI a_ij) P_jJ) at its number, so the
+//      terms of coarse row I are contiguous;
+//   3. reduce: one wave per coarse row holds the row's terms in registers,
+//      finds the distinct J with an LDS hash, places every term after the
+//      earlier terms of the same J (ballot peeling within a chunk of 64), and
+//      sums each J's terms in segment order; the sorted (J, sum) pairs
+//      overwrite the head of the row's term range;
+//   4. a scan of the distinct counts makes the row pointers and a copy
+//      compacts the rows.
+// Each coarse entry is the sum of its terms in segment order, so the result
+// does not depend on timing.  Rows with more terms than a wave holds go to a
+// wider wave, and the rare rows beyond that to a block-per-row extraction.
 #include <climits>
 
 #include "amg_internal.hpp"
@@ -17,109 +26,166 @@
 namespace amg {
 
 namespace {
-constexpr int kBig = 256;       // threads per block on the large-row path
+constexpr int kBig = 256;        // threads per block on the extraction path
+constexpr int kSmallC = 2;       // terms per lane of the first reduce pass
+constexpr int kWideC = 8;        // terms per lane of the second
+constexpr int kMaxWaveTerms = kWave * kWideC;
 
-// One coarse row per group of NT threads (NT = 64: a wave; NT = 256: a block).
-// Terms are staged in LDS up to CAP; rows with more terms go to the next
-// overflow list in the count pass and are skipped in the fill pass.
-template <int NT, int CAP, int HB, bool FILL, bool LISTED>
-__global__ void __launch_bounds__(NT) k_galerkin_stage(
-    int nc, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
-    const int* __restrict__ agg, const double* __restrict__ pval, const int* __restrict__ agg_ptr,
-    const int* __restrict__ agg_rows, int* __restrict__ row_count, const int* __restrict__ in_list,
-    const int* __restrict__ in_count, int* __restrict__ out_list, int* __restrict__ out_count,
-    const int* __restrict__ rp_c, int* __restrict__ ci_c, double* __restrict__ val_c) {
-  constexpr int HS = 1 << HB;
-  __shared__ int keys[CAP];
-  __shared__ double vals[FILL ? CAP : 1];
-  __shared__ int hkey[HS];
-  __shared__ int hfirst[HS];
-  __shared__ int ukeys[CAP];
-  __shared__ int tmp[NT / kWave + 1];
-  __shared__ int s_cnt;
-  __shared__ int m_start[NT], m_off[NT + 1];   // staging: member rows of one step
-  __shared__ double m_pi[FILL ? NT : 1];
-  const int tid = threadIdx.x;
-  const int count = LISTED ? *in_count : nc;
-  for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-    const int I = LISTED ? in_list[idx] : idx;
-    const int sb = agg_ptr[I], se = agg_ptr[I + 1];
-    int T = 0;
-    for (int base = sb; base < se; base += NT) {
-      const int k = base + tid;
-      int len = 0;
-      if (k < se) { const int i = agg_rows[k]; len = rp[i + 1] - rp[i]; }
-      int tot;
-      (void)block_exclusive_scan(len, tmp, &tot);
-      T += tot;
+// Step 1: number of terms of the k-th fine row in segment order (0 beyond the
+// rows that belong to an aggregate), and the inverse of the member order.
+__global__ void k_gal_lens(int n, const int* __restrict__ rp, const int* __restrict__ agg_ptr, int nc,
+                           const int* __restrict__ agg_rows, int* __restrict__ lens, int* __restrict__ inv) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int len = 0;
+  if (k < agg_ptr[nc]) {
+    const int i = agg_rows[k];
+    len = rp[i + 1] - rp[i];
+    inv[i] = k;
+  }
+  lens[k] = len;
+}
+
+// Step 2: the terms of fine row i at toff[inv[i]] .. + its length; rows are
+// read in their own order (streaming), the short runs of terms scattered.
+template <int G>
+__global__ void __launch_bounds__(256) k_gal_expand(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ val, const int* __restrict__ agg,
+                                                    const double* __restrict__ pval, const int* __restrict__ inv,
+                                                    const int* __restrict__ toff, int* __restrict__ tkey,
+                                                    double* __restrict__ tval) {
+  RowGroup<G> rg;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    if (agg[i] < 0) continue;   // a row of a system that is not coarsened
+    const int s = rp[i], e = rp[i + 1];
+    const int o = toff[inv[i]] - s;
+    const double pi = pval[i];
+    for (int x = s + rg.lane; x < e; x += G) {
+      const int j = ci[x];
+      tkey[o + x] = agg[j];
+      tval[o + x] = __dmul_rn(__dmul_rn(pi, val[x]), pval[j]);
     }
+  }
+}
+
+// Step 3 for rows of at most 64*C terms, one wave per row (HS hash slots).
+// Rows with more terms are appended to out_list.
+template <int C, bool LISTED>
+__global__ void __launch_bounds__(kWave) k_gal_reduce(int nc, const int* __restrict__ agg_ptr,
+                                                      const int* __restrict__ toff, int* __restrict__ tkey,
+                                                      double* __restrict__ tval, int* __restrict__ ucount,
+                                                      const int* __restrict__ in_list,
+                                                      const int* __restrict__ in_count, int* __restrict__ out_list,
+                                                      int* __restrict__ out_count) {
+  constexpr int CAP = kWave * C;
+  constexpr int HS = CAP;   // U <= CAP, so linear probing always ends
+  constexpr int HB = C == 1 ? 6 : C == 2 ? 7 : C == 4 ? 8 : C == 8 ? 9 : 10;
+  static_assert((1 << HB) == HS, "C must be a power of two up to 16");
+  __shared__ int hkey[HS], hcnt[HS], hrun[HS], hrank[HS];
+  __shared__ int ukey[CAP], skey[CAP], sbase[CAP + 1];
+  __shared__ double sv[CAP];
+  const int lane = threadIdx.x;
+  const uint64_t below = (1ull << lane) - 1;
+  const int count = LISTED ? *in_count : nc;
+  for (int idx = xcd_block_index(); idx < count; idx += gridDim.x) {
+    const int I = LISTED ? in_list[idx] : idx;
+    const int t0 = toff[agg_ptr[I]];
+    const int T = toff[agg_ptr[I + 1]] - t0;
     if (T > CAP) {
-      if (!FILL && tid == 0) out_list[atomicAdd(out_count, 1)] = I;
+      if (lane == 0) out_list[atomicAdd(out_count, 1)] = I;
       continue;
     }
-    for (int q = tid; q < HS; q += NT) { hkey[q] = -1; hfirst[q] = INT_MAX; }
-    if (tid == 0) s_cnt = 0;
-    // stage the terms in segment order (row by row, entries in column order);
-    // lanes take terms, not rows, so the gathers of a step are independent
-    int off = 0;
-    for (int base = sb; base < se; base += NT) {
-      const int k = base + tid;
-      int i = -1, len = 0, start = 0;
-      if (k < se) { i = agg_rows[k]; start = rp[i]; len = rp[i + 1] - start; }
-      int tot;
-      const int pos = block_exclusive_scan(len, tmp, &tot);
-      m_start[tid] = start;
-      m_off[tid] = pos;
-      if (FILL) m_pi[tid] = i >= 0 ? pval[i] : 0.0;
-      if (tid == 0) m_off[NT] = tot;
-      __syncthreads();
-      for (int t = tid; t < tot; t += NT) {
-        int lo = 0, hi = NT;   // member m with m_off[m] <= t < m_off[m + 1]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (m_off[mid] <= t) lo = mid; else hi = mid;
+    for (int q = lane; q < HS; q += kWave) { hkey[q] = -1; hcnt[q] = 0; hrun[q] = 0; }
+    int J[C], Q[C];
+    double V[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int t = c * kWave + lane;
+      J[c] = -1; Q[c] = 0; V[c] = 0.0;
+      if (t < T) { J[c] = tkey[t0 + t]; V[c] = tval[t0 + t]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (c * kWave + lane < T) {
+        int q = (int)(((uint32_t)J[c] * 0x9E3779B1u) >> (32 - HB));
+        while (true) {
+          const int prev = atomicCAS(&hkey[q], -1, J[c]);
+          if (prev == -1 || prev == J[c]) break;
+          q = q + 1 == HS ? 0 : q + 1;
         }
-        const int e = m_start[lo] + (t - m_off[lo]);
-        const int j = ci[e];
-        keys[off + t] = agg[j];
-        if (FILL) vals[off + t] = __dmul_rn(__dmul_rn(m_pi[lo], val[e]), pval[j]);
+        atomicAdd(&hcnt[q], 1);
+        Q[c] = q;
       }
-      off += tot;
+    }
+    __syncthreads();
+    // the occupied slots, in slot order
+    int U = 0;
+    for (int base = 0; base < HS; base += kWave) {
+      const int q = base + lane;
+      const bool occ = hkey[q] != -1;
+      const uint64_t bits = __ballot(occ);
+      if (occ) ukey[U + __popcll(bits & below)] = q;
+      U += __popcll(bits);
+    }
+    __syncthreads();
+    // rank of every distinct J (they are distinct, so ranks are a permutation)
+    for (int u = lane; u < U; u += kWave) {
+      const int q = ukey[u], key = hkey[q];
+      int r = 0;
+      for (int v = 0; v < U; ++v) r += hkey[ukey[v]] < key;
+      hrank[q] = r;
+      skey[r] = key;
+      sbase[r] = hcnt[q];
+    }
+    __syncthreads();
+    // exclusive scan of the per-J term counts, in rank order
+    int run = 0;
+    for (int base = 0; base < U; base += kWave) {
+      const int r = base + lane;
+      const int v = r < U ? sbase[r] : 0;
+      int incl = v;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+      }
+      __syncthreads();
+      if (r < U) sbase[r] = run + incl - v;
+      run += __shfl(incl, kWave - 1, kWave);
       __syncthreads();
     }
-    for (int t = tid; t < T; t += NT) {
-      const int J = keys[t];
-      int q = (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - HB));
-      while (true) {
-        const int prev = atomicCAS(&hkey[q], -1, J);
-        if (prev == -1 || prev == J) { atomicMin(&hfirst[q], t); break; }
-        q = (q + 1) & (HS - 1);
+    if (lane == 0) sbase[U] = run;
+    // place the terms: within a J, in segment order
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (c * kWave >= T) break;
+      const bool act = c * kWave + lane < T;
+      const int q = Q[c];
+      uint64_t rem = __ballot(act);
+      int before = 0, lead_add = 0;
+      while (rem) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int ql = __shfl(q, leader, kWave);
+        const uint64_t m = __ballot(act && q == ql);
+        if (act && q == ql) before = __popcll(m & below);
+        if (lane == leader) lead_add = __popcll(m);
+        rem &= ~m;
       }
+      if (act) sv[sbase[hrank[q]] + hrun[q] + before] = V[c];
+      __syncthreads();
+      if (lead_add) hrun[q] += lead_add;
+      __syncthreads();
     }
-    __syncthreads();
-    for (int t = tid; t < T; t += NT) {
-      const int J = keys[t];
-      int q = (int)(((uint32_t)J * 0x9E3779B1u) >> (32 - HB));
-      while (hkey[q] != J) q = (q + 1) & (HS - 1);
-      if (hfirst[q] == t) ukeys[atomicAdd(&s_cnt, 1)] = J;
+    // sums in segment order; sorted pairs over the head of the term range
+    for (int r = lane; r < U; r += kWave) {
+      double s = 0.0;
+      for (int x = sbase[r]; x < sbase[r + 1]; ++x) s = __dadd_rn(s, sv[x]);
+      tkey[t0 + r] = skey[r];
+      tval[t0 + r] = s;
     }
-    __syncthreads();
-    const int U = s_cnt;
-    if (!FILL) {
-      if (tid == 0) row_count[I] = U;
-    } else {
-      const int out0 = rp_c[I];
-      for (int u = tid; u < U; u += NT) {
-        const int J = ukeys[u];
-        int rank = 0;
-        for (int v = 0; v < U; ++v) rank += ukeys[v] < J;
-        double sum = 0.0;
-        for (int t = 0; t < T; ++t)
-          if (keys[t] == J) sum = __dadd_rn(sum, vals[t]);
-        ci_c[out0 + rank] = J;
-        val_c[out0 + rank] = sum;
-      }
-    }
+    if (lane == 0) ucount[I] = U;
     __syncthreads();
   }
 }
@@ -138,45 +204,36 @@ __device__ __forceinline__ int block_min_int(int v, int* red) {
   return r;
 }
 
-// Large coarse rows: repeatedly take the smallest J above the last one over
-// all terms of the segment, then sum its terms (fixed thread assignment and
-// reduction order).  Grid-strides over the overflow list.
+// Rows beyond the widest wave: repeatedly take the smallest J above the last
+// one over the row's terms, then sum its terms (fixed thread assignment and
+// reduction order).  The count pass runs before the row pointers exist, the
+// fill pass writes the final row directly.
 template <bool FILL>
-__global__ void __launch_bounds__(kBig) k_galerkin_big(
-    const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ val,
-    const int* __restrict__ agg, const double* __restrict__ pval, const int* __restrict__ agg_ptr,
-    const int* __restrict__ agg_rows, int* __restrict__ row_count, const int* __restrict__ ovf_list,
-    const int* __restrict__ ovf_count, const int* __restrict__ rp_c, int* __restrict__ ci_c,
-    double* __restrict__ val_c) {
+__global__ void __launch_bounds__(kBig) k_gal_big(const int* __restrict__ agg_ptr, const int* __restrict__ toff,
+                                                  const int* __restrict__ tkey, const double* __restrict__ tval,
+                                                  int* __restrict__ ucount, const int* __restrict__ ovf_list,
+                                                  const int* __restrict__ ovf_count, const int* __restrict__ rp_c,
+                                                  int* __restrict__ ci_c, double* __restrict__ val_c) {
   __shared__ int ired[kBig / kWave];
   __shared__ double dred[kBig / kWave];
   const int count = *ovf_count;
   for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int I = ovf_list[idx];
-    const int sb = agg_ptr[I], se = agg_ptr[I + 1];
+    const int t0 = toff[agg_ptr[I]], t1 = toff[agg_ptr[I + 1]];
     const int out0 = FILL ? rp_c[I] : 0;
     int last = -1, U = 0;
     while (true) {
       int mn = INT_MAX;
-      for (int k = sb + threadIdx.x; k < se; k += kBig) {
-        int i = agg_rows[k];
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
-          int J = agg[ci[e]];
-          if (J > last && J < mn) mn = J;
-        }
+      for (int t = t0 + threadIdx.x; t < t1; t += kBig) {
+        const int key = tkey[t];
+        if (key > last && key < mn) mn = key;
       }
       mn = block_min_int(mn, ired);
       if (mn == INT_MAX) break;
       if (FILL) {
         double s = 0.0;
-        for (int k = sb + threadIdx.x; k < se; k += kBig) {
-          int i = agg_rows[k];
-          double pi = pval[i];
-          for (int e = rp[i]; e < rp[i + 1]; ++e) {
-            int j = ci[e];
-            if (agg[j] == mn) s = __dadd_rn(s, __dmul_rn(__dmul_rn(pi, val[e]), pval[j]));
-          }
-        }
+        for (int t = t0 + threadIdx.x; t < t1; t += kBig)
+          if (tkey[t] == mn) s = __dadd_rn(s, tval[t]);
         double v[1] = {s};
         block_sum<1>(v, dred);
         if (threadIdx.x == 0) {
@@ -187,43 +244,67 @@ __global__ void __launch_bounds__(kBig) k_galerkin_big(
       ++U;
       last = mn;
     }
-    if (!FILL && threadIdx.x == 0) row_count[I] = U;
+    if (!FILL && threadIdx.x == 0) ucount[I] = U;
     __syncthreads();
+  }
+}
+
+// Step 4: rows reduced in place move to their final position (rows beyond
+// the widest wave were written by the extraction path).
+template <int G>
+__global__ void __launch_bounds__(256) k_gal_compact(int nc, const int* __restrict__ agg_ptr,
+                                                     const int* __restrict__ toff, const int* __restrict__ tkey,
+                                                     const double* __restrict__ tval, const int* __restrict__ rp_c,
+                                                     int* __restrict__ ci_c, double* __restrict__ val_c) {
+  RowGroup<G> rg;
+  for (long I0 = rg.gid; I0 < nc; I0 += rg.ngroups) {
+    const int I = (int)I0;
+    const int t0 = toff[agg_ptr[I]];
+    if (toff[agg_ptr[I + 1]] - t0 > kMaxWaveTerms) continue;
+    const int o = rp_c[I], U = rp_c[I + 1] - o;
+    for (int u = rg.lane; u < U; u += G) {
+      ci_c[o + u] = tkey[t0 + u];
+      val_c[o + u] = tval[t0 + u];
+    }
   }
 }
 }  // namespace
 
-// Count pass: waves take rows of up to 256 terms; blocks take the rows
-// listed as larger (up to 1536 terms); the rest go to the extraction path.
-void launch_galerkin_count(int nc, const int* rp, const int* ci, const int* agg, const int* agg_ptr,
-                           const int* agg_rows, int* row_count, int* ovf_list, int* ctl_ovf, hipStream_t s) {
+// Steps 1-3: on return ucount[I] holds the number of distinct J of every row.
+void launch_galerkin_stage(const GalerkinScratch& g, int n, int nc, int nnz, const int* rp, const int* ci,
+                           const double* val, const int* agg, const double* pval, const int* agg_ptr,
+                           const int* agg_rows, ScanCtx& sc, hipStream_t s) {
   if (nc <= 0) return;
-  int* list1 = ovf_list;
-  int* list2 = ovf_list + nc;
-  launch_fill_int(2, ctl_ovf, 0, s);
-  k_galerkin_stage<kWave, 256, 9, false, false><<<nc, kWave, 0, s>>>(
-      nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, nullptr, nullptr, list1, ctl_ovf, nullptr,
-      nullptr, nullptr);
-  k_galerkin_stage<256, 1536, 12, false, true><<<1024, 256, 0, s>>>(
-      nc, rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, list1, ctl_ovf, list2, ctl_ovf + 1,
-      nullptr, nullptr, nullptr);
-  k_galerkin_big<false><<<256, kBig, 0, s>>>(rp, ci, nullptr, agg, nullptr, agg_ptr, agg_rows, row_count, list2,
-                                             ctl_ovf + 1, nullptr, nullptr, nullptr);
+  k_gal_lens<<<(n + 255) / 256 > 0 ? (n + 255) / 256 : 1, 256, 0, s>>>(n, rp, agg_ptr, nc, agg_rows, g.lens,
+                                                                      g.inv);
+  scan_to_ptr(g.lens, g.toff, n, sc, s);
+  const int G = group_lanes(n, nnz);
+  with_lanes(G, [&](auto gl) {
+    k_gal_expand<decltype(gl)::value><<<group_grid(n, G), 256, 0, s>>>(n, rp, ci, val, agg, pval, g.inv, g.toff,
+                                                                       g.tkey, g.tval);
+  });
+  int* list1 = g.list;
+  int* list2 = g.list + nc;
+  launch_fill_int(2, g.ctl, 0, s);
+  k_gal_reduce<kSmallC, false><<<nc, kWave, 0, s>>>(nc, agg_ptr, g.toff, g.tkey, g.tval, g.ucount, nullptr,
+                                                    nullptr, list1, g.ctl);
+  k_gal_reduce<kWideC, true><<<2048, kWave, 0, s>>>(nc, agg_ptr, g.toff, g.tkey, g.tval, g.ucount, list1, g.ctl,
+                                                    list2, g.ctl + 1);
+  k_gal_big<false><<<256, kBig, 0, s>>>(agg_ptr, g.toff, g.tkey, g.tval, g.ucount, list2, g.ctl + 1, nullptr,
+                                        nullptr, nullptr);
 }
 
-void launch_galerkin_fill(int nc, const int* rp, const int* ci, const double* val, const int* agg,
-                          const double* pval, const int* agg_ptr, const int* agg_rows, const int* rp_c,
-                          int* ci_c, double* val_c, const int* ovf_list, const int* ctl_ovf, hipStream_t s) {
+// Step 4 once the row pointers rp_c exist.
+void launch_galerkin_finish(const GalerkinScratch& g, int nc, const int* agg_ptr, const int* rp_c, int* ci_c,
+                            double* val_c, hipStream_t s) {
   if (nc <= 0) return;
-  const int* list1 = ovf_list;
-  const int* list2 = ovf_list + nc;
-  k_galerkin_stage<kWave, 256, 9, true, false><<<nc, kWave, 0, s>>>(
-      nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, nullptr, nullptr, nullptr, nullptr, rp_c, ci_c,
-      val_c);
-  k_galerkin_stage<256, 1536, 12, true, true><<<1024, 256, 0, s>>>(
-      nc, rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, list1, ctl_ovf, nullptr, nullptr, rp_c, ci_c, val_c);
-  k_galerkin_big<true><<<256, kBig, 0, s>>>(rp, ci, val, agg, pval, agg_ptr, agg_rows, nullptr, list2,
-                                            ctl_ovf + 1, rp_c, ci_c, val_c);
+  const int G = group_lanes(nc, (long)nc * 16);
+  with_lanes(G, [&](auto gl) {
+    k_gal_compact<decltype(gl)::value><<<group_grid(nc, G), 256, 0, s>>>(nc, agg_ptr, g.toff, g.tkey, g.tval, rp_c,
+                                                                         ci_c, val_c);
+  });
+  k_gal_big<true><<<256, kBig, 0, s>>>(agg_ptr, g.toff, g.tkey, g.tval, nullptr, g.list + nc, g.ctl + 1, rp_c,
+                                       ci_c, val_c);
 }
 
 }  // namespace amg

@@ -177,14 +177,21 @@ namespace {
 
 struct Sync {
   Hierarchy& h;
+  Mailbox m{};
   int* hp() { return static_cast<int*>(h.h_pinned); }
-  // copy `count` ints from device to the pinned mirror (slot offset), no sync
-  void fetch(const int* dptr, int slot, int count = 1) {
-    AMG_HIP(hipMemcpyAsync(hp() + slot, dptr, count * sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  // ask for one device int in pinned slot `slot` at the next wait
+  void fetch(const int* dptr, int slot, int count = 1, int stride = 1) {
+    if (m.n == 8) throw Error(AMG_EINVAL, "more than 8 pending read-backs");
+    m.src[m.n] = dptr;
+    m.slot[m.n] = slot;
+    m.count[m.n] = count;
+    m.stride[m.n] = stride;
+    ++m.n;
   }
   void wait_and_check() {
     AMG_HIP(hipGetLastError());   // a failed launch surfaces here
-    AMG_HIP(hipMemcpyAsync(hp() + 63, h.d_err, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    launch_mailbox(m, h.d_err, hp(), h.stream);
+    m.n = 0;
     AMG_HIP(hipStreamSynchronize(h.stream));
     AMG_HIP(hipGetLastError());
     const int e = hp()[63];
@@ -201,9 +208,10 @@ struct Sync {
   }
   // true (and the bit cleared) when the SPD elimination met a non-positive pivot
   bool take_not_spd() {
-    AMG_HIP(hipMemcpyAsync(hp() + 62, h.d_err, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+    Mailbox none{};
+    launch_mailbox(none, h.d_err, hp(), h.stream);
     AMG_HIP(hipStreamSynchronize(h.stream));
-    const int e = hp()[62];
+    const int e = hp()[63];
     if (!(e & kErrNotSPD)) return false;
     launch_fill_int(1, h.d_err, e & ~kErrNotSPD, h.stream);
     return true;
@@ -237,21 +245,29 @@ void alloc_solve_vectors(Hierarchy& h) {
 }
 
 // Sliced-ELL copy of A_k for the solve kernels.
-void build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
-  Sync sy{h};
+// First half: slice widths and their scan; the total goes to pinned slot
+// `slot` at the next wait of `sy`.
+void sell_begin(Hierarchy& h, Arena& tmp, Level& lv, Sync& sy, int slot) {
   const int nsl = (lv.n + 63) / 64;
   int* widths = tmp.alloc_n<int>(nsl);
   launch_sell_widths(lv.n, lv.rp, widths, h.stream);
   lv.nslices = nsl;
   lv.sl_ptr = h.arena.alloc_n<int>(nsl + 1);
-  scan_to_ptr(widths, lv.sl_ptr, nsl, h.d_scan, h.stream);
-  sy.fetch(lv.sl_ptr + nsl, 0);
-  sy.wait_and_check();
-  const size_t total = (size_t)sy.hp()[0];
+  scan_to_ptr(widths, lv.sl_ptr, nsl, h.scan, h.stream);
+  sy.fetch(lv.sl_ptr + nsl, slot);
+}
+void sell_finish(Hierarchy& h, Level& lv, size_t total) {
   lv.sl_col = h.arena.alloc_n<int>(total);
   lv.sl_val = h.arena.alloc_n<double>(total);
   if (h.mixed()) lv.sl_val32 = h.arena.alloc_n<float>(total);
-  launch_sell_fill(lv.n, nsl, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_val, lv.sl_val32, h.stream);
+  launch_sell_fill(lv.n, lv.nslices, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_val, lv.sl_val32,
+                   h.stream);
+}
+void build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
+  Sync sy{h};
+  sell_begin(h, tmp, lv, sy, 0);
+  sy.wait_and_check();
+  sell_finish(h, lv, (size_t)sy.hp()[0]);
 }
 
 }  // namespace
@@ -296,7 +312,7 @@ static void build_segments(Hierarchy& h, Arena& tmp, int n, int nc, const int* a
   int* counts = tmp.alloc_n<int>(nc);
   launch_fill_int(nc, counts, 0, s);
   launch_agg_count(n, agg, counts, s);
-  scan_to_ptr(counts, agg_ptr, nc, h.d_scan, s);
+  scan_to_ptr(counts, agg_ptr, nc, h.scan, s);
   launch_fill_int(nc, counts, 0, s);
   launch_agg_scatter(n, agg, agg_ptr, counts, agg_rows, s);
   launch_agg_sort(nc, agg_ptr, agg_rows, s);
@@ -308,19 +324,25 @@ static void galerkin_product(Hierarchy& h, Arena& tmp, Arena& out, const Level& 
                              int** rp_c, int** ci_c, double** val_c, int* nnz_c) {
   hipStream_t s = h.stream;
   Sync sy{h};
-  int* row_count = tmp.alloc_n<int>(nc);
-  int* ovf = tmp.alloc_n<int>(2 * (size_t)nc);
-  int* ctl_ovf = h.d_ctl + kCtlAggFill;
-  launch_galerkin_count(nc, lv.rp, lv.ci, agg, agg_ptr, agg_rows, row_count, ovf, ctl_ovf, s);
-  *rp_c = out.alloc_n<int>(nc + 1);
-  scan_to_ptr(row_count, *rp_c, nc, h.d_scan, s);
+  const int n = lv.n, nnz = lv.nnz;
+  GalerkinScratch g;
+  g.lens = tmp.alloc_n<int>(n > 0 ? n : 1);
+  g.inv = tmp.alloc_n<int>(n > 0 ? n : 1);
+  g.toff = tmp.alloc_n<int>((size_t)n + 1);
+  g.tkey = tmp.alloc_n<int>(nnz > 0 ? nnz : 1);
+  g.tval = tmp.alloc_n<double>(nnz > 0 ? nnz : 1);
+  g.ucount = tmp.alloc_n<int>(nc > 0 ? nc : 1);
+  g.list = tmp.alloc_n<int>(2 * (size_t)(nc > 0 ? nc : 1));
+  g.ctl = h.d_ctl + kCtlAggFill;
+  launch_galerkin_stage(g, n, nc, nnz, lv.rp, lv.ci, lv.val, agg, pval, agg_ptr, agg_rows, h.scan, s);
+  *rp_c = out.alloc_n<int>((size_t)nc + 1);
+  scan_to_ptr(g.ucount, *rp_c, nc, h.scan, s);
   sy.fetch(*rp_c + nc, 0);
   sy.wait_and_check();
   *nnz_c = sy.hp()[0];
-  *ci_c = out.alloc_n<int>(*nnz_c);
-  *val_c = out.alloc_n<double>(*nnz_c);
-  launch_galerkin_fill(nc, lv.rp, lv.ci, lv.val, agg, pval, agg_ptr, agg_rows, *rp_c, *ci_c, *val_c, ovf,
-                       ctl_ovf, s);
+  *ci_c = out.alloc_n<int>(*nnz_c > 0 ? *nnz_c : 1);
+  *val_c = out.alloc_n<double>(*nnz_c > 0 ? *nnz_c : 1);
+  launch_galerkin_finish(g, nc, agg_ptr, *rp_c, *ci_c, *val_c, s);
 }
 
 void galerkin_standalone(Hierarchy& h, const amg_csr& A, const int* agg, const double* pval, int nc,
@@ -356,12 +378,30 @@ void init_control(Hierarchy& h) {
   h.d_sc = h.arena.alloc_n<double>(kScWords);
   h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4);
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
+  h.d_mis = h.arena.alloc_n<int>(kMisWords);
   launch_fill_int(64, h.d_err, 0, h.stream);
   launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);
   launch_fill_double(kScWords, h.d_sc, 0.0, h.stream);   // arena memory is recycled, not cleared
   launch_fill_int(64, reinterpret_cast<int*>(h.d_ticket), 0, h.stream);
   launch_fill_int(1, h.d_ctl + kCtlOne, 1, h.stream);
-  if (!h.h_pinned) AMG_HIP(hipHostMalloc(&h.h_pinned, 4096, hipHostMallocDefault));
+  if (!h.h_pinned) AMG_HIP(hipHostMalloc(&h.h_pinned, kPinnedBytes, hipHostMallocDefault));
+}
+
+// omega_k = jacobi_scale / rho from the Arnoldi Hessenberg H (row stride 8,
+// m columns; wn = ||D^-1 A q_j||), then the weights omega_k / a_ii.
+static void set_jacobi_weight(Hierarchy& h, Level& lv, int m, const double* Hh, const double* wn) {
+  int size = m;
+  for (int j = 0; j < m; ++j) {
+    if (Hh[(j + 1) * 8 + j] <= 1e-14 * wn[j]) { size = j + 1; break; }
+  }
+  // upper Hessenberg: the slots below the subdiagonal are never written
+  double Hs[64];
+  for (int i = 0; i < size; ++i)
+    for (int j = 0; j < size; ++j) Hs[i * size + j] = i <= j + 1 ? Hh[i * 8 + j] : 0.0;
+  lv.rho = hessenberg_spectral_radius(Hs, size);
+  if (!(lv.rho > 0.0) || !std::isfinite(lv.rho)) throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive");
+  lv.omega = h.opt.jacobi_scale / lv.rho;
+  launch_jacobi_weights(lv.n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, h.stream);
 }
 
 void build_hierarchy(Hierarchy& h, const amg_csr& A) {
@@ -372,7 +412,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   // on any exit, drain the stream before the scratch chunks go back to the cache
   struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
   // scan scratch sized for the largest level
-  h.d_scan = h.arena.alloc_n<int>(scan_blocks_needed(std::max(A.n, A.nnz)) + 2);
+  init_scan(h.scan, h.arena, std::max(A.n, A.nnz), s);
 
   Level l0;
   l0.n = A.n;
@@ -384,8 +424,8 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
   // the row pointers must be consistent before any kernel walks the rows
-  sy.fetch(l0.rp, 0, 1);
-  sy.fetch(l0.rp + A.n, 1, 1);
+  sy.fetch(l0.rp, 0);
+  sy.fetch(l0.rp + A.n, 1);
   sy.wait_and_check();
   if (sy.hp()[0] != 0 || sy.hp()[1] != A.nnz) throw Error(AMG_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
   launch_check_rowptr(l0.n, l0.rp, h.d_err, s);   // monotone: every row lies inside [0, nnz)
@@ -397,6 +437,37 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   sy.wait_and_check();
 
   const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  // The Arnoldi estimate of a level needs only that level's matrix: it runs on
+  // a second stream, overlapped with the coarsening of the next levels, and
+  // the weights are applied once every level exists.  (The learned smoother
+  // validates against omega_k during the level loop, so it waits instead.)
+  const bool async_arn = o.smoother != AMG_SMOOTHER_LEARNED;
+  hipStream_t as = nullptr;
+  struct AsyncStream {
+    hipStream_t* s;
+    ~AsyncStream() {
+      if (*s) {
+        (void)hipStreamSynchronize(*s);
+        (void)hipStreamDestroy(*s);
+      }
+    }
+  } as_guard{&as};
+  struct PendingArn { int k, m; hipEvent_t done; };
+  std::vector<PendingArn> pending;
+  struct EventGuard {
+    std::vector<PendingArn>* p;
+    ~EventGuard() {
+      for (auto& q : *p)
+        if (q.done) (void)hipEventDestroy(q.done);
+    }
+  } ev_guard{&pending};
+  RedCtx arn_rc{nullptr, nullptr};
+  if (async_arn) {
+    AMG_HIP(hipStreamCreateWithFlags(&as, hipStreamNonBlocking));
+    arn_rc.part = tmp.alloc_n<double>(kMaxPartialBlocks * 4);
+    arn_rc.ticket = tmp.alloc_n<unsigned>(64);
+    launch_fill_int(64, reinterpret_cast<int*>(arn_rc.ticket), 0, s);
+  }
   if (o.smoother == AMG_SMOOTHER_LEARNED) {
     if (!o.mlp_weights) throw Error(AMG_EINVAL, "learned smoother without weights");
     const int np = mlp_num_params();
@@ -416,38 +487,42 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     if (lv.n <= o.coarse_max || k + 1 >= o.max_levels) break;
     const int n = lv.n, nnz = lv.nnz;
 
+    // the sliced-ELL copy serves the solve and, on stencil-like levels, the
+    // Arnoldi mat-vecs; its size is read back with the graph's
+    sell_begin(h, tmp, lv, sy, 2);
+
     // strength (Section 2.1.1) and the strong graph G = C u C^T
     lv.strong = h.arena.alloc_n<uint8_t>(nnz);
-    launch_strength(n, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, h.d_err, s);
+    launch_strength(n, nnz, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, s);
     uint8_t* gmask = tmp.alloc_n<uint8_t>(nnz);
     int* gdeg = tmp.alloc_n<int>(n);
     int* cnt = tmp.alloc_n<int>(n);
-    launch_graph_count(n, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
+    launch_graph_count(n, nnz, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
     int* gptr = tmp.alloc_n<int>(n + 1);
-    scan_to_ptr(gdeg, gptr, n, h.d_scan, s);
+    scan_to_ptr(gdeg, gptr, n, h.scan, s);
     sy.fetch(gptr + n, 0);
     sy.wait_and_check();
     const int nnzg = sy.hp()[0];
+    sell_finish(h, lv, (size_t)sy.hp()[2]);
     int* gcol = tmp.alloc_n<int>(nnzg > 0 ? nnzg : 1);
-    launch_graph_fill(n, lv.rp, lv.ci, gmask, gptr, gcol, s);
+    launch_graph_fill(n, nnz, lv.rp, lv.ci, gmask, gptr, gcol, s);
 
     // MIS(2) rounds (Algorithm 2)
     lv.tuple = h.arena.alloc_n<uint64_t>(n);
     uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
-    int* mis_flags = tmp.alloc_n<int>(2048);
-    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_ctl, h.d_err, s);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_mis, h.d_err, s);
     int round = 0;
-    const int batch = 4;
-    int glanes = 1;
-    while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
+    int batch = 8;   // rounds between read-backs: a round after the last exits at entry
+    const int glanes = group_lanes(n, nnzg);
     while (true) {
       for (int b = 0; b < batch; ++b, ++round)
-        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, mis_flags, s);
-      sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
-      sy.fetch(h.d_ctl + kCtlMisRounds, 1);
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s);
+      sy.fetch(h.d_mis + mis_word(round & 1, 0), 0, kMisSlots, mis_word(0, 1));
+      sy.fetch(h.d_mis + kMisRoundsWord, 1);
       sy.wait_and_check();
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
+      batch = 4;
     }
     lv.mis_rounds = sy.hp()[1];
     if (debug) std::fprintf(stderr, "amg: level %d n=%d nnz=%d nnz(G)=%d mis_rounds=%d\n", k, n, nnz, nnzg,
@@ -457,7 +532,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     int* flags = tmp.alloc_n<int>(n);
     int* root_id = tmp.alloc_n<int>(n + 1);
     launch_root_flags(n, lv.tuple, flags, s);
-    scan_to_ptr(flags, root_id, n, h.d_scan, s);
+    scan_to_ptr(flags, root_id, n, h.scan, s);
     sy.fetch(root_id + n, 0);
     sy.wait_and_check();
     const int nc = sy.hp()[0];
@@ -468,7 +543,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     }
     int* choice = tmp.alloc_n<int>(n);
     lv.agg = h.arena.alloc_n<int>(n);
-    launch_aggregate(n, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    launch_aggregate(n, nnzg, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
     lv.nc = nc;
     lv.agg_ptr = h.arena.alloc_n<int>(nc + 1);
     lv.agg_rows = h.arena.alloc_n<int>(n);
@@ -489,31 +564,33 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
                      &lc.val, &lc.nnz);
 
-    // damped Jacobi weight (Section 2.2.1); the sliced-ELL copy serves the
-    // Arnoldi mat-vecs on stencil-like levels
-    build_sell(h, tmp, lv);
+    // damped Jacobi weight (Section 2.2.1)
     const int m = std::min(o.arnoldi_m, n);
     double* Q = tmp.alloc_n<double>((size_t)(m + 1) * n);
     double* w = tmp.alloc_n<double>(n);
-    double Hh[48], wn[8];
-    arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
-    int size = m;
-    for (int j = 0; j < m; ++j) {
-      if (Hh[(j + 1) * 8 + j] <= 1e-14 * wn[j]) { size = j + 1; break; }
-    }
-    // upper Hessenberg: the slots below the subdiagonal are never written
-    double Hs[64];
-    for (int i = 0; i < size; ++i)
-      for (int j = 0; j < size; ++j) Hs[i * size + j] = i <= j + 1 ? Hh[i * 8 + j] : 0.0;
-    lv.rho = hessenberg_spectral_radius(Hs, size);
-    if (!(lv.rho > 0.0) || !std::isfinite(lv.rho))
-      throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive");
-    lv.omega = o.jacobi_scale / lv.rho;
-    if (debug) std::fprintf(stderr, "amg: level %d nc=%d nnz_c=%d rho=%.6f omega=%.6f\n", k, nc, lc.nnz, lv.rho,
-                            lv.omega);
     lv.wdinv = h.arena.alloc_n<double>(n);
     if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
-    launch_jacobi_weights(n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, s);
+    if (async_arn) {
+      if (k >= 24) throw Error(AMG_EINVAL, "more than 24 levels");
+      hipEvent_t ready = nullptr;
+      AMG_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      AMG_HIP(hipEventRecord(ready, s));
+      AMG_HIP(hipStreamWaitEvent(as, ready, 0));
+      AMG_HIP(hipEventDestroy(ready));
+      double* sc = tmp.alloc_n<double>(kScArn + 64);
+      double* host = static_cast<double*>(h.h_pinned) + kPinnedArn + 64 * k;
+      arnoldi_enqueue(h, lv, m, o.seed + 1, Q, w, sc, arn_rc, host, as);
+      PendingArn p{k, m, nullptr};
+      AMG_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming));
+      AMG_HIP(hipEventRecord(p.done, as));
+      pending.push_back(p);
+    } else {
+      double Hh[48], wn[8];
+      arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
+      set_jacobi_weight(h, lv, m, Hh, wn);
+      if (debug) std::fprintf(stderr, "amg: level %d nc=%d nnz_c=%d rho=%.6f omega=%.6f\n", k, nc, lc.nnz, lv.rho,
+                              lv.omega);
+    }
     if (o.smoother == AMG_SMOOTHER_LEARNED) {
       // learned per-row weights, kept only when they smooth better than
       // omega_k on validation samples (or always, when the caller says so)
@@ -537,6 +614,15 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       sy.wait_and_check();
     }
     h.levels.push_back(lc);
+  }
+
+  // damped Jacobi weights of the levels whose Arnoldi ran alongside
+  for (const PendingArn& p : pending) {
+    AMG_HIP(hipEventSynchronize(p.done));
+    const double* host = static_cast<const double*>(h.h_pinned) + kPinnedArn + 64 * p.k;
+    set_jacobi_weight(h, h.levels[p.k], p.m, host, host + 48);
+    if (debug) std::fprintf(stderr, "amg: level %d rho=%.6f omega=%.6f\n", p.k, h.levels[p.k].rho,
+                            h.levels[p.k].omega);
   }
 
   // coarsest level: dense inverse
@@ -587,7 +673,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
   Sync sy{h};
   Arena tmp;
   struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
-  h.d_scan = h.arena.alloc_n<int>(scan_blocks_needed(std::max(A.n, A.nnz)) + 2);
+  init_scan(h.scan, h.arena, std::max(A.n, A.nnz), s);
   batch_control(h);   // per-system scalars and block partials, used from the first Arnoldi on
 
   Level l0;
@@ -599,8 +685,8 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
   AMG_HIP(hipMemcpyAsync(l0.rp, A.row_ptr, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
-  sy.fetch(l0.rp, 0, 1);
-  sy.fetch(l0.rp + A.n, 1, 1);
+  sy.fetch(l0.rp, 0);
+  sy.fetch(l0.rp + A.n, 1);
   sy.wait_and_check();
   if (sy.hp()[0] != 0 || sy.hp()[1] != A.nnz) throw Error(AMG_EINVAL, "row_ptr[0] != 0 or row_ptr[n] != nnz");
   launch_check_rowptr(l0.n, l0.rp, h.d_err, s);
@@ -639,35 +725,35 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
 
     // strength, strong graph, MIS(2) with per-system priorities
     lv.strong = h.arena.alloc_n<uint8_t>(nnz);
-    launch_strength(n, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, h.d_err, s);
+    launch_strength(n, nnz, lv.rp, lv.ci, lv.val, o.strength_alpha, lv.strong, lv.diag, s);
     uint8_t* gmask = tmp.alloc_n<uint8_t>(nnz);
     int* gdeg = tmp.alloc_n<int>(n);
     int* cnt = tmp.alloc_n<int>(n);
-    launch_graph_count(n, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
+    launch_graph_count(n, nnz, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
     int* gptr = tmp.alloc_n<int>(n + 1);
-    scan_to_ptr(gdeg, gptr, n, h.d_scan, s);
+    scan_to_ptr(gdeg, gptr, n, h.scan, s);
     sy.fetch(gptr + n, 0);
     sy.wait_and_check();
     const int nnzg = sy.hp()[0];
     int* gcol = tmp.alloc_n<int>(nnzg > 0 ? nnzg : 1);
-    launch_graph_fill(n, lv.rp, lv.ci, gmask, gptr, gcol, s);
+    launch_graph_fill(n, nnz, lv.rp, lv.ci, gmask, gptr, gcol, s);
     int* lbase = tmp.alloc_n<int>(n);
     batch_local_base(lv, lbase, s);
     lv.tuple = h.arena.alloc_n<uint64_t>(n);
     uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
-    int* mis_flags = tmp.alloc_n<int>(2048);
-    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_ctl, h.d_err, s, lbase);
+    launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_mis, h.d_err, s, lbase);
     int round = 0;
-    int glanes = 1;
-    while (glanes < 32 && glanes * (long)n < (long)nnzg) glanes <<= 1;
+    int batch = 8;
+    const int glanes = group_lanes(n, nnzg);
     while (true) {
-      for (int b = 0; b < 4; ++b, ++round)
-        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_ctl, round, glanes, mis_flags, s);
-      sy.fetch(h.d_ctl + kCtlMisPing + (round & 1), 0);
-      sy.fetch(h.d_ctl + kCtlMisRounds, 1);
+      for (int b = 0; b < batch; ++b, ++round)
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s);
+      sy.fetch(h.d_mis + mis_word(round & 1, 0), 0, kMisSlots, mis_word(0, 1));
+      sy.fetch(h.d_mis + kMisRoundsWord, 1);
       sy.wait_and_check();
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
+      batch = 4;
     }
     lv.mis_rounds = sy.hp()[1];
 
@@ -675,7 +761,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     int* flags = tmp.alloc_n<int>(n);
     int* root_id = tmp.alloc_n<int>(n + 1);
     launch_root_flags(n, lv.tuple, flags, s);
-    scan_to_ptr(flags, root_id, n, h.d_scan, s);
+    scan_to_ptr(flags, root_id, n, h.scan, s);
     batch_gather(nsys + 1, root_id, lv.d_sys_off, d_sysint, s);
     AMG_HIP(hipMemcpyAsync(hroot.data(), d_sysint, (nsys + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
     sy.wait_and_check();
@@ -709,7 +795,7 @@ void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off) {
     AMG_HIP(hipMemcpyAsync(d_sysint + nsys, shift.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
     int* choice = tmp.alloc_n<int>(n);
     lv.agg = h.arena.alloc_n<int>(n);
-    launch_aggregate(n, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    launch_aggregate(n, nnzg, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
     batch_remap_agg(lv, d_sysint, d_sysint + nsys, lv.agg, s);
     lv.nc = nc;
     lv.agg_ptr = h.arena.alloc_n<int>(nc + 1);

@@ -23,10 +23,6 @@ constexpr int kBlock = 256;
 // XCD's L2, which grows expensive when many blocks of a large kernel do it.
 constexpr int kTailBlocks = 64;
 
-struct RedCtx {
-  double* part;       // kMaxPartialBlocks * NV doubles
-  unsigned* ticket;   // arrival counter of the in-kernel finalize (zero between kernels)
-};
 
 template <int NV, class Op>
 __device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc, const Op& op, bool tail) {

@@ -3,6 +3,10 @@
 // nearest-root aggregation, aggregate segments and the interpolation of
 // Algorithm 3.  One thread per row / node: these run once per level and their
 // rows are short, so the simple mapping keeps the integer decisions exact.
+#include <algorithm>
+#include <climits>
+#include <type_traits>
+
 #include "amg_internal.hpp"
 #include "device_utils.hpp"
 
@@ -48,24 +52,36 @@ __global__ void k_check_index(int n, const int* __restrict__ idx, int limit, int
 }
 
 // C_ij = [-s_i a_ij > alpha * max_{-s_i a_ij > 0} (-s_i a_ij)], s_i = sign(a_ii).
-__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ val, double alpha,
-                           uint8_t* __restrict__ strong, double* __restrict__ diag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int s = rp[i], e = rp[i + 1];
-  double d = 0.0;
-  for (int k = s; k < e; ++k)
-    if (ci[k] == i) d = val[k];
-  const double sg = d > 0.0 ? 1.0 : -1.0;
-  double m = 0.0;
-  for (int k = s; k < e; ++k) {
-    double t = -sg * val[k];
-    if (t > m) m = t;            // the running max only ever holds positive values
+// G lanes per row; the maximum is exact, so the lane split changes nothing.
+template <int G>
+__global__ void __launch_bounds__(256) k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const double* __restrict__ val, double alpha,
+                                                  uint8_t* __restrict__ strong, double* __restrict__ diag) {
+  RowGroup<G> rg;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    const int s = rp[i], e = rp[i + 1];
+    int kd = -1;   // the last diagonal entry of the row counts
+    double d = 0.0;
+    for (int k = s + rg.lane; k < e; k += G)
+      if (ci[k] == i) { kd = k; d = val[k]; }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      const int ok = __shfl_xor(kd, off, G);
+      const double od = __shfl_xor(d, off, G);
+      if (ok > kd) { kd = ok; d = od; }
+    }
+    const double sg = d > 0.0 ? 1.0 : -1.0;
+    double m = 0.0;
+    for (int k = s + rg.lane; k < e; k += G) {
+      const double t = -sg * val[k];
+      if (t > m) m = t;            // the running max only ever holds positive values
+    }
+    m = RowGroup<G>::max(m);
+    const double thr = __dmul_rn(alpha, m);
+    for (int k = s + rg.lane; k < e; k += G) strong[k] = (-sg * val[k] > thr) ? 1 : 0;
+    if (rg.lane == 0) diag[i] = d;
   }
-  const double thr = __dmul_rn(alpha, m);
-  for (int k = s; k < e; ++k) strong[k] = (-sg * val[k] > thr) ? 1 : 0;
-  diag[i] = d;
 }
 
 __device__ __forceinline__ int find_in_row(const int* __restrict__ ci, int lo, int hi, int key) {
@@ -81,38 +97,57 @@ __device__ __forceinline__ int find_in_row(const int* __restrict__ ci, int lo, i
 
 // G = C union C^T over A's (structurally symmetric) pattern; influence counts
 // cnt_i = #{j : C_ji = 1}.
-__global__ void k_graph_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                              const uint8_t* __restrict__ strong, uint8_t* __restrict__ gmask,
-                              int* __restrict__ gdeg, int* __restrict__ cnt, int* err) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int s = rp[i], e = rp[i + 1];
-  int gd = 0, c = 0;
+template <int G>
+__global__ void __launch_bounds__(256) k_graph_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const uint8_t* __restrict__ strong,
+                                                     uint8_t* __restrict__ gmask, int* __restrict__ gdeg,
+                                                     int* __restrict__ cnt, int* err) {
+  RowGroup<G> rg;
   bool nonsym = false;
-  for (int k = s; k < e; ++k) {
-    int j = ci[k];
-    if (j == i) { gmask[k] = 0; continue; }
-    int t = find_in_row(ci, rp[j], rp[j + 1], i);
-    if (t < 0) nonsym = true;
-    bool cji = t >= 0 && strong[t];
-    bool g = strong[k] || cji;
-    gmask[k] = g ? 1 : 0;
-    gd += g;
-    c += cji;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    const int s = rp[i], e = rp[i + 1];
+    int gd = 0, c = 0;
+    for (int k = s + rg.lane; k < e; k += G) {
+      const int j = ci[k];
+      if (j == i) { gmask[k] = 0; continue; }
+      const int t = find_in_row(ci, rp[j], rp[j + 1], i);
+      if (t < 0) nonsym = true;
+      const bool cji = t >= 0 && strong[t];
+      const bool g = strong[k] || cji;
+      gmask[k] = g ? 1 : 0;
+      gd += g;
+      c += cji;
+    }
+    gd = RowGroup<G>::sum(gd);
+    c = RowGroup<G>::sum(c);
+    if (rg.lane == 0) {
+      gdeg[i] = gd;
+      cnt[i] = c;
+    }
   }
-  gdeg[i] = gd;
-  cnt[i] = c;
   if (nonsym) atomic_or_flag(err, kErrNonSymPattern);
 }
 
-__global__ void k_graph_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                             const uint8_t* __restrict__ gmask, const int* __restrict__ gptr,
-                             int* __restrict__ gcol) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int o = gptr[i];
-  for (int k = rp[i]; k < rp[i + 1]; ++k)
-    if (gmask[k]) gcol[o++] = ci[k];
+// Columns of G in the order of A's row (a group ballot places each kept entry).
+template <int G>
+__global__ void __launch_bounds__(256) k_graph_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const uint8_t* __restrict__ gmask,
+                                                    const int* __restrict__ gptr, int* __restrict__ gcol) {
+  RowGroup<G> rg;
+  const uint64_t below = (1ull << rg.lane) - 1;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    const int s = rp[i], e = rp[i + 1];
+    int o = gptr[i];
+    for (int base = s; base < e; base += G) {
+      const int k = base + rg.lane;
+      const bool keep = k < e && gmask[k];
+      const uint64_t bits = RowGroup<G>::group_bits(__ballot(keep));
+      if (keep) gcol[o + __popcll(bits & below)] = ci[k];
+      o += __popcll(bits);
+    }
+  }
 }
 
 // Tuple T_i = (s_i, v_i, i) packed so that integer order is lexicographic
@@ -121,14 +156,13 @@ __global__ void k_graph_fill(int n, const int* __restrict__ rp, const int* __res
 // With lbase (batched systems) the hash takes the index local to the row's
 // system, i - lbase[i], so each system draws the priorities it would alone.
 __global__ void k_mis_init(int n, const int* __restrict__ cnt, uint32_t seed,
-                           uint64_t* __restrict__ T, uint64_t* __restrict__ M1, int* ctl, int* err,
+                           uint64_t* __restrict__ T, uint64_t* __restrict__ M1, int* mc, int* err,
                            const int* __restrict__ lbase) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    ctl[kCtlMisPing] = n > 0 ? 1 : 0;
-    ctl[kCtlMisPing + 1] = 0;
-    ctl[kCtlMisRounds] = 0;
-  }
+  if (i < 2 * kMisSlots)   // round 0 starts pending (if there are nodes)
+    __hip_atomic_store(&mc[mis_word(i / kMisSlots, i % kMisSlots)], i == 0 && n > 0 ? 1 : 0, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  if (i == 0) __hip_atomic_store(&mc[kMisRoundsWord], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (i >= n) return;
   int c = cnt[i];
   if (c >= (1 << 21)) atomic_or_flag(err, kErrCountOverflow);
@@ -147,6 +181,21 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
   return v;
 }
 
+// Whether the previous round left a node undecided (round 0: whether there
+// are nodes), for the whole block: the first wave reads the 64 counters of
+// the round's parity with atomic loads (they were formed by atomics of
+// other XCDs).
+__device__ __forceinline__ bool mis_pending(const int* mc, int round, int* s_flag) {
+  if (threadIdx.x < kMisSlots) {
+    const int v = __hip_atomic_load(&mc[mis_word(round & 1, threadIdx.x)], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t any = __ballot(v != 0);
+    if (threadIdx.x == 0) *s_flag = any != 0;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
 // Node groups of one MIS(2) sweep: grid of at most kMisBlocks blocks (a
 // multiple of 8), each taking a contiguous run of node groups, so per-block
 // flags stay few and no flag is written by more than one block.
@@ -159,13 +208,18 @@ template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol,
                                                     const uint64_t* __restrict__ T,
-                                                    uint64_t* __restrict__ M1, const int* ctl, int round) {
-  if (ctl[kCtlMisPing + (round & 1)] == 0) return;   // nothing undecided
-  constexpr int NPB = 256 / G;                       // nodes per block step
+                                                    uint64_t* __restrict__ M1, int* mc, int round) {
+  __shared__ int s_flag;
+  // the counters of this round's second sweep start from zero (they last held
+  // the previous round's counts, read by that round's sweeps only)
+  if (blockIdx.x == 0 && threadIdx.x < kMisSlots)
+    __hip_atomic_store(&mc[mis_word((round + 1) & 1, threadIdx.x)], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!mis_pending(mc, round, &s_flag)) return;   // nothing undecided
+  constexpr int NPB = 256 / G;                // nodes per block step
   const int lane = threadIdx.x & (G - 1);
   const int groups = (n + NPB - 1) / NPB;
   const int per = (groups + gridDim.x - 1) / gridDim.x;
-  const int g0 = blockIdx.x * per, g1 = min(groups, g0 + per);
+  const int g0 = xcd_block_index() * per, g1 = min(groups, g0 + per);
   for (int g = g0; g < g1; ++g) {
     const int i = g * NPB + threadIdx.x / G;
     uint64_t t = 0;
@@ -192,9 +246,9 @@ __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol, uint64_t* __restrict__ T,
-                                                    const uint64_t* __restrict__ M1, const int* ctl, int round,
-                                                    int* __restrict__ block_flag) {
-  if (ctl[kCtlMisPing + (round & 1)] == 0) return;
+                                                    const uint64_t* __restrict__ M1, int* mc, int round) {
+  __shared__ int s_flag;
+  if (!mis_pending(mc, round, &s_flag)) return;
   constexpr int NPB = 256 / G;
   __shared__ int s_any;
   if (threadIdx.x == 0) s_any = 0;
@@ -202,7 +256,7 @@ __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict
   const int lane = threadIdx.x & (G - 1);
   const int groups = (n + NPB - 1) / NPB;
   const int per = (groups + gridDim.x - 1) / gridDim.x;
-  const int g0 = blockIdx.x * per, g1 = min(groups, g0 + per);
+  const int g0 = xcd_block_index() * per, g1 = min(groups, g0 + per);
   int undecided = 0;
   for (int g = g0; g < g1; ++g) {
     const int i = g * NPB + threadIdx.x / G;
@@ -230,20 +284,13 @@ __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict
   }
   if (undecided) s_any = 1;   // benign race: every writer stores 1
   __syncthreads();
-  if (threadIdx.x == 0) block_flag[blockIdx.x] = s_any;
-}
-
-// End of a round: OR of the block flags into the next round's "undecided"
-// word, and the count of rounds that found undecided nodes.
-__global__ void __launch_bounds__(256) k_mis_ping(int nb, const int* __restrict__ block_flag, int* ctl, int round) {
-  const int cur = ctl[kCtlMisPing + (round & 1)];
-  int any = 0;
-  if (cur)
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) any |= block_flag[b];
-  any = __syncthreads_or(any);
   if (threadIdx.x == 0) {
-    ctl[kCtlMisPing + ((round + 1) & 1)] = any;
-    if (cur) ctl[kCtlMisRounds] += 1;
+    // spread over 64 counters in separate lines, so the blocks' atomics do
+    // not queue on one address
+    if (s_any)
+      __hip_atomic_fetch_add(&mc[mis_word((round + 1) & 1, blockIdx.x % kMisSlots)], 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (blockIdx.x == 0) __hip_atomic_fetch_add(&mc[kMisRoundsWord], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -252,48 +299,79 @@ __global__ void k_root_flags(int n, const uint64_t* __restrict__ T, int* __restr
   if (i < n) flags[i] = tstate(T[i]) == 2 ? 1 : 0;
 }
 
-// Round 1: roots take themselves; nodes next to roots take the adjacent root
-// with the largest tuple.
-__global__ void k_agg_round1(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
-                             const uint64_t* __restrict__ T, int* __restrict__ choice) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t own = T[i];
-  if (tstate(own) == 2) { choice[i] = i; return; }
-  uint64_t best = 0;
-  int bj = -1;
-  for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
-    int j = gcol[k];
-    uint64_t u = T[j];
-    if (tstate(u) == 2 && u > best) { best = u; bj = j; }
+// Largest tuple over a group's lanes, the first entry of the row among equal
+// ones (the order a sequential scan of the row would keep).
+template <int G>
+__device__ __forceinline__ void group_argmax(uint64_t& best, int& bk, int& bj) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    const uint64_t ob = __shfl_xor(best, off, G);
+    const int ok = __shfl_xor(bk, off, G);
+    const int oj = __shfl_xor(bj, off, G);
+    if (ob > best || (ob == best && ok < bk)) { best = ob; bk = ok; bj = oj; }
   }
-  choice[i] = bj;
+}
+
+// Round 1: roots take themselves; nodes next to roots take the adjacent root
+// with the largest tuple.  G lanes per node.
+template <int G>
+__global__ void __launch_bounds__(256) k_agg_round1(int n, const int* __restrict__ gptr,
+                                                    const int* __restrict__ gcol, const uint64_t* __restrict__ T,
+                                                    int* __restrict__ choice) {
+  RowGroup<G> rg;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    const uint64_t own = T[i];
+    if (tstate(own) == 2) {
+      if (rg.lane == 0) choice[i] = i;
+      continue;
+    }
+    uint64_t best = 0;
+    int bk = INT_MAX, bj = -1;
+    const int e = gptr[i + 1];
+    for (int k = gptr[i] + rg.lane; k < e; k += G) {
+      const int j = gcol[k];
+      const uint64_t u = T[j];
+      if (tstate(u) == 2 && u > best) { best = u; bk = k; bj = j; }
+    }
+    group_argmax<G>(best, bk, bj);
+    if (rg.lane == 0) choice[i] = bj;
+  }
 }
 
 // Round 2: the remaining nodes (distance 2 from every root) take, among the
 // roots chosen by their round-1 neighbours, the one with the largest tuple.
-__global__ void k_agg_round2(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
-                             const uint64_t* __restrict__ T, const int* __restrict__ choice,
-                             const int* __restrict__ root_id, int* __restrict__ agg, int* err) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int c = choice[i];
-  if (c < 0) {
-    uint64_t best = 0;
-    for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
-      int cj = choice[gcol[k]];
-      if (cj >= 0) {
-        uint64_t u = T[cj];
-        if (u > best) { best = u; c = cj; }
+template <int G>
+__global__ void __launch_bounds__(256) k_agg_round2(int n, const int* __restrict__ gptr,
+                                                    const int* __restrict__ gcol, const uint64_t* __restrict__ T,
+                                                    const int* __restrict__ choice,
+                                                    const int* __restrict__ root_id, int* __restrict__ agg,
+                                                    int* err) {
+  RowGroup<G> rg;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    int c = choice[i];
+    if (c < 0) {
+      uint64_t best = 0;
+      int bk = INT_MAX;
+      const int e = gptr[i + 1];
+      for (int k = gptr[i] + rg.lane; k < e; k += G) {
+        const int cj = choice[gcol[k]];
+        if (cj >= 0) {
+          const uint64_t u = T[cj];
+          if (u > best) { best = u; bk = k; c = cj; }
+        }
       }
+      group_argmax<G>(best, bk, c);
     }
+    if (rg.lane != 0) continue;
+    if (c < 0) {
+      atomic_or_flag(err, kErrUnassigned);
+      agg[i] = 0;
+      continue;
+    }
+    agg[i] = root_id[c];
   }
-  if (c < 0) {
-    atomic_or_flag(err, kErrUnassigned);
-    agg[i] = 0;
-    return;
-  }
-  agg[i] = root_id[c];
 }
 
 __global__ void k_agg_count(int n, const int* __restrict__ agg, int* counts) {
@@ -326,25 +404,42 @@ __device__ void sift_down(int* a, int start, int end) {
 }
 
 // Each aggregate's member list sorted ascending (atomics left it in arrival
-// order); insertion sort for short segments, heap sort for long ones.
-__global__ void k_agg_sort(int nc, const int* __restrict__ agg_ptr, int* __restrict__ agg_rows) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  int* a = agg_rows + agg_ptr[I];
-  int m = agg_ptr[I + 1] - agg_ptr[I];
-  if (m <= 32) {
-    for (int k = 1; k < m; ++k) {
-      int x = a[k];
-      int j = k - 1;
-      while (j >= 0 && a[j] > x) { a[j + 1] = a[j]; --j; }
-      a[j + 1] = x;
+// order).  A group of 32 lanes takes one aggregate: with at most 32 members
+// every member finds its rank by counting the smaller ones (members are
+// distinct), so the sort costs one load, one pass over LDS and one store per
+// member; longer lists fall back to a heap sort by the group's first lane.
+constexpr int kSortGroup = 32;
+__global__ void __launch_bounds__(256) k_agg_sort(int nc, const int* __restrict__ agg_ptr,
+                                                  int* __restrict__ agg_rows) {
+  constexpr int NG = 256 / kSortGroup;
+  __shared__ int sv[NG][kSortGroup];
+  const int grp = threadIdx.x / kSortGroup, lane = threadIdx.x % kSortGroup;
+  const int chunks = (nc + NG - 1) / NG;
+  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int I = c * NG + grp;
+    int m = 0, x = 0;
+    int* a = nullptr;
+    if (I < nc) {
+      a = agg_rows + agg_ptr[I];
+      m = agg_ptr[I + 1] - agg_ptr[I];
+      if (m <= kSortGroup && lane < m) x = a[lane];
     }
-    return;
-  }
-  for (int start = (m - 2) / 2; start >= 0; --start) sift_down(a, start, m - 1);
-  for (int end = m - 1; end > 0; --end) {
-    int t = a[0]; a[0] = a[end]; a[end] = t;
-    sift_down(a, 0, end - 1);
+    if (m <= kSortGroup && lane < m) sv[grp][lane] = x;
+    __syncthreads();
+    if (m <= kSortGroup) {
+      if (lane < m) {
+        int rank = 0;
+        for (int q = 0; q < m; ++q) rank += sv[grp][q] < x;
+        a[rank] = x;
+      }
+    } else if (lane == 0) {
+      for (int start = (m - 2) / 2; start >= 0; --start) sift_down(a, start, m - 1);
+      for (int end = m - 1; end > 0; --end) {
+        int t = a[0]; a[0] = a[end]; a[end] = t;
+        sift_down(a, 0, end - 1);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -446,6 +541,21 @@ __global__ void k_fill_int(size_t n, int* p, int v) {
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = v;
 }
+// Values the host waits for, written straight into its pinned mirror: one
+// launch replaces a copy per value.  Wave w reads item w (its count values
+// spread over the lanes); slot 63 receives the error word.
+__global__ void __launch_bounds__(512) k_mailbox(Mailbox m, const int* __restrict__ err, int* host) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (w < m.n) {
+    int v = 0;
+    for (int c = lane; c < m.count[w]; c += kWave)
+      v += __hip_atomic_load(m.src[w] + (size_t)c * m.stride[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane == 0) host[m.slot[w]] = v;
+  }
+  if (threadIdx.x == 0) host[63] = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 }  // namespace
 
 void launch_check_rowptr(int n, const int* rp, int* err, hipStream_t s) {
@@ -457,53 +567,79 @@ void launch_check_index(int n, const int* idx, int limit, int* err, hipStream_t 
 void launch_check_matrix(int n, const int* rp, const int* ci, const double* val, int* err, hipStream_t s) {
   k_check_matrix<<<grid_for(n), kT, 0, s>>>(n, rp, ci, val, err);
 }
-void launch_strength(int n, const int* rp, const int* ci, const double* val, double alpha,
-                     uint8_t* strong, double* diag, int* err, hipStream_t s) {
-  (void)err;
-  k_strength<<<grid_for(n), kT, 0, s>>>(n, rp, ci, val, alpha, strong, diag);
+void launch_mailbox(const Mailbox& m, const int* err, int* host, hipStream_t s) {
+  k_mailbox<<<1, 512, 0, s>>>(m, err, host);
 }
-void launch_graph_count(int n, const int* rp, const int* ci, const uint8_t* strong, uint8_t* gmask,
+
+int group_lanes(int n, long entries) {
+  int g = 1;
+  while (g < 32 && 4L * g * n < entries) g <<= 1;
+  while (g < 32 && (long)g * n < (1L << 19)) g <<= 1;
+  return g;
+}
+
+
+void launch_strength(int n, int nnz, const int* rp, const int* ci, const double* val, double alpha,
+                     uint8_t* strong, double* diag, hipStream_t s) {
+  if (n <= 0) return;
+  const int G = group_lanes(n, nnz);
+  with_lanes(G, [&](auto g) {
+    k_strength<decltype(g)::value><<<group_grid(n, G), kT, 0, s>>>(n, rp, ci, val, alpha, strong, diag);
+  });
+}
+void launch_graph_count(int n, int nnz, const int* rp, const int* ci, const uint8_t* strong, uint8_t* gmask,
                         int* gdeg, int* cnt, int* err, hipStream_t s) {
-  k_graph_count<<<grid_for(n), kT, 0, s>>>(n, rp, ci, strong, gmask, gdeg, cnt, err);
+  if (n <= 0) return;
+  const int G = group_lanes(n, nnz);
+  with_lanes(G, [&](auto g) {
+    k_graph_count<decltype(g)::value><<<group_grid(n, G), kT, 0, s>>>(n, rp, ci, strong, gmask, gdeg, cnt, err);
+  });
 }
-void launch_graph_fill(int n, const int* rp, const int* ci, const uint8_t* gmask, const int* gptr,
+void launch_graph_fill(int n, int nnz, const int* rp, const int* ci, const uint8_t* gmask, const int* gptr,
                        int* gcol, hipStream_t s) {
-  k_graph_fill<<<grid_for(n), kT, 0, s>>>(n, rp, ci, gmask, gptr, gcol);
+  if (n <= 0) return;
+  const int G = group_lanes(n, nnz);
+  with_lanes(G, [&](auto g) {
+    k_graph_fill<decltype(g)::value><<<group_grid(n, G), kT, 0, s>>>(n, rp, ci, gmask, gptr, gcol);
+  });
 }
-void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* ctl, int* err,
+void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t* M1, int* mc, int* err,
                      hipStream_t s, const int* lbase) {
-  k_mis_init<<<grid_for(n > 0 ? n : 1), kT, 0, s>>>(n, cnt, seed, T, M1, ctl, err, lbase);
+  k_mis_init<<<grid_for(n > 2 * kMisSlots ? n : 2 * kMisSlots), kT, 0, s>>>(n, cnt, seed, T, M1, mc, err, lbase);
 }
 template <int G>
-static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl, int round,
-                        int* block_flag, hipStream_t s) {
+static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc, int round,
+                        hipStream_t s) {
   long g = ((long)n * G + kT - 1) / kT;
   if (g < 1) g = 1;
   if (g > kMisBlocks) g = kMisBlocks;
-  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round);
-  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, ctl, round, block_flag);
-  k_mis_ping<<<1, kT, 0, s>>>((int)g, block_flag, ctl, round);
+  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round);
+  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round);
 }
 
-// block_flag: kMisBlocks ints of scratch
-void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* ctl,
-                      int round, int lanes, int* block_flag, hipStream_t s) {
+void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc,
+                      int round, int lanes, hipStream_t s) {
   switch (lanes) {
-    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
-    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
-    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
-    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
-    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
-    default: mis_round_g<32>(n, gptr, gcol, T, M1, ctl, round, block_flag, s); break;
+    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, mc, round, s); break;
+    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, mc, round, s); break;
+    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, mc, round, s); break;
+    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, mc, round, s); break;
+    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, mc, round, s); break;
+    default: mis_round_g<32>(n, gptr, gcol, T, M1, mc, round, s); break;
   }
 }
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s) {
   k_root_flags<<<grid_for(n), kT, 0, s>>>(n, T, flags);
 }
-void launch_aggregate(int n, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
+void launch_aggregate(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
                       int* choice, int* agg, int* err, hipStream_t s) {
-  k_agg_round1<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, choice);
-  k_agg_round2<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, choice, root_id, agg, err);
+  if (n <= 0) return;
+  const int G = group_lanes(n, nnzg);
+  with_lanes(G, [&](auto g) {
+    constexpr int L = decltype(g)::value;
+    k_agg_round1<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, choice);
+    k_agg_round2<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, choice, root_id, agg, err);
+  });
 }
 void launch_agg_count(int n, const int* agg, int* counts, hipStream_t s) {
   k_agg_count<<<grid_for(n), kT, 0, s>>>(n, agg, counts);
@@ -512,7 +648,10 @@ void launch_agg_scatter(int n, const int* agg, const int* agg_ptr, int* fill, in
   k_agg_scatter<<<grid_for(n), kT, 0, s>>>(n, agg, agg_ptr, fill, agg_rows);
 }
 void launch_agg_sort(int nc, const int* agg_ptr, int* agg_rows, hipStream_t s) {
-  k_agg_sort<<<grid_for(nc), kT, 0, s>>>(nc, agg_ptr, agg_rows);
+  if (nc <= 0) return;
+  long g = (nc + 7) / 8;
+  if (g > 8192) g = 8192;
+  k_agg_sort<<<(int)g, 256, 0, s>>>(nc, agg_ptr, agg_rows);
 }
 void launch_interp(int n, int nc, const int* agg, const int* agg_ptr, const int* agg_rows,
                    const double* B, double* Bc, double* pval, hipStream_t s) {

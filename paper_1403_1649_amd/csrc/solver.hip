@@ -1255,15 +1255,15 @@ void build_solve_graphs(Hierarchy& h) {
   AMG_HIP(hipStreamDestroy(cs));
 }
 
-// Arnoldi on D^-1 A_k (modified Gram-Schmidt) from the seeded start vector;
-// the (m+1) x m Hessenberg matrix and the norms ||D^-1 A q_j|| are copied to
-// the host (row stride 8).
-void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double* w, double* H_out,
-             double* wnorm_out) {
-  hipStream_t s = h.stream;
-  RedCtx rc = red(h);
+// Arnoldi on D^-1 A_k (modified Gram-Schmidt) from the seeded start vector,
+// enqueued on stream s with scalar slots sc (kScArn .. kScArn + 64) and
+// reduction context rc; the (m+1) x m Hessenberg matrix (row stride 8) and
+// the norms ||D^-1 A q_j|| (at 48 + j) are copied to host_out (pinned, 56
+// doubles) without waiting.
+void arnoldi_enqueue(Hierarchy& h, const Level& lv, int m, uint32_t stream, double* Q, double* w, double* sc,
+                     RedCtx rc, double* host_out, hipStream_t s) {
+  (void)h;
   const int n = lv.n;
-  double* sc = h.d_sc;
   launch_elem(n, OpArnStart{Q, sc, stream}, rc, s);
   launch_elem(n, OpDivide{Q, Q, sc + kScArn + 56}, rc, s);
   for (int j = 0; j < m; ++j) {
@@ -1280,9 +1280,15 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
     }
     launch_elem(n, OpDivide{w, Q + (size_t)(j + 1) * n, sc + kScArn + (j + 1) * 8 + j}, rc, s);
   }
-  double* hd = static_cast<double*>(h.h_pinned);
-  AMG_HIP(hipMemcpyAsync(hd, sc + kScArn, 56 * sizeof(double), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  AMG_HIP(hipMemcpyAsync(host_out, sc + kScArn, 56 * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+// The same on the hierarchy's stream, waiting for the result.
+void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double* w, double* H_out,
+             double* wnorm_out) {
+  double* hd = static_cast<double*>(h.h_pinned) + kPinnedArn;
+  arnoldi_enqueue(h, lv, m, stream, Q, w, h.d_sc, red(h), hd, h.stream);
+  AMG_HIP(hipStreamSynchronize(h.stream));
   for (int i = 0; i < 48; ++i) H_out[i] = hd[i];
   for (int j = 0; j < 8; ++j) wnorm_out[j] = hd[48 + j];
 }
