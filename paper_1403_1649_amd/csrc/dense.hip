@@ -503,8 +503,10 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
   }
 }
 
-// A_J += (Y - E) T for every column J outside the panel: 64 x 64 output tiles,
-// each thread 4 x 4 outputs; the panel's pivot rows get Y T directly.
+// A_J += (Y - E) T for every column J outside the panel: 64 x 64 output tiles
+// on the FP64 matrix cores (each wave a 32 x 32 quadrant = 2 x 2 MFMA tiles,
+// k in steps of 4 over the panel width, zero-padded); the panel's pivot rows
+// get Y T directly.
 __global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__ ti, const int* __restrict__ tiles,
                                                     double* __restrict__ work, const double* __restrict__ ybuf,
                                                     const double* __restrict__ tbuf, int K, int b) {
@@ -522,43 +524,49 @@ __global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__
   const double* Y = ybuf + (size_t)t.row0 * b;
   const double* T = tbuf + (size_t)t.row0 * b;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kUpdTile * w; e += 256) {
-    const int i = e / w, j = e - i * w;
-    sY[i][j] = (r0 + i < n) ? Y[(size_t)(r0 + i) * b + j] : 0.0;
+  const int kw = (w + 3) & ~3;   // panel width padded to the MFMA k step
+  for (int e = tid; e < kUpdTile * kw; e += 256) {
+    const int i = e / kw, j = e - i * kw;
+    sY[i][j] = (r0 + i < n && j < w) ? Y[(size_t)(r0 + i) * b + j] : 0.0;
   }
-  for (int e = tid; e < w * kUpdTile; e += 256) {
+  for (int e = tid; e < kw * kUpdTile; e += 256) {
     const int j = e / kUpdTile, c = e - j * kUpdTile;
-    sT[j][c] = (q0 + c < n) ? T[(size_t)j * n + q0 + c] : 0.0;
+    sT[j][c] = (q0 + c < n && j < w) ? T[(size_t)j * n + q0 + c] : 0.0;
   }
   __syncthreads();
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4];
+  const int wv = tid / kWave, l = tid & (kWave - 1);
+  const int qr = (wv >> 1) * 32, qc = (wv & 1) * 32;   // this wave's quadrant
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int sr = 0; sr < 2; ++sr)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = r0 + ty * 4 + a, J = q0 + tx * 4 + c;
-      const bool pivot_row = i >= c0 && i < c0 + w;
-      acc[a][c] = (i < n && J < n && !pivot_row) ? W[(size_t)i * n + J] : 0.0;
-    }
-  for (int j = 0; j < w; ++j) {
-    double y[4], tv[4];
+    for (int sc = 0; sc < 2; ++sc)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) y[a] = sY[ty * 4 + a][j];
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + qr + 16 * sr + mfma_row(l, i), col = q0 + qc + 16 * sc + mfma_col(l);
+        const bool pivot_row = row >= c0 && row < c0 + w;
+        acc[sr][sc][i] = (row < n && col < n && !pivot_row) ? W[(size_t)row * n + col] : 0.0;
+      }
+  for (int kk = 0; kk < kw; kk += 4) {
+    double av[2], bv[2];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) tv[c] = sT[j][tx * 4 + c];
+    for (int sr = 0; sr < 2; ++sr) av[sr] = sY[qr + 16 * sr + (l & 15)][kk + (l >> 4)];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int sc = 0; sc < 2; ++sc) bv[sc] = sT[kk + (l >> 4)][qc + 16 * sc + (l & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = fma(y[a], tv[c], acc[a][c]);
+    for (int sr = 0; sr < 2; ++sr)
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) acc[sr][sc] = mfma_f64_16x16x4(av[sr], bv[sc], acc[sr][sc]);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int sr = 0; sr < 2; ++sr)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = r0 + ty * 4 + a, J = q0 + tx * 4 + c;
-      if (i < n && J < n && (J < c0 || J >= c0 + w)) W[(size_t)i * n + J] = acc[a][c];
-    }
+    for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = r0 + qr + 16 * sr + mfma_row(l, i), col = q0 + qc + 16 * sc + mfma_col(l);
+        if (row < n && col < n && (col < c0 || col >= c0 + w)) W[(size_t)row * n + col] = acc[sr][sc][i];
+      }
 }
 
 __global__ void k_dense_to_float(size_t nn, const double* __restrict__ in, float* __restrict__ out) {

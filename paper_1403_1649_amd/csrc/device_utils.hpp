@@ -108,6 +108,17 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* tmp, int* total)
   return res;
 }
 
+// FP64 matrix-core step D = A B + C on a 16 x 16 tile with k = 4
+// (v_mfma_f64_16x16x4f64).  Operands per lane l of the wave: a = A[l % 16][l / 16],
+// b = B[l / 16][l % 16]; the accumulator holds D[l / 16 + 4 i][l % 16] in
+// element i (rows interleaved by four; checked on the device).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f64x4 mfma_f64_16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int mfma_row(int lane, int i) { return (lane >> 4) + 4 * i; }
+__device__ __forceinline__ int mfma_col(int lane) { return lane & 15; }
+
 // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
 // This bijection of [0, gridDim.x) gives every XCD a contiguous run of
 // logical blocks, so rows that gather from overlapping neighbourhoods share

@@ -410,18 +410,31 @@ struct MProlongK {
   __device__ void finalize(int, const double*) const {}
 };
 
-// coarsest level: X_L = A_L^-1 B_L, one wave per row, lanes over columns
+// coarsest level: X_L = A_L^-1 B_L on the FP64 matrix cores, one wave per
+// 16 x 16 tile of X (rows x right-hand sides), k in steps of 4 over the
+// inverse's columns (zero-padded); operands of the FP32 cycle are widened.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gemm_coarse(int n, int R, const T* __restrict__ Ainv,
+__global__ void __launch_bounds__(kBlock) k_gemm_coarse(int n, int R, const double* __restrict__ Ainv,
                                                         const T* __restrict__ B, T* __restrict__ X, ActAny a) {
   if (!a.on()) return;
-  const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  const int c = threadIdx.x & (kWave - 1);
-  if (row >= n || c >= R) return;
-  const T* Ar = Ainv + (size_t)row * n;
-  T s = T(0);
-  for (int j = 0; j < n; ++j) s += Ar[j] * B[(size_t)j * R + c];
-  X[(size_t)row * R + c] = s;
+  const int tiles_c = (R + 15) / 16;
+  const int wt = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (wt >= ((n + 15) / 16) * tiles_c) return;
+  const int l = threadIdx.x & (kWave - 1);
+  const int R0 = (wt / tiles_c) * 16, C0 = (wt % tiles_c) * 16;
+  const int ar = R0 + (l & 15), bc = C0 + (l & 15);
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < n; k += 4) {
+    const int kk = k + (l >> 4);
+    const double av = (ar < n && kk < n) ? Ainv[(size_t)ar * n + kk] : 0.0;
+    const double bv = (bc < R && kk < n) ? (double)B[(size_t)kk * R + bc] : 0.0;
+    acc = mfma_f64_16x16x4(av, bv, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = R0 + mfma_row(l, i), col = C0 + mfma_col(l);
+    if (row < n && col < R) X[(size_t)row * R + col] = (T)acc[i];
+  }
 }
 
 // outer flexible CG, per column
@@ -647,9 +660,6 @@ template <> const float* pvals_t<float>(const Level& l) { return l.pval32; }
 template <typename T> const T* rvals_t(const Level& l);
 template <> const double* rvals_t<double>(const Level& l) { return l.rval; }
 template <> const float* rvals_t<float>(const Level& l) { return l.rval32; }
-template <typename T> const T* cinv_t(const Hierarchy& h);
-template <> const double* cinv_t<double>(const Hierarchy& h) { return h.cinv; }
-template <> const float* cinv_t<float>(const Hierarchy& h) { return h.cinv32; }
 
 // per-level work blocks [n][R] (or [n_{k+1}][R])
 struct MLevel {
@@ -670,8 +680,9 @@ struct MWork {
 template <typename T>
 void coarse_m(Hierarchy& h, const MCtx& m, const T* b, T* x, const int* act) {
   const int n = h.levels.back().n;
-  const int rpb = kBlock / kWave;
-  k_gemm_coarse<T><<<(n + rpb - 1) / rpb, kBlock, 0, h.stream>>>(n, m.R, cinv_t<T>(h), b, x, ActAny{act});
+  const int wpb = kBlock / kWave;
+  const int tiles = ((n + 15) / 16) * ((m.R + 15) / 16);
+  k_gemm_coarse<T><<<(tiles + wpb - 1) / wpb, kBlock, 0, h.stream>>>(n, m.R, h.cinv, b, x, ActAny{act});
 }
 
 template <typename T>
