@@ -228,9 +228,9 @@ enum KSlot : int {
 };
 constexpr int kMaxPartialBlocks = 2048;
 // pinned host mirror: ints 0..63 for control read-backs, then (in doubles
-// from kPinnedArn) 64 per level for Arnoldi results
+// from kPinnedArn) the Arnoldi results
 constexpr int kPinnedArn = 64;
-constexpr size_t kPinnedBytes = (kPinnedArn + 64 * 24) * sizeof(double);
+constexpr size_t kPinnedBytes = (kPinnedArn + 64) * sizeof(double);
 constexpr int kBlockRowsGemv = 4;   // rows per 256-thread block of a dense GEMV (one wave per row)
 
 // ---------------------------------------------------------------- launchers

@@ -437,37 +437,6 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   sy.wait_and_check();
 
   const bool debug = std::getenv("AMG_DEBUG") != nullptr;
-  // The Arnoldi estimate of a level needs only that level's matrix: it runs on
-  // a second stream, overlapped with the coarsening of the next levels, and
-  // the weights are applied once every level exists.  (The learned smoother
-  // validates against omega_k during the level loop, so it waits instead.)
-  const bool async_arn = o.smoother != AMG_SMOOTHER_LEARNED;
-  hipStream_t as = nullptr;
-  struct AsyncStream {
-    hipStream_t* s;
-    ~AsyncStream() {
-      if (*s) {
-        (void)hipStreamSynchronize(*s);
-        (void)hipStreamDestroy(*s);
-      }
-    }
-  } as_guard{&as};
-  struct PendingArn { int k, m; hipEvent_t done; };
-  std::vector<PendingArn> pending;
-  struct EventGuard {
-    std::vector<PendingArn>* p;
-    ~EventGuard() {
-      for (auto& q : *p)
-        if (q.done) (void)hipEventDestroy(q.done);
-    }
-  } ev_guard{&pending};
-  RedCtx arn_rc{nullptr, nullptr};
-  if (async_arn) {
-    AMG_HIP(hipStreamCreateWithFlags(&as, hipStreamNonBlocking));
-    arn_rc.part = tmp.alloc_n<double>(kMaxPartialBlocks * 4);
-    arn_rc.ticket = tmp.alloc_n<unsigned>(64);
-    launch_fill_int(64, reinterpret_cast<int*>(arn_rc.ticket), 0, s);
-  }
   if (o.smoother == AMG_SMOOTHER_LEARNED) {
     if (!o.mlp_weights) throw Error(AMG_EINVAL, "learned smoother without weights");
     const int np = mlp_num_params();
@@ -570,21 +539,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     double* w = tmp.alloc_n<double>(n);
     lv.wdinv = h.arena.alloc_n<double>(n);
     if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
-    if (async_arn) {
-      if (k >= 24) throw Error(AMG_EINVAL, "more than 24 levels");
-      hipEvent_t ready = nullptr;
-      AMG_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-      AMG_HIP(hipEventRecord(ready, s));
-      AMG_HIP(hipStreamWaitEvent(as, ready, 0));
-      AMG_HIP(hipEventDestroy(ready));
-      double* sc = tmp.alloc_n<double>(kScArn + 64);
-      double* host = static_cast<double*>(h.h_pinned) + kPinnedArn + 64 * k;
-      arnoldi_enqueue(h, lv, m, o.seed + 1, Q, w, sc, arn_rc, host, as);
-      PendingArn p{k, m, nullptr};
-      AMG_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming));
-      AMG_HIP(hipEventRecord(p.done, as));
-      pending.push_back(p);
-    } else {
+    {
       double Hh[48], wn[8];
       arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
       set_jacobi_weight(h, lv, m, Hh, wn);
@@ -614,15 +569,6 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       sy.wait_and_check();
     }
     h.levels.push_back(lc);
-  }
-
-  // damped Jacobi weights of the levels whose Arnoldi ran alongside
-  for (const PendingArn& p : pending) {
-    AMG_HIP(hipEventSynchronize(p.done));
-    const double* host = static_cast<const double*>(h.h_pinned) + kPinnedArn + 64 * p.k;
-    set_jacobi_weight(h, h.levels[p.k], p.m, host, host + 48);
-    if (debug) std::fprintf(stderr, "amg: level %d rho=%.6f omega=%.6f\n", p.k, h.levels[p.k].rho,
-                            h.levels[p.k].omega);
   }
 
   // coarsest level: dense inverse

@@ -87,6 +87,34 @@ def test_galerkin_large_rows_path():
     assert np.allclose(got_v, want.data, rtol=1e-12, atol=1e-12 * np.abs(want.data).max())
 
 
+def test_galerkin_every_row_tier():
+    """Coarse rows of every size class in one product: a few terms (wave,
+    two per lane), up to 512 terms (wave, eight per lane) and beyond (block
+    extraction), with aggregates of 1 to 120 members in a random order."""
+    rng = np.random.default_rng(9)
+    import scipy.sparse as sp
+    n = 4000
+    M = sp.random(n, n, density=6.0 / n, random_state=rng)
+    M = M + M.T + sp.identity(n) * 20
+    S = M.tocsr()
+    S.sort_indices()
+    A = P.CSR(S.indptr, S.indices, S.data)
+    sizes = np.concatenate([np.ones(300, int), rng.integers(2, 12, 150), rng.integers(30, 60, 20),
+                            rng.integers(100, 121, 6)])
+    sizes = sizes[np.cumsum(sizes) <= n]
+    sizes[-1] += n - sizes.sum()
+    nc = len(sizes)
+    agg = rng.permutation(np.repeat(np.arange(nc), sizes)).astype(np.int32)
+    pval = rng.uniform(0.5, 1.5, n)
+    terms = np.bincount(agg, weights=np.diff(S.indptr), minlength=nc)
+    assert terms.min() <= 128 and ((terms > 128) & (terms <= 512)).any() and terms.max() > 512
+    rp, ci, v = to_dev(A)
+    got_rp, got_ci, got_v = amg.galerkin(rp, ci, v, torch.from_numpy(agg).cuda(), dev_vec(pval), nc)
+    want = O.galerkin(S, agg.astype(np.int64), pval, nc)
+    assert np.array_equal(got_rp, want.indptr) and np.array_equal(got_ci, want.indices)
+    assert np.allclose(got_v, want.data, rtol=1e-12, atol=1e-12 * np.abs(want.data).max())
+
+
 CASES = [
     ("poisson2d_128", lambda: P.poisson2d(128), 2),
     ("poisson2d_37x53", lambda: P.poisson2d(37, 53), 2),
