@@ -503,6 +503,127 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
   }
 }
 
+// The panel in two launches, so that one workgroup per system only does the
+// b steps on the b x b pivot block.  A step is linear in every non-pivot row:
+// row <- row * E_j, where E_j depends only on the pivot row of step j.  So the
+// pivot block's workgroup also runs the steps on b virtual rows that start as
+// the unit rows, which end as X = E_0 E_1 ... E_{b-1}; every other row of the
+// panel is then row * X, a (n - b) x b x b product done by many workgroups.
+// k_gjb_pivot: one workgroup of 2b threads per system: thread j < b holds
+// pivot row c0 + j, thread b + q the virtual row e_q.
+template <int B>
+__global__ void __launch_bounds__(2 * B) k_gjb_pivot(const TermInfo* __restrict__ ti, double* __restrict__ work,
+                                                     double* __restrict__ ybuf, double* __restrict__ xbuf, int K,
+                                                     int* err) {
+  __shared__ double s_row[B];
+  const TermInfo t = ti[blockIdx.x];
+  const int n = t.n, c0 = K * B;
+  if (c0 >= n) return;
+  const int w = min(B, n - c0);
+  double* W = work + t.off;
+  double* Y = ybuf + (size_t)t.row0 * B;
+  const int tid = threadIdx.x;
+  const bool pivot = tid < B;
+  const int q0 = tid - B;   // virtual row index
+  double P[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q)
+    P[q] = pivot ? ((tid < w && q < w) ? W[(size_t)(c0 + tid) * n + c0 + q] : 0.0) : (q == q0 ? 1.0 : 0.0);
+#pragma unroll 1
+  for (int j = 0; j < w; ++j) {
+    if (tid == j) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) s_row[q] = P[q];
+    }
+    __syncthreads();
+    const double p = s_row[j];
+    if (tid == 0 && !(p > 0.0 && p < INFINITY)) atomic_or_flag(err, kErrNotSPD);
+    const double inv = 1.0 / p;
+    double c = 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) c = (q == j) ? P[q] : c;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (q == j) {
+        P[q] = (tid == j) ? inv : -c * inv;
+      } else {
+        const double rk = s_row[q] * inv;
+        P[q] = (tid == j) ? rk : P[q] - c * rk;
+      }
+    }
+    __syncthreads();
+  }
+  if (pivot) {
+    if (tid < w) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        if (q < w) {
+          W[(size_t)(c0 + tid) * n + c0 + q] = P[q];
+          Y[(size_t)(c0 + tid) * B + q] = P[q];
+        }
+      }
+    }
+  } else {
+    double* X = xbuf + (size_t)blockIdx.x * B * B;
+#pragma unroll
+    for (int q = 0; q < B; ++q) X[q0 * B + q] = P[q];
+  }
+}
+
+// k_gjb_apply: the non-pivot rows of every system's 32-column panel times X
+// on the FP64 matrix cores (each wave 16 rows x 32 columns: 2 MFMA tiles, 8
+// k-steps), and the pivot rows of A (all columns) copied to T for the update.
+// Work items are (system, block of 256 rows) pairs from the host's table.
+__global__ void __launch_bounds__(256) k_gjb_apply(const TermInfo* __restrict__ ti, const int* __restrict__ items,
+                                                   double* __restrict__ work, double* __restrict__ ybuf,
+                                                   double* __restrict__ tbuf, const double* __restrict__ xbuf,
+                                                   int K) {
+  constexpr int B = 32;
+  __shared__ double sX[B][B + 1];
+  const int sys = items[2 * blockIdx.x], rb = items[2 * blockIdx.x + 1];
+  const TermInfo t = ti[sys];
+  const int n = t.n, c0 = K * B;
+  if (c0 >= n) return;
+  const int w = min(B, n - c0);
+  double* W = work + t.off;
+  double* Y = ybuf + (size_t)t.row0 * B;
+  double* T = tbuf + (size_t)t.row0 * B;
+  const double* X = xbuf + (size_t)sys * B * B;
+  for (int e = threadIdx.x; e < B * B; e += 256) sX[e / B][e % B] = X[e];
+  // the pivot rows of A before the update (their panel entries no longer
+  // matter: the update writes only columns outside the panel); item rb
+  // copies its share [256 B rb, 256 B (rb + 1))
+  const int e1 = min(w * n, (rb + 1) * 256 * B);
+  for (int e = rb * 256 * B + threadIdx.x; e < e1; e += 256) {
+    const int j = e / n, J = e - j * n;
+    T[(size_t)j * n + J] = W[(size_t)(c0 + j) * n + J];
+  }
+  __syncthreads();
+  const int wv = threadIdx.x / kWave, l = threadIdx.x & (kWave - 1);
+  for (int R0 = rb * 256 + wv * 16; R0 < min(n, (rb + 1) * 256); R0 += 64) {
+    const int ar = R0 + (l & 15);
+    const bool arow = ar < n && !(ar >= c0 && ar < c0 + w);
+    f64x4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int kk = 0; kk < B; kk += 4) {
+      const int kc = kk + (l >> 4);
+      const double av = (arow && kc < w) ? W[(size_t)ar * n + c0 + kc] : 0.0;
+#pragma unroll
+      for (int sc = 0; sc < 2; ++sc) acc[sc] = mfma_f64_16x16x4(av, sX[kc][16 * sc + (l & 15)], acc[sc]);
+    }
+#pragma unroll
+    for (int sc = 0; sc < 2; ++sc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = R0 + mfma_row(l, i), col = 16 * sc + mfma_col(l);
+        if (row < n && !(row >= c0 && row < c0 + w) && col < w) {
+          W[(size_t)row * n + c0 + col] = acc[sc][i];
+          Y[(size_t)row * B + col] = acc[sc][i];
+        }
+      }
+  }
+}
+
 // A_J += (Y - E) T for every column J outside the panel: 64 x 64 output tiles
 // on the FP64 matrix cores (each wave a 32 x 32 quadrant = 2 x 2 MFMA tiles,
 // k in steps of 4 over the panel width, zero-padded); the panel's pivot rows
@@ -686,9 +807,29 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
   AMG_HIP(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
   const int npanels = (nmax + b - 1) / b;
   const int ntiles = (int)(tiles.size() / 2);
+  // panels of 32 columns: pivot block + product; narrower panels (systems of
+  // more than 1024 rows) keep the one-workgroup register panel
+  int* d_items = nullptr;
+  double* xbuf = nullptr;
+  int nitems = 0;
+  if (b == 32) {
+    std::vector<int> items;
+    for (int t = 0; t < nterm; ++t)
+      for (int rb = 0; rb * 256 < h_term[t].n; ++rb) {
+        items.push_back(t);
+        items.push_back(rb);
+      }
+    nitems = (int)(items.size() / 2);
+    d_items = tmp.alloc_n<int>(items.size());
+    xbuf = tmp.alloc_n<double>((size_t)nterm * 32 * 32);
+    AMG_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
   for (int K = 0; K < npanels; ++K) {
     switch (b) {
-      case 32: k_gjb_panel_reg<32, 1><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
+      case 32:
+        k_gjb_pivot<32><<<nterm, 64, 0, s>>>(d_term, inv, ybuf, xbuf, K, err);
+        k_gjb_apply<<<nitems, 256, 0, s>>>(d_term, d_items, inv, ybuf, tbuf, xbuf, K);
+        break;
       case 16: k_gjb_panel_reg<16, 2><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
       case 8: k_gjb_panel_reg<8, 4><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
       default: k_gjb_panel_reg<4, 8><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
