@@ -509,13 +509,15 @@ __global__ void __launch_bounds__(kPanelThreads) k_gjb_panel_reg(const TermInfo*
 // pivot block's workgroup also runs the steps on b virtual rows that start as
 // the unit rows, which end as X = E_0 E_1 ... E_{b-1}; every other row of the
 // panel is then row * X, a (n - b) x b x b product done by many workgroups.
-// k_gjb_pivot: one workgroup of 2b threads per system: thread j < b holds
-// pivot row c0 + j, thread b + q the virtual row e_q.
-template <int B>
-__global__ void __launch_bounds__(2 * B) k_gjb_pivot(const TermInfo* __restrict__ ti, double* __restrict__ work,
-                                                     double* __restrict__ ybuf, double* __restrict__ xbuf, int K,
-                                                     int* err) {
-  __shared__ double s_row[B];
+// k_gjb_pivot: one workgroup per system, the 64 x 32 block (32 pivot rows,
+// then the 32 virtual rows) in LDS and every element updated in parallel at
+// each step (two per thread), with the arithmetic of the register panel:
+// pivot row s / p, column j -c / p (1 / p at the pivot), others a - c (s / p).
+__global__ void __launch_bounds__(1024) k_gjb_pivot(const TermInfo* __restrict__ ti, double* __restrict__ work,
+                                                    double* __restrict__ ybuf, double* __restrict__ xbuf, int K,
+                                                    int* err) {
+  constexpr int B = 32, ROWS = 2 * B;
+  __shared__ double M[ROWS][B + 1];
   const TermInfo t = ti[blockIdx.x];
   const int n = t.n, c0 = K * B;
   if (c0 >= n) return;
@@ -523,61 +525,57 @@ __global__ void __launch_bounds__(2 * B) k_gjb_pivot(const TermInfo* __restrict_
   double* W = work + t.off;
   double* Y = ybuf + (size_t)t.row0 * B;
   const int tid = threadIdx.x;
-  const bool pivot = tid < B;
-  const int q0 = tid - B;   // virtual row index
-  double P[B];
-#pragma unroll
-  for (int q = 0; q < B; ++q)
-    P[q] = pivot ? ((tid < w && q < w) ? W[(size_t)(c0 + tid) * n + c0 + q] : 0.0) : (q == q0 ? 1.0 : 0.0);
+  for (int e = tid; e < ROWS * B; e += 1024) {
+    const int i = e / B, q = e % B;
+    M[i][q] = i < B ? ((i < w && q < w) ? W[(size_t)(c0 + i) * n + c0 + q] : 0.0) : (q == i - B ? 1.0 : 0.0);
+  }
+  __syncthreads();
 #pragma unroll 1
   for (int j = 0; j < w; ++j) {
-    if (tid == j) {
-#pragma unroll
-      for (int q = 0; q < B; ++q) s_row[q] = P[q];
-    }
-    __syncthreads();
-    const double p = s_row[j];
+    const double p = M[j][j];
     if (tid == 0 && !(p > 0.0 && p < INFINITY)) atomic_or_flag(err, kErrNotSPD);
     const double inv = 1.0 / p;
-    double c = 0.0;
+    double nv[2];
 #pragma unroll
-    for (int q = 0; q < B; ++q) c = (q == j) ? P[q] : c;
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * 1024, i = e / B, q = e % B;
+      const double c = M[i][j];
       if (q == j) {
-        P[q] = (tid == j) ? inv : -c * inv;
+        nv[h] = (i == j) ? inv : -c * inv;
       } else {
-        const double rk = s_row[q] * inv;
-        P[q] = (tid == j) ? rk : P[q] - c * rk;
+        const double rk = M[j][q] * inv;
+        nv[h] = (i == j) ? rk : M[i][q] - c * rk;
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + h * 1024;
+      M[e / B][e % B] = nv[h];
     }
     __syncthreads();
   }
-  if (pivot) {
-    if (tid < w) {
-#pragma unroll
-      for (int q = 0; q < B; ++q) {
-        if (q < w) {
-          W[(size_t)(c0 + tid) * n + c0 + q] = P[q];
-          Y[(size_t)(c0 + tid) * B + q] = P[q];
-        }
+  double* X = xbuf + (size_t)blockIdx.x * B * B;
+  for (int e = tid; e < ROWS * B; e += 1024) {
+    const int i = e / B, q = e % B;
+    if (i < B) {
+      if (i < w && q < w) {
+        W[(size_t)(c0 + i) * n + c0 + q] = M[i][q];
+        Y[(size_t)(c0 + i) * B + q] = M[i][q];
       }
+    } else {
+      X[(i - B) * B + q] = M[i][q];
     }
-  } else {
-    double* X = xbuf + (size_t)blockIdx.x * B * B;
-#pragma unroll
-    for (int q = 0; q < B; ++q) X[q0 * B + q] = P[q];
   }
 }
 
 // k_gjb_apply: the non-pivot rows of every system's 32-column panel times X
 // on the FP64 matrix cores (each wave 16 rows x 32 columns: 2 MFMA tiles, 8
-// k-steps), and the pivot rows of A (all columns) copied to T for the update.
-// Work items are (system, block of 256 rows) pairs from the host's table.
+// k-steps).  Work items are (system, block of 256 rows) pairs from the host's
+// table.
 __global__ void __launch_bounds__(256) k_gjb_apply(const TermInfo* __restrict__ ti, const int* __restrict__ items,
                                                    double* __restrict__ work, double* __restrict__ ybuf,
-                                                   double* __restrict__ tbuf, const double* __restrict__ xbuf,
-                                                   int K) {
+                                                   const double* __restrict__ xbuf, int K) {
   constexpr int B = 32;
   __shared__ double sX[B][B + 1];
   const int sys = items[2 * blockIdx.x], rb = items[2 * blockIdx.x + 1];
@@ -587,17 +585,8 @@ __global__ void __launch_bounds__(256) k_gjb_apply(const TermInfo* __restrict__ 
   const int w = min(B, n - c0);
   double* W = work + t.off;
   double* Y = ybuf + (size_t)t.row0 * B;
-  double* T = tbuf + (size_t)t.row0 * B;
   const double* X = xbuf + (size_t)sys * B * B;
   for (int e = threadIdx.x; e < B * B; e += 256) sX[e / B][e % B] = X[e];
-  // the pivot rows of A before the update (their panel entries no longer
-  // matter: the update writes only columns outside the panel); item rb
-  // copies its share [256 B rb, 256 B (rb + 1))
-  const int e1 = min(w * n, (rb + 1) * 256 * B);
-  for (int e = rb * 256 * B + threadIdx.x; e < e1; e += 256) {
-    const int j = e / n, J = e - j * n;
-    T[(size_t)j * n + J] = W[(size_t)(c0 + j) * n + J];
-  }
   __syncthreads();
   const int wv = threadIdx.x / kWave, l = threadIdx.x & (kWave - 1);
   for (int R0 = rb * 256 + wv * 16; R0 < min(n, (rb + 1) * 256); R0 += 64) {
@@ -628,9 +617,14 @@ __global__ void __launch_bounds__(256) k_gjb_apply(const TermInfo* __restrict__ 
 // on the FP64 matrix cores (each wave a 32 x 32 quadrant = 2 x 2 MFMA tiles,
 // k in steps of 4 over the panel width, zero-padded); the panel's pivot rows
 // get Y T directly.
+// mode 0: every row of the tile, T from tbuf (copied before the panel wrote
+// its pivot rows); mode 1: the rows outside the pivot block only, T read from
+// the pivot rows of A themselves (no launch writes them until mode 2); mode 2:
+// the pivot rows only (tiles (system, column tile), rows from c0), each
+// workgroup reading its columns of the pivot rows before writing them.
 __global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__ ti, const int* __restrict__ tiles,
                                                     double* __restrict__ work, const double* __restrict__ ybuf,
-                                                    const double* __restrict__ tbuf, int K, int b) {
+                                                    const double* __restrict__ tbuf, int K, int b, int mode) {
   __shared__ double sY[kUpdTile][33];
   __shared__ double sT[32][kUpdTile + 1];
   const TermInfo t = ti[tiles[2 * blockIdx.x]];
@@ -639,11 +633,12 @@ __global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__
   const int w = min(b, n - c0);
   const int nt = (n + kUpdTile - 1) / kUpdTile;
   const int tile = tiles[2 * blockIdx.x + 1];
-  const int r0 = (tile / nt) * kUpdTile, q0 = (tile % nt) * kUpdTile;
+  const int r0 = mode == 2 ? c0 : (tile / nt) * kUpdTile, q0 = (tile % nt) * kUpdTile;
   if (q0 >= c0 && q0 + kUpdTile <= c0 + w) return;   // tile entirely inside the panel
+  if (mode == 1 && r0 >= c0 && r0 + kUpdTile <= c0 + w) return;   // pivot rows only: mode 2
   double* W = work + t.off;
   const double* Y = ybuf + (size_t)t.row0 * b;
-  const double* T = tbuf + (size_t)t.row0 * b;
+  const double* T = mode == 0 ? tbuf + (size_t)t.row0 * b : W + (size_t)c0 * n;
   const int tid = threadIdx.x;
   const int kw = (w + 3) & ~3;   // panel width padded to the MFMA k step
   for (int e = tid; e < kUpdTile * kw; e += 256) {
@@ -686,7 +681,9 @@ __global__ void __launch_bounds__(256) k_gjb_update(const TermInfo* __restrict__
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = r0 + qr + 16 * sr + mfma_row(l, i), col = q0 + qc + 16 * sc + mfma_col(l);
-        if (row < n && col < n && (col < c0 || col >= c0 + w)) W[(size_t)row * n + col] = acc[sr][sc][i];
+        const bool pivot_row = row >= c0 && row < c0 + w;
+        const bool mine = mode == 0 || (mode == 1) != pivot_row;
+        if (mine && row < n && col < n && (col < c0 || col >= c0 + w)) W[(size_t)row * n + col] = acc[sr][sc][i];
       }
 }
 
@@ -810,31 +807,42 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
   // panels of 32 columns: pivot block + product; narrower panels (systems of
   // more than 1024 rows) keep the one-workgroup register panel
   int* d_items = nullptr;
+  int* d_ptiles = nullptr;
   double* xbuf = nullptr;
-  int nitems = 0;
+  int nitems = 0, nptiles = 0;
   if (b == 32) {
-    std::vector<int> items;
-    for (int t = 0; t < nterm; ++t)
+    std::vector<int> items, ptiles;
+    for (int t = 0; t < nterm; ++t) {
       for (int rb = 0; rb * 256 < h_term[t].n; ++rb) {
         items.push_back(t);
         items.push_back(rb);
       }
+      for (int q = 0; q * kUpdTile < h_term[t].n; ++q) {   // mode-2 tiles: one per column tile
+        ptiles.push_back(t);
+        ptiles.push_back(q);
+      }
+    }
     nitems = (int)(items.size() / 2);
+    nptiles = (int)(ptiles.size() / 2);
     d_items = tmp.alloc_n<int>(items.size());
+    d_ptiles = tmp.alloc_n<int>(ptiles.size());
     xbuf = tmp.alloc_n<double>((size_t)nterm * 32 * 32);
     AMG_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(d_ptiles, ptiles.data(), ptiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
   }
   for (int K = 0; K < npanels; ++K) {
     switch (b) {
       case 32:
-        k_gjb_pivot<32><<<nterm, 64, 0, s>>>(d_term, inv, ybuf, xbuf, K, err);
-        k_gjb_apply<<<nitems, 256, 0, s>>>(d_term, d_items, inv, ybuf, tbuf, xbuf, K);
-        break;
+        k_gjb_pivot<<<nterm, 1024, 0, s>>>(d_term, inv, ybuf, xbuf, K, err);
+        k_gjb_apply<<<nitems, 256, 0, s>>>(d_term, d_items, inv, ybuf, xbuf, K);
+        k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, nullptr, K, b, 1);
+        k_gjb_update<<<nptiles, 256, 0, s>>>(d_term, d_ptiles, inv, ybuf, nullptr, K, b, 2);
+        continue;
       case 16: k_gjb_panel_reg<16, 2><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
       case 8: k_gjb_panel_reg<8, 4><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
       default: k_gjb_panel_reg<4, 8><<<nterm, pth, 0, s>>>(d_term, inv, ybuf, tbuf, K, err); break;
     }
-    k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, tbuf, K, b);
+    k_gjb_update<<<ntiles, 256, 0, s>>>(d_term, d_tiles, inv, ybuf, tbuf, K, b, 0);
   }
   if (inv32) k_dense_to_float<<<(int)std::min<size_t>((total + 255) / 256, 4096), 256, 0, s>>>(total, inv, inv32);
   AMG_HIP(hipStreamSynchronize(s));   // the host tile table is read before it goes away
