@@ -447,6 +447,20 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     sy.wait_and_check();
     h.opt.mlp_weights = nullptr;   // the host pointer is not kept
   }
+  // The Arnoldi of a level runs behind the next level's first kernels: its
+  // Hessenberg matrix is read at the next sync, not waited for on its own.
+  int arn_level = -1, arn_m = 0;
+  double* arn_host = static_cast<double*>(h.h_pinned) + kPinnedArn;
+  auto take_arnoldi = [&]() {
+    if (arn_level < 0) return;
+    double Hh[48], wn[8];
+    for (int i = 0; i < 48; ++i) Hh[i] = arn_host[i];
+    for (int j = 0; j < 8; ++j) wn[j] = arn_host[48 + j];
+    Level& la = h.levels[arn_level];
+    set_jacobi_weight(h, la, arn_m, Hh, wn);
+    if (debug) std::fprintf(stderr, "amg: level %d rho=%.6f omega=%.6f\n", arn_level, la.rho, la.omega);
+    arn_level = -1;
+  };
   while (true) {
     const int k = (int)h.levels.size() - 1;
     Level& lv = h.levels[k];
@@ -457,7 +471,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     const int n = lv.n, nnz = lv.nnz;
 
     // the sliced-ELL copy serves the solve and, on stencil-like levels, the
-    // Arnoldi mat-vecs; its size is read back with the graph's
+    // Arnoldi mat-vecs; its size is read back with the first MIS(2) count
     sell_begin(h, tmp, lv, sy, 2);
 
     // strength (Section 2.1.1) and the strong graph G = C u C^T
@@ -469,11 +483,10 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     launch_graph_count(n, nnz, lv.rp, lv.ci, lv.strong, gmask, gdeg, cnt, h.d_err, s);
     int* gptr = tmp.alloc_n<int>(n + 1);
     scan_to_ptr(gdeg, gptr, n, h.scan, s);
-    sy.fetch(gptr + n, 0);
-    sy.wait_and_check();
-    const int nnzg = sy.hp()[0];
-    sell_finish(h, lv, (size_t)sy.hp()[2]);
-    int* gcol = tmp.alloc_n<int>(nnzg > 0 ? nnzg : 1);
+    sy.fetch(gptr + n, 3);
+    // the pattern is structurally symmetric with a full diagonal (checked),
+    // so G has at most nnz - n entries: no read-back before the fill
+    int* gcol = tmp.alloc_n<int>(nnz > 0 ? nnz : 1);
     launch_graph_fill(n, nnz, lv.rp, lv.ci, gmask, gptr, gcol, s);
 
     // MIS(2) rounds (Algorithm 2)
@@ -482,13 +495,19 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_mis, h.d_err, s);
     int round = 0;
     int batch = 8;   // rounds between read-backs: a round after the last exits at entry
-    const int glanes = group_lanes(n, nnzg);
+    int nnzg = -1;
+    const int glanes = group_lanes(n, (long)nnz - n);
     while (true) {
       for (int b = 0; b < batch; ++b, ++round)
         launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s);
       sy.fetch(h.d_mis + mis_word(round & 1, 0), 0, kMisSlots, mis_word(0, 1));
       sy.fetch(h.d_mis + kMisRoundsWord, 1);
       sy.wait_and_check();
+      if (nnzg < 0) {   // the level's first read-back also brings the sizes of G and of the sliced ELL
+        take_arnoldi();
+        nnzg = sy.hp()[3];
+        sell_finish(h, lv, (size_t)sy.hp()[2]);
+      }
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
       batch = 4;
@@ -539,14 +558,16 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     double* w = tmp.alloc_n<double>(n);
     lv.wdinv = h.arena.alloc_n<double>(n);
     if (h.mixed()) lv.wdinv32 = h.arena.alloc_n<float>(n);
-    {
+    if (debug) std::fprintf(stderr, "amg: level %d nc=%d nnz_c=%d\n", k, nc, lc.nnz);
+    if (o.smoother != AMG_SMOOTHER_LEARNED) {
+      arnoldi_enqueue(h, lv, m, o.seed + 1, Q, w, h.d_sc, RedCtx{h.d_part, h.d_ticket}, arn_host, s);
+      arn_level = k;
+      arn_m = m;
+    } else {
       double Hh[48], wn[8];
       arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
       set_jacobi_weight(h, lv, m, Hh, wn);
-      if (debug) std::fprintf(stderr, "amg: level %d nc=%d nnz_c=%d rho=%.6f omega=%.6f\n", k, nc, lc.nnz, lv.rho,
-                              lv.omega);
-    }
-    if (o.smoother == AMG_SMOOTHER_LEARNED) {
+      if (debug) std::fprintf(stderr, "amg: level %d rho=%.6f omega=%.6f\n", k, lv.rho, lv.omega);
       // learned per-row weights, kept only when they smooth better than
       // omega_k on validation samples (or always, when the caller says so)
       const bool always = (o.flags & AMG_FLAG_LEARNED_ALWAYS) != 0;
@@ -596,6 +617,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   for (int k = 0; k < h.L(); ++k)
     if (h.levels[k].nslices == 0) build_sell(h, tmp, h.levels[k]);
   sy.wait_and_check();
+  take_arnoldi();
   if (!(o.flags & AMG_FLAG_NO_TUNE)) autotune_levels(h);
   if (o.probe != AMG_PROBE_NONE) {
     AMG_HIP(hipEventCreate(&h.pev[0]));
