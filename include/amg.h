@@ -267,8 +267,9 @@ int32_t amg_export_level(const amg_hierarchy* h, int32_t k, int32_t* row_ptr, in
  * kernel families the solve uses: lanes_per_row in {1,2,4,8,16,32,64} selects
  * the CSR kernel with that many lanes per row, 0 picks the lane count from the
  * average row length, -1 selects the sliced-ELL kernel (the matrix is
- * converted into a temporary copy first; synchronises s).  Otherwise enqueue
- * only. */
+ * converted into a temporary copy first; synchronises s), -2 the sliced-ELL
+ * kernel reading 16-bit column offsets col - row (EINVAL when an offset lies
+ * outside [-32768, 32767]; synchronises s).  Otherwise enqueue only. */
 int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s);
 
 /* Node hash of the MIS(2) priorities (the random r_i of Algorithm 2 made

@@ -90,10 +90,15 @@ struct Level {
   int nslices = 0;
   int* sl_ptr = nullptr;       // element offset of each slice (nslices + 1)
   int* sl_col = nullptr;
+  // the same columns as 16-bit offsets col - row, when every offset of the
+  // level fits (null otherwise); sl_wide is the device flag the fill raises
+  // when one does not
+  int16_t* sl_dcol = nullptr;
+  int* sl_wide = nullptr;
   double* sl_val = nullptr;
   float* sl_val32 = nullptr;
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
-  // per row, fmt 1 = sliced ELL
+  // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets
   struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; } t64, t32;
   // setup products (absent on the coarsest level)
   uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
@@ -292,7 +297,7 @@ void launch_fill_double(size_t n, double* p, double v, hipStream_t s);
 void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s);
 void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s);
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
-                      int* sl_col, double* sl_val, float* sl_val32, hipStream_t s);
+                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s);
 
 // galerkin.hip: scratch of one Galerkin product (n fine rows, nnz entries,
 // nc coarse rows): lens[n], inv[n], toff[n+1], tkey[nnz], tval[nnz],
@@ -364,8 +369,8 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
                               const int* ci, const double* val, double* inv, float* inv32, Arena& tmp, int* err,
                               hipStream_t s);
 void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off);
-void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y);
-void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y);
+void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, bool offsets16);
+void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y, bool offsets16);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
               int lpr, hipStream_t s);
 int pick_lanes_per_row(int n, int nnz);

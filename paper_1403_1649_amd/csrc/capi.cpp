@@ -312,17 +312,17 @@ int32_t amg_export_level(const amg_hierarchy* H, int32_t k, int32_t* row_ptr, in
 
 int32_t amg_spmv(const amg_csr* A, const double* x, double* y, int32_t lanes_per_row, hipStream_t s) {
   if (!csr_args_ok(A) || !x || !y) return fail(AMG_EINVAL, "amg_spmv: bad argument");
-  if (lanes_per_row == -1) {
+  if (lanes_per_row == -1 || lanes_per_row == -2) {
     return guarded("amg_spmv", [&] {
       amg::Hierarchy h;
       h.stream = s;
       amg::init_control(h);
       amg::init_scan(h.scan, h.arena, A->n, s);
-      amg::spmv_sell_f64(h, *A, x, y);
+      amg::spmv_sell_f64(h, *A, x, y, lanes_per_row == -2);
     });
   }
   if (lanes_per_row < 0 || lanes_per_row > 64 || (lanes_per_row & (lanes_per_row - 1)))
-    return fail(AMG_EINVAL, "amg_spmv: lanes_per_row must be -1, 0 or a power of two <= 64");
+    return fail(AMG_EINVAL, "amg_spmv: lanes_per_row must be -2, -1, 0 or a power of two <= 64");
   return guarded("amg_spmv", [&] {
     amg::spmv_f64(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, x, y, lanes_per_row, s);
     AMG_HIP(hipGetLastError());

@@ -256,23 +256,38 @@ void sell_begin(Hierarchy& h, Arena& tmp, Level& lv, Sync& sy, int slot) {
   scan_to_ptr(widths, lv.sl_ptr, nsl, h.scan, h.stream);
   sy.fetch(lv.sl_ptr + nsl, slot);
 }
-void sell_finish(Hierarchy& h, Level& lv, size_t total) {
+// Second half; the 16-bit offsets stay usable only if the flag read back in
+// pinned slot `slot` at the next wait of `sy` is clear (sell_take_wide).
+void sell_finish(Hierarchy& h, Level& lv, size_t total, Sync& sy, int slot) {
   lv.sl_col = h.arena.alloc_n<int>(total);
+  lv.sl_dcol = h.arena.alloc_n<int16_t>(total);
+  lv.sl_wide = h.arena.alloc_n<int>(1);
   lv.sl_val = h.arena.alloc_n<double>(total);
   if (h.mixed()) lv.sl_val32 = h.arena.alloc_n<float>(total);
-  launch_sell_fill(lv.n, lv.nslices, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_val, lv.sl_val32,
-                   h.stream);
+  launch_fill_int(1, lv.sl_wide, 0, h.stream);
+  launch_sell_fill(lv.n, lv.nslices, lv.rp, lv.ci, lv.val, lv.sl_ptr, lv.sl_col, lv.sl_dcol, lv.sl_wide, lv.sl_val,
+                   lv.sl_val32, h.stream);
+  sy.fetch(lv.sl_wide, slot);
 }
-void build_sell(Hierarchy& h, Arena& tmp, Level& lv) {
+void sell_take_wide(Level& lv, Sync& sy, int slot) {
+  if (sy.hp()[slot]) lv.sl_dcol = nullptr;
+}
+void build_sell(Hierarchy& h, Arena& tmp, Level& lv, bool offsets16 = false) {
   Sync sy{h};
   sell_begin(h, tmp, lv, sy, 0);
   sy.wait_and_check();
-  sell_finish(h, lv, (size_t)sy.hp()[0]);
+  sell_finish(h, lv, (size_t)sy.hp()[0], sy, 0);
+  if (!offsets16) {   // not checked, so not used
+    lv.sl_dcol = nullptr;
+    return;
+  }
+  sy.wait_and_check();
+  sell_take_wide(lv, sy, 0);
 }
 
 }  // namespace
 
-void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y) {
+void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y, bool offsets16) {
   Arena tmp;
   struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{h.stream};
   Level lv;
@@ -281,8 +296,9 @@ void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y) {
   lv.rp = const_cast<int*>(A.row_ptr);
   lv.ci = const_cast<int*>(A.col_idx);
   lv.val = const_cast<double*>(A.val);
-  build_sell(h, tmp, lv);
-  spmv_sell_level(h, lv, x, y);
+  build_sell(h, tmp, lv, offsets16);
+  if (offsets16 && !lv.sl_dcol) throw Error(AMG_EINVAL, "a column offset col - row does not fit in 16 bits");
+  spmv_sell_level(h, lv, x, y, offsets16);
   Sync sy{h};
   sy.wait_and_check();
 }
@@ -506,7 +522,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       if (nnzg < 0) {   // the level's first read-back also brings the sizes of G and of the sliced ELL
         take_arnoldi();
         nnzg = sy.hp()[3];
-        sell_finish(h, lv, (size_t)sy.hp()[2]);
+        sell_finish(h, lv, (size_t)sy.hp()[2], sy, 4);
       }
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
@@ -523,6 +539,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     scan_to_ptr(flags, root_id, n, h.scan, s);
     sy.fetch(root_id + n, 0);
     sy.wait_and_check();
+    if (lv.sl_wide) sell_take_wide(lv, sy, 4);   // fetched with the first MIS(2) count or here
     const int nc = sy.hp()[0];
     if (nc <= 0 || nc > 0.9 * n) {
       lv.strong = nullptr;   // stalled: this level is the coarsest

@@ -123,9 +123,12 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
 // column-major, element (row s*64 + l, k) at sl_ptr[s] + 64 k + l, padded
 // with zero values that point at the row itself.  One thread per row, so
 // every value and column load of a wave is one contiguous 512 / 256 bytes.
-template <typename T, class Op>
+// D16: the columns come as 16-bit offsets col - row (128 bytes per wave and
+// entry instead of 256), for levels whose couplings all lie within 32767
+// rows, as on the lexicographically ordered grids.
+template <typename T, class Op, bool D16>
 __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* __restrict__ sl_ptr,
-                                                 const int* __restrict__ sl_col, const T* __restrict__ sl_val,
+                                                 const void* __restrict__ sl_cols, const T* __restrict__ sl_val,
                                                  Op op, RedCtx rc) {
   if (!op.active()) {
     if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
@@ -148,7 +151,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
     const int base = sl_ptr[sl];
     const int w = (sl_ptr[sl + 1] - base) / kWave;
     T sum = T(0);
-    const int* cp = sl_col + base + lane;
+    const int* cp = static_cast<const int*>(sl_cols) + base + lane;
+    const int16_t* dp = static_cast<const int16_t*>(sl_cols) + base + lane;
     const T* vp = sl_val + base + lane;
     // chunks of 8 entries: all column and value loads of a chunk, then all
     // gathers, then the FMAs in entry order, so a chunk costs one round trip
@@ -158,7 +162,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const bool in = k0 + q < w;
-        c[q] = in ? cp[(k0 + q) * kWave] : 0;
+        if constexpr (D16) c[q] = in ? row + (int)dp[(k0 + q) * kWave] : 0;
+        else c[q] = in ? cp[(k0 + q) * kWave] : 0;
         v[q] = in ? vp[(k0 + q) * kWave] : T(0);
       }
       T xv[8];
@@ -228,16 +233,18 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
     if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
 }
 
+// sl_dcol non-null: the kernel reads the 16-bit column offsets instead of sl_col.
 template <typename T, class Op>
 void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const T* sl_val, const Op& op,
-                 RedCtx rc, hipStream_t s) {
+                 RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr) {
   long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > 8) g &= ~7L;
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
-  k_sell<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op,
-                                          RedCtx{rc.part, tail ? rc.ticket : nullptr});
+  const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
+  if (sl_dcol) k_sell<T, Op, true><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_dcol, sl_val, op, r2);
+  else k_sell<T, Op, false><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, r2);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, (int)g);
 }

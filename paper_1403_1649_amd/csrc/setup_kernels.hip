@@ -502,10 +502,13 @@ __global__ void k_sell_widths(int n, const int* __restrict__ rp, int* __restrict
 
 // Fill the slices: entry k of row s*64+l at sl_ptr[s] + 64 k + l; padding
 // (short rows and the rows past n in the last slice) has value 0 and a valid
-// column (the row itself, or 0).
+// column (the row itself, or n - 1 past the end).  sl_dcol holds col - row
+// in 16 bits; an offset that does not fit raises *wide (the 16-bit copy is
+// then unusable).
 __global__ void k_sell_fill(int n, int nslices, const int* __restrict__ rp, const int* __restrict__ ci,
                             const double* __restrict__ val, const int* __restrict__ sl_ptr,
-                            int* __restrict__ sl_col, double* __restrict__ sl_val, float* __restrict__ sl_val32) {
+                            int* __restrict__ sl_col, int16_t* __restrict__ sl_dcol, int* __restrict__ wide,
+                            double* __restrict__ sl_val, float* __restrict__ sl_val32) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   const int sl = row / kWave, l = row & (kWave - 1);
   if (sl >= nslices) return;
@@ -513,15 +516,20 @@ __global__ void k_sell_fill(int n, int nslices, const int* __restrict__ rp, cons
   const int w = (sl_ptr[sl + 1] - base) / kWave;
   const int s0 = row < n ? rp[row] : 0;
   const int len = row < n ? rp[row + 1] - s0 : 0;
+  bool fits = true;
   for (int k = 0; k < w; ++k) {
     const int idx = base + k * kWave + l;
-    int c = row < n ? row : 0;
+    int c = row < n ? row : n - 1;
     double v = 0.0;
     if (k < len) { c = ci[s0 + k]; v = val[s0 + k]; }
     sl_col[idx] = c;
+    const int d = c - row;
+    fits = fits && d >= -32768 && d <= 32767;
+    sl_dcol[idx] = (int16_t)d;
     sl_val[idx] = v;
     if (sl_val32) sl_val32[idx] = (float)v;
   }
+  if (!fits) atomicOr(wide, 1);
 }
 
 __global__ void k_gather_double(int m, const int* __restrict__ idx, const double* __restrict__ src,
@@ -684,9 +692,9 @@ void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s) {
   k_sell_widths<<<(nsl * kWave + kT - 1) / kT, kT, 0, s>>>(n, rp, widths);
 }
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
-                      int* sl_col, double* sl_val, float* sl_val32, hipStream_t s) {
-  k_sell_fill<<<(nslices * kWave + kT - 1) / kT, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, sl_col, sl_val,
-                                                             sl_val32);
+                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s) {
+  k_sell_fill<<<(nslices * kWave + kT - 1) / kT, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, sl_col, sl_dcol,
+                                                             wide, sl_val, sl_val32);
 }
 void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s) {
   if (m > 0) k_gather_double<<<grid_for(m), kT, 0, s>>>(m, idx, src, dst);

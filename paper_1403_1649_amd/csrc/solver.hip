@@ -625,7 +625,9 @@ template <> const float* sell_vals<float>(const Level& l) { return l.sl_val32; }
 template <typename T, class Op>
 void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
   const Level::Tune& t = tune_of<T>(lv);
-  if (t.fmt == 1 && lv.sl_ptr) launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s);
+  if (t.fmt >= 1 && lv.sl_ptr)
+    launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s,
+                   t.fmt == 2 ? lv.sl_dcol : nullptr);
   else launch_rows<T>(lv.n, t.lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s);
 }
 
@@ -1195,8 +1197,9 @@ struct OpFillT {
   __device__ void finalize(const double*) const {}
 };
 
-// Time y = A x for CSR with 2..32 lanes per row and for sliced ELL; keep the
-// fastest.  Results are cached per (n, nnz, value size) for the process and,
+// Time y = A x for CSR with 2..32 lanes per row and for sliced ELL with 32-
+// and 16-bit columns; keep the fastest (AMG_TUNE_FORCE = csr, sell or sell16
+// pins the format where the level has it, for tests).  Results are cached per (n, nnz, value size) for the process and,
 // when AMG_TUNE_CACHE names a file, across processes (one JSON object per line).
 template <typename T>
 Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
@@ -1211,7 +1214,8 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     return t;
   }
   TuneKey key{lv.n, lv.nnz, (int)sizeof(T)};
-  {
+  const char* force = std::getenv("AMG_TUNE_FORCE");
+  if (!force) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto& c = tune_cache();
     auto it = c.find(key);
@@ -1248,6 +1252,19 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   if (lv.sl_ptr && sell_vals<T>(lv)) {
     const float us = time_it([&] { launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s); });
     if (us < best.us) { best.us = us; best.fmt = 1; best.lpr = lv.lpr; }
+    if (lv.sl_dcol) {
+      const float u16 = time_it([&] {
+        launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, lv.sl_dcol);
+      });
+      if (u16 < best.us) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; }
+    }
+  }
+  if (force) {
+    const std::string w(force);
+    if (w == "csr") best.fmt = 0;
+    else if (w == "sell" && lv.sl_ptr) best.fmt = 1;
+    else if (w == "sell16" && lv.sl_dcol) best.fmt = 2;
+    return best;   // not cached
   }
   std::lock_guard<std::mutex> g(g_tune_mu);
   tune_cache()[key] = best;
@@ -1342,7 +1359,7 @@ void arnoldi_enqueue(Hierarchy& h, const Level& lv, int m, uint32_t stream, doub
     const double* qj = Q + (size_t)j * n;
     const OpArnSpmv op{qj, Q, lv.diag, w, sc, j};
     if (lv.nslices > 0 && lv.nnz <= 12L * n)   // short, even rows: sliced ELL
-      launch_sell<double>(n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, op, rc, s);
+      launch_sell<double>(n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, op, rc, s, lv.sl_dcol);
     else
       launch_rows<double>(n, lv.lpr, lv.rp, lv.ci, lv.val, op, rc, s);
     for (int i = 0; i <= j; ++i) {
@@ -1367,9 +1384,9 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 
 int pick_lanes_per_row(int n, int nnz) { return pick_lpr(n, nnz); }
 
-void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y) {
+void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, bool offsets16) {
   launch_sell<double>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, OpSpmv<double>{Act{nullptr}, x, y},
-                      red(h), h.stream);
+                      red(h), h.stream, offsets16 ? lv.sl_dcol : nullptr);
 }
 
 // y = A x for a caller's matrix (float64)

@@ -286,15 +286,64 @@ def test_probe_timing_samples_in_solve(probe):
     assert rel <= 1e-8 and n >= 1 and 0.0 < ms < 50.0
 
 
+@pytest.mark.parametrize("lanes", [-1, -2])
 @pytest.mark.parametrize("make", [lambda: P.poisson2d(37, 53), lambda: P.hetero3d(17, seed=2)])
-def test_sell_spmv_ragged_rows(make):
-    """Sliced ELL on ragged inputs: n not a multiple of 64, short boundary rows."""
+def test_sell_spmv_ragged_rows(make, lanes):
+    """Sliced ELL (32-bit columns, or 16-bit offsets col - row) on ragged
+    inputs: n not a multiple of 64, short boundary rows."""
     A = make()
     rp, ci, v = to_dev(A)
     x = P.exact_solution(A.n, 5)
-    y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=-1).cpu().numpy()
+    y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=lanes).cpu().numpy()
     S = A.to_scipy()
     assert np.all(np.abs(y - S @ x) <= 1e-15 * 8 * (abs(S) @ np.abs(x)) + 1e-300)
+
+
+def test_sell16_offsets_at_the_limits():
+    """Couplings at offsets +-32767 fit the 16-bit columns, +-32768 (one
+    past on the positive side) do not: the 16-bit form is refused, the 32-bit
+    sliced ELL still serves."""
+    import scipy.sparse as sp
+    n = 40000
+    for far, ok in ((32767, True), (32768, False)):
+        S = sp.diags([-np.ones(n - 1), 4.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="lil")
+        for i in (0, 5, n - far - 1):
+            S[i, i + far] = -0.25
+            S[i + far, i] = -0.25
+        S = S.tocsr()
+        S.sort_indices()
+        A = P.CSR(S.indptr, S.indices, S.data)
+        rp, ci, v = to_dev(A)
+        x = P.exact_solution(n, 3)
+        ref = S @ x
+        y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=-1).cpu().numpy()
+        assert np.all(np.abs(y - ref) <= 1e-15 * 8 * (abs(S) @ np.abs(x)))
+        if ok:
+            y = amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=-2).cpu().numpy()
+            assert np.all(np.abs(y - ref) <= 1e-15 * 8 * (abs(S) @ np.abs(x)))
+        else:
+            with pytest.raises(amg.AmgError) as e:
+                amg.spmv(rp, ci, v, dev_vec(x), lanes_per_row=-2)
+            assert e.value.code == 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_forced_formats_agree_on_a_tuned_level(precision, monkeypatch):
+    """Above 65,536 rows the level kernels are chosen by timing; pin each
+    format in turn (CSR, sliced ELL, sliced ELL with 16-bit offsets) and
+    check the solves against the oracle's iteration count and each other."""
+    A = P.poisson3d(42)   # 74,088 rows: level 0 is tuned
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    ref = O.solve(O.setup(A.row_ptr, A.col, A.val, _oracle_opts(3)), b, 1e-8)
+    xs = []
+    for fmt in ("csr", "sell", "sell16"):
+        monkeypatch.setenv("AMG_TUNE_FORCE", fmt)
+        h, _ = _setup(A, 3, precision=precision)
+        x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+        assert rel <= 1e-8 and abs(it - ref.iters) <= 1
+        xs.append(x.cpu().numpy())
+    for x in xs[1:]:
+        assert np.linalg.norm(x - xs[0]) / np.linalg.norm(xs[0]) < 1e-7
 
 
 def test_tuned_and_untuned_kernels_agree():
