@@ -43,6 +43,12 @@ def presmooth_bytes(n, nnz, val_bytes=8):
     return (val_bytes + 4) * nnz + 4 * (n + 1) + 4 * val_bytes * n
 
 
+def presmooth_bytes_offsets16(n, nnz, val_bytes=8):
+    """The same kernel's compulsory traffic in the sliced ELL with 16-bit
+    column offsets: values + offsets + slice pointers + b, w read, x, r written."""
+    return (val_bytes + 2) * nnz + 4 * ((n + 63) // 64 + 1) + 4 * val_bytes * n
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "l0_presmooth_c2_traffic.md")
 KERNEL_SOURCES = ["solver.hip", "kernels_common.hpp", "device_utils.hpp", "amg_internal.hpp"]
 
@@ -75,7 +81,9 @@ def measured_traffic(workload: str):
 
 
 def kernel_name(fmt: int, lpr: int, op: str) -> str:
-    return f"k_sell<double,{op}>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"
+    if fmt == 2:
+        return f"k_sell<double,{op},true> (sliced ELL, 16-bit column offsets)"
+    return f"k_sell<double,{op},false>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"
 
 
 def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
@@ -389,6 +397,10 @@ def main():
                                       + " (level-0 pre-smoothing + residual, inside the solve)",
                             "bytes_per_launch": pbytes, "avg_us": round(probe_ms * 1e3, 2),
                             "samples": probe_n}
+        if probe_fmt and probe_fmt[0] == 2:
+            fb = presmooth_bytes_offsets16(A.n, A.nnz)
+            line["roofline"]["format_bytes_per_launch"] = fb
+            line["roofline"]["format_gb_s"] = round(fb / (probe_ms * 1e-3) / 1e9, 1)
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline (single thread)")
         line["cpu_baseline"] = cpu_baseline(A, dim, b)
