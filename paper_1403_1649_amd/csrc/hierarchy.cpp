@@ -563,10 +563,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     lv.nr = n;
     lv.rval = h.arena.alloc_n<double>(n);
     launch_gather_double(n, lv.agg_rows, lv.pval, lv.rval, s);
-    // half the lanes of a row kernel of that average length (about 1.4 members
-    // per lane): twice the coarse rows per block pass; C2 solve 9.54 -> 9.28 ms
-    // (a quarter: 9.51 ms)
-    lv.rlpr = std::max(2, pick_lanes_per_row(nc, n) / 2);
+    lv.rlpr = pick_lanes_per_row(nc, n);
 
     // Galerkin product (Section 3.1)
     galerkin_product(h, tmp, h.arena, lv, nc, lv.agg, lv.pval, lv.agg_ptr, lv.agg_rows, &lc.rp, &lc.ci,
