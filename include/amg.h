@@ -171,10 +171,19 @@ int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off
 /* SpMV format the autotuner chose for level k in the given arithmetic
  * (amg_precision: FP64 for the float64 kernels, MIXED for the float32 cycle):
  * format (host) 0 = CSR with *lanes_per_row lanes per row, 1 = sliced ELL
- * with 64-row slices; us (host, may be NULL) = its timed duration (0 if the
- * level was not timed).  EINVAL if k is not a level that runs a cycle. */
+ * with 64-row slices, 2 = sliced ELL with 16-bit column offsets col - row;
+ * us (host, may be NULL) = its timed duration (0 if the level was not timed).
+ * EINVAL if k is not a level that runs a cycle. */
 int32_t amg_level_format(const amg_hierarchy* h, int32_t k, int32_t precision, int32_t* format,
                          int32_t* lanes_per_row, float* us);
+
+/* y = A_k x on level k of a hierarchy, float64, with the kernel the
+ * autotuner chose for that level in FP64 (amg_level_format; CSR on levels it
+ * did not time): the sparse mat-vec of Section 3 as the solve runs it.
+ * x[n_k] and y[n_k] are device vectors owned by the caller (n_k from
+ * amg_level_info; not checked).  Enqueue only, on s.  EINVAL for a NULL
+ * hierarchy or vector or a level outside [0, amg_num_levels). */
+int32_t amg_level_spmv(const amg_hierarchy* h, int32_t k, const double* x, double* y, hipStream_t s);
 
 /* Per-system outer iterations and true relative residuals of the last
  * amg_solve on a batched hierarchy.  iters: (host) int32[nsys] or NULL;

@@ -21,7 +21,7 @@ EXPORTED = [
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
-    "amg_batch_level", "amg_level_format",
+    "amg_batch_level", "amg_level_format", "amg_level_spmv",
 ]
 
 
@@ -86,6 +86,8 @@ def lib():
     L.amg_export_level.restype = i32
     L.amg_spmv.argtypes = [P(AmgCsrC), vp, vp, i32, vp]
     L.amg_spmv.restype = i32
+    L.amg_level_spmv.argtypes = [vp, i32, vp, vp, vp]
+    L.amg_level_spmv.restype = i32
     L.amg_node_hash.argtypes = [i32, u32, vp, vp]
     L.amg_node_hash.restype = i32
     L.amg_galerkin.argtypes = [P(AmgCsrC), vp, vp, i32, P(i32), vp, vp, vp, i32, vp]
@@ -263,10 +265,21 @@ class Hierarchy:
 
     def level_format(self, k: int, precision: str = "fp64"):
         """(format, lanes_per_row, timed us) the autotuner chose for level k;
-        format 0 = CSR, 1 = sliced ELL."""
+        format 0 = CSR, 1 = sliced ELL, 2 = sliced ELL with 16-bit column offsets."""
         f, l, us = C.c_int32(), C.c_int32(), C.c_float()
         _check(lib().amg_level_format(self._h, int(k), _PREC[precision], C.byref(f), C.byref(l), C.byref(us)))
         return f.value, l.value, us.value
+
+    def level_spmv(self, k: int, x, y=None):
+        """y = A_k x with level k's tuned FP64 kernel (amg_level_spmv)."""
+        import torch
+        n = self.level_info(k)["n"]
+        if x.numel() != n or x.dtype != torch.float64 or not x.is_cuda:
+            raise ValueError(f"level_spmv: x must be a float64 device vector of {n} entries")
+        if y is None:
+            y = torch.empty(n, dtype=torch.float64, device=x.device)
+        _check(lib().amg_level_spmv(self._h, int(k), _ptr(x), _ptr(y), _stream()))
+        return y
 
     def batch_results(self):
         """Per-system (iters[], relres[]) of the last solve of a batched hierarchy."""

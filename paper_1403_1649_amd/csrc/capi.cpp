@@ -190,6 +190,14 @@ int32_t amg_level_format(const amg_hierarchy* H, int32_t k, int32_t precision, i
   return AMG_OK;
 }
 
+int32_t amg_level_spmv(const amg_hierarchy* H, int32_t k, const double* x, double* y, hipStream_t s) {
+  if (!H || k < 0 || k >= (int32_t)H->h.levels.size() || !x || !y) return fail(AMG_EINVAL, "amg_level_spmv: bad argument");
+  return guarded("amg_level_spmv", [&] {
+    amg::level_spmv(H->h, k, x, y, s);
+    AMG_HIP(hipGetLastError());
+  });
+}
+
 int32_t amg_batch_results(const amg_hierarchy* H, int32_t* iters, double* relres) {
   if (!H || H->h.nsys == 0) return fail(AMG_EINVAL, "amg_batch_results: not a batched hierarchy");
   if (H->h.b_iters.empty()) return fail(AMG_EINVAL, "amg_batch_results: no solve yet");

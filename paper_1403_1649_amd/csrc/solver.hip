@@ -1390,6 +1390,11 @@ void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, 
                       red(h), h.stream, offsets16 ? lv.sl_dcol : nullptr);
 }
 
+// y = A_k x with level k's tuned FP64 kernel
+void level_spmv(const Hierarchy& h, int k, const double* x, double* y, hipStream_t s) {
+  launch_level<double>(h.levels[k], OpSpmv<double>{Act{nullptr}, x, y}, RedCtx{nullptr, nullptr}, s);
+}
+
 // y = A x for a caller's matrix (float64)
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
               int lpr, hipStream_t s) {

@@ -59,6 +59,14 @@ def test_c2_level0_products_entrywise(c2, lanes):
     assert np.all(np.abs(y - S @ x) <= bound)
 
 
+def test_c2_tuned_level0_product_entrywise(c2):
+    A, _, _, h = c2
+    x = P.exact_solution(A.n, 9)
+    y = h.level_spmv(0, dev_vec(x)).cpu().numpy()
+    S = A.to_scipy()
+    assert np.all(np.abs(y - S @ x) <= 1e-15 * 8 * (abs(S) @ np.abs(x)))
+
+
 def test_c2_solve_matches_oracle(c2):
     A, dim, _, h = c2
     b = P.rhs(A, P.exact_solution(A.n, 1))

@@ -299,6 +299,23 @@ def test_sell_spmv_ragged_rows(make, lanes):
     assert np.all(np.abs(y - S @ x) <= 1e-15 * 8 * (abs(S) @ np.abs(x)) + 1e-300)
 
 
+@pytest.mark.parametrize("make", [lambda: P.hetero3d(30, seed=8), lambda: P.poisson3d(42)])
+def test_level_spmv_every_level(make):
+    """amg_level_spmv on every level (fixed lanes on small levels, the tuned
+    format on the 74,088-row level 0) against the exported A_k."""
+    import scipy.sparse as sp
+    A = make()
+    h, _ = _setup(A, 3)
+    for k in range(h.num_levels()):
+        ex = h.export_level(k, what=("A",))
+        S = sp.csr_matrix((ex["val"], ex["col"], ex["row_ptr"]), shape=(ex["n"], ex["n"]))
+        x = P.exact_solution(ex["n"], 11 + k)
+        y = h.level_spmv(k, dev_vec(x)).cpu().numpy()
+        assert np.all(np.abs(y - S @ x) <= 1e-15 * 8 * (abs(S) @ np.abs(x)) + 1e-300), f"level {k}"
+    with pytest.raises(amg.AmgError):
+        h.level_spmv(h.num_levels(), dev_vec(np.zeros(1)))
+
+
 def test_sell16_offsets_at_the_limits():
     """Couplings at offsets +-32767 fit the 16-bit columns, +-32768 (one
     past on the positive side) do not: the 16-bit form is refused, the 32-bit
