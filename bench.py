@@ -283,7 +283,7 @@ def main():
         print(kernel_sources_sha256())
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no "
               "multi-GPU path", file=sys.stderr)
         return 2
 

@@ -42,7 +42,7 @@ typedef enum {
   AMG_EBREAKDOWN = 5,   /* Krylov breakdown (p^T A p <= 0) or a non-positive spectral estimate */
   AMG_ECOARSEN = 6,     /* coarsening stalled above the dense-solve limit, or an unsupported aggregate */
   AMG_ENANINF = 7,      /* non-finite value in the matrix, the right-hand side or the iteration */
-  AMG_EUNSUPPORTED = 8  /* option combination not provided by this build */
+  AMG_EUNSUPPORTED = 8  /* option combination the library does not provide */
 } amg_status;
 
 typedef enum { AMG_KRYLOV_FCG = 0, AMG_KRYLOV_FGMRES = 1 } amg_krylov;
