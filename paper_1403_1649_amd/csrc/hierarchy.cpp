@@ -512,17 +512,22 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     int round = 0;
     int batch = 8;   // rounds between read-backs: a round after the last exits at entry
     int nnzg = -1;
+    bool arn_due = false;   // the previous level's Hessenberg matrix has arrived
     const int glanes = group_lanes(n, (long)nnz - n);
     while (true) {
       for (int b = 0; b < batch; ++b, ++round)
         launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s);
+      if (arn_due) {   // its eigenvalues on the host while the rounds run
+        take_arnoldi();
+        arn_due = false;
+      }
       sy.fetch(h.d_mis + mis_word(round & 1, 0), 0, kMisSlots, mis_word(0, 1));
       sy.fetch(h.d_mis + kMisRoundsWord, 1);
       sy.wait_and_check();
       if (nnzg < 0) {   // the level's first read-back also brings the sizes of G and of the sliced ELL
-        take_arnoldi();
         nnzg = sy.hp()[3];
         sell_finish(h, lv, (size_t)sy.hp()[2], sy, 4);
+        arn_due = true;
       }
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
@@ -538,6 +543,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     launch_root_flags(n, lv.tuple, flags, s);
     scan_to_ptr(flags, root_id, n, h.scan, s);
     sy.fetch(root_id + n, 0);
+    if (arn_due) take_arnoldi();
     sy.wait_and_check();
     if (lv.sl_wide) sell_take_wide(lv, sy, 4);   // fetched with the first MIS(2) count or here
     const int nc = sy.hp()[0];
