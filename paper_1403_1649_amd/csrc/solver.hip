@@ -139,8 +139,8 @@ struct OpResidSmoothDot {
 
 // first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r)
 template <typename T>
-struct OpKDots1 {
-  static constexpr int NV = 2;
+struct OpKDots1 {   // also ||r_c||^2 for the test of the second step
+  static constexpr int NV = 3;
   Act a;
   const T* c;
   const T* rcv;
@@ -155,10 +155,12 @@ struct OpKDots1 {
     const double l = gmres ? (double)ax : (double)c[i];
     acc[0] += l * (double)ax;
     acc[1] += l * (double)rcv[i];
+    acc[2] += (double)rcv[i] * (double)rcv[i];
   }
   __device__ void finalize(const double* s) const {
     K[kKRho1] = s[0];
     K[kKAlpha1] = s[1];
+    K[kKRcRc] = s[2];
   }
 };
 
@@ -731,7 +733,8 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T, true>{A, r, rcv, K}, rc, s);
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T, false>{A, r, rcv, nullptr},
+                   rc, s);
     cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
     launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
