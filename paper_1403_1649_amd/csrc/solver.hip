@@ -387,24 +387,19 @@ struct OpCopy {
   __device__ void finalize(const double*) const {}
 };
 
-// restriction r_c = P^T r by aggregate segments (ascending fine index)
-template <typename T, bool DOT>
-struct OpRestrict {   // rows of R = P^T (aggregates): r_c = R r, with ||r_c||^2
-  static constexpr int NV = DOT ? 1 : 0;
+// restriction r_c = P^T r by aggregate segments (ascending fine index); the
+// K-cycle takes ||r_c||^2 with the first inner step's dots (OpKDots1)
+template <typename T>
+struct OpRestrict {   // rows of R = P^T (aggregates)
+  static constexpr int NV = 0;
   Act a;
   const T* r;
   T* rcv;
-  double* K;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
   __device__ T x(int j) const { return r[j]; }
-  __device__ void row(int I, T s, double* acc) const {
-    rcv[I] = s;
-    if (DOT) acc[0] += (double)s * (double)s;
-  }
-  __device__ void finalize(const double* s) const {
-    if (DOT) K[kKRcRc] = s[0];
-  }
+  __device__ void row(int I, T s, double*) const { rcv[I] = s; }
+  __device__ void finalize(const double*) const {}
 };
 
 // prolongation x += P c
@@ -713,7 +708,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
                 [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
     if (!kcyc)
       launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv),
-                     OpRestrict<T, false>{A, r, rcv, nullptr}, rc, s);
+                     OpRestrict<T>{A, r, rcv}, rc, s);
   }
   if (!kcyc) {
     if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
@@ -733,8 +728,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T, false>{A, r, rcv, nullptr},
-                   rc, s);
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv}, rc, s);
     cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
     launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
     launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
