@@ -278,8 +278,17 @@ constexpr int kMisRoundsWord = 2 * kMisSlots * 32;
 constexpr int kMisWords = kMisRoundsWord + 32;
 // one MIS(2) round (two sweeps; the second counts the blocks that left a node
 // undecided, for the next round's early exit)
+// late-round node list of MIS(2) (setup_kernels.hip): flags fnear[n], their
+// scan pnear[n+1] (pnear[n] = the list's length, read by the sweeps) and the
+// list near[n]
+struct MisLists {
+  int *fnear, *pnear, *near, *count;
+};
+void launch_mis_lists(int n, const int* gptr, const int* gcol, const uint64_t* T, const MisLists& ml,
+                      ScanCtx& sc, hipStream_t s);
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc, int round,
-                      int lanes, hipStream_t s);
+                      int lanes, hipStream_t s,
+                      const MisLists* ml = nullptr);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
 void launch_aggregate(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
                       int* choice, int* agg, int* err, hipStream_t s);

@@ -405,6 +405,10 @@ void init_control(Hierarchy& h) {
 
 // omega_k = jacobi_scale / rho from the Arnoldi Hessenberg H (row stride 8,
 // m columns; wn = ||D^-1 A q_j||), then the weights omega_k / a_ii.
+// Levels above this size sweep node lists after the first MIS(2) read-back
+// (C2 level 0, 16 rounds: after 8 rounds 0.2 % of the nodes are undecided).
+constexpr int kMisListRows = 65536;
+
 static void set_jacobi_weight(Hierarchy& h, Level& lv, int m, const double* Hh, const double* wn) {
   int size = m;
   for (int j = 0; j < m; ++j) {
@@ -514,9 +518,11 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     int nnzg = -1;
     bool arn_due = false;   // the previous level's Hessenberg matrix has arrived
     const int glanes = group_lanes(n, (long)nnz - n);
+    MisLists ml{};
+    bool lists = false;   // late rounds sweep only the nodes that can still change
     while (true) {
       for (int b = 0; b < batch; ++b, ++round)
-        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s);
+        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s, lists ? &ml : nullptr);
       if (arn_due) {   // its eigenvalues on the host while the rounds run
         take_arnoldi();
         arn_due = false;
@@ -532,6 +538,14 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
       batch = 4;
+      if (!lists && n > kMisListRows) {
+        ml.fnear = tmp.alloc_n<int>(n);
+        ml.pnear = tmp.alloc_n<int>((size_t)n + 1);
+        ml.near = tmp.alloc_n<int>(n);
+        ml.count = ml.pnear + n;
+        launch_mis_lists(n, gptr, gcol, lv.tuple, ml, h.scan, s);
+        lists = true;
+      }
     }
     lv.mis_rounds = sy.hp()[1];
     if (debug) std::fprintf(stderr, "amg: level %d n=%d nnz=%d nnz(G)=%d mis_rounds=%d\n", k, n, nnz, nnzg,

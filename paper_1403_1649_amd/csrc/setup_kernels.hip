@@ -204,11 +204,14 @@ constexpr int kMisBlocks = 2048;
 // First max sweep of a round: M1_i = max(T_i, max_{j in N_i} T_j), G lanes per
 // node.  A node whose M1 already holds an MIS tuple keeps it: two MIS(2) nodes
 // never share a closed neighbourhood, so that maximum cannot change again.
+// With a node list (late rounds), the sweep visits list[0 .. *count) instead
+// of 0 .. n.
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol,
                                                     const uint64_t* __restrict__ T,
-                                                    uint64_t* __restrict__ M1, int* mc, int round) {
+                                                    uint64_t* __restrict__ M1, int* mc, int round,
+                                                    const int* __restrict__ list, const int* __restrict__ count) {
   __shared__ int s_flag;
   // the counters of this round's second sweep start from zero (they last held
   // the previous round's counts, read by that round's sweeps only)
@@ -217,11 +220,13 @@ __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict
   if (!mis_pending(mc, round, &s_flag)) return;   // nothing undecided
   constexpr int NPB = 256 / G;                // nodes per block step
   const int lane = threadIdx.x & (G - 1);
-  const int groups = (n + NPB - 1) / NPB;
+  const int m = list ? *count : n;
+  const int groups = (m + NPB - 1) / NPB;
   const int per = (groups + gridDim.x - 1) / gridDim.x;
   const int g0 = xcd_block_index() * per, g1 = min(groups, g0 + per);
   for (int g = g0; g < g1; ++g) {
-    const int i = g * NPB + threadIdx.x / G;
+    const int q = g * NPB + threadIdx.x / G;
+    const int i = q < m ? (list ? list[q] : q) : n;
     uint64_t t = 0;
     bool work = false;
     if (i < n) {
@@ -246,7 +251,8 @@ __global__ void __launch_bounds__(256) k_mis_sweep1(int n, const int* __restrict
 template <int G>
 __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict__ gptr,
                                                     const int* __restrict__ gcol, uint64_t* __restrict__ T,
-                                                    const uint64_t* __restrict__ M1, int* mc, int round) {
+                                                    const uint64_t* __restrict__ M1, int* mc, int round,
+                                                    const int* __restrict__ list, const int* __restrict__ count) {
   __shared__ int s_flag;
   if (!mis_pending(mc, round, &s_flag)) return;
   constexpr int NPB = 256 / G;
@@ -254,12 +260,14 @@ __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict
   if (threadIdx.x == 0) s_any = 0;
   __syncthreads();
   const int lane = threadIdx.x & (G - 1);
-  const int groups = (n + NPB - 1) / NPB;
+  const int m = list ? *count : n;
+  const int groups = (m + NPB - 1) / NPB;
   const int per = (groups + gridDim.x - 1) / gridDim.x;
   const int g0 = xcd_block_index() * per, g1 = min(groups, g0 + per);
   int undecided = 0;
   for (int g = g0; g < g1; ++g) {
-    const int i = g * NPB + threadIdx.x / G;
+    const int q = g * NPB + threadIdx.x / G;
+    const int i = q < m ? (list ? list[q] : q) : n;
     uint64_t own = 0, t = 0;
     if (i < n) {
       own = T[i];
@@ -292,6 +300,22 @@ __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict
                              __HIP_MEMORY_SCOPE_AGENT);
     if (blockIdx.x == 0) __hip_atomic_fetch_add(&mc[kMisRoundsWord], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// Late-round node list: the closed neighbourhoods of the undecided nodes.
+// Only those nodes' first-sweep maxima are still read by an undecided node,
+// and they include every node the second sweep can still change (the sweep
+// skips the decided ones).  The flag array starts zeroed.
+__global__ void k_mis_mark(int n, const int* __restrict__ gptr, const int* __restrict__ gcol,
+                           const uint64_t* __restrict__ T, int* __restrict__ near) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || tstate(T[i]) != 1) return;
+  near[i] = 1;
+  for (int k = gptr[i]; k < gptr[i + 1]; ++k) near[gcol[k]] = 1;   // every writer stores 1
+}
+__global__ void k_compact(int n, const int* __restrict__ flag, const int* __restrict__ pos, int* __restrict__ list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) list[pos[i]] = i;
 }
 
 __global__ void k_root_flags(int n, const uint64_t* __restrict__ T, int* __restrict__ flags) {
@@ -617,24 +641,38 @@ void launch_mis_init(int n, const int* cnt, uint32_t seed, uint64_t* T, uint64_t
 }
 template <int G>
 static void mis_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc, int round,
-                        hipStream_t s) {
+                        const MisLists* ml, hipStream_t s) {
   long g = ((long)n * G + kT - 1) / kT;
   if (g < 1) g = 1;
   if (g > kMisBlocks) g = kMisBlocks;
-  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round);
-  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round);
+  if (ml) {   // the lists hold a few percent of the nodes
+    long gl = g / 8;
+    g = gl < 8 ? 8 : gl;
+  }
+  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round, ml ? ml->near : nullptr,
+                                        ml ? ml->count : nullptr);
+  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round, ml ? ml->near : nullptr,
+                                        ml ? ml->count : nullptr);
 }
 
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc,
-                      int round, int lanes, hipStream_t s) {
+                      int round, int lanes, hipStream_t s, const MisLists* ml) {
   switch (lanes) {
-    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, mc, round, s); break;
-    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, mc, round, s); break;
-    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, mc, round, s); break;
-    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, mc, round, s); break;
-    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, mc, round, s); break;
-    default: mis_round_g<32>(n, gptr, gcol, T, M1, mc, round, s); break;
+    case 1: mis_round_g<1>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
+    case 2: mis_round_g<2>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
+    case 4: mis_round_g<4>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
+    case 8: mis_round_g<8>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
+    case 16: mis_round_g<16>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
+    default: mis_round_g<32>(n, gptr, gcol, T, M1, mc, round, ml, s); break;
   }
+}
+
+void launch_mis_lists(int n, const int* gptr, const int* gcol, const uint64_t* T, const MisLists& ml,
+                      ScanCtx& sc, hipStream_t s) {
+  launch_fill_int((size_t)n, ml.fnear, 0, s);
+  k_mis_mark<<<grid_for(n), kT, 0, s>>>(n, gptr, gcol, T, ml.fnear);
+  scan_to_ptr(ml.fnear, ml.pnear, n, sc, s);
+  k_compact<<<grid_for(n), kT, 0, s>>>(n, ml.fnear, ml.pnear, ml.near);
 }
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s) {
   k_root_flags<<<grid_for(n), kT, 0, s>>>(n, T, flags);
