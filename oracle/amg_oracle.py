@@ -462,77 +462,78 @@ def smooth(lv: Level, b, x):
     return x + lv.wdinv * (b - lv.A @ x)
 
 
-def kcycle_coefficients(c, d, v, w, r, rt, variant: str, rho1=None):
-    """Scalars of the two inner Krylov steps of Algorithm 5.
+def kcycle_coefficients(c, d, v, w, r, rt, variant: str):
+    """Coefficients of the two-step inner Krylov update of Algorithm 5.
 
-    Returns (coef_c, coef_d) with x_{k+1} = coef_c c + coef_d d."""
+    c, d: the two inner-cycle corrections; v = A c, w = A d; r: the coarse
+    right-hand side; rt = r - (alpha1/rho1) v, what the first step leaves.
+    The CG variant pairs each vector with c or d (A-norm error), the GMRES
+    variant with v or w (residual 2-norm).  Returns (coef_c, coef_d) with
+    x = coef_c c + coef_d d.  When the second direction adds nothing
+    (rho2 = beta - gamma^2/rho1 <= 0, a guard the paper leaves open) the first
+    step alone is kept: (alpha1/rho1, 0)."""
     if variant == "cg":
-        rho1 = c @ v if rho1 is None else rho1
-        alpha1 = c @ r
+        rho1, alpha1 = c @ v, c @ r
         gamma, beta, alpha2 = d @ v, d @ w, d @ rt
     else:
-        rho1 = v @ v if rho1 is None else rho1
-        alpha1 = v @ r
+        rho1, alpha1 = v @ v, v @ r
         gamma, beta, alpha2 = w @ v, w @ w, w @ rt
     rho2 = beta - gamma * gamma / rho1
+    if not rho2 > 0.0:
+        return alpha1 / rho1, 0.0
     return alpha1 / rho1 - gamma * alpha2 / (rho1 * rho2), alpha2 / rho2
 
 
 def vcycle(H: Hierarchy, k: int, b):
-    """Algorithm 4 with x_k = 0 on entry."""
+    """Algorithm 4 with x_k = 0 on entry: smoothing around one coarse-grid
+    correction by a recursive cycle (or the exact solve on the coarsest level)."""
     lv = H.levels[k]
-    x = smooth(lv, b, np.zeros_like(b))               # pre-smoothing
-    r = b - lv.A @ x                                   # residual
-    rc = lv.R @ r                                      # restriction
-    if k + 1 == H.L:
-        xc = H.coarse_solve(rc)                        # exact coarse solve
-    else:
-        xc = cycle(H, k + 1, rc)                       # recursion, zero guess
-    x = x + lv.P @ xc                                  # prolongation
-    return smooth(lv, b, x)                            # post-smoothing
-
-
-def kcycle(H: Hierarchy, k: int, b):
-    """Algorithm 5 with x_k = 0 on entry (readings in the module docstring).
-
-    Guards the paper leaves open: rho1 <= 0 (zero correction c) gives a zero
-    coarse correction; rho2 <= 0 keeps the first inner step's result."""
-    lv = H.levels[k]
-    variant = "cg" if H.opts.krylov == "fcg" else "gmres"
-    x = smooth(lv, b, np.zeros_like(b))               # pre-smoothing
-    r = b - lv.A @ x
-    rc = lv.R @ r
+    x = smooth(lv, b, np.zeros_like(b))
+    rc = lv.R @ (b - lv.A @ x)
     if k + 1 == H.L:
         xc = H.coarse_solve(rc)
     else:
-        Ac = H.levels[k + 1].A
-        c = cycle(H, k + 1, rc)                        # first inner Krylov iteration
-        v = Ac @ c
-        if variant == "cg":
-            rho1, alpha1 = c @ v, c @ rc
-        else:
-            rho1, alpha1 = v @ v, v @ rc
-        if not rho1 > 0.0:
-            xc = np.zeros_like(rc)
-        else:
-            rt = rc - (alpha1 / rho1) * v
-            if np.linalg.norm(rt) <= H.opts.kcycle_t * np.linalg.norm(rc):
-                xc = (alpha1 / rho1) * c
-            else:
-                d = cycle(H, k + 1, rt)                # second inner Krylov iteration
-                w = Ac @ d
-                if variant == "cg":
-                    gamma, beta, alpha2 = d @ v, d @ w, d @ rt
-                else:
-                    gamma, beta, alpha2 = w @ v, w @ w, w @ rt
-                rho2 = beta - gamma * gamma / rho1
-                if not rho2 > 0.0:
-                    xc = (alpha1 / rho1) * c
-                else:
-                    xc = (alpha1 / rho1 - gamma * alpha2 / (rho1 * rho2)) * c + (alpha2 / rho2) * d
-    x = x + lv.P @ xc                                  # prolongation
-    r = b - lv.A @ x                                   # new residual
-    return x + lv.wdinv * r                            # post-smoothing
+        xc = cycle(H, k + 1, rc)
+    return smooth(lv, b, x + lv.P @ xc)
+
+
+def kcycle_correction(H: Hierarchy, kc: int, rc):
+    """The coarse-grid correction of Algorithm 5 on level kc for the restricted
+    residual rc: the level's cycle is used as the preconditioner of at most two
+    steps of a Krylov method on A_kc e = rc, started from e = 0.
+
+    One inner cycle c gives the best multiple of c (A-norm error for the CG
+    variant, residual 2-norm for the GMRES variant); if what it leaves,
+    r~ = rc - A_kc (alpha1/rho1) c, is not below t ||rc||, a second inner cycle
+    d on r~ and the best element of span{c, d} (kcycle_coefficients).
+    Returns (e, steps) with steps the number of inner cycles that entered e.
+    Guard the paper leaves open: rho1 <= 0 gives e = 0."""
+    if kc == H.L:
+        return H.coarse_solve(rc), 0
+    cg = H.opts.krylov == "fcg"
+    Ac = H.levels[kc].A
+    c = cycle(H, kc, rc)
+    v = Ac @ c
+    rho1, alpha1 = ((c @ v), (c @ rc)) if cg else ((v @ v), (v @ rc))
+    if not rho1 > 0.0:
+        return np.zeros_like(rc), 0
+    rt = rc - (alpha1 / rho1) * v
+    if np.linalg.norm(rt) <= H.opts.kcycle_t * np.linalg.norm(rc):
+        return (alpha1 / rho1) * c, 1
+    d = cycle(H, kc, rt)
+    coef_c, coef_d = kcycle_coefficients(c, d, v, Ac @ d, rc, rt, "cg" if cg else "gmres")
+    return coef_c * c + coef_d * d, 2
+
+
+def kcycle(H: Hierarchy, k: int, b):
+    """Algorithm 5 with x_k = 0 on entry (readings in the module docstring):
+    the V-cycle's smoothing and transfers around the Krylov-accelerated coarse
+    correction of kcycle_correction."""
+    lv = H.levels[k]
+    x = smooth(lv, b, np.zeros_like(b))
+    rc = lv.R @ (b - lv.A @ x)
+    xc, _ = kcycle_correction(H, k + 1, rc)
+    return smooth(lv, b, x + lv.P @ xc)
 
 
 def cycle(H: Hierarchy, k: int, b):

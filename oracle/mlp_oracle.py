@@ -13,10 +13,10 @@ features of row i on level k (9 values, then rounded to bfloat16):
 MLP 9 -> 32 -> 32 -> 1 with ReLU: bfloat16 weights and inputs (round to
 nearest even), FP32 biases; hidden activations are rounded to bfloat16 before
 the next layer (straight-through in the backward pass).  Each pre-activation
-is accumulated in FP32, bias first, then the products in ascending input
-index (a product of two bfloat16 values is exact in FP32, so each step is one
-FP32 rounding): the bfloat16 rounding of a hidden unit is a quantisation, and
-both sides take it from the same FP32 value.
+is the FP64 sum of the bias and the products of bfloat16-rounded operands
+(every such product is exact); the kernels accumulate in FP32, and the GPU
+tests bound that difference, including the bfloat16 roundings of hidden units
+that it can flip, instead of reproducing the kernel's summation order.
 omega_i = sigmoid(y_i) * 2|a_ii| / (|a_ii| + sum_{j != i} |a_ij|): then
 2 D Omega^-1 - A is strictly diagonally dominant with a positive diagonal, so
 the smoother x += Omega D^-1 (b - A x) converges for SPD A.
@@ -84,36 +84,21 @@ def omega_bound(A: sp.csr_matrix) -> np.ndarray:
     return 2.0 * d / (d + (rowabs - d))
 
 
-def _acc32(bias, X, W):
-    """FP32 accumulation in index order: s = bias, then s += W[:, q] * X[:, q]
-    for q ascending (operands are bfloat16 values, products exact in FP32)."""
-    s = np.broadcast_to(np.asarray(bias, np.float32), (X.shape[0], W.shape[0])).copy()
-    X32, W32 = X.astype(np.float32), W.astype(np.float32)
-    for q in range(X.shape[1]):
-        s = s + X32[:, q:q + 1] * W32[:, q][None, :]
-    return s.astype(np.float64)
-
-
 def forward(w, F, round_bf16=True):
-    """Returns y and the intermediates needed by backward."""
+    """y = W3 h2 + b3, h2 = q(relu(W2 h1 + b2)), h1 = q(relu(W1 q(x) + b1)) with
+    q = bfloat16 rounding (identity when round_bf16 is False) and the weights
+    W1, W2, W3 rounded the same way; sums in FP64.  Returns y and the
+    intermediates needed by backward."""
     p = unpack(w)
-    if round_bf16:
-        X = bf16(F)
-        W1, W2, W3 = bf16(p["W1"]), bf16(p["W2"]), bf16(p["W3"])
-        z1 = _acc32(p["b1"], X, W1)
-        h1 = bf16(np.maximum(z1, 0.0))
-        z2 = _acc32(p["b2"], h1, W2)
-        h2 = bf16(np.maximum(z2, 0.0))
-        y = _acc32(p["b3"], h2, W3[None, :])[:, 0]
-    else:
-        X = np.asarray(F, np.float64)
-        W1, W2, W3 = p["W1"], p["W2"], p["W3"]
-        z1 = X @ W1.T + p["b1"]
-        h1 = np.maximum(z1, 0.0)
-        z2 = h1 @ W2.T + p["b2"]
-        h2 = np.maximum(z2, 0.0)
-        y = h2 @ W3 + p["b3"][0]
-    return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2, W2=W2, W3=W3)
+    r = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    X = r(F)
+    W1, W2, W3 = r(p["W1"]), r(p["W2"]), r(p["W3"])
+    z1 = X @ W1.T + p["b1"]
+    h1 = r(np.maximum(z1, 0.0))
+    z2 = h1 @ W2.T + p["b2"]
+    h2 = r(np.maximum(z2, 0.0))
+    y = h2 @ W3 + p["b3"][0]
+    return y, dict(X=X, z1=z1, h1=h1, z2=z2, h2=h2, W1=W1, W2=W2, W3=W3)
 
 
 def omega(w, A, F, round_bf16=True):
@@ -132,13 +117,10 @@ def projected_errors(A: sp.csr_matrix, agg, pval, nc: int, nsamples: int, seed: 
     return E
 
 
-def loss_and_grad(w, A: sp.csr_matrix, F, E, round_bf16=True):
-    """Smoothing loss and its gradient with respect to the 1409 weights."""
-    y, c = forward(w, F, round_bf16)
+def loss_omega(A: sp.csr_matrix, E, om):
+    """Smoothing loss as a function of the per-row weights omega and its
+    derivative dL/domega_i (W = diag(omega_i / a_ii))."""
     a = A.diagonal()
-    beta = omega_bound(A)
-    sig = 1.0 / (1.0 + np.exp(-y))
-    om = sig * beta
     AE = A @ E
     ee = np.einsum("is,is->s", E, AE)
     E2 = E - (om / a)[:, None] * AE
@@ -147,8 +129,17 @@ def loss_and_grad(w, A: sp.csr_matrix, F, E, round_bf16=True):
     S = E.shape[1]
     loss = float(np.mean(num / ee))
     domega = (-2.0 / S) * np.sum(AE2 * AE / ee[None, :], axis=1) / a
+    return loss, domega
+
+
+def loss_and_grad(w, A: sp.csr_matrix, F, E, round_bf16=True):
+    """Smoothing loss and its gradient with respect to the 1409 weights
+    (chain rule through omega_i = sigmoid(y_i) beta_i and the network)."""
+    y, c = forward(w, F, round_bf16)
+    beta = omega_bound(A)
+    sig = 1.0 / (1.0 + np.exp(-y))
+    loss, domega = loss_omega(A, E, sig * beta)
     dy = domega * beta * sig * (1.0 - sig)
-    p = unpack(w)
     g = {}
     g["W3"] = c["h2"].T @ dy
     g["b3"] = np.array([dy.sum()])
@@ -160,7 +151,6 @@ def loss_and_grad(w, A: sp.csr_matrix, F, E, round_bf16=True):
     dz1 = dh1 * (c["z1"] > 0)
     g["W1"] = dz1.T @ c["X"]
     g["b1"] = dz1.sum(axis=0)
-    del p
     return loss, pack(g)
 
 

@@ -1,6 +1,7 @@
 """CPU pins of the learned-weight oracle: finite differences for the gradient,
 the convergence bound, the bfloat16 rounding, and the feature definition."""
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from oracle import amg_oracle as O
@@ -74,20 +75,81 @@ def test_gradient_matches_central_differences():
     assert 0.0 < loss < 1.0
 
 
-def test_fp32_accumulation_of_the_forward_pass():
-    """The pre-activations accumulate in FP32 (bias first, ascending index):
-    exact when every partial sum is representable, otherwise within one FP32
-    rounding per step of the FP64 sum."""
-    rng = np.random.default_rng(5)
-    # small integers: products and partial sums exact in FP32 and FP64 alike
-    X = rng.integers(-8, 9, size=(50, M.N_IN)).astype(np.float64)
-    W = rng.integers(-8, 9, size=(M.N_H, M.N_IN)).astype(np.float64)
-    b = rng.integers(-8, 9, size=M.N_H).astype(np.float64)
-    assert np.array_equal(M._acc32(b, X, W), X @ W.T + b)
-    # general bfloat16 operands: bounded by the FP32 rounding of each step
-    X = M.bf16(rng.standard_normal((200, M.N_IN)))
-    W = M.bf16(rng.standard_normal((M.N_H, M.N_IN)))
-    b = rng.standard_normal(M.N_H).astype(np.float32).astype(np.float64)
-    got, want = M._acc32(b, X, W), X @ W.T + b
-    bound = (M.N_IN + 1) * 2.0 ** -24 * (np.abs(X) @ np.abs(W).T + np.abs(b))
-    assert np.all(np.abs(got - want) <= bound)
+def test_forward_hand_network():
+    """A network small enough to evaluate by hand: only hidden unit 0 of each
+    layer is wired, all values exact in bfloat16.
+    x = (1, 2, 0, ..., 0): z1_0 = 0.5*1 + 0.25*2 + 1 = 2, h1_0 = 2;
+    z1_1 = -3 (bias only) -> h1_1 = 0; z2_0 = 1.5*2 - 1 = 2, h2_0 = 2;
+    y = 0.75*2 + 0.5 = 2."""
+    d = {k: np.zeros(s) for k, s in M.SIZES}
+    d["W1"][0, 0], d["W1"][0, 1], d["b1"][0], d["b1"][1] = 0.5, 0.25, 1.0, -3.0
+    d["W2"][0, 0], d["W2"][0, 1], d["b2"][0] = 1.5, 7.0, -1.0
+    d["W3"][0], d["b3"][0] = 0.75, 0.5
+    F = np.zeros((2, M.N_IN))
+    F[0, :2] = (1.0, 2.0)
+    F[1, :2] = (-8.0, 0.0)   # z1_0 = -3 -> every hidden unit off: y = b3
+    y, c = M.forward(M.pack(d), F)
+    assert np.array_equal(y, [2.0, 0.5])
+    assert c["h1"][0, 0] == 2.0 and c["h1"][0, 1] == 0.0 and c["h2"][0, 0] == 2.0
+
+
+def test_forward_rounds_hidden_units_to_bfloat16():
+    """1 + 2^-8 is a tie between 1 and 1 + 2^-7 (even mantissa wins): a hidden
+    unit with that pre-activation enters the next layer as exactly 1."""
+    d = {k: np.zeros(s) for k, s in M.SIZES}
+    d["b1"][0] = 1.0 + 2.0 ** -8    # exact in FP32, a bfloat16 tie
+    d["W2"][0, 0] = 1.0
+    d["W3"][0] = 1.0
+    y, c = M.forward(M.pack(d), np.zeros((1, M.N_IN)))
+    assert c["z1"][0, 0] == 1.0 + 2.0 ** -8 and c["h1"][0, 0] == 1.0 and y[0] == 1.0
+    y64, _ = M.forward(M.pack(d), np.zeros((1, M.N_IN)), round_bf16=False)
+    assert y64[0] == 1.0 + 2.0 ** -8
+
+
+def test_loss_omega_derivative_and_closed_form():
+    """dL/domega against central differences; omega = 0 leaves every error
+    unchanged (loss 1)."""
+    A = P.hetero3d(5, seed=6).to_scipy()
+    lv = O.coarsen_level(A, np.ones(A.shape[0]), O.Options.for_dim(3))
+    E = M.projected_errors(A, lv.agg, lv.pval, lv.nc, 3, 5)
+    assert M.loss_omega(A, E, np.zeros(A.shape[0]))[0] == pytest.approx(1.0, rel=1e-14)
+    om = 0.3 + 0.4 * np.random.default_rng(2).random(A.shape[0])
+    L, g = M.loss_omega(A, E, om)
+    for i in (0, 17, A.shape[0] - 1):
+        h = 1e-6
+        e = np.zeros_like(om)
+        e[i] = h
+        fd = (M.loss_omega(A, E, om + e)[0] - M.loss_omega(A, E, om - e)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1e-3, np.abs(g).max())
+
+
+def test_deviation_bounds_cover_fp32_evaluations():
+    """The bounds the GPU tests use (tests/mlp_bounds.py) contain FP32
+    evaluations of the same network in two different summation orders."""
+    from tests import mlp_bounds as MB
+    A = P.hetero3d(8, seed=4).to_scipy()
+    w = M.init_weights(7)
+    F = M.features(A, 1)
+    om, dom, flips, fb = MB.omega_bounds(w, A, F)
+    p = M.unpack(w)
+
+    def fp32_forward(order):
+        X = M.bf16(F).astype(np.float32)
+        W1, W2, W3 = (M.bf16(p[k]).astype(np.float32) for k in ("W1", "W2", "W3"))
+
+        def acc(bias, Xl, W):
+            s = np.broadcast_to(np.asarray(bias, np.float32), (Xl.shape[0], W.shape[0])).copy()
+            for q in order(Xl.shape[1]):
+                s = s + Xl[:, q:q + 1] * W[:, q][None, :]
+            return s
+
+        h1 = M.bf16(np.maximum(acc(p["b1"], X, W1), 0)).astype(np.float32)
+        h2 = M.bf16(np.maximum(acc(p["b2"], h1, W2), 0)).astype(np.float32)
+        return acc(p["b3"], h2, W3[None, :])[:, 0].astype(np.float64)
+
+    for order in (lambda m: range(m), lambda m: range(m - 1, -1, -1)):
+        y32 = fp32_forward(order)
+        assert np.all(np.abs(y32 - fb["y"]) <= fb["ey"])
+        om32 = 1.0 / (1.0 + np.exp(-y32)) * M.omega_bound(A)
+        assert np.all(np.abs(om32 - om) <= dom)
+    assert 0.0 <= flips.mean() < 0.5

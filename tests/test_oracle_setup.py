@@ -406,3 +406,36 @@ def test_validate_rejects_bad_input():
     v[3] = np.nan
     with pytest.raises(O.OracleError):
         O.validate_csr(A.row_ptr, A.col, v)
+
+
+def test_strong_graph_and_influence_on_nonsymmetric_strength():
+    """A structurally symmetric matrix whose strength relation is not
+    symmetric (each row measures against its own largest coupling), with C,
+    G = C u C^T and the influence counts #{j : C_ji = 1} worked out by hand.
+
+    row 0: couplings 1 (col 1), 3 (col 3), alpha m = 1.5 -> C_03
+    row 1: couplings 2 (col 0), 2 (col 2), alpha m = 1   -> C_10, C_12
+    row 2: couplings 0.1 (col 1), 5 (col 3), alpha m = 2.5 -> C_23
+    row 3: couplings 1 (col 0), 4 (col 2), alpha m = 2   -> C_32
+    """
+    dense = np.array([[4.0, -1.0, 0.0, -3.0],
+                      [-2.0, 4.0, -2.0, 0.0],
+                      [0.0, -0.1, 4.0, -5.0],
+                      [-1.0, 0.0, -4.0, 6.0]])
+    A = sp.csr_matrix(dense)
+    A.sort_indices()
+    C = O.strength(A, 0.5)
+    rows = np.repeat(np.arange(4), np.diff(A.indptr))
+    strong = {(int(i), int(j)) for i, j, s in zip(rows, A.indices, C) if s}
+    assert strong == {(0, 3), (1, 0), (1, 2), (2, 3), (3, 2)}
+    G = O.strong_graph(A, C)
+    edges = {(int(i), int(j)) for i in range(4) for j in G.indices[G.indptr[i]:G.indptr[i + 1]]}
+    # the union adds (3,0), (0,1), (2,1): a 4-cycle 0-1-2-3-0, symmetric, no self loops
+    assert edges == {(0, 1), (1, 0), (1, 2), (2, 1), (2, 3), (3, 2), (0, 3), (3, 0)}
+    # column counts of C: col 0 <- row 1; col 1 <- none; col 2 <- rows 1, 3; col 3 <- rows 0, 2
+    assert list(O.influence_count(A, C)) == [1, 0, 2, 2]
+    # a negative diagonal flips the sign convention of its row: row 1 negated
+    # keeps the same strong set
+    A2 = sp.csr_matrix(dense * np.array([1, -1, 1, 1])[:, None])
+    A2.sort_indices()
+    assert np.array_equal(O.strength(A2, 0.5), C)

@@ -164,3 +164,96 @@ def test_batch_equals_individual_solves():
         H = O.setup(m.row_ptr, m.col, m.val, opts)
         ref = O.solve(H, b[off[s]:off[s + 1]])
         assert out[s].iters == ref.iters and np.array_equal(out[s].x, ref.x)
+
+
+def _three_level(krylov="fcg", kcycle_levels=1, t=0.25):
+    A = P.poisson2d(48)
+    H = O.setup(A.row_ptr, A.col, A.val,
+                O.Options.for_dim(2, coarse_max=40, krylov=krylov, kcycle_levels=kcycle_levels, kcycle_t=t))
+    assert H.L >= 2, "the K-cycle pin needs inner cycles on a level that is not the coarsest"
+    return H
+
+
+def _first_step(H, rc, cg):
+    """c = one inner cycle on level 1 and what the best multiple of c leaves,
+    written from the definition of the minimiser along c."""
+    A1 = H.levels[1].A.toarray()
+    c = O.cycle(H, 1, rc)
+    if cg:   # argmin_a ||A1^-1 rc - a c||_A1: a = c'rc / c'A1 c
+        a = (c @ rc) / (c @ A1 @ c)
+    else:    # argmin_a ||rc - a A1 c||_2
+        a = ((A1 @ c) @ rc) / ((A1 @ c) @ (A1 @ c))
+    return A1, c, a, rc - a * (A1 @ c)
+
+
+@pytest.mark.parametrize("krylov", ["fcg", "fgmres"])
+def test_kcycle_correction_is_minimiser_over_two_inner_cycles(krylov):
+    """With t = 0 the K-cycle always takes the second inner step; its coarse
+    correction is then the minimiser over span{c, d} (A_1-norm error for CG,
+    residual 2-norm for GMRES), solved here as a dense 2x2 Gram / least-squares
+    system from the two inner cycles computed independently."""
+    cg = krylov == "fcg"
+    H = _three_level(krylov, t=0.0)
+    rc = np.random.default_rng(11).standard_normal(H.levels[1].n)
+    A1, c, _a, rt = _first_step(H, rc, cg)
+    d = O.cycle(H, 1, rt)
+    if cg:
+        G = np.array([[c @ A1 @ c, c @ A1 @ d], [d @ A1 @ c, d @ A1 @ d]])
+        y = np.linalg.solve(G, np.array([c @ rc, d @ rc]))
+    else:
+        y, *_ = np.linalg.lstsq(np.stack([A1 @ c, A1 @ d], 1), rc, rcond=None)
+    e, steps = O.kcycle_correction(H, 1, rc)
+    assert steps == 2
+    want = y[0] * c + y[1] * d
+    assert np.linalg.norm(e - want) <= 1e-10 * np.linalg.norm(want)
+    # and it is a minimiser: the error (CG) or residual (GMRES) is orthogonal to the space
+    res = rc - A1 @ e
+    basis = (c, d) if cg else (A1 @ c, A1 @ d)
+    for u in basis:
+        assert abs(u @ res) <= 1e-10 * np.linalg.norm(u) * np.linalg.norm(rc)
+
+
+@pytest.mark.parametrize("krylov", ["fcg", "fgmres"])
+def test_kcycle_second_step_threshold(krylov):
+    """The second inner step runs exactly when ||r~|| > t ||rc||: just above
+    the measured ratio the correction is the best multiple of c, just below it
+    the two-step minimiser."""
+    cg = krylov == "fcg"
+    H0 = _three_level(krylov)
+    rc = np.random.default_rng(12).standard_normal(H0.levels[1].n)
+    _A1, c, a, rt = _first_step(H0, rc, cg)
+    q = np.linalg.norm(rt) / np.linalg.norm(rc)
+    assert 0.0 < q < 1.0
+    H0.opts.kcycle_t = q * 1.001
+    e, steps = O.kcycle_correction(H0, 1, rc)
+    assert steps == 1 and np.allclose(e, a * c, rtol=1e-12, atol=0)
+    H0.opts.kcycle_t = q * 0.999
+    e2, steps2 = O.kcycle_correction(H0, 1, rc)
+    assert steps2 == 2 and not np.allclose(e2, a * c, rtol=1e-6)
+
+
+def test_kcycle_nested_levels_and_v_only():
+    """kcycle_levels = 0 makes cycle() the V-cycle everywhere; with two
+    K-levels the level-0 cycle uses the level-1 K-cycle inside, and the
+    resulting preconditioned solve still converges."""
+    H = _three_level(kcycle_levels=0)
+    b = np.random.default_rng(13).standard_normal(H.levels[0].n)
+    assert np.array_equal(O.cycle(H, 0, b), O.vcycle(H, 0, b))
+    H2 = _three_level(kcycle_levels=2)
+    A = H2.levels[0].A
+    res = O.solve(H2, b, rtol=1e-10)
+    assert res.converged and np.linalg.norm(b - A @ res.x) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_kcycle_coefficients_guard_keeps_first_step():
+    """rho2 <= 0 (d adds nothing: d parallel to c) keeps alpha1/rho1 c."""
+    rng = np.random.default_rng(4)
+    n = 12
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n)
+    r, c = rng.standard_normal(n), rng.standard_normal(n)
+    d = 2.0 * c
+    v, w = A @ c, A @ d
+    rt = r - (c @ r) / (c @ v) * v
+    cc, cd = O.kcycle_coefficients(c, d, v, w, r, rt, "cg")
+    assert cd == 0.0 and cc == (c @ r) / (c @ v)
