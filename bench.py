@@ -1,15 +1,17 @@
 """Benchmark: aggregation-AMG setup + solve to a relative residual of 1e-8.
 
-One step = amg_setup + amg_solve of the named workload (3-D 7-point Poisson
-128^3 by default: 2,097,152 unknowns, 14,581,760 nonzeros), inputs already
+One step = amg_setup + amg_solve of the named workload (by default the
+largest single system: 3-D heterogeneous finite-volume diffusion on 160^3
+cells, k = exp(2g), 4,096,000 unknowns, 28,518,400 nonzeros), inputs already
 resident in device memory.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload C2]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload C3]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import subprocess
 
 import numpy as np
 import os
@@ -49,7 +51,10 @@ def presmooth_bytes_offsets16(n, nnz, val_bytes=8):
     return (val_bytes + 2) * nnz + 4 * ((n + 63) // 64 + 1) + 4 * val_bytes * n
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "l0_presmooth_c2_traffic.md")
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"l0_presmooth_{workload.lower()}_traffic.md")
+
+
 KERNEL_SOURCES = ["solver.hip", "kernels_common.hpp", "device_utils.hpp", "amg_internal.hpp"]
 
 
@@ -69,7 +74,7 @@ def measured_traffic(workload: str):
     changed since the counters were taken."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(traffic_file(workload)):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
@@ -93,6 +98,7 @@ def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
     opts = amg.Options(dim=dim, **opt)
     results = []
     probe = [0.0, 0]
+    fmt = None
     for i in range(warmup + steps):
         if i == warmup:
             torch.cuda.synchronize()
@@ -101,18 +107,42 @@ def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):
         _, it, rel = amg.solve(h, bt, 1e-8, x=x)
         if i >= warmup:
             s_ms, v_ms = h.timings()
-            results.append((it, rel, s_ms, v_ms))
+            results.append((it, rel, s_ms, v_ms) + h.setup_phases())
             ms, cnt = h.probe_timing()
             probe[0] += ms * cnt
             probe[1] += cnt
             if opt.get("probe"):
-                probe.append(h.level_format(0, "fp64"))
-        del h
+                fmt = h.level_format(0, "fp64")
+        h.close()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     probe_ms = probe[0] / probe[1] if probe[1] else None
-    fmt = probe[2] if len(probe) > 2 else None
     return wall, results, x, (probe_ms, probe[1], fmt)
+
+
+def form_summary(A, wall, res):
+    ok = all(r[1] <= 1e-8 for r in res)
+    med = lambda q: round(float(np.median([r[q] for r in res])), 3)   # noqa: E731
+    return {"mdof_s": round(A.n / wall / 1e6, 3) if ok else 0.0, "iters": res[-1][0],
+            "relres": max(r[1] for r in res), "setup_ms": med(2), "solve_ms": med(3), "tune_ms": med(4),
+            "graph_capture_ms": med(5)}
+
+
+def cold_start(amg, torch, dev, dim, b):
+    """The first setup + solve of the process on this workload: library load,
+    autotuner timing runs, device chunk allocation and graph capture included."""
+    bt = torch.from_numpy(b).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = amg.setup(*dev, amg.Options(dim=dim))
+    _, it, rel = amg.solve(h, bt, 1e-8)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s_ms, v_ms = h.timings()
+    tune, cap = h.setup_phases()
+    h.close()
+    return {"ms": round(t * 1e3, 2), "setup_ms": round(s_ms, 2), "solve_ms": round(v_ms, 2),
+            "tune_ms": round(tune, 2), "graph_capture_ms": round(cap, 2), "iters": it, "relres": rel}
 
 
 def multi_rhs_form(amg, torch, P, reps=2):
@@ -132,7 +162,7 @@ def multi_rhs_form(amg, torch, P, reps=2):
         X, its, rels = amg.solve_multi(h, Bm, 1e-8)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
-        del h
+        h.close()
         t0 = time.perf_counter()
         h = amg.setup(*dev, amg.Options(dim=3))
         its_s = []
@@ -141,7 +171,7 @@ def multi_rhs_form(amg, torch, P, reps=2):
             its_s.append(it)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
-        del h
+        h.close()
         best_b = tb if best_b is None else min(best_b, tb)
         best_s = ts if best_s is None else min(best_s, ts)
     ok = bool(np.all(rels <= 1e-8))
@@ -176,7 +206,7 @@ def batch_form(amg, torch, P, reps=2):
             t = time.perf_counter() - t0
             s_ms, v_ms = h.timings()
             its, rels = h.batch_results()
-            del h
+            h.close()
             if best is None or t < best:
                 best, info = t, (int(its.max()), float(rels.max()), s_ms, v_ms)
         ok = info[1] <= 1e-8
@@ -191,7 +221,7 @@ def batch_form(amg, torch, P, reps=2):
             h = amg.setup(*d, amg.Options(dim=2))
             bs = bt[int(off[q]):int(off[q + 1])]
             amg.solve(h, bs, 1e-8)
-            del h
+            h.close()
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         best = t if best is None else min(best, t)
@@ -235,7 +265,7 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
             t = time.perf_counter() - t1
             s_ms, v_ms = h.timings()
             kept = [int(h.smoother_info(k)[0]) for k in range(h.num_levels() - 1)] if "mlp_weights" in kw else None
-            del h
+            h.close()
             if best is None or t < best:
                 best, info = t, (it, rel, s_ms, v_ms, kept)
         out[name] = {"mdof_s": round(A.n / best / 1e6, 3) if info[1] <= 1e-8 else 0.0, "iters": info[0],
@@ -245,7 +275,24 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
     return out
 
 
-def cpu_baseline(A, dim, b):
+def cpu_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return {"nproc": os.cpu_count(), "sched_affinity": len(os.sched_getaffinity(0)), "lscpu_model": model}
+
+
+def cpu_baseline(A, dim, b, iters_gpu, sample_iters=2):
+    """The oracle on one host core: its full setup of the workload plus
+    `sample_iters` outer iterations, the solve scaled to the iteration count
+    the GPU needed (the oracle's iterations match the GPU's within one)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg_oracle as O
@@ -253,11 +300,33 @@ def cpu_baseline(A, dim, b):
         t0 = time.perf_counter()
         H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(dim))
         t1 = time.perf_counter()
-        res = O.solve(H, b, 1e-8)
+        res = O.solve(H, b, 1e-8, max_iter=sample_iters)
         t2 = time.perf_counter()
-    return {"value": A.n / (t2 - t0) / 1e6, "unit": "MDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"full workload, one setup+solve ({res.iters} FCG iterations, relres "
-                      f"{res.relres:.2e}); setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s"}
+    per_it = (t2 - t1) / max(res.iters, 1)
+    total = (t1 - t0) + per_it * iters_gpu
+    out = {"value": round(A.n / total / 1e6, 4), "unit": "MDOF/s", "cores": 1, "kind": "oracle",
+           "sample": f"oracle setup of the full workload ({t1 - t0:.1f} s) + {res.iters} FCG iterations "
+                     f"({t2 - t1:.1f} s), solve scaled to {iters_gpu} iterations"}
+    out.update(cpu_info())
+    return out
+
+
+def spmv_flushed(torch, launch, reps=20):
+    """Median time of one launch, each after a 1 GiB device write that evicts
+    the 256 MB Infinity Cache, timed with events on the current stream."""
+    flush = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    launch()
+    times = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        e0.record()
+        launch()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del flush
+    return float(np.median(times))
 
 
 def main():
@@ -265,12 +334,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-spmv", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched C4b form and print its JSON (for profiling)")
     ap.add_argument("--print-source-hash", action="store_true",
@@ -313,31 +384,33 @@ def main():
     dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
     torch.cuda.synchronize()
 
+    log("bench: cold start (first setup + solve of the process)")
+    cold = cold_start(amg, torch, dev, dim, b)
     log("bench: fp64 setup+solve")
     wall, res, x, (probe_ms, probe_n, probe_fmt) = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup,
-                                                 probe="l0_presmooth")
-    iters = [r[0] for r in res]
-    rels = [r[1] for r in res]
-    ok = all(r <= 1e-8 for r in rels)
-    value = A.n / wall / 1e6 if ok else 0.0
-
-    forms = {"fp64": {"mdof_s": round(value, 3), "iters": iters[-1], "relres": max(rels),
-                      "setup_ms": round(float(np.median([r[2] for r in res])), 3),
-                      "solve_ms": round(float(np.median([r[3] for r in res])), 3)}}
+                                                            probe="l0_presmooth")
+    forms = {"fp64": form_summary(A, wall, res)}
+    value = forms["fp64"]["mdof_s"]
     if not args.no_mixed:
         log("bench: mixed setup+solve")
         wall_m, res_m, xm, _ = run_form(amg, torch, dev, A, dim, b, args.steps, args.warmup, precision="mixed")
-        ok_m = all(r[1] <= 1e-8 for r in res_m)
-        forms["mixed"] = {"mdof_s": round(A.n / wall_m / 1e6 if ok_m else 0.0, 3), "iters": res_m[-1][0],
-                          "relres": max(r[1] for r in res_m),
-                          "setup_ms": round(float(np.median([r[2] for r in res_m])), 3),
-                          "solve_ms": round(float(np.median([r[3] for r in res_m])), 3),
-                          "x_err_vs_fp64": float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))}
+        forms["mixed"] = form_summary(A, wall_m, res_m)
+        forms["mixed"]["x_err_vs_fp64"] = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+    if not args.no_c2 and args.workload != "C2":
+        log("bench: C2 sub-form (3-D Poisson 128^3)")
+        A2, _, _ = P.config("C2")
+        b2 = P.rhs(A2, P.exact_solution(A2.n, 1))
+        dev2 = tuple(torch.from_numpy(a).cuda() for a in (A2.row_ptr, A2.col, A2.val))
+        c2 = {"workload": "C2 " + WORKLOADS["C2"][0], "n": A2.n, "nnz": A2.nnz}
+        for name, kw in (("fp64", {}), ("mixed", {"precision": "mixed"})):
+            w2, r2, _, _ = run_form(amg, torch, dev2, A2, 3, b2, args.steps, args.warmup, **kw)
+            c2[name] = form_summary(A2, w2, r2)
+        forms["c2"] = c2
+        del dev2
 
     if not args.no_multi:
         log("bench: multi-RHS form (C4a)")
         forms["multi_rhs"] = multi_rhs_form(amg, torch, P)
-
     if not args.no_batch:
         log("bench: batched form (C4b)")
         forms["batch"] = batch_form(amg, torch, P)
@@ -359,43 +432,6 @@ def main():
     copy_gbs = 2 * src_c.numel() * 8 / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
     del src_c, dst_c
 
-    # level-0 SpMV: events around repeated launches on the current stream
-    log("bench: level-0 SpMV")
-    xv = torch.from_numpy(xs).cuda()
-    y = torch.empty_like(xv)
-    reps = 50
-    for _ in range(5):
-        amg.spmv(*dev, xv, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        amg.spmv(*dev, xv, y)
-    e1.record()
-    torch.cuda.synchronize()
-    t_spmv = e0.elapsed_time(e1) / reps * 1e-3
-    nbytes = spmv_bytes(A.n, A.nnz)
-    gbs = nbytes / t_spmv / 1e9
-
-    # the same product with the level-0 kernel the autotuner picks (the solve's)
-    h0 = amg.setup(*dev, amg.Options(dim=dim))
-    fmt0, lpr0, _ = h0.level_format(0)
-    for _ in range(5):
-        h0.level_spmv(0, xv, y)
-    e0.record()
-    for _ in range(reps):
-        h0.level_spmv(0, xv, y)
-    e1.record()
-    torch.cuda.synchronize()
-    t_lvl = e0.elapsed_time(e1) / reps * 1e-3
-    del h0
-    tuned = {"kernel": kernel_name(fmt0, lpr0, "OpSpmv<double>"), "us": round(t_lvl * 1e6, 2),
-             "gb_s": round(nbytes / t_lvl / 1e9, 1), "bytes": nbytes,
-             "frac": round(nbytes / t_lvl / 1e9 / PEAK_HBM_GBS, 4)}
-    if fmt0 == 2:
-        fb = 10 * A.nnz + 4 * ((A.n + 63) // 64 + 1) + 16 * A.n
-        tuned["format_bytes"] = fb
-        tuned["format_gb_s"] = round(fb / t_lvl / 1e9, 1)
-
     line = {
         "metric": "setup+solve MDOF/s to rel-res 1e-8, FP64 vs mixed/batched/learned; SpMV GB/s",
         "value": round(value, 3), "unit": "MDOF/s", "n_gpus": 1, "steps": args.steps,
@@ -403,12 +439,36 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "n": A.n, "nnz": A.nnz, "rtol": 1e-8},
         "forms": forms,
-        "spmv": tuned,
-        "spmv_csr": {"kernel": "k_rows<double,L,OpSpmv<double>> (lanes from the row length)",
-                     "gb_s": round(gbs, 1), "us": round(t_spmv * 1e6, 2), "bytes": nbytes,
-                     "frac": round(gbs / PEAK_HBM_GBS, 4)},
+        "cold_start": cold,
         "device_copy_gb_s": round(copy_gbs, 1),
     }
+
+    if not args.no_spmv:
+        # level-0 SpMV, each launch after a cache-evicting write: the CSR kernel
+        # and the kernel the autotuner picks (the solve's)
+        log("bench: level-0 SpMV (cache flushed before every launch)")
+        xv = torch.from_numpy(xs).cuda()
+        y = torch.empty_like(xv)
+        nbytes = spmv_bytes(A.n, A.nnz)
+        t_csr = spmv_flushed(torch, lambda: amg.spmv(*dev, xv, y))
+        h0 = amg.setup(*dev, amg.Options(dim=dim))
+        fmt0, lpr0, _ = h0.level_format(0)
+        t_lvl = spmv_flushed(torch, lambda: h0.level_spmv(0, xv, y))
+        h0.close()
+        tuned = {"kernel": kernel_name(fmt0, lpr0, "OpSpmv<double>"), "us": round(t_lvl * 1e6, 2),
+                 "gb_s": round(nbytes / t_lvl / 1e9, 1), "bytes": nbytes,
+                 "frac": round(nbytes / t_lvl / 1e9 / PEAK_HBM_GBS, 4), "cache": "flushed before each launch"}
+        if fmt0 == 2:
+            fb = 10 * A.nnz + 4 * ((A.n + 63) // 64 + 1) + 16 * A.n
+            tuned["format_bytes"] = fb
+            tuned["format_gb_s"] = round(fb / t_lvl / 1e9, 1)
+            tuned["format_frac"] = round(fb / t_lvl / 1e9 / PEAK_HBM_GBS, 4)
+        line["spmv"] = tuned
+        line["spmv_csr"] = {"kernel": "k_rows<double,L,OpSpmv<double>> (lanes from the row length)",
+                            "gb_s": round(nbytes / t_csr / 1e9, 1), "us": round(t_csr * 1e6, 2), "bytes": nbytes,
+                            "frac": round(nbytes / t_csr / 1e9 / PEAK_HBM_GBS, 4),
+                            "cache": "flushed before each launch"}
+
     pbytes = presmooth_bytes(A.n, A.nnz)
     if probe_ms:
         ach = pbytes / (probe_ms * 1e-3) / 1e9
@@ -424,8 +484,8 @@ def main():
             line["roofline"]["format_bytes_per_launch"] = fb
             line["roofline"]["format_gb_s"] = round(fb / (probe_ms * 1e-3) / 1e9, 1)
     if not args.no_cpu_baseline:
-        log("bench: oracle CPU baseline (single thread)")
-        line["cpu_baseline"] = cpu_baseline(A, dim, b)
+        log("bench: oracle CPU baseline (single thread, bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(A, dim, b, forms["fp64"]["iters"])
     print(json.dumps(line), flush=True)
     return 0
 

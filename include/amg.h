@@ -88,6 +88,11 @@ typedef struct {
  * every level without the setup-time comparison against plain omega_k (for
  * weights already validated by the caller on actual solves). */
 #define AMG_FLAG_LEARNED_ALWAYS 8u
+/* amg_options.flags: amg_setup borrows A instead of copying it: level 0 of the
+ * hierarchy reads the caller's row_ptr, col_idx and val, which must stay
+ * allocated and unchanged until amg_destroy (or until amg_resetup hands over
+ * new values).  The library never writes them. */
+#define AMG_FLAG_BORROW_A 16u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {
@@ -116,8 +121,10 @@ const char* amg_last_error(void);
  * until a level has at most coarse_max unknowns; per level the damped Jacobi
  * weight of eq. damped_jacobi from an Arnoldi estimate of rho(D^-1 A), and a
  * dense factorisation of the coarsest level (Section 3).
- * A: device CSR (copied; the caller may free it after the call returns).
- * opt: (host) options, NULL for amg_default_options(dim=3).
+ * A: device CSR, copied (the caller may free it after the call returns)
+ * unless opt->flags holds AMG_FLAG_BORROW_A.
+ * opt: (host) options, NULL for amg_default_options(dim=3); kcycle_levels
+ * at most 24.
  * out: (host) receives the new hierarchy; free it with amg_destroy.
  * Errors: EINVAL (structure, zero diagonal, nonsymmetric pattern), ENANINF,
  * ECOARSEN, ENOMEM, EHIP; *out is NULL on error.  Synchronises s. */
@@ -248,8 +255,16 @@ int32_t amg_level_smoother(const amg_hierarchy* h, int32_t k, int32_t* learned, 
 /* (host) copy of omega_i / a_ii, the Jacobi scaling the cycle applies on level k. */
 int32_t amg_export_jacobi(const amg_hierarchy* h, int32_t k, double* wdinv);
 
-/* Release the hierarchy and its device memory (NULL is ignored). */
+/* Release the hierarchy (NULL is ignored).  Its device memory returns to a
+ * process-wide cache of large chunks that later setups reuse without
+ * allocating; amg_release_cached_memory gives that cache back to HIP. */
 void amg_destroy(amg_hierarchy* h);
+
+/* Free every cached device chunk that no live hierarchy uses (hipFree);
+ * returns the number of bytes released.  Live hierarchies are unaffected.
+ * Call it after destroying hierarchies whose memory should return to the
+ * device, and before the HIP runtime shuts down. */
+size_t amg_release_cached_memory(void);
 
 /* Number of levels L+1 of a hierarchy (the coarsest level is index L). */
 int32_t amg_num_levels(const amg_hierarchy* h);
@@ -304,6 +319,12 @@ int32_t amg_hessenberg_radius(const double* H, int32_t m, double* rho);
 /* (host) timing of the last setup and solve on this hierarchy, in ms, from
  * HIP events on the hierarchy's stream. */
 int32_t amg_timings(const amg_hierarchy* h, double* setup_ms, double* solve_ms);
+
+/* (host) parts of the last setup's time, in ms of host wall clock: the
+ * per-level SpMV autotuner (near 0 when its results came from the cache of
+ * an earlier setup with the same level sizes) and the capture of the outer
+ * iteration into HIP graphs.  Both are inside amg_timings' setup_ms. */
+int32_t amg_setup_phases(const amg_hierarchy* h, double* tune_ms, double* capture_ms);
 
 /* (host) average duration in ms of the kernel selected by opt.probe, over the
  * samples taken since setup: HIP events recorded on the solve stream right

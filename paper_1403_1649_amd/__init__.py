@@ -21,6 +21,7 @@ from .binding import (  # noqa: F401
     mlp_omega,
     library_path,
     node_hash,
+    release_cached_memory,
     setup,
     setup_batched,
     solve,

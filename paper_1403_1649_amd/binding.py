@@ -1,8 +1,10 @@
 """ctypes marshalling for the C ABI in include/amg.h (argument passing only)."""
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -14,6 +16,7 @@ AMG_EBREAKDOWN, AMG_ECOARSEN, AMG_ENANINF, AMG_EUNSUPPORTED = 5, 6, 7, 8
 _PREC = {"fp64": 0, "mixed": 1}
 _PROBE = {"none": 0, "l0_presmooth": 1, "l0_postsmooth": 2, "outer_spmv": 3}
 _KRYLOV = {"fcg": 0, "fgmres": 1}
+FLAG_NO_GRAPH, FLAG_NO_TUNE, FLAG_LEARNED_ALWAYS, FLAG_BORROW_A = 1, 2, 8, 16
 
 EXPORTED = [
     "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",
@@ -21,7 +24,8 @@ EXPORTED = [
     "amg_node_hash", "amg_galerkin", "amg_hessenberg_radius", "amg_timings", "amg_probe_timing",
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
-    "amg_batch_level", "amg_level_format", "amg_level_spmv",
+    "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
+    "amg_setup_phases",
 ]
 
 
@@ -122,8 +126,30 @@ def lib():
     L.amg_batch_level.restype = i32
     L.amg_level_format.argtypes = [vp, i32, i32, P(i32), P(i32), P(C.c_float)]
     L.amg_level_format.restype = i32
+    L.amg_setup_phases.argtypes = [vp, P(dbl), P(dbl)]
+    L.amg_setup_phases.restype = i32
+    L.amg_release_cached_memory.argtypes = []
+    L.amg_release_cached_memory.restype = C.c_size_t
     _LIB = L
+    atexit.register(_teardown)
     return L
+
+
+_LIVE = weakref.WeakSet()
+
+
+def _teardown():
+    """At interpreter exit, before the HIP runtime shuts down: destroy the
+    hierarchies still alive and give the library's cached device memory back."""
+    for h in list(_LIVE):
+        h.close()
+    if _LIB is not None:
+        _LIB.amg_release_cached_memory()
+
+
+def release_cached_memory() -> int:
+    """amg_release_cached_memory: bytes of cached device chunks freed."""
+    return int(lib().amg_release_cached_memory())
 
 
 def status_string(code: int) -> str:
@@ -198,16 +224,23 @@ def _csr(row_ptr, col, val) -> AmgCsrC:
 class Hierarchy:
     """An amg_hierarchy handle (destroyed with the object)."""
 
-    def __init__(self, handle: C.c_void_p, n: int, opts: Options, nsys: int = 0):
+    def __init__(self, handle: C.c_void_p, n: int, opts: Options, nsys: int = 0, keep=None):
         self._h = handle
         self.n = n
         self.opts = opts
         self.nsys = nsys
+        self._keep = keep   # borrowed device arrays (AMG_FLAG_BORROW_A) stay alive with the handle
+        _LIVE.add(self)
 
-    def __del__(self):
+    def close(self):
+        """amg_destroy (also run when the object is collected)."""
         if getattr(self, "_h", None) and _LIB is not None:
             _LIB.amg_destroy(self._h)
-            self._h = None
+        self._h = None
+        self._keep = None
+
+    def __del__(self):
+        self.close()
 
     @property
     def handle(self):
@@ -250,6 +283,12 @@ class Hierarchy:
         s, v = C.c_double(), C.c_double()
         _check(lib().amg_timings(self._h, C.byref(s), C.byref(v)))
         return s.value, v.value
+
+    def setup_phases(self):
+        """(autotuner ms, graph capture ms) of the last setup (host wall clock)."""
+        t, g = C.c_double(), C.c_double()
+        _check(lib().amg_setup_phases(self._h, C.byref(t), C.byref(g)))
+        return t.value, g.value
 
     def smoother_info(self, k: int):
         """(learned?, validation loss with plain omega, with learned weights)."""
@@ -308,7 +347,8 @@ def setup(row_ptr, col, val, opts: Options | None = None, dim: int = 3) -> Hiera
     A = _csr(row_ptr, col, val)
     h = C.c_void_p()
     _check(lib().amg_setup(C.byref(A), C.byref(opts.c), _stream(), C.byref(h)))
-    return Hierarchy(h, A.n, opts)
+    keep = (row_ptr, col, val) if opts.c.flags & FLAG_BORROW_A else None
+    return Hierarchy(h, A.n, opts, keep=keep)
 
 
 def setup_batched(row_ptr, col, val, sys_off, opts: Options | None = None, dim: int = 2) -> Hierarchy:

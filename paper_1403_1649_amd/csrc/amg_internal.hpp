@@ -197,6 +197,7 @@ struct Hierarchy {
   double probe_ms = 0.0;
   int probe_samples = 0;
   float setup_ms = 0.f, solve_ms = 0.f;
+  double tune_ms = 0.0, capture_ms = 0.0;   // host time of the autotuner and of the graph capture in setup
   // batched systems: count (0 = one system), per-system control of the solve
   // and the results of the last solve
   int nsys = 0;
@@ -389,6 +390,7 @@ int pick_lanes_per_row(int n, int nnz);
 double hessenberg_spectral_radius(const double* H, int m);
 void init_control(Hierarchy& h);
 void build_hierarchy(Hierarchy& h, const amg_csr& A);
+size_t release_cached_chunks();
 void galerkin_standalone(Hierarchy& h, const amg_csr& A, const int* agg, const double* pval, int nc,
                          int* nnz_c, int** rp_c, int** ci_c, double** val_c);
 

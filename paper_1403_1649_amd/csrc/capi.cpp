@@ -98,8 +98,8 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
   amg_options o;
   if (opt) o = *opt; else amg_default_options(&o, 3);
   if (!(o.strength_alpha >= 0.0) || o.coarse_max < 1 || o.max_levels < 1 || o.kcycle_levels < 0 ||
-      !(o.kcycle_t >= 0.0) || !(o.jacobi_scale > 0.0) || o.arnoldi_m < 1 || o.arnoldi_m > 5 ||
-      o.max_iter < 0 || o.dense_max < 1 || o.dense_max > 8192)
+      o.kcycle_levels > 24 || !(o.kcycle_t >= 0.0) || !(o.jacobi_scale > 0.0) || o.arnoldi_m < 1 ||
+      o.arnoldi_m > 5 || o.max_iter < 0 || o.dense_max < 1 || o.dense_max > 8192)
     return fail(AMG_EINVAL, "amg_setup: option out of range");
   if (o.krylov != AMG_KRYLOV_FCG && o.krylov != AMG_KRYLOV_FGMRES) return fail(AMG_EINVAL, "amg_setup: krylov");
   if (o.gmres_restart < 1 || o.gmres_restart > 64) return fail(AMG_EINVAL, "amg_setup: gmres_restart in [1, 64]");
@@ -275,6 +275,14 @@ int32_t amg_solve_multi(amg_hierarchy* H, int32_t nrhs, const double* B, double 
 
 void amg_destroy(amg_hierarchy* H) { delete H; }
 
+size_t amg_release_cached_memory(void) {
+  try {
+    return amg::release_cached_chunks();
+  } catch (...) {
+    return 0;
+  }
+}
+
 int32_t amg_num_levels(const amg_hierarchy* H) { return H ? (int32_t)H->h.levels.size() : 0; }
 
 int32_t amg_level_info(const amg_hierarchy* H, int32_t k, int32_t* n, int32_t* nnz, double* omega,
@@ -385,6 +393,13 @@ int32_t amg_timings(const amg_hierarchy* H, double* setup_ms, double* solve_ms) 
   if (!H) return fail(AMG_EINVAL, "amg_timings: NULL hierarchy");
   if (setup_ms) *setup_ms = H->h.setup_ms;
   if (solve_ms) *solve_ms = H->h.solve_ms;
+  return AMG_OK;
+}
+
+int32_t amg_setup_phases(const amg_hierarchy* H, double* tune_ms, double* capture_ms) {
+  if (!H) return fail(AMG_EINVAL, "amg_setup_phases: NULL hierarchy");
+  if (tune_ms) *tune_ms = H->h.tune_ms;
+  if (capture_ms) *capture_ms = H->h.capture_ms;
   return AMG_OK;
 }
 

@@ -9,9 +9,10 @@
 // matrix in global memory); per pivot step the owner of
 // column k picks the pivot and publishes column k, one grid barrier, then
 // every block updates its band.  A single block needs no grid barrier.  The
-// barrier needs all blocks resident at once: each block is one 1024-thread
-// workgroup (one CU), and the grid never exceeds 128 of the 256 CUs, so later
-// blocks always find room even while other work occupies the device.
+// barrier needs all blocks resident at once, so the kernel is launched as a
+// cooperative launch, which the runtime refuses (an error, not a hang) when
+// the grid cannot be resident together; the grid never exceeds 128 one-CU
+// workgroups of the 256 CUs.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -717,7 +718,10 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
       const size_t bytes = ((size_t)band * n + n + band) * sizeof(double);
       AMG_HIP(hipFuncSetAttribute((const void*)k_gauss_jordan_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)bytes));
-      k_gauss_jordan_lds<<<(int)nb, kGJThreads, bytes, s>>>(n, (int)band, work, piv, colbuf, sync, err);
+      int bandi = (int)band;
+      void* args[] = {&n, &bandi, &work, &piv, &colbuf, &sync, &err};
+      AMG_HIP(hipLaunchCooperativeKernel((const void*)k_gauss_jordan_lds, dim3((unsigned)nb), dim3(kGJThreads), args,
+                                         (unsigned)bytes, s));
       const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
       k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
       return;
@@ -727,7 +731,10 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
   int bandg = (n + nbg - 1) / nbg;
   if (bandg > 1024) bandg = 1024;
   nbg = (n + bandg - 1) / bandg;
-  k_gauss_jordan<<<nbg, kGJThreads, 0, s>>>(n, bandg, work, piv, colbuf, sync, err);
+  {
+    void* args[] = {&n, &bandg, &work, &piv, &colbuf, &sync, &err};
+    AMG_HIP(hipLaunchCooperativeKernel((const void*)k_gauss_jordan, dim3((unsigned)nbg), dim3(kGJThreads), args, 0u, s));
+  }
   const int g = (int)std::min<size_t>((nn + 255) / 256, 1024);
   k_gj_unpermute<<<g, 256, n * sizeof(int), s>>>(n, work, piv, inv, inv32, nullptr);
 }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -20,9 +21,11 @@ namespace amg {
 // ---------------------------------------------------------------- arena
 namespace {
 std::mutex g_cache_mu;
+// Never destroyed: no destructor of the library runs at process exit, when the
+// HIP runtime may already be shut down.
 std::multimap<size_t, void*>& chunk_cache() {
-  static std::multimap<size_t, void*> c;
-  return c;
+  static auto* c = new std::multimap<size_t, void*>();
+  return *c;
 }
 constexpr size_t kMinChunk = size_t(64) << 20;
 constexpr size_t kAlign = 256;
@@ -61,6 +64,17 @@ void give_chunk(void* p, size_t sz) {
   chunk_cache().emplace(sz, p);
 }
 }  // namespace
+
+size_t release_cached_chunks() {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  size_t bytes = 0;
+  for (auto& kv : chunk_cache()) {
+    bytes += kv.first;
+    (void)hipFree(kv.second);
+  }
+  chunk_cache().clear();
+  return bytes;
+}
 
 Arena::~Arena() {
   for (auto& c : chunks_) give_chunk(c.base, c.size);
@@ -437,12 +451,18 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   Level l0;
   l0.n = A.n;
   l0.nnz = A.nnz;
-  l0.rp = h.arena.alloc_n<int>(A.n + 1);
-  l0.ci = h.arena.alloc_n<int>(A.nnz);
-  l0.val = h.arena.alloc_n<double>(A.nnz);
-  AMG_HIP(hipMemcpyAsync(l0.rp, A.row_ptr, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (o.flags & AMG_FLAG_BORROW_A) {   // the caller keeps A alive and unchanged; nothing writes level 0
+    l0.rp = const_cast<int*>(A.row_ptr);
+    l0.ci = const_cast<int*>(A.col_idx);
+    l0.val = const_cast<double*>(A.val);
+  } else {
+    l0.rp = h.arena.alloc_n<int>(A.n + 1);
+    l0.ci = h.arena.alloc_n<int>(A.nnz);
+    l0.val = h.arena.alloc_n<double>(A.nnz);
+    AMG_HIP(hipMemcpyAsync(l0.rp, A.row_ptr, (A.n + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(l0.ci, A.col_idx, (size_t)A.nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipMemcpyAsync(l0.val, A.val, (size_t)A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   // the row pointers must be consistent before any kernel walks the rows
   sy.fetch(l0.rp, 0);
   sy.fetch(l0.rp + A.n, 1);
@@ -655,12 +675,17 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     if (h.levels[k].nslices == 0) build_sell(h, tmp, h.levels[k]);
   sy.wait_and_check();
   take_arnoldi();
+  using clk = std::chrono::steady_clock;
+  const auto t_tune = clk::now();
   if (!(o.flags & AMG_FLAG_NO_TUNE)) autotune_levels(h);
+  const auto t_graph = clk::now();
+  h.tune_ms = std::chrono::duration<double, std::milli>(t_graph - t_tune).count();
   if (o.probe != AMG_PROBE_NONE) {
     AMG_HIP(hipEventCreate(&h.pev[0]));
     AMG_HIP(hipEventCreate(&h.pev[1]));
   }
   if (!(o.flags & AMG_FLAG_NO_GRAPH) && o.krylov == AMG_KRYLOV_FCG) build_solve_graphs(h);
+  h.capture_ms = std::chrono::duration<double, std::milli>(clk::now() - t_graph).count();
 }
 
 

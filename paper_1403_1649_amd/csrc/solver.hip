@@ -1156,7 +1156,7 @@ struct TuneKey {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Level::Tune>& tune_cache() {
-  static std::map<TuneKey, Level::Tune> c;
+  static auto& c = *new std::map<TuneKey, Level::Tune>();   // never destroyed (no exit-time destructor)
   static bool loaded = false;
   if (!loaded) {
     loaded = true;

@@ -98,3 +98,23 @@ def test_batched_setup_validation_without_gpu():
     assert b"flexible CG" in L.amg_last_error()
     assert L.amg_batch_results(None, None, None) == 1
     assert L.amg_batch_level(None, 0, None, None) == 1
+
+
+def test_setup_rejects_too_many_kcycle_levels_without_gpu():
+    """The K-cycle keeps per-level device slots for 24 levels: more is EINVAL
+    before any device work (the matrix pointers are never dereferenced)."""
+    L = _lib_or_skip()
+    h = C.c_void_p()
+    dummy = np.zeros(8, np.int64)
+    p = dummy.ctypes.data
+    A = amg.binding.AmgCsrC(10, 28, p, p, p)
+    opts = amg.Options(dim=3, kcycle_levels=25, max_levels=40)
+    assert L.amg_setup(C.byref(A), C.byref(opts.c), None, C.byref(h)) == 1
+    assert b"option out of range" in L.amg_last_error()
+    assert not h.value
+
+
+def test_release_cached_memory_without_gpu():
+    """Nothing is cached before any setup: the call frees nothing."""
+    _lib_or_skip()
+    assert amg.release_cached_memory() == 0

@@ -424,3 +424,26 @@ def test_omega_independent_of_recycled_device_memory():
         S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
         omega, _ = O.jacobi_weight(S, oo.arnoldi_m, oo.seed + 1, oo.jacobi_scale)
         assert abs(ex["omega"] - omega) <= 1e-12 * omega, (k, ex["omega"], omega)
+
+
+def test_borrowed_matrix_and_cache_release():
+    """AMG_FLAG_BORROW_A: the hierarchy reads the caller's arrays (identical
+    hierarchy and solve); amg_release_cached_memory returns cached chunks once
+    no hierarchy holds them."""
+    A = P.poisson3d(24)
+    rp, ci, v = to_dev(A)
+    b = dev_vec(P.rhs(A, P.exact_solution(A.n, 1)))
+    h1 = amg.setup(rp, ci, v, amg.Options(dim=3))
+    x1, it1, rel1 = amg.solve(h1, b, 1e-8)
+    h2 = amg.setup(rp, ci, v, amg.Options(dim=3, flags=amg.binding.FLAG_BORROW_A))
+    x2, it2, rel2 = amg.solve(h2, b, 1e-8)
+    assert it1 == it2 and rel2 <= 1e-8 and torch.equal(x1, x2)
+    for k in range(h1.num_levels() - 1):
+        e1, e2 = h1.export_level(k), h2.export_level(k)
+        for key in ("row_ptr", "col", "val", "agg", "state"):
+            assert np.array_equal(e1[key], e2[key]), (k, key)
+    h1.close()
+    h2.close()
+    torch.cuda.synchronize()
+    assert amg.release_cached_memory() > 0
+    assert amg.release_cached_memory() == 0
