@@ -158,15 +158,16 @@ def priorities(cnt: np.ndarray, seed: int) -> np.ndarray:
     return cnt.astype(np.float64) + h.astype(np.float64) * 2.0 ** -32
 
 
-def mis2_parallel(G: sp.csr_matrix, v: np.ndarray):
-    """Algorithm 2 as printed, in synchronous rounds.
+def mis_parallel(G: sp.csr_matrix, v: np.ndarray, k: int = 2):
+    """Algorithm 2 in synchronous rounds, for MIS(k) (Section 2.1.2: roots
+    more than k apart; Algorithm 2 is k = 2, with two sweeps).
 
     Tuples T_i = (s_i, v_i, i) are compared lexicographically.  Each round
-    builds the tuples, takes two max sweeps over N_i (each sweep reads the
-    previous sweep's tuples: double buffered), then every undecided node i
-    becomes an MIS node if the maximal tuple it sees is its own, or a non-MIS
-    node if that tuple belongs to an MIS node.  Returns (s, rounds) with
-    s in {1 (MIS), -1 (non-MIS)}."""
+    builds the tuples, takes k max sweeps over N_i (each sweep reads the
+    previous sweep's tuples: double buffered), so every node sees the largest
+    tuple within distance k; then every undecided node i becomes an MIS node
+    if that tuple is its own, or a non-MIS node if it belongs to an MIS node.
+    Returns (s, rounds) with s in {1 (MIS), -1 (non-MIS)}."""
     n = G.shape[0]
     ball = (G + sp.identity(n, dtype=np.int8, format="csr")).tocsr()  # N_i with i itself
     s = np.zeros(n, dtype=np.int64)
@@ -178,7 +179,7 @@ def mis2_parallel(G: sp.csr_matrix, v: np.ndarray):
         order = np.lexsort((nodes, v, s))          # primary s, then v, then i
         T = np.empty(n, dtype=np.int64)
         T[order] = nodes
-        for _d in (1, 2):
+        for _d in range(k):
             T = np.maximum.reduceat(T[ball.indices], ball.indptr[:-1])   # T <- T-hat
         i_max = order[T]
         s_max = s[i_max]
@@ -190,9 +191,14 @@ def mis2_parallel(G: sp.csr_matrix, v: np.ndarray):
     return s, rounds
 
 
-def mis2_greedy(G: sp.csr_matrix, v: np.ndarray) -> np.ndarray:
-    """Sequential greedy MIS(2): visit nodes by decreasing v; a node becomes an
-    MIS node when no MIS node lies within graph distance 2.  (Small graphs.)"""
+def mis2_parallel(G: sp.csr_matrix, v: np.ndarray):
+    """Algorithm 2 as printed: MIS(2)."""
+    return mis_parallel(G, v, 2)
+
+
+def mis_greedy(G: sp.csr_matrix, v: np.ndarray, k: int = 2) -> np.ndarray:
+    """Sequential greedy MIS(k): visit nodes by decreasing v; a node becomes an
+    MIS node when no MIS node lies within graph distance k.  (Small graphs.)"""
     n = G.shape[0]
     nbr = [G.indices[G.indptr[i]:G.indptr[i + 1]] for i in range(n)]
     s = -np.ones(n, dtype=np.int64)
@@ -201,20 +207,31 @@ def mis2_greedy(G: sp.csr_matrix, v: np.ndarray) -> np.ndarray:
         if blocked[i]:
             continue
         s[i] = 1
-        blocked[i] = True
-        for j in nbr[i]:
-            blocked[j] = True
-            for k in nbr[j]:
-                blocked[k] = True
+        frontier, seen = [i], {i}
+        for _d in range(k):                        # everything within distance k
+            nxt = []
+            for u in frontier:
+                for j in nbr[u]:
+                    if j not in seen:
+                        seen.add(j)
+                        nxt.append(j)
+            frontier = nxt
+        blocked[list(seen)] = True
     return s
+
+
+def mis2_greedy(G: sp.csr_matrix, v: np.ndarray) -> np.ndarray:
+    """Sequential greedy MIS(2)."""
+    return mis_greedy(G, v, 2)
 
 
 # ---------------------------------------------------------------------------
 # Section 2.1.2 (end): aggregates around the MIS(2) roots
 # ---------------------------------------------------------------------------
 
-def aggregate(G: sp.csr_matrix, s: np.ndarray, v: np.ndarray):
-    """Every non-MIS node joins its nearest MIS node (graph distance in G).
+def aggregate(G: sp.csr_matrix, s: np.ndarray, v: np.ndarray, k: int = 2):
+    """Every non-MIS node joins its nearest MIS node (graph distance in G, at
+    most k for MIS(k) roots).
 
     Ties between equally near roots go to the root with the larger v; coarse
     ids number the roots in ascending node order.  Returns (agg, n_c)."""
@@ -233,13 +250,19 @@ def aggregate(G: sp.csr_matrix, s: np.ndarray, v: np.ndarray):
         best = _segmax(cand, M.indptr, -1)
         return np.where(best >= 0, order_to_node[np.maximum(best, 0)], -1)
 
-    d1 = best_root(G)                                  # roots at distance 1
-    G2 = (G @ G).tocsr()                               # walks of length 2
-    G2.sort_indices()
-    d2 = best_root(G2)                                 # roots reachable in 2 steps
-    chosen = np.where(is_root, np.arange(n), np.where(d1 >= 0, d1, d2))
+    # walks of length d reach exactly the roots at distance d from a node that
+    # has none nearer, so the first d with a reachable root gives the nearest
+    chosen = np.where(is_root, np.arange(n), -1)
+    W = G.copy()
+    for d in range(1, k + 1):
+        if d > 1:
+            W = (W @ G).tocsr()
+            W.data[:] = 1
+        W.sort_indices()
+        bd = best_root(W)
+        chosen = np.where(chosen >= 0, chosen, bd)
     if np.any(chosen < 0):
-        raise OracleError("EINVAL", "node farther than 2 from every MIS(2) node")
+        raise OracleError("EINVAL", f"node farther than {k} from every MIS({k}) node")
     return coarse_id[chosen], int(roots.shape[0])
 
 
@@ -337,6 +360,7 @@ class Options:
     coarse_max: int = 600            # "about 600" unknowns on the coarsest level (Section 3)
     max_levels: int = 20
     kcycle_levels: int = 2           # K-cycles on the top two levels (Section 2.2)
+    mis_k: int = 2                   # roots form an MIS(k) (Section 2.1.2; Algorithm 2 is k = 2)
     kcycle_t: float = 0.25
     jacobi_scale: float = 4.0 / 3.0
     arnoldi_m: int = 5
@@ -345,6 +369,13 @@ class Options:
     gmres_restart: int = 30
     max_iter: int = 200
     dense_max: int = 4096            # largest coarsest level accepted after a stall
+    # smoother S_k (Section 2.2.1): "jacobi" (damped Jacobi, eq. damped_jacobi),
+    # "chebyshev" (polynomial smoother, Section 5) or "mcsgs" (multi-colour
+    # symmetric Gauss-Seidel, Section 2.2.1)
+    smoother: str = "jacobi"
+    cheb_degree: int = 2             # SpMVs per Chebyshev smoothing step
+    cheb_ratio: float = 4.0          # Chebyshev interval [b / ratio, b], b = cheb_upper * rho
+    cheb_upper: float = 1.1          # margin over the Arnoldi estimate of rho(D^-1 A)
 
     @staticmethod
     def for_dim(dim: int, **kw) -> "Options":
@@ -369,6 +400,9 @@ class Level:
     omega: float = 0.0
     rho: float = 0.0
     wdinv: np.ndarray | None = None      # omega / a_ii
+    smoother: str = "jacobi"
+    cheb: tuple | None = None            # (theta, delta, degree) of the Chebyshev smoother
+    colors: np.ndarray | None = None     # colour of every row (multi-colour Gauss-Seidel)
 
     @property
     def n(self) -> int:
@@ -404,8 +438,8 @@ def coarsen_level(A: sp.csr_matrix, B: np.ndarray, opts: Options) -> Level:
     lv.G = strong_graph(A, lv.C)
     lv.cnt = influence_count(A, lv.C)
     lv.v = priorities(lv.cnt, opts.seed)
-    lv.s, lv.mis_rounds = mis2_parallel(lv.G, lv.v)
-    lv.agg, lv.nc = aggregate(lv.G, lv.s, lv.v)
+    lv.s, lv.mis_rounds = mis_parallel(lv.G, lv.v, opts.mis_k)
+    lv.agg, lv.nc = aggregate(lv.G, lv.s, lv.v, opts.mis_k)
     lv.pval, Bc, lv.P = interpolation(lv.agg, lv.nc, B)
     lv.R = lv.P.T.tocsr()
     lv.Ac = galerkin(A, lv.agg, lv.pval, lv.nc)
@@ -433,6 +467,13 @@ def setup(row_ptr, col, val, opts: Options | None = None) -> Hierarchy:
             break
         lv.omega, lv.rho = jacobi_weight(A, opts.arnoldi_m, opts.seed + 1, opts.jacobi_scale)
         lv.wdinv = lv.omega / A.diagonal()
+        lv.smoother = opts.smoother
+        if opts.smoother == "chebyshev":
+            lv.cheb = chebyshev_interval(lv.rho, opts)
+        elif opts.smoother == "mcsgs":
+            lv.colors = color_greedy(A, opts.seed + 2)
+        elif opts.smoother != "jacobi":
+            raise OracleError("EINVAL", f"unknown smoother {opts.smoother}")
         levels.append(lv)
         A, B = lv.Ac, lv.Bc
     H = Hierarchy(levels=levels, opts=opts)
@@ -458,8 +499,104 @@ def setup(row_ptr, col, val, opts: Options | None = None) -> Hierarchy:
 # ---------------------------------------------------------------------------
 
 def smooth(lv: Level, b, x):
-    """Damped Jacobi (eq. damped_jacobi): x <- x + omega D^{-1} (b - A x)."""
+    """One smoothing step S_k(b, A_k, x) (Section 2.2.1): damped Jacobi
+    (eq. damped_jacobi) x <- x + omega D^{-1} (b - A x) by default."""
+    if lv.smoother == "chebyshev":
+        return chebyshev_smooth(lv, b, x)
+    if lv.smoother == "mcsgs":
+        return sgs_smooth(lv, b, x)
     return x + lv.wdinv * (b - lv.A @ x)
+
+
+# ---------------------------------------------------------------------------
+# Other smoothers: polynomial (Section 5, future work) and multi-colour
+# symmetric Gauss-Seidel (Section 2.2.1)
+# ---------------------------------------------------------------------------
+
+def chebyshev_interval(rho: float, opts: Options):
+    """The interval [a, b] of the spectrum of D^-1 A that the polynomial damps:
+    b = cheb_upper * rho (the Arnoldi estimate errs low), a = b / cheb_ratio.
+    Returns (theta, delta, degree): centre, half-width, polynomial degree."""
+    b = opts.cheb_upper * rho
+    a = b / opts.cheb_ratio
+    return 0.5 * (b + a), 0.5 * (b - a), opts.cheb_degree
+
+
+def chebyshev_smooth(lv: Level, b, x):
+    """Chebyshev acceleration of the Jacobi iteration (the three-term
+    recurrence of the Chebyshev polynomials, scaled to [a, b]): after m steps
+    the error is T_m((theta - M)/delta) / T_m(theta/delta) times the initial
+    error, M = D^-1 A, which is at most 1/T_m(theta/delta) on [a, b]."""
+    theta, delta, m = lv.cheb
+    dinv = 1.0 / lv.A.diagonal()
+    sigma = theta / delta
+    r = dinv * (b - lv.A @ x)                          # preconditioned residual
+    d = r / theta
+    x = x + d
+    rho_prev = 1.0 / sigma
+    for _ in range(1, m):
+        rho_k = 1.0 / (2.0 * sigma - rho_prev)
+        r = r - dinv * (lv.A @ d)
+        d = (rho_k * rho_prev) * d + (2.0 * rho_k / delta) * r
+        x = x + d
+        rho_prev = rho_k
+    return x
+
+
+def color_greedy(A: sp.csr_matrix, stream: int) -> np.ndarray:
+    """First-fit colouring of the graph of A (off-diagonal pattern): rows in
+    decreasing priority h_i = node_hash(i, stream) take the smallest colour no
+    neighbour already holds."""
+    n = A.shape[0]
+    prio = node_hash(np.arange(n), stream)
+    color = np.full(n, -1, dtype=np.int64)
+    for i in np.argsort(-prio.astype(np.int64), kind="stable"):
+        nb = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        used = set(int(c) for c in color[nb[nb != i]] if c >= 0)
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    return color
+
+
+def color_parallel(A: sp.csr_matrix, stream: int) -> tuple:
+    """The same colouring in synchronous rounds (Jones-Plassmann): in each
+    round every uncoloured row whose priority beats all its uncoloured
+    neighbours takes the smallest colour its coloured neighbours leave free.
+    Returns (colors, rounds)."""
+    n = A.shape[0]
+    prio = node_hash(np.arange(n), stream).astype(np.int64)
+    color = np.full(n, -1, dtype=np.int64)
+    rounds = 0
+    while np.any(color < 0):
+        rounds += 1
+        new = color.copy()
+        for i in np.flatnonzero(color < 0):
+            nb = A.indices[A.indptr[i]:A.indptr[i + 1]]
+            nb = nb[nb != i]
+            if np.any((color[nb] < 0) & (prio[nb] > prio[i])):
+                continue
+            used = set(int(c) for c in color[nb] if c >= 0)
+            c = 0
+            while c in used:
+                c += 1
+            new[i] = c
+        color = new
+    return color, rounds
+
+
+def sgs_smooth(lv: Level, b, x):
+    """Symmetric Gauss-Seidel in colour order: a forward sweep over the
+    colours (rows of one colour are not coupled, so each colour updates at
+    once: x_i += (b - A x)_i / a_ii), then a backward sweep."""
+    d = lv.A.diagonal()
+    ncol = int(lv.colors.max()) + 1
+    for c in list(range(ncol)) + list(range(ncol - 1, -1, -1)):
+        rows = np.flatnonzero(lv.colors == c)
+        x = x.copy()
+        x[rows] += (b[rows] - lv.A[rows] @ x) / d[rows]
+    return x
 
 
 def kcycle_coefficients(c, d, v, w, r, rt, variant: str):

@@ -439,3 +439,100 @@ def test_strong_graph_and_influence_on_nonsymmetric_strength():
     A2 = sp.csr_matrix(dense * np.array([1, -1, 1, 1])[:, None])
     A2.sort_indices()
     assert np.array_equal(O.strength(A2, 0.5), C)
+
+
+@pytest.mark.slow
+def test_table1_hierarchy_and_complexities():
+    """Paper Table 1 beyond level 1: levels 1-4 within 4 % of the printed
+    sizes and the operator complexity (sum of nnz over nnz_0 = 1.498 in the
+    table) within 1 %."""
+    table = [(1000000, 4996000), (274979, 1770339), (77433, 525877), (21823, 147803), (6150, 39298)]
+    A = P.aniso2d(1000, 1e-3)
+    H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(2))
+    for k in range(1, 5):
+        assert abs(H.levels[k].n - table[k][0]) <= 0.04 * table[k][0], k
+    paper_oc = (4996000 + 1770339 + 525877 + 147803 + 39298 + 5128 + 641) / 4996000
+    assert abs(O.operator_complexity(H) - paper_oc) <= 0.01 * paper_oc
+
+
+# --------------------------------------------------------------------------- MIS(k), k > 2
+
+def _check_misk(G, s, k):
+    roots = np.flatnonzero(s == 1)
+    n = G.shape[0]
+    near = np.full(n, 10 ** 9)
+    for r in roots:
+        d = _dist(G, r)
+        others = roots[roots != r]
+        assert np.all(d[others] > k), f"two MIS({k}) nodes within distance {k}"
+        near = np.minimum(near, d)
+    assert np.all(near <= k), f"a node farther than {k} from every MIS({k}) node"
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_misk_rounds_equal_greedy_and_are_misk(k):
+    """Section 2.1.2's MIS(k) with k sweeps per round of Algorithm 2 is the
+    sequential greedy MIS(k) by decreasing priority, and it is an MIS(k):
+    roots more than k apart, every node within k of one."""
+    rng = np.random.default_rng(30 + k)
+    for trial in range(80):
+        n = int(rng.integers(1, 60))
+        G = _random_graph(rng, n, float(rng.uniform(0.02, 0.2)))
+        v = O.priorities(rng.integers(0, 5, size=n), seed=trial)
+        s, _ = O.mis_parallel(G, v, k)
+        assert np.array_equal(s, O.mis_greedy(G, v, k))
+        _check_misk(G, s, k)
+
+
+def test_mis3_brute_force_tiny():
+    """The lexicographically largest distance-3-independent indicator (nodes by
+    decreasing v), found by enumeration."""
+    rng = np.random.default_rng(7)
+    for trial in range(40):
+        n = int(rng.integers(1, 11))
+        G = _random_graph(rng, n, float(rng.uniform(0.1, 0.5)))
+        v = O.priorities(rng.integers(0, 3, size=n), seed=200 + trial)
+        dist = np.array([_dist(G, i) for i in range(n)])
+        order = np.argsort(-v)
+        best = None
+        for mask in itertools.product([0, 1], repeat=n):
+            S = [i for i in range(n) if mask[i]]
+            if any(dist[a, b] <= 3 for a, b in itertools.combinations(S, 2)):
+                continue
+            key = tuple(mask[i] for i in order)
+            if best is None or key > best[0]:
+                best = (key, mask)
+        s, _ = O.mis_parallel(G, v, 3)
+        assert np.array_equal((s == 1).astype(int), np.array(best[1]))
+
+
+@pytest.mark.parametrize("k", [3, 4])
+def test_aggregate_nearest_root_distance_k(k):
+    rng = np.random.default_rng(40 + k)
+    for trial in range(50):
+        n = int(rng.integers(2, 60))
+        G = _random_graph(rng, n, float(rng.uniform(0.02, 0.15)))
+        v = O.priorities(rng.integers(0, 4, size=n), seed=trial)
+        s, _ = O.mis_parallel(G, v, k)
+        agg, nc = O.aggregate(G, s, v, k)
+        roots = np.flatnonzero(s == 1)
+        D = np.array([_dist(G, r) for r in roots])
+        for i in range(n):
+            dmin = D[:, i].min()
+            assert dmin <= k
+            cands = roots[D[:, i] == dmin]
+            assert agg[i] == np.flatnonzero(roots == cands[np.argmax(v[cands])])[0]
+
+
+def test_mis3_coarsens_faster_and_still_converges():
+    """Aggressive coarsening (Section 2.1.2): MIS(3) roots give larger
+    aggregates than MIS(2), and the solve still converges."""
+    A = P.poisson2d(64)
+    o2 = O.Options.for_dim(2, coarse_max=50)
+    o3 = O.Options.for_dim(2, coarse_max=50, mis_k=3)
+    l2 = O.coarsen_level(A.to_scipy(), np.ones(A.n), o2)
+    l3 = O.coarsen_level(A.to_scipy(), np.ones(A.n), o3)
+    assert l3.nc < 0.7 * l2.nc
+    H = O.setup(A.row_ptr, A.col, A.val, o3)
+    res = O.solve(H, P.rhs(A, P.exact_solution(A.n, 1)), 1e-8)
+    assert res.converged
