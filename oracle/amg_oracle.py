@@ -480,18 +480,61 @@ def setup(row_ptr, col, val, opts: Options | None = None) -> Hierarchy:
     Ac = levels[-1].A
     if Ac.shape[0] > opts.dense_max:
         raise OracleError("ECOARSEN", f"coarsest level has {Ac.shape[0]} unknowns")
-    dense = Ac.toarray()
-    if opts.krylov == "fcg":
+    coarse_factor(H)
+    return H
+
+
+def coarse_factor(H: Hierarchy) -> None:
+    """Dense factorisation of the coarsest matrix: Cholesky for the CG path
+    (LU when Cholesky fails), LU for the GMRES path."""
+    dense = H.levels[-1].A.toarray()
+    if H.opts.krylov == "fcg":
         try:
             H.coarse_factor = sla.cho_factor(dense, lower=True)
             H.coarse_kind = "cholesky"
+            return
         except np.linalg.LinAlgError:
-            H.coarse_factor = sla.lu_factor(dense)
-            H.coarse_kind = "lu"
-    else:
-        H.coarse_factor = sla.lu_factor(dense)
-        H.coarse_kind = "lu"
-    return H
+            pass
+    H.coarse_factor = sla.lu_factor(dense)
+    H.coarse_kind = "lu"
+
+
+def resetup(H: Hierarchy, val) -> Hierarchy:
+    """Numeric re-setup on a fixed pattern (Section 3.1: when only the values of
+    A_0 change, as across Newton steps, the sort and segmented-reduction indices
+    of the Galerkin product are stored and reused).  The aggregation of every
+    level (strength, MIS(2), aggregates) and P_k are kept; A_0 takes the new
+    values and, level by level, A_{k+1} = P_k^T A_k P_k is formed again with
+    the same P_k, followed by the level's Jacobi weight and finally the coarse
+    factorisation.  Returns a new hierarchy; H is left unchanged."""
+    opts = H.opts
+    A0 = H.levels[0].A
+    val = np.asarray(val, dtype=np.float64)
+    if val.shape != A0.data.shape:
+        raise OracleError("EINVAL", "new values do not match the pattern")
+    A = sp.csr_matrix((val.copy(), A0.indices.copy(), A0.indptr.copy()), shape=A0.shape)
+    validate_csr(A.indptr, A.indices, A.data)
+    levels = []
+    for old in H.levels[:-1]:
+        lv = Level(A=A, B=old.B, C=old.C, G=old.G, cnt=old.cnt, v=old.v, s=old.s, mis_rounds=old.mis_rounds,
+                   agg=old.agg, nc=old.nc, pval=old.pval, P=old.P, R=old.R)
+        lv.Ac = galerkin(A, lv.agg, lv.pval, lv.nc)
+        lv.Bc = old.Bc
+        lv.omega, lv.rho = jacobi_weight(A, opts.arnoldi_m, opts.seed + 1, opts.jacobi_scale)
+        lv.wdinv = lv.omega / A.diagonal()
+        lv.smoother = old.smoother
+        if lv.smoother == "chebyshev":
+            lv.cheb = chebyshev_interval(lv.rho, opts)
+        elif lv.smoother == "mcsgs":
+            lv.colors = old.colors                       # the graph of A_k is unchanged
+        levels.append(lv)
+        A = lv.Ac
+    levels.append(Level(A=A, B=H.levels[-1].B))
+    out = Hierarchy(levels=levels, opts=opts)
+    if A.shape[0] > opts.dense_max:
+        raise OracleError("ECOARSEN", f"coarsest level has {A.shape[0]} unknowns")
+    coarse_factor(out)
+    return out
 
 
 # ---------------------------------------------------------------------------
