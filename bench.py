@@ -275,6 +275,124 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
     return out
 
 
+def resetup_form(amg, torch, P, A, dev, dim, reps=3):
+    """Numeric re-setup (Section 3.1 index reuse) on the workload's pattern with
+    the coefficients of another field (seed 5): its time against a full setup,
+    then the solve with the re-set-up hierarchy."""
+    A2 = P.hetero3d(round(A.n ** (1.0 / 3.0)), seed=5) if dim == 3 else None
+    if A2 is None or A2.nnz != A.nnz or not np.array_equal(A2.col, A.col):
+        return None
+    v2 = torch.from_numpy(A2.val).cuda()
+    b2 = torch.from_numpy(P.rhs(A2, P.exact_solution(A2.n, 1))).cuda()
+    h = amg.setup(*dev, amg.Options(dim=dim))
+    setup_ms = h.timings()[0]
+    h.resetup(v2)                      # first call: also builds the term lists
+    first_ms = h.resetup_ms()
+    times = []
+    for _ in range(reps):
+        h.resetup(v2)
+        times.append(h.resetup_ms())
+    _, it, rel = amg.solve(h, b2, 1e-8)
+    solve_ms = h.timings()[1]
+    h.close()
+    h2 = amg.setup(dev[0], dev[1], v2, amg.Options(dim=dim))
+    _, it2, rel2 = amg.solve(h2, b2, 1e-8)
+    full2 = h2.timings()[0]
+    h2.close()
+    return {"workload": "pattern of the headline workload, coefficients of the seed-5 field",
+            "setup_ms": round(setup_ms, 3), "resetup_first_ms": round(first_ms, 3),
+            "resetup_ms": round(float(np.median(times)), 3),
+            "resetup_vs_setup": round(float(np.median(times)) / setup_ms, 4),
+            "iters_after_resetup": it, "relres": rel, "solve_ms": round(solve_ms, 3),
+            "fresh_setup_ms": round(full2, 3), "fresh_setup_iters": it2}
+
+
+GAMPACK_TABLE1 = [(1000000, 4996000), (274979, 1770339), (77433, 525877), (21823, 147803), (6150, 39298),
+                  (938, 5128), (169, 641)]
+
+
+def table1_form(amg, torch, P, eps_list=(1e-2, 1e-3, 1e-4)):
+    """Paper Table 1: the hierarchy of the 2-D anisotropic Poisson problem on a
+    1000 x 1000 grid (unknowns, nonzeros and nonzeros per row per level) for
+    several anisotropies, beside the printed unsmoothed-aggregation column."""
+    out = {"paper_unsmoothed_aggregation": [[n, z, round(z / n, 2)] for n, z in GAMPACK_TABLE1]}
+    for eps in eps_list:
+        A = P.aniso2d(1000, eps)
+        dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+        b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+        h = amg.setup(*dev, amg.Options(dim=2))
+        lv = []
+        for k in range(h.num_levels()):
+            info = h.level_info(k)
+            lv.append([info["n"], info["nnz"], round(info["nnz"] / info["n"], 2)])
+        _, it, rel = amg.solve(h, b, 1e-8)
+        s_ms, v_ms = h.timings()
+        h.close()
+        oc = sum(z for _, z, _ in lv) / lv[0][1]
+        out[f"eps={eps:g}"] = {"levels": lv, "operator_complexity": round(oc, 4), "iters": it, "relres": rel,
+                               "setup_ms": round(s_ms, 2), "solve_ms": round(v_ms, 2)}
+    out["paper_operator_complexity"] = round(sum(z for _, z in GAMPACK_TABLE1) / GAMPACK_TABLE1[0][1], 4)
+    return out
+
+
+def kcycle_ablation_form(amg, torch, P, names=("C2", "C3"), reps=3):
+    """K-cycle depth (Section 2.2: K-cycles on the top two levels only): the
+    number of K-cycle levels 0 (V-cycle only), 1, 2 and every level, FP64."""
+    out = {}
+    for name in names:
+        A, _, _ = P.config(name)
+        dim = WORKLOADS[name][1]
+        b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+        dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
+        res = {}
+        for kl in (0, 1, 2, 24):
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h = amg.setup(*dev, amg.Options(dim=dim, kcycle_levels=kl))
+                _, it, rel = amg.solve(h, b, 1e-8)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                s_ms, v_ms = h.timings()
+                h.close()
+                if best is None or t < best[0]:
+                    best = (t, it, rel, s_ms, v_ms)
+            res["all" if kl == 24 else str(kl)] = {
+                "iters": best[1], "relres": best[2], "setup_ms": round(best[3], 2), "solve_ms": round(best[4], 2),
+                "mdof_s": round(A.n / best[0] / 1e6, 2) if best[2] <= 1e-8 else 0.0}
+        out[name] = res
+        del dev
+    return out
+
+
+def misk_form(amg, torch, A, dev, dim, b, reps=3):
+    """MIS(k) aggressive coarsening (Section 2.1.2) on the headline workload:
+    levels, level-1 size, iterations and setup+solve time for k = 2, 3, 4."""
+    bt = torch.from_numpy(b).cuda()
+    out = {}
+    for k in (2, 3, 4):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = amg.setup(*dev, amg.Options(dim=dim, mis_k=k))
+            _, it, rel = amg.solve(h, bt, 1e-8)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            s_ms, v_ms = h.timings()
+            info = (h.num_levels(), h.level_info(0)["nc"],
+                    sum(h.level_info(q)["nnz"] for q in range(h.num_levels())) / A.nnz)
+            h.close()
+            if best is None or t < best[0]:
+                best = (t, it, rel, s_ms, v_ms, info)
+        out[f"k={k}"] = {"levels": best[5][0], "n1": best[5][1], "operator_complexity": round(best[5][2], 4),
+                         "iters": best[1], "relres": best[2], "setup_ms": round(best[3], 2),
+                         "solve_ms": round(best[4], 2),
+                         "mdof_s": round(A.n / best[0] / 1e6, 2) if best[2] <= 1e-8 else 0.0}
+    return out
+
+
 def cpu_info():
     """Host cores and CPU model of the machine the oracle runs on."""
     model = None
@@ -342,6 +460,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-spmv", action="store_true")
+    ap.add_argument("--no-resetup", action="store_true")
+    ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-misk", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched C4b form and print its JSON (for profiling)")
     ap.add_argument("--print-source-hash", action="store_true",
@@ -417,6 +539,20 @@ def main():
     if not args.no_learned:
         log("bench: learned smoother form (C5 -> C3)")
         forms["learned"] = learned_form(amg, torch, P)
+    if not args.no_resetup:
+        log("bench: numeric re-setup on the fixed pattern")
+        rs = resetup_form(amg, torch, P, A, dev, dim)
+        if rs is not None:
+            forms["resetup"] = rs
+    if not args.no_table1:
+        log("bench: Table 1 hierarchy (2-D anisotropic 1000^2)")
+        forms["table1"] = table1_form(amg, torch, P)
+    if not args.no_misk:
+        log("bench: MIS(k) aggressive coarsening")
+        forms["misk"] = misk_form(amg, torch, A, dev, dim, b)
+    if not args.no_ablation:
+        log("bench: K-cycle depth ablation")
+        forms["kcycle_depth"] = kcycle_ablation_form(amg, torch, P)
 
     # device copy bandwidth (reference for the attainable HBM rate): 1 GiB read + 1 GiB written
     src_c = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)

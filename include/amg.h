@@ -47,7 +47,15 @@ typedef enum {
 
 typedef enum { AMG_KRYLOV_FCG = 0, AMG_KRYLOV_FGMRES = 1 } amg_krylov;
 typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_MIXED = 1 } amg_precision;
-typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1 } amg_smoother;
+/* Smoothers: damped Jacobi (eq. damped_jacobi), learned per-row Jacobi weights
+ * (an extension), the Chebyshev polynomial smoother (Section 5) of degree
+ * cheb_degree on D^-1 A over [b / cheb_ratio, b], b = cheb_upper * the Arnoldi
+ * estimate of rho(D^-1 A), and multi-colour symmetric Gauss-Seidel (Section
+ * 2.2.1): rows coloured first-fit in decreasing node-hash priority (stream
+ * seed + 2; at most 64 colours), one sweep over the colours forward and one
+ * backward per smoothing step. */
+typedef enum { AMG_SMOOTHER_JACOBI = 0, AMG_SMOOTHER_LEARNED = 1, AMG_SMOOTHER_CHEBYSHEV = 2,
+               AMG_SMOOTHER_MCSGS = 3 } amg_smoother;
 /* Kernels that amg_probe_timing can report: the level-0 pre-smoothing plus
  * residual kernel (x = omega D^-1 b, r = b - A x), the level-0 residual plus
  * post-smoothing kernel, and the outer Krylov mat-vec q = A p. */
@@ -76,6 +84,12 @@ typedef struct {
   uint32_t flags;         /* AMG_FLAG_* bits (0) */
   const float* mlp_weights; /* (host) AMG_SMOOTHER_LEARNED: the 1409 FP32 weights of
                                amg_mlp_num_params(), copied during setup (NULL) */
+  int32_t mis_k;          /* roots form an MIS(k) (Section 2.1.2): 2 as Algorithm 2, up to
+                             8 for aggressive coarsening (k sweeps per round, nodes join the
+                             nearest root within distance k) (2) */
+  int32_t cheb_degree;    /* AMG_SMOOTHER_CHEBYSHEV: mat-vecs per smoothing step, 1..8 (2) */
+  double cheb_ratio;      /* AMG_SMOOTHER_CHEBYSHEV: damped interval [b / ratio, b] (4) */
+  double cheb_upper;      /* AMG_SMOOTHER_CHEBYSHEV: b = cheb_upper * rho(D^-1 A) estimate (1.1) */
 } amg_options;
 
 /* amg_options.flags: launch every kernel from the host instead of replaying
@@ -129,6 +143,26 @@ const char* amg_last_error(void);
  * Errors: EINVAL (structure, zero diagonal, nonsymmetric pattern), ENANINF,
  * ECOARSEN, ENOMEM, EHIP; *out is NULL on error.  Synchronises s. */
 int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_hierarchy** out);
+
+/* Numeric re-setup on a fixed pattern (Section 3.1: when only the values of
+ * A_0 change, as across the steps of a Newton iteration, the indices of the
+ * Galerkin product are stored and reused).  val: device float64[nnz], the new
+ * values of A_0 on the pattern given to amg_setup (same row_ptr, col_idx).
+ * Every level keeps its strength mask, MIS(2) state, aggregates and P_k;
+ * A_{k+1} = P_k^T A_k P_k is formed again from term lists that the first call
+ * stores (8 bytes per stored entry of each non-coarsest level, kept until
+ * amg_destroy), then every level's damped Jacobi weight (eq. damped_jacobi,
+ * Arnoldi estimate) and the coarsest inverse; the autotuned kernels stay.
+ * Without AMG_FLAG_BORROW_A the values are copied (the caller may free val
+ * after the call); with it, level 0 reads val from then on, which must stay
+ * allocated and unchanged until amg_destroy or the next amg_resetup.
+ * Errors: EINVAL (zero diagonal), ENANINF, EBREAKDOWN (spectral estimate),
+ * EUNSUPPORTED (batched hierarchy, learned smoother), ENOMEM, EHIP; after an
+ * error the hierarchy is only fit for amg_destroy.  Synchronises s. */
+int32_t amg_resetup(amg_hierarchy* h, const double* val, hipStream_t s);
+
+/* (host) duration in ms of the last amg_resetup, from HIP events on its stream. */
+int32_t amg_resetup_time(const amg_hierarchy* h, double* ms);
 
 /* Outer Krylov solve of A x = b to ||b - A x|| <= rtol ||b|| from x_0 = 0,
  * preconditioned by one cycle (Algorithms 4 and 5 with the K-cycle on the
@@ -251,6 +285,11 @@ int32_t amg_mlp_adam(float* w, float* m, float* v, const float* g, int32_t n, in
  * the learned weights (0 when not evaluated). */
 int32_t amg_level_smoother(const amg_hierarchy* h, int32_t k, int32_t* learned, double* loss_plain,
                            double* loss_learned);
+
+/* (host) the multi-colour ordering of level k (AMG_SMOOTHER_MCSGS): colors
+ * int32[n_k] (may be NULL) and *ncolors (may be NULL).  EINVAL when the
+ * hierarchy does not smooth by colours or k has no smoother. */
+int32_t amg_level_colors(const amg_hierarchy* h, int32_t k, int32_t* colors, int32_t* ncolors);
 
 /* (host) copy of omega_i / a_ii, the Jacobi scaling the cycle applies on level k. */
 int32_t amg_export_jacobi(const amg_hierarchy* h, int32_t k, double* wdinv);

@@ -16,6 +16,7 @@ AMG_EBREAKDOWN, AMG_ECOARSEN, AMG_ENANINF, AMG_EUNSUPPORTED = 5, 6, 7, 8
 _PREC = {"fp64": 0, "mixed": 1}
 _PROBE = {"none": 0, "l0_presmooth": 1, "l0_postsmooth": 2, "outer_spmv": 3}
 _KRYLOV = {"fcg": 0, "fgmres": 1}
+_SMOOTHER = {"jacobi": 0, "learned": 1, "chebyshev": 2, "mcsgs": 3}
 FLAG_NO_GRAPH, FLAG_NO_TUNE, FLAG_LEARNED_ALWAYS, FLAG_BORROW_A = 1, 2, 8, 16
 
 EXPORTED = [
@@ -25,7 +26,7 @@ EXPORTED = [
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
     "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
-    "amg_setup_phases",
+    "amg_setup_phases", "amg_resetup", "amg_resetup_time", "amg_level_colors",
 ]
 
 
@@ -36,7 +37,8 @@ class AmgOptionsC(C.Structure):
         ("arnoldi_m", C.c_int32), ("seed", C.c_uint32), ("krylov", C.c_int32),
         ("gmres_restart", C.c_int32), ("precision", C.c_int32), ("smoother", C.c_int32),
         ("max_iter", C.c_int32), ("dense_max", C.c_int32), ("probe", C.c_int32), ("check_every", C.c_int32),
-        ("flags", C.c_uint32), ("mlp_weights", C.c_void_p),
+        ("flags", C.c_uint32), ("mlp_weights", C.c_void_p), ("mis_k", C.c_int32), ("cheb_degree", C.c_int32),
+        ("cheb_ratio", C.c_double), ("cheb_upper", C.c_double),
     ]
 
 
@@ -96,6 +98,12 @@ def lib():
     L.amg_node_hash.restype = i32
     L.amg_galerkin.argtypes = [P(AmgCsrC), vp, vp, i32, P(i32), vp, vp, vp, i32, vp]
     L.amg_galerkin.restype = i32
+    L.amg_resetup.argtypes = [vp, vp, vp]
+    L.amg_resetup.restype = i32
+    L.amg_resetup_time.argtypes = [vp, P(dbl)]
+    L.amg_resetup_time.restype = i32
+    L.amg_level_colors.argtypes = [vp, i32, vp, P(i32)]
+    L.amg_level_colors.restype = i32
     L.amg_hessenberg_radius.argtypes = [vp, i32, P(dbl)]
     L.amg_hessenberg_radius.restype = i32
     L.amg_timings.argtypes = [vp, P(dbl), P(dbl)]
@@ -200,6 +208,8 @@ class Options:
                 v = _KRYLOV[v]
             if k == "probe" and isinstance(v, str):
                 v = _PROBE[v]
+            if k == "smoother" and isinstance(v, str):
+                v = _SMOOTHER[v]
             if not hasattr(self.c, k):
                 raise KeyError(k)
             setattr(self.c, k, v)
@@ -284,6 +294,17 @@ class Hierarchy:
         _check(lib().amg_timings(self._h, C.byref(s), C.byref(v)))
         return s.value, v.value
 
+    def resetup(self, val):
+        """amg_resetup: new values of A_0 (device float64[nnz]) on the same pattern."""
+        _check(lib().amg_resetup(self._h, _ptr(val), _stream()))
+        if self._keep is not None and self.opts.c.flags & FLAG_BORROW_A:
+            self._keep = (self._keep[0], self._keep[1], val)   # level 0 now reads these values
+
+    def resetup_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().amg_resetup_time(self._h, C.byref(ms)))
+        return ms.value
+
     def setup_phases(self):
         """(autotuner ms, graph capture ms) of the last setup (host wall clock)."""
         t, g = C.c_double(), C.c_double()
@@ -295,6 +316,13 @@ class Hierarchy:
         l, a, b = C.c_int32(), C.c_double(), C.c_double()
         _check(lib().amg_level_smoother(self._h, k, C.byref(l), C.byref(a), C.byref(b)))
         return bool(l.value), a.value, b.value
+
+    def level_colors(self, k: int):
+        """(colour of every row, number of colours) of level k (MC-SGS smoother)."""
+        out = np.empty(self.level_info(k)["n"], np.int32)
+        nc = C.c_int32()
+        _check(lib().amg_level_colors(self._h, k, _nptr(out), C.byref(nc)))
+        return out, nc.value
 
     def jacobi_weights(self, k: int) -> np.ndarray:
         """omega_i / a_ii of level k (host copy)."""

@@ -40,6 +40,7 @@ enum : int {
   kErrBadColumn = 128,
   kErrCrossSystem = 256,
   kErrNotSPD = 512,
+  kErrColors = 1024,
 };
 
 // ---------------------------------------------------------------- memory
@@ -149,6 +150,24 @@ struct Level {
   double* tinv = nullptr;      // row-major dense inverses of the terminal systems
   float* tinv32 = nullptr;
   std::vector<double> sys_omega, sys_rho;
+  // Chebyshev smoother: device coefficients [1/theta, (c1, c2) per later
+  // step] and its vectors (cycle precision, size n): residual, two directions
+  double* cheb = nullptr;
+  double cheb_host[16] = {};
+  void* cr = nullptr;
+  void* cd0 = nullptr;
+  void* cd1 = nullptr;
+  // multi-colour Gauss-Seidel smoother: colour of every row and the rows of
+  // colour c at crow[coff[c] .. coff[c+1]) (coff on the host)
+  int* colors = nullptr;
+  int* crow = nullptr;
+  std::vector<int> coff;
+  // numeric re-setup (built by the first amg_resetup): the terms of every
+  // entry c of A_{k+1} in segment order at rs_tptr[c] .. rs_tptr[c+1]: fine
+  // entry rs_f[t] of fine row rs_i[t]
+  int* rs_tptr = nullptr;
+  int* rs_f = nullptr;
+  int* rs_i = nullptr;
 };
 
 // A system whose coarsest level is a given level: its rows there and the
@@ -196,7 +215,7 @@ struct Hierarchy {
   hipEvent_t pev[2] = {nullptr, nullptr};   // around the probed kernel
   double probe_ms = 0.0;
   int probe_samples = 0;
-  float setup_ms = 0.f, solve_ms = 0.f;
+  float setup_ms = 0.f, solve_ms = 0.f, resetup_ms = 0.f;
   double tune_ms = 0.0, capture_ms = 0.0;   // host time of the autotuner and of the graph capture in setup
   // batched systems: count (0 = one system), per-system control of the solve
   // and the results of the last solve
@@ -290,6 +309,12 @@ void launch_mis_lists(int n, const int* gptr, const int* gcol, const uint64_t* T
 void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, int* mc, int round,
                       int lanes, hipStream_t s,
                       const MisLists* ml = nullptr);
+// MIS(k), k > 2: one round of k sweeps (M1 as in MIS(2); Ma, Mb scratch), and
+// the k-round nearest-root aggregation (choice, choice2 scratch)
+void launch_misk_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, uint64_t* Ma,
+                       uint64_t* Mb, int* mc, int round, int k, int lanes, hipStream_t s);
+void launch_aggregate_k(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
+                        int k, int* choice, int* choice2, int* agg, int* err, hipStream_t s);
 void launch_root_flags(int n, const uint64_t* T, int* flags, hipStream_t s);
 void launch_aggregate(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
                       int* choice, int* agg, int* err, hipStream_t s);
@@ -386,10 +411,24 @@ void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, c
               int lpr, hipStream_t s);
 int pick_lanes_per_row(int n, int nnz);
 
+// resetup.hip: numeric re-setup on a fixed pattern
+void launch_rs_count(const Level& lv, const Level& lc, int* cnt, int* err, hipStream_t s);
+void launch_rs_fill(const Level& lv, const Level& lc, int* cur, int* tf, int* ti, int* err, hipStream_t s);
+void launch_rs_values(const Level& lv, Level& lc, hipStream_t s);
+void launch_rs_diag(const Level& lv, hipStream_t s);
+void launch_rs_sell_values(const Level& lv, hipStream_t s);
+void launch_set16(double* dst, const double* host16, hipStream_t s);
+// coloring.hip: first-fit colouring by node-hash priority in synchronous rounds
+void launch_color_round(int n, const int* rp, const int* ci, uint32_t stream, const int* cin, int* cout, int* left,
+                        int round, int* err, hipStream_t s);
+void launch_color_count(int n, const int* col, int* cnt, hipStream_t s);
+void launch_color_lists(int n, const int* col, int* cnt, const int* coff, int* crow, hipStream_t s);
+
 // host runtime (hierarchy.cpp)
 double hessenberg_spectral_radius(const double* H, int m);
 void init_control(Hierarchy& h);
 void build_hierarchy(Hierarchy& h, const amg_csr& A);
+void resetup_hierarchy(Hierarchy& h, const double* val);
 size_t release_cached_chunks();
 void galerkin_standalone(Hierarchy& h, const amg_csr& A, const int* agg, const double* pval, int nc,
                          int* nnz_c, int** rp_c, int** ci_c, double** val_c);

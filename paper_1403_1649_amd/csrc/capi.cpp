@@ -72,6 +72,10 @@ void amg_default_options(amg_options* opt, int32_t dim) {
   opt->check_every = 16;
   opt->flags = 0;
   opt->mlp_weights = nullptr;
+  opt->mis_k = 2;
+  opt->cheb_degree = 2;
+  opt->cheb_ratio = 4.0;
+  opt->cheb_upper = 1.1;
 }
 
 const char* amg_status_string(int32_t status) {
@@ -105,11 +109,17 @@ int32_t amg_setup(const amg_csr* A, const amg_options* opt, hipStream_t s, amg_h
   if (o.gmres_restart < 1 || o.gmres_restart > 64) return fail(AMG_EINVAL, "amg_setup: gmres_restart in [1, 64]");
   if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_MIXED)
     return fail(AMG_EINVAL, "amg_setup: unknown precision");
-  if (o.smoother != AMG_SMOOTHER_JACOBI && o.smoother != AMG_SMOOTHER_LEARNED)
+  if (o.smoother != AMG_SMOOTHER_JACOBI && o.smoother != AMG_SMOOTHER_LEARNED &&
+      o.smoother != AMG_SMOOTHER_CHEBYSHEV && o.smoother != AMG_SMOOTHER_MCSGS)
     return fail(AMG_EINVAL, "amg_setup: smoother");
+  if (o.smoother == AMG_SMOOTHER_CHEBYSHEV &&
+      (o.cheb_degree < 1 || o.cheb_degree > 8 || !(o.cheb_ratio > 1.0) || !(o.cheb_upper > 0.0) ||
+       !std::isfinite(o.cheb_ratio) || !std::isfinite(o.cheb_upper)))
+    return fail(AMG_EINVAL, "amg_setup: Chebyshev degree in [1, 8], ratio > 1, upper > 0");
   if (o.smoother == AMG_SMOOTHER_LEARNED && !o.mlp_weights)
     return fail(AMG_EINVAL, "amg_setup: the learned smoother needs mlp_weights");
   if (o.probe < AMG_PROBE_NONE || o.probe > AMG_PROBE_OUTER_SPMV) return fail(AMG_EINVAL, "amg_setup: probe");
+  if (o.mis_k < 2 || o.mis_k > 8) return fail(AMG_EINVAL, "amg_setup: mis_k in [2, 8]");
   auto* H = new (std::nothrow) amg_hierarchy();
   if (!H) return fail(AMG_ENOMEM, "amg_setup: host allocation");
   int32_t st = guarded("amg_setup", [&] {
@@ -154,6 +164,7 @@ int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off
   if (o.smoother != AMG_SMOOTHER_JACOBI)
     return fail(AMG_EUNSUPPORTED, "amg_setup_batched: batches use the damped Jacobi smoother");
   if (o.probe != AMG_PROBE_NONE) return fail(AMG_EUNSUPPORTED, "amg_setup_batched: no kernel probe in batches");
+  if (o.mis_k != 2) return fail(AMG_EUNSUPPORTED, "amg_setup_batched: batches use MIS(2)");
   auto* H = new (std::nothrow) amg_hierarchy();
   if (!H) return fail(AMG_ENOMEM, "amg_setup_batched: host allocation");
   int32_t st = guarded("amg_setup_batched", [&] {
@@ -219,6 +230,21 @@ int32_t amg_batch_level(const amg_hierarchy* H, int32_t k, int32_t* sys_off, dou
   return AMG_OK;
 }
 
+int32_t amg_resetup(amg_hierarchy* H, const double* val, hipStream_t s) {
+  if (!H || !val) return fail(AMG_EINVAL, "amg_resetup: NULL argument");
+  amg::Hierarchy& h = H->h;
+  if (h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_resetup: batched hierarchy");
+  if (h.opt.smoother == AMG_SMOOTHER_LEARNED) return fail(AMG_EUNSUPPORTED, "amg_resetup: learned smoother");
+  return guarded("amg_resetup", [&] {
+    h.stream = s;
+    AMG_HIP(hipEventRecord(h.ev[0], s));
+    amg::resetup_hierarchy(h, val);
+    AMG_HIP(hipEventRecord(h.ev[1], s));
+    AMG_HIP(hipEventSynchronize(h.ev[1]));
+    AMG_HIP(hipEventElapsedTime(&h.resetup_ms, h.ev[0], h.ev[1]));
+  });
+}
+
 int32_t amg_solve(amg_hierarchy* H, const double* b, double rtol, double* x, int32_t* iters, double* relres,
                   hipStream_t s) {
   if (!H || !b || !x || !iters || !relres) return fail(AMG_EINVAL, "amg_solve: NULL argument");
@@ -258,6 +284,8 @@ int32_t amg_solve_multi(amg_hierarchy* H, int32_t nrhs, const double* B, double 
   if (nrhs < 1 || nrhs > 64) return fail(AMG_EINVAL, "amg_solve_multi: nrhs must be in [1, 64]");
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(AMG_EINVAL, "amg_solve_multi: rtol must be positive");
   if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_solve_multi: batched hierarchy");
+  if (H->h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV || H->h.opt.smoother == AMG_SMOOTHER_MCSGS)
+    return fail(AMG_EUNSUPPORTED, "amg_solve_multi: the block cycle smooths by Jacobi only");
   int32_t status = AMG_OK;
   int32_t st = guarded("amg_solve_multi", [&] {
     amg::Hierarchy& h = H->h;
@@ -396,6 +424,12 @@ int32_t amg_timings(const amg_hierarchy* H, double* setup_ms, double* solve_ms) 
   return AMG_OK;
 }
 
+int32_t amg_resetup_time(const amg_hierarchy* H, double* ms) {
+  if (!H || !ms) return fail(AMG_EINVAL, "amg_resetup_time: NULL argument");
+  *ms = H->h.resetup_ms;
+  return AMG_OK;
+}
+
 int32_t amg_setup_phases(const amg_hierarchy* H, double* tune_ms, double* capture_ms) {
   if (!H) return fail(AMG_EINVAL, "amg_setup_phases: NULL hierarchy");
   if (tune_ms) *tune_ms = H->h.tune_ms;
@@ -477,6 +511,19 @@ int32_t amg_level_smoother(const amg_hierarchy* H, int32_t k, int32_t* learned, 
   if (loss_plain) *loss_plain = lv.loss_plain;
   if (loss_learned) *loss_learned = lv.loss_learned;
   return AMG_OK;
+}
+
+int32_t amg_level_colors(const amg_hierarchy* H, int32_t k, int32_t* colors, int32_t* ncolors) {
+  if (!H || k < 0 || k >= (int32_t)H->h.levels.size() - 1) return fail(AMG_EINVAL, "amg_level_colors: level");
+  const amg::Level& lv = H->h.levels[k];
+  if (!lv.colors) return fail(AMG_EINVAL, "amg_level_colors: no colour ordering on this hierarchy");
+  return guarded("amg_level_colors", [&] {
+    if (ncolors) *ncolors = (int32_t)lv.coff.size() - 1;
+    if (colors) {
+      AMG_HIP(hipStreamSynchronize(H->h.stream));
+      AMG_HIP(hipMemcpy(colors, lv.colors, (size_t)lv.n * sizeof(int), hipMemcpyDeviceToHost));
+    }
+  });
 }
 
 int32_t amg_export_jacobi(const amg_hierarchy* H, int32_t k, double* wdinv) {

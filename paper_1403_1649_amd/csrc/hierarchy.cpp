@@ -215,9 +215,10 @@ struct Sync {
     if (e & kErrBadColumn) throw Error(AMG_EINVAL, "column index out of range or not strictly increasing");
     if (e & kErrNonSymPattern) throw Error(AMG_EINVAL, "sparsity pattern is not structurally symmetric");
     if (e & kErrCountOverflow) throw Error(AMG_EINVAL, "strong influence count exceeds 2^21");
-    if (e & kErrUnassigned) throw Error(AMG_ECOARSEN, "node farther than 2 from every MIS(2) node");
+    if (e & kErrUnassigned) throw Error(AMG_ECOARSEN, "node farther than k from every MIS(k) node");
     if (e & kErrSingular) throw Error(AMG_EBREAKDOWN, "coarsest matrix is singular");
     if (e & kErrCrossSystem) throw Error(AMG_EINVAL, "a matrix entry couples two systems of the batch");
+    if (e & kErrColors) throw Error(AMG_EUNSUPPORTED, "the multi-colour ordering needs more than 64 colours");
     throw Error(AMG_EHIP, "device error bits " + std::to_string(e));
   }
   // true (and the bit cleared) when the SPD elimination met a non-positive pivot
@@ -242,6 +243,11 @@ void alloc_solve_vectors(Hierarchy& h) {
     lv.xt = h.arena.alloc(n * es);
     lv.rc = h.arena.alloc(nc * es);
     lv.c = h.arena.alloc(nc * es);
+    if (h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV) {
+      lv.cr = h.arena.alloc(n * es);
+      lv.cd0 = h.arena.alloc(n * es);
+      lv.cd1 = h.arena.alloc(n * es);
+    }
     if (k < h.opt.kcycle_levels) {
       lv.v = h.arena.alloc(nc * es);
       lv.rt = h.arena.alloc(nc * es);
@@ -435,7 +441,102 @@ static void set_jacobi_weight(Hierarchy& h, Level& lv, int m, const double* Hh, 
   lv.rho = hessenberg_spectral_radius(Hs, size);
   if (!(lv.rho > 0.0) || !std::isfinite(lv.rho)) throw Error(AMG_EBREAKDOWN, "spectral radius estimate not positive");
   lv.omega = h.opt.jacobi_scale / lv.rho;
+  if (h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV) {
+    // the polynomial acts on D^-1 A: the scaling is 1 / a_ii; the interval
+    // [b / ratio, b] around the estimate, b = upper * rho, gives the
+    // recurrence coefficients (centre theta, half-width delta)
+    const double bb = h.opt.cheb_upper * lv.rho, aa = bb / h.opt.cheb_ratio;
+    const double theta = 0.5 * (bb + aa), delta = 0.5 * (bb - aa), sigma = theta / delta;
+    double* c = lv.cheb_host;
+    c[0] = 1.0 / theta;
+    double rho_prev = 1.0 / sigma;
+    for (int j = 1; j < h.opt.cheb_degree; ++j) {
+      const double rj = 1.0 / (2.0 * sigma - rho_prev);
+      c[2 * j - 1] = rj * rho_prev;
+      c[2 * j] = 2.0 * rj / delta;
+      rho_prev = rj;
+    }
+    if (!lv.cheb) lv.cheb = h.arena.alloc_n<double>(16);
+    launch_set16(lv.cheb, c, h.stream);
+    launch_jacobi_weights(lv.n, 1.0, lv.diag, lv.wdinv, lv.wdinv32, h.stream);
+    return;
+  }
+  if (h.opt.smoother == AMG_SMOOTHER_MCSGS) {   // Gauss-Seidel divides by a_ii
+    launch_jacobi_weights(lv.n, 1.0, lv.diag, lv.wdinv, lv.wdinv32, h.stream);
+    return;
+  }
   launch_jacobi_weights(lv.n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, h.stream);
+}
+
+// Dense inverse of the coarsest level (allocated on the first call): flexible
+// CG assumes a symmetric positive definite operator, so blocked elimination
+// without pivoting, unless a pivot says otherwise; partial pivoting for
+// FGMRES or a non-positive pivot.
+static void coarse_inverse(Hierarchy& h, Arena& tmp, Sync& sy) {
+  hipStream_t s = h.stream;
+  const amg_options& o = h.opt;
+  Level& cl = h.levels.back();
+  if (cl.n > o.dense_max)
+    throw Error(AMG_ECOARSEN, "coarsest level has " + std::to_string(cl.n) + " unknowns");
+  const size_t nn = (size_t)cl.n * cl.n;
+  double* work = tmp.alloc_n<double>(2 * nn + 2 * (size_t)cl.n);
+  int* gj_sync = tmp.alloc_n<int>(4 + cl.n);
+  if (!h.cinv) {
+    h.cinv = h.arena.alloc_n<double>(nn);
+    if (h.mixed()) h.cinv32 = h.arena.alloc_n<float>(nn);
+  }
+  bool inverted = false;
+  if (o.krylov == AMG_KRYLOV_FCG) {
+    const TermInfo t{0, 0, cl.n, 0, 0};
+    TermInfo* dt = tmp.alloc_n<TermInfo>(1);
+    AMG_HIP(hipMemcpyAsync(dt, &t, sizeof(TermInfo), hipMemcpyHostToDevice, s));
+    launch_dense_inverse_spd(1, dt, &t, cl.n, cl.rp, cl.ci, cl.val, h.cinv, h.cinv32, tmp, h.d_err, s);
+    inverted = !sy.take_not_spd();
+  }
+  if (!inverted) launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
+}
+
+// Multi-colour ordering of level k (symmetric Gauss-Seidel smoother): rounds
+// of first-fit colouring by node-hash priority (stream seed + 2) until every
+// row has a colour, then the rows of each colour listed together.
+static void color_level(Hierarchy& h, Arena& tmp, Level& lv, Sync& sy) {
+  hipStream_t s = h.stream;
+  const int n = lv.n;
+  int* in = tmp.alloc_n<int>(n);
+  int* out = tmp.alloc_n<int>(n);
+  int* left = tmp.alloc_n<int>(2);
+  launch_fill_int(n, in, -1, s);
+  launch_fill_int(2, left, 0, s);
+  int round = 0;
+  while (true) {
+    for (int b = 0; b < 4; ++b, ++round) {
+      launch_color_round(n, lv.rp, lv.ci, h.opt.seed + 2, in, out, left, round, h.d_err, s);
+      std::swap(in, out);
+    }
+    sy.fetch(left + ((round - 1) & 1), 0);
+    sy.wait_and_check();
+    if (sy.hp()[0] == 0) break;
+    if (round > 100000) throw Error(AMG_ECOARSEN, "colouring rounds did not terminate");
+  }
+  lv.colors = h.arena.alloc_n<int>(n);
+  AMG_HIP(hipMemcpyAsync(lv.colors, in, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+  int* cnt = tmp.alloc_n<int>(64);
+  launch_fill_int(64, cnt, 0, s);
+  launch_color_count(n, lv.colors, cnt, s);
+  int hc[64];
+  AMG_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  int nc = 0;
+  for (int c = 0; c < 64; ++c)
+    if (hc[c] > 0) nc = c + 1;
+  lv.coff.assign(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) lv.coff[c + 1] = lv.coff[c] + hc[c];
+  int* dcoff = tmp.alloc_n<int>(nc + 1);
+  AMG_HIP(hipMemcpyAsync(dcoff, lv.coff.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  lv.crow = h.arena.alloc_n<int>(n);
+  launch_fill_int(64, cnt, 0, s);
+  launch_color_lists(n, lv.colors, cnt, dcoff, lv.crow, s);
+  AMG_HIP(hipStreamSynchronize(s));   // the host offsets array is read by the copy above
 }
 
 void build_hierarchy(Hierarchy& h, const amg_csr& A) {
@@ -529,9 +630,12 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     int* gcol = tmp.alloc_n<int>(nnz > 0 ? nnz : 1);
     launch_graph_fill(n, nnz, lv.rp, lv.ci, gmask, gptr, gcol, s);
 
-    // MIS(2) rounds (Algorithm 2)
+    // MIS(2) rounds (Algorithm 2); MIS(k) with k sweeps per round (Section 2.1.2)
+    const int mk = o.mis_k;
     lv.tuple = h.arena.alloc_n<uint64_t>(n);
     uint64_t* M1 = tmp.alloc_n<uint64_t>(n);
+    uint64_t* Ma = mk > 2 ? tmp.alloc_n<uint64_t>(n) : nullptr;
+    uint64_t* Mb = mk > 3 ? tmp.alloc_n<uint64_t>(n) : nullptr;
     launch_mis_init(n, cnt, o.seed, lv.tuple, M1, h.d_mis, h.d_err, s);
     int round = 0;
     int batch = 8;   // rounds between read-backs: a round after the last exits at entry
@@ -541,8 +645,10 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     MisLists ml{};
     bool lists = false;   // late rounds sweep only the nodes that can still change
     while (true) {
-      for (int b = 0; b < batch; ++b, ++round)
-        launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s, lists ? &ml : nullptr);
+      for (int b = 0; b < batch; ++b, ++round) {
+        if (mk == 2) launch_mis_round(n, gptr, gcol, lv.tuple, M1, h.d_mis, round, glanes, s, lists ? &ml : nullptr);
+        else launch_misk_round(n, gptr, gcol, lv.tuple, M1, Ma, Mb, h.d_mis, round, mk, glanes, s);
+      }
       if (arn_due) {   // its eigenvalues on the host while the rounds run
         take_arnoldi();
         arn_due = false;
@@ -558,7 +664,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       if (sy.hp()[0] == 0) break;
       if (round > 4096) throw Error(AMG_ECOARSEN, "MIS(2) rounds did not terminate");
       batch = 4;
-      if (!lists && n > kMisListRows) {
+      if (!lists && mk == 2 && n > kMisListRows) {
         ml.fnear = tmp.alloc_n<int>(n);
         ml.pnear = tmp.alloc_n<int>((size_t)n + 1);
         ml.near = tmp.alloc_n<int>(n);
@@ -588,7 +694,12 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     }
     int* choice = tmp.alloc_n<int>(n);
     lv.agg = h.arena.alloc_n<int>(n);
-    launch_aggregate(n, nnzg, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    if (mk == 2) {
+      launch_aggregate(n, nnzg, gptr, gcol, lv.tuple, root_id, choice, lv.agg, h.d_err, s);
+    } else {
+      int* choice2 = tmp.alloc_n<int>(n);
+      launch_aggregate_k(n, nnzg, gptr, gcol, lv.tuple, root_id, mk, choice, choice2, lv.agg, h.d_err, s);
+    }
     lv.nc = nc;
     lv.agg_ptr = h.arena.alloc_n<int>(nc + 1);
     lv.agg_rows = h.arena.alloc_n<int>(n);
@@ -649,26 +760,9 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
     h.levels.push_back(lc);
   }
 
-  // coarsest level: dense inverse
-  Level& cl = h.levels.back();
-  if (cl.n > o.dense_max)
-    throw Error(AMG_ECOARSEN, "coarsest level has " + std::to_string(cl.n) + " unknowns");
-  const size_t nn = (size_t)cl.n * cl.n;
-  double* work = tmp.alloc_n<double>(2 * nn + 2 * (size_t)cl.n);
-  int* gj_sync = tmp.alloc_n<int>(4 + cl.n);
-  h.cinv = h.arena.alloc_n<double>(nn);
-  if (h.mixed()) h.cinv32 = h.arena.alloc_n<float>(nn);
-  // flexible CG assumes a symmetric positive definite operator: blocked
-  // elimination without pivoting, unless a pivot says otherwise
-  bool inverted = false;
-  if (o.krylov == AMG_KRYLOV_FCG) {
-    const TermInfo t{0, 0, cl.n, 0, 0};
-    TermInfo* dt = tmp.alloc_n<TermInfo>(1);
-    AMG_HIP(hipMemcpyAsync(dt, &t, sizeof(TermInfo), hipMemcpyHostToDevice, s));
-    launch_dense_inverse_spd(1, dt, &t, cl.n, cl.rp, cl.ci, cl.val, h.cinv, h.cinv32, tmp, h.d_err, s);
-    inverted = !sy.take_not_spd();
-  }
-  if (!inverted) launch_dense_inverse(cl.n, cl.rp, cl.ci, cl.val, work, h.cinv, h.cinv32, gj_sync, h.d_err, s);
+  coarse_inverse(h, tmp, sy);
+  if (o.smoother == AMG_SMOOTHER_MCSGS)
+    for (int k = 0; k < h.L(); ++k) color_level(h, tmp, h.levels[k], sy);
   if (h.mixed()) make_float_copies(h);
   alloc_solve_vectors(h);
   for (int k = 0; k < h.L(); ++k)
@@ -686,6 +780,76 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   }
   if (!(o.flags & AMG_FLAG_NO_GRAPH) && o.krylov == AMG_KRYLOV_FCG) build_solve_graphs(h);
   h.capture_ms = std::chrono::duration<double, std::milli>(clk::now() - t_graph).count();
+}
+
+
+// Numeric re-setup on the fixed pattern (Section 3.1, index reuse): new
+// values of A_0; every level keeps its strength, MIS(2), aggregates and P_k;
+// A_{k+1} is replayed from the stored term lists (built by the first call),
+// then the diagonals, the sliced-ELL values and FP32 copies, each level's
+// Jacobi weight (Arnoldi) and the coarse inverse are formed again.  The
+// autotuned kernels and the captured solve graphs stay; with a borrowed A_0
+// given at a new address the graphs are captured again.
+void resetup_hierarchy(Hierarchy& h, const double* val) {
+  hipStream_t s = h.stream;
+  const amg_options& o = h.opt;
+  Sync sy{h};
+  Arena tmp;
+  struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
+  Level& l0 = h.levels[0];
+  bool repoint = false;
+  if (o.flags & AMG_FLAG_BORROW_A) {
+    if (val != l0.val) {
+      l0.val = const_cast<double*>(val);
+      repoint = true;
+    }
+  } else if (val != l0.val) {
+    AMG_HIP(hipMemcpyAsync(l0.val, val, (size_t)l0.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  launch_check_matrix(l0.n, l0.rp, l0.ci, l0.val, h.d_err, s);
+  sy.wait_and_check();
+  const int L = h.L();
+  for (int k = 0; k < L; ++k) {   // term lists in segment order, once per hierarchy
+    Level& lv = h.levels[k];
+    Level& lc = h.levels[k + 1];
+    if (lv.rs_tptr) continue;
+    int* cnt = tmp.alloc_n<int>(lc.nnz > 0 ? lc.nnz : 1);
+    launch_fill_int(lc.nnz, cnt, 0, s);
+    launch_rs_count(lv, lc, cnt, h.d_err, s);
+    lv.rs_tptr = h.arena.alloc_n<int>((size_t)lc.nnz + 1);
+    scan_to_ptr(cnt, lv.rs_tptr, lc.nnz, h.scan, s);
+    lv.rs_f = h.arena.alloc_n<int>(lv.nnz);
+    lv.rs_i = h.arena.alloc_n<int>(lv.nnz);
+    launch_fill_int(lc.nnz, cnt, 0, s);
+    launch_rs_fill(lv, lc, cnt, lv.rs_f, lv.rs_i, h.d_err, s);
+  }
+  for (int k = 0; k < L; ++k) launch_rs_values(h.levels[k], h.levels[k + 1], s);
+  for (int k = 0; k <= L; ++k) {
+    Level& lv = h.levels[k];
+    launch_rs_diag(lv, s);
+    launch_rs_sell_values(lv, s);
+    if (h.mixed()) launch_to_float(lv.nnz, lv.val, lv.val32, s);
+  }
+  sy.wait_and_check();
+  for (int k = 0; k < L; ++k) {
+    Level& lv = h.levels[k];
+    const int m = std::min(o.arnoldi_m, lv.n);
+    Arena at;
+    double* Q = at.alloc_n<double>((size_t)(m + 1) * lv.n);
+    double* w = at.alloc_n<double>(lv.n);
+    double Hh[48], wn[8];
+    arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
+    set_jacobi_weight(h, lv, m, Hh, wn);
+  }
+  coarse_inverse(h, tmp, sy);
+  sy.wait_and_check();
+  if (repoint && !h.g_iter.empty()) {
+    for (auto& g : h.g_iter) (void)hipGraphExecDestroy(g);
+    h.g_iter.clear();
+    if (h.g_restart) (void)hipGraphExecDestroy(h.g_restart);
+    h.g_restart = nullptr;
+    build_solve_graphs(h);
+  }
 }
 
 

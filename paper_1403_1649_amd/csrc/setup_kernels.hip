@@ -302,6 +302,36 @@ __global__ void __launch_bounds__(256) k_mis_sweep2(int n, const int* __restrict
   }
 }
 
+// MIS(k), k > 2 (Section 2.1.2, aggressive coarsening): the sweeps between
+// the first and the last of a round, out_i = max(in_i, max_{j in N_i} in_j),
+// so after sweep d every node holds the largest tuple within distance d.
+template <int G>
+__global__ void __launch_bounds__(256) k_misk_sweep(int n, const int* __restrict__ gptr,
+                                                    const int* __restrict__ gcol,
+                                                    const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                    int* mc, int round) {
+  __shared__ int s_flag;
+  if (!mis_pending(mc, round, &s_flag)) return;
+  constexpr int NPB = 256 / G;
+  const int lane = threadIdx.x & (G - 1);
+  const int groups = (n + NPB - 1) / NPB;
+  const int per = (groups + gridDim.x - 1) / gridDim.x;
+  const int g0 = xcd_block_index() * per, g1 = min(groups, g0 + per);
+  for (int g = g0; g < g1; ++g) {
+    const int i = g * NPB + threadIdx.x / G;
+    uint64_t t = 0;
+    if (i < n) {
+      if (lane == 0) t = in[i];
+      for (int k = gptr[i] + lane; k < gptr[i + 1]; k += G) {
+        const uint64_t u = in[gcol[k]];
+        t = u > t ? u : t;
+      }
+    }
+    t = group_max_u64<G>(t);
+    if (i < n && lane == 0) out[i] = t;
+  }
+}
+
 // Late-round node list: the closed neighbourhoods of the undecided nodes.
 // Only those nodes' first-sweep maxima are still read by an undecided node,
 // and they include every node the second sweep can still change (the sweep
@@ -396,6 +426,50 @@ __global__ void __launch_bounds__(256) k_agg_round2(int n, const int* __restrict
     }
     agg[i] = root_id[c];
   }
+}
+
+// MIS(k) aggregation, rounds 2..k: a node still without a root takes, among
+// the roots its neighbours chose in the previous round, the one with the
+// largest tuple (a neighbour assigned at all was assigned in that round, one
+// step nearer its root); the others keep their choice.  Double buffered.
+template <int G>
+__global__ void __launch_bounds__(256) k_agg_round_next(int n, const int* __restrict__ gptr,
+                                                        const int* __restrict__ gcol,
+                                                        const uint64_t* __restrict__ T,
+                                                        const int* __restrict__ cin, int* __restrict__ cout) {
+  RowGroup<G> rg;
+  for (long i0 = rg.gid; i0 < n; i0 += rg.ngroups) {
+    const int i = (int)i0;
+    int c = cin[i];
+    if (c < 0) {
+      uint64_t best = 0;
+      int bk = INT_MAX;
+      const int e = gptr[i + 1];
+      for (int k = gptr[i] + rg.lane; k < e; k += G) {
+        const int cj = cin[gcol[k]];
+        if (cj >= 0) {
+          const uint64_t u = T[cj];
+          if (u > best) { best = u; bk = k; c = cj; }
+        }
+      }
+      group_argmax<G>(best, bk, c);
+    }
+    if (rg.lane == 0) cout[i] = c;
+  }
+}
+
+// Coarse index of every node's root (an unassigned node is an error).
+__global__ void k_agg_map(int n, const int* __restrict__ choice, const int* __restrict__ root_id,
+                          int* __restrict__ agg, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = choice[i];
+  if (c < 0) {
+    atomic_or_flag(err, kErrUnassigned);
+    agg[i] = 0;
+    return;
+  }
+  agg[i] = root_id[c];
 }
 
 __global__ void k_agg_count(int n, const int* __restrict__ agg, int* counts) {
@@ -667,6 +741,37 @@ void launch_mis_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint
   }
 }
 
+// One MIS(k) round for k > 2: the first sweep (distance-1 maxima into M1,
+// settled ones kept), k - 2 plain sweeps alternating between Ma and Mb, and
+// the last sweep with the state update.
+template <int G>
+static void misk_round_g(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, uint64_t* Ma,
+                         uint64_t* Mb, int* mc, int round, int k, hipStream_t s) {
+  long g = ((long)n * G + kT - 1) / kT;
+  if (g < 1) g = 1;
+  if (g > kMisBlocks) g = kMisBlocks;
+  k_mis_sweep1<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, M1, mc, round, nullptr, nullptr);
+  const uint64_t* in = M1;
+  for (int d = 2; d < k; ++d) {
+    uint64_t* out = (d & 1) ? Mb : Ma;
+    k_misk_sweep<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, in, out, mc, round);
+    in = out;
+  }
+  k_mis_sweep2<G><<<(int)g, kT, 0, s>>>(n, gptr, gcol, T, in, mc, round, nullptr, nullptr);
+}
+
+void launch_misk_round(int n, const int* gptr, const int* gcol, uint64_t* T, uint64_t* M1, uint64_t* Ma,
+                       uint64_t* Mb, int* mc, int round, int k, int lanes, hipStream_t s) {
+  switch (lanes) {
+    case 1: misk_round_g<1>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+    case 2: misk_round_g<2>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+    case 4: misk_round_g<4>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+    case 8: misk_round_g<8>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+    case 16: misk_round_g<16>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+    default: misk_round_g<32>(n, gptr, gcol, T, M1, Ma, Mb, mc, round, k, s); break;
+  }
+}
+
 void launch_mis_lists(int n, const int* gptr, const int* gcol, const uint64_t* T, const MisLists& ml,
                       ScanCtx& sc, hipStream_t s) {
   launch_fill_int((size_t)n, ml.fnear, 0, s);
@@ -685,6 +790,24 @@ void launch_aggregate(int n, int nnzg, const int* gptr, const int* gcol, const u
     constexpr int L = decltype(g)::value;
     k_agg_round1<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, choice);
     k_agg_round2<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, choice, root_id, agg, err);
+  });
+}
+void launch_aggregate_k(int n, int nnzg, const int* gptr, const int* gcol, const uint64_t* T, const int* root_id,
+                        int k, int* choice, int* choice2, int* agg, int* err, hipStream_t s) {
+  if (n <= 0) return;
+  const int G = group_lanes(n, nnzg);
+  with_lanes(G, [&](auto g) {
+    constexpr int L = decltype(g)::value;
+    k_agg_round1<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, choice);
+    int* in = choice;
+    int* out = choice2;
+    for (int r = 2; r <= k; ++r) {
+      k_agg_round_next<L><<<group_grid(n, G), kT, 0, s>>>(n, gptr, gcol, T, in, out);
+      int* t = in;
+      in = out;
+      out = t;
+    }
+    k_agg_map<<<grid_for(n), kT, 0, s>>>(n, in, root_id, agg, err);
   });
 }
 void launch_agg_count(int n, const int* agg, int* counts, hipStream_t s) {

@@ -137,6 +137,176 @@ struct OpResidSmoothDot {
   __device__ void finalize(const double* s) const { sc[kScBeta] = -s[0] / sc[kScPQ]; }
 };
 
+// ---- Chebyshev smoothing (the polynomial smoother of Section 5): the
+// three-term Chebyshev recurrence on M = D^-1 A over [a, b].  First step from
+// an iterate x0: r = D^-1 (b - A x0), d = r / theta, x = x0 + d; each later
+// step j: r -= D^-1 A d, d = c1_j d + c2_j r, x += d.  Device coefficients
+// K[0] = 1 / theta, K[2j - 1] = c1_j, K[2j] = c2_j (j >= 1 counts the later
+// steps); dv = 1 / a_ii.
+
+// pre-smoothing from x0 = 0, first and second step in one pass: the gathered
+// d_j = (dv_j b_j) / theta, and at row i the second step's update
+template <typename T>
+struct OpChebPre2 {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* dv;
+  const double* K;
+  T* r;
+  T* dout;
+  T* xo;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return (T)K[0] * (dv[j] * b[j]); }
+  __device__ void row(int i, T ad, double*) const {
+    const T r0 = dv[i] * b[i];
+    const T d0 = (T)K[0] * r0;
+    const T rr = r0 - dv[i] * ad;
+    const T dn = (T)K[1] * d0 + (T)K[2] * rr;
+    r[i] = rr;
+    dout[i] = dn;
+    xo[i] = d0 + dn;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// pre-smoothing of degree one from x0 = 0 with the residual: x = d, r = b - A x
+template <typename T>
+struct OpChebPre1Resid {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* dv;
+  const double* K;
+  T* xt;
+  T* r;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return (T)K[0] * (dv[j] * b[j]); }
+  __device__ void row(int i, T ax, double*) const {
+    xt[i] = (T)K[0] * (dv[i] * b[i]);
+    r[i] = b[i] - ax;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// a later step j (din gathered, dout written: two buffers)
+template <typename T>
+struct OpChebStep {
+  static constexpr int NV = 0;
+  Act a;
+  const T* dv;
+  const T* din;
+  T* dout;
+  T* r;
+  T* xo;
+  const double* K;
+  int j;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int c) const { return din[c]; }
+  __device__ void row(int i, T ad, double*) const {
+    const T rr = r[i] - dv[i] * ad;
+    const T dn = (T)K[2 * j - 1] * din[i] + (T)K[2 * j] * rr;
+    r[i] = rr;
+    dout[i] = dn;
+    xo[i] += dn;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// first post-smoothing step on the corrected iterate x0 = xt + P e
+template <typename T, class Corr>
+struct OpChebPost1 {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* xt;
+  const T* dv;
+  const double* K;
+  T* r;
+  T* dout;
+  T* xo;
+  Corr corr;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return corr.at(xt, j); }
+  __device__ void row(int i, T ax, double*) const {
+    const T rr = dv[i] * (b[i] - ax);
+    const T d = (T)K[0] * rr;
+    r[i] = rr;
+    dout[i] = d;
+    xo[i] = corr.at(xt, i) + d;
+  }
+  __device__ void finalize(const double*) const {}
+};
+
+// residual of a given iterate: r = b - A x
+template <typename T>
+struct OpResid {
+  static constexpr int NV = 0;
+  Act a;
+  const T* b;
+  const T* xv;
+  T* r;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ T x(int j) const { return xv[j]; }
+  __device__ void row(int i, T ax, double*) const { r[i] = b[i] - ax; }
+  __device__ void finalize(const double*) const {}
+};
+
+// ---- multi-colour symmetric Gauss-Seidel (Section 2.2.1): the rows of one
+// colour share no entry of A, so x_i += (b_i - (A x)_i) / a_ii for all of them
+// at once, in place (no row of the colour reads another's x_i).  LPR lanes
+// per listed row.
+template <typename T, int LPR>
+__global__ void __launch_bounds__(256) k_sgs_color(int m, const int* __restrict__ rows, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ av,
+                                                   const T* __restrict__ b, const T* __restrict__ dv, T* x, Act a) {
+  if (!a.on()) return;
+  constexpr int RPB = 256 / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  for (int q0 = blockIdx.x * RPB; q0 < m; q0 += gridDim.x * RPB) {
+    const int q = q0 + threadIdx.x / LPR;
+    T sum = T(0);
+    int i = -1;
+    if (q < m) {
+      i = rows[q];
+      for (int k = rp[i] + lane; k < rp[i + 1]; k += LPR) sum += av[k] * x[ci[k]];
+    }
+    sum = group_sum<LPR>(sum);
+    if (q < m && lane == 0) x[i] += (b[i] - sum) * dv[i];
+  }
+}
+
+// x = value (guarded)
+template <typename T>
+struct OpFillAct {
+  static constexpr int NV = 0;
+  Act a;
+  T* p;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { p[i] = T(0); }
+  __device__ void finalize(const double*) const {}
+};
+
+// xo = the corrected iterate xt + P e
+template <typename T, class Corr>
+struct OpApplyCorr {
+  static constexpr int NV = 0;
+  Act a;
+  const T* xt;
+  T* xo;
+  Corr corr;
+  __device__ bool active() const { return a.on(); }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { xo[i] = corr.at(xt, i); }
+  __device__ void finalize(const double*) const {}
+};
+
 // first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r)
 template <typename T>
 struct OpKDots1 {   // also ||r_c||^2 for the test of the second step
@@ -659,11 +829,102 @@ void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
 
 // Residual + post-smoothing of level k on the corrected iterate (and z'q at
 // the top of the outer iteration when fuse_q is given).
+// Chebyshev vectors of a level in the cycle precision: r, two d buffers
+template <typename T>
+struct ChebVecs {
+  T* r;
+  T* d0;
+  T* d1;
+};
+template <typename T>
+ChebVecs<T> cheb_vecs(const Level& lv) {
+  return ChebVecs<T>{static_cast<T*>(lv.cr), static_cast<T*>(lv.cd0), static_cast<T*>(lv.cd1)};
+}
+
+// Pre-smoothing by Chebyshev from x = 0 (degree m = cheb_degree), then the
+// residual r_out = b - A x.
+template <typename T>
+void cheb_pre(Hierarchy& h, const Level& lv, int k, Act A, const T* b, T* xt, T* r_out) {
+  const Level* lp = &lv;
+  RedCtx rc = red(h);
+  const T* dv = wdinv<T>(lv);
+  const int m = h.opt.cheb_degree;
+  const bool sel = k == 0 && h.opt.probe == AMG_PROBE_L0_PRESMOOTH;
+  if (m == 1) {
+    const OpChebPre1Resid<T> op{A, b, dv, lv.cheb, xt, r_out};
+    probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+    return;
+  }
+  ChebVecs<T> cv = cheb_vecs<T>(lv);
+  {
+    const OpChebPre2<T> op{A, b, dv, lv.cheb, cv.r, cv.d0, xt};
+    probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+  }
+  T* din = cv.d0;
+  T* dout = cv.d1;
+  for (int j = 2; j < m; ++j) {
+    launch_level<T>(lv, OpChebStep<T>{A, dv, din, dout, cv.r, xt, lv.cheb, j}, rc, h.stream);
+    std::swap(din, dout);
+  }
+  launch_level<T>(lv, OpResid<T>{A, b, xt, r_out}, rc, h.stream);
+}
+
+// Post-smoothing by Chebyshev on the corrected iterate, into xo.
+template <typename T, class Corr>
+void cheb_post(Hierarchy& h, const Level& lv, int k, Act A, const T* b, const T* xt, T* xo, Corr corr) {
+  const Level* lp = &lv;
+  RedCtx rc = red(h);
+  const T* dv = wdinv<T>(lv);
+  ChebVecs<T> cv = cheb_vecs<T>(lv);
+  {
+    const OpChebPost1<T, Corr> op{A, b, xt, dv, lv.cheb, cv.r, cv.d0, xo, corr};
+    probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH,
+                [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+  }
+  T* din = cv.d0;
+  T* dout = cv.d1;
+  for (int j = 1; j < h.opt.cheb_degree; ++j) {
+    launch_level<T>(lv, OpChebStep<T>{A, dv, din, dout, cv.r, xo, lv.cheb, j}, rc, h.stream);
+    std::swap(din, dout);
+  }
+}
+
+// One symmetric Gauss-Seidel step on x in place: the colours forward, then
+// backward.
+template <typename T>
+void sgs_sweeps(Hierarchy& h, const Level& lv, Act A, const T* b, T* x) {
+  const int nc = (int)lv.coff.size() - 1;
+  const int lpr = lv.lpr < 2 ? 2 : lv.lpr > 32 ? 32 : lv.lpr;
+  for (int pass = 0; pass < 2 * nc; ++pass) {
+    const int c = pass < nc ? pass : 2 * nc - 1 - pass;
+    const int m = lv.coff[c + 1] - lv.coff[c];
+    if (m <= 0) continue;
+    const int* rows = lv.crow + lv.coff[c];
+    long g = ((long)m * lpr + 255) / 256;
+    if (g > 4096) g = 4096;
+    with_lanes(lpr, [&](auto gl) {
+      k_sgs_color<T, decltype(gl)::value><<<(int)g, 256, 0, h.stream>>>(m, rows, lv.rp, lv.ci, vals<T>(lv), b,
+                                                                          wdinv<T>(lv), x, A);
+    });
+  }
+}
+
 template <typename T, class Corr>
 void post_smooth(Hierarchy& h, const Level& lv, int k, Act A, const T* b, const T* xt, const T* wd, T* xo, Corr corr,
                  const double* fuse_q, RedCtx rc) {
   const Level* lp = &lv;
   const bool sel = k == 0 && h.opt.probe == AMG_PROBE_L0_POSTSMOOTH;
+  if (h.opt.smoother == AMG_SMOOTHER_MCSGS) {
+    launch_elem(lv.n, OpApplyCorr<T, Corr>{A, xt, xo, corr}, rc, h.stream);
+    sgs_sweeps<T>(h, lv, A, b, xo);
+    if (fuse_q) launch_elem(lv.n, OpDotZQ<T>{A, xo, fuse_q, h.d_sc}, rc, h.stream);
+    return;
+  }
+  if (h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV) {
+    cheb_post<T>(h, lv, k, A, b, xt, xo, corr);
+    if (fuse_q) launch_elem(lv.n, OpDotZQ<T>{A, xo, fuse_q, h.d_sc}, rc, h.stream);
+    return;
+  }
   if (fuse_q) {
     const OpResidSmoothDot<T, Corr> op{A, b, xt, wd, xo, corr, fuse_q, h.d_sc};
     probe_point(h, sel, [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
@@ -694,7 +955,19 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
   const Act A{act};
 
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
-  if (!kcyc && k > 0 && lv.n <= kFuseCorrectionRows) {
+  const bool cheb = h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV;
+  const bool sgs = h.opt.smoother == AMG_SMOOTHER_MCSGS;
+  if (cheb || sgs) {
+    if (cheb) {
+      cheb_pre<T>(h, lv, k, A, b, xt, r);
+    } else {   // from x = 0, then the residual
+      launch_elem(lv.n, OpFillAct<T>{A, xt}, rc, s);
+      sgs_sweeps<T>(h, lv, A, b, xt);
+      launch_level<T>(lv, OpResid<T>{A, b, xt, r}, rc, s);
+    }
+    if (!kcyc)
+      launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv}, rc, s);
+  } else if (!kcyc && k > 0 && lv.n <= kFuseCorrectionRows) {
     const int lpr = tune_of<T>(lv).lpr;
     const int grid = lv.nc < 1 ? 1 : lv.nc < 65536 ? lv.nc : 65536;
     with_lanes(lpr, [&](auto g) {

@@ -118,3 +118,27 @@ def test_release_cached_memory_without_gpu():
     """Nothing is cached before any setup: the call frees nothing."""
     _lib_or_skip()
     assert amg.release_cached_memory() == 0
+
+
+def test_setup_rejects_mis_k_out_of_range_without_gpu():
+    """MIS(k) needs k >= 2 (the first sweep keeps settled maxima, which holds
+    only when two roots never share a closed neighbourhood) and at most 8;
+    batches coarsen by MIS(2) only.  Both are refused before any device work."""
+    L = _lib_or_skip()
+    h = C.c_void_p()
+    dummy = np.zeros(8, np.int64)
+    p = dummy.ctypes.data
+    A = amg.binding.AmgCsrC(10, 28, p, p, p)
+    for k in (1, 9):
+        opts = amg.Options(dim=3, mis_k=k)
+        assert L.amg_setup(C.byref(A), C.byref(opts.c), None, C.byref(h)) == 1
+        assert b"mis_k" in L.amg_last_error()
+        assert not h.value
+    o = np.array([0, 5, 10], np.int32)
+    opts = amg.Options(dim=2, mis_k=3)
+    assert L.amg_setup_batched(C.byref(A), 2, o.ctypes.data, C.byref(opts.c), None, C.byref(h)) == 8
+
+
+def test_default_options_extensions():
+    o = amg.Options(dim=3)
+    assert o.mis_k == 2 and o.cheb_degree == 2 and o.cheb_ratio == 4.0 and o.cheb_upper == 1.1

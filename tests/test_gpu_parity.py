@@ -175,7 +175,7 @@ def test_mixed_precision_solve(name, make, dim):
     x = x.cpu().numpy()
     assert rel <= 1e-8
     assert np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1.01e-8
-    assert it <= it64 + 3
+    assert abs(it - it64) <= 1, (it, it64)   # FP32 cycle: same iteration count up to one near-tie flip
 
 
 def test_single_level_and_zero_rhs():
@@ -384,7 +384,7 @@ def test_fgmres_matches_oracle(precision):
     ref = O.solve(H, b, 1e-8)
     x = x.cpu().numpy()
     assert rel <= 1e-8 and np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1.01e-8
-    assert abs(it - ref.iters) <= (1 if precision == "fp64" else 3), (it, ref.iters)
+    assert abs(it - ref.iters) <= 1, (it, ref.iters)
 
 
 def test_fgmres_nonsymmetric_and_restart():
