@@ -265,13 +265,15 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
             t = time.perf_counter() - t1
             s_ms, v_ms = h.timings()
             kept = [int(h.smoother_info(k)[0]) for k in range(h.num_levels() - 1)] if "mlp_weights" in kw else None
+            judge = h.learned_judge() if "mlp_weights" in kw else None
             h.close()
             if best is None or t < best:
-                best, info = t, (it, rel, s_ms, v_ms, kept)
+                best, info = t, (it, rel, s_ms, v_ms, kept, judge)
         out[name] = {"mdof_s": round(A.n / best / 1e6, 3) if info[1] <= 1e-8 else 0.0, "iters": info[0],
                      "relres": info[1], "setup_ms": round(info[2], 2), "solve_ms": round(info[3], 2)}
         if info[4] is not None:
             out[name]["learned_levels"] = info[4]
+            out[name]["judge"] = info[5]
     return out
 
 
@@ -393,6 +395,34 @@ def misk_form(amg, torch, A, dev, dim, b, reps=3):
     return out
 
 
+def smoothers_form(amg, torch, A, dev, dim, b, reps=3):
+    """Other smoothers (Sections 2.2.1 and 5) on the headline workload against
+    damped Jacobi, FP64: Chebyshev of degree 2 and multi-colour symmetric
+    Gauss-Seidel."""
+    bt = torch.from_numpy(b).cuda()
+    out = {}
+    for name, kw in (("jacobi", {}), ("chebyshev_2", {"smoother": "chebyshev", "cheb_degree": 2}),
+                     ("chebyshev_3", {"smoother": "chebyshev", "cheb_degree": 3}), ("mcsgs", {"smoother": "mcsgs"})):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = amg.setup(*dev, amg.Options(dim=dim, **kw))
+            _, it, rel = amg.solve(h, bt, 1e-8)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            s_ms, v_ms = h.timings()
+            ncol = h.level_colors(0)[1] if name == "mcsgs" else None
+            h.close()
+            if best is None or t < best[0]:
+                best = (t, it, rel, s_ms, v_ms, ncol)
+        out[name] = {"iters": best[1], "relres": best[2], "setup_ms": round(best[3], 2), "solve_ms": round(best[4], 2),
+                     "mdof_s": round(A.n / best[0] / 1e6, 2) if best[2] <= 1e-8 else 0.0}
+        if best[5] is not None:
+            out[name]["colours_level0"] = best[5]
+    return out
+
+
 def cpu_info():
     """Host cores and CPU model of the machine the oracle runs on."""
     model = None
@@ -464,8 +494,11 @@ def main():
     ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-misk", action="store_true")
+    ap.add_argument("--no-smoothers", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched C4b form and print its JSON (for profiling)")
+    ap.add_argument("--multi-only", action="store_true",
+                    help="run only the multi-RHS C4a form and print its JSON (for profiling)")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the hash of the roofline kernel's sources and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -496,6 +529,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps({"batch": batch_form(amg, torch, P, reps=max(1, args.steps))}), flush=True)
+        return 0
+    if args.multi_only:
+        print(json.dumps({"multi_rhs": multi_rhs_form(amg, torch, P, reps=max(1, args.steps))}), flush=True)
         return 0
 
     desc, dim = WORKLOADS[args.workload]
@@ -550,6 +586,9 @@ def main():
     if not args.no_misk:
         log("bench: MIS(k) aggressive coarsening")
         forms["misk"] = misk_form(amg, torch, A, dev, dim, b)
+    if not args.no_smoothers:
+        log("bench: other smoothers")
+        forms["smoothers"] = smoothers_form(amg, torch, A, dev, dim, b)
     if not args.no_ablation:
         log("bench: K-cycle depth ablation")
         forms["kcycle_depth"] = kcycle_ablation_form(amg, torch, P)

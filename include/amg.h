@@ -247,7 +247,9 @@ int32_t amg_batch_level(const amg_hierarchy* h, int32_t k, int32_t* sys_off, dou
  * The bound keeps the smoother convergent for SPD A.  With
  * opt.smoother = AMG_SMOOTHER_LEARNED, setup uses the learned weights on a
  * level only when they lower the smoothing loss below the plain omega_k on
- * four validation samples, and falls back to plain damped Jacobi otherwise. */
+ * four validation samples, and then keeps them only when a probe solve with
+ * them needs fewer iterations than with plain damped Jacobi (amg_learned_judge);
+ * it falls back to plain damped Jacobi otherwise. */
 
 /* Number of MLP parameters (1409): W1[32][9], b1[32], W2[32][32], b2[32], W3[32], b3. */
 int32_t amg_mlp_num_params(void);
@@ -290,6 +292,17 @@ int32_t amg_level_smoother(const amg_hierarchy* h, int32_t k, int32_t* learned, 
  * int32[n_k] (may be NULL) and *ncolors (may be NULL).  EINVAL when the
  * hierarchy does not smooth by colours or k has no smoother. */
 int32_t amg_level_colors(const amg_hierarchy* h, int32_t k, int32_t* colors, int32_t* ncolors);
+
+/* (host) the setup's judgement of the learned weights (AMG_SMOOTHER_LEARNED
+ * without AMG_FLAG_LEARNED_ALWAYS, when some level passed the loss check): a
+ * probe solve of A x = A u (u hashed from seed + 3) to relative residual 1e-4
+ * with the learned weights and with the plain omega_k on every level; the
+ * learned ones stay (*kept = 1) only with fewer iterations, or as many and a
+ * smaller true residual; otherwise every level falls back to damped Jacobi
+ * (*kept = 0).  *kept = -1 when no judgement was made.  Any pointer may be
+ * NULL. */
+int32_t amg_learned_judge(const amg_hierarchy* h, int32_t* kept, int32_t* iters_plain, double* relres_plain,
+                          int32_t* iters_learned, double* relres_learned);
 
 /* (host) copy of omega_i / a_ii, the Jacobi scaling the cycle applies on level k. */
 int32_t amg_export_jacobi(const amg_hierarchy* h, int32_t k, double* wdinv);

@@ -26,7 +26,7 @@ EXPORTED = [
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
     "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
-    "amg_setup_phases", "amg_resetup", "amg_resetup_time", "amg_level_colors",
+    "amg_setup_phases", "amg_resetup", "amg_resetup_time", "amg_level_colors", "amg_learned_judge",
 ]
 
 
@@ -104,6 +104,8 @@ def lib():
     L.amg_resetup_time.restype = i32
     L.amg_level_colors.argtypes = [vp, i32, vp, P(i32)]
     L.amg_level_colors.restype = i32
+    L.amg_learned_judge.argtypes = [vp, P(i32), P(i32), P(dbl), P(i32), P(dbl)]
+    L.amg_learned_judge.restype = i32
     L.amg_hessenberg_radius.argtypes = [vp, i32, P(dbl)]
     L.amg_hessenberg_radius.restype = i32
     L.amg_timings.argtypes = [vp, P(dbl), P(dbl)]
@@ -316,6 +318,14 @@ class Hierarchy:
         l, a, b = C.c_int32(), C.c_double(), C.c_double()
         _check(lib().amg_level_smoother(self._h, k, C.byref(l), C.byref(a), C.byref(b)))
         return bool(l.value), a.value, b.value
+
+    def learned_judge(self) -> dict:
+        """The setup's probe-solve judgement of the learned weights."""
+        kept, ip, il = C.c_int32(), C.c_int32(), C.c_int32()
+        rp, rl = C.c_double(), C.c_double()
+        _check(lib().amg_learned_judge(self._h, C.byref(kept), C.byref(ip), C.byref(rp), C.byref(il), C.byref(rl)))
+        return {"kept": kept.value, "iters_plain": ip.value, "relres_plain": rp.value, "iters_learned": il.value,
+                "relres_learned": rl.value}
 
     def level_colors(self, k: int):
         """(colour of every row, number of colours) of level k (MC-SGS smoother)."""

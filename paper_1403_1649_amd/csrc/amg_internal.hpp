@@ -217,6 +217,10 @@ struct Hierarchy {
   int probe_samples = 0;
   float setup_ms = 0.f, solve_ms = 0.f, resetup_ms = 0.f;
   double tune_ms = 0.0, capture_ms = 0.0;   // host time of the autotuner and of the graph capture in setup
+  // learned weights judged by probe solves: kept?, iterations and true
+  // relative residuals with the plain weights and with the learned ones
+  int judge_kept = -1, judge_it_plain = 0, judge_it_learned = 0;
+  double judge_rel_plain = 0.0, judge_rel_learned = 0.0;
   // batched systems: count (0 = one system), per-system control of the solve
   // and the results of the last solve
   int nsys = 0;
@@ -406,6 +410,7 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
 void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off);
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, bool offsets16);
 void level_spmv(const Hierarchy& h, int k, const double* x, double* y, hipStream_t s);
+void launch_hash_vector(int n, uint32_t stream, double* q, hipStream_t s);
 void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y, bool offsets16);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,
               int lpr, hipStream_t s);

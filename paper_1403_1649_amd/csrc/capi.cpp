@@ -513,6 +513,18 @@ int32_t amg_level_smoother(const amg_hierarchy* H, int32_t k, int32_t* learned, 
   return AMG_OK;
 }
 
+int32_t amg_learned_judge(const amg_hierarchy* H, int32_t* kept, int32_t* iters_plain, double* relres_plain,
+                          int32_t* iters_learned, double* relres_learned) {
+  if (!H) return fail(AMG_EINVAL, "amg_learned_judge: NULL hierarchy");
+  const amg::Hierarchy& h = H->h;
+  if (kept) *kept = h.judge_kept;
+  if (iters_plain) *iters_plain = h.judge_it_plain;
+  if (relres_plain) *relres_plain = h.judge_rel_plain;
+  if (iters_learned) *iters_learned = h.judge_it_learned;
+  if (relres_learned) *relres_learned = h.judge_rel_learned;
+  return AMG_OK;
+}
+
 int32_t amg_level_colors(const amg_hierarchy* H, int32_t k, int32_t* colors, int32_t* ncolors) {
   if (!H || k < 0 || k >= (int32_t)H->h.levels.size() - 1) return fail(AMG_EINVAL, "amg_level_colors: level");
   const amg::Level& lv = H->h.levels[k];

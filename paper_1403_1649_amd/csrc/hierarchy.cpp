@@ -539,6 +539,70 @@ static void color_level(Hierarchy& h, Arena& tmp, Level& lv, Sync& sy) {
   AMG_HIP(hipStreamSynchronize(s));   // the host offsets array is read by the copy above
 }
 
+// The learned weights face the method's own judge (iteration count, then the
+// final residual): a probe solve of A x = A u (u hashed from seed + 3) to a
+// loose tolerance with the learned weights and with the plain omega_k / a_ii
+// on every level; the learned ones stay only when they need fewer
+// iterations, or as many and end with a smaller true residual.
+constexpr double kJudgeRtol = 1e-4;
+static void judge_learned(Hierarchy& h, Arena& tmp) {
+  const int L = h.L();
+  bool any = false;
+  for (int k = 0; k < L; ++k) any = any || h.levels[k].learned;
+  if (!any) return;
+  hipStream_t s = h.stream;
+  const int n = h.levels[0].n;
+  double* u = tmp.alloc_n<double>(n);
+  double* b = tmp.alloc_n<double>(n);
+  double* x = tmp.alloc_n<double>(n);
+  launch_hash_vector(n, h.opt.seed + 3, u, s);
+  level_spmv(h, 0, u, b, s);
+  std::vector<double*> keep64(L, nullptr);
+  std::vector<float*> keep32(L, nullptr);
+  for (int k = 0; k < L; ++k) {
+    Level& lv = h.levels[k];
+    if (!lv.learned) continue;
+    keep64[k] = tmp.alloc_n<double>(lv.n);
+    AMG_HIP(hipMemcpyAsync(keep64[k], lv.wdinv, (size_t)lv.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (lv.wdinv32) {
+      keep32[k] = tmp.alloc_n<float>(lv.n);
+      AMG_HIP(hipMemcpyAsync(keep32[k], lv.wdinv32, (size_t)lv.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  auto probe = [&](int* it, double* rel) {
+    const int mi = h.opt.max_iter;
+    h.opt.max_iter = 500;
+    try {
+      (void)solve_fcg_impl(h, b, kJudgeRtol, x, it, rel);
+    } catch (...) {
+      h.opt.max_iter = mi;
+      throw;
+    }
+    h.opt.max_iter = mi;
+  };
+  probe(&h.judge_it_learned, &h.judge_rel_learned);
+  for (int k = 0; k < L; ++k) {
+    Level& lv = h.levels[k];
+    if (lv.learned) launch_jacobi_weights(lv.n, lv.omega, lv.diag, lv.wdinv, lv.wdinv32, s);
+  }
+  probe(&h.judge_it_plain, &h.judge_rel_plain);
+  const bool keep = h.judge_it_learned < h.judge_it_plain ||
+                    (h.judge_it_learned == h.judge_it_plain && h.judge_rel_learned < h.judge_rel_plain);
+  h.judge_kept = keep ? 1 : 0;
+  for (int k = 0; k < L; ++k) {
+    Level& lv = h.levels[k];
+    if (!lv.learned) continue;
+    if (!keep) {
+      lv.learned = 0;
+      continue;
+    }
+    AMG_HIP(hipMemcpyAsync(lv.wdinv, keep64[k], (size_t)lv.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (keep32[k])
+      AMG_HIP(hipMemcpyAsync(lv.wdinv32, keep32[k], (size_t)lv.n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
 void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   hipStream_t s = h.stream;
   const amg_options& o = h.opt;
@@ -772,6 +836,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
   using clk = std::chrono::steady_clock;
   const auto t_tune = clk::now();
   if (!(o.flags & AMG_FLAG_NO_TUNE)) autotune_levels(h);
+  if (o.smoother == AMG_SMOOTHER_LEARNED && !(o.flags & AMG_FLAG_LEARNED_ALWAYS)) judge_learned(h, tmp);
   const auto t_graph = clk::now();
   h.tune_ms = std::chrono::duration<double, std::milli>(t_graph - t_tune).count();
   if (o.probe != AMG_PROBE_NONE) {

@@ -644,6 +644,16 @@ struct OpRtilde {
   }
 };
 
+struct OpHashVector {
+  static constexpr int NV = 0;
+  double* q;
+  uint32_t stream;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { q[i] = unit_uniform((uint32_t)i, stream); }
+  __device__ void finalize(const double*) const {}
+};
+
 struct OpArnStart {
   static constexpr int NV = 1;
   double* q;
@@ -1654,6 +1664,11 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 }
 
 int pick_lanes_per_row(int n, int nnz) { return pick_lpr(n, nnz); }
+
+// q_i = unit_uniform(i, stream), the seeded hash vector in [-1, 1)
+void launch_hash_vector(int n, uint32_t stream, double* q, hipStream_t s) {
+  launch_elem(n, OpHashVector{q, stream}, RedCtx{nullptr, nullptr}, s);
+}
 
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, bool offsets16) {
   launch_sell<double>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, OpSpmv<double>{Act{nullptr}, x, y},

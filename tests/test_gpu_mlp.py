@@ -121,9 +121,11 @@ def test_training_reduces_loss_and_learned_setup_is_safe():
     b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
     x, it, rel = amg.solve(hl, b, 1e-8)
     assert rel <= 1e-8
+    judge = hl.learned_judge()
     for k in range(hl.num_levels() - 1):
         learned, lp, ll = hl.smoother_info(k)
-        assert lp > 0 and ll > 0 and learned == (ll < lp)
+        assert lp > 0 and ll > 0
+        assert learned == (ll < lp and judge["kept"] == 1)
         if learned:
             ex = hl.export_level(k, what=("A",))
             S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
@@ -160,3 +162,37 @@ def test_raw_extra_samples_and_learned_always():
     b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
     _, it, rel = amg.solve(hl, b, 1e-8)
     assert rel <= 1e-8
+
+
+def test_learned_weights_judged_by_solve():
+    """The method's judge of the learned weights (iteration count, then the
+    final residual) on a 64^3 heterogeneous field (the training fields' size):
+    the setup keeps them only when its probe solve needs fewer iterations than
+    plain damped Jacobi; the full solve then needs no more iterations than the
+    plain method, and a rejection leaves exactly the plain method."""
+    from paper_1403_1649_amd import learned as Ld
+    train = [P.hetero3d(16, seed=100 + i) for i in range(3)]
+    systems = []
+    for A in train:
+        h = _setup(A)
+        systems.append((h, Ld.solver_errors(h, A, P.exact_solution(A.n, 1))))
+    w = Ld.train(systems, steps=60, lr=3e-3, samples=8)
+    A = P.hetero3d(64, seed=7)
+    print(f"learned judge: n={A.n}", flush=True)
+    b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+    hp = _setup(A)
+    xp, itp, relp = amg.solve(hp, b, 1e-8)
+    hl = _setup(A, mlp_weights=w)
+    xl, itl, rell = amg.solve(hl, b, 1e-8)
+    j = hl.learned_judge()
+    assert rell <= 1e-8 and relp <= 1e-8
+    assert j["kept"] in (-1, 0, 1)
+    if j["kept"] == 1:
+        assert j["iters_learned"] < j["iters_plain"] or (
+            j["iters_learned"] == j["iters_plain"] and j["relres_learned"] < j["relres_plain"])
+        assert itl <= itp, (itl, itp, j)
+    else:
+        assert all(not hl.smoother_info(k)[0] for k in range(hl.num_levels() - 1))
+        assert itl == itp and np.array_equal(xl.cpu().numpy(), xp.cpu().numpy())
+    hp.close()
+    hl.close()
