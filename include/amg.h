@@ -363,6 +363,22 @@ int32_t amg_galerkin(const amg_csr* A, const int32_t* agg, const double* pval, i
                      int32_t* nnz_c, int32_t* row_ptr_c, int32_t* col_c, double* val_c,
                      int32_t cap, hipStream_t s);
 
+/* amg_galerkin for callers that cannot allocate memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same product
+ * by aggregate index (Section 3.1, eq. galerkin) with the same kernels, all of
+ * their scratch in one static device array of the library (about 17 MiB per
+ * device, held until the process ends); no hipMalloc, hipHostMalloc or other
+ * allocating call.  Limits: A->n <= 131072 and A->nnz <= 1048576 (EINVAL
+ * beyond).  Outputs are DEVICE arrays owned by the caller: row_ptr_c[nc+1]
+ * (always written once the checks pass), col_c[cap] and val_c[cap] (written
+ * only when cap >= nnz(A_c); otherwise EINVAL with *nnz_c set).  nnz_c: (host).
+ * Input checks and errors as amg_galerkin.  Every call on one device shares
+ * the array, so calls that overlap on one device (other streams or threads)
+ * race; calls in sequence are independent.  Synchronises s. */
+int32_t amg_galerkin_noalloc(const amg_csr* A, const int32_t* agg, const double* pval, int32_t nc,
+                             int32_t* row_ptr_c, int32_t* col_c, double* val_c, int32_t cap, int32_t* nnz_c,
+                             hipStream_t s);
+
 /* (host) largest eigenvalue modulus of a real m-by-m upper Hessenberg matrix
  * H (row-major, m <= 8): the spectral estimate of Section 2.2.1 taken from
  * the Arnoldi Hessenberg matrix.  No device work. */

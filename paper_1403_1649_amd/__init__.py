@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     Options,
     default_options,
     galerkin,
+    galerkin_noalloc,
     hessenberg_radius,
     lib,
     mlp_adam,

@@ -26,7 +26,7 @@ EXPORTED = [
     "amg_solve_multi", "amg_mlp_num_params", "amg_mlp_features", "amg_mlp_omega", "amg_mlp_loss_grad",
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
     "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
-    "amg_setup_phases", "amg_resetup", "amg_resetup_time", "amg_level_colors", "amg_learned_judge",
+    "amg_setup_phases", "amg_galerkin_noalloc", "amg_resetup", "amg_resetup_time", "amg_level_colors", "amg_learned_judge",
 ]
 
 
@@ -98,6 +98,8 @@ def lib():
     L.amg_node_hash.restype = i32
     L.amg_galerkin.argtypes = [P(AmgCsrC), vp, vp, i32, P(i32), vp, vp, vp, i32, vp]
     L.amg_galerkin.restype = i32
+    L.amg_galerkin_noalloc.argtypes = [P(AmgCsrC), vp, vp, i32, vp, vp, vp, i32, P(i32), vp]
+    L.amg_galerkin_noalloc.restype = i32
     L.amg_resetup.argtypes = [vp, vp, vp]
     L.amg_resetup.restype = i32
     L.amg_resetup_time.argtypes = [vp, P(dbl)]
@@ -461,6 +463,23 @@ def galerkin(row_ptr, col, val, agg, pval, nc: int):
     _check(lib().amg_galerkin(C.byref(A), _ptr(agg), _ptr(pval), int(nc), C.byref(nnz), _nptr(rp),
                               _nptr(ci), _nptr(v), int(nnz.value), _stream()))
     return rp, ci, v
+
+
+def galerkin_noalloc(row_ptr, col, val, agg, pval, nc: int, cap: int | None = None):
+    """amg_galerkin_noalloc: returns (row_ptr_c, col_c, val_c) as device tensors
+    (col_c / val_c of length cap, default nnz(A); the first nnz(A_c) entries hold
+    the product) and nnz(A_c)."""
+    import torch
+    A = _csr(row_ptr, col, val)
+    cap = int(A.nnz) if cap is None else int(cap)
+    dev = row_ptr.device
+    rp = torch.empty(nc + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    v = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    nnz = C.c_int32()
+    _check(lib().amg_galerkin_noalloc(C.byref(A), _ptr(agg), _ptr(pval), int(nc), _ptr(rp), _ptr(ci), _ptr(v), cap,
+                                      C.byref(nnz), _stream()))
+    return rp, ci, v, nnz.value
 
 
 def hessenberg_radius(H: np.ndarray) -> float:

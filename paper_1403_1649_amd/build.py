@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libamg_hip.so")
 SOURCES = ["scan.hip", "setup_kernels.hip", "galerkin.hip", "dense.hip", "solver.hip", "solver_multi.hip", "mlp.hip", "batch.hip",
-           "resetup.hip", "coloring.hip", "hierarchy.cpp", "capi.cpp"]
+           "noalloc.hip", "resetup.hip", "coloring.hip", "hierarchy.cpp", "capi.cpp"]
 ARCH = "gfx950"
 
 

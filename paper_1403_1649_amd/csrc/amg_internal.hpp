@@ -416,6 +416,11 @@ void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, c
               int lpr, hipStream_t s);
 int pick_lanes_per_row(int n, int nnz);
 
+// noalloc.hip: the Galerkin product with its scratch in a static device array;
+// returns AMG_EINVAL (nnz_c set, col_c / val_c untouched) when cap < nnz_c.
+int galerkin_noalloc(const amg_csr& A, const int* agg, const double* pval, int nc, int* row_ptr_c, int* col_c,
+                     double* val_c, int cap, int* nnz_c, hipStream_t s);
+
 // resetup.hip: numeric re-setup on a fixed pattern
 void launch_rs_count(const Level& lv, const Level& lc, int* cnt, int* err, hipStream_t s);
 void launch_rs_fill(const Level& lv, const Level& lc, int* cur, int* tf, int* ti, int* err, hipStream_t s);

@@ -411,6 +411,21 @@ int32_t amg_galerkin(const amg_csr* A, const int32_t* agg, const double* pval, i
   return AMG_OK;
 }
 
+int32_t amg_galerkin_noalloc(const amg_csr* A, const int32_t* agg, const double* pval, int32_t nc,
+                             int32_t* row_ptr_c, int32_t* col_c, double* val_c, int32_t cap, int32_t* nnz_c,
+                             hipStream_t s) {
+  if (!csr_args_ok(A) || !agg || !pval || nc < 1 || nc > A->n || !nnz_c || !row_ptr_c || cap < 0 ||
+      (cap > 0 && (!col_c || !val_c)))
+    return fail(AMG_EINVAL, "amg_galerkin_noalloc: bad argument");
+  int32_t code = AMG_OK;
+  int32_t st = guarded("amg_galerkin_noalloc", [&] {
+    code = amg::galerkin_noalloc(*A, agg, pval, nc, row_ptr_c, col_c, val_c, cap, nnz_c, s);
+  });
+  if (st != AMG_OK) return st;
+  if (code != AMG_OK) return fail(code, "amg_galerkin_noalloc: output capacity too small");
+  return AMG_OK;
+}
+
 int32_t amg_hessenberg_radius(const double* H, int32_t m, double* rho) {
   if (!H || !rho || m < 1 || m > 8) return fail(AMG_EINVAL, "amg_hessenberg_radius: bad argument");
   *rho = amg::hessenberg_spectral_radius(H, m);
