@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <functional>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -231,6 +232,10 @@ struct Hierarchy {
   int* b_again = nullptr;      // systems restarted from their true residual
   std::vector<int> b_iters;
   std::vector<double> b_relres;
+  // several right-hand sides: the block workspace and the captured block
+  // iteration of the last amg_solve_multi, kept for the next call with the
+  // same number of columns (solver_multi.hip)
+  std::shared_ptr<void> multi;
   bool mixed() const { return opt.precision == AMG_PREC_MIXED; }
   int L() const { return (int)levels.size() - 1; }
   ~Hierarchy();
@@ -256,6 +261,7 @@ enum KSlot : int {
   kKAlpha2 = 6, kKCoefC = 7, kKCoefD = 8,
 };
 constexpr int kMaxPartialBlocks = 2048;
+constexpr int kMaxReduce = 8;        // values one reduction may carry (partials: kMaxReduce x blocks)
 // pinned host mirror: ints 0..63 for control read-backs, then (in doubles
 // from kPinnedArn) the Arnoldi results
 constexpr int kPinnedArn = 64;
@@ -365,7 +371,7 @@ void launch_dense_inverse(int n, const int* rp, const int* ci, const double* val
 // Reduction context of the solve-phase kernels: per-block partials and the
 // arrival counter of the in-kernel finalize (zero between kernels).
 struct RedCtx {
-  double* part;       // kMaxPartialBlocks * 4 doubles
+  double* part;       // kMaxPartialBlocks * kMaxReduce doubles
   unsigned* ticket;
 };
 void arnoldi_enqueue(Hierarchy& h, const Level& lv, int m, uint32_t stream, double* Q, double* w, double* sc,

@@ -412,7 +412,7 @@ void init_control(Hierarchy& h) {
   h.d_err = h.arena.alloc_n<int>(64);
   h.d_ctl = h.arena.alloc_n<int>(kCtlWords);
   h.d_sc = h.arena.alloc_n<double>(kScWords);
-  h.d_part = h.arena.alloc_n<double>(kMaxPartialBlocks * 4);
+  h.d_part = h.arena.alloc_n<double>((size_t)kMaxPartialBlocks * kMaxReduce);
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
   h.d_mis = h.arena.alloc_n<int>(kMisWords);
   launch_fill_int(64, h.d_err, 0, h.stream);
@@ -908,6 +908,7 @@ void resetup_hierarchy(Hierarchy& h, const double* val) {
   }
   coarse_inverse(h, tmp, sy);
   sy.wait_and_check();
+  if (repoint) h.multi.reset();   // the kept block workspace's graphs read level 0's old values
   if (repoint && !h.g_iter.empty()) {
     for (auto& g : h.g_iter) (void)hipGraphExecDestroy(g);
     h.g_iter.clear();

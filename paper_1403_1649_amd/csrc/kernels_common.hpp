@@ -26,6 +26,7 @@ constexpr int kTailBlocks = 64;
 
 template <int NV, class Op>
 __device__ __forceinline__ void write_partials(double (&acc)[NV], RedCtx rc, const Op& op, bool tail) {
+  static_assert(NV <= kMaxReduce, "the partials buffer holds kMaxReduce values per block");
   __shared__ double red[NV * (kBlock / kWave)];
   __shared__ int s_last;
   block_sum<NV>(acc, red);
@@ -115,7 +116,25 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
     T sum = T(0);
     if (row < n) {
       const int s = rp[row], e = rp[row + 1];
-      for (int k = s + lane; k < e; k += LPR) sum += av[k] * op.x(ci[k]);
+      // a lane's entries four at a time: the column and value loads, then the
+      // gathers, then the products in entry order (the same sum as one entry
+      // at a time), so four gathers are in flight instead of one
+      for (int k0 = s + lane; k0 < e; k0 += 4 * LPR) {
+        int c[4];
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + q * LPR;
+          c[q] = k < e ? ci[k] : 0;
+          v[q] = k < e ? av[k] : T(0);
+        }
+        T xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = k0 + q * LPR < e ? op.x(c[q]) : T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + q * LPR < e) sum += v[q] * xv[q];
+      }
     }
     sum = group_sum<LPR>(sum);
     if (row < n && lane == 0) op.row(row, sum, acc);

@@ -307,30 +307,52 @@ struct OpApplyCorr {
   __device__ void finalize(const double*) const {}
 };
 
-// first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r)
+// first inner step: v = A c, rho1 and alpha1 (CG: c'v, c'r; GMRES: v'v, v'r),
+// and the test of the second step in the same reduction: with a = alpha1 /
+// rho1, ||r~||^2 = ||r_c - a v||^2 = r_c'r_c - 2 a v'r_c + a^2 v'v, so the
+// flag is decided here and r~ itself is formed only when the step runs
 template <typename T>
-struct OpKDots1 {   // also ||r_c||^2 for the test of the second step
-  static constexpr int NV = 3;
+struct OpKDots1 {
+  static constexpr int NV = 5;
   Act a;
   const T* c;
   const T* rcv;
   T* v;
   double* K;
+  int* F;
   int gmres;
+  double t;
   __device__ bool active() const { return a.on(); }
-  __device__ void idle() const {}
+  __device__ void idle() const { F[0] = 0; }
   __device__ T x(int j) const { return c[j]; }
   __device__ void row(int i, T ax, double* acc) const {
     v[i] = ax;
-    const double l = gmres ? (double)ax : (double)c[i];
-    acc[0] += l * (double)ax;
-    acc[1] += l * (double)rcv[i];
-    acc[2] += (double)rcv[i] * (double)rcv[i];
+    const double av = (double)ax, rr = (double)rcv[i];
+    const double l = gmres ? av : (double)c[i];
+    acc[0] += l * av;
+    acc[1] += l * rr;
+    acc[2] += rr * rr;
+    acc[3] += av * av;
+    acc[4] += av * rr;
   }
   __device__ void finalize(const double* s) const {
-    K[kKRho1] = s[0];
-    K[kKAlpha1] = s[1];
+    const double rho1 = s[0], alpha1 = s[1];
+    K[kKRho1] = rho1;
+    K[kKAlpha1] = alpha1;
     K[kKRcRc] = s[2];
+    F[1] = 0;
+    if (rho1 > 0.0) {
+      const double ar = alpha1 / rho1;
+      double rt2 = s[2] - 2.0 * ar * s[4] + ar * ar * s[3];
+      rt2 = rt2 > 0.0 ? rt2 : 0.0;
+      K[kKRtRt] = rt2;
+      K[kKCoefC] = ar;
+      F[0] = (sqrt(rt2) <= t * sqrt(s[2])) ? 0 : 1;
+    } else {
+      K[kKRtRt] = s[2];
+      K[kKCoefC] = 0.0;
+      F[0] = 0;
+    }
   }
 };
 
@@ -611,37 +633,23 @@ struct OpProlongK {
   __device__ void finalize(const double*) const {}
 };
 
-// r~ = r - (alpha1/rho1) v with ||r~||^2; decides the second inner step
+// r~ = r_c - (alpha1/rho1) v, the right-hand side of the second inner step
+// (only when that step runs)
 template <typename T>
 struct OpRtilde {
-  static constexpr int NV = 1;
+  static constexpr int NV = 0;
   Act a;
   const T* rcv;
   const T* v;
   T* rt;
-  double* K;
-  int* F;
-  double t;
+  const double* K;
   __device__ bool active() const { return a.on(); }
-  __device__ void idle() const { F[0] = 0; }
-  __device__ void elem(int i, double* acc) const {
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
     const T ar = (T)(K[kKAlpha1] / K[kKRho1]);
-    const T u = rcv[i] - ar * v[i];
-    rt[i] = u;
-    acc[0] += (double)u * (double)u;
+    rt[i] = rcv[i] - ar * v[i];
   }
-  __device__ void finalize(const double* s) const {
-    const double rho1 = K[kKRho1];
-    K[kKRtRt] = s[0];
-    F[1] = 0;
-    if (rho1 > 0.0) {
-      K[kKCoefC] = K[kKAlpha1] / rho1;
-      F[0] = (sqrt(s[0]) <= t * sqrt(K[kKRcRc])) ? 0 : 1;
-    } else {
-      K[kKCoefC] = 0.0;
-      F[0] = 0;
-    }
-  }
+  __device__ void finalize(const double*) const {}
 };
 
 struct OpHashVector {
@@ -1013,8 +1021,8 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
     launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv}, rc, s);
     cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
-    launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, gm}, rc, s);
-    launch_elem(lc.n, OpRtilde<T>{A, rcv, v, rt, K, F, h.opt.kcycle_t}, rc, s);
+    launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, F, gm, h.opt.kcycle_t}, rc, s);
+    launch_elem(lc.n, OpRtilde<T>{Act{F}, rcv, v, rt, K}, rc, s);
     cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
     launch_level<T>(lc, OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm}, rc, s);
     if (lv.n <= kFuseCorrectionRows) {

@@ -124,7 +124,25 @@ __global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, const int* __re
     const int row = g * RPB + threadIdx.x / W;
     if (row < n && c < R) {
       T sum = T(0);
-      for (int k = rp[row]; k < rp[row + 1]; ++k) sum += av[k] * op.x(ci[k], c);
+      const int e = rp[row + 1];
+      // eight entries at a time: their columns and values, then the eight
+      // gathered block rows, then the products in entry order, so the
+      // gathers of a chunk are in flight together
+      for (int k0 = rp[row]; k0 < e; k0 += 8) {
+        int cj[8];
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          cj[q] = k0 + q < e ? ci[k0 + q] : 0;
+          v[q] = k0 + q < e ? av[k0 + q] : T(0);
+        }
+        T xv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xv[q] = k0 + q < e ? op.x(cj[q], c) : T(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < e) sum += v[q] * xv[q];
+      }
       op.row(row, c, sum, acc);
     }
   }
@@ -803,34 +821,106 @@ void alloc_work(Hierarchy& h, MWork& W, int R) {
   launch_fill_int(aWords, W.m.any, 0, h.stream);
 }
 
+// The block workspace of one column count and the block iteration and
+// (re)start captured into HIP graphs: every kernel of an iteration reads its
+// device flags, so one graph serves all branches, and the workspace stays with
+// the hierarchy, so the graphs stay valid for later solves with as many columns.
+struct MultiState {
+  MWork W;
+  hipGraphExec_t g_iter = nullptr;
+  hipGraphExec_t g_restart = nullptr;
+  MultiState() = default;
+  MultiState(const MultiState&) = delete;
+  MultiState& operator=(const MultiState&) = delete;
+  ~MultiState() {
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (g_restart) (void)hipGraphExecDestroy(g_restart);
+  }
+};
+
+void capture_multi(Hierarchy& h, MultiState& st) {
+  hipStream_t user = h.stream;
+  hipStream_t cs = nullptr;
+  AMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  auto finish = [&](hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    AMG_HIP(hipStreamEndCapture(cs, &g));
+    AMG_HIP(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    AMG_HIP(hipGraphDestroy(g));
+  };
+  try {
+    h.stream = cs;
+    h.capturing = true;
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (h.mixed()) iteration_m<float>(h, st.W);
+    else iteration_m<double>(h, st.W);
+    finish(&st.g_iter);
+    AMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    if (h.mixed()) restart_m<float>(h, st.W);
+    else restart_m<double>(h, st.W);
+    finish(&st.g_restart);
+  } catch (...) {
+    h.stream = user;
+    h.capturing = false;
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  h.stream = user;
+  h.capturing = false;
+  AMG_HIP(hipStreamDestroy(cs));
+}
+
+// The workspace (and graphs) for R columns: the one kept from an earlier call
+// with as many columns, or a new one.
+MultiState& multi_state(Hierarchy& h, int R) {
+  MultiState* st = static_cast<MultiState*>(h.multi.get());
+  if (st && st->W.R == R) return *st;
+  AMG_HIP(hipStreamSynchronize(h.stream));   // the old workspace is idle before it goes
+  h.multi.reset();
+  auto ns = std::make_shared<MultiState>();
+  alloc_work(h, ns->W, R);
+  if (!(h.opt.flags & AMG_FLAG_NO_GRAPH)) capture_multi(h, *ns);
+  h.multi = ns;
+  return *ns;
+}
+
+void enqueue_iteration_m(Hierarchy& h, MultiState& st) {
+  if (st.g_iter) AMG_HIP(hipGraphLaunch(st.g_iter, h.stream));
+  else if (h.mixed()) iteration_m<float>(h, st.W);
+  else iteration_m<double>(h, st.W);
+}
+
+void enqueue_restart_m(Hierarchy& h, MultiState& st) {
+  if (st.g_restart) AMG_HIP(hipGraphLaunch(st.g_restart, h.stream));
+  else if (h.mixed()) restart_m<float>(h, st.W);
+  else restart_m<double>(h, st.W);
+}
+
 }  // namespace
 
 // Solve A X = B for R columns from X_0 = 0.  iters / relres: host arrays[R].
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres) {
   if (R < 1 || R > kMaxRhs) throw Error(AMG_EINVAL, "nrhs must be in [1, 64]");
-  MWork W;
   hipStream_t s = h.stream;
   struct Drain { hipStream_t s; ~Drain() { (void)hipStreamSynchronize(s); } } drain{s};
-  alloc_work(h, W, R);
+  MultiState& st = multi_state(h, R);
+  MWork& W = st.W;
+  launch_fill_int((size_t)fWords * R, W.m.fl, 0, s);
+  launch_fill_int(aWords, W.m.any, 0, s);
   const Level& l0 = h.levels[0];
   const int n = l0.n;
-  const bool mixed = h.mixed();
   std::vector<int> hfl((size_t)fWords * R);
   std::vector<double> hsc((size_t)mK0 * R);
   std::vector<int> again(R);
   elem_m(n, W.m, MFcgInit{ActAny{nullptr}, R, B, W.r, W.xv, W.m.sc, W.m.fl, W.m.any, W.m.err, rtol}, s);
-  if (mixed) restart_m<float>(h, W);
-  else restart_m<double>(h, W);
+  enqueue_restart_m(h, st);
   const int max_iter = h.opt.max_iter;
   int enqueued = 0;
   int status = AMG_OK;
   int* hp = static_cast<int*>(h.h_pinned);
   while (true) {
     const int batch = std::min(4, max_iter - enqueued);
-    for (int i = 0; i < batch; ++i) {
-      if (mixed) iteration_m<float>(h, W);
-      else iteration_m<double>(h, W);
-    }
+    for (int i = 0; i < batch; ++i) enqueue_iteration_m(h, st);
     enqueued += batch;
     AMG_HIP(hipGetLastError());
     AMG_HIP(hipMemcpyAsync(hp, W.m.any + aRun, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -860,8 +950,7 @@ int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* 
     if (!any_again) break;
     AMG_HIP(hipMemcpyAsync(W.again, again.data(), R * sizeof(int), hipMemcpyHostToDevice, s));
     elem_m(n, W.m, MRestartMask{ActAny{nullptr}, R, W.q, W.r, W.again, W.m.fl, W.m.any}, s);
-    if (mixed) restart_m<float>(h, W);
-    else restart_m<double>(h, W);
+    enqueue_restart_m(h, st);
   }
   AMG_HIP(hipMemcpyAsync(X, W.xv, (size_t)n * R * sizeof(double), hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));

@@ -71,3 +71,28 @@ def test_multi_rhs_bad_arguments():
     with pytest.raises(amg.AmgError) as e:
         amg.solve_multi(h, torch.from_numpy(np.ascontiguousarray(B)).cuda())
     assert e.value.code == 7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_block_graph_replay_matches_eager_launches(precision):
+    """The block iteration captured into HIP graphs (kept with the hierarchy for
+    the next solve with as many columns) gives the eager launches' results bit
+    for bit, on a first solve, a repeated one and one with another column count."""
+    A = P.hetero3d(16, seed=8)
+    rp, ci, v = to_dev(A)
+    hg = amg.setup(rp, ci, v, amg.Options(dim=3, precision=precision))
+    he = amg.setup(rp, ci, v, amg.Options(dim=3, precision=precision, flags=amg.binding.FLAG_NO_GRAPH))
+    B = torch.from_numpy(np.ascontiguousarray(_block(A, 5, seed=3))).cuda()
+    Xe, itse, relse = amg.solve_multi(he, B)
+    for _ in range(2):
+        Xg, itsg, relsg = amg.solve_multi(hg, B)
+        assert np.array_equal(itsg, itse) and np.array_equal(relsg, relse)
+        assert torch.equal(Xg, Xe)
+    B3 = B[:, :3].contiguous()
+    Xe3, itse3, _ = amg.solve_multi(he, B3)
+    Xg3, itsg3, _ = amg.solve_multi(hg, B3)
+    assert np.array_equal(itsg3, itse3) and torch.equal(Xg3, Xe3)
+    Xg5, itsg5, _ = amg.solve_multi(hg, B)
+    assert np.array_equal(itsg5, itse) and torch.equal(Xg5, Xe)
+    hg.close()
+    he.close()
