@@ -101,7 +101,8 @@ struct Level {
   float* sl_val32 = nullptr;
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
   // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets
-  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; } t64, t32;
+  // pz: plane steps of the sliced-ELL schedule (0 = contiguous)
+  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; } t64, t32;
   // setup products (absent on the coarsest level)
   uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
   uint64_t* tuple = nullptr;   // final MIS(2) tuples (state in the top two bits)

@@ -149,10 +149,15 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
 // D16: the columns come as 16-bit offsets col - row (128 bytes per wave and
 // entry instead of 256), for levels whose couplings all lie within 32767
 // rows, as on the lexicographically ordered grids.
+// pstep > 0 (plane-ordered schedule): the block steps of 4 slices form
+// planes of pstep steps (a grid plane of rows, the largest column offset of
+// the level); logical step u runs physical step (u % planes) * pstep +
+// u / planes, so a block walks the same rows plane after plane and finds the
+// entries it gathers from the next plane in the cache.  0: contiguous steps.
 template <typename T, class Op, bool D16>
 __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* __restrict__ sl_ptr,
                                                  const void* __restrict__ sl_cols, const T* __restrict__ sl_val,
-                                                 Op op, RedCtx rc) {
+                                                 Op op, RedCtx rc, int pstep) {
   if (!op.active()) {
     if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
     return;
@@ -167,9 +172,11 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
   const int per = (steps + gridDim.x - 1) / gridDim.x;
   const int t0 = xcd_logical_block() * per;
   const int t1 = min(steps, t0 + per);
-  for (int t = t0; t < t1; ++t) {
+  const int planes = pstep > 0 ? steps / pstep : 1;
+  for (int u = t0; u < t1; ++u) {
+    const int t = pstep > 0 ? (u % planes) * pstep + u / planes : u;
     const int sl = t * SPB + wv;
-    if (sl >= nslices) break;
+    if (sl >= nslices) continue;
     const int row = sl * kWave + lane;
     const int base = sl_ptr[sl];
     const int w = (sl_ptr[sl + 1] - base) / kWave;
@@ -263,15 +270,15 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
 // sl_dcol non-null: the kernel reads the 16-bit column offsets instead of sl_col.
 template <typename T, class Op>
 void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const T* sl_val, const Op& op,
-                 RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr) {
+                 RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr, int pstep = 0) {
   long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > 8) g &= ~7L;
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
-  if (sl_dcol) k_sell<T, Op, true><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_dcol, sl_val, op, r2);
-  else k_sell<T, Op, false><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, r2);
+  if (sl_dcol) k_sell<T, Op, true><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_dcol, sl_val, op, r2, pstep);
+  else k_sell<T, Op, false><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, r2, pstep);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }

@@ -813,7 +813,7 @@ void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
   const Level::Tune& t = tune_of<T>(lv);
   if (t.fmt >= 1 && lv.sl_ptr)
     launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s,
-                   t.fmt == 2 ? lv.sl_dcol : nullptr);
+                   t.fmt == 2 ? lv.sl_dcol : nullptr, t.pz);
   else launch_rows<T>(lv.n, t.lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s);
 }
 
@@ -1455,8 +1455,8 @@ std::map<TuneKey, Level::Tune>& tune_cache() {
       if (FILE* f = std::fopen(path, "r")) {
         TuneKey k{};
         Level::Tune t{};
-        while (std::fscanf(f, " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"us\": %f}",
-                           &k.n, &k.nnz, &k.bytes, &t.fmt, &t.lpr, &t.us) == 6)
+        while (std::fscanf(f, " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"pz\": %d, \"us\": %f}",
+                           &k.n, &k.nnz, &k.bytes, &t.fmt, &t.lpr, &t.pz, &t.us) == 7)
           c[k] = t;
         std::fclose(f);
       }
@@ -1468,11 +1468,31 @@ std::map<TuneKey, Level::Tune>& tune_cache() {
 void save_tune(const TuneKey& k, const Level::Tune& t) {
   if (const char* path = std::getenv("AMG_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"us\": %.3f}\n", k.n,
-                   k.nnz, k.bytes, t.fmt, t.lpr, t.us);
+      std::fprintf(f, "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"pz\": %d, \"us\": %.3f}\n",
+                   k.n, k.nnz, k.bytes, t.fmt, t.lpr, t.pz, t.us);
       std::fclose(f);
     }
   }
+}
+
+// The largest column offset col - row of a level (rows are sorted, so the
+// last entry of each row), read back to the host.
+__global__ void k_max_offset(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int e = rp[i + 1];
+    if (e > rp[i]) atomicMax(out, ci[e - 1] - i);
+  }
+}
+
+int max_column_offset(Hierarchy& h, const Level& lv) {
+  int* d = h.d_ctl + kCtlAggFill;   // scratch word, free outside the Galerkin product
+  launch_fill_int(1, d, 0, h.stream);
+  const long g = ((long)lv.n + 255) / 256;
+  k_max_offset<<<(int)(g < 4096 ? g : 4096), 256, 0, h.stream>>>(lv.n, lv.rp, lv.ci, d);
+  int v = 0;
+  AMG_HIP(hipMemcpyAsync(&v, d, sizeof(int), hipMemcpyDeviceToHost, h.stream));
+  AMG_HIP(hipStreamSynchronize(h.stream));
+  return v;
 }
 
 template <typename T>
@@ -1539,13 +1559,23 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     if (us < best.us) { best.us = us; best.fmt = 0; best.lpr = lpr; }
   }
   if (lv.sl_ptr && sell_vals<T>(lv)) {
-    const float us = time_it([&] { launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s); });
-    if (us < best.us) { best.us = us; best.fmt = 1; best.lpr = lv.lpr; }
-    if (lv.sl_dcol) {
-      const float u16 = time_it([&] {
-        launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, lv.sl_dcol);
+    // the plane-ordered schedule, when the level's largest column offset is a
+    // whole number of 4-slice steps that tiles the slices (lexicographic grids)
+    const int off = max_column_offset(h, lv);
+    const int pz = (lv.nslices % 4 == 0 && off > 0 && off % 256 == 0 && (lv.nslices / 4) % (off / 256) == 0 &&
+                    (lv.nslices / 4) / (off / 256) >= 2) ? off / 256 : 0;
+    for (int p : {0, pz}) {
+      const float us = time_it([&] {
+        launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, nullptr, p);
       });
-      if (u16 < best.us) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; }
+      if (us < best.us) { best.us = us; best.fmt = 1; best.lpr = lv.lpr; best.pz = p; }
+      if (lv.sl_dcol) {
+        const float u16 = time_it([&] {
+          launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, lv.sl_dcol, p);
+        });
+        if (u16 < best.us) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; best.pz = p; }
+      }
+      if (pz == 0) break;
     }
   }
   if (force) {
@@ -1574,8 +1604,8 @@ void autotune_levels(Hierarchy& h) {
       lv.t64 = tune_one<double>(h, lv, static_cast<double*>(lv.xt), static_cast<double*>(lv.r));
     }
     if (debug)
-      std::fprintf(stderr, "amg: tune level %d n=%d fp64 fmt=%d lpr=%d %.2f us | fp32 fmt=%d lpr=%d %.2f us\n", k,
-                   lv.n, lv.t64.fmt, lv.t64.lpr, lv.t64.us, lv.t32.fmt, lv.t32.lpr, lv.t32.us);
+      std::fprintf(stderr, "amg: tune level %d n=%d fp64 fmt=%d lpr=%d pz=%d %.2f us | fp32 fmt=%d lpr=%d pz=%d %.2f us\n",
+                   k, lv.n, lv.t64.fmt, lv.t64.lpr, lv.t64.pz, lv.t64.us, lv.t32.fmt, lv.t32.lpr, lv.t32.pz, lv.t32.us);
   }
 }
 

@@ -20,7 +20,7 @@ namespace amg {
 namespace {
 
 constexpr int kMaxRhs = 64;
-constexpr int kMultiBlocks = 512;
+constexpr int kMultiBlocks = 2048;   // reducing block kernels: blocks (and partials per total)
 
 // per-column scalar slots: slot s of column c at sc[s * R + c]
 enum : int {
@@ -42,6 +42,8 @@ struct MCtx {
   int* any;
   double* part;
   int* err;
+  double* tot;        // totals of a reduction, NV * R
+  unsigned* ticket;   // arrival counter of the finalize blocks (zero between kernels)
 };
 
 struct ActAny {
@@ -74,26 +76,45 @@ __device__ __forceinline__ void write_partials_m(double (&acc)[NV], int R, doubl
   }
 }
 
-// per-column totals (fixed block order), then the op's per-column and
-// all-column finalizers
+// Per-column totals, then the op's per-column and all-column finalizers.
+// One block per (value, column) total: its threads add the partials of blocks
+// t, t + 256, ... in order and a fixed block reduction combines them, so the
+// totals do not depend on timing; the last block to arrive (a ticket counter,
+// after a release fence of the one value each block wrote) runs the
+// finalizers on all totals.
+constexpr int kFinMBlock = 256;
 template <class Op>
-__global__ void __launch_bounds__(kWave) k_finalize_m(Op op, const double* __restrict__ part, int nb, int R) {
+__global__ void __launch_bounds__(kFinMBlock) k_finalize_m(Op op, const double* __restrict__ part, int nb, int R,
+                                                           double* tot, unsigned* ticket) {
   if (!op.active()) return;
   constexpr int NV = Op::NV;
-  const int c = threadIdx.x;
-  if (c < R) {
-    double v[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      const double* p = part + ((size_t)k * R + c) * nb;
-      for (int b = 0; b < nb; ++b) s += p[b];
-      v[k] = s;
-    }
-    op.finalize(c, v);
+  __shared__ double red[kFinMBlock / kWave];
+  __shared__ int s_last;
+  const int q = blockIdx.x;
+  const double* p = part + (size_t)q * nb;
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += kFinMBlock) v[0] += p[b];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) {
+    tot[q] = v[0];
+    __threadfence();
+    s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
   }
   __syncthreads();
-  if (c == 0) op.finalize_all();
+  if (!s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int c = threadIdx.x;
+  if (c < R) {
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = __hip_atomic_load(&tot[k * R + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    op.finalize(c, t);
+  }
+  __syncthreads();
+  if (c == 0) {
+    op.finalize_all();
+    *ticket = 0u;
+  }
 }
 
 __device__ __forceinline__ int xcd_block() {
@@ -185,14 +206,14 @@ template <typename T, int W, class Op>
 void rows_m_w(int n, const MCtx& m, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
   const int g = grid_m(n, W, Op::NV > 0);
   k_rows_m<T, W, Op><<<g, kBlock, 0, s>>>(n, m.R, rp, ci, av, op, m.part);
-  if constexpr (Op::NV > 0) k_finalize_m<Op><<<1, kWave, 0, s>>>(op, m.part, g, m.R);
+  if constexpr (Op::NV > 0) k_finalize_m<Op><<<Op::NV * m.R, kFinMBlock, 0, s>>>(op, m.part, g, m.R, m.tot, m.ticket);
 }
 
 template <int W, class Op>
 void elem_m_w(int n, const MCtx& m, const Op& op, hipStream_t s) {
   const int g = grid_m(n, W, Op::NV > 0);
   k_elem_m<W, Op><<<g, kBlock, 0, s>>>(n, m.R, op, m.part);
-  if constexpr (Op::NV > 0) k_finalize_m<Op><<<1, kWave, 0, s>>>(op, m.part, g, m.R);
+  if constexpr (Op::NV > 0) k_finalize_m<Op><<<Op::NV * m.R, kFinMBlock, 0, s>>>(op, m.part, g, m.R, m.tot, m.ticket);
 }
 
 inline int width_of(int R) {
@@ -428,30 +449,43 @@ struct MProlongK {
   __device__ void finalize(int, const double*) const {}
 };
 
-// coarsest level: X_L = A_L^-1 B_L on the FP64 matrix cores, one wave per
-// 16 x 16 tile of X (rows x right-hand sides), k in steps of 4 over the
-// inverse's columns (zero-padded); operands of the FP32 cycle are widened.
+// coarsest level: X_L = A_L^-1 B_L on the FP64 matrix cores, one block per
+// 16 x 16 tile of X (rows x right-hand sides); the block's four waves split
+// the inner dimension (in steps of 4 over the inverse's columns, zero-padded)
+// into four contiguous parts and their accumulators are added in wave order
+// through LDS.  Operands of the FP32 cycle are widened.
+constexpr int kGemmSplit = kBlock / kWave;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gemm_coarse(int n, int R, const double* __restrict__ Ainv,
                                                         const T* __restrict__ B, T* __restrict__ X, ActAny a) {
   if (!a.on()) return;
+  __shared__ double part[kGemmSplit][4][kWave];
   const int tiles_c = (R + 15) / 16;
-  const int wt = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  if (wt >= ((n + 15) / 16) * tiles_c) return;
+  const int tile = blockIdx.x;
+  const int w = threadIdx.x / kWave;
   const int l = threadIdx.x & (kWave - 1);
-  const int R0 = (wt / tiles_c) * 16, C0 = (wt % tiles_c) * 16;
+  const int R0 = (tile / tiles_c) * 16, C0 = (tile % tiles_c) * 16;
   const int ar = R0 + (l & 15), bc = C0 + (l & 15);
+  const int ksteps = (n + 3) / 4;
+  const int per = (ksteps + kGemmSplit - 1) / kGemmSplit;
+  const int k0 = w * per * 4, k1 = min(n, (w + 1) * per * 4);
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < n; k += 4) {
+  for (int k = k0; k < k1; k += 4) {
     const int kk = k + (l >> 4);
-    const double av = (ar < n && kk < n) ? Ainv[(size_t)ar * n + kk] : 0.0;
-    const double bv = (bc < R && kk < n) ? (double)B[(size_t)kk * R + bc] : 0.0;
+    const double av = (ar < n && kk < k1) ? Ainv[(size_t)ar * n + kk] : 0.0;
+    const double bv = (bc < R && kk < k1) ? (double)B[(size_t)kk * R + bc] : 0.0;
     acc = mfma_f64_16x16x4(av, bv, acc);
   }
 #pragma unroll
+  for (int i = 0; i < 4; ++i) part[w][i][l] = acc[i];
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
   for (int i = 0; i < 4; ++i) {
+    double v = part[0][i][l];
+    for (int q = 1; q < kGemmSplit; ++q) v += part[q][i][l];
     const int row = R0 + mfma_row(l, i), col = C0 + mfma_col(l);
-    if (row < n && col < R) X[(size_t)row * R + col] = (T)acc[i];
+    if (row < n && col < R) X[(size_t)row * R + col] = (T)v;
   }
 }
 
@@ -698,9 +732,8 @@ struct MWork {
 template <typename T>
 void coarse_m(Hierarchy& h, const MCtx& m, const T* b, T* x, const int* act) {
   const int n = h.levels.back().n;
-  const int wpb = kBlock / kWave;
   const int tiles = ((n + 15) / 16) * ((m.R + 15) / 16);
-  k_gemm_coarse<T><<<(tiles + wpb - 1) / wpb, kBlock, 0, h.stream>>>(n, m.R, h.cinv, b, x, ActAny{act});
+  k_gemm_coarse<T><<<tiles, kBlock, 0, h.stream>>>(n, m.R, h.cinv, b, x, ActAny{act});
 }
 
 template <typename T>
@@ -815,6 +848,9 @@ void alloc_work(Hierarchy& h, MWork& W, int R) {
   W.m.fl = W.arena.alloc_n<int>((size_t)fWords * R);
   W.m.any = W.arena.alloc_n<int>(aWords);
   W.m.part = W.arena.alloc_n<double>((size_t)3 * R * kMultiBlocks);
+  W.m.tot = W.arena.alloc_n<double>((size_t)3 * R);
+  W.m.ticket = W.arena.alloc_n<unsigned>(64);
+  launch_fill_int(64, reinterpret_cast<int*>(W.m.ticket), 0, h.stream);
   W.m.err = h.d_err;
   W.again = W.arena.alloc_n<int>(kMaxRhs);
   launch_fill_int((size_t)fWords * R, W.m.fl, 0, h.stream);
