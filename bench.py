@@ -148,13 +148,14 @@ def cold_start(amg, torch, dev, dim, b):
 def multi_rhs_form(amg, torch, P, reps=2):
     """C4a: 3-D anisotropic 96^3 (eps_z = 1e-3), 32 right-hand sides.  One
     mixed-precision setup + one block solve against one plain FP64 setup + 32
-    single solves; MDOF/s counts n * 32."""
+    single solves; MDOF/s counts n * 32.  column_tiles: the autotuner's columns
+    per pass of the block kernels per level (last: the FP64 level-0 products)."""
     A = P.aniso3d(96, 1e-3)
     R = 32
     Xs = P.multi_exact_solution(A.n, R, 1)
     Bm = torch.from_numpy(np.ascontiguousarray(P.rhs(A, Xs))).cuda()
     dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
-    best_b, best_s = None, None
+    best_b, best_s, tile_ms = None, None, None
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -162,6 +163,8 @@ def multi_rhs_form(amg, torch, P, reps=2):
         X, its, rels = amg.solve_multi(h, Bm, 1e-8)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        tiles, tms = h.multi_tiles(R)
+        tile_ms = tms if tile_ms is None else tile_ms   # the first (uncached) choice
         h.close()
         t0 = time.perf_counter()
         h = amg.setup(*dev, amg.Options(dim=3))
@@ -178,7 +181,8 @@ def multi_rhs_form(amg, torch, P, reps=2):
     return {"workload": "C4a 96^3 anisotropic, 32 RHS", "mdof_s": round(A.n * R / best_b / 1e6, 3) if ok else 0.0,
             "ms": round(best_b * 1e3, 2), "sequential_fp64_ms": round(best_s * 1e3, 2),
             "speedup_vs_sequential": round(best_s / best_b, 3), "iters_max": int(its.max()),
-            "iters_sequential_max": int(max(its_s)), "relres_max": float(rels.max())}
+            "iters_sequential_max": int(max(its_s)), "relres_max": float(rels.max()),
+            "column_tiles": tiles, "tile_tune_ms": round(tile_ms, 2)}
 
 
 def batch_form(amg, torch, P, reps=2):

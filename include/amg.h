@@ -184,6 +184,20 @@ int32_t amg_solve(amg_hierarchy* h, const double* b, double rtol, double* x,
 int32_t amg_solve_multi(amg_hierarchy* h, int32_t nrhs, const double* B, double rtol, double* X,
                         int32_t* iters, double* relres, hipStream_t s);
 
+/* Column tiles the autotuner chose for the block solve with nrhs columns
+ * (the one amg_solve_multi last ran on h; its workspace is kept for the next
+ * solve with as many columns).  The block kernels take a row's entries once
+ * per tile of columns: W = pow2(nrhs) is one pass, W/2 or W/4 two or four
+ * passes over A with a narrower gathered working set (Section 3: the sparse
+ * products of the cycle, here for a block of vectors).
+ * tiles: (host) int32[cap] with cap >= amg_num_levels(h); tiles[k] for the
+ * cycle's kernels on level k's rows (k < amg_num_levels(h) - 1), and
+ * tiles[amg_num_levels(h) - 1] for the FP64 level-0 products of the outer
+ * iteration.  tune_ms (host, may be NULL): host time of the choice (near 0
+ * when it came from the cache).  EINVAL when the last block solve had
+ * another column count, or none ran, or cap is too small. */
+int32_t amg_multi_tiles(const amg_hierarchy* h, int32_t nrhs, int32_t* tiles, int32_t cap, double* tune_ms);
+
 /* Independent systems in one hierarchy, each set up and solved as if alone
  * (Algorithm 1 and the solve of Algorithms 4/5 applied per system).  A is
  * their block-diagonal matrix: system q owns rows and columns

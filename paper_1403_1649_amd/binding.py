@@ -27,6 +27,7 @@ EXPORTED = [
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
     "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
     "amg_setup_phases", "amg_galerkin_noalloc", "amg_resetup", "amg_resetup_time", "amg_level_colors", "amg_learned_judge",
+    "amg_multi_tiles",
 ]
 
 
@@ -140,6 +141,8 @@ def lib():
     L.amg_level_format.restype = i32
     L.amg_setup_phases.argtypes = [vp, P(dbl), P(dbl)]
     L.amg_setup_phases.restype = i32
+    L.amg_multi_tiles.argtypes = [vp, i32, P(i32), i32, P(dbl)]
+    L.amg_multi_tiles.restype = i32
     L.amg_release_cached_memory.argtypes = []
     L.amg_release_cached_memory.restype = C.c_size_t
     _LIB = L
@@ -314,6 +317,15 @@ class Hierarchy:
         t, g = C.c_double(), C.c_double()
         _check(lib().amg_setup_phases(self._h, C.byref(t), C.byref(g)))
         return t.value, g.value
+
+    def multi_tiles(self, nrhs: int):
+        """(column tile per level, then of the FP64 level-0 products; tuner ms) of the
+        block solve with nrhs columns."""
+        cap = self.num_levels()
+        t = (C.c_int32 * cap)()
+        ms = C.c_double()
+        _check(lib().amg_multi_tiles(self._h, nrhs, t, cap, C.byref(ms)))
+        return list(t), ms.value
 
     def smoother_info(self, k: int):
         """(learned?, validation loss with plain omega, with learned weights)."""

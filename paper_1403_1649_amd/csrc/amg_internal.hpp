@@ -99,10 +99,12 @@ struct Level {
   int* sl_wide = nullptr;
   double* sl_val = nullptr;
   float* sl_val32 = nullptr;
+  long sl_total = 0;           // stored sliced-ELL elements (64 x the longest row, summed over slices)
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
   // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets
   // pz: plane steps of the sliced-ELL schedule (0 = contiguous)
-  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; } t64, t32;
+  // tile: columns per pass of the block kernels (several right-hand sides)
+  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; int tile = 0; } t64, t32;
   // setup products (absent on the coarsest level)
   uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
   uint64_t* tuple = nullptr;   // final MIS(2) tuples (state in the top two bits)
@@ -384,6 +386,16 @@ void arnoldi(Hierarchy& h, Level& lv, int m, uint32_t stream, double* Q, double*
 int solve_fcg_impl(Hierarchy& h, const double* b, double rtol, double* x, int* iters, double* relres);
 void build_solve_graphs(Hierarchy& h);
 void autotune_levels(Hierarchy& h);
+// Autotuner cache, per process and (AMG_TUNE_CACHE) across processes: one
+// decision per level shape, value size and column count.  rowstat: the
+// level's sliced-ELL element count, which measures how uneven its rows are.
+struct TuneKey {
+  int n = 0, nnz = 0, bytes = 0, nrhs = 1;
+  long rowstat = 0;
+  bool operator<(const TuneKey& o) const;
+};
+bool tune_cache_get(const TuneKey& k, Level::Tune* t);
+void tune_cache_put(const TuneKey& k, const Level::Tune& t);
 int mlp_num_params();
 void mlp_features(Hierarchy& h, const Level& lv, int level, float* F, double* beta);
 void mlp_omega(Hierarchy& h, const Level& lv, const float* F, const double* beta, const float* wdev, double* omega,
@@ -394,6 +406,7 @@ double mlp_loss_grad(Hierarchy& h, Arena& tmp, const Level& lv, int level, const
 void mlp_adam(float* w, float* m, float* v, const float* g, int n, int step, float lr, float b1, float b2, float eps,
               hipStream_t s);
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres);
+int multi_tiles(const Hierarchy& h, int R, int* tiles, int cap, double* tune_ms);
 // batch.hip: independent systems on the block diagonal
 void batch_blocks(Hierarchy& h, Level& lv);
 void batch_local_base(const Level& lv, int* lbase, hipStream_t s);

@@ -452,6 +452,13 @@ int32_t amg_setup_phases(const amg_hierarchy* H, double* tune_ms, double* captur
   return AMG_OK;
 }
 
+int32_t amg_multi_tiles(const amg_hierarchy* H, int32_t nrhs, int32_t* tiles, int32_t cap, double* tune_ms) {
+  if (!H || !tiles) return fail(AMG_EINVAL, "amg_multi_tiles: NULL argument");
+  const int rc = amg::multi_tiles(H->h, nrhs, tiles, cap, tune_ms);
+  if (rc != AMG_OK) return fail(rc, "amg_multi_tiles: no block solve with this column count, or cap too small");
+  return AMG_OK;
+}
+
 int32_t amg_mlp_num_params(void) { return amg::mlp_num_params(); }
 
 static bool level_ok(const amg_hierarchy* H, int32_t k) {

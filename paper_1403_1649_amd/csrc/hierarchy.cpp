@@ -279,6 +279,7 @@ void sell_begin(Hierarchy& h, Arena& tmp, Level& lv, Sync& sy, int slot) {
 // Second half; the 16-bit offsets stay usable only if the flag read back in
 // pinned slot `slot` at the next wait of `sy` is clear (sell_take_wide).
 void sell_finish(Hierarchy& h, Level& lv, size_t total, Sync& sy, int slot) {
+  lv.sl_total = (long)total;
   lv.sl_col = h.arena.alloc_n<int>(total);
   lv.sl_dcol = h.arena.alloc_n<int16_t>(total);
   lv.sl_wide = h.arena.alloc_n<int>(1);

@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 
 #include "kernels_common.hpp"
 
@@ -1439,12 +1440,6 @@ int fgmres(Hierarchy& h, const double* b, double rtol, double* x, int* iters, do
 }
 
 // ------------------------------------------------------------ autotuner
-struct TuneKey {
-  int n, nnz, bytes;
-  bool operator<(const TuneKey& o) const {
-    return n != o.n ? n < o.n : (nnz != o.nnz ? nnz < o.nnz : bytes < o.bytes);
-  }
-};
 std::mutex g_tune_mu;
 std::map<TuneKey, Level::Tune>& tune_cache() {
   static auto& c = *new std::map<TuneKey, Level::Tune>();   // never destroyed (no exit-time destructor)
@@ -1455,8 +1450,10 @@ std::map<TuneKey, Level::Tune>& tune_cache() {
       if (FILE* f = std::fopen(path, "r")) {
         TuneKey k{};
         Level::Tune t{};
-        while (std::fscanf(f, " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"pz\": %d, \"us\": %f}",
-                           &k.n, &k.nnz, &k.bytes, &t.fmt, &t.lpr, &t.pz, &t.us) == 7)
+        while (std::fscanf(f,
+                           " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"nrhs\": %d, \"rowstat\": %ld, \"fmt\": %d, "
+                           "\"lpr\": %d, \"pz\": %d, \"tile\": %d, \"us\": %f}",
+                           &k.n, &k.nnz, &k.bytes, &k.nrhs, &k.rowstat, &t.fmt, &t.lpr, &t.pz, &t.tile, &t.us) == 10)
           c[k] = t;
         std::fclose(f);
       }
@@ -1465,15 +1462,36 @@ std::map<TuneKey, Level::Tune>& tune_cache() {
   return c;
 }
 
-void save_tune(const TuneKey& k, const Level::Tune& t) {
+}  // namespace
+
+bool TuneKey::operator<(const TuneKey& o) const {
+  return std::tie(n, nnz, bytes, nrhs, rowstat) < std::tie(o.n, o.nnz, o.bytes, o.nrhs, o.rowstat);
+}
+
+bool tune_cache_get(const TuneKey& k, Level::Tune* t) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto& c = tune_cache();
+  auto it = c.find(k);
+  if (it == c.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+void tune_cache_put(const TuneKey& k, const Level::Tune& t) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_cache()[k] = t;
   if (const char* path = std::getenv("AMG_TUNE_CACHE")) {
     if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"fmt\": %d, \"lpr\": %d, \"pz\": %d, \"us\": %.3f}\n",
-                   k.n, k.nnz, k.bytes, t.fmt, t.lpr, t.pz, t.us);
+      std::fprintf(f,
+                   "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"nrhs\": %d, \"rowstat\": %ld, \"fmt\": %d, "
+                   "\"lpr\": %d, \"pz\": %d, \"tile\": %d, \"us\": %.3f}\n",
+                   k.n, k.nnz, k.bytes, k.nrhs, k.rowstat, t.fmt, t.lpr, t.pz, t.tile, t.us);
       std::fclose(f);
     }
   }
 }
+
+namespace {
 
 // The largest column offset col - row of a level (rows are sorted, so the
 // last entry of each row), read back to the host.
@@ -1506,10 +1524,12 @@ struct OpFillT {
   __device__ void finalize(const double*) const {}
 };
 
-// Time y = A x for CSR with 2..32 lanes per row and for sliced ELL with 32-
-// and 16-bit columns; keep the fastest (AMG_TUNE_FORCE = csr, sell or sell16
-// pins the format where the level has it, for tests).  Results are cached per (n, nnz, value size) for the process and,
-// when AMG_TUNE_CACHE names a file, across processes (one JSON object per line).
+// Time the pre-smoothing kernel for CSR with 2..32 lanes per row and for
+// sliced ELL with 32- and 16-bit columns (contiguous and plane-ordered); keep
+// the fastest (AMG_TUNE_FORCE = csr, sell or sell16 pins the format where the
+// level has it, for tests).  Results are cached per level shape (n, nnz,
+// sliced-ELL size) and value size for the process and, when AMG_TUNE_CACHE
+// names a file, across processes (one JSON object per line).
 template <typename T>
 Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   if (lv.n <= kFuseCorrectionRows) {
@@ -1522,13 +1542,16 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     while (t.lpr < 32 && (long)t.lpr * lv.n < lv.nnz) t.lpr <<= 1;
     return t;
   }
-  TuneKey key{lv.n, lv.nnz, (int)sizeof(T)};
+  TuneKey key;
+  key.n = lv.n;
+  key.nnz = lv.nnz;
+  key.bytes = (int)sizeof(T);
+  key.nrhs = 1;
+  key.rowstat = lv.sl_total;
   const char* force = std::getenv("AMG_TUNE_FORCE");
   if (!force) {
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    auto& c = tune_cache();
-    auto it = c.find(key);
-    if (it != c.end()) return it->second;
+    Level::Tune t;
+    if (tune_cache_get(key, &t)) return t;
   }
   hipStream_t s = h.stream;
   RedCtx rc = red(h);
@@ -1585,9 +1608,7 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     else if (w == "sell16" && lv.sl_dcol) best.fmt = 2;
     return best;   // not cached
   }
-  std::lock_guard<std::mutex> g(g_tune_mu);
-  tune_cache()[key] = best;
-  save_tune(key, best);
+  tune_cache_put(key, best);
   return best;
 }
 

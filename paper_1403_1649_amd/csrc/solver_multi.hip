@@ -3,13 +3,18 @@
 // Each matrix row is handled by W = pow2(R) lanes, lane c owning column c:
 // the row's values and columns are loaded once (a broadcast within the lane
 // group) and the gathered X rows are contiguous, so A is streamed once for
-// all R columns.  Every scalar of the K-cycle and of the outer iteration is
+// all R columns.  Per level, an autotuner may instead split the columns into
+// tiles of W/2 or W/4 (one pass over A each), where the narrower gathered
+// working set stays in the caches.  Every scalar of the K-cycle and of the outer iteration is
 // per column, and so is the K-cycle branch: the second inner step runs when
 // any column needs it, and only the columns that need it use its result, so
 // each column follows exactly the arithmetic of a single-column solve.
 // Converged columns stop updating; kernels stop when no column is running.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 #include <vector>
 
@@ -51,8 +56,9 @@ struct ActAny {
   __device__ __forceinline__ bool on() const { return p == nullptr || *p != 0; }
 };
 
+// per-block partials of columns c0 .. c0 + W - 1
 template <int NV, int W>
-__device__ __forceinline__ void write_partials_m(double (&acc)[NV], int R, double* part) {
+__device__ __forceinline__ void write_partials_m(double (&acc)[NV], int R, int c0, double* part) {
   __shared__ double red[NV][kBlock / kWave][W];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -66,12 +72,12 @@ __device__ __forceinline__ void write_partials_m(double (&acc)[NV], int R, doubl
   }
   __syncthreads();
   const int c = threadIdx.x;
-  if (c < W && c < R) {
+  if (c < W && c0 + c < R) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
       for (int w = 0; w < kBlock / kWave; ++w) s += red[k][w][c];
-      part[((size_t)k * R + c) * gridDim.x + blockIdx.x] = s;
+      part[((size_t)k * R + c0 + c) * gridDim.x + blockIdx.x] = s;
     }
   }
 }
@@ -123,9 +129,9 @@ __device__ __forceinline__ int xcd_block() {
   return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-// rows of A times the block, W lanes per row
+// rows of A times columns c0 .. c0 + W - 1 of the block, W lanes per row
 template <typename T, int W, class Op>
-__global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, const int* __restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, int c0, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const T* __restrict__ av,
                                                    Op op, double* part) {
   if (!op.active()) {
@@ -134,14 +140,19 @@ __global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, const int* __re
   }
   constexpr int NV = Op::NV > 0 ? Op::NV : 1;
   constexpr int RPB = kBlock / W;
-  const int c = threadIdx.x & (W - 1);
+  const int c = c0 + (threadIdx.x & (W - 1));
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  // The blocks of one XCD (block ids congruent mod 8) own a contiguous eighth
+  // of the row groups and sweep it side by side, group j, j + blocks, ...:
+  // the rows they gather at any time lie in one window of the XCD's L2.
   const int groups = (n + RPB - 1) / RPB;
-  const int per = (groups + gridDim.x - 1) / gridDim.x;
-  const int g0 = xcd_block() * per, g1 = min(groups, g0 + per);
-  for (int g = g0; g < g1; ++g) {
+  const int nx = (gridDim.x >= 8 && !(gridDim.x & 7)) ? 8 : 1;
+  const int bpx = gridDim.x / nx;
+  const int gpx = (groups + nx - 1) / nx;
+  const int gbeg = (blockIdx.x % nx) * gpx, gend = min(groups, gbeg + gpx);
+  for (int g = gbeg + blockIdx.x / nx; g < gend; g += bpx) {
     const int row = g * RPB + threadIdx.x / W;
     if (row < n && c < R) {
       T sum = T(0);
@@ -167,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_m(int n, int R, const int* __re
       op.row(row, c, sum, acc);
     }
   }
-  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, part);
+  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, c0, part);
 }
 
 template <int W, class Op>
@@ -189,7 +200,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_m(int n, int R, Op op, double* 
     const int i = g * RPB + threadIdx.x / W;
     if (i < n && c < R) op.elem(i, c, acc);
   }
-  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, part);
+  if constexpr (Op::NV > 0) write_partials_m<Op::NV, W>(acc, R, 0, part);
 }
 
 inline int grid_m(int n, int W, bool reduce) {
@@ -202,10 +213,13 @@ inline int grid_m(int n, int W, bool reduce) {
   return (int)g;
 }
 
+// The columns in tiles of W (one pass over the rows per tile, so a tile's
+// gathered block rows are a narrower working set in the caches), then the
+// totals of all columns.
 template <typename T, int W, class Op>
 void rows_m_w(int n, const MCtx& m, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
   const int g = grid_m(n, W, Op::NV > 0);
-  k_rows_m<T, W, Op><<<g, kBlock, 0, s>>>(n, m.R, rp, ci, av, op, m.part);
+  for (int c0 = 0; c0 < m.R; c0 += W) k_rows_m<T, W, Op><<<g, kBlock, 0, s>>>(n, m.R, c0, rp, ci, av, op, m.part);
   if constexpr (Op::NV > 0) k_finalize_m<Op><<<Op::NV * m.R, kFinMBlock, 0, s>>>(op, m.part, g, m.R, m.tot, m.ticket);
 }
 
@@ -222,9 +236,10 @@ inline int width_of(int R) {
   return w;
 }
 
+// tile: columns per pass (a power of two; 0 = all columns in one pass)
 template <typename T, class Op>
-void rows_m(int n, const MCtx& m, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
-  switch (width_of(m.R)) {
+void rows_m(int n, const MCtx& m, int tile, const int* rp, const int* ci, const T* av, const Op& op, hipStream_t s) {
+  switch (tile > 0 ? std::min(tile, width_of(m.R)) : width_of(m.R)) {
     case 1: rows_m_w<T, 1>(n, m, rp, ci, av, op, s); break;
     case 2: rows_m_w<T, 2>(n, m, rp, ci, av, op, s); break;
     case 4: rows_m_w<T, 4>(n, m, rp, ci, av, op, s); break;
@@ -673,6 +688,20 @@ struct MTrueResid {
   __device__ void finalize(int c, const double* s) const { sc[mTrue * R + c] = s[0]; }
 };
 
+// Y = A X: the kernel the block autotuner times
+template <typename T>
+struct MSpmvT {
+  static constexpr int NV = 0;
+  ActAny a;
+  int R;
+  const T* xin;
+  T* y;
+  M_COMMON
+  __device__ T x(int j, int c) const { return xin[(size_t)j * R + c]; }
+  __device__ void row(int i, int c, T ax, double*) const { y[(size_t)i * R + c] = ax; }
+  __device__ void finalize(int, const double*) const {}
+};
+
 // restart the columns whose recurrence converged but whose true residual did
 // not: r = b - A x for them, running again
 struct MRestartMask {
@@ -722,6 +751,9 @@ struct MWork {
   int R = 0;
   Arena arena;
   std::vector<MLevel> lv;
+  std::vector<int> tile;    // per level: columns per pass of the cycle's block kernels (0 = all)
+  int tile0 = 0;            // ... of the FP64 level-0 products of the outer iteration
+  double tune_ms = 0.0;     // host time of choosing them
   double *r = nullptr, *p = nullptr, *q = nullptr, *xv = nullptr, *rtrue = nullptr;
   void* z = nullptr;
   void* bz = nullptr;
@@ -754,10 +786,12 @@ void cycle_m(Hierarchy& h, MWork& W, int k, const T* b, T* xo, const int* act) {
   const T* wd = wdinv_t<T>(lv);
   const T* pv = pvals_t<T>(lv);
   const ActAny A{act};
-  rows_m<T>(lv.n, m, lv.rp, lv.ci, vals_t<T>(lv), MPresmoothResid<T>{A, R, b, wd, xt, r}, s);
+  const int tk = W.tile[k];                                  // columns per pass on level k's rows
+  const int tc = k + 1 < L ? W.tile[k + 1] : 0;              // ... and on level k+1's
+  rows_m<T>(lv.n, m, tk, lv.rp, lv.ci, vals_t<T>(lv), MPresmoothResid<T>{A, R, b, wd, xt, r}, s);
   const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
   if (!kcyc) {
-    rows_m<T>(lv.nc, m, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, false>{A, R, r, rcv, nullptr}, s);
+    rows_m<T>(lv.nc, m, tk, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, false>{A, R, r, rcv, nullptr}, s);
     if (k + 1 == L) coarse_m<T>(h, m, rcv, c, act);
     else cycle_m<T>(h, W, k + 1, rcv, c, act);
     elem_m(lv.n, m, MProlong<T>{A, R, lv.agg, pv, c, xt}, s);
@@ -771,15 +805,15 @@ void cycle_m(Hierarchy& h, MWork& W, int k, const T* b, T* xo, const int* act) {
     T* d = static_cast<T*>(ml.d);
     T* w = static_cast<T*>(ml.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    rows_m<T>(lv.nc, m, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, true>{A, R, r, rcv, K}, s);
+    rows_m<T>(lv.nc, m, tk, lv.agg_ptr, lv.agg_rows, rvals_t<T>(lv), MRestrict<T, true>{A, R, r, rcv, K}, s);
     cycle_m<T>(h, W, k + 1, rcv, c, act);
-    rows_m<T>(lc.n, m, lc.rp, lc.ci, vals_t<T>(lc), MKDots1<T>{A, R, c, rcv, v, K, gm}, s);
+    rows_m<T>(lc.n, m, tc, lc.rp, lc.ci, vals_t<T>(lc), MKDots1<T>{A, R, c, rcv, v, K, gm}, s);
     elem_m(lc.n, m, MRtilde<T>{A, R, rcv, v, rt, K, F, any2, h.opt.kcycle_t}, s);
     cycle_m<T>(h, W, k + 1, rt, d, any2);
-    rows_m<T>(lc.n, m, lc.rp, lc.ci, vals_t<T>(lc), MKDots2<T>{ActAny{any2}, R, d, v, rt, w, K, F, gm}, s);
+    rows_m<T>(lc.n, m, tc, lc.rp, lc.ci, vals_t<T>(lc), MKDots2<T>{ActAny{any2}, R, d, v, rt, w, K, F, gm}, s);
     elem_m(lv.n, m, MProlongK<T>{A, R, lv.agg, pv, c, d, xt, K, F}, s);
   }
-  rows_m<T>(lv.n, m, lv.rp, lv.ci, vals_t<T>(lv), MResidSmooth<T>{A, R, b, xt, wd, xo}, s);
+  rows_m<T>(lv.n, m, tk, lv.rp, lv.ci, vals_t<T>(lv), MResidSmooth<T>{A, R, b, xt, wd, xo}, s);
 }
 
 template <typename T>
@@ -801,7 +835,7 @@ void iteration_m(Hierarchy& h, MWork& W) {
   const int* run = m.any + aRun;
   const ActAny A{run};
   hipStream_t s = h.stream;
-  rows_m<double>(n, m, l0.rp, l0.ci, l0.val, MFcgSpmv{A, R, W.p, W.r, W.q, m.sc, m.fl, m.any, m.err}, s);
+  rows_m<double>(n, m, W.tile0, l0.rp, l0.ci, l0.val, MFcgSpmv{A, R, W.p, W.r, W.q, m.sc, m.fl, m.any, m.err}, s);
   elem_m(n, m, MFcgUpdate{A, R, W.p, W.q, W.xv, W.r, m.sc, m.fl, m.any, m.err}, s);
   precondition_m<T>(h, W, run);
   elem_m(n, m, MDotZQ<T>{A, R, static_cast<const T*>(W.z), W.q, m.sc}, s);
@@ -821,6 +855,7 @@ void alloc_work(Hierarchy& h, MWork& W, int R) {
   W.R = R;
   const int L = h.L();
   W.lv.assign(std::max(L, 1), MLevel{});
+  W.tile.assign(std::max(L, 1), 0);
   for (int k = 0; k < L; ++k) {
     const Level& lv = h.levels[k];
     MLevel& ml = W.lv[k];
@@ -855,6 +890,81 @@ void alloc_work(Hierarchy& h, MWork& W, int R) {
   W.again = W.arena.alloc_n<int>(kMaxRhs);
   launch_fill_int((size_t)fWords * R, W.m.fl, 0, h.stream);
   launch_fill_int(aWords, W.m.any, 0, h.stream);
+}
+
+// Columns per pass of the block row kernels, per level and arithmetic type:
+// the pre-smoothing-sized product Y = A_k X timed with all W = pow2(R)
+// columns in one pass and in tiles of W/2 and W/4 (at least 8 columns), the
+// fastest kept (ties to the wider tile).  Small levels, latency-bound, take
+// all columns.  Cached like the single-vector choices, keyed by the column
+// count as well; AMG_TUNE_FORCE_TILE = 8, 16, ... pins the tile (for tests).
+constexpr int kTileTuneRows = 65536;
+
+template <typename T>
+int tune_tile(Hierarchy& h, const Level& lv, const MWork& W, T* x, T* y) {
+  const int R = W.R, wf = width_of(R);
+  if (const char* f = std::getenv("AMG_TUNE_FORCE_TILE")) {
+    const int t = std::atoi(f);
+    return (t > 0 && (t & (t - 1)) == 0) ? std::min(t, wf) : 0;
+  }
+  if (lv.n <= kTileTuneRows || wf < 16) return 0;
+  TuneKey key;
+  key.n = lv.n;
+  key.nnz = lv.nnz;
+  key.bytes = (int)sizeof(T);
+  key.nrhs = R;
+  key.rowstat = lv.sl_total;
+  Level::Tune t;
+  if (tune_cache_get(key, &t)) return t.tile;
+  hipStream_t s = h.stream;
+  AMG_HIP(hipMemsetAsync(x, 0, (size_t)lv.n * R * sizeof(T), s));
+  const T* av = vals_t<T>(lv);
+  const MSpmvT<T> op{ActAny{nullptr}, R, x, y};
+  hipEvent_t e0 = h.ev[2], e1 = h.ev[3];
+  float best_us = 1e30f;
+  int best = wf;
+  for (int tw = wf; tw >= 8 && tw * 4 >= wf; tw >>= 1) {
+    rows_m<T>(lv.n, W.m, tw, lv.rp, lv.ci, av, op, s);
+    float us = 1e30f;
+    for (int trial = 0; trial < 2; ++trial) {
+      AMG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 4; ++r) rows_m<T>(lv.n, W.m, tw, lv.rp, lv.ci, av, op, s);
+      AMG_HIP(hipEventRecord(e1, s));
+      AMG_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      us = std::min(us, ms * 1000.f / 4);
+    }
+    if (std::getenv("AMG_DEBUG"))
+      std::fprintf(stderr, "amg: block tile n=%d R=%d bytes=%d tile=%d: %.2f us\n", lv.n, R, (int)sizeof(T), tw, us);
+    if (us < best_us * 0.98f) {
+      best_us = us;
+      best = tw;
+    }
+  }
+  t = Level::Tune{};
+  t.tile = best == wf ? 0 : best;
+  t.us = best_us;
+  tune_cache_put(key, t);
+  return t.tile;
+}
+
+void tune_tiles(Hierarchy& h, MWork& W) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int L = h.L();
+  for (int k = 0; k < L; ++k) {
+    const Level& lv = h.levels[k];
+    const MLevel& ml = W.lv[k];
+    W.tile[k] = h.mixed() ? tune_tile<float>(h, lv, W, static_cast<float*>(ml.xt), static_cast<float*>(ml.r))
+                          : tune_tile<double>(h, lv, W, static_cast<double*>(ml.xt), static_cast<double*>(ml.r));
+  }
+  if (L > 0) W.tile0 = h.mixed() ? tune_tile<double>(h, h.levels[0], W, W.p, W.q) : W.tile[0];
+  AMG_HIP(hipStreamSynchronize(h.stream));
+  W.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (std::getenv("AMG_DEBUG")) {
+    for (int k = 0; k < L; ++k) std::fprintf(stderr, "amg: block tile level %d R=%d: %d\n", k, W.R, W.tile[k]);
+    std::fprintf(stderr, "amg: block tile level 0 fp64 R=%d: %d (%.1f ms)\n", W.R, W.tile0, W.tune_ms);
+  }
 }
 
 // The block workspace of one column count and the block iteration and
@@ -915,6 +1025,7 @@ MultiState& multi_state(Hierarchy& h, int R) {
   h.multi.reset();
   auto ns = std::make_shared<MultiState>();
   alloc_work(h, ns->W, R);
+  if (!(h.opt.flags & AMG_FLAG_NO_TUNE)) tune_tiles(h, ns->W);
   if (!(h.opt.flags & AMG_FLAG_NO_GRAPH)) capture_multi(h, *ns);
   h.multi = ns;
   return *ns;
@@ -933,6 +1044,21 @@ void enqueue_restart_m(Hierarchy& h, MultiState& st) {
 }
 
 }  // namespace
+
+// The column tiles of the block solve with R columns (its workspace must be
+// the hierarchy's current one): tiles[k], k < L, for the cycle's kernels on
+// level k's rows, tiles[L] for the FP64 level-0 products of the outer
+// iteration; a tile of W = pow2(R) is one pass over all columns.
+int multi_tiles(const Hierarchy& h, int R, int* tiles, int cap, double* tune_ms) {
+  const MultiState* st = static_cast<const MultiState*>(h.multi.get());
+  const int L = h.L();
+  if (!st || st->W.R != R || cap < L + 1) return AMG_EINVAL;
+  const int wf = width_of(R);
+  for (int k = 0; k < L; ++k) tiles[k] = st->W.tile[k] > 0 ? st->W.tile[k] : wf;
+  tiles[L] = st->W.tile0 > 0 ? st->W.tile0 : wf;
+  if (tune_ms) *tune_ms = st->W.tune_ms;
+  return AMG_OK;
+}
 
 // Solve A X = B for R columns from X_0 = 0.  iters / relres: host arrays[R].
 int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* X, int* iters, double* relres) {
@@ -968,7 +1094,7 @@ int solve_multi_impl(Hierarchy& h, int R, const double* B, double rtol, double* 
       throw Error(AMG_EHIP, "device error bits " + std::to_string(hp[1]));
     }
     if (hp[0] && enqueued < max_iter) continue;
-    rows_m<double>(n, W.m, l0.rp, l0.ci, l0.val, MTrueResid{ActAny{nullptr}, R, B, W.xv, W.q, W.m.sc}, s);
+    rows_m<double>(n, W.m, W.tile0, l0.rp, l0.ci, l0.val, MTrueResid{ActAny{nullptr}, R, B, W.xv, W.q, W.m.sc}, s);
     AMG_HIP(hipMemcpyAsync(hfl.data(), W.m.fl, hfl.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipMemcpyAsync(hsc.data(), W.m.sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     AMG_HIP(hipStreamSynchronize(s));

@@ -96,3 +96,64 @@ def test_block_graph_replay_matches_eager_launches(precision):
     assert np.array_equal(itsg5, itse) and torch.equal(Xg5, Xe)
     hg.close()
     he.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("tile", [8, 16])
+def test_column_tiles_match_one_pass(precision, tile, monkeypatch):
+    """The block kernels in tiles of 8 or 16 of the 32 columns (forced; the
+    autotuner's candidates) take the same entries in the same order per row as
+    one pass over all columns: every column converges as in the one-pass solve
+    (iterations within one, same solution to the tolerance's accuracy) and as
+    the oracle's single-column solve."""
+    A = P.hetero3d(18, seed=6)
+    rp, ci, v = to_dev(A)
+    B = _block(A, 32, seed=3)
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    h1 = amg.setup(rp, ci, v, amg.Options(dim=3, precision=precision))
+    X1, its1, rels1 = amg.solve_multi(h1, Bd, 1e-8)
+    L = h1.num_levels()
+    assert h1.multi_tiles(32)[0] == [32] * L
+    monkeypatch.setenv("AMG_TUNE_FORCE_TILE", str(tile))
+    h2 = amg.setup(rp, ci, v, amg.Options(dim=3, precision=precision))
+    X2, its2, rels2 = amg.solve_multi(h2, Bd, 1e-8)
+    assert h2.multi_tiles(32)[0] == [tile] * L
+    X1, X2 = X1.cpu().numpy(), X2.cpu().numpy()
+    S = A.to_scipy()
+    for c in range(32):
+        assert rels2[c] <= 1e-8 and abs(its2[c] - its1[c]) <= 1, (c, its2[c], its1[c])
+        assert np.linalg.norm(B[:, c] - S @ X2[:, c]) <= 1.01e-8 * np.linalg.norm(B[:, c])
+        assert np.linalg.norm(X2[:, c] - X1[:, c]) <= 1e-6 * np.linalg.norm(X1[:, c])
+    H = O.setup(A.row_ptr, A.col, A.val, O.Options.for_dim(3))
+    for c in (0, 17, 31):
+        ref = O.solve(H, B[:, c], 1e-8)
+        assert abs(its2[c] - ref.iters) <= 1
+        assert np.linalg.norm(X2[:, c] - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    with pytest.raises(amg.AmgError):
+        h2.multi_tiles(31)        # no block solve with 31 columns on this hierarchy
+    h1.close()
+    h2.close()
+
+
+def test_column_tile_autotuner_on_a_large_level():
+    """On a level above the tuning threshold (110,592 rows) the autotuner
+    times 32, 16 and 8 columns per pass and keeps one; the solve converges
+    with it, and a second hierarchy of the same shape takes the cached choice."""
+    A = P.poisson3d(48)
+    rp, ci, v = to_dev(A)
+    B = _block(A, 32, seed=4)
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    h = amg.setup(rp, ci, v, amg.Options(dim=3, precision="mixed"))
+    X, its, rels = amg.solve_multi(h, Bd, 1e-8)
+    tiles, ms = h.multi_tiles(32)
+    assert tiles[0] in (8, 16, 32) and tiles[-1] in (8, 16, 32) and ms > 0.0
+    X = X.cpu().numpy()
+    S = A.to_scipy()
+    for c in range(32):
+        assert rels[c] <= 1e-8
+        assert np.linalg.norm(B[:, c] - S @ X[:, c]) <= 1.01e-8 * np.linalg.norm(B[:, c])
+    h2 = amg.setup(rp, ci, v, amg.Options(dim=3, precision="mixed"))
+    amg.solve_multi(h2, Bd, 1e-8)
+    assert h2.multi_tiles(32)[0] == tiles
+    h.close()
+    h2.close()
