@@ -86,9 +86,11 @@ def measured_traffic(workload: str):
 
 
 def kernel_name(fmt: int, lpr: int, op: str) -> str:
+    """lpr: lanes per row (for the sliced ELL, 64 / slice height)."""
+    h = 64 // max(lpr, 1)
     if fmt == 2:
-        return f"k_sell<double,{op},true> (sliced ELL, 16-bit column offsets)"
-    return f"k_sell<double,{op},false>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"
+        return f"k_sell<double,{op},true,{h}> (sliced ELL in {h}-row slices, 16-bit column offsets)"
+    return f"k_sell<double,{op},false,{h}>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"
 
 
 def run_form(amg, torch, dev, A, dim, b, steps, warmup, **opt):

@@ -100,11 +100,27 @@ struct Level {
   double* sl_val = nullptr;
   float* sl_val32 = nullptr;
   long sl_total = 0;           // stored sliced-ELL elements (64 x the longest row, summed over slices)
+  // a second sliced-ELL copy in shorter slices (h = 32 or 16 rows, 64/h lanes
+  // per row) over rows ordered by length within 256-row windows, built for
+  // the autotuner on levels whose rows vary in length and kept while it is
+  // the chosen kernel; its memory is held by sh_mem
+  struct ShortSell {
+    int h = 0, nslices = 0;
+    long total = 0;
+    int* perm = nullptr;       // slot -> row: each 256-row window by decreasing row length
+    int* ptr = nullptr;
+    int* col = nullptr;
+    int16_t* dcol = nullptr;
+    double* val = nullptr;
+    float* val32 = nullptr;
+  } sh;
+  std::shared_ptr<Arena> sh_mem;
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
   // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets
   // pz: plane steps of the sliced-ELL schedule (0 = contiguous)
   // tile: columns per pass of the block kernels (several right-hand sides)
-  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; int tile = 0; } t64, t32;
+  // sh: slice height of the sliced-ELL copy used (0 = the 64-row copy)
+  struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; int tile = 0; int sh = 0; } t64, t32;
   // setup products (absent on the coarsest level)
   uint8_t* strong = nullptr;   // strength mask C over A_k's pattern
   uint64_t* tuple = nullptr;   // final MIS(2) tuples (state in the top two bits)
@@ -343,9 +359,15 @@ void launch_state_from_tuple(int n, const uint64_t* T, int8_t* state, hipStream_
 void launch_fill_int(size_t n, int* p, int v, hipStream_t s);
 void launch_fill_double(size_t n, double* p, double v, hipStream_t s);
 void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s);
-void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s);
+// sliced ELL in slices of slice_h = 64, 32 or 16 rows
+// (perm: slot -> row, null for rows in order)
+void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s, int slice_h = 64,
+                        const int* perm = nullptr);
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
-                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s);
+                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s,
+                      int slice_h = 64, const int* perm = nullptr);
+// rows of each 256-row window by decreasing length; perm: ceil(n/256)*256 slots
+void launch_window_order(int n, const int* rp, int* perm, hipStream_t s);
 
 // galerkin.hip: scratch of one Galerkin product (n fine rows, nnz entries,
 // nc coarse rows): lens[n], inv[n], toff[n+1], tkey[nnz], tval[nnz],
@@ -447,6 +469,9 @@ void launch_rs_fill(const Level& lv, const Level& lc, int* cur, int* tf, int* ti
 void launch_rs_values(const Level& lv, Level& lc, hipStream_t s);
 void launch_rs_diag(const Level& lv, hipStream_t s);
 void launch_rs_sell_values(const Level& lv, hipStream_t s);
+// the short-slice copy of a level, when it pays (slice_h = 0) or in slices of
+// slice_h = 32 or 16 rows (hierarchy.cpp)
+void build_short_sell(Hierarchy& h, Level& lv, int slice_h);
 void launch_set16(double* dst, const double* host16, hipStream_t s);
 // coloring.hip: first-fit colouring by node-hash priority in synchronous rounds
 void launch_color_round(int n, const int* rp, const int* ci, uint32_t stream, const int* cin, int* cout, int* left,

@@ -324,6 +324,54 @@ void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y, b
   sy.wait_and_check();
 }
 
+// The short-slice copy of a level whose rows vary in length: the rows of
+// every 256-row window ordered by decreasing length, then slices of 16 rows
+// (4 lanes per row) where rows average at least 12 entries, else of 32; built
+// when it stores at least kShortSellGain fewer elements than the 64-row copy
+// in row order.  slice_h = 32 or 16 builds that height regardless (tests).
+// Its memory is an arena of its own, released when the level drops the copy.
+constexpr double kShortSellGain = 0.08;
+
+void build_short_sell(Hierarchy& h, Level& lv, int slice_h) {
+  lv.sh = Level::ShortSell{};
+  lv.sh_mem.reset();
+  if (lv.n <= 0 || !lv.sl_ptr) return;
+  const bool forced = slice_h == 32 || slice_h == 16;
+  const int H = forced ? slice_h : (lv.nnz >= 12L * lv.n ? 16 : 32);
+  auto mem = std::make_shared<Arena>();
+  const int nwin = (lv.n + 255) / 256;
+  const int nsl = (lv.n + H - 1) / H;
+  int* perm = mem->alloc_n<int>((size_t)nwin * 256);
+  int* widths = mem->alloc_n<int>(nsl);
+  int* ptr = mem->alloc_n<int>(nsl + 1);
+  launch_window_order(lv.n, lv.rp, perm, h.stream);
+  launch_sell_widths(lv.n, lv.rp, widths, h.stream, H, perm);
+  scan_to_ptr(widths, ptr, nsl, h.scan, h.stream);
+  Sync sy{h};
+  sy.fetch(ptr + nsl, 0);
+  sy.wait_and_check();
+  const long total = sy.hp()[0];
+  if (std::getenv("AMG_DEBUG"))
+    std::fprintf(stderr, "amg: sliced ELL elements n=%d nnz=%d: 64 rows in order %ld, %d rows by length %ld\n", lv.n,
+                 lv.nnz, lv.sl_total, H, total);
+  if (!forced && (double)total > (1.0 - kShortSellGain) * (double)lv.sl_total) return;
+  Level::ShortSell sh;
+  sh.h = H;
+  sh.nslices = nsl;
+  sh.total = total;
+  sh.perm = perm;
+  sh.ptr = ptr;
+  const size_t t = (size_t)std::max(total, 1L);
+  sh.col = mem->alloc_n<int>(t);
+  sh.dcol = lv.sl_dcol ? mem->alloc_n<int16_t>(t) : nullptr;   // the offsets fit: they do in the 64-row copy
+  sh.val = mem->alloc_n<double>(t);
+  sh.val32 = h.mixed() ? mem->alloc_n<float>(t) : nullptr;
+  launch_sell_fill(lv.n, sh.nslices, lv.rp, lv.ci, lv.val, sh.ptr, sh.col, sh.dcol, nullptr, sh.val, sh.val32,
+                   h.stream, sh.h, sh.perm);
+  lv.sh = sh;
+  lv.sh_mem = mem;
+}
+
 namespace {
 
 void make_float_copies(Hierarchy& h) {

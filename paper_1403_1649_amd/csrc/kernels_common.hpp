@@ -142,22 +142,30 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
 
-// Sliced ELL with slices of 64 rows (one wave): slice s holds its rows
-// column-major, element (row s*64 + l, k) at sl_ptr[s] + 64 k + l, padded
-// with zero values that point at the row itself.  One thread per row, so
-// every value and column load of a wave is one contiguous 512 / 256 bytes.
+// Sliced ELL with slices of H rows (H = 64, 32 or 16): slice s holds the rows
+// of slots s*H .. s*H + H - 1 column-major, element (slot s*H + l, k) at
+// sl_ptr[s] + H k + l, padded with zero values that point at the row itself.
+// Slot i holds row perm[i] (perm null: row i); the copies in shorter slices
+// order the rows of each 256-row window by decreasing length, so a slice's
+// rows are of nearly equal length and the padding small.  One wave per slice
+// and G = 64/H lanes per row: lane j*H + l takes entries j, j + G, ... of the
+// row in slot l, so every value and column load of a wave is one contiguous
+// run of 64 elements; the G partial sums are added by lane exchange (lane xor
+// H, 2H, ...).
 // D16: the columns come as 16-bit offsets col - row (128 bytes per wave and
 // entry instead of 256), for levels whose couplings all lie within 32767
 // rows, as on the lexicographically ordered grids.
-// pstep > 0 (plane-ordered schedule): the block steps of 4 slices form
-// planes of pstep steps (a grid plane of rows, the largest column offset of
-// the level); logical step u runs physical step (u % planes) * pstep +
+// pstep > 0 (plane-ordered schedule, H = 64): the block steps of 4 slices
+// form planes of pstep steps (a grid plane of rows, the largest column offset
+// of the level); logical step u runs physical step (u % planes) * pstep +
 // u / planes, so a block walks the same rows plane after plane and finds the
 // entries it gathers from the next plane in the cache.  0: contiguous steps.
-template <typename T, class Op, bool D16>
+template <typename T, class Op, bool D16, int H = kWave>
 __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* __restrict__ sl_ptr,
                                                  const void* __restrict__ sl_cols, const T* __restrict__ sl_val,
-                                                 Op op, RedCtx rc, int pstep) {
+                                                 const int* __restrict__ perm, Op op, RedCtx rc, int pstep) {
+  static_assert(H == 64 || H == 32 || H == 16, "slice height");
+  constexpr int G = kWave / H;   // lanes per row
   if (!op.active()) {
     if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
     return;
@@ -167,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
   for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
   constexpr int SPB = kBlock / kWave;   // slices per block step
   const int lane = threadIdx.x & (kWave - 1);
+  const int j = lane / H;               // this lane's entries: j, j + G, j + 2G, ...
   const int wv = threadIdx.x / kWave;
   const int steps = (nslices + SPB - 1) / SPB;
   const int per = (steps + gridDim.x - 1) / gridDim.x;
@@ -177,37 +186,44 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
     const int t = pstep > 0 ? (u % planes) * pstep + u / planes : u;
     const int sl = t * SPB + wv;
     if (sl >= nslices) continue;
-    const int row = sl * kWave + lane;
+    const int slot = sl * H + (lane & (H - 1));
+    const int row = perm ? perm[slot] : slot;
     const int base = sl_ptr[sl];
-    const int w = (sl_ptr[sl + 1] - base) / kWave;
+    const int w = (sl_ptr[sl + 1] - base) / H;
     T sum = T(0);
     const int* cp = static_cast<const int*>(sl_cols) + base + lane;
     const int16_t* dp = static_cast<const int16_t*>(sl_cols) + base + lane;
     const T* vp = sl_val + base + lane;
-    // chunks of 8 entries: all column and value loads of a chunk, then all
-    // gathers, then the FMAs in entry order, so a chunk costs one round trip
-    for (int k0 = 0; k0 < w; k0 += 8) {
+    // chunks of 8 entries per lane: all column and value loads of a chunk,
+    // then all gathers, then the FMAs in entry order, so a chunk costs one
+    // round trip.  Entry k0 + G q + j of the row sits at H k0 + 64 q + lane.
+    for (int k0 = 0; k0 < w; k0 += 8 * G) {
       int c[8];
       T v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const bool in = k0 + q < w;
-        if constexpr (D16) c[q] = in ? row + (int)dp[(k0 + q) * kWave] : 0;
-        else c[q] = in ? cp[(k0 + q) * kWave] : 0;
+        const bool in = k0 + G * q + j < w;
+        const int off = H * k0 + kWave * q;
+        if constexpr (D16) c[q] = in ? row + (int)dp[off] : 0;
+        else c[q] = in ? cp[off] : 0;
         // the values stream through once per pass: non-temporal loads keep
         // them from displacing what the next kernels reuse from the caches
         // (the coarse levels' data in the Infinity Cache); 128^3 Poisson
         // solve 9.20 -> 8.92 ms
-        v[q] = in ? __builtin_nontemporal_load(vp + (k0 + q) * kWave) : T(0);
+        v[q] = in ? __builtin_nontemporal_load(vp + off) : T(0);
       }
       T xv[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) xv[q] = k0 + q < w ? op.x(c[q]) : T(0);
+      for (int q = 0; q < 8; ++q) xv[q] = k0 + G * q + j < w ? op.x(c[q]) : T(0);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (k0 + q < w) sum += v[q] * xv[q];
+        if (k0 + G * q + j < w) sum += v[q] * xv[q];
     }
-    if (row < n) op.row(row, sum, acc);
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int o = H; o < kWave; o <<= 1) sum += __shfl_xor(sum, o, kWave);
+    }
+    if (row < n && j == 0) op.row(row, sum, acc);
   }
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
@@ -268,17 +284,35 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
 }
 
 // sl_dcol non-null: the kernel reads the 16-bit column offsets instead of sl_col.
+template <typename T, class Op, bool D16, int H>
+void launch_sell_h(int g, int n, int nslices, const int* sl_ptr, const void* cols, const T* sl_val, const int* perm,
+                   const Op& op, RedCtx r2, hipStream_t s, int pstep) {
+  k_sell<T, Op, D16, H><<<g, kBlock, 0, s>>>(n, nslices, sl_ptr, cols, sl_val, perm, op, r2,
+                                             H == kWave ? pstep : 0);
+}
+
+// slice_h: the slice height of the copy (64, 32 or 16 rows); perm: its row
+// order (null: rows in order)
 template <typename T, class Op>
 void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const T* sl_val, const Op& op,
-                 RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr, int pstep = 0) {
+                 RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr, int pstep = 0, int slice_h = kWave,
+                 const int* perm = nullptr) {
   long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
   if (g < 1) g = 1;
   if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > 8) g &= ~7L;
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
-  if (sl_dcol) k_sell<T, Op, true><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_dcol, sl_val, op, r2, pstep);
-  else k_sell<T, Op, false><<<(int)g, kBlock, 0, s>>>(n, nslices, sl_ptr, sl_col, sl_val, op, r2, pstep);
+  const void* cols = sl_dcol ? static_cast<const void*>(sl_dcol) : static_cast<const void*>(sl_col);
+  if (sl_dcol) {
+    if (slice_h == 32) launch_sell_h<T, Op, true, 32>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    else if (slice_h == 16) launch_sell_h<T, Op, true, 16>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    else launch_sell_h<T, Op, true, 64>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+  } else {
+    if (slice_h == 32) launch_sell_h<T, Op, false, 32>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    else if (slice_h == 16) launch_sell_h<T, Op, false, 16>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    else launch_sell_h<T, Op, false, 64>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+  }
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }

@@ -93,21 +93,24 @@ __global__ void __launch_bounds__(kT) k_rs_diag(int n, const int* __restrict__ r
   }
 }
 
-// New values of the sliced-ELL copy (the slice layout and the columns stay):
-// element (row, k) of slice s at sl_ptr[s] + 64 k + lane, zero padding.
+// New values of a sliced-ELL copy (the slice layout and the columns stay):
+// element (slot s*H + l, k) at sl_ptr[s] + H k + l, zero padding; slot i
+// holds row perm[i] (perm null: row i).
+template <int H>
 __global__ void __launch_bounds__(kT) k_rs_sell_values(int n, int nslices, const int* __restrict__ rp,
                                                        const double* __restrict__ val,
-                                                       const int* __restrict__ sl_ptr, double* __restrict__ sl_val,
-                                                       float* __restrict__ sl_val32) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  const int sl = row / kWave, l = row & (kWave - 1);
+                                                       const int* __restrict__ sl_ptr, const int* __restrict__ perm,
+                                                       double* __restrict__ sl_val, float* __restrict__ sl_val32) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = slot / H, l = slot & (H - 1);
   if (sl >= nslices) return;
+  const int row = perm ? perm[slot] : slot;
   const int base = sl_ptr[sl];
-  const int w = (sl_ptr[sl + 1] - base) / kWave;
+  const int w = (sl_ptr[sl + 1] - base) / H;
   const int s0 = row < n ? rp[row] : 0;
   const int len = row < n ? rp[row + 1] - s0 : 0;
   for (int k = 0; k < w; ++k) {
-    const int idx = base + k * kWave + l;
+    const int idx = base + k * H + l;
     const double v = k < len ? val[s0 + k] : 0.0;
     sl_val[idx] = v;
     if (sl_val32) sl_val32[idx] = (float)v;
@@ -150,8 +153,17 @@ void launch_rs_diag(const Level& lv, hipStream_t s) {
 
 void launch_rs_sell_values(const Level& lv, hipStream_t s) {
   if (lv.nslices > 0 && lv.sl_val)
-    k_rs_sell_values<<<(lv.nslices * kWave + kT - 1) / kT, kT, 0, s>>>(lv.n, lv.nslices, lv.rp, lv.val, lv.sl_ptr,
-                                                                       lv.sl_val, lv.sl_val32);
+    k_rs_sell_values<64><<<(lv.nslices * kWave + kT - 1) / kT, kT, 0, s>>>(lv.n, lv.nslices, lv.rp, lv.val,
+                                                                           lv.sl_ptr, nullptr, lv.sl_val,
+                                                                           lv.sl_val32);
+  const Level::ShortSell& q = lv.sh;   // the copy in shorter slices, when the level keeps one
+  if (q.nslices > 0 && q.val) {
+    const int g = (int)(((long)q.nslices * q.h + kT - 1) / kT);
+    if (q.h == 32)
+      k_rs_sell_values<32><<<g, kT, 0, s>>>(lv.n, q.nslices, lv.rp, lv.val, q.ptr, q.perm, q.val, q.val32);
+    else
+      k_rs_sell_values<16><<<g, kT, 0, s>>>(lv.n, q.nslices, lv.rp, lv.val, q.ptr, q.perm, q.val, q.val32);
+  }
 }
 
 }  // namespace amg

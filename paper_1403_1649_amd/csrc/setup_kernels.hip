@@ -587,47 +587,86 @@ __global__ void k_state_from_tuple(int n, const uint64_t* __restrict__ T, int8_t
 }
 
 // Sliced ELL: slice width = longest row of its 64 rows (one wave per slice).
-__global__ void k_sell_widths(int n, const int* __restrict__ rp, int* __restrict__ widths) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+// Per slice of H slots, H x its longest row (the slice's element count); slot
+// i holds row perm[i] (perm null: row i).
+template <int H>
+__global__ void k_sell_widths(int n, int nsl, const int* __restrict__ rp, const int* __restrict__ perm,
+                              int* __restrict__ widths) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = perm && slot < nsl * H ? perm[slot] : slot;
   int len = row < n ? rp[row + 1] - rp[row] : 0;
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
+  for (int off = H / 2; off > 0; off >>= 1) {
     const int o = __shfl_xor(len, off, kWave);
     len = o > len ? o : len;
   }
-  if ((threadIdx.x & (kWave - 1)) == 0) widths[row / kWave] = len * kWave;
+  if ((threadIdx.x & (H - 1)) == 0 && slot / H < nsl) widths[slot / H] = len * H;
 }
 
-// Fill the slices: entry k of row s*64+l at sl_ptr[s] + 64 k + l; padding
-// (short rows and the rows past n in the last slice) has value 0 and a valid
-// column (the row itself, or n - 1 past the end).  sl_dcol holds col - row
-// in 16 bits; an offset that does not fit raises *wide (the 16-bit copy is
-// then unusable).
+// The row order of the copies in shorter slices: within each window of 256
+// rows, rows by decreasing length (ties by index), a bitonic sort of
+// (length, index) keys in LDS.  perm has a whole number of windows; its slots
+// past n get indices >= n (padding).
+constexpr int kOrderWindow = 64;
+__global__ void __launch_bounds__(256) k_window_order(int n, const int* __restrict__ rp, int* __restrict__ perm) {
+  __shared__ uint32_t key[256];
+  const int t = threadIdx.x;
+  const int w0 = blockIdx.x * 256;
+  const int row = w0 + t;
+  const int len = row < n ? rp[row + 1] - rp[row] : 0;
+  // longer rows first; rows past n (length key 0xFFFF) last
+  const uint32_t lk = row < n ? 0xFFFEu - (uint32_t)min(len, 0xFFFE) : 0xFFFFu;
+  key[t] = (lk << 16) | (uint32_t)t;   // t: the index in the block; windows sort within themselves
+  for (int k = 2; k <= kOrderWindow; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+      const int p = t ^ j;
+      if (p > t) {
+        const uint32_t a = key[t], b = key[p];
+        const bool up = k == kOrderWindow || (t & k) == 0;   // every window ends ascending
+        if ((a > b) == up) {
+          key[t] = b;
+          key[p] = a;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  perm[w0 + t] = w0 + (int)(key[t] & 0xFFFFu);
+}
+
+// Fill the slices: entry k of the row in slot s*H+l at sl_ptr[s] + H k + l;
+// padding (short rows and the slots past n) has value 0 and a valid column
+// (the row itself, or n - 1 past the end).  sl_dcol (may be null)
+// holds col - row in 16 bits; an offset that does not fit raises *wide (the
+// 16-bit copy is then unusable).
+template <int H>
 __global__ void k_sell_fill(int n, int nslices, const int* __restrict__ rp, const int* __restrict__ ci,
                             const double* __restrict__ val, const int* __restrict__ sl_ptr,
-                            int* __restrict__ sl_col, int16_t* __restrict__ sl_dcol, int* __restrict__ wide,
-                            double* __restrict__ sl_val, float* __restrict__ sl_val32) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  const int sl = row / kWave, l = row & (kWave - 1);
+                            const int* __restrict__ perm, int* __restrict__ sl_col, int16_t* __restrict__ sl_dcol,
+                            int* __restrict__ wide, double* __restrict__ sl_val, float* __restrict__ sl_val32) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = slot / H, l = slot & (H - 1);
   if (sl >= nslices) return;
+  const int row = perm ? perm[slot] : slot;
   const int base = sl_ptr[sl];
-  const int w = (sl_ptr[sl + 1] - base) / kWave;
+  const int w = (sl_ptr[sl + 1] - base) / H;
   const int s0 = row < n ? rp[row] : 0;
   const int len = row < n ? rp[row + 1] - s0 : 0;
   bool fits = true;
   for (int k = 0; k < w; ++k) {
-    const int idx = base + k * kWave + l;
+    const int idx = base + k * H + l;
     int c = row < n ? row : n - 1;
     double v = 0.0;
     if (k < len) { c = ci[s0 + k]; v = val[s0 + k]; }
     sl_col[idx] = c;
     const int d = c - row;
     fits = fits && d >= -32768 && d <= 32767;
-    sl_dcol[idx] = (int16_t)d;
+    if (sl_dcol) sl_dcol[idx] = (int16_t)d;
     sl_val[idx] = v;
     if (sl_val32) sl_val32[idx] = (float)v;
   }
-  if (!fits) atomicOr(wide, 1);
+  if (!fits && wide) atomicOr(wide, 1);
 }
 
 __global__ void k_gather_double(int m, const int* __restrict__ idx, const double* __restrict__ src,
@@ -848,14 +887,29 @@ void launch_fill_int(size_t n, int* p, int v, hipStream_t s) {
   k_fill_int<<<(int)(g < 8192 ? g : 8192), kT, 0, s>>>(n, p, v);
 }
 
-void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s) {
-  const int nsl = (n + kWave - 1) / kWave;
-  k_sell_widths<<<(nsl * kWave + kT - 1) / kT, kT, 0, s>>>(n, rp, widths);
+void launch_sell_widths(int n, const int* rp, int* widths, hipStream_t s, int slice_h, const int* perm) {
+  const int nsl = (n + slice_h - 1) / slice_h;
+  const int g = (int)(((long)nsl * slice_h + kT - 1) / kT);
+  if (slice_h == 32) k_sell_widths<32><<<g, kT, 0, s>>>(n, nsl, rp, perm, widths);
+  else if (slice_h == 16) k_sell_widths<16><<<g, kT, 0, s>>>(n, nsl, rp, perm, widths);
+  else k_sell_widths<64><<<g, kT, 0, s>>>(n, nsl, rp, perm, widths);
 }
 void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const double* val, const int* sl_ptr,
-                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s) {
-  k_sell_fill<<<(nslices * kWave + kT - 1) / kT, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, sl_col, sl_dcol,
-                                                             wide, sl_val, sl_val32);
+                      int* sl_col, int16_t* sl_dcol, int* wide, double* sl_val, float* sl_val32, hipStream_t s,
+                      int slice_h, const int* perm) {
+  const int g = (int)(((long)nslices * slice_h + kT - 1) / kT);
+  if (slice_h == 32)
+    k_sell_fill<32><<<g, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, perm, sl_col, sl_dcol, wide, sl_val,
+                                     sl_val32);
+  else if (slice_h == 16)
+    k_sell_fill<16><<<g, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, perm, sl_col, sl_dcol, wide, sl_val,
+                                     sl_val32);
+  else
+    k_sell_fill<64><<<g, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, perm, sl_col, sl_dcol, wide, sl_val,
+                                     sl_val32);
+}
+void launch_window_order(int n, const int* rp, int* perm, hipStream_t s) {
+  if (n > 0) k_window_order<<<(n + 255) / 256, 256, 0, s>>>(n, rp, perm);
 }
 void launch_gather_double(int m, const int* idx, const double* src, double* dst, hipStream_t s) {
   if (m > 0) k_gather_double<<<grid_for(m), kT, 0, s>>>(m, idx, src, dst);

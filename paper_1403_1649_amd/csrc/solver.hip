@@ -807,12 +807,19 @@ template <> const Level::Tune& tune_of<float>(const Level& l) { return l.t32; }
 template <typename T> const T* sell_vals(const Level& l);
 template <> const double* sell_vals<double>(const Level& l) { return l.sl_val; }
 template <> const float* sell_vals<float>(const Level& l) { return l.sl_val32; }
+template <typename T> const T* short_vals(const Level& l);
+template <> const double* short_vals<double>(const Level& l) { return l.sh.val; }
+template <> const float* short_vals<float>(const Level& l) { return l.sh.val32; }
 
-// A row operation on A_k with the level's tuned kernel (CSR or sliced ELL).
+// A row operation on A_k with the level's tuned kernel (CSR, or sliced ELL
+// in 64-row slices or in the level's shorter slices).
 template <typename T, class Op>
 void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
   const Level::Tune& t = tune_of<T>(lv);
-  if (t.fmt >= 1 && lv.sl_ptr)
+  if (t.fmt >= 1 && t.sh > 0 && t.sh == lv.sh.h && short_vals<T>(lv))
+    launch_sell<T>(lv.n, lv.sh.nslices, lv.sh.ptr, lv.sh.col, short_vals<T>(lv), op, rc, s,
+                   t.fmt == 2 ? lv.sh.dcol : nullptr, 0, lv.sh.h, lv.sh.perm);
+  else if (t.fmt >= 1 && lv.sl_ptr)
     launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s,
                    t.fmt == 2 ? lv.sl_dcol : nullptr, t.pz);
   else launch_rows<T>(lv.n, t.lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s);
@@ -1452,8 +1459,9 @@ std::map<TuneKey, Level::Tune>& tune_cache() {
         Level::Tune t{};
         while (std::fscanf(f,
                            " {\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"nrhs\": %d, \"rowstat\": %ld, \"fmt\": %d, "
-                           "\"lpr\": %d, \"pz\": %d, \"tile\": %d, \"us\": %f}",
-                           &k.n, &k.nnz, &k.bytes, &k.nrhs, &k.rowstat, &t.fmt, &t.lpr, &t.pz, &t.tile, &t.us) == 10)
+                           "\"lpr\": %d, \"pz\": %d, \"sh\": %d, \"tile\": %d, \"us\": %f}",
+                           &k.n, &k.nnz, &k.bytes, &k.nrhs, &k.rowstat, &t.fmt, &t.lpr, &t.pz, &t.sh, &t.tile,
+                           &t.us) == 11)
           c[k] = t;
         std::fclose(f);
       }
@@ -1484,8 +1492,8 @@ void tune_cache_put(const TuneKey& k, const Level::Tune& t) {
     if (FILE* f = std::fopen(path, "a")) {
       std::fprintf(f,
                    "{\"n\": %d, \"nnz\": %d, \"bytes\": %d, \"nrhs\": %d, \"rowstat\": %ld, \"fmt\": %d, "
-                   "\"lpr\": %d, \"pz\": %d, \"tile\": %d, \"us\": %.3f}\n",
-                   k.n, k.nnz, k.bytes, k.nrhs, k.rowstat, t.fmt, t.lpr, t.pz, t.tile, t.us);
+                   "\"lpr\": %d, \"pz\": %d, \"sh\": %d, \"tile\": %d, \"us\": %.3f}\n",
+                   k.n, k.nnz, k.bytes, k.nrhs, k.rowstat, t.fmt, t.lpr, t.pz, t.sh, t.tile, t.us);
       std::fclose(f);
     }
   }
@@ -1549,7 +1557,7 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   key.nrhs = 1;
   key.rowstat = lv.sl_total;
   const char* force = std::getenv("AMG_TUNE_FORCE");
-  if (!force) {
+  if (!force && !std::getenv("AMG_TUNE_SLICE")) {
     Level::Tune t;
     if (tune_cache_get(key, &t)) return t;
   }
@@ -1593,22 +1601,58 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
       });
       if (us < best.us) { best.us = us; best.fmt = 1; best.lpr = lv.lpr; best.pz = p; }
       if (lv.sl_dcol) {
+        // 16-bit offsets move 2 bytes less per entry.  Back-to-back timed
+        // launches find part of a level's data in the Infinity Cache, which
+        // in the cycle (other levels' kernels in between) it is not, so they
+        // understate that saving: the 16-bit form is kept unless the 32-bit
+        // one is more than kPrefer16 faster (C3 mixed, level 0 in FP32: 32-bit
+        // columns timed faster, 16-bit offsets solved 1.3 ms faster).
+        constexpr float kPrefer16 = 1.05f;
         const float u16 = time_it([&] {
           launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, lv.sl_dcol, p);
         });
-        if (u16 < best.us) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; best.pz = p; }
+        const bool over32 = best.fmt == 1 && best.pz == p && u16 <= kPrefer16 * best.us;
+        if (u16 < best.us || over32) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; best.pz = p; }
       }
       if (pz == 0) break;
     }
   }
-  if (force) {
-    const std::string w(force);
-    if (w == "csr") best.fmt = 0;
-    else if (w == "sell" && lv.sl_ptr) best.fmt = 1;
-    else if (w == "sell16" && lv.sl_dcol) best.fmt = 2;
+  if (lv.sh.ptr && short_vals<T>(lv)) {   // the copy in shorter slices, 32- and 16-bit columns
+    for (int f = 1; f <= 2; ++f) {
+      if (f == 2 && !lv.sh.dcol) break;
+      const float us = time_it([&] {
+        launch_sell<T>(lv.n, lv.sh.nslices, lv.sh.ptr, lv.sh.col, short_vals<T>(lv), op, rc, s,
+                       f == 2 ? lv.sh.dcol : nullptr, 0, lv.sh.h, lv.sh.perm);
+      });
+      if (std::getenv("AMG_DEBUG"))
+        std::fprintf(stderr, "amg: level n=%d %d-row slices fmt=%d: %.2f us (best so far %.2f)\n", lv.n, lv.sh.h, f,
+                     us, best.us);
+      if (us < best.us) { best.us = us; best.fmt = f; best.lpr = lv.lpr; best.pz = 0; best.sh = lv.sh.h; }
+    }
+  }
+  if (force) {   // "csr", "sell" or "sell16", the last two optionally ":32" or ":16" (slice height)
+    std::string w(force);
+    int fh = 0;
+    const size_t colon = w.find(':');
+    if (colon != std::string::npos) {
+      fh = std::atoi(w.c_str() + colon + 1);
+      w = w.substr(0, colon);
+    }
+    const bool short_ok = fh > 0 && lv.sh.h == fh && short_vals<T>(lv) != nullptr;
+    if (w == "csr") {
+      best.fmt = 0;
+      best.sh = 0;
+    } else if (w == "sell" && lv.sl_ptr) {
+      best.fmt = 1;
+      best.sh = short_ok ? fh : 0;
+    } else if (w == "sell16" && lv.sl_dcol) {
+      best.fmt = 2;
+      best.sh = short_ok && lv.sh.dcol ? fh : 0;
+    }
+    if (best.sh) best.pz = 0;
     return best;   // not cached
   }
-  tune_cache_put(key, best);
+  if (!std::getenv("AMG_TUNE_SLICE")) tune_cache_put(key, best);
   return best;
 }
 
@@ -1616,17 +1660,42 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
 
 void autotune_levels(Hierarchy& h) {
   const bool debug = std::getenv("AMG_DEBUG") != nullptr;
+  const char* force_h = std::getenv("AMG_TUNE_SLICE");   // 32 or 16: build that slice height (tests)
+  const bool pinned = force_h || std::getenv("AMG_TUNE_FORCE");
   for (int k = 0; k < h.L(); ++k) {
     Level& lv = h.levels[k];
+    // a candidate copy in shorter slices, where the rows vary in length; not
+    // built when the cached decisions of this level shape do not use one
+    bool need = lv.n > kFuseCorrectionRows && lv.sl_ptr;
+    if (need && !pinned) {
+      TuneKey key;
+      key.n = lv.n;
+      key.nnz = lv.nnz;
+      key.rowstat = lv.sl_total;
+      Level::Tune c32, c64;
+      key.bytes = 4;
+      const bool h32 = !h.mixed() || tune_cache_get(key, &c32);
+      key.bytes = 8;
+      const bool h64 = (h.mixed() && k > 0) || tune_cache_get(key, &c64);
+      if (h32 && h64) need = (h.mixed() && c32.sh > 0) || ((!h.mixed() || k == 0) && c64.sh > 0);
+    }
+    if (need) build_short_sell(h, lv, force_h ? std::atoi(force_h) : 0);
     if (h.mixed()) {
       lv.t32 = tune_one<float>(h, lv, static_cast<float*>(lv.xt), static_cast<float*>(lv.r));
       if (k == 0) lv.t64 = tune_one<double>(h, lv, h.p, h.q);
     } else {
       lv.t64 = tune_one<double>(h, lv, static_cast<double*>(lv.xt), static_cast<double*>(lv.r));
     }
+    if (lv.sh.ptr && lv.t64.sh != lv.sh.h && lv.t32.sh != lv.sh.h) {   // not chosen: release it
+      lv.sh = Level::ShortSell{};
+      lv.sh_mem.reset();
+    }
     if (debug)
-      std::fprintf(stderr, "amg: tune level %d n=%d fp64 fmt=%d lpr=%d pz=%d %.2f us | fp32 fmt=%d lpr=%d pz=%d %.2f us\n",
-                   k, lv.n, lv.t64.fmt, lv.t64.lpr, lv.t64.pz, lv.t64.us, lv.t32.fmt, lv.t32.lpr, lv.t32.pz, lv.t32.us);
+      std::fprintf(stderr,
+                   "amg: tune level %d n=%d fp64 fmt=%d lpr=%d pz=%d sh=%d %.2f us | fp32 fmt=%d lpr=%d pz=%d sh=%d "
+                   "%.2f us\n",
+                   k, lv.n, lv.t64.fmt, lv.t64.lpr, lv.t64.pz, lv.t64.sh, lv.t64.us, lv.t32.fmt, lv.t32.lpr,
+                   lv.t32.pz, lv.t32.sh, lv.t32.us);
   }
 }
 

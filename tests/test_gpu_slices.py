@@ -1,0 +1,85 @@
+"""Sliced ELL in 32- and 16-row slices (2 or 4 lanes per row): the autotuner's
+candidate for levels whose rows vary in length (Section 3's sparse products,
+in the layout that pads less).  Forced on the tuned levels of a 96^3 Poisson
+hierarchy (level 0: 884,736 uniform rows; level 1: about 80,000 rows of
+uneven length), every level's product is checked entry by entry against the
+exported A_k, and the solve against the default hierarchy's and a re-setup
+on new values."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from synthetic import problems as P
+from tests.gpu_helpers import dev_vec, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+amg = pytest.importorskip("paper_1403_1649_amd")
+
+FMT = {"sell": 1, "sell16": 2}
+
+
+@pytest.fixture(scope="module")
+def base():
+    A = P.poisson3d(96)
+    dev = to_dev(A)
+    b = P.rhs(A, P.exact_solution(A.n, 1))
+    h = amg.setup(*dev, amg.Options(dim=3))
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    yield A, dev, b, x.cpu().numpy(), it
+    h.close()
+
+
+def _entrywise(h, k, seed):
+    ex = h.export_level(k, what=("A",))
+    S = sp.csr_matrix((ex["val"], ex["col"], ex["row_ptr"]), shape=(ex["n"], ex["n"]))
+    x = P.exact_solution(ex["n"], seed)
+    y = h.level_spmv(k, dev_vec(x)).cpu().numpy()
+    rowlen = np.diff(ex["row_ptr"]).max()
+    # both sides sum at most rowlen products: each within (rowlen - 1) u of the exact row sum
+    assert np.all(np.abs(y - S @ x) <= 2.5e-16 * rowlen * (abs(S) @ np.abs(x)))
+
+
+@pytest.mark.parametrize("slice_h,fmt", [(32, "sell"), (16, "sell"), (32, "sell16"), (16, "sell16")])
+def test_short_slices_products_and_solve(base, slice_h, fmt, monkeypatch):
+    A, dev, b, x0, it0 = base
+    monkeypatch.setenv("AMG_TUNE_SLICE", str(slice_h))
+    monkeypatch.setenv("AMG_TUNE_FORCE", f"{fmt}:{slice_h}")
+    print(f"slices: {fmt} h={slice_h}", flush=True)
+    h = amg.setup(*dev, amg.Options(dim=3))
+    tuned = [k for k in range(h.num_levels() - 1) if h.level_info(k)["n"] > 65536]
+    assert tuned[:2] == [0, 1]
+    for k in tuned:
+        f, lanes, _ = h.level_format(k)
+        assert (f, lanes) == (FMT[fmt], 64 // slice_h), (k, f, lanes)
+        _entrywise(h, k, 10 + k)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and abs(it - it0) <= 1
+    assert np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x - x0) <= 1e-7 * np.linalg.norm(x0)
+    # new values on the same pattern: the short-slice copies take them too
+    v2 = dev[2] * 2.0
+    h.resetup(v2)
+    for k in tuned:
+        _entrywise(h, k, 20 + k)
+    x2, it2, rel2 = amg.solve(h, dev_vec(b), 1e-8)
+    assert rel2 <= 1e-8 and abs(it2 - it0) <= 1
+    assert np.linalg.norm(x2.cpu().numpy() - 0.5 * x0) <= 1e-7 * np.linalg.norm(0.5 * x0)
+    h.close()
+
+
+@pytest.mark.parametrize("slice_h", [32, 16])
+def test_short_slices_mixed_precision(base, slice_h, monkeypatch):
+    A, dev, b, x0, it0 = base
+    monkeypatch.setenv("AMG_TUNE_SLICE", str(slice_h))
+    monkeypatch.setenv("AMG_TUNE_FORCE", f"sell16:{slice_h}")
+    h = amg.setup(*dev, amg.Options(dim=3, precision="mixed"))
+    assert h.level_format(1, "mixed")[:2] == (2, 64 // slice_h)
+    assert h.level_format(0, "fp64")[:2] == (2, 64 // slice_h)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and abs(it - it0) <= 1
+    assert np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+    h.close()
