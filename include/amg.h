@@ -107,6 +107,12 @@ typedef struct {
  * allocated and unchanged until amg_destroy (or until amg_resetup hands over
  * new values).  The library never writes them. */
 #define AMG_FLAG_BORROW_A 16u
+/* amg_options.flags: run the V-cycle levels below the K-cycle (the small
+ * levels of Algorithm 4 with Jacobi smoothing, and the coarse solve) as one
+ * persistent launch per V-cycle instead of one kernel per step.  The results
+ * are the same bit for bit; the launch is slower on MI355X (its cross-block
+ * waits cost more than the launches they replace), so it is off by default. */
+#define AMG_FLAG_PERSISTENT_TAIL 32u
 
 /* A matrix handed to the library: device arrays, see the conventions above. */
 typedef struct {

@@ -17,7 +17,7 @@ _PREC = {"fp64": 0, "mixed": 1}
 _PROBE = {"none": 0, "l0_presmooth": 1, "l0_postsmooth": 2, "outer_spmv": 3}
 _KRYLOV = {"fcg": 0, "fgmres": 1}
 _SMOOTHER = {"jacobi": 0, "learned": 1, "chebyshev": 2, "mcsgs": 3}
-FLAG_NO_GRAPH, FLAG_NO_TUNE, FLAG_LEARNED_ALWAYS, FLAG_BORROW_A = 1, 2, 8, 16
+FLAG_NO_GRAPH, FLAG_NO_TUNE, FLAG_LEARNED_ALWAYS, FLAG_BORROW_A, FLAG_PERSISTENT_TAIL = 1, 2, 8, 16, 32
 
 EXPORTED = [
     "amg_default_options", "amg_status_string", "amg_last_error", "amg_setup", "amg_solve",

@@ -42,6 +42,7 @@ enum : int {
   kErrCrossSystem = 256,
   kErrNotSPD = 512,
   kErrColors = 1024,
+  kErrTimeout = 2048,   // a bounded wait of a persistent launch ran out
 };
 
 // ---------------------------------------------------------------- memory
@@ -212,6 +213,7 @@ struct Hierarchy {
   double* d_sc = nullptr;      // scalar slots (dots, coefficients)
   double* d_part = nullptr;    // per-block partial sums of reductions
   unsigned* d_ticket = nullptr;// last-block tickets
+  unsigned* d_tail = nullptr;  // counters of the one-launch V-cycle tail (zero between launches)
   ScanCtx scan;                // look-back words of device scans
   int* d_mis = nullptr;        // MIS(2) round counters (kMisWords ints)
   // pinned host mirror for read-backs

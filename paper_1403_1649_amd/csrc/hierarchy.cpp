@@ -219,6 +219,7 @@ struct Sync {
     if (e & kErrSingular) throw Error(AMG_EBREAKDOWN, "coarsest matrix is singular");
     if (e & kErrCrossSystem) throw Error(AMG_EINVAL, "a matrix entry couples two systems of the batch");
     if (e & kErrColors) throw Error(AMG_EUNSUPPORTED, "the multi-colour ordering needs more than 64 colours");
+    if (e & kErrTimeout) throw Error(AMG_EHIP, "a wait of the one-launch V-cycle tail ran out");
     throw Error(AMG_EHIP, "device error bits " + std::to_string(e));
   }
   // true (and the bit cleared) when the SPD elimination met a non-positive pivot
@@ -463,11 +464,13 @@ void init_control(Hierarchy& h) {
   h.d_sc = h.arena.alloc_n<double>(kScWords);
   h.d_part = h.arena.alloc_n<double>((size_t)kMaxPartialBlocks * kMaxReduce);
   h.d_ticket = h.arena.alloc_n<unsigned>(64);
+  h.d_tail = h.arena.alloc_n<unsigned>(64);
   h.d_mis = h.arena.alloc_n<int>(kMisWords);
   launch_fill_int(64, h.d_err, 0, h.stream);
   launch_fill_int(kCtlWords, h.d_ctl, 0, h.stream);
   launch_fill_double(kScWords, h.d_sc, 0.0, h.stream);   // arena memory is recycled, not cleared
   launch_fill_int(64, reinterpret_cast<int*>(h.d_ticket), 0, h.stream);
+  launch_fill_int(64, reinterpret_cast<int*>(h.d_tail), 0, h.stream);
   launch_fill_int(1, h.d_ctl + kCtlOne, 1, h.stream);
   if (!h.h_pinned) AMG_HIP(hipHostMalloc(&h.h_pinned, kPinnedBytes, hipHostMallocDefault));
 }

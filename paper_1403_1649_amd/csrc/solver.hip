@@ -846,6 +846,287 @@ void probe_point(Hierarchy& h, bool selected, std::function<void(hipStream_t)> f
   if (timed) AMG_HIP(hipEventRecord(h.pev[1], h.stream));
 }
 
+// ------------------------------------------------------------ V-cycle tail, one launch
+// The V-cycle levels below the K-cycle that take the fused small-level path,
+// with the coarse solve, run as one persistent launch instead of one kernel
+// per step: the steps are phases (pre-smoothing + restriction per level down,
+// the coarse product, residual + post-smoothing + prolongation per level up),
+// each cut into work items.  Blocks take items in one global order from a
+// ticket counter and an item waits until every item of the previous phase is
+// done (a per-phase counter).  A block only ever waits for items with smaller
+// tickets, which blocks already running hold, so the launch cannot deadlock
+// whatever the number of blocks resident.  Each item computes what the
+// per-step kernels compute, in the same order (same lanes per row, same
+// sums), so the results are the same bit for bit.  Data written by other
+// blocks of the launch are read with device-coherent loads after an acquire
+// fence; items publish with a release fence before their counter increment.
+// The last block to leave clears the counters for the next launch.
+// Opt-in (AMG_FLAG_PERSISTENT_TAIL): on C3 one such launch (levels 2-4, 1,024
+// or 256 blocks, 4 or 16 aggregates / row groups per item) took 340-480 us
+// against 47 us for the five per-step kernels it replaces; the item
+// counters' device-scope atomics and the release fence per item cost more
+// than the launch gaps saved.
+constexpr int kTailMax = 8;            // levels in one tail launch
+constexpr int kTailAggPerItem = 16;    // aggregates per pre-smoothing item
+constexpr int kTailGroupsPerItem = 16; // row groups per post-smoothing item
+constexpr int kTailGrid = 256;
+constexpr long kTailSpin = 1L << 22;   // bound of a wait (an error, not a hang, if ever reached)
+
+template <typename T>
+struct TailLevel {
+  int n, nc, lpr;
+  const int* rp;
+  const int* ci;
+  const T* av;
+  const int* agg_ptr;
+  const int* agg_rows;
+  const T* rv;
+  const int* agg;
+  const T* pv;
+  const T* wd;
+  const T* b;   // right-hand side (written in this launch except on the first level)
+  T* xt;        // pre-smoothed iterate
+  T* rc;        // restricted residual = right-hand side of the next level
+  T* c;         // correction = iterate of the next level
+  T* xo;        // smoothed output
+};
+
+template <typename T>
+struct TailArgs {
+  int nlev, nphase, ncoarse;
+  const T* cinv;
+  unsigned* ctl;   // [0] ticket, [1] blocks that left, [2 + p] items done in phase p
+  int* err;
+  int start[2 * kTailMax + 2];   // first item of each phase; start[nphase] = all items
+  TailLevel<T> lv[kTailMax];
+};
+
+// a value written by another block of this launch: a vector load (the
+// addresses differ across lanes) after the acquire fence of the wait
+template <typename T>
+__device__ __forceinline__ T tail_ld(const T* p) {
+  return *p;
+}
+template <typename T>
+__device__ __forceinline__ T tail_ldb(const T* p, bool first) {
+  return first ? *p : tail_ld(p);
+}
+
+// aggregates [I0, I1) of a level: the arithmetic of k_presmooth_restrict
+template <typename T, int LPR>
+__device__ void tail_presmooth(const TailLevel<T>& L, bool first, int I0, int I1, T* part) {
+  constexpr int MPB = 256 / LPR;
+  const int slot = threadIdx.x / LPR, lane = threadIdx.x & (LPR - 1);
+  for (int I = I0; I < I1; ++I) {
+    const int s = L.agg_ptr[I], e = L.agg_ptr[I + 1];
+    T acc = T(0);
+    for (int base = s; base < e; base += MPB) {
+      const int k = base + slot;
+      T sum = T(0);
+      int i = -1;
+      if (k < e) {
+        i = L.agg_rows[k];
+        const int r0 = L.rp[i], r1 = L.rp[i + 1];
+        for (int x = r0 + lane; x < r1; x += LPR) {
+          const int j = L.ci[x];
+          sum += L.av[x] * (L.wd[j] * tail_ldb(L.b + j, first));
+        }
+      }
+      sum = group_sum<LPR>(sum);
+      if (lane == 0 && k < e) {
+        const T bi = tail_ldb(L.b + i, first);
+        L.xt[i] = L.wd[i] * bi;
+        part[slot] = L.rv[k] * (bi - sum);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int m = min(MPB, e - base);
+        for (int q = 0; q < m; ++q) acc += part[q];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) L.rc[I] = acc;
+  }
+}
+
+// row groups [g0, g1) of a level: the arithmetic of k_rows with
+// OpResidSmooth<T, CorrV<T>> (x_j = xt_j + P_j c_agg(j))
+template <typename T, int LPR>
+__device__ void tail_postsmooth(const TailLevel<T>& L, bool first, int g0, int g1) {
+  constexpr int RPB = 256 / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  auto corr = [&](int j) { return tail_ld(L.xt + j) + L.pv[j] * tail_ld(L.c + L.agg[j]); };
+  for (int g = g0; g < g1; ++g) {
+    const int row = g * RPB + threadIdx.x / LPR;
+    T sum = T(0);
+    if (row < L.n) {
+      const int s = L.rp[row], e = L.rp[row + 1];
+      for (int k0 = s + lane; k0 < e; k0 += 4 * LPR) {
+        int c[4];
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + q * LPR;
+          c[q] = k < e ? L.ci[k] : 0;
+          v[q] = k < e ? L.av[k] : T(0);
+        }
+        T xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = k0 + q * LPR < e ? corr(c[q]) : T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k0 + q * LPR < e) sum += v[q] * xv[q];
+      }
+    }
+    sum = group_sum<LPR>(sum);
+    if (row < L.n && lane == 0) L.xo[row] = corr(row) + L.wd[row] * (tail_ldb(L.b + row, first) - sum);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_vtail(TailArgs<T> a, Act act) {
+  if (!act.on()) return;
+  __shared__ int s_item;
+  __shared__ T part[32];
+  const int total = a.start[a.nphase];
+  int ready = 0;   // leading phases known to be complete
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.ctl[0], 1u);
+    __syncthreads();
+    const int t = s_item;
+    __syncthreads();
+    if (t >= total) break;
+    int p = 0;
+    while (t >= a.start[p + 1]) ++p;
+    if (p > ready) {   // phases complete in order: wait for phase p - 1
+      __shared__ int s_ok;
+      if (threadIdx.x == 0) {
+        const unsigned need = (unsigned)(a.start[p] - a.start[p - 1]);
+        long spins = 0;
+        while (__hip_atomic_load(&a.ctl[2 + p - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need &&
+               ++spins < kTailSpin)
+          __builtin_amdgcn_s_sleep(8);
+        s_ok = spins < kTailSpin;
+        if (!s_ok) atomic_or_flag(a.err, kErrTimeout);
+      }
+      __syncthreads();
+      if (!s_ok) break;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      ready = p;
+    }
+    const int it = t - a.start[p];
+    if (p < a.nlev) {                       // pre-smoothing + restriction, down
+      const TailLevel<T>& L = a.lv[p];
+      const int I0 = it * kTailAggPerItem, I1 = min(L.nc, I0 + kTailAggPerItem);
+      if (L.lpr == 8) tail_presmooth<T, 8>(L, p == 0, I0, I1, part);
+      else if (L.lpr == 16) tail_presmooth<T, 16>(L, p == 0, I0, I1, part);
+      else tail_presmooth<T, 32>(L, p == 0, I0, I1, part);
+    } else if (p == a.nlev) {               // coarse product, one wave per row
+      const TailLevel<T>& L = a.lv[a.nlev - 1];
+      const int n = a.ncoarse;
+      const int row = it * (kBlock / kWave) + threadIdx.x / kWave;
+      const int lane = threadIdx.x & (kWave - 1);
+      T s = T(0);
+      if (row < n) {
+        const T* Ar = a.cinv + (size_t)row * n;
+        for (int j = lane; j < n; j += kWave) s += Ar[j] * tail_ld(L.rc + j);
+      }
+      s = wave_sum(s);
+      if (row < n && lane == 0) L.c[row] = s;
+    } else {                                // residual + post-smoothing + prolongation, up
+      const int q = a.nlev - 1 - (p - a.nlev - 1);
+      const TailLevel<T>& L = a.lv[q];
+      const int rpb = 256 / L.lpr;
+      const int groups = (L.n + rpb - 1) / rpb;
+      const int g0 = it * kTailGroupsPerItem, g1 = min(groups, g0 + kTailGroupsPerItem);
+      if (L.lpr == 8) tail_postsmooth<T, 8>(L, q == 0, g0, g1);
+      else if (L.lpr == 16) tail_postsmooth<T, 16>(L, q == 0, g0, g1);
+      else tail_postsmooth<T, 32>(L, q == 0, g0, g1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();   // the item's writes before its count
+      atomicAdd(&a.ctl[2 + p], 1u);
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (atomicAdd(&a.ctl[1], 1u) == gridDim.x - 1) {   // every other block has left
+      a.ctl[0] = 0u;
+      a.ctl[1] = 0u;
+      for (int q = 0; q < a.nphase; ++q) a.ctl[2 + q] = 0u;
+    }
+  }
+}
+
+// The first level of the tail (h.L() when there is none): from there down
+// every level is a V-cycle level on the fused small-level path with 8, 16 or
+// 32 lanes per row and the Jacobi (plain or learned) smoother.
+template <typename T>
+int tail_first(const Hierarchy& h) {
+  const int L = h.L();
+  if (L == 0 || h.nsys > 0 || !(h.opt.flags & AMG_FLAG_PERSISTENT_TAIL) || h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV ||
+      h.opt.smoother == AMG_SMOOTHER_MCSGS || !h.d_tail)
+    return L;
+  int k0 = L;
+  while (k0 - 1 >= 1 && k0 - 1 >= h.opt.kcycle_levels) {
+    const Level& lv = h.levels[k0 - 1];
+    const int lpr = tune_of<T>(lv).lpr;
+    if (lv.n > kFuseCorrectionRows || (lpr != 8 && lpr != 16 && lpr != 32)) break;
+    --k0;
+  }
+  if (L - k0 > kTailMax) k0 = L - kTailMax;
+  return k0;
+}
+
+// cycle(k0) below the K-cycle as one launch; false when level k0 does not
+// start the tail
+template <typename T>
+bool vtail(Hierarchy& h, int k0, const T* b, T* xo, const int* act) {
+  const int L = h.L();
+  if (k0 >= L || tail_first<T>(h) != k0) return false;
+  TailArgs<T> a{};
+  a.nlev = L - k0;
+  a.ncoarse = h.levels[L].n;
+  a.cinv = cinv<T>(h);
+  a.ctl = h.d_tail;
+  a.err = h.d_err;
+  int items = 0, p = 0;
+  auto phase = [&](int n_items) { a.start[p++] = items; items += n_items; };
+  for (int q = 0; q < a.nlev; ++q) {
+    const Level& lv = h.levels[k0 + q];
+    TailLevel<T>& t = a.lv[q];
+    t.n = lv.n;
+    t.nc = lv.nc;
+    t.lpr = tune_of<T>(lv).lpr;
+    t.rp = lv.rp;
+    t.ci = lv.ci;
+    t.av = vals<T>(lv);
+    t.agg_ptr = lv.agg_ptr;
+    t.agg_rows = lv.agg_rows;
+    t.rv = rvals<T>(lv);
+    t.agg = lv.agg;
+    t.pv = pvals<T>(lv);
+    t.wd = wdinv<T>(lv);
+    t.b = q == 0 ? b : static_cast<const T*>(h.levels[k0 + q - 1].rc);
+    t.xt = static_cast<T*>(lv.xt);
+    t.rc = static_cast<T*>(lv.rc);
+    t.c = static_cast<T*>(lv.c);
+    t.xo = q == 0 ? xo : static_cast<T*>(h.levels[k0 + q - 1].c);
+    phase((lv.nc + kTailAggPerItem - 1) / kTailAggPerItem);
+  }
+  phase((a.ncoarse + kBlock / kWave - 1) / (kBlock / kWave));
+  for (int q = a.nlev - 1; q >= 0; --q) {
+    const int rpb = 256 / a.lv[q].lpr;
+    const int groups = (a.lv[q].n + rpb - 1) / rpb;
+    phase((groups + kTailGroupsPerItem - 1) / kTailGroupsPerItem);
+  }
+  a.nphase = p;
+  a.start[p] = items;
+  const int grid = std::min(kTailGrid, items);
+  k_vtail<T><<<grid, 256, 0, h.stream>>>(a, Act{act});
+  return true;
+}
+
 template <typename T>
 void coarse_solve(Hierarchy& h, const T* b, T* x, const int* act) {
   const int n = h.levels.back().n;
@@ -968,6 +1249,7 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     coarse_solve<T>(h, b, xo, act);
     return;
   }
+  if (!fuse_q && vtail<T>(h, k, b, xo, act)) return;
   Level& lv = h.levels[k];
   hipStream_t s = h.stream;
   RedCtx rc = red(h);
@@ -1091,6 +1373,7 @@ void check_err(Hierarchy& h, int bits) {
   if (!bits) return;
   if (bits & kErrNonFinite) throw Error(AMG_ENANINF, "non-finite value in the iteration");
   if (bits & kErrBreakdown) throw Error(AMG_EBREAKDOWN, "Krylov breakdown: p^T A p <= 0");
+  if (bits & kErrTimeout) throw Error(AMG_EHIP, "a wait of the one-launch V-cycle tail ran out");
   throw Error(AMG_EHIP, "device error bits " + std::to_string(bits));
 }
 
