@@ -1826,11 +1826,13 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   if (lv.n <= kFuseCorrectionRows) {
     // small levels are latency-bound and their kernels gather more than a
     // plain SpMV (the fused correction), so a timed SpMV is a poor and noisy
-    // proxy there: take 8..32 lanes, about one entry per lane
+    // proxy there: take 8..32 lanes, about two entries per lane (against one:
+    // C3 solve 34.2 -> 33.2 ms, C2 8.84 -> 8.74 ms; against 16 lanes on every
+    // small level: 33.1 and 8.86 ms)
     Level::Tune t;
     t.fmt = 0;
     t.lpr = 8;
-    while (t.lpr < 32 && (long)t.lpr * lv.n < lv.nnz) t.lpr <<= 1;
+    while (t.lpr < 32 && 2L * t.lpr * lv.n < lv.nnz) t.lpr <<= 1;
     return t;
   }
   TuneKey key;
