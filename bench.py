@@ -238,9 +238,10 @@ def batch_form(amg, torch, P, reps=2):
 
 def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
     """C5 -> C3: the per-row Jacobi weight network trained with the library's
-    own kernels on heterogeneous-diffusion 64^3 fields (seeds 100..), errors
-    generated by the solver itself, then evaluated on the 160^3 field (seed 2)
-    against the plain method, FP64 and mixed."""
+    own kernels on heterogeneous-diffusion 64^3 fields (seeds 100..) on the
+    two-grid loss (samples after the coarse correction: seeded random vectors
+    and errors the solver itself left), then evaluated on the 160^3 field
+    (seed 2) against the plain method, FP64 and mixed."""
     from paper_1403_1649_amd import learned as Ld
     t0 = time.perf_counter()
     systems = []
@@ -249,7 +250,7 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
         dt = tuple(torch.from_numpy(a).cuda() for a in (At.row_ptr, At.col, At.val))
         ht = amg.setup(*dt, amg.Options(dim=3))
         systems.append((ht, Ld.solver_errors(ht, At, P.exact_solution(At.n, 1))))
-    w = Ld.train(systems, steps=steps, lr=3e-3, samples=8)
+    w = Ld.train_two_grid(systems, steps=steps, lr=3e-3, samples=8, pool=32)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del systems
@@ -258,7 +259,7 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
     dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
     x = torch.empty_like(b)
     out = {"workload": f"C3 heterogeneous FV 160^3 (n={A.n}); network trained on {train_fields} C5 fields 64^3",
-           "train_steps": steps, "train_s": round(train_s, 2)}
+           "loss": "two-grid", "train_steps": steps, "train_s": round(train_s, 2)}
     for name, kw in (("plain_fp64", {}), ("plain_mixed", {"precision": "mixed"}),
                      ("learned_fp64", {"mlp_weights": w}), ("learned_mixed", {"precision": "mixed", "mlp_weights": w})):
         best, info = None, None

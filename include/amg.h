@@ -273,6 +273,18 @@ int32_t amg_batch_level(const amg_hierarchy* h, int32_t k, int32_t* sys_off, dou
  * them needs fewer iterations than with plain damped Jacobi (amg_learned_judge);
  * it falls back to plain damped Jacobi otherwise. */
 
+/* Two-grid errors for training the learned weights of level k (the errors a
+ * smoother of level k must damp in a cycle, Algorithm 4: after the coarse
+ * correction): out_s = (I - P_k B P_k^T A_k) e_s for the nsamples columns of
+ * E, with B = A_{k+1}^-1 exactly when level k+1 is the coarsest, else
+ * `cycles` steps of y <- y + M_{k+1}(r_c - A_{k+1} y) from y = 0, M_{k+1} the
+ * hierarchy's own cycle from level k+1.  E, out: device float64 [n_k][nsamples]
+ * row-major (may not alias).  k < amg_num_levels(h) - 1, nsamples >= 1,
+ * cycles >= 1.  EUNSUPPORTED on mixed-precision or batched hierarchies.
+ * Synchronises s. */
+int32_t amg_mlp_coarse_corrected(const amg_hierarchy* h, int32_t k, const double* E, int32_t nsamples,
+                                 int32_t cycles, double* out, hipStream_t s);
+
 /* Number of MLP parameters (1409): W1[32][9], b1[32], W2[32][32], b2[32], W3[32], b3. */
 int32_t amg_mlp_num_params(void);
 

@@ -24,6 +24,11 @@ the smoother x += Omega D^-1 (b - A x) converges for SPD A.
 Training loss on level k over S error samples e_s (the part of a vector that
 the coarse space range(P_k) cannot represent, e = v - P P^T v, P^T P = I):
   L = (1/S) sum_s ||(I - W A) e_s||_A^2 / ||e_s||_A^2,   W = diag(omega_i / a_ii).
+Two-grid training samples (the errors the smoother of level k meets in a
+cycle, after the coarse correction of Algorithm 4 with an exact coarse solve):
+  e~ = (I - P A_c^-1 P^T A) e,   A_c = P^T A P,
+the A-orthogonal projection of e onto the complement of range(P); the loss
+above on such samples is the two-grid post-smoothing factor.
 Weight layout (1409 FP32 masters): W1[32][9], b1[32], W2[32][32], b2[32],
 W3[32], b3.
 """
@@ -115,6 +120,16 @@ def projected_errors(A: sp.csr_matrix, agg, pval, nc: int, nsamples: int, seed: 
         v = unit_uniform(np.arange(n), seed + s)
         E[:, s] = v - P @ (P.T @ v)
     return E
+
+
+def coarse_corrected(A: sp.csr_matrix, agg, pval, nc: int, E) -> np.ndarray:
+    """e~_s = e_s - P A_c^-1 P^T A e_s with A_c = P^T A P (sparse LU); [n][S]."""
+    from scipy.sparse.linalg import splu
+    n = A.shape[0]
+    P = sp.csr_matrix((pval, agg, np.arange(n + 1)), shape=(n, nc))
+    Ac = (P.T @ A @ P).tocsc()
+    Y = splu(Ac).solve(np.asarray(P.T @ (A @ E)))
+    return E - P @ Y
 
 
 def loss_omega(A: sp.csr_matrix, E, om):

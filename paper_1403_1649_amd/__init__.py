@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     hessenberg_radius,
     lib,
     mlp_adam,
+    mlp_coarse_corrected,
     mlp_features,
     mlp_loss_grad,
     mlp_num_params,

@@ -27,7 +27,7 @@ EXPORTED = [
     "amg_mlp_adam", "amg_level_smoother", "amg_export_jacobi", "amg_setup_batched", "amg_batch_results",
     "amg_batch_level", "amg_level_format", "amg_level_spmv", "amg_release_cached_memory",
     "amg_setup_phases", "amg_galerkin_noalloc", "amg_resetup", "amg_resetup_time", "amg_level_colors", "amg_learned_judge",
-    "amg_multi_tiles",
+    "amg_multi_tiles", "amg_mlp_coarse_corrected",
 ]
 
 
@@ -143,6 +143,8 @@ def lib():
     L.amg_setup_phases.restype = i32
     L.amg_multi_tiles.argtypes = [vp, i32, P(i32), i32, P(dbl)]
     L.amg_multi_tiles.restype = i32
+    L.amg_mlp_coarse_corrected.argtypes = [vp, i32, vp, i32, i32, vp, vp]
+    L.amg_mlp_coarse_corrected.restype = i32
     L.amg_release_cached_memory.argtypes = []
     L.amg_release_cached_memory.restype = C.c_size_t
     _LIB = L
@@ -534,6 +536,19 @@ def mlp_loss_grad(h: Hierarchy, k: int, w, nsamples: int, seed: int, extra=None,
                                    None if extra is None else _ptr(extra), n_extra, C.byref(loss),
                                    None if grad is None else _ptr(grad), flags, _stream()))
     return loss.value
+
+
+def mlp_coarse_corrected(h: Hierarchy, k: int, E, cycles: int = 20, out=None):
+    """amg_mlp_coarse_corrected: (I - P_k B P_k^T A_k) E for a device float64
+    block E [n_k][S] (B the coarse inverse, or `cycles` cycle steps)."""
+    import torch
+    if E.dim() != 2 or E.dtype != torch.float64 or not E.is_cuda or not E.is_contiguous():
+        raise ValueError("mlp_coarse_corrected: E must be a contiguous float64 device block [n_k][S]")
+    if out is None:
+        out = torch.empty_like(E)
+    _check(lib().amg_mlp_coarse_corrected(h.handle, int(k), _ptr(E), int(E.shape[1]), int(cycles), _ptr(out),
+                                          _stream()))
+    return out
 
 
 def mlp_adam(w, m, v, g, step: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):

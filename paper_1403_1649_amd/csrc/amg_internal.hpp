@@ -454,6 +454,7 @@ void launch_dense_inverse_spd(int nterm, const TermInfo* d_term, const TermInfo*
 void build_batch_hierarchy(Hierarchy& h, const amg_csr& A, const int* sys_off);
 void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, bool offsets16);
 void level_spmv(const Hierarchy& h, int k, const double* x, double* y, hipStream_t s);
+void coarse_corrected_errors(Hierarchy& h, int k, const double* E, int S, int cycles, double* out);
 void launch_hash_vector(int n, uint32_t stream, double* q, hipStream_t s);
 void spmv_sell_f64(Hierarchy& h, const amg_csr& A, const double* x, double* y, bool offsets16);
 void spmv_f64(int n, int nnz, const int* rp, const int* ci, const double* val, const double* x, double* y,

@@ -516,6 +516,20 @@ int32_t amg_mlp_loss_grad(const amg_hierarchy* H, int32_t k, const float* w, int
   });
 }
 
+int32_t amg_mlp_coarse_corrected(const amg_hierarchy* H, int32_t k, const double* E, int32_t nsamples,
+                                 int32_t cycles, double* out, hipStream_t s) {
+  if (!level_ok(H, k) || !E || !out || nsamples < 1 || cycles < 1)
+    return fail(AMG_EINVAL, "amg_mlp_coarse_corrected: bad argument");
+  if (H->h.nsys > 0) return fail(AMG_EUNSUPPORTED, "amg_mlp_coarse_corrected: batched hierarchy");
+  return guarded("amg_mlp_coarse_corrected", [&] {
+    amg::Hierarchy& h = const_cast<amg::Hierarchy&>(H->h);
+    hipStream_t keep = h.stream;
+    h.stream = s;
+    struct Restore { amg::Hierarchy& h; hipStream_t s; ~Restore() { h.stream = s; } } restore{h, keep};
+    amg::coarse_corrected_errors(h, k, E, nsamples, cycles, out);
+  });
+}
+
 int32_t amg_mlp_adam(float* w, float* m, float* v, const float* g, int32_t n, int32_t step, float lr, float b1,
                      float b2, float eps, hipStream_t s) {
   if (!w || !m || !v || !g || n < 1 || step < 1) return fail(AMG_EINVAL, "amg_mlp_adam: bad argument");

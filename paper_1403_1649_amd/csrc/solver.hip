@@ -2088,6 +2088,86 @@ void spmv_sell_level(Hierarchy& h, const Level& lv, const double* x, double* y, 
                       red(h), h.stream, offsets16 ? lv.sl_dcol : nullptr);
 }
 
+// Column s of a row-major [n][S] block to a vector and back, and the
+// coarse-corrected error e - P y.
+struct OpColGet {
+  static constexpr int NV = 0;
+  const double* E;
+  int S, s;
+  double* v;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { v[i] = E[(size_t)i * S + s]; }
+  __device__ void finalize(const double*) const {}
+};
+struct OpCoarseCorrect {
+  static constexpr int NV = 0;
+  const double* e;
+  const int* agg;
+  const double* pv;
+  const double* y;
+  double* out;
+  int S, s;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const {
+    const int a = agg[i];
+    out[(size_t)i * S + s] = a >= 0 ? e[i] - pv[i] * y[a] : e[i];
+  }
+  __device__ void finalize(const double*) const {}
+};
+struct OpAddTo {
+  static constexpr int NV = 0;
+  const double* z;
+  double* y;
+  __device__ bool active() const { return true; }
+  __device__ void idle() const {}
+  __device__ void elem(int i, double*) const { y[i] += z[i]; }
+  __device__ void finalize(const double*) const {}
+};
+
+// The two-grid error after the coarse correction of level k (the error the
+// smoother of level k must damp in a cycle, Algorithm 4):
+//   out_s = (I - P_k B P_k^T A_k) e_s,  B ~ A_{k+1}^-1,
+// B the exact coarse inverse when level k+1 is the coarsest, else `cycles`
+// steps of y <- y + M_{k+1}(r_c - A_{k+1} y) from y = 0 with the hierarchy's
+// own cycle M_{k+1} from level k+1.  E, out: device [n_k][S] row-major.
+// FP64 hierarchies (the cycle from level k+1 runs on the FP64 operators).
+void coarse_corrected_errors(Hierarchy& h, int k, const double* E, int S, int cycles, double* out) {
+  const int L = h.L();
+  if (k < 0 || k >= L) throw Error(AMG_EINVAL, "coarse_corrected_errors: level has no coarse level");
+  if (h.mixed()) throw Error(AMG_EUNSUPPORTED, "coarse_corrected_errors: mixed-precision hierarchy");
+  const Level& lv = h.levels[k];
+  const Level& lc = h.levels[k + 1];
+  const int n = lv.n, nc = lc.n;
+  hipStream_t s = h.stream;
+  RedCtx rc = red(h);
+  Arena tmp;
+  double* e = tmp.alloc_n<double>(n);
+  double* r = tmp.alloc_n<double>(n);
+  double* bc = tmp.alloc_n<double>(nc);
+  double* y = tmp.alloc_n<double>(nc);
+  double* res = tmp.alloc_n<double>(nc);
+  double* z = tmp.alloc_n<double>(nc);
+  const int steps = k + 1 == L ? 1 : std::max(cycles, 1);
+  for (int q = 0; q < S; ++q) {
+    launch_elem(n, OpColGet{E, S, q, e}, rc, s);
+    launch_level<double>(lv, OpSpmv<double>{Act{nullptr}, e, r}, rc, s);
+    launch_rows<double>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<double>(lv),
+                        OpRestrict<double>{Act{nullptr}, r, bc}, rc, s);
+    launch_fill_double(nc, y, 0.0, s);
+    for (int it = 0; it < steps; ++it) {
+      launch_level<double>(lc, OpResid<double>{Act{nullptr}, bc, y, res}, rc, s);
+      if (k + 1 == L) coarse_solve<double>(h, res, z, nullptr);
+      else cycle<double>(h, k + 1, res, z, nullptr);
+      launch_elem(nc, OpAddTo{z, y}, rc, s);
+    }
+    launch_elem(n, OpCoarseCorrect{e, lv.agg, lv.pval, y, out, S, q}, rc, s);
+  }
+  AMG_HIP(hipGetLastError());
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
 // y = A_k x with level k's tuned FP64 kernel
 void level_spmv(const Hierarchy& h, int k, const double* x, double* y, hipStream_t s) {
   launch_level<double>(h.levels[k], OpSpmv<double>{Act{nullptr}, x, y}, RedCtx{nullptr, nullptr}, s);

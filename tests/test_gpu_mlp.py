@@ -196,3 +196,53 @@ def test_learned_weights_judged_by_solve():
         assert itl == itp and np.array_equal(xl.cpu().numpy(), xp.cpu().numpy())
     hp.close()
     hl.close()
+
+
+@pytest.mark.parametrize("name,make", [("hetero3d_16", lambda: P.hetero3d(16, seed=21)),
+                                       ("aniso2d_64", lambda: P.aniso2d(64, 1e-2))])
+def test_coarse_corrected_errors_match_oracle(name, make):
+    """amg_mlp_coarse_corrected against the oracle's exact two-grid projection
+    e - P A_c^-1 P^T A e on every level (A_c formed by the oracle from the
+    GPU's exported A_k): exact coarse solve on the last level, 200 cycle steps
+    from level k+1 above it (a stationary iteration whose factor per cycle is
+    about 0.7 on the anisotropic case, so the result is exact to rounding)."""
+    A = make()
+    d = 3 if "3d" in name else 2
+    h = amg.setup(*to_dev(A), amg.Options(dim=d))
+    rng = np.random.default_rng(9)
+    for k in range(h.num_levels() - 1):
+        ex = h.export_level(k)
+        S = O.validate_csr(ex["row_ptr"], ex["col"], ex["val"])
+        E = rng.standard_normal((ex["n"], 3))
+        T = amg.mlp_coarse_corrected(h, k, torch.from_numpy(E).cuda(), cycles=200).cpu().numpy()
+        R = M.coarse_corrected(S, ex["agg"], ex["pval"], ex["nc"], E)
+        last = k == h.num_levels() - 2
+        tol = 1e-10 if last else 1e-9
+        assert np.linalg.norm(T - R) <= tol * np.linalg.norm(R), (k, np.linalg.norm(T - R) / np.linalg.norm(R))
+    with pytest.raises(amg.AmgError):
+        amg.mlp_coarse_corrected(h, h.num_levels() - 1, torch.zeros((1, 1), dtype=torch.float64, device="cuda"))
+    hm = amg.setup(*to_dev(A), amg.Options(dim=d, precision="mixed"))
+    with pytest.raises(amg.AmgError) as e:
+        amg.mlp_coarse_corrected(hm, 0, torch.from_numpy(rng.standard_normal((A.n, 1))).cuda())
+    assert e.value.code == 8
+    h.close()
+    hm.close()
+
+
+@pytest.mark.skip(reason="no gain measured: networks trained on the one-step smoothing loss, on solver "
+                         "errors, and on the two-grid loss (errors after the coarse correction) all need "
+                         "40-42 iterations on C3 against 39 with plain damped Jacobi; the setup's judge "
+                         "then keeps the plain weights (test_learned_weights_judged_by_solve)")
+def test_learned_weights_beat_plain_jacobi_on_c3():
+    from paper_1403_1649_amd import learned as Ld
+    systems = []
+    for q in range(4):
+        At = P.hetero3d(64, seed=100 + q)
+        h = _setup(At)
+        systems.append((h, Ld.solver_errors(h, At, P.exact_solution(At.n, 1))))
+    w = Ld.train_two_grid(systems, steps=100, lr=3e-3, samples=8, pool=32)
+    A = P.hetero3d(160, seed=2)
+    b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
+    _, itp, _ = amg.solve(_setup(A), b, 1e-8)
+    _, itl, rel = amg.solve(_setup(A, mlp_weights=w, flags=8), b, 1e-8)
+    assert rel <= 1e-8 and itl < itp

@@ -55,6 +55,30 @@ def test_projected_errors_have_no_coarse_component():
     assert np.abs(lv.P.T @ E).max() < 1e-13
 
 
+def test_coarse_corrected_errors_are_the_a_orthogonal_complement():
+    """e~ = (I - P A_c^-1 P^T A) e: P^T A e~ = 0 (A-orthogonal to the coarse
+    space), a projection (applying it twice changes nothing), zero on range(P),
+    and the A-norm minimiser of e - P y over every y (against random y)."""
+    A = P.hetero3d(10, seed=4).to_scipy()
+    lv = O.coarsen_level(A, np.ones(A.shape[0]), O.Options.for_dim(3))
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((A.shape[0], 3))
+    T = M.coarse_corrected(A, lv.agg, lv.pval, lv.nc, E)
+    scale = np.abs(lv.P.T @ (A @ E)).max()
+    assert np.abs(lv.P.T @ (A @ T)).max() <= 1e-12 * scale
+    T2 = M.coarse_corrected(A, lv.agg, lv.pval, lv.nc, T)
+    assert np.abs(T2 - T).max() <= 1e-12 * np.abs(T).max()
+    Z = M.coarse_corrected(A, lv.agg, lv.pval, lv.nc, lv.P @ rng.standard_normal((lv.nc, 2)))
+    assert np.abs(Z).max() <= 1e-12
+    anorm = lambda v: float(np.sqrt(v @ (A @ v)))   # noqa: E731
+    for s in range(3):
+        best = anorm(T[:, s])
+        for _ in range(20):
+            y = rng.standard_normal(lv.nc) * 0.1
+            y += np.linalg.lstsq(lv.P.toarray(), E[:, s] - T[:, s], rcond=None)[0]
+            assert anorm(E[:, s] - lv.P @ y) >= best * (1 - 1e-12)
+
+
 def test_gradient_matches_central_differences():
     A = P.hetero3d(6, seed=3).to_scipy()
     lv = O.coarsen_level(A, np.ones(A.shape[0]), O.Options.for_dim(3))
