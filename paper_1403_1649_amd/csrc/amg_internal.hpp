@@ -376,7 +376,6 @@ void launch_window_order(int n, const int* rp, int* perm, hipStream_t s);
 // ucount[nc], list[2 nc], ctl: two counters.
 struct GalerkinScratch {
   int* lens;
-  int* inv;
   int* toff;
   int* tkey;
   double* tval;

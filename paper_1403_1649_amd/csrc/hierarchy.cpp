@@ -413,7 +413,6 @@ static void galerkin_product(Hierarchy& h, Arena& tmp, Arena& out, const Level& 
   const int n = lv.n, nnz = lv.nnz;
   GalerkinScratch g;
   g.lens = tmp.alloc_n<int>(n > 0 ? n : 1);
-  g.inv = tmp.alloc_n<int>(n > 0 ? n : 1);
   g.toff = tmp.alloc_n<int>((size_t)n + 1);
   g.tkey = tmp.alloc_n<int>(nnz > 0 ? nnz : 1);
   g.tval = tmp.alloc_n<double>(nnz > 0 ? nnz : 1);

@@ -31,8 +31,7 @@ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 constexpr size_t kOffTkey = 0;                                                    // int[nnz]
 constexpr size_t kOffTval = kOffTkey + align256(sizeof(int) * kNaMaxNnz);         // double[nnz]
 constexpr size_t kOffLens = kOffTval + align256(sizeof(double) * kNaMaxNnz);      // int[n]
-constexpr size_t kOffInv = kOffLens + align256(sizeof(int) * kNaMaxRows);         // int[n]
-constexpr size_t kOffToff = kOffInv + align256(sizeof(int) * kNaMaxRows);         // int[n + 1]
+constexpr size_t kOffToff = kOffLens + align256(sizeof(int) * kNaMaxRows);        // int[n + 1]
 constexpr size_t kOffAggPtr = kOffToff + align256(sizeof(int) * (kNaMaxRows + 1));   // int[nc + 1]
 constexpr size_t kOffAggRows = kOffAggPtr + align256(sizeof(int) * (kNaMaxRows + 1));  // int[n]
 constexpr size_t kOffCounts = kOffAggRows + align256(sizeof(int) * kNaMaxRows);   // int[nc]
@@ -138,7 +137,6 @@ int galerkin_noalloc(const amg_csr& A, const int* agg, const double* pval, int n
   // terms in segment order, reduced per coarse row; row pointers of A_c
   GalerkinScratch g;
   g.lens = at<int>(base, kOffLens);
-  g.inv = at<int>(base, kOffInv);
   g.toff = at<int>(base, kOffToff);
   g.tkey = at<int>(base, kOffTkey);
   g.tval = at<double>(base, kOffTval);
