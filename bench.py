@@ -88,6 +88,8 @@ def measured_traffic(workload: str):
 def kernel_name(fmt: int, lpr: int, op: str) -> str:
     """lpr: lanes per row (for the sliced ELL, 64 / slice height)."""
     h = 64 // max(lpr, 1)
+    if fmt == 3:
+        return f"k_sdia<double,{op}> (sliced diagonals, 64-row slices, no column indices)"
     if fmt == 2:
         return f"k_sell<double,{op},true,{h}> (sliced ELL in {h}-row slices, 16-bit column offsets)"
     return f"k_sell<double,{op},false,{h}>" if fmt == 1 else f"k_rows<double,{lpr},{op}>"

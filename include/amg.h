@@ -232,7 +232,10 @@ int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off
 /* SpMV format the autotuner chose for level k in the given arithmetic
  * (amg_precision: FP64 for the float64 kernels, MIXED for the float32 cycle):
  * format (host) 0 = CSR with *lanes_per_row lanes per row, 1 = sliced ELL,
- * 2 = sliced ELL with 16-bit column offsets col - row; for the sliced ELL,
+ * 2 = sliced ELL with 16-bit column offsets col - row, 3 = sliced diagonals
+ * (per 64-row slice a list of offsets col - row and their values, no column
+ * indices; built for levels whose slices have few diagonals, as on
+ * structured grids; *lanes_per_row = 1); for the sliced ELL,
  * *lanes_per_row = 64 / slice height (1: 64-row slices; 2 or 4: the level's
  * copy in 32- or 16-row slices, built where rows vary in length);
  * us (host, may be NULL) = its timed duration (0 if the level was not timed).

@@ -116,8 +116,21 @@ struct Level {
     float* val32 = nullptr;
   } sh;
   std::shared_ptr<Arena> sh_mem;
+  // sliced diagonals (levels from structured grids): per 64-row slice its
+  // diagonal offsets and their values, no columns; built for the autotuner
+  // where every slice has few diagonals, kept while it is the chosen kernel
+  struct Sdia {
+    int nslices = 0;
+    long total = 0;              // diagonals over all slices
+    int* ptr = nullptr;          // first diagonal of each slice (nslices + 1)
+    int* off = nullptr;          // offsets col - row
+    double* val = nullptr;       // [total][64]
+    float* val32 = nullptr;
+  } dia;
+  std::shared_ptr<Arena> dia_mem;
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
-  // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets
+  // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets,
+  // fmt 3 = sliced diagonals
   // pz: plane steps of the sliced-ELL schedule (0 = contiguous)
   // tile: columns per pass of the block kernels (several right-hand sides)
   // sh: slice height of the sliced-ELL copy used (0 = the 64-row copy)
@@ -370,6 +383,11 @@ void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const do
                       int slice_h = 64, const int* perm = nullptr);
 // rows of each 256-row window by decreasing length; perm: ceil(n/256)*256 slots
 void launch_window_order(int n, const int* rp, int* perm, hipStream_t s);
+// sliced diagonals: per 64-row slice the number of distinct offsets (*over
+// raised above cap), then offsets and values at dg_ptr
+void launch_sdia_count(int n, const int* rp, const int* ci, int cap, int* cnt, int* over, hipStream_t s);
+void launch_sdia_fill(int n, const int* rp, const int* ci, const double* val, const int* dg_ptr, int* dg_off,
+                      double* dg_val, float* dg_val32, hipStream_t s);
 
 // galerkin.hip: scratch of one Galerkin product (n fine rows, nnz entries,
 // nc coarse rows): lens[n], inv[n], toff[n+1], tkey[nnz], tval[nnz],
@@ -474,6 +492,8 @@ void launch_rs_sell_values(const Level& lv, hipStream_t s);
 // the short-slice copy of a level, when it pays (slice_h = 0) or in slices of
 // slice_h = 32 or 16 rows (hierarchy.cpp)
 void build_short_sell(Hierarchy& h, Level& lv, int slice_h);
+// the sliced-diagonal copy of a level, when its slices have few diagonals
+void build_sdia(Hierarchy& h, Level& lv);
 void launch_set16(double* dst, const double* host16, hipStream_t s);
 // coloring.hip: first-fit colouring by node-hash priority in synchronous rounds
 void launch_color_round(int n, const int* rp, const int* ci, uint32_t stream, const int* cin, int* cout, int* left,

@@ -373,6 +373,48 @@ void build_short_sell(Hierarchy& h, Level& lv, int slice_h) {
   lv.sh_mem = mem;
 }
 
+// The sliced-diagonal copy of a level: built when no 64-row slice has more
+// than kSdiaCap distinct offsets col - row and the stored values (diagonals x
+// 64) exceed the level's entries by at most kSdiaPad; its memory is an arena
+// of its own, released when the level drops the copy.
+constexpr int kSdiaCap = 32;
+constexpr double kSdiaPad = 0.10;
+constexpr int kSdiaRows = 64;   // rows per slice (one wave)
+
+void build_sdia(Hierarchy& h, Level& lv) {
+  lv.dia = Level::Sdia{};
+  lv.dia_mem.reset();
+  if (lv.n <= 0 || lv.nnz <= 0) return;
+  auto mem = std::make_shared<Arena>();
+  const int nsl = (lv.n + kSdiaRows - 1) / kSdiaRows;
+  int* cnt = mem->alloc_n<int>(nsl);
+  int* ptr = mem->alloc_n<int>(nsl + 1);
+  int* over = mem->alloc_n<int>(1);
+  launch_fill_int(1, over, 0, h.stream);
+  launch_sdia_count(lv.n, lv.rp, lv.ci, kSdiaCap, cnt, over, h.stream);
+  scan_to_ptr(cnt, ptr, nsl, h.scan, h.stream);
+  Sync sy{h};
+  sy.fetch(ptr + nsl, 0);
+  sy.fetch(over, 1);
+  sy.wait_and_check();
+  const long total = sy.hp()[0];
+  const bool over_cap = sy.hp()[1] != 0;
+  if (std::getenv("AMG_DEBUG"))
+    std::fprintf(stderr, "amg: sliced diagonals n=%d nnz=%d: %ld values%s\n", lv.n, lv.nnz, total * kSdiaRows,
+                 over_cap ? " (a slice over the cap)" : "");
+  if (over_cap || (double)total * kSdiaRows > (1.0 + kSdiaPad) * (double)lv.nnz) return;
+  Level::Sdia d;
+  d.nslices = nsl;
+  d.total = total;
+  d.ptr = ptr;
+  d.off = mem->alloc_n<int>((size_t)std::max(total, 1L));
+  d.val = mem->alloc_n<double>((size_t)std::max(total, 1L) * kSdiaRows);
+  d.val32 = h.mixed() ? mem->alloc_n<float>((size_t)std::max(total, 1L) * kSdiaRows) : nullptr;
+  launch_sdia_fill(lv.n, lv.rp, lv.ci, lv.val, d.ptr, d.off, d.val, d.val32, h.stream);
+  lv.dia = d;
+  lv.dia_mem = mem;
+}
+
 namespace {
 
 void make_float_copies(Hierarchy& h) {

@@ -188,8 +188,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
     if (sl >= nslices) continue;
     const int slot = sl * H + (lane & (H - 1));
     const int row = perm ? perm[slot] : slot;
-    const int base = sl_ptr[sl];
-    const int w = (sl_ptr[sl + 1] - base) / H;
+    const int base = __builtin_amdgcn_readfirstlane(sl_ptr[sl]);   // wave-uniform
+    const int w = (__builtin_amdgcn_readfirstlane(sl_ptr[sl + 1]) - base) / H;
     T sum = T(0);
     const int* cp = static_cast<const int*>(sl_cols) + base + lane;
     const int16_t* dp = static_cast<const int16_t*>(sl_cols) + base + lane;
@@ -224,6 +224,68 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
       for (int o = H; o < kWave; o <<= 1) sum += __shfl_xor(sum, o, kWave);
     }
     if (row < n && j == 0) op.row(row, sum, acc);
+  }
+  if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
+}
+
+// Sliced diagonals: slices of 64 rows (one wave), each with its own short
+// list of diagonal offsets d (col = row + d, ascending): slice s holds
+// offsets dg_off[dg_ptr[s] .. dg_ptr[s+1]) and, for the q-th of them, the
+// value of row s*64 + l at (dg_ptr[s] + q) * 64 + l (zero where the row has no
+// entry on that diagonal).  No column is stored: the offset is one scalar per
+// wave and diagonal, so a level from a structured grid moves 8 bytes per entry
+// (4 in FP32) plus the vectors.  pstep: the plane-ordered schedule of k_sell.
+template <typename T, class Op>
+__global__ void __launch_bounds__(kBlock) k_sdia(int n, int nslices, const int* __restrict__ dg_ptr,
+                                                 const int* __restrict__ dg_off, const T* __restrict__ dg_val,
+                                                 Op op, RedCtx rc, int pstep) {
+  if (!op.active()) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
+    return;
+  }
+  double acc[Op::NV > 0 ? Op::NV : 1];
+#pragma unroll
+  for (int k = 0; k < (Op::NV > 0 ? Op::NV : 1); ++k) acc[k] = 0.0;
+  constexpr int SPB = kBlock / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int steps = (nslices + SPB - 1) / SPB;
+  const int per = (steps + gridDim.x - 1) / gridDim.x;
+  const int t0 = xcd_logical_block() * per;
+  const int t1 = min(steps, t0 + per);
+  const int planes = pstep > 0 ? steps / pstep : 1;
+  for (int u = t0; u < t1; ++u) {
+    const int t = pstep > 0 ? (u % planes) * pstep + u / planes : u;
+    const int sl = t * SPB + wv;
+    if (sl >= nslices) continue;
+    const int row = sl * kWave + lane;
+    // wave-uniform: the offsets come by scalar loads and the entry loop needs
+    // no lane masks (so no wait between the loads of a chunk)
+    const int base = __builtin_amdgcn_readfirstlane(dg_ptr[sl]);
+    const int w = __builtin_amdgcn_readfirstlane(dg_ptr[sl + 1]) - base;
+    const T* vp = dg_val + (size_t)base * kWave + lane;
+    T sum = T(0);
+    for (int k0 = 0; k0 < w; k0 += 8) {
+      int c[8];
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        // the chunk's offsets unconditionally (scalar loads; slots past the
+        // slice repeat its last offset); padding may point past either end
+        // of the rows: clamp (its value is zero)
+        const int col = row + dg_off[base + min(k0 + q, w - 1)];
+        c[q] = col < 0 ? 0 : (col >= n ? n - 1 : col);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = k0 + q < w ? __builtin_nontemporal_load(vp + (size_t)(k0 + q) * kWave) : T(0);
+      T xv[8];   // padding slots gather their slice's last column again (a cache hit)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[q] = op.x(c[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < w) sum += v[q] * xv[q];
+    }
+    if (row < n) op.row(row, sum, acc);
   }
   if constexpr (Op::NV > 0) write_partials<Op::NV>(acc, rc, op, rc.ticket != nullptr);
 }
@@ -313,6 +375,20 @@ void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const
     else if (slice_h == 16) launch_sell_h<T, Op, false, 16>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
     else launch_sell_h<T, Op, false, 64>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
   }
+  if constexpr (Op::NV > 0)
+    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
+}
+
+template <typename T, class Op>
+void launch_sdia(int n, int nslices, const int* dg_ptr, const int* dg_off, const T* dg_val, const Op& op,
+                 RedCtx rc, hipStream_t s, int pstep = 0) {
+  long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
+  if (g < 1) g = 1;
+  if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
+  if (g > 8) g &= ~7L;
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
+  const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
+  k_sdia<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, dg_ptr, dg_off, dg_val, op, r2, pstep);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }

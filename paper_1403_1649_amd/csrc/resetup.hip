@@ -156,6 +156,8 @@ void launch_rs_sell_values(const Level& lv, hipStream_t s) {
     k_rs_sell_values<64><<<(lv.nslices * kWave + kT - 1) / kT, kT, 0, s>>>(lv.n, lv.nslices, lv.rp, lv.val,
                                                                            lv.sl_ptr, nullptr, lv.sl_val,
                                                                            lv.sl_val32);
+  if (lv.dia.val)   // the sliced diagonals, when the level keeps them
+    launch_sdia_fill(lv.n, lv.rp, lv.ci, lv.val, lv.dia.ptr, lv.dia.off, lv.dia.val, lv.dia.val32, s);
   const Level::ShortSell& q = lv.sh;   // the copy in shorter slices, when the level keeps one
   if (q.nslices > 0 && q.val) {
     const int g = (int)(((long)q.nslices * q.h + kT - 1) / kT);

@@ -603,6 +603,54 @@ __global__ void k_sell_widths(int n, int nsl, const int* __restrict__ rp, const 
   if ((threadIdx.x & (H - 1)) == 0 && slot / H < nsl) widths[slot / H] = len * H;
 }
 
+// Sliced diagonals, one wave per 64-row slice: the distinct offsets col - row
+// of the slice's rows in ascending order, found by merging (each lane walks
+// its row's sorted columns; the wave minimum of the lanes' next offsets is
+// the next diagonal, and the lanes holding it step past it).  COUNT: their
+// number per slice into cnt, *over raised when a slice has more than cap.
+// FILL: the offsets and values at the positions of dg_ptr (zero where a row
+// has no entry on a diagonal); the same pass refreshes the values when A's
+// values change on the same pattern.
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_sdia_build(int n, int nslices, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ val,
+                                                    int cap, int* __restrict__ cnt, const int* __restrict__ dg_ptr,
+                                                    int* __restrict__ dg_off, double* __restrict__ dg_val,
+                                                    float* __restrict__ dg_val32, int* __restrict__ over) {
+  const int sl = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (sl >= nslices) return;   // the whole wave
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = sl * kWave + lane;
+  int e = row < n ? rp[row] : 0;
+  const int end = row < n ? rp[row + 1] : 0;
+  const int base = FILL ? dg_ptr[sl] : 0;
+  int q = 0;
+  while (true) {
+    const int mine = e < end ? ci[e] - row : INT_MAX;
+    int d = mine;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const int o = __shfl_xor(d, off, kWave);
+      d = o < d ? o : d;
+    }
+    if (d == INT_MAX) break;
+    if (!FILL && q == cap) {
+      if (lane == 0) atomicOr(over, 1);
+      break;
+    }
+    if (FILL) {
+      if (lane == 0) dg_off[base + q] = d;
+      const double v = mine == d ? val[e] : 0.0;
+      const size_t idx = (size_t)(base + q) * kWave + lane;
+      dg_val[idx] = v;
+      if (dg_val32) dg_val32[idx] = (float)v;
+    }
+    if (mine == d) ++e;
+    ++q;
+  }
+  if (!FILL && lane == 0) cnt[sl] = q;
+}
+
 // The row order of the copies in shorter slices: within each window of 256
 // rows, rows by decreasing length (ties by index), a bitonic sort of
 // (length, index) keys in LDS.  perm has a whole number of windows; its slots
@@ -907,6 +955,21 @@ void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const do
   else
     k_sell_fill<64><<<g, kT, 0, s>>>(n, nslices, rp, ci, val, sl_ptr, perm, sl_col, sl_dcol, wide, sl_val,
                                      sl_val32);
+}
+void launch_sdia_count(int n, const int* rp, const int* ci, int cap, int* cnt, int* over, hipStream_t s) {
+  const int nsl = (n + kWave - 1) / kWave;
+  const int g = (int)(((long)nsl * kWave + 255) / 256);
+  if (nsl > 0)
+    k_sdia_build<false><<<g, 256, 0, s>>>(n, nsl, rp, ci, nullptr, cap, cnt, nullptr, nullptr, nullptr, nullptr,
+                                          over);
+}
+void launch_sdia_fill(int n, const int* rp, const int* ci, const double* val, const int* dg_ptr, int* dg_off,
+                      double* dg_val, float* dg_val32, hipStream_t s) {
+  const int nsl = (n + kWave - 1) / kWave;
+  const int g = (int)(((long)nsl * kWave + 255) / 256);
+  if (nsl > 0)
+    k_sdia_build<true><<<g, 256, 0, s>>>(n, nsl, rp, ci, val, 0, nullptr, dg_ptr, dg_off, dg_val, dg_val32,
+                                         nullptr);
 }
 void launch_window_order(int n, const int* rp, int* perm, hipStream_t s) {
   if (n > 0) k_window_order<<<(n + 255) / 256, 256, 0, s>>>(n, rp, perm);

@@ -810,13 +810,18 @@ template <> const float* sell_vals<float>(const Level& l) { return l.sl_val32; }
 template <typename T> const T* short_vals(const Level& l);
 template <> const double* short_vals<double>(const Level& l) { return l.sh.val; }
 template <> const float* short_vals<float>(const Level& l) { return l.sh.val32; }
+template <typename T> const T* dia_vals(const Level& l);
+template <> const double* dia_vals<double>(const Level& l) { return l.dia.val; }
+template <> const float* dia_vals<float>(const Level& l) { return l.dia.val32; }
 
-// A row operation on A_k with the level's tuned kernel (CSR, or sliced ELL
-// in 64-row slices or in the level's shorter slices).
+// A row operation on A_k with the level's tuned kernel (CSR, sliced ELL in
+// 64-row slices or in the level's shorter slices, or sliced diagonals).
 template <typename T, class Op>
 void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
   const Level::Tune& t = tune_of<T>(lv);
-  if (t.fmt >= 1 && t.sh > 0 && t.sh == lv.sh.h && short_vals<T>(lv))
+  if (t.fmt == 3 && dia_vals<T>(lv))
+    launch_sdia<T>(lv.n, lv.dia.nslices, lv.dia.ptr, lv.dia.off, dia_vals<T>(lv), op, rc, s, t.pz);
+  else if (t.fmt >= 1 && t.sh > 0 && t.sh == lv.sh.h && short_vals<T>(lv))
     launch_sell<T>(lv.n, lv.sh.nslices, lv.sh.ptr, lv.sh.col, short_vals<T>(lv), op, rc, s,
                    t.fmt == 2 ? lv.sh.dcol : nullptr, 0, lv.sh.h, lv.sh.perm);
   else if (t.fmt >= 1 && lv.sl_ptr)
@@ -1853,6 +1858,7 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   best.us = 1e30f;
   hipEvent_t e0 = h.ev[2], e1 = h.ev[3];
   const int reps = 8;
+  constexpr float kPreferFewerBytes = 1.05f;
   auto time_it = [&](auto&& launch) {   // the better of two timed runs
     launch();
     float best_us = 1e30f;
@@ -1890,13 +1896,12 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
         // launches find part of a level's data in the Infinity Cache, which
         // in the cycle (other levels' kernels in between) it is not, so they
         // understate that saving: the 16-bit form is kept unless the 32-bit
-        // one is more than kPrefer16 faster (C3 mixed, level 0 in FP32: 32-bit
+        // one is more than kPreferFewerBytes faster (C3 mixed, level 0 in FP32: 32-bit
         // columns timed faster, 16-bit offsets solved 1.3 ms faster).
-        constexpr float kPrefer16 = 1.05f;
         const float u16 = time_it([&] {
           launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, lv.sl_dcol, p);
         });
-        const bool over32 = best.fmt == 1 && best.pz == p && u16 <= kPrefer16 * best.us;
+        const bool over32 = best.fmt == 1 && best.pz == p && u16 <= kPreferFewerBytes * best.us;
         if (u16 < best.us || over32) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; best.pz = p; }
       }
       if (pz == 0) break;
@@ -1915,7 +1920,25 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
       if (us < best.us) { best.us = us; best.fmt = f; best.lpr = lv.lpr; best.pz = 0; best.sh = lv.sh.h; }
     }
   }
-  if (force) {   // "csr", "sell" or "sell16", the last two optionally ":32" or ":16" (slice height)
+  if (dia_vals<T>(lv)) {   // sliced diagonals, contiguous and plane-ordered
+    const int off = max_column_offset(h, lv);
+    const int pz = (lv.dia.nslices % 4 == 0 && off > 0 && off % 256 == 0 &&
+                    (lv.dia.nslices / 4) % (off / 256) == 0 && (lv.dia.nslices / 4) / (off / 256) >= 2)
+                       ? off / 256 : 0;
+    for (int p : {0, pz}) {
+      const float us = time_it([&] {
+        launch_sdia<T>(lv.n, lv.dia.nslices, lv.dia.ptr, lv.dia.off, dia_vals<T>(lv), op, rc, s, p);
+      });
+      if (std::getenv("AMG_DEBUG"))
+        std::fprintf(stderr, "amg: level n=%d sliced diagonals pz=%d: %.2f us (best so far %.2f)\n", lv.n, p, us,
+                     best.us);
+      // fewer bytes than any sliced ELL: preferred within kPreferFewerBytes, as the 16-bit offsets are
+      const bool over_sell = best.fmt >= 1 && best.fmt <= 2 && best.sh == 0 && us <= kPreferFewerBytes * best.us;
+      if (us < best.us || over_sell) { best.us = us; best.fmt = 3; best.lpr = lv.lpr; best.pz = p; best.sh = 0; }
+      if (pz == 0) break;
+    }
+  }
+  if (force) {   // "csr", "sell", "sell16" or "sdia", the sliced ELL optionally ":32" or ":16" (slice height)
     std::string w(force);
     int fh = 0;
     const size_t colon = w.find(':');
@@ -1927,6 +1950,11 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     if (w == "csr") {
       best.fmt = 0;
       best.sh = 0;
+    } else if (w == "sdia") {
+      if (dia_vals<T>(lv)) {
+        best.fmt = 3;
+        best.sh = 0;
+      }
     } else if (w == "sell" && lv.sl_ptr) {
       best.fmt = 1;
       best.sh = short_ok ? fh : 0;
@@ -1949,10 +1977,12 @@ void autotune_levels(Hierarchy& h) {
   const bool pinned = force_h || std::getenv("AMG_TUNE_FORCE");
   for (int k = 0; k < h.L(); ++k) {
     Level& lv = h.levels[k];
-    // a candidate copy in shorter slices, where the rows vary in length; not
-    // built when the cached decisions of this level shape do not use one
-    bool need = lv.n > kFuseCorrectionRows && lv.sl_ptr;
-    if (need && !pinned) {
+    // candidate copies in shorter slices (rows that vary in length) and in
+    // sliced diagonals (structured levels); not built when the cached
+    // decisions of this level shape use neither
+    bool need_sh = lv.n > kFuseCorrectionRows && lv.sl_ptr;
+    bool need_dia = need_sh;
+    if (need_sh && !pinned) {
       TuneKey key;
       key.n = lv.n;
       key.nnz = lv.nnz;
@@ -1961,10 +1991,15 @@ void autotune_levels(Hierarchy& h) {
       key.bytes = 4;
       const bool h32 = !h.mixed() || tune_cache_get(key, &c32);
       key.bytes = 8;
-      const bool h64 = (h.mixed() && k > 0) || tune_cache_get(key, &c64);
-      if (h32 && h64) need = (h.mixed() && c32.sh > 0) || ((!h.mixed() || k == 0) && c64.sh > 0);
+      const bool use64 = !h.mixed() || k == 0;
+      const bool h64 = !use64 || tune_cache_get(key, &c64);
+      if (h32 && h64) {
+        need_sh = (h.mixed() && c32.sh > 0) || (use64 && c64.sh > 0);
+        need_dia = (h.mixed() && c32.fmt == 3) || (use64 && c64.fmt == 3);
+      }
     }
-    if (need) build_short_sell(h, lv, force_h ? std::atoi(force_h) : 0);
+    if (need_sh) build_short_sell(h, lv, force_h ? std::atoi(force_h) : 0);
+    if (need_dia) build_sdia(h, lv);
     if (h.mixed()) {
       lv.t32 = tune_one<float>(h, lv, static_cast<float*>(lv.xt), static_cast<float*>(lv.r));
       if (k == 0) lv.t64 = tune_one<double>(h, lv, h.p, h.q);
@@ -1974,6 +2009,10 @@ void autotune_levels(Hierarchy& h) {
     if (lv.sh.ptr && lv.t64.sh != lv.sh.h && lv.t32.sh != lv.sh.h) {   // not chosen: release it
       lv.sh = Level::ShortSell{};
       lv.sh_mem.reset();
+    }
+    if (lv.dia.ptr && lv.t64.fmt != 3 && lv.t32.fmt != 3) {
+      lv.dia = Level::Sdia{};
+      lv.dia_mem.reset();
     }
     if (debug)
       std::fprintf(stderr,

@@ -1,9 +1,12 @@
-"""Sliced ELL in 32- and 16-row slices (2 or 4 lanes per row): the autotuner's
-candidate for levels whose rows vary in length (Section 3's sparse products,
-in the layout that pads less).  Forced on the tuned levels of a 96^3 Poisson
-hierarchy (level 0: 884,736 uniform rows; level 1: about 80,000 rows of
-uneven length), every level's product is checked entry by entry against the
-exported A_k, and the solve against the default hierarchy's and a re-setup
+"""The autotuner's other sparse layouts (Section 3's sparse products, in the
+layouts that pad or move less): sliced ELL in 32- and 16-row slices (2 or 4
+lanes per row, rows ordered by length within 64-row windows), for levels
+whose rows vary in length, and sliced diagonals (per 64-row slice its
+diagonal offsets and their values, no column indices), for levels from
+structured grids.  Forced on the tuned levels of a 96^3 Poisson hierarchy
+(level 0: 884,736 uniform rows; level 1: about 80,000 rows of uneven length)
+and of a heterogeneous field, every product is checked entry by entry against
+the exported A_k, the solve against the default hierarchy's, and a re-setup
 on new values."""
 import numpy as np
 import pytest
@@ -82,4 +85,49 @@ def test_short_slices_mixed_precision(base, slice_h, monkeypatch):
     x = x.cpu().numpy()
     assert rel <= 1e-8 and abs(it - it0) <= 1
     assert np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sliced_diagonals_products_and_solve(base, precision, monkeypatch):
+    """Sliced diagonals (per 64-row slice its diagonal offsets and values, no
+    column indices) on the 96^3 Poisson hierarchy's level 0 (seven diagonals):
+    the product entry by entry against the exported A_0, the solve against the
+    default hierarchy, and a re-setup on new values."""
+    A, dev, b, x0, it0 = base
+    monkeypatch.setenv("AMG_TUNE_FORCE", "sdia")
+    print(f"sliced diagonals: {precision}", flush=True)
+    h = amg.setup(*dev, amg.Options(dim=3, precision=precision))
+    assert h.level_format(0, "fp64" if precision == "fp64" else "mixed")[:2] == (3, 1)
+    if precision == "mixed":
+        assert h.level_format(0, "fp64")[:2] == (3, 1)
+    _entrywise(h, 0, 31)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and abs(it - it0) <= 1
+    assert np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+    if precision == "fp64":
+        assert np.linalg.norm(x - x0) <= 1e-7 * np.linalg.norm(x0)
+        h.resetup(dev[2] * 2.0)
+        _entrywise(h, 0, 32)
+        x2, it2, rel2 = amg.solve(h, dev_vec(b), 1e-8)
+        assert rel2 <= 1e-8 and abs(it2 - it0) <= 1
+        assert np.linalg.norm(x2.cpu().numpy() - 0.5 * x0) <= 1e-7 * np.linalg.norm(0.5 * x0)
+    h.close()
+
+
+def test_sliced_diagonals_on_the_heterogeneous_field(monkeypatch):
+    """The 3-D heterogeneous finite-volume field (seven-point rows, fewer at
+    the Dirichlet faces): forced sliced diagonals on level 0, its product
+    entry by entry and the solve."""
+    A = P.hetero3d(48, seed=5)
+    dev = to_dev(A)
+    b = P.rhs(A, P.exact_solution(A.n, 2))
+    monkeypatch.setenv("AMG_TUNE_FORCE", "sdia")
+    h = amg.setup(*dev, amg.Options(dim=3))
+    assert h.level_format(0)[:2] == (3, 1)
+    _entrywise(h, 0, 41)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    assert rel <= 1e-8
+    assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
     h.close()
