@@ -45,6 +45,21 @@ def presmooth_bytes(n, nnz, val_bytes=8):
     return (val_bytes + 4) * nnz + 4 * (n + 1) + 4 * val_bytes * n
 
 
+def sdia_diagonals(A) -> int:
+    """Diagonals stored by the sliced-diagonal format: distinct offsets col - row
+    per 64-row slice, summed over the slices (byte count for the report only)."""
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    key = (rows // 64) * (2 * A.n + 1) + (A.col.astype(np.int64) - rows + A.n)
+    return int(np.unique(key).size)
+
+
+def sdia_bytes(n, ndiag, vectors, val_bytes=8):
+    """Compulsory bytes of a sliced-diagonal kernel: the stored values (64 per
+    diagonal and slice), the offsets and slice pointers, and `vectors` n-long
+    vectors read or written."""
+    return val_bytes * 64 * ndiag + 4 * ndiag + 4 * ((n + 63) // 64 + 1) + vectors * val_bytes * n
+
+
 def presmooth_bytes_offsets16(n, nnz, val_bytes=8):
     """The same kernel's compulsory traffic in the sliced ELL with 16-bit
     column offsets: values + offsets + slice pointers + b, w read, x, r written."""
@@ -642,8 +657,9 @@ def main():
         tuned = {"kernel": kernel_name(fmt0, lpr0, "OpSpmv<double>"), "us": round(t_lvl * 1e6, 2),
                  "gb_s": round(nbytes / t_lvl / 1e9, 1), "bytes": nbytes,
                  "frac": round(nbytes / t_lvl / 1e9 / PEAK_HBM_GBS, 4), "cache": "flushed before each launch"}
-        if fmt0 == 2:
-            fb = 10 * A.nnz + 4 * ((A.n + 63) // 64 + 1) + 16 * A.n
+        if fmt0 in (2, 3):
+            fb = (10 * A.nnz + 4 * ((A.n + 63) // 64 + 1) + 16 * A.n if fmt0 == 2
+                  else sdia_bytes(A.n, sdia_diagonals(A), 2))
             tuned["format_bytes"] = fb
             tuned["format_gb_s"] = round(fb / t_lvl / 1e9, 1)
             tuned["format_frac"] = round(fb / t_lvl / 1e9 / PEAK_HBM_GBS, 4)
@@ -663,10 +679,12 @@ def main():
                                       + " (level-0 pre-smoothing + residual, inside the solve)",
                             "bytes_per_launch": pbytes, "avg_us": round(probe_ms * 1e3, 2),
                             "samples": probe_n}
-        if probe_fmt and probe_fmt[0] == 2:
-            fb = presmooth_bytes_offsets16(A.n, A.nnz)
+        if probe_fmt and probe_fmt[0] in (2, 3):
+            fb = (presmooth_bytes_offsets16(A.n, A.nnz) if probe_fmt[0] == 2
+                  else sdia_bytes(A.n, sdia_diagonals(A), 4))
             line["roofline"]["format_bytes_per_launch"] = fb
             line["roofline"]["format_gb_s"] = round(fb / (probe_ms * 1e-3) / 1e9, 1)
+            line["roofline"]["format_frac"] = round(fb / (probe_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline (single thread, bounded sample)")
         line["cpu_baseline"] = cpu_baseline(A, dim, b, forms["fp64"]["iters"])

@@ -131,3 +131,25 @@ def test_sliced_diagonals_on_the_heterogeneous_field(monkeypatch):
     assert rel <= 1e-8
     assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
     h.close()
+
+
+@pytest.mark.parametrize("fmt", ["sdia", "sell:32", "sell16:16"])
+def test_ragged_last_slice(fmt, monkeypatch):
+    """A level whose row count is not a multiple of the slice height (43^3 =
+    79,507 rows: the last 64-row slice holds 19 rows): the padded slots of the
+    last slice (rows past n) contribute nothing and write nothing."""
+    A = P.poisson3d(43)
+    assert A.n % 64 != 0 and A.n > 65536
+    dev = to_dev(A)
+    b = P.rhs(A, P.exact_solution(A.n, 6))
+    if ":" in fmt:
+        monkeypatch.setenv("AMG_TUNE_SLICE", fmt.split(":")[1])
+    monkeypatch.setenv("AMG_TUNE_FORCE", fmt)
+    h = amg.setup(*dev, amg.Options(dim=3))
+    f, lanes, _ = h.level_format(0)
+    assert f == {"sdia": 3, "sell:32": 1, "sell16:16": 2}[fmt]
+    _entrywise(h, 0, 51)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    assert rel <= 1e-8
+    assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
+    h.close()
