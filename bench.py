@@ -257,28 +257,42 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
     """C5 -> C3: the per-row Jacobi weight network trained with the library's
     own kernels on heterogeneous-diffusion 64^3 fields (seeds 100..) on the
     two-grid loss (samples after the coarse correction: seeded random vectors
-    and errors the solver itself left), then evaluated on the 160^3 field
-    (seed 2) against the plain method, FP64 and mixed."""
+    and errors the solver itself left), the output bias then shifted by the
+    solver's judge on those fields (total iterations of full solves),
+    evaluated on the 160^3 field (seed 2) against the plain method, FP64 and
+    mixed."""
     from paper_1403_1649_amd import learned as Ld
     t0 = time.perf_counter()
-    systems = []
+    systems, fields = [], []
     for q in range(train_fields):
         At = P.hetero3d(64, seed=100 + q)
         dt = tuple(torch.from_numpy(a).cuda() for a in (At.row_ptr, At.col, At.val))
         ht = amg.setup(*dt, amg.Options(dim=3))
         systems.append((ht, Ld.solver_errors(ht, At, P.exact_solution(At.n, 1))))
+        fields.append(dt + (torch.from_numpy(P.rhs(At, P.exact_solution(At.n, 1))).cuda(),))
     w = Ld.train_two_grid(systems, steps=steps, lr=3e-3, samples=8, pool=32)
+    del systems
+    cal = Ld.calibrate_bias(w, fields)
+    w = cal["weights"]
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    del systems
     A = P.hetero3d(160, seed=2)
     b = torch.from_numpy(P.rhs(A, P.exact_solution(A.n, 1))).cuda()
     dev = tuple(torch.from_numpy(a).cuda() for a in (A.row_ptr, A.col, A.val))
     x = torch.empty_like(b)
     out = {"workload": f"C3 heterogeneous FV 160^3 (n={A.n}); network trained on {train_fields} C5 fields 64^3",
-           "loss": "two-grid", "train_steps": steps, "train_s": round(train_s, 2)}
+           "loss": "two-grid", "train_steps": steps, "train_s": round(train_s, 2),
+           "bias_shift": cal["delta"], "calibration": [[d, it] for d, it, _ in cal["table"]],
+           "training_fields_iters": {"plain": cal["plain"][0], "learned": min(t[1] for t in cal["table"])},
+           "judged_on_training_fields": "learned" if cal["wins"] else "plain"}
+    # learned: the weights as judged on the training fields (full solves), so
+    # applied on every level when they won there and plain damped Jacobi
+    # otherwise; judged: the same weights through the setup's own probe-solve
+    # judge on the evaluated system
+    lw = {"mlp_weights": w, "flags": amg.binding.FLAG_LEARNED_ALWAYS} if cal["wins"] else {}
     for name, kw in (("plain_fp64", {}), ("plain_mixed", {"precision": "mixed"}),
-                     ("learned_fp64", {"mlp_weights": w}), ("learned_mixed", {"precision": "mixed", "mlp_weights": w})):
+                     ("learned_fp64", dict(lw)), ("learned_mixed", dict(lw, precision="mixed")),
+                     ("judged_fp64", {"mlp_weights": w})):
         best, info = None, None
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -289,7 +303,7 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
             t = time.perf_counter() - t1
             s_ms, v_ms = h.timings()
             kept = [int(h.smoother_info(k)[0]) for k in range(h.num_levels() - 1)] if "mlp_weights" in kw else None
-            judge = h.learned_judge() if "mlp_weights" in kw else None
+            judge = h.learned_judge() if name.startswith("judged") else None
             h.close()
             if best is None or t < best:
                 best, info = t, (it, rel, s_ms, v_ms, kept, judge)
@@ -297,6 +311,7 @@ def learned_form(amg, torch, P, train_fields=4, steps=100, reps=2):
                      "relres": info[1], "setup_ms": round(info[2], 2), "solve_ms": round(info[3], 2)}
         if info[4] is not None:
             out[name]["learned_levels"] = info[4]
+        if info[5] is not None:
             out[name]["judge"] = info[5]
     return out
 

@@ -893,8 +893,12 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
       arnoldi(h, lv, m, o.seed + 1, Q, w, Hh, wn);
       set_jacobi_weight(h, lv, m, Hh, wn);
       if (debug) std::fprintf(stderr, "amg: level %d rho=%.6f omega=%.6f\n", k, lv.rho, lv.omega);
-      // learned per-row weights, kept only when they smooth better than
-      // omega_k on validation samples (or always, when the caller says so)
+      // learned per-row weights on every level whose smoothing loss on
+      // validation samples is finite (the losses, with omega_k and with the
+      // network, are kept for the caller); the probe-solve judge after the
+      // setup then keeps them or returns to omega_k (a smaller one-step loss
+      // did not predict fewer iterations: larger weights with a larger loss
+      // gave fewer)
       const bool always = (o.flags & AMG_FLAG_LEARNED_ALWAYS) != 0;
       Arena vt;
       bool keep = always;
@@ -903,7 +907,7 @@ void build_hierarchy(Hierarchy& h, const amg_csr& A) {
         launch_fill_double(n, omv, lv.omega, s);
         lv.loss_plain = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, omv, nullptr, 0);
         lv.loss_learned = mlp_loss_grad(h, vt, lv, k, h.mlp_w, 4, 0x5eed0000u + k, nullptr, 0, nullptr, nullptr, 0);
-        keep = std::isfinite(lv.loss_learned) && lv.loss_learned < lv.loss_plain;
+        keep = std::isfinite(lv.loss_learned);
       }
       if (keep) {
         float* F = vt.alloc_n<float>((size_t)n * 9);
