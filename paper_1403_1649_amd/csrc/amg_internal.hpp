@@ -131,7 +131,8 @@ struct Level {
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
   // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets,
   // fmt 3 = sliced diagonals
-  // pz: plane steps of the sliced-ELL schedule (0 = contiguous)
+  // pz: schedule of the slice kernels (0 contiguous, -1 XCD sweep, > 0
+  // plane-ordered over that many steps)
   // tile: columns per pass of the block kernels (several right-hand sides)
   // sh: slice height of the sliced-ELL copy used (0 = the 64-row copy)
   struct Tune { int fmt = 0; int lpr = 8; float us = 0.f; int pz = 0; int tile = 0; int sh = 0; } t64, t32;

@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(Op op, const double* __r
 //   T x(int j) const;                  the gathered operand
 //   void row(int i, T ax, double* acc) the epilogue of row i
 //   void finalize(const double* v)     totals of the reductions
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // The logical block index gives every XCD a contiguous run of blocks, and
 // each logical block a contiguous chunk of the work, so the neighbouring rows
@@ -92,6 +93,49 @@ __device__ __forceinline__ int xcd_logical_block() {
   const int g = gridDim.x, b = blockIdx.x;
   if (g < 8 || (g & 7)) return b;
   return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// Schedules of the slice kernels, whose unit of work is a step of 4 slices
+// (one per wave of a block).  sched:
+//    0   contiguous: each logical block a run of ceil(steps / grid) steps;
+//   > 0  plane-ordered over planes of sched steps (a grid plane of rows, the
+//        largest column offset of the level; steps a multiple of it): logical
+//        step u of that run executes step (u % planes) * sched + u / planes,
+//        so a block walks the same rows plane after plane and finds what it
+//        gathers from the next plane in the cache;
+//   -1   XCD sweep: each XCD a contiguous eighth of the steps, which its B
+//        blocks take together (its block j: steps j, j + B, j + 2B, ... of
+//        that eighth), so what the XCD reads at a time is one run of
+//        adjacent rows and their neighbours (grids that are not a multiple
+//        of 8: block j takes steps j, j + grid, ...).
+struct Steps {
+  int u, end, inc, planes, pstep;
+  __device__ int step() const { return pstep > 0 ? (u % planes) * pstep + u / planes : u; }
+};
+
+__device__ __forceinline__ Steps block_steps(int steps, int sched) {
+  Steps r;
+  r.inc = 1;
+  r.pstep = sched > 0 ? sched : 0;
+  r.planes = sched > 0 ? steps / sched : 1;
+  const int g = gridDim.x;
+  if (sched == -1) {
+    if (g >= 8 && !(g & 7)) {
+      const int per8 = (steps + 7) / 8, x = blockIdx.x & 7;
+      r.u = x * per8 + (blockIdx.x >> 3);
+      r.end = min(steps, (x + 1) * per8);
+      r.inc = g >> 3;
+    } else {
+      r.u = blockIdx.x;
+      r.end = steps;
+      r.inc = g;
+    }
+    return r;
+  }
+  const int per = (steps + g - 1) / g;
+  r.u = xcd_logical_block() * per;
+  r.end = min(steps, r.u + per);
+  return r;
 }
 
 template <typename T, int LPR, class Op>
@@ -155,11 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
 // D16: the columns come as 16-bit offsets col - row (128 bytes per wave and
 // entry instead of 256), for levels whose couplings all lie within 32767
 // rows, as on the lexicographically ordered grids.
-// pstep > 0 (plane-ordered schedule, H = 64): the block steps of 4 slices
-// form planes of pstep steps (a grid plane of rows, the largest column offset
-// of the level); logical step u runs physical step (u % planes) * pstep +
-// u / planes, so a block walks the same rows plane after plane and finds the
-// entries it gathers from the next plane in the cache.  0: contiguous steps.
+// pstep: the schedule of the block steps (block_steps).
 template <typename T, class Op, bool D16, int H = kWave>
 __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* __restrict__ sl_ptr,
                                                  const void* __restrict__ sl_cols, const T* __restrict__ sl_val,
@@ -178,13 +218,8 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
   const int j = lane / H;               // this lane's entries: j, j + G, j + 2G, ...
   const int wv = threadIdx.x / kWave;
   const int steps = (nslices + SPB - 1) / SPB;
-  const int per = (steps + gridDim.x - 1) / gridDim.x;
-  const int t0 = xcd_logical_block() * per;
-  const int t1 = min(steps, t0 + per);
-  const int planes = pstep > 0 ? steps / pstep : 1;
-  for (int u = t0; u < t1; ++u) {
-    const int t = pstep > 0 ? (u % planes) * pstep + u / planes : u;
-    const int sl = t * SPB + wv;
+  for (Steps st = block_steps(steps, pstep); st.u < st.end; st.u += st.inc) {
+    const int sl = st.step() * SPB + wv;
     if (sl >= nslices) continue;
     const int slot = sl * H + (lane & (H - 1));
     const int row = perm ? perm[slot] : slot;
@@ -234,7 +269,7 @@ __global__ void __launch_bounds__(kBlock) k_sell(int n, int nslices, const int* 
 // value of row s*64 + l at (dg_ptr[s] + q) * 64 + l (zero where the row has no
 // entry on that diagonal).  No column is stored: the offset is one scalar per
 // wave and diagonal, so a level from a structured grid moves 8 bytes per entry
-// (4 in FP32) plus the vectors.  pstep: the plane-ordered schedule of k_sell.
+// (4 in FP32) plus the vectors.  pstep: the schedule (block_steps).
 template <typename T, class Op>
 __global__ void __launch_bounds__(kBlock) k_sdia(int n, int nslices, const int* __restrict__ dg_ptr,
                                                  const int* __restrict__ dg_off, const T* __restrict__ dg_val,
@@ -250,13 +285,8 @@ __global__ void __launch_bounds__(kBlock) k_sdia(int n, int nslices, const int* 
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int steps = (nslices + SPB - 1) / SPB;
-  const int per = (steps + gridDim.x - 1) / gridDim.x;
-  const int t0 = xcd_logical_block() * per;
-  const int t1 = min(steps, t0 + per);
-  const int planes = pstep > 0 ? steps / pstep : 1;
-  for (int u = t0; u < t1; ++u) {
-    const int t = pstep > 0 ? (u % planes) * pstep + u / planes : u;
-    const int sl = t * SPB + wv;
+  for (Steps st = block_steps(steps, pstep); st.u < st.end; st.u += st.inc) {
+    const int sl = st.step() * SPB + wv;
     if (sl >= nslices) continue;
     const int row = sl * kWave + lane;
     // wave-uniform: the offsets come by scalar loads and the entry loop needs
@@ -326,31 +356,75 @@ inline int elem_grid(int n, bool reduce) {
   return (int)(g < cap ? g : cap);
 }
 
-template <typename T, class Op>
-void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc,
-                 hipStream_t s) {
-  const int g = rows_grid(n, lpr, Op::NV > 0);
+// Blocks of kernel k that the device holds at once, at most
+// kMaxPartialBlocks: a slice kernel gives each block a fixed share of the
+// steps, so a grid larger than what is resident would run its last blocks
+// in a second, mostly empty round (kernels whose registers allow fewer than
+// 8 blocks of 256 threads per CU).  Per kernel instance, taken once.
+template <class K>
+int resident_blocks(K k) {
+  static int g = 0;
+  if (g == 0) {
+    int per = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0) != hipSuccess || per < 1) per = 8;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    const long r = (long)per * cus;
+    g = (int)(r < kMaxPartialBlocks ? r : kMaxPartialBlocks);
+  }
+  return g;
+}
+
+template <typename T, int LPR, class Op>
+void launch_rows_l(int n, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc, hipStream_t s) {
+  int g = rows_grid(n, LPR, Op::NV > 0);
+  const int cap = resident_blocks(k_rows<T, LPR, Op>);
+  if (g > cap) g = cap > 8 ? cap & ~7 : cap;
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
-  switch (lpr) {
-    case 1: k_rows<T, 1, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    case 2: k_rows<T, 2, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    case 4: k_rows<T, 4, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    case 8: k_rows<T, 8, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    case 16: k_rows<T, 16, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    case 32: k_rows<T, 32, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-    default: k_rows<T, 64, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2); break;
-  }
+  k_rows<T, LPR, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, g);
 }
 
+template <typename T, class Op>
+void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc,
+                 hipStream_t s) {
+  switch (lpr) {
+    case 1: launch_rows_l<T, 1>(n, rp, ci, av, op, rc, s); break;
+    case 2: launch_rows_l<T, 2>(n, rp, ci, av, op, rc, s); break;
+    case 4: launch_rows_l<T, 4>(n, rp, ci, av, op, rc, s); break;
+    case 8: launch_rows_l<T, 8>(n, rp, ci, av, op, rc, s); break;
+    case 16: launch_rows_l<T, 16>(n, rp, ci, av, op, rc, s); break;
+    case 32: launch_rows_l<T, 32>(n, rp, ci, av, op, rc, s); break;
+    default: launch_rows_l<T, 64>(n, rp, ci, av, op, rc, s); break;
+  }
+}
+
+
+// Grid of a slice kernel over `steps` steps: one block per step up to the
+// resident cap, a multiple of 8 above 8 blocks (the XCD mapping).
+inline int step_grid(int steps, int resident) {
+  long g = steps;
+  if (g < 1) g = 1;
+  if (g > resident) g = resident;
+  if (g > 8) g &= ~7L;
+  return (int)g;
+}
+
 // sl_dcol non-null: the kernel reads the 16-bit column offsets instead of sl_col.
+
+
 template <typename T, class Op, bool D16, int H>
-void launch_sell_h(int g, int n, int nslices, const int* sl_ptr, const void* cols, const T* sl_val, const int* perm,
-                   const Op& op, RedCtx r2, hipStream_t s, int pstep) {
-  k_sell<T, Op, D16, H><<<g, kBlock, 0, s>>>(n, nslices, sl_ptr, cols, sl_val, perm, op, r2,
-                                             H == kWave ? pstep : 0);
+void launch_sell_h(int n, int nslices, const int* sl_ptr, const void* cols, const T* sl_val, const int* perm,
+                   const Op& op, RedCtx rc, hipStream_t s, int pstep) {
+  const int g = step_grid((nslices + kBlock / kWave - 1) / (kBlock / kWave), resident_blocks(k_sell<T, Op, D16, H>));
+  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
+  const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
+  k_sell<T, Op, D16, H><<<g, kBlock, 0, s>>>(n, nslices, sl_ptr, cols, sl_val, perm, op, r2, pstep);
+  if constexpr (Op::NV > 0)
+    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, g);
 }
 
 // slice_h: the slice height of the copy (64, 32 or 16 rows); perm: its row
@@ -359,36 +433,26 @@ template <typename T, class Op>
 void launch_sell(int n, int nslices, const int* sl_ptr, const int* sl_col, const T* sl_val, const Op& op,
                  RedCtx rc, hipStream_t s, const int16_t* sl_dcol = nullptr, int pstep = 0, int slice_h = kWave,
                  const int* perm = nullptr) {
-  long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
-  if (g < 1) g = 1;
-  if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
-  if (g > 8) g &= ~7L;
-  const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
-  const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
+  if (slice_h != kWave) pstep = 0;
   const void* cols = sl_dcol ? static_cast<const void*>(sl_dcol) : static_cast<const void*>(sl_col);
   if (sl_dcol) {
-    if (slice_h == 32) launch_sell_h<T, Op, true, 32>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
-    else if (slice_h == 16) launch_sell_h<T, Op, true, 16>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
-    else launch_sell_h<T, Op, true, 64>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    if (slice_h == 32) launch_sell_h<T, Op, true, 32>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
+    else if (slice_h == 16) launch_sell_h<T, Op, true, 16>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
+    else launch_sell_h<T, Op, true, 64>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
   } else {
-    if (slice_h == 32) launch_sell_h<T, Op, false, 32>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
-    else if (slice_h == 16) launch_sell_h<T, Op, false, 16>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
-    else launch_sell_h<T, Op, false, 64>((int)g, n, nslices, sl_ptr, cols, sl_val, perm, op, r2, s, pstep);
+    if (slice_h == 32) launch_sell_h<T, Op, false, 32>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
+    else if (slice_h == 16) launch_sell_h<T, Op, false, 16>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
+    else launch_sell_h<T, Op, false, 64>(n, nslices, sl_ptr, cols, sl_val, perm, op, rc, s, pstep);
   }
-  if constexpr (Op::NV > 0)
-    if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }
 
 template <typename T, class Op>
 void launch_sdia(int n, int nslices, const int* dg_ptr, const int* dg_off, const T* dg_val, const Op& op,
                  RedCtx rc, hipStream_t s, int pstep = 0) {
-  long g = (nslices + kBlock / kWave - 1) / (kBlock / kWave);
-  if (g < 1) g = 1;
-  if (g > kMaxPartialBlocks) g = kMaxPartialBlocks;
-  if (g > 8) g &= ~7L;
+  const int g = step_grid((nslices + kBlock / kWave - 1) / (kBlock / kWave), resident_blocks(k_sdia<T, Op>));
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
-  k_sdia<T, Op><<<(int)g, kBlock, 0, s>>>(n, nslices, dg_ptr, dg_off, dg_val, op, r2, pstep);
+  k_sdia<T, Op><<<g, kBlock, 0, s>>>(n, nslices, dg_ptr, dg_off, dg_val, op, r2, pstep);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, (int)g);
 }

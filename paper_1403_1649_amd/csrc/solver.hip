@@ -581,17 +581,24 @@ struct OpCopy {
 };
 
 // restriction r_c = P^T r by aggregate segments (ascending fine index); the
-// K-cycle takes ||r_c||^2 with the first inner step's dots (OpKDots1)
+// K-cycle takes ||r_c||^2 with the first inner step's dots (OpKDots1).
+// xtc non-null: also the coarse level's first smoothing step from zero,
+// xtc = wdc .* r_c, so its pre-smoothing gathers one array instead of two.
 template <typename T>
 struct OpRestrict {   // rows of R = P^T (aggregates)
   static constexpr int NV = 0;
   Act a;
   const T* r;
   T* rcv;
+  const T* wdc = nullptr;
+  T* xtc = nullptr;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
   __device__ T x(int j) const { return r[j]; }
-  __device__ void row(int I, T s, double*) const { rcv[I] = s; }
+  __device__ void row(int I, T s, double*) const {
+    rcv[I] = s;
+    if (xtc) xtc[I] = wdc[I] * s;
+  }
   __device__ void finalize(const double*) const {}
 };
 
@@ -635,7 +642,7 @@ struct OpProlongK {
 };
 
 // r~ = r_c - (alpha1/rho1) v, the right-hand side of the second inner step
-// (only when that step runs)
+// (only when that step runs); xt non-null: also xt = wd .* r~, as OpRestrict
 template <typename T>
 struct OpRtilde {
   static constexpr int NV = 0;
@@ -644,11 +651,15 @@ struct OpRtilde {
   const T* v;
   T* rt;
   const double* K;
+  const T* wd = nullptr;
+  T* xt = nullptr;
   __device__ bool active() const { return a.on(); }
   __device__ void idle() const {}
   __device__ void elem(int i, double*) const {
     const T ar = (T)(K[kKAlpha1] / K[kKRho1]);
-    rt[i] = rcv[i] - ar * v[i];
+    const T v2 = rcv[i] - ar * v[i];
+    rt[i] = v2;
+    if (xt) xt[i] = wd[i] * v2;
   }
   __device__ void finalize(const double*) const {}
 };
@@ -1246,10 +1257,25 @@ void post_smooth(Hierarchy& h, const Level& lv, int k, Act A, const T* b, const 
   }
 }
 
+// Whether cycle(k) pre-smooths with the row kernel of its level from a zero
+// guess (damped Jacobi, a level that is not the coarsest and does not take the
+// fused pre-smoothing + restriction of small V-cycle levels): then whoever
+// writes its right-hand side can also write the first step x = wd .* b.
+bool plain_presmooth(const Hierarchy& h, int k) {
+  const int L = h.L();
+  if (k <= 0 || k >= L || h.opt.smoother == AMG_SMOOTHER_CHEBYSHEV || h.opt.smoother == AMG_SMOOTHER_MCSGS)
+    return false;
+  const bool kcyc = k < h.opt.kcycle_levels && k + 1 < L;
+  return kcyc || h.levels[k].n > kFuseCorrectionRows;
+}
+
 // cycle(k): x_out = M_k b with a zero initial guess (Algorithm 5 on the top
 // kcycle_levels levels, Algorithm 4 below); `act` guards every kernel.
+// x0: the level's xt already holds wd .* b (written with b by the kernel
+// that formed it), so the pre-smoothing takes the residual of that iterate.
 template <typename T>
-void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double* fuse_q = nullptr) {
+void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double* fuse_q = nullptr,
+           bool x0 = false) {
   if (h.L() == 0) {
     coarse_solve<T>(h, b, xo, act);
     return;
@@ -1278,8 +1304,6 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
       sgs_sweeps<T>(h, lv, A, b, xt);
       launch_level<T>(lv, OpResid<T>{A, b, xt, r}, rc, s);
     }
-    if (!kcyc)
-      launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv}, rc, s);
   } else if (!kcyc && k > 0 && lv.n <= kFuseCorrectionRows) {
     const int lpr = tune_of<T>(lv).lpr;
     const int grid = lv.nc < 1 ? 1 : lv.nc < 65536 ? lv.nc : 65536;
@@ -1289,16 +1313,24 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     });
   } else {
     const Level* lp = &lv;
-    const OpPresmoothResid<T> op{A, b, wd, xt, r};
-    probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_PRESMOOTH,
-                [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
-    if (!kcyc)
-      launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv),
-                     OpRestrict<T>{A, r, rcv}, rc, s);
+    if (x0) {
+      launch_level<T>(lv, OpResid<T>{A, b, xt, r}, rc, s);
+    } else {
+      const OpPresmoothResid<T> op{A, b, wd, xt, r};
+      probe_point(h, k == 0 && h.opt.probe == AMG_PROBE_L0_PRESMOOTH,
+                  [=](hipStream_t st) { launch_level<T>(*lp, op, rc, st); });
+    }
   }
+  // the next level's first smoothing step goes out with its right-hand side
+  const bool nx0 = k + 1 < L && plain_presmooth(h, k + 1);
+  const T* wdn = nx0 ? wdinv<T>(h.levels[k + 1]) : nullptr;
+  T* xtn = nx0 ? static_cast<T*>(h.levels[k + 1].xt) : nullptr;
+  if (!kcyc && !(!cheb && !sgs && k > 0 && lv.n <= kFuseCorrectionRows))
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv, wdn, xtn}, rc,
+                   s);
   if (!kcyc) {
     if (k + 1 == L) coarse_solve<T>(h, rcv, c, act);
-    else cycle<T>(h, k + 1, rcv, c, act);
+    else cycle<T>(h, k + 1, rcv, c, act, nullptr, nx0);
     if (lv.n <= kFuseCorrectionRows) {
       post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrV<T>{lv.agg, pv, c}, fuse_q, rc);
     } else {
@@ -1314,11 +1346,12 @@ void cycle(Hierarchy& h, int k, const T* b, T* xo, const int* act, const double*
     T* d = static_cast<T*>(lv.d);
     T* w = static_cast<T*>(lv.w);
     const int gm = h.opt.krylov == AMG_KRYLOV_FGMRES ? 1 : 0;
-    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv}, rc, s);
-    cycle<T>(h, k + 1, rcv, c, act);                                   // first inner iteration
+    launch_rows<T>(lv.nc, lv.rlpr, lv.agg_ptr, lv.agg_rows, rvals<T>(lv), OpRestrict<T>{A, r, rcv, wdn, xtn}, rc,
+                   s);
+    cycle<T>(h, k + 1, rcv, c, act, nullptr, nx0);                     // first inner iteration
     launch_level<T>(lc, OpKDots1<T>{A, c, rcv, v, K, F, gm, h.opt.kcycle_t}, rc, s);
-    launch_elem(lc.n, OpRtilde<T>{Act{F}, rcv, v, rt, K}, rc, s);
-    cycle<T>(h, k + 1, rt, d, F);                                      // second inner iteration
+    launch_elem(lc.n, OpRtilde<T>{Act{F}, rcv, v, rt, K, wdn, xtn}, rc, s);
+    cycle<T>(h, k + 1, rt, d, F, nullptr, nx0);                        // second inner iteration
     launch_level<T>(lc, OpKDots2<T>{Act{F}, d, v, rt, w, K, F, gm}, rc, s);
     if (lv.n <= kFuseCorrectionRows) {
       post_smooth<T>(h, lv, k, A, b, xt, wd, xo, CorrK<T>{lv.agg, pv, c, d, K, F}, fuse_q, rc);
@@ -1820,8 +1853,32 @@ struct OpFillT {
   __device__ void finalize(const double*) const {}
 };
 
+// Schedules (block_steps) of the 64-row slice kernels worth timing on a
+// level of nslices slices whose largest column offset is off rows:
+// contiguous (0), the XCD sweep (-1) and plane-ordered (the plane in 4-slice
+// steps, when it is a whole number of steps that tiles the slices, as on
+// lexicographic grids).  AMG_TUNE_SCHEDULE = contiguous, sweep or plane
+// keeps that one where it applies (tests).
+std::vector<int> schedules(int nslices, int off) {
+  std::vector<int> v{0, -1};
+  const int steps = (nslices + 3) / 4;
+  if (off > 0 && off % 256 == 0) {
+    const int p = off / 256;
+    if (nslices % 4 == 0 && steps % p == 0 && steps / p >= 2) v.push_back(p);
+  }
+  if (const char* f = std::getenv("AMG_TUNE_SCHEDULE")) {
+    const std::string w(f);
+    std::vector<int> k;
+    for (int c : v)
+      if ((w == "contiguous" && c == 0) || (w == "sweep" && c == -1) || (w == "plane" && c > 0))
+        k.push_back(c);
+    if (!k.empty()) return k;
+  }
+  return v;
+}
+
 // Time the pre-smoothing kernel for CSR with 2..32 lanes per row and for
-// sliced ELL with 32- and 16-bit columns (contiguous and plane-ordered); keep
+// sliced ELL with 32- and 16-bit columns (in the schedules above); keep
 // the fastest (AMG_TUNE_FORCE = csr, sell or sell16 pins the format where the
 // level has it, for tests).  Results are cached per level shape (n, nnz,
 // sliced-ELL size) and value size for the process and, when AMG_TUNE_CACHE
@@ -1847,7 +1904,7 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
   key.nrhs = 1;
   key.rowstat = lv.sl_total;
   const char* force = std::getenv("AMG_TUNE_FORCE");
-  if (!force && !std::getenv("AMG_TUNE_SLICE")) {
+  if (!force && !std::getenv("AMG_TUNE_SLICE") && !std::getenv("AMG_TUNE_SCHEDULE")) {
     Level::Tune t;
     if (tune_cache_get(key, &t)) return t;
   }
@@ -1880,13 +1937,9 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     const float us = time_it([&] { launch_rows<T>(lv.n, lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s); });
     if (us < best.us) { best.us = us; best.fmt = 0; best.lpr = lpr; }
   }
+  const int off = (lv.sl_ptr && sell_vals<T>(lv)) || dia_vals<T>(lv) ? max_column_offset(h, lv) : 0;
   if (lv.sl_ptr && sell_vals<T>(lv)) {
-    // the plane-ordered schedule, when the level's largest column offset is a
-    // whole number of 4-slice steps that tiles the slices (lexicographic grids)
-    const int off = max_column_offset(h, lv);
-    const int pz = (lv.nslices % 4 == 0 && off > 0 && off % 256 == 0 && (lv.nslices / 4) % (off / 256) == 0 &&
-                    (lv.nslices / 4) / (off / 256) >= 2) ? off / 256 : 0;
-    for (int p : {0, pz}) {
+    for (int p : schedules(lv.nslices, off)) {
       const float us = time_it([&] {
         launch_sell<T>(lv.n, lv.nslices, lv.sl_ptr, lv.sl_col, sell_vals<T>(lv), op, rc, s, nullptr, p);
       });
@@ -1904,7 +1957,6 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
         const bool over32 = best.fmt == 1 && best.pz == p && u16 <= kPreferFewerBytes * best.us;
         if (u16 < best.us || over32) { best.us = u16; best.fmt = 2; best.lpr = lv.lpr; best.pz = p; }
       }
-      if (pz == 0) break;
     }
   }
   if (lv.sh.ptr && short_vals<T>(lv)) {   // the copy in shorter slices, 32- and 16-bit columns
@@ -1920,12 +1972,8 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
       if (us < best.us) { best.us = us; best.fmt = f; best.lpr = lv.lpr; best.pz = 0; best.sh = lv.sh.h; }
     }
   }
-  if (dia_vals<T>(lv)) {   // sliced diagonals, contiguous and plane-ordered
-    const int off = max_column_offset(h, lv);
-    const int pz = (lv.dia.nslices % 4 == 0 && off > 0 && off % 256 == 0 &&
-                    (lv.dia.nslices / 4) % (off / 256) == 0 && (lv.dia.nslices / 4) / (off / 256) >= 2)
-                       ? off / 256 : 0;
-    for (int p : {0, pz}) {
+  if (dia_vals<T>(lv)) {   // sliced diagonals, in the same schedules
+    for (int p : schedules(lv.dia.nslices, off)) {
       const float us = time_it([&] {
         launch_sdia<T>(lv.n, lv.dia.nslices, lv.dia.ptr, lv.dia.off, dia_vals<T>(lv), op, rc, s, p);
       });
@@ -1935,7 +1983,6 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
       // fewer bytes than any sliced ELL: preferred within kPreferFewerBytes, as the 16-bit offsets are
       const bool over_sell = best.fmt >= 1 && best.fmt <= 2 && best.sh == 0 && us <= kPreferFewerBytes * best.us;
       if (us < best.us || over_sell) { best.us = us; best.fmt = 3; best.lpr = lv.lpr; best.pz = p; best.sh = 0; }
-      if (pz == 0) break;
     }
   }
   if (force) {   // "csr", "sell", "sell16" or "sdia", the sliced ELL optionally ":32" or ":16" (slice height)
@@ -1963,9 +2010,11 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
       best.sh = short_ok && lv.sh.dcol ? fh : 0;
     }
     if (best.sh) best.pz = 0;
+    else if (best.fmt != 0 && std::getenv("AMG_TUNE_SCHEDULE"))
+      best.pz = schedules(best.fmt == 3 ? lv.dia.nslices : lv.nslices, off).front();
     return best;   // not cached
   }
-  if (!std::getenv("AMG_TUNE_SLICE")) tune_cache_put(key, best);
+  if (!std::getenv("AMG_TUNE_SLICE") && !std::getenv("AMG_TUNE_SCHEDULE")) tune_cache_put(key, best);
   return best;
 }
 
@@ -1974,7 +2023,7 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
 void autotune_levels(Hierarchy& h) {
   const bool debug = std::getenv("AMG_DEBUG") != nullptr;
   const char* force_h = std::getenv("AMG_TUNE_SLICE");   // 32 or 16: build that slice height (tests)
-  const bool pinned = force_h || std::getenv("AMG_TUNE_FORCE");
+  const bool pinned = force_h || std::getenv("AMG_TUNE_FORCE") || std::getenv("AMG_TUNE_SCHEDULE");
   for (int k = 0; k < h.L(); ++k) {
     Level& lv = h.levels[k];
     // candidate copies in shorter slices (rows that vary in length) and in

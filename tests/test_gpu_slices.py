@@ -153,3 +153,43 @@ def test_ragged_last_slice(fmt, monkeypatch):
     assert rel <= 1e-8
     assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
     h.close()
+
+
+@pytest.mark.parametrize("sched", ["contiguous", "sweep", "plane"])
+@pytest.mark.parametrize("fmt", ["sdia", "sell", "sell16"])
+def test_slice_schedules(base, fmt, sched, monkeypatch):
+    """Every schedule of the slice kernels over the 96^3 Poisson level 0
+    (3,456 steps of four slices; a grid plane is 36 steps): contiguous runs
+    of steps per block, the XCD sweep (each XCD's blocks walk its eighth of
+    the steps together) and plane-ordered.  The product entry by entry against
+    the exported A_0 and the solve against the default hierarchy."""
+    A, dev, b, x0, it0 = base
+    monkeypatch.setenv("AMG_TUNE_FORCE", fmt)
+    monkeypatch.setenv("AMG_TUNE_SCHEDULE", sched)
+    print(f"schedule: {fmt} {sched}", flush=True)
+    h = amg.setup(*dev, amg.Options(dim=3))
+    assert h.level_format(0)[0] == {"sdia": 3, "sell": 1, "sell16": 2}[fmt]
+    _entrywise(h, 0, 61)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and abs(it - it0) <= 1
+    assert np.linalg.norm(x - x0) <= 1e-7 * np.linalg.norm(x0)
+    h.close()
+
+
+@pytest.mark.parametrize("fmt", ["sdia", "sell"])
+def test_sweep_on_a_ragged_level(fmt, monkeypatch):
+    """The XCD sweep where the steps do not divide evenly among the XCDs
+    (43^3 = 79,507 rows: 311 steps over 304 blocks, 39 steps per XCD, the
+    last XCD 38) and the last slice is partial."""
+    A = P.poisson3d(43)
+    dev = to_dev(A)
+    b = P.rhs(A, P.exact_solution(A.n, 7))
+    monkeypatch.setenv("AMG_TUNE_FORCE", fmt)
+    monkeypatch.setenv("AMG_TUNE_SCHEDULE", "sweep")
+    h = amg.setup(*dev, amg.Options(dim=3))
+    _entrywise(h, 0, 71)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    assert rel <= 1e-8
+    assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
+    h.close()
