@@ -297,6 +297,8 @@ enum KSlot : int {
 };
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kMaxReduce = 8;        // values one reduction may carry (partials: kMaxReduce x blocks)
+constexpr int kArnMax = 5;           // Arnoldi steps at most (amg_options.arnoldi_m)
+static_assert(1 + kArnMax <= kMaxReduce, "an Arnoldi step's norm and projections in one reduction");
 // pinned host mirror: ints 0..63 for control read-backs, then (in doubles
 // from kPinnedArn) the Arnoldi results
 constexpr int kPinnedArn = 64;

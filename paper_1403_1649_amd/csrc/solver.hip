@@ -443,15 +443,17 @@ struct OpTrueResid {
   __device__ void finalize(const double* s) const { sc[kScTrue] = s[0]; }
 };
 
-// Arnoldi: w = D^-1 A q_j with ||w||^2 and q_0'w
+// Arnoldi step j (classical Gram-Schmidt): w = D^-1 A q_j with ||w||^2 and
+// the projections q_k'w, k <= j, in the same pass (the basis q_k at Q + k n)
 struct OpArnSpmv {
-  static constexpr int NV = 2;
+  static constexpr int NV = 1 + kArnMax;
   const double* q;
-  const double* q0;
+  const double* Q;
   const double* diag;
   double* w;
   double* sc;
   int j;
+  int n;
   __device__ bool active() const { return true; }
   __device__ void idle() const {}
   __device__ double x(int c) const { return q[c]; }
@@ -459,11 +461,13 @@ struct OpArnSpmv {
     const double t = (1.0 / diag[i]) * ax;
     w[i] = t;
     acc[0] += t * t;
-    acc[1] += q0[i] * t;
+#pragma unroll
+    for (int k = 0; k < kArnMax; ++k)
+      if (k <= j) acc[1 + k] += Q[(size_t)k * n + i] * t;
   }
   __device__ void finalize(const double* s) const {
     sc[kScArn + 48 + j] = sqrt(s[0]);
-    sc[kScArn + 0 * 8 + j] = s[1];
+    for (int k = 0; k <= j; ++k) sc[kScArn + k * 8 + j] = s[1 + k];
   }
 };
 
@@ -700,23 +704,27 @@ struct OpDivide {
   __device__ void finalize(const double*) const {}
 };
 
-// modified Gram-Schmidt step: w -= h q_i, then the next dot (q_{i+1}'w, or
-// ||w|| after the last projection)
-struct OpArnAxpyDot {
+// the projections off w in one pass, w -= sum_k h_kj q_k (k = 0..j in
+// order), and h_{j+1,j} = ||w||
+struct OpArnUpdate {
   static constexpr int NV = 1;
-  const double* qi;
-  const double* qn;   // nullptr: norm of w
+  const double* Q;
   double* w;
-  const double* h;
+  const double* sc;
   double* out;
+  int j;
+  int n;
   __device__ bool active() const { return true; }
   __device__ void idle() const {}
   __device__ void elem(int i, double* acc) const {
-    const double t = w[i] - (*h) * qi[i];
+    double t = w[i];
+#pragma unroll
+    for (int k = 0; k < kArnMax; ++k)
+      if (k <= j) t -= sc[kScArn + k * 8 + j] * Q[(size_t)k * n + i];
     w[i] = t;
-    acc[0] += (qn ? qn[i] : t) * t;
+    acc[0] += t * t;
   }
-  __device__ void finalize(const double* s) const { *out = qn ? s[0] : sqrt(s[0]); }
+  __device__ void finalize(const double* s) const { *out = sqrt(s[0]); }
 };
 
 struct OpSetCtl {
@@ -2139,16 +2147,12 @@ void arnoldi_enqueue(Hierarchy& h, const Level& lv, int m, uint32_t stream, doub
   launch_elem(n, OpDivide{Q, Q, sc + kScArn + 56}, rc, s);
   for (int j = 0; j < m; ++j) {
     const double* qj = Q + (size_t)j * n;
-    const OpArnSpmv op{qj, Q, lv.diag, w, sc, j};
+    const OpArnSpmv op{qj, Q, lv.diag, w, sc, j, n};
     if (lv.nslices > 0 && lv.nnz <= 12L * n)   // short, even rows: sliced ELL
       launch_sell<double>(n, lv.nslices, lv.sl_ptr, lv.sl_col, lv.sl_val, op, rc, s, lv.sl_dcol);
     else
       launch_rows<double>(n, lv.lpr, lv.rp, lv.ci, lv.val, op, rc, s);
-    for (int i = 0; i <= j; ++i) {
-      const double* qi = Q + (size_t)i * n;
-      const double* qn = i < j ? Q + (size_t)(i + 1) * n : nullptr;
-      launch_elem(n, OpArnAxpyDot{qi, qn, w, sc + kScArn + i * 8 + j, sc + kScArn + (i + 1) * 8 + j}, rc, s);
-    }
+    launch_elem(n, OpArnUpdate{Q, w, sc, sc + kScArn + (j + 1) * 8 + j, j, n}, rc, s);
     launch_elem(n, OpDivide{w, Q + (size_t)(j + 1) * n, sc + kScArn + (j + 1) * 8 + j}, rc, s);
   }
   AMG_HIP(hipMemcpyAsync(host_out, sc + kScArn, 56 * sizeof(double), hipMemcpyDeviceToHost, s));
