@@ -8,6 +8,8 @@
 // kernel entry, so branches of the K-cycle and the outer iteration are
 // decided on the device.
 #pragma once
+#include <atomic>
+
 #include "amg_internal.hpp"
 #include "device_utils.hpp"
 
@@ -360,10 +362,12 @@ inline int elem_grid(int n, bool reduce) {
 // kMaxPartialBlocks: a slice kernel gives each block a fixed share of the
 // steps, so a grid larger than what is resident would run its last blocks
 // in a second, mostly empty round (kernels whose registers allow fewer than
-// 8 blocks of 256 threads per CU).  Per kernel instance, taken once.
+// 8 blocks of 256 threads per CU).  Per kernel instance, taken once (host
+// threads that race on the first launch compute the same value).
 template <class K>
 int resident_blocks(K k) {
-  static int g = 0;
+  static std::atomic<int> cached{0};
+  int g = cached.load(std::memory_order_relaxed);
   if (g == 0) {
     int per = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, 0) != hipSuccess || per < 1) per = 8;
@@ -372,6 +376,7 @@ int resident_blocks(K k) {
       cus = 256;
     const long r = (long)per * cus;
     g = (int)(r < kMaxPartialBlocks ? r : kMaxPartialBlocks);
+    cached.store(g, std::memory_order_relaxed);
   }
   return g;
 }
