@@ -103,6 +103,8 @@ def measured_traffic(workload: str):
 def kernel_name(fmt: int, lpr: int, op: str) -> str:
     """lpr: lanes per row (for the sliced ELL, 64 / slice height)."""
     h = 64 // max(lpr, 1)
+    if fmt == 4:
+        return f"k_rows<double,{lpr},{op},true> (CSR with 16-bit column offsets)"
     if fmt == 3:
         return f"k_sdia<double,{op}> (sliced diagonals, 64-row slices, no column indices)"
     if fmt == 2:

@@ -235,7 +235,9 @@ int32_t amg_setup_batched(const amg_csr* A, int32_t nsys, const int32_t* sys_off
  * 2 = sliced ELL with 16-bit column offsets col - row, 3 = sliced diagonals
  * (per 64-row slice a list of offsets col - row and their values, no column
  * indices; built for levels whose slices have few diagonals, as on
- * structured grids; *lanes_per_row = 1); for the sliced ELL,
+ * structured grids; *lanes_per_row = 1), 4 = CSR with its columns as 16-bit
+ * offsets col - row (levels whose offsets all fit; *lanes_per_row lanes per
+ * row); for the sliced ELL,
  * *lanes_per_row = 64 / slice height (1: 64-row slices; 2 or 4: the level's
  * copy in 32- or 16-row slices, built where rows vary in length);
  * us (host, may be NULL) = its timed duration (0 if the level was not timed).

@@ -128,9 +128,14 @@ struct Level {
     float* val32 = nullptr;
   } dia;
   std::shared_ptr<Arena> dia_mem;
+  // the CSR columns as 16-bit offsets col - row (2 bytes per entry instead of
+  // 4), for the row kernels on levels whose offsets all fit (those with the
+  // 16-bit sliced ELL); built for the autotuner, kept while it is chosen
+  int16_t* ci16 = nullptr;
+  std::shared_ptr<Arena> ci16_mem;
   // kernel choice per arithmetic type (autotuned): fmt 0 = CSR with lpr lanes
   // per row, fmt 1 = sliced ELL, fmt 2 = sliced ELL with 16-bit column offsets,
-  // fmt 3 = sliced diagonals
+  // fmt 3 = sliced diagonals, fmt 4 = CSR with 16-bit column offsets
   // pz: schedule of the slice kernels (0 contiguous, -1 XCD sweep, > 0
   // plane-ordered over that many steps)
   // tile: columns per pass of the block kernels (several right-hand sides)
@@ -388,6 +393,8 @@ void launch_sell_fill(int n, int nslices, const int* rp, const int* ci, const do
 void launch_window_order(int n, const int* rp, int* perm, hipStream_t s);
 // sliced diagonals: per 64-row slice the number of distinct offsets (*over
 // raised above cap), then offsets and values at dg_ptr
+// ci16[k] = ci[k] - row for the entries of each row (offsets known to fit)
+void launch_ci16(int n, const int* rp, const int* ci, int16_t* ci16, hipStream_t s);
 void launch_sdia_count(int n, const int* rp, const int* ci, int cap, int* cnt, int* over, hipStream_t s);
 void launch_sdia_fill(int n, const int* rp, const int* ci, const double* val, const int* dg_ptr, int* dg_off,
                       double* dg_val, float* dg_val32, hipStream_t s);

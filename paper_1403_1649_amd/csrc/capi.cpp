@@ -196,7 +196,7 @@ int32_t amg_level_format(const amg_hierarchy* H, int32_t k, int32_t precision, i
   const amg::Level& lv = H->h.levels[k];
   const amg::Level::Tune& t = precision == AMG_PREC_FP64 ? lv.t64 : lv.t32;
   *format = t.fmt;
-  *lanes_per_row = t.fmt == 0 ? t.lpr : t.fmt == 3 ? 1 : 64 / (t.sh > 0 ? t.sh : 64);   // sliced: 64 / slice height
+  *lanes_per_row = t.fmt == 0 || t.fmt == 4 ? t.lpr : t.fmt == 3 ? 1 : 64 / (t.sh > 0 ? t.sh : 64);   // sliced: 64 / slice height
   if (us) *us = t.us;
   return AMG_OK;
 }

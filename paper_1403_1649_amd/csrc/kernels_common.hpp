@@ -140,9 +140,10 @@ __device__ __forceinline__ Steps block_steps(int steps, int sched) {
   return r;
 }
 
-template <typename T, int LPR, class Op>
+// D16: the columns come as 16-bit offsets col - row (Level::ci16).
+template <typename T, int LPR, class Op, bool D16 = false>
 __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci,
+                                                 const void* __restrict__ cols,
                                                  const T* __restrict__ av, Op op, RedCtx rc) {
   if (!op.active()) {
     if (blockIdx.x == 0 && threadIdx.x == 0) op.idle();
@@ -171,7 +172,8 @@ __global__ void __launch_bounds__(kBlock) k_rows(int n, const int* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int k = k0 + q * LPR;
-          c[q] = k < e ? ci[k] : 0;
+          if constexpr (D16) c[q] = k < e ? row + (int)static_cast<const int16_t*>(cols)[k] : 0;
+          else c[q] = k < e ? static_cast<const int*>(cols)[k] : 0;
           v[q] = k < e ? av[k] : T(0);
         }
         T xv[4];
@@ -381,14 +383,14 @@ int resident_blocks(K k) {
   return g;
 }
 
-template <typename T, int LPR, class Op>
-void launch_rows_l(int n, const int* rp, const int* ci, const T* av, const Op& op, RedCtx rc, hipStream_t s) {
+template <typename T, int LPR, class Op, bool D16 = false>
+void launch_rows_l(int n, const int* rp, const void* ci, const T* av, const Op& op, RedCtx rc, hipStream_t s) {
   int g = rows_grid(n, LPR, Op::NV > 0);
-  const int cap = resident_blocks(k_rows<T, LPR, Op>);
+  const int cap = resident_blocks(k_rows<T, LPR, Op, D16>);
   if (g > cap) g = cap > 8 ? cap & ~7 : cap;
   const bool tail = Op::NV > 0 && g <= kTailBlocks && rc.ticket != nullptr;
   const RedCtx r2{rc.part, tail ? rc.ticket : nullptr};
-  k_rows<T, LPR, Op><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2);
+  k_rows<T, LPR, Op, D16><<<g, kBlock, 0, s>>>(n, rp, ci, av, op, r2);
   if constexpr (Op::NV > 0)
     if (!tail) k_finalize<Op><<<1, kFinBlock, 0, s>>>(op, rc.part, g);
 }
@@ -404,6 +406,19 @@ void launch_rows(int n, int lpr, const int* rp, const int* ci, const T* av, cons
     case 16: launch_rows_l<T, 16>(n, rp, ci, av, op, rc, s); break;
     case 32: launch_rows_l<T, 32>(n, rp, ci, av, op, rc, s); break;
     default: launch_rows_l<T, 64>(n, rp, ci, av, op, rc, s); break;
+  }
+}
+
+// The same with the columns as 16-bit offsets (2 to 32 lanes per row).
+template <typename T, class Op>
+void launch_rows16(int n, int lpr, const int* rp, const int16_t* ci16, const T* av, const Op& op, RedCtx rc,
+                   hipStream_t s) {
+  switch (lpr) {
+    case 2: launch_rows_l<T, 2, Op, true>(n, rp, ci16, av, op, rc, s); break;
+    case 4: launch_rows_l<T, 4, Op, true>(n, rp, ci16, av, op, rc, s); break;
+    case 8: launch_rows_l<T, 8, Op, true>(n, rp, ci16, av, op, rc, s); break;
+    case 16: launch_rows_l<T, 16, Op, true>(n, rp, ci16, av, op, rc, s); break;
+    default: launch_rows_l<T, 32, Op, true>(n, rp, ci16, av, op, rc, s); break;
   }
 }
 

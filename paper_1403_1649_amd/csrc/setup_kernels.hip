@@ -971,6 +971,14 @@ void launch_sdia_fill(int n, const int* rp, const int* ci, const double* val, co
     k_sdia_build<true><<<g, 256, 0, s>>>(n, nsl, rp, ci, val, 0, nullptr, dg_ptr, dg_off, dg_val, dg_val32,
                                          nullptr);
 }
+// the CSR columns as 16-bit offsets, one thread per row
+__global__ void k_ci16(int n, const int* __restrict__ rp, const int* __restrict__ ci, int16_t* __restrict__ ci16) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    for (int k = rp[i]; k < rp[i + 1]; ++k) ci16[k] = (int16_t)(ci[k] - i);
+}
+void launch_ci16(int n, const int* rp, const int* ci, int16_t* ci16, hipStream_t s) {
+  if (n > 0) k_ci16<<<grid_for(n), kT, 0, s>>>(n, rp, ci, ci16);
+}
 void launch_window_order(int n, const int* rp, int* perm, hipStream_t s) {
   if (n > 0) k_window_order<<<(n + 255) / 256, 256, 0, s>>>(n, rp, perm);
 }

@@ -838,7 +838,9 @@ template <> const float* dia_vals<float>(const Level& l) { return l.dia.val32; }
 template <typename T, class Op>
 void launch_level(const Level& lv, const Op& op, RedCtx rc, hipStream_t s) {
   const Level::Tune& t = tune_of<T>(lv);
-  if (t.fmt == 3 && dia_vals<T>(lv))
+  if (t.fmt == 4 && lv.ci16)
+    launch_rows16<T>(lv.n, t.lpr, lv.rp, lv.ci16, vals<T>(lv), op, rc, s);
+  else if (t.fmt == 3 && dia_vals<T>(lv))
     launch_sdia<T>(lv.n, lv.dia.nslices, lv.dia.ptr, lv.dia.off, dia_vals<T>(lv), op, rc, s, t.pz);
   else if (t.fmt >= 1 && t.sh > 0 && t.sh == lv.sh.h && short_vals<T>(lv))
     launch_sell<T>(lv.n, lv.sh.nslices, lv.sh.ptr, lv.sh.col, short_vals<T>(lv), op, rc, s,
@@ -1885,10 +1887,10 @@ std::vector<int> schedules(int nslices, int off) {
   return v;
 }
 
-// Time the pre-smoothing kernel for CSR with 2..32 lanes per row and for
-// sliced ELL with 32- and 16-bit columns (in the schedules above); keep
-// the fastest (AMG_TUNE_FORCE = csr, sell or sell16 pins the format where the
-// level has it, for tests).  Results are cached per level shape (n, nnz,
+// Time the pre-smoothing kernel for CSR with 2..32 lanes per row (with 32-
+// and 16-bit columns) and for sliced ELL with 32- and 16-bit columns (in the
+// schedules above); keep the fastest (AMG_TUNE_FORCE = csr, csr16, sell,
+// sell16 or sdia pins the format where the level has it, for tests).  Results are cached per level shape (n, nnz,
 // sliced-ELL size) and value size for the process and, when AMG_TUNE_CACHE
 // names a file, across processes (one JSON object per line).
 template <typename T>
@@ -1945,6 +1947,16 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     const float us = time_it([&] { launch_rows<T>(lv.n, lpr, lv.rp, lv.ci, vals<T>(lv), op, rc, s); });
     if (us < best.us) { best.us = us; best.fmt = 0; best.lpr = lpr; }
   }
+  if (lv.ci16) {   // 16-bit column offsets: 2 bytes less per entry, taken within kPreferFewerBytes of CSR
+    for (int lpr = 2; lpr <= 32; lpr <<= 1) {
+      const float us = time_it([&] { launch_rows16<T>(lv.n, lpr, lv.rp, lv.ci16, vals<T>(lv), op, rc, s); });
+      if (std::getenv("AMG_DEBUG"))
+        std::fprintf(stderr, "amg: level n=%d CSR 16-bit offsets lanes=%d: %.2f us (best so far %.2f)\n", lv.n,
+                     lpr, us, best.us);
+      const bool over_csr = best.fmt == 0 && us <= kPreferFewerBytes * best.us;
+      if (us < best.us || over_csr) { best.us = us; best.fmt = 4; best.lpr = lpr; }
+    }
+  }
   const int off = (lv.sl_ptr && sell_vals<T>(lv)) || dia_vals<T>(lv) ? max_column_offset(h, lv) : 0;
   if (lv.sl_ptr && sell_vals<T>(lv)) {
     for (int p : schedules(lv.nslices, off)) {
@@ -1989,11 +2001,11 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
         std::fprintf(stderr, "amg: level n=%d sliced diagonals pz=%d: %.2f us (best so far %.2f)\n", lv.n, p, us,
                      best.us);
       // fewer bytes than any sliced ELL: preferred within kPreferFewerBytes, as the 16-bit offsets are
-      const bool over_sell = best.fmt >= 1 && best.fmt <= 2 && best.sh == 0 && us <= kPreferFewerBytes * best.us;
+      const bool over_sell = (best.fmt == 1 || best.fmt == 2) && best.sh == 0 && us <= kPreferFewerBytes * best.us;
       if (us < best.us || over_sell) { best.us = us; best.fmt = 3; best.lpr = lv.lpr; best.pz = p; best.sh = 0; }
     }
   }
-  if (force) {   // "csr", "sell", "sell16" or "sdia", the sliced ELL optionally ":32" or ":16" (slice height)
+  if (force) {   // "csr", "csr16", "sell", "sell16" or "sdia", the sliced ELL optionally ":32" or ":16" (slice height)
     std::string w(force);
     int fh = 0;
     const size_t colon = w.find(':');
@@ -2005,6 +2017,12 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     if (w == "csr") {
       best.fmt = 0;
       best.sh = 0;
+    } else if (w == "csr16") {
+      if (lv.ci16) {
+        best.fmt = 4;
+        best.sh = 0;
+        if (best.lpr < 2) best.lpr = 4;
+      }
     } else if (w == "sdia") {
       if (dia_vals<T>(lv)) {
         best.fmt = 3;
@@ -2039,6 +2057,7 @@ void autotune_levels(Hierarchy& h) {
     // decisions of this level shape use neither
     bool need_sh = lv.n > kFuseCorrectionRows && lv.sl_ptr;
     bool need_dia = need_sh;
+    bool need_c16 = need_sh && lv.sl_dcol;   // the offsets fit in 16 bits
     if (need_sh && !pinned) {
       TuneKey key;
       key.n = lv.n;
@@ -2053,10 +2072,17 @@ void autotune_levels(Hierarchy& h) {
       if (h32 && h64) {
         need_sh = (h.mixed() && c32.sh > 0) || (use64 && c64.sh > 0);
         need_dia = (h.mixed() && c32.fmt == 3) || (use64 && c64.fmt == 3);
+        need_c16 = need_c16 && ((h.mixed() && c32.fmt == 4) || (use64 && c64.fmt == 4));
       }
     }
     if (need_sh) build_short_sell(h, lv, force_h ? std::atoi(force_h) : 0);
     if (need_dia) build_sdia(h, lv);
+    if (need_c16 && !lv.ci16) {
+      auto mem = std::make_shared<Arena>();
+      lv.ci16 = mem->alloc_n<int16_t>((size_t)std::max(lv.nnz, 1));
+      launch_ci16(lv.n, lv.rp, lv.ci, lv.ci16, h.stream);
+      lv.ci16_mem = mem;
+    }
     if (h.mixed()) {
       lv.t32 = tune_one<float>(h, lv, static_cast<float*>(lv.xt), static_cast<float*>(lv.r));
       if (k == 0) lv.t64 = tune_one<double>(h, lv, h.p, h.q);
@@ -2070,6 +2096,10 @@ void autotune_levels(Hierarchy& h) {
     if (lv.dia.ptr && lv.t64.fmt != 3 && lv.t32.fmt != 3) {
       lv.dia = Level::Sdia{};
       lv.dia_mem.reset();
+    }
+    if (lv.ci16 && lv.t64.fmt != 4 && lv.t32.fmt != 4) {
+      lv.ci16 = nullptr;
+      lv.ci16_mem.reset();
     }
     if (debug)
       std::fprintf(stderr,

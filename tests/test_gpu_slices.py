@@ -133,7 +133,7 @@ def test_sliced_diagonals_on_the_heterogeneous_field(monkeypatch):
     h.close()
 
 
-@pytest.mark.parametrize("fmt", ["sdia", "sell:32", "sell16:16"])
+@pytest.mark.parametrize("fmt", ["sdia", "sell:32", "sell16:16", "csr16"])
 def test_ragged_last_slice(fmt, monkeypatch):
     """A level whose row count is not a multiple of the slice height (43^3 =
     79,507 rows: the last 64-row slice holds 19 rows): the padded slots of the
@@ -147,7 +147,7 @@ def test_ragged_last_slice(fmt, monkeypatch):
     monkeypatch.setenv("AMG_TUNE_FORCE", fmt)
     h = amg.setup(*dev, amg.Options(dim=3))
     f, lanes, _ = h.level_format(0)
-    assert f == {"sdia": 3, "sell:32": 1, "sell16:16": 2}[fmt]
+    assert f == {"sdia": 3, "sell:32": 1, "sell16:16": 2, "csr16": 4}[fmt]
     _entrywise(h, 0, 51)
     x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
     assert rel <= 1e-8
@@ -192,4 +192,36 @@ def test_sweep_on_a_ragged_level(fmt, monkeypatch):
     x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
     assert rel <= 1e-8
     assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1.01e-8 * np.linalg.norm(b)
+    h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_csr_with_16bit_offsets(base, precision, monkeypatch):
+    """The CSR row kernels reading the columns as 16-bit offsets col - row
+    (forced on the tuned levels of the 96^3 Poisson hierarchy, whose offsets
+    all fit): each product entry by entry against the exported A_k, the solve
+    against the default hierarchy, and a re-setup on new values."""
+    A, dev, b, x0, it0 = base
+    monkeypatch.setenv("AMG_TUNE_FORCE", "csr16")
+    print(f"csr16: {precision}", flush=True)
+    h = amg.setup(*dev, amg.Options(dim=3, precision=precision))
+    tuned = [k for k in range(h.num_levels() - 1) if h.level_info(k)["n"] > 65536]
+    assert tuned[:2] == [0, 1]
+    for k in tuned:
+        f, lanes, _ = h.level_format(k, "fp64" if precision == "fp64" else "mixed")
+        assert f == 4 and lanes in (2, 4, 8, 16, 32), (k, f, lanes)
+    assert h.level_format(0, "fp64")[0] == 4
+    for k in tuned:
+        _entrywise(h, k, 81 + k)
+    x, it, rel = amg.solve(h, dev_vec(b), 1e-8)
+    x = x.cpu().numpy()
+    assert rel <= 1e-8 and abs(it - it0) <= 1
+    assert np.linalg.norm(b - A.to_scipy() @ x) <= 1.01e-8 * np.linalg.norm(b)
+    if precision == "fp64":
+        assert np.linalg.norm(x - x0) <= 1e-7 * np.linalg.norm(x0)
+        h.resetup(dev[2] * 2.0)
+        for k in tuned:
+            _entrywise(h, k, 91 + k)
+        x2, it2, rel2 = amg.solve(h, dev_vec(b), 1e-8)
+        assert rel2 <= 1e-8 and abs(it2 - it0) <= 1
     h.close()
