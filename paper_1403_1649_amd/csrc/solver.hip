@@ -1948,14 +1948,13 @@ Level::Tune tune_one(Hierarchy& h, Level& lv, T* x, T* y) {
     if (us < best.us) { best.us = us; best.fmt = 0; best.lpr = lpr; }
   }
   if (lv.ci16) {   // 16-bit column offsets: 2 bytes less per entry, taken within kPreferFewerBytes of CSR
-    for (int lpr = 2; lpr <= 32; lpr <<= 1) {
-      const float us = time_it([&] { launch_rows16<T>(lv.n, lpr, lv.rp, lv.ci16, vals<T>(lv), op, rc, s); });
-      if (std::getenv("AMG_DEBUG"))
-        std::fprintf(stderr, "amg: level n=%d CSR 16-bit offsets lanes=%d: %.2f us (best so far %.2f)\n", lv.n,
-                     lpr, us, best.us);
-      const bool over_csr = best.fmt == 0 && us <= kPreferFewerBytes * best.us;
-      if (us < best.us || over_csr) { best.us = us; best.fmt = 4; best.lpr = lpr; }
-    }
+    // the same rows and lanes as CSR with fewer bytes: timed with CSR's best lanes only
+    const int lpr = best.lpr;
+    const float us = time_it([&] { launch_rows16<T>(lv.n, lpr, lv.rp, lv.ci16, vals<T>(lv), op, rc, s); });
+    if (std::getenv("AMG_DEBUG"))
+      std::fprintf(stderr, "amg: level n=%d CSR 16-bit offsets lanes=%d: %.2f us (best so far %.2f)\n", lv.n, lpr,
+                   us, best.us);
+    if (us <= kPreferFewerBytes * best.us) { best.us = std::min(us, best.us); best.fmt = 4; }
   }
   const int off = (lv.sl_ptr && sell_vals<T>(lv)) || dia_vals<T>(lv) ? max_column_offset(h, lv) : 0;
   if (lv.sl_ptr && sell_vals<T>(lv)) {
