@@ -358,7 +358,8 @@ class Hierarchy:
 
     def level_format(self, k: int, precision: str = "fp64"):
         """(format, lanes_per_row, timed us) the autotuner chose for level k;
-        format 0 = CSR, 1 = sliced ELL, 2 = sliced ELL with 16-bit column offsets."""
+        format 0 = CSR, 1 = sliced ELL, 2 = sliced ELL with 16-bit column
+        offsets, 3 = sliced diagonals, 4 = CSR with 16-bit column offsets."""
         f, l, us = C.c_int32(), C.c_int32(), C.c_float()
         _check(lib().amg_level_format(self._h, int(k), _PREC[precision], C.byref(f), C.byref(l), C.byref(us)))
         return f.value, l.value, us.value
